@@ -1,0 +1,218 @@
+"""Seeded synthetic inputs for the Local Exponential Method workloads.
+
+This module only draws numbers: grid sizes, physical coefficients (velocity,
+diffusivity, time step) and initial states.  It holds none of the method's
+arithmetic -- no stencil weights, no exponentials, no partitions -- so that both
+the CPU oracle and the GPU path can consume the same inputs while sharing no
+code.  Every generator uses NumPy's PCG64 ``default_rng(seed)`` with a fixed
+draw order, so a (workload, seed) pair always yields the same arrays.
+
+The physical problem is the advection-diffusion equation of the paper's model
+problem (eq. (2), and its 2D conservative form in section 4.3) on the periodic
+unit square/interval, discretized on ``n`` points per axis, ``dx = 1/n``.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+
+@dataclass
+class Problem:
+    """Physical description of one periodic advection-diffusion problem.
+
+    ndim      1 or 2
+    n         points per axis (grid is n or n x n, x index fastest)
+    dx        grid spacing (= 1/n on the unit domain)
+    dt        time step
+    vel       constant velocity (a_x, a_y); a_y ignored in 1D
+    nu        scalar diffusivity, or None when ``nu_field`` is given
+    nu_field  per-node diffusivity, shape (n,) or (n, n) [y, x], float64
+    states    initial states, shape (N, n_states) with N = n**ndim, DOF
+              index j*n + i (x fastest), ensemble index fastest in memory
+    """
+
+    ndim: int
+    n: int
+    dx: float
+    dt: float
+    vel: Tuple[float, float]
+    nu: Optional[float]
+    nu_field: Optional[np.ndarray]
+    states: np.ndarray
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def N(self) -> int:
+        return self.n ** self.ndim
+
+
+def _grid(n: int) -> np.ndarray:
+    return np.arange(n, dtype=np.float64) / n
+
+
+def bump_plus_modes(n: int, seed: int, n_modes: int = 8, kmax: int = 32,
+                    sigma: float = 0.05, amp_max: float = 0.1) -> np.ndarray:
+    """1D state: Gaussian bump at x=0.5 plus ``n_modes`` random cosines.
+
+    Draw order: wavenumbers (distinct, from 1..kmax), amplitudes U(0, amp_max),
+    phases U(0, 2 pi).
+    """
+    rng = np.random.default_rng(seed)
+    k = rng.choice(np.arange(1, kmax + 1), size=n_modes, replace=False)
+    a = rng.uniform(0.0, amp_max, size=n_modes)
+    ph = rng.uniform(0.0, 2.0 * np.pi, size=n_modes)
+    x = _grid(n)
+    u = np.exp(-((x - 0.5) ** 2) / (2.0 * sigma ** 2))
+    for kr, ar, pr in zip(k, a, ph):
+        u = u + ar * np.cos(2.0 * np.pi * kr * x + pr)
+    return u
+
+
+def _cos_sum(x: np.ndarray, kx, ky, a, ph) -> np.ndarray:
+    """sum_q a_q cos(2 pi (kx_q x + ky_q y) + ph_q) on the grid, shape (n, n)
+    [y, x], evaluated as the real part of a rank-(#modes) outer product."""
+    ex = np.exp(2j * np.pi * np.outer(kx, x))            # (modes, n) along x
+    ey = np.exp(2j * np.pi * np.outer(ky, x))            # (modes, n) along y
+    coef = (np.asarray(a) * np.exp(1j * np.asarray(ph)))[:, None]
+    return np.real((coef * ey).T @ ex)
+
+
+def smooth_states_2d(n: int, n_states: int, seed: int, n_modes: int = 16,
+                     kmax: int = 8) -> np.ndarray:
+    """Ensemble of smooth periodic 2D states, unit RMS each.
+
+    Each state is a sum of ``n_modes`` cosines with integer wavevectors in
+    [-kmax, kmax]^2, N(0,1) amplitudes and U(0, 2 pi) phases.  Draw order per
+    state: kx, ky, amplitudes, phases.  Returns shape (n*n, n_states).
+    """
+    rng = np.random.default_rng(seed)
+    x = _grid(n)
+    out = np.empty((n * n, n_states), dtype=np.float64)
+    for s in range(n_states):
+        kx = rng.integers(-kmax, kmax + 1, size=n_modes)
+        ky = rng.integers(-kmax, kmax + 1, size=n_modes)
+        a = rng.standard_normal(n_modes)
+        ph = rng.uniform(0.0, 2.0 * np.pi, size=n_modes)
+        u = _cos_sum(x, kx, ky, a, ph)
+        rms = np.sqrt(np.mean(u * u))
+        if rms == 0.0:
+            u[:] = 1.0
+            rms = 1.0
+        out[:, s] = (u / rms).reshape(-1)
+    return out
+
+
+def white_noise_states(N: int, n_states: int, seed: int) -> np.ndarray:
+    """iid N(0,1) states, shape (N, n_states) (rough stress inputs)."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((N, n_states))
+
+
+def lognormal_field_2d(n: int, seed: int, median: float = 1e-3,
+                       sigma_log: float = 1.0, n_modes: int = 64,
+                       kmax: int = 8) -> np.ndarray:
+    """Smooth lognormal diffusivity field nu(x, y) of shape (n, n) [y, x].
+
+    z is a sum of ``n_modes`` random cosines (wavevectors in [-kmax, kmax]^2,
+    N(0,1) amplitudes, U(0, 2 pi) phases), standardized to mean 0 / std 1;
+    nu = median * exp(sigma_log * z).
+    """
+    rng = np.random.default_rng(seed)
+    kx = rng.integers(-kmax, kmax + 1, size=n_modes)
+    ky = rng.integers(-kmax, kmax + 1, size=n_modes)
+    a = rng.standard_normal(n_modes)
+    ph = rng.uniform(0.0, 2.0 * np.pi, size=n_modes)
+    z = _cos_sum(_grid(n), kx, ky, a, ph)
+    z = (z - z.mean()) / z.std()
+    return median * np.exp(sigma_log * z)
+
+
+# ---------------------------------------------------------------------------
+# The five workloads.  Sizes may be scaled down (``n``) for parity tests that
+# the oracle must finish in seconds; the defaults are the full sizes.
+# ---------------------------------------------------------------------------
+
+def workload_1d(n: int = 1024, seed: int = 0, cfl: float = 4.0,
+                a: float = 1.0, nu: float = 1e-3) -> Problem:
+    """1D periodic advection-diffusion, Gaussian bump + 8 random modes,
+    a=1, nu=1e-3, dt = cfl*dx (default 4 dx), 1024 points."""
+    dx = 1.0 / n
+    u0 = bump_plus_modes(n, seed)
+    return Problem(1, n, dx, cfl * dx, (a, 0.0), nu, None, u0.reshape(n, 1),
+                   meta={"name": "adv-diff-1d", "seed": seed})
+
+
+def workload_2d_ensemble(n: int = 256, n_states: int = 64, seed: int = 1,
+                         cfl: float = 2.0, vel=(1.0, 0.5),
+                         nu: float = 1e-3) -> Problem:
+    """2D periodic advection-diffusion, velocity (1, 0.5), nu=1e-3,
+    dt = 2 dx, ensemble of smooth unit-RMS states."""
+    dx = 1.0 / n
+    st = smooth_states_2d(n, n_states, seed)
+    return Problem(2, n, dx, cfl * dx, tuple(vel), nu, None, st,
+                   meta={"name": "adv-diff-2d-ensemble", "seed": seed})
+
+
+def workload_2d_mixed(n: int = 512, n_smooth: int = 128, n_noise: int = 0,
+                      seed: int = 3) -> Problem:
+    """The 2D ensemble operator at 512^2 with smooth states (plus optional
+    white-noise stress states appended as extra columns)."""
+    dx = 1.0 / n
+    st = smooth_states_2d(n, n_smooth, seed)
+    if n_noise:
+        st = np.concatenate([st, white_noise_states(n * n, n_noise, seed + 1000)],
+                            axis=1)
+    return Problem(2, n, dx, 2.0 * dx, (1.0, 0.5), 1e-3, None, st,
+                   meta={"name": "adv-diff-2d-mixed", "seed": seed})
+
+
+def workload_2d_variable(n: int = 1024, seed: int = 2,
+                         dt_over_dx: float = 0.25) -> Problem:
+    """2D periodic diffusion-advection with lognormal nu(x) (median 1e-3,
+    sigma_log 1), velocity (1, 0), one smooth state, dt = dx/4."""
+    dx = 1.0 / n
+    nuf = lognormal_field_2d(n, seed)
+    st = smooth_states_2d(n, 1, seed + 100)
+    return Problem(2, n, dx, dt_over_dx * dx, (1.0, 0.0), None, nuf, st,
+                   meta={"name": "adv-diff-2d-lognormal", "seed": seed})
+
+
+@dataclass
+class Request:
+    """One served time-stepping request."""
+
+    rid: int
+    arrival: float          # seconds since the stream start
+    problem: Problem
+    n_steps: int
+
+
+def serving_stream(n_requests: int, seed: int = 4, rate: float = 200.0,
+                   sides=(64, 128, 256, 512), dt_mults=(1, 2, 4),
+                   steps_range=(20, 200), nu_range=(1e-4, 1e-2),
+                   vel=(1.0, 0.5)) -> List[Request]:
+    """Poisson arrival stream of independent 2D periodic problems.
+
+    Gaps are exponential with the given mean rate.  Per request, in this draw
+    order: gap, grid side, log-uniform nu, dt multiple of dx, step count; the
+    initial state comes from ``smooth_states_2d`` with a per-request seed.
+    """
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for r in range(n_requests):
+        t += rng.exponential(1.0 / rate)
+        n = int(rng.choice(np.asarray(sides)))
+        nu = float(np.exp(rng.uniform(np.log(nu_range[0]), np.log(nu_range[1]))))
+        mult = int(rng.choice(np.asarray(dt_mults)))
+        steps = int(rng.integers(steps_range[0], steps_range[1] + 1))
+        dx = 1.0 / n
+        st = smooth_states_2d(n, 1, seed * 100003 + r, n_modes=8, kmax=4)
+        out.append(Request(r, t, Problem(2, n, dx, mult * dx, tuple(vel), nu,
+                                         None, st,
+                                         meta={"name": "served", "rid": r}),
+                           steps))
+    return out

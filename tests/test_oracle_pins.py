@@ -1,0 +1,402 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by
+mathematics, independent of the oracle's own formulas (no GPU needed)."""
+from fractions import Fraction
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import lem_inputs as L
+import oracle
+from oracle import expm as E
+from oracle import globalexp as ge
+from oracle import halo as H
+from oracle import krylov as K
+from oracle import lem
+from oracle import operator as op
+from oracle import partition as P
+from oracle import phi as PHI
+from oracle.metrics import rel_l2, rel_linf
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    out = {}
+    for line in open(os.path.join(GOLDEN, name)):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        k, *v = line.split()
+        out[k] = v
+    return out
+
+
+# ---------------------------------------------------------------- expm ----
+
+def test_pade_coefficients_match_published_table():
+    g = _golden("pade13_higham2005.txt")
+    assert [int(x) for x in g["b"]] == [int(c) for c in E.pade_coefficients()]
+    assert float(g["theta13"][0]) == E.THETA_13
+
+
+def _rational_taylor_expm(A_frac, terms_tol=Fraction(1, 10 ** 30)):
+    """exp(A) by its Taylor series in exact rational arithmetic."""
+    n = len(A_frac)
+    nrm = max(sum(abs(x) for x in row) for row in A_frac)
+    S = [[Fraction(int(i == j)) for j in range(n)] for i in range(n)]
+    T = [row[:] for row in S]
+    k = 0
+    while True:
+        k += 1
+        T = [[sum(T[i][l] * A_frac[l][j] for l in range(n)) / k for j in range(n)]
+             for i in range(n)]
+        S = [[S[i][j] + T[i][j] for j in range(n)] for i in range(n)]
+        # tail bound: sum_{j>k} nrm^j/j! <= 2 nrm^{k+1}/(k+1)! once nrm < k/2
+        tail = 2 * nrm ** (k + 1) / math.factorial(k + 1)
+        if k > 2 * nrm and tail < terms_tol:
+            return S
+
+
+@pytest.mark.parametrize("C,mu", [(Fraction(1, 2), Fraction(1, 4)),
+                                  (Fraction(2), Fraction(1, 2)),
+                                  (Fraction(1), Fraction(2))])
+def test_local_expm_matches_exact_rational_taylor(C, mu):
+    # tiny 1D grid n=8, core 2, halo 2 -> local 6x6; dx = 1/8, a = 1
+    n, dx = 8, Fraction(1, 8)
+    dt = C * dx
+    nu = mu * dx * dx / dt
+    W = op.weights(1, n, float(dx), float(dt), (1.0, 0.0), nu=float(nu))
+    box = P.uniform_boxes(1, n, 2, 2)[1]
+    G = P.gather_map(box, 1, n)
+    A_loc = lem.local_matrix(op.sparse(W), G)
+    # exact local matrix: tridiagonal, west mu + C/2, east mu - C/2, diag -2 mu
+    Af = [[Fraction(0)] * 6 for _ in range(6)]
+    for i in range(6):
+        Af[i][i] = -2 * mu
+        if i > 0:
+            Af[i][i - 1] = mu + C / 2
+        if i < 5:
+            Af[i][i + 1] = mu - C / 2
+    assert np.array_equal(A_loc, np.array([[float(x) for x in r] for r in Af]))
+    exact = np.array([[float(x) for x in r] for r in _rational_taylor_expm(Af)])
+    assert np.abs(E.expm(A_loc) - exact).max() <= 4e-16 * max(1.0, np.abs(exact).max())
+
+
+def test_pure_diffusion_block_matches_dst_closed_form():
+    # symmetric tridiagonal Toeplitz (-2mu, mu): eigenvalues -2mu + 2mu cos(j pi/(m+1)),
+    # eigenvectors sqrt(2/(m+1)) sin(i j pi/(m+1)) (the DST-I basis)
+    n, c, h = 256, 64, 16
+    mu = 4.096
+    dx = 1.0 / n
+    dt = 4 * dx
+    W = op.weights(1, n, dx, dt, (0.0, 0.0), nu=mu * dx * dx / dt)
+    box = P.uniform_boxes(1, n, c, h)[2]
+    A_loc = lem.local_matrix(op.sparse(W), P.gather_map(box, 1, n))
+    m = A_loc.shape[0]
+    j = np.arange(1, m + 1)
+    lam = -2 * mu + 2 * mu * np.cos(j * np.pi / (m + 1))
+    Q = np.sqrt(2.0 / (m + 1)) * np.sin(np.outer(j, j) * np.pi / (m + 1))
+    closed = Q @ np.diag(np.exp(lam)) @ Q
+    assert np.abs(E.expm(A_loc) - closed).max() < 1e-14
+
+
+def test_expm_matches_library_on_random_and_large_norm():
+    rng = np.random.default_rng(7)
+    for n, scale in [(5, 0.1), (30, 3.0), (40, 60.0)]:
+        A = rng.standard_normal((n, n)) * scale / np.sqrt(n)
+        ref = sla.expm(A)
+        assert np.abs(E.expm(A) - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert E.expm(np.zeros((0, 0))).shape == (0, 0)
+    assert np.abs(E.expm(np.zeros((3, 3))) - np.eye(3)).max() <= 4.5e-16
+
+
+def test_semigroup_local_and_global():
+    p = L.workload_1d(n=256)
+    W1 = op.from_problem(p)
+    W2 = op.weights(1, p.n, p.dx, 2 * p.dt, p.vel, nu=p.nu)
+    box = P.uniform_boxes(1, p.n, 64, 16)[0]
+    G = P.gather_map(box, 1, p.n)
+    E1 = E.expm(lem.local_matrix(op.sparse(W1), G))
+    E2 = E.expm(lem.local_matrix(op.sparse(W2), G))
+    assert np.abs(E1 @ E1 - E2).max() < 1e-13
+    # two FFT half steps = one step (2D)
+    q = L.workload_2d_ensemble(n=32, n_states=3)
+    Wf = op.from_problem(q)
+    Wh = op.weights(2, q.n, q.dx, q.dt / 2, q.vel, nu=q.nu)
+    u = q.states
+    assert rel_l2(ge.fft_steps(Wh, ge.fft_steps(Wh, u)), ge.fft_steps(Wf, u)) < 1e-14
+
+
+# ------------------------------------------------------------ operator ----
+
+def test_fft_global_matches_dense_expm_1d_2d():
+    for ndim, n, k in [(1, 16, 2), (2, 8, 3)]:
+        W = op.weights(ndim, n, 1.0 / n, 2.0 / n, (1.0, 0.5), nu=3e-2)
+        u = np.random.default_rng(1).standard_normal((W.N, k))
+        ref = sla.expm(op.dense(W)) @ u
+        assert rel_l2(ge.fft_steps(W, u), ref) < 5e-14
+        assert rel_l2(ge.dense_step(W, u), ref) < 5e-14
+
+
+def test_operator_matches_continuum_derivatives():
+    """dt*A u approximates dt(-a.grad u + nu lap u) to second order: this fixes
+    the sign and scale of every stencil weight independently of the weights'
+    formulas (a swapped east/west or a missing factor fails)."""
+    errs = []
+    for n in (64, 128):
+        dx = 1.0 / n
+        dt = 0.5 * dx
+        a, b, nu = 1.3, -0.7, 0.02
+        x = np.arange(n) * dx
+        X, Y = np.meshgrid(x, x, indexing="xy")
+        f = np.sin(2 * np.pi * X) * np.cos(4 * np.pi * Y) + np.cos(2 * np.pi * (X + Y))
+        fx = 2 * np.pi * np.cos(2 * np.pi * X) * np.cos(4 * np.pi * Y) - 2 * np.pi * np.sin(2 * np.pi * (X + Y))
+        fy = -4 * np.pi * np.sin(2 * np.pi * X) * np.sin(4 * np.pi * Y) - 2 * np.pi * np.sin(2 * np.pi * (X + Y))
+        lap = -(4 + 16) * np.pi ** 2 * np.sin(2 * np.pi * X) * np.cos(4 * np.pi * Y) \
+              - 8 * np.pi ** 2 * np.cos(2 * np.pi * (X + Y))
+        W = op.weights(2, n, dx, dt, (a, b), nu=nu)
+        got = op.apply(W, f.reshape(-1))
+        want = dt * (-a * fx - b * fy + nu * lap).reshape(-1)
+        errs.append(np.abs(got - want).max() / np.abs(want).max())
+    assert errs[0] < 5e-3 and errs[1] < errs[0] / 3.5  # second-order convergence
+
+
+def test_advection_moves_downstream():
+    # pure advection of a smooth bump by the global exponential shifts it by a*t
+    n = 512
+    dx = 1.0 / n
+    W = op.weights(1, n, dx, 64 * dx, (1.0, 0.0), nu=0.0)
+    x = np.arange(n) * dx
+    u0 = np.exp(-((x - 0.3) ** 2) / (2 * 0.03 ** 2))
+    u1 = ge.fft_steps(W, u0)
+    assert abs(x[np.argmax(u1)] - (0.3 + 64 * dx)) <= 2 * dx
+
+
+def test_sparse_and_shift_application_agree_and_variable_nu_conservative():
+    p = L.workload_2d_variable(n=32)
+    W = op.from_problem(p)
+    A = op.sparse(W)
+    u = p.states
+    assert np.abs(A @ u - op.apply(W, u)).max() < 1e-15
+    # conservative flux form: column sums vanish, and exp(dt A) preserves mass
+    assert np.abs(np.asarray(A.sum(axis=0))).max() < 1e-12
+    Ed = E.expm(A.toarray())
+    assert abs((Ed @ u).sum() - u.sum()) < 1e-12 * np.abs(u).sum()
+
+
+def test_mass_conservation_global_constant():
+    q = L.workload_2d_ensemble(n=64, n_states=4)
+    W = op.from_problem(q)
+    out = ge.fft_steps(W, q.states, 10)
+    assert np.abs(out.sum(axis=0) - q.states.sum(axis=0)).max() < 1e-10
+
+
+# ----------------------------------------------------------- partition ----
+
+def test_kronecker_identity_2d_local_block():
+    # 2D constant-coefficient box operator = A_x (+) A_y, so expm = expm(A_y) kron expm(A_x)
+    n, c, h = 64, 16, 4
+    dx = 1.0 / n
+    dt = 2 * dx
+    vel = (1.0, 0.5)
+    nu = 1e-3 * 4  # mu = 0.128 * ...
+    W2 = op.weights(2, n, dx, dt, vel, nu=nu)
+    box = P.uniform_boxes(2, n, c, h)[5]
+    A2 = lem.local_matrix(op.sparse(W2), P.gather_map(box, 2, n))
+    Wx = op.weights(1, n, dx, dt, (vel[0], 0.0), nu=nu)
+    Wy = op.weights(1, n, dx, dt, (vel[1], 0.0), nu=nu)
+    b1 = P.uniform_boxes(1, n, c, h)[1]
+    Ax = lem.local_matrix(op.sparse(Wx), P.gather_map(b1, 1, n))
+    Ay = lem.local_matrix(op.sparse(Wy), P.gather_map(b1, 1, n))
+    assert A2.shape == (576, 576)
+    ref = np.kron(E.expm(Ay), E.expm(Ax))
+    assert np.abs(E.expm(A2) - ref).max() < 1e-14
+
+
+def test_maps_are_consistent_permutations():
+    for ndim, n, c, h in [(1, 1024, 64, 16), (2, 64, 16, 4), (2, 48, 16, 7)]:
+        boxes = P.uniform_boxes(ndim, n, c, h)
+        P.check_tiling(boxes, ndim, n)
+        Gc, goff, Sc, soff = P.all_maps(boxes, ndim, n)
+        assert np.array_equal(np.sort(Sc), np.arange(n ** ndim))
+        for k, b in enumerate(boxes):
+            G = Gc[goff[k]:goff[k + 1]]
+            S = Sc[soff[k]:soff[k + 1]]
+            Lx, Ly = P.box_dims(b, ndim)
+            assert len(G) == Lx * Ly
+            assert np.array_equal(G[P.core_local_rows(b, ndim)], S)
+            assert len(np.unique(G)) == len(G)
+    with pytest.raises(ValueError):
+        P.gather_map(P.Box(0, 0, 16, 16, 24), 2, 64)  # 16 + 48 >= 64
+    with pytest.raises(ValueError):
+        P.check_tiling(P.uniform_boxes(2, 64, 16, 4)[1:], 2, 64)
+
+
+def test_uneven_boxes_tile():
+    boxes = [P.Box(0, 0, 32, 32, 4), P.Box(32, 0, 32, 32, 5),
+             P.Box(0, 32, 16, 16, 6), P.Box(16, 32, 16, 16, 4),
+             P.Box(0, 48, 16, 16, 4), P.Box(16, 48, 16, 16, 8),
+             P.Box(32, 32, 32, 32, 7)]
+    P.check_tiling(boxes, 2, 64)
+
+
+# ----------------------------------------------------------------- LEM ----
+
+def test_single_domain_lem_equals_global():
+    for ndim, n in [(1, 64), (2, 16)]:
+        W = op.weights(ndim, n, 1.0 / n, 4.0 / n, (1.0, 0.5), nu=5e-3)
+        u = np.random.default_rng(3).standard_normal((W.N, 2))
+        boxes = [P.Box(0, 0, n, n if ndim == 2 else 1, 0)]
+        got = lem.step(op.sparse(W), boxes, ndim, n, u)
+        assert rel_l2(got, ge.fft_steps(W, u)) < 1e-14
+
+
+def test_lem_error_decreases_with_halo_to_roundoff():
+    p = L.workload_1d()
+    W = op.from_problem(p)
+    A = op.sparse(W)
+    u0 = p.states[:, 0]
+    g10 = ge.fft_steps(W, u0, 10)
+    errs = [rel_l2(lem.run(A, P.uniform_boxes(1, p.n, 64, h), 1, p.n, u0, 10), g10)
+            for h in (4, 8, 12, 16, 20, 24, 28)]
+    assert all(b < a / 3 for a, b in zip(errs, errs[1:]))
+    assert errs[-1] < 1e-10
+
+
+def test_lem_huge_halo_matches_fft_over_100_steps():
+    p = L.workload_1d()
+    W = op.from_problem(p)
+    u = lem.run(op.sparse(W), P.uniform_boxes(1, p.n, 64, 32), 1, p.n,
+                p.states[:, 0], 100)
+    assert rel_l2(u, ge.fft_steps(W, p.states[:, 0], 100)) < 4e-13
+
+
+def test_paper_buffer_example():
+    g = _golden("paper_buffer_example.txt")
+    n = int(g["n"][0]); Ld = float(g["L"][0]); D = int(g["subdomains"][0])
+    dx = Ld / n
+    dt = float(g["C"][0]) * dx
+    nu = float(g["mu"][0]) * dx * dx / dt
+    steps = int(round(float(g["T"][0]) / dt))
+    x = np.arange(n) * dx
+    u0 = np.exp(-(x - Ld / 2) ** 2)
+    W = op.weights(1, n, dx, dt, (1.0, 0.0), nu=nu)
+    A = op.sparse(W)
+    ref = ge.fft_steps(W, u0, steps)
+    good = lem.run(A, P.uniform_boxes(1, n, n // D, int(g["good_buffer"][0])), 1, n, u0, steps)
+    bad = lem.run(A, P.uniform_boxes(1, n, n // D, int(g["bad_buffer"][0])), 1, n, u0, steps)
+    level = float(g["paper_error_level"][0])
+    assert rel_l2(good, ref) < level / 10      # indistinguishable from the global method
+    assert rel_linf(bad, ref) > 0.1            # visibly wrong
+
+
+def test_exp_euler_form_equals_exp_form():
+    p = L.workload_1d(n=256)
+    W = op.from_problem(p)
+    box = P.uniform_boxes(1, p.n, 64, 16)[1]
+    G = P.gather_map(box, 1, p.n)
+    B = lem.local_matrix(op.sparse(W), G)
+    v = p.states[G, 0]
+    assert np.abs(PHI.exp_euler_step(B, v) - E.expm(B) @ v).max() < 1e-13
+    # phi_1 scalar check: z phi_1(z) = e^z - 1
+    z = np.array([[0.7]])
+    assert abs(PHI.phi1_action(z, np.array([1.0]))[0] * 0.7 - math.expm1(0.7)) < 1e-15
+
+
+def test_nonnegative_local_exponential_when_mu_ge_half_c():
+    p = L.workload_1d()
+    W = op.from_problem(p)  # C = 4, mu = 4.096 >= C/2
+    box = P.uniform_boxes(1, p.n, 64, 20)[0]
+    Ek = E.expm(lem.local_matrix(op.sparse(W), P.gather_map(box, 1, p.n)))
+    assert Ek.min() > -1e-15
+    assert Ek.sum(axis=1).max() <= 1.0 + 1e-13
+
+
+# -------------------------------------------------------------- Krylov ----
+
+def test_krylov_full_dimension_reproduces_dense():
+    p = L.workload_1d(n=256)
+    W = op.from_problem(p)
+    box = P.uniform_boxes(1, p.n, 32, 8)[0]
+    B = lem.local_matrix(op.sparse(W), P.gather_map(box, 1, p.n))
+    v = np.random.default_rng(5).standard_normal(B.shape[0])
+    beta, V, Hm, k = K.arnoldi(lambda x: B @ x, v, B.shape[0])
+    approx = beta * V[:, :k] @ E.expm(Hm[:k, :k])[:, 0]
+    assert rel_l2(approx, E.expm(B) @ v) < 1e-13
+    got = K.expv(lambda x: B @ x, v, m=30, tol=1e-15)
+    assert rel_l2(got, E.expm(B) @ v) < 1e-13
+
+
+def test_krylov_fourier_mode_happy_breakdown():
+    W = op.weights(2, 32, 1 / 32, 2 / 32, (1.0, 0.5), nu=1e-2)
+    j = np.arange(32 * 32)
+    th = 2 * np.pi * 3 / 32
+    v = np.exp(1j * th * (j % 32))  # an eigenvector of the circulant operator
+    beta, V, Hm, k = K.arnoldi(lambda x: op.apply(W, x), v, 10)
+    assert k == 1
+    lam = ge.symbol(W)[0, 3]
+    got = beta * V[:, :1] @ E.expm(Hm[:1, :1])[:, 0]
+    assert np.abs(got - np.exp(lam) * v).max() < 1e-13
+
+
+def test_global_krylov_matches_fft_2d():
+    q = L.workload_2d_ensemble(n=64, n_states=2)
+    W = op.from_problem(q)
+    got = ge.krylov_step(W, q.states, m=30, tol=1e-14)
+    assert rel_l2(got, ge.fft_steps(W, q.states)) < 1e-12
+
+
+# ---------------------------------------------------------------- halo ----
+
+def _per_step_inf_error(W, ndim, n, c, h, u):
+    boxes = P.uniform_boxes(ndim, n, c, h)
+    got = lem.step(op.sparse(W), boxes, ndim, n, u)
+    ref = ge.fft_steps(W, u)
+    return np.abs(got - ref).max() / np.abs(u).max()
+
+
+@pytest.mark.parametrize("case", ["1d", "2d"])
+def test_decay_bound_dominates_actual_error(case):
+    if case == "1d":
+        p = L.workload_1d()
+        W, ndim, n, c = op.from_problem(p), 1, p.n, 64
+        u = p.states[:, 0]
+        hs = (8, 12, 16, 20)
+    else:
+        q = L.workload_2d_ensemble(n=64, n_states=1)
+        W, ndim, n, c = op.from_problem(q), 2, q.n, 16
+        u = L.white_noise_states(q.N, 1, 9)[:, 0]
+        hs = (2, 4, 6, 8)
+    G = H.growth_factor(W)
+    for h in hs:
+        box = P.uniform_boxes(ndim, n, c, h)[0]
+        bound = H.eps(H.block_coefficients(W, box, ndim), h, ndim, G)
+        actual = _per_step_inf_error(W, ndim, n, c, h, u)
+        assert actual <= bound
+        assert bound < 1e3 * actual  # and it is not vacuous
+
+
+def test_decay_bound_minimizer_vs_brute_force():
+    for (ws, wsb, w0, Pp, h) in [(6.096, 2.096, -8.192, 0.0, 16),
+                                 (1.512, 0.488, -2.048, 1.024, 9),
+                                 (0.5, 0.0, -1.0, 0.0, 5)]:
+        t = np.linspace(-6, 6, 400001)
+        phi = w0 + Pp + ws * np.exp(t) + wsb * np.exp(-t)
+        with np.errstate(over="ignore", invalid="ignore", divide="ignore"):
+            vals = np.log(np.expm1(phi) / phi) - h * t
+        vals = vals[np.isfinite(vals)]
+        brute = math.log(ws) + vals.min()
+        assert abs(H.side_log_bound(ws, wsb, w0, Pp, h) - brute) < 1e-6
+
+
+def test_halo_rule_and_tie_acceptance():
+    p = L.workload_1d()
+    W = op.from_problem(p)
+    co = H.block_coefficients(W, P.uniform_boxes(1, p.n, 64, 16)[0], 1)
+    h, clamped = H.halo_width(co, 1, 1e-6, 4, 40)
+    assert not clamped and H.eps(co, h, 1) <= 1e-6 < H.eps(co, h - 1, 1)
+    assert H.accepts(co, 1, 1e-6, 4, h) and not H.accepts(co, 1, 1e-6, 4, h + 1)
+    assert H.halo_width(co, 1, 1e-30, 4, 10) == (10, True)
