@@ -1,0 +1,201 @@
+/*
+ * lem.h -- C ABI of the MI355X (gfx950) Local Exponential Method library.
+ *
+ * The Local Exponential Method (L. Bonaventura, "Local Exponential Methods: a
+ * domain decomposition approach to exponential time integration of PDEs",
+ * section 3) advances the semi-discrete linear system du/dt = A u (eq. (3)
+ * with zero forcing, periodic boundaries) by one step dt as follows: the grid
+ * is covered by regions M_i = D_i u B_i (disjoint cores D_i plus buffers B_i);
+ * on each region the local problem (4) -- A restricted to M_i with the
+ * couplings to outside nodes removed (homogeneous Dirichlet data) -- is
+ * advanced by the exponential update (5), which for zero forcing is
+ * v <- exp(dt A_{M_i}) v; the core rows of every local result overwrite the
+ * global state (step 3).  The operator is the centered finite-difference
+ * advection-diffusion operator of the paper's model problem (eq. (2); 1D as
+ * in section 4.1, 2D conservative form as in section 4.3).
+ *
+ * Conventions shared by every call:
+ *  - Status: every call returns a lem_status; on anything but LEM_OK a
+ *    message is available from lem_last_error() (thread-local).
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the legacy
+ *    default stream).  Device work is enqueued asynchronously on it; argument
+ *    validation happens synchronously before anything is enqueued.
+ *  - State layout: a state array holds N = n^ndim grid values for each of
+ *    n_states ensemble members, DOF-major with the ensemble index fastest:
+ *    x[(j*n + i) * n_states + s] for grid point (i, j) (x fastest), float64,
+ *    in DEVICE memory owned by the caller.
+ *  - Ownership: a plan owns every buffer it allocates (index maps, local
+ *    exponential blocks, coefficients, work space) and frees them in
+ *    lem_plan_destroy.  Host arrays passed in are copied during the call.
+ *  - Device-side failures (Krylov estimate above tolerance, non-finite
+ *    values) are latched in the plan's status word; they are reported by
+ *    lem_plan_query (field device_status) after the stream has drained.
+ *  - A plan is not thread-safe: do not call lem_step on one plan from two
+ *    threads at once, nor enqueue two steps of one plan on different streams.
+ */
+#ifndef LEM_H
+#define LEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LEM_OK = 0,
+  LEM_ERR_INVALID = 1,        /* bad argument (sizes, aliasing, NULL)         */
+  LEM_ERR_NOMEM = 2,          /* device or host allocation failed            */
+  LEM_ERR_HIP = 3,            /* a HIP runtime call failed                    */
+  LEM_ERR_NOT_CONVERGED = 4,  /* Krylov estimate above tolerance              */
+  LEM_ERR_BUDGET = 5,         /* request does not fit the memory budget       */
+  LEM_ERR_UNSUPPORTED = 6,    /* valid but not implemented combination        */
+  LEM_ERR_NOT_FOUND = 7       /* unknown request id                           */
+} lem_status;
+
+/* Method used for the local exponential actions. */
+enum {
+  LEM_METHOD_KRYLOV = 0,  /* Arnoldi-Krylov action per block (section 4.3)     */
+  LEM_METHOD_DENSE = 1,   /* stored local exponentials by Pade scaling and
+                             squaring, applied as matrix products (sections 3
+                             and 4: "computed only at the first time step")  */
+  LEM_METHOD_GLOBAL = 2   /* no decomposition (D = 1): global Krylov action  */
+};
+
+/* Arithmetic used to apply stored local exponentials (dense method only). */
+enum {
+  LEM_FP64 = 0,     /* float64 throughout                                    */
+  LEM_FP32 = 1,     /* float32 products, float32 accumulation                */
+  LEM_BF16X2 = 2,   /* bf16 hi/lo split of both operands, 3 products,
+                       float32 accumulation (one correction of the bf16
+                       product)                                              */
+  LEM_BF16X3 = 3    /* bf16 hi/mid/lo split, 6 products, float32 accumulation */
+};
+
+/* The semi-discrete operator: the periodic advection-diffusion operator of
+ * eq. (2), centered finite differences on n (1D) or n x n (2D) points with
+ * spacing dx.  With constant nu the 1D row of dt*A is
+ *   (mu + C/2) u_{i-1} - 2 mu u_i + (mu - C/2) u_{i+1},
+ * C = vel*dt/dx, mu = nu*dt/dx^2, and 2D adds the same along y.  When
+ * nu_field is given (HOST pointer to N values, [j][i], copied by lem_plan)
+ * the diffusion is in conservative flux form with arithmetic face means
+ * mu_{i+1/2} = dt (nu_i + nu_{i+1}) / (2 dx^2). */
+typedef struct {
+  int32_t ndim;            /* 1 or 2                                          */
+  int32_t n;               /* points per axis, >= 3                           */
+  double dx;               /* grid spacing, > 0                               */
+  double vel[2];           /* constant velocity (vel[1] ignored in 1D)        */
+  double nu;               /* constant diffusivity >= 0 (if nu_field == NULL) */
+  const double* nu_field;  /* optional per-node diffusivity, host, or NULL    */
+} lem_operator;
+
+typedef struct {
+  int32_t method;        /* LEM_METHOD_*                                     */
+  int32_t precision;     /* LEM_FP64 / LEM_FP32 / LEM_BF16X2 / LEM_BF16X3    */
+  int32_t n_states;      /* ensemble members per state array, >= 1          */
+  int32_t core;          /* core side c (must divide n); 0 = uneven cores
+                            chosen per 64x64 tile (Krylov, 2D only)          */
+  int32_t halo;          /* buffer width h per side; 0 = decay bound        */
+  int32_t halo_min;      /* clamp range for the decay-bound halo            */
+  int32_t halo_max;
+  double halo_tol;       /* per-step relative bound the halo must meet      */
+  int32_t krylov_m;      /* Krylov dimension; 0 = calibrate per block       */
+  int32_t krylov_m_max;  /* largest dimension allowed (<= 48)               */
+  int32_t max_substeps;  /* largest number of equal sub-steps per step      */
+  double krylov_tol;     /* relative tolerance of the Krylov estimate       */
+  int32_t use_graph;     /* capture lem_step's launches in a HIP graph      */
+  int32_t autotune;      /* time candidate launch shapes at plan time       */
+  int32_t dry_run;       /* 1: build partition and maps on the host only;
+                            no device memory is touched (lem_step fails)     */
+} lem_options;
+
+typedef struct {
+  int32_t n_blocks;        /* number of regions M_i                           */
+  int32_t n_unique;        /* distinct local operators (dense method)         */
+  int64_t n_loc_total;     /* sum of local box sizes |M_i|                    */
+  int32_t n_loc_max;
+  int32_t halo_min, halo_max;  /* range of buffer widths used                */
+  int32_t halo_clamped;    /* blocks whose decay-bound halo hit halo_max      */
+  int32_t m_min, m_max;    /* Krylov dimensions used                          */
+  int32_t substeps_max;
+  int32_t squarings;       /* Pade squarings of the largest dense block       */
+  int64_t bytes_blocks;    /* device bytes of stored local exponentials       */
+  int64_t bytes_work;      /* device bytes of work space                      */
+  int32_t device_status;   /* latched device-side lem_status (0 = fine)       */
+  double max_estimate;     /* largest Krylov error estimate seen (relative)   */
+  double plan_ms;          /* wall time of lem_plan                           */
+  int32_t tile_config;     /* launch shape chosen (autotuner id)              */
+} lem_plan_info;
+
+typedef struct lem_plan_s* lem_plan_t;
+
+/* Fill *opt with defaults: Krylov, FP64, one state, core 64 (1D) / 32 (2D),
+ * decay-bound halo in [4, 64] at tol 1e-8, calibrated m <= 40 at tol 1e-13,
+ * up to 64 sub-steps, no graph, no autotune. */
+void lem_options_default(lem_options* opt);
+
+/* Build a plan for steps of size dt of the operator *op (section 3).
+ * Partitions the grid into cores with buffers (uniform core side, or uneven
+ * cores with per-block buffer widths from the off-diagonal decay bound of
+ * section 2), builds index maps, and for the dense method computes every
+ * distinct local exponential exp(dt A_{M_i}) once by Pade [13/13] scaling and
+ * squaring in float64 on the device (the paper computes these once, at the
+ * first step).  For the Krylov methods, calibrates the Krylov dimension per
+ * block on a pseudo-random probe.  Blocks until the plan is ready.
+ * Errors: LEM_ERR_INVALID for a bad operator/options (c must divide n, a box
+ * c + 2h must be < n unless it is the whole grid), LEM_ERR_NOMEM, LEM_ERR_HIP,
+ * LEM_ERR_NOT_CONVERGED when no (m, sub-step) pair within the limits meets
+ * krylov_tol. */
+lem_status lem_plan(const lem_operator* op, double dt, const lem_options* opt,
+                    void* stream, lem_plan_t* out);
+
+/* Advance x_in by n_steps >= 1 LEM steps (local problems (4), updates (5),
+ * core overwrite) and leave the result in x_out.  x_in and x_out are device
+ * arrays of N * n_states doubles and must not overlap (buffers read
+ * neighbouring cores); x_in is not modified.  Intermediate steps ping-pong
+ * through a plan-owned buffer.  Asynchronous on `stream`. */
+lem_status lem_step(lem_plan_t plan, const double* x_in, double* x_out,
+                    int32_t n_steps, void* stream);
+
+/* y = exp(t A) x on the whole grid (no decomposition) by the Krylov method
+ * of section 4.3, for n_states ensemble members; device arrays, may not
+ * overlap.  Allocates and frees its own work space (a plan with
+ * LEM_METHOD_GLOBAL avoids that for repeated use).  Synchronous. */
+lem_status lem_global_expmv(const lem_operator* op, double t, const double* x,
+                            double* y, int32_t n_states, double tol,
+                            int32_t m_max, void* stream);
+
+/* Plan statistics; device_status requires the plan's stream to have drained
+ * (this call synchronizes the plan's last stream). */
+lem_status lem_plan_query(lem_plan_t plan, lem_plan_info* info);
+
+/* Copy the partition to HOST arrays (any may be NULL):
+ *   boxes  [n_blocks][5] int32: core origin x, origin y, core size x,
+ *          core size y, halo h (1D: origin y = 0, size y = 1);
+ *   gather [n_loc_total] int32: per block in order, the global DOF of every
+ *          local point (row-major, x fastest, wrapped periodically);
+ *   scatter[N] int32: per block in order, the global DOF of every core row. */
+lem_status lem_plan_copy_maps(lem_plan_t plan, int32_t* boxes, int32_t* gather,
+                              int32_t* scatter);
+
+/* Copy the per-block Krylov dimensions and sub-step counts (host arrays of
+ * n_blocks int32 each; either may be NULL). */
+lem_status lem_plan_copy_krylov(lem_plan_t plan, int32_t* m, int32_t* substeps);
+
+/* Copy the core rows of stored local exponential `unique` (dense method) to a
+ * host array of (core rows) x (local size) doubles, row-major. */
+lem_status lem_plan_copy_block(lem_plan_t plan, int32_t unique, double* out,
+                               int32_t* rows, int32_t* cols);
+
+/* Free a plan and everything it owns (waits for its stream).  NULL is ok. */
+lem_status lem_plan_destroy(lem_plan_t plan);
+
+/* Message for the last non-OK status on this thread ("" if none). */
+const char* lem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LEM_H */

@@ -1,0 +1,251 @@
+"""MI355X (gfx950) Local Exponential Method: Python binding of ``liblem.so``.
+
+A thin ctypes layer over the C ABI in ``include/lem.h``: it marshals
+arguments (device pointers of torch tensors, HIP stream handles, host numpy
+arrays) and returns results; every step of the method runs in the library's
+HIP kernels.  There is no fallback: if the library is missing, importing the
+binding's entry points raises.
+
+The Local Exponential Method (L. Bonaventura, section 3) advances du/dt = A u
+on overlapping subdomains: each region (core + buffer) is advanced by its own
+local exponential exp(dt A_M) and the core rows overwrite the global state.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblem.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "lem.h")
+
+LEM_OK = 0
+STATUS_NAMES = {0: "LEM_OK", 1: "LEM_ERR_INVALID", 2: "LEM_ERR_NOMEM", 3: "LEM_ERR_HIP",
+                4: "LEM_ERR_NOT_CONVERGED", 5: "LEM_ERR_BUDGET", 6: "LEM_ERR_UNSUPPORTED",
+                7: "LEM_ERR_NOT_FOUND"}
+METHODS = {"krylov": 0, "dense": 1, "global": 2}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x2": 2, "bf16x3": 3}
+
+
+class LemError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Operator(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("n", ctypes.c_int32), ("dx", ctypes.c_double),
+                ("vel", ctypes.c_double * 2), ("nu", ctypes.c_double),
+                ("nu_field", ctypes.POINTER(ctypes.c_double))]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("n_states", ctypes.c_int32), ("core", ctypes.c_int32),
+                ("halo", ctypes.c_int32), ("halo_min", ctypes.c_int32),
+                ("halo_max", ctypes.c_int32), ("halo_tol", ctypes.c_double),
+                ("krylov_m", ctypes.c_int32), ("krylov_m_max", ctypes.c_int32),
+                ("max_substeps", ctypes.c_int32), ("krylov_tol", ctypes.c_double),
+                ("use_graph", ctypes.c_int32), ("autotune", ctypes.c_int32),
+                ("dry_run", ctypes.c_int32)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("n_blocks", ctypes.c_int32), ("n_unique", ctypes.c_int32),
+                ("n_loc_total", ctypes.c_int64), ("n_loc_max", ctypes.c_int32),
+                ("halo_min", ctypes.c_int32), ("halo_max", ctypes.c_int32),
+                ("halo_clamped", ctypes.c_int32), ("m_min", ctypes.c_int32),
+                ("m_max", ctypes.c_int32), ("substeps_max", ctypes.c_int32),
+                ("squarings", ctypes.c_int32), ("bytes_blocks", ctypes.c_int64),
+                ("bytes_work", ctypes.c_int64), ("device_status", ctypes.c_int32),
+                ("max_estimate", ctypes.c_double), ("plan_ms", ctypes.c_double),
+                ("tile_config", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load liblem.so (built in-tree by ``build.py``); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run paper_1505_02248_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, D, VP = ctypes.POINTER, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p
+    lib.lem_options_default.argtypes = [P(_Options)]
+    lib.lem_options_default.restype = None
+    lib.lem_plan.argtypes = [P(_Operator), D, P(_Options), VP, P(VP)]
+    lib.lem_step.argtypes = [VP, VP, VP, I32, VP]
+    lib.lem_global_expmv.argtypes = [P(_Operator), D, VP, VP, I32, D, I32, VP]
+    lib.lem_plan_query.argtypes = [VP, P(_Info)]
+    lib.lem_plan_copy_maps.argtypes = [VP, P(I32), P(I32), P(I32)]
+    lib.lem_plan_copy_krylov.argtypes = [VP, P(I32), P(I32)]
+    lib.lem_plan_copy_block.argtypes = [VP, I32, P(D), P(I32), P(I32)]
+    lib.lem_plan_destroy.argtypes = [VP]
+    lib.lem_last_error.restype = ctypes.c_char_p
+    for name in ("lem_plan", "lem_step", "lem_global_expmv", "lem_plan_query",
+                 "lem_plan_copy_maps", "lem_plan_copy_krylov", "lem_plan_copy_block",
+                 "lem_plan_destroy"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def declared_functions(header: str = HEADER):
+    """Names of the functions declared in include/lem.h."""
+    text = open(header).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    pat = r"^\s*(?:lem_status|void|const\s+char\s*\*)\s*(lem_[a-z_0-9]+)\s*\("
+    return sorted(set(re.findall(pat, text, flags=re.M)))
+
+
+def _check(status: int) -> None:
+    if status != LEM_OK:
+        raise LemError(status, load().lem_last_error().decode())
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if hasattr(stream, "cuda_stream"):
+        return stream.cuda_stream
+    return int(stream)
+
+
+class Operator:
+    """Periodic advection-diffusion operator of the model problem (eq. (2)),
+    centered finite differences on n (1D) or n x n (2D) points."""
+
+    def __init__(self, ndim: int, n: int, dx: float, vel=(1.0, 0.0), nu: float = 0.0,
+                 nu_field: Optional[np.ndarray] = None):
+        self.ndim, self.n, self.dx = int(ndim), int(n), float(dx)
+        self.vel = (float(vel[0]), float(vel[1]) if len(vel) > 1 else 0.0)
+        self.nu = float(nu)
+        self.nu_field = None if nu_field is None else np.ascontiguousarray(nu_field, dtype=np.float64).reshape(-1)
+
+    @property
+    def N(self) -> int:
+        return self.n ** self.ndim
+
+    @classmethod
+    def from_problem(cls, p) -> "Operator":
+        return cls(p.ndim, p.n, p.dx, p.vel, p.nu if p.nu is not None else 0.0, p.nu_field)
+
+    def _c(self) -> _Operator:
+        o = _Operator()
+        o.ndim, o.n, o.dx = self.ndim, self.n, self.dx
+        o.vel[0], o.vel[1] = self.vel
+        o.nu = self.nu
+        if self.nu_field is not None:
+            if self.nu_field.size != self.N:
+                raise ValueError("nu_field must have N entries")
+            o.nu_field = self.nu_field.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        else:
+            o.nu_field = None
+        return o
+
+
+def _tensor_ptr(t, N: int, ns: int) -> int:
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float64:
+        raise TypeError("state must be a float64 CUDA (HIP) tensor")
+    if not t.is_contiguous() or t.numel() != N * ns:
+        raise ValueError(f"state must be contiguous with {N * ns} elements")
+    return t.data_ptr()
+
+
+class Plan:
+    """A planned LEM stepper (``lem_plan``); see include/lem.h."""
+
+    def __init__(self, op: Operator, dt: float, method: str = "krylov",
+                 precision: str = "fp64", n_states: int = 1, core: int = 0,
+                 halo: int = 0, halo_min: int = 4, halo_max: int = 64,
+                 halo_tol: float = 1e-8, krylov_m: int = 0, krylov_m_max: int = 40,
+                 max_substeps: int = 64, krylov_tol: float = 1e-13,
+                 use_graph: bool = False, autotune: bool = False, dry_run: bool = False,
+                 stream=None):
+        lib = load()
+        o = _Options()
+        lib.lem_options_default(ctypes.byref(o))
+        o.method = METHODS[method]
+        o.precision = PRECISIONS[precision]
+        o.n_states, o.core, o.halo = n_states, core, halo
+        o.halo_min, o.halo_max, o.halo_tol = halo_min, halo_max, halo_tol
+        o.krylov_m, o.krylov_m_max, o.max_substeps = krylov_m, krylov_m_max, max_substeps
+        o.krylov_tol = krylov_tol
+        o.use_graph, o.autotune, o.dry_run = int(use_graph), int(autotune), int(dry_run)
+        self.op, self.dt, self.n_states, self.method = op, float(dt), int(n_states), method
+        self._op_c = op._c()
+        h = ctypes.c_void_p()
+        st = 0 if dry_run else _stream_handle(stream)
+        _check(lib.lem_plan(ctypes.byref(self._op_c), self.dt, ctypes.byref(o),
+                            ctypes.c_void_p(st), ctypes.byref(h)))
+        self._h = h
+
+    def step(self, x_in, x_out, n_steps: int = 1, stream=None) -> None:
+        N, ns = self.op.N, self.n_states
+        _check(load().lem_step(self._h, ctypes.c_void_p(_tensor_ptr(x_in, N, ns)),
+                               ctypes.c_void_p(_tensor_ptr(x_out, N, ns)), int(n_steps),
+                               ctypes.c_void_p(_stream_handle(stream))))
+
+    def query(self) -> dict:
+        info = _Info()
+        _check(load().lem_plan_query(self._h, ctypes.byref(info)))
+        return {f: getattr(info, f) for f, _ in _Info._fields_}
+
+    def maps(self):
+        """(boxes [nb, 5], gather [sum n_loc], scatter [N]) as int32 arrays."""
+        q = self.query()
+        boxes = np.zeros((q["n_blocks"], 5), dtype=np.int32)
+        gather = np.zeros(q["n_loc_total"], dtype=np.int32)
+        scatter = np.zeros(self.op.N, dtype=np.int32)
+        P = ctypes.POINTER(ctypes.c_int32)
+        _check(load().lem_plan_copy_maps(self._h, boxes.ctypes.data_as(P),
+                                         gather.ctypes.data_as(P), scatter.ctypes.data_as(P)))
+        return boxes, gather, scatter
+
+    def krylov(self):
+        nb = max(self.query()["n_blocks"], 1)
+        m = np.zeros(nb, dtype=np.int32)
+        s = np.zeros(nb, dtype=np.int32)
+        P = ctypes.POINTER(ctypes.c_int32)
+        _check(load().lem_plan_copy_krylov(self._h, m.ctypes.data_as(P), s.ctypes.data_as(P)))
+        return m, s
+
+    def block(self, unique: int = 0) -> np.ndarray:
+        r, c = ctypes.c_int32(), ctypes.c_int32()
+        _check(load().lem_plan_copy_block(self._h, unique, None, ctypes.byref(r), ctypes.byref(c)))
+        out = np.zeros((r.value, c.value), dtype=np.float64)
+        _check(load().lem_plan_copy_block(self._h, unique,
+                                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                          None, None))
+        return out
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) and self._h.value:
+            load().lem_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def global_expmv(op: Operator, t: float, x, y, n_states: int = 1, tol: float = 1e-13,
+                 m_max: int = 40, stream=None) -> None:
+    """y = exp(t A) x on the whole grid (``lem_global_expmv``)."""
+    N = op.N
+    oc = op._c()
+    _check(load().lem_global_expmv(ctypes.byref(oc), float(t),
+                                   ctypes.c_void_p(_tensor_ptr(x, N, n_states)),
+                                   ctypes.c_void_p(_tensor_ptr(y, N, n_states)), int(n_states),
+                                   float(tol), int(m_max), ctypes.c_void_p(_stream_handle(stream))))

@@ -1,0 +1,764 @@
+// Dense local exponentials and their application (gfx950).
+//
+// Sections 3 and 4 of the paper store the local matrices exp(dt A_{M_i}) (or
+// phi) of small subdomains, computed once by Pade approximation with scaling
+// and squaring, and reuse them every step.  Here:
+//
+//  plan time (float64 throughout):
+//   assemble_kernel     dense dt*A_M of every distinct local operator
+//   dgemm_kernel        batched C = A B on FP64 MFMA (v_mfma_f64_16x16x4):
+//                       the powers A^2, A^4, A^6, the two Pade polynomials
+//                       and the squarings
+//   lincomb_kernel      elementwise linear combinations of those powers
+//   lu_* kernels        Q X = P by LU with partial pivoting (right-hand
+//                       sides eliminated alongside), then back substitution
+//   pack_kernel         core rows of exp(dt A_M) into MFMA fragment order,
+//                       in float64, float32 and bf16 hi/mid/lo pieces
+//
+//  step time:
+//   apply_*_kernel      Y_k = E[core, :] X_k for every block k at once: the
+//                       B operand rows are gathered from the global state by
+//                       the box (periodic wrap), the epilogue writes the core
+//                       rows straight into the new state (fused scatter).
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+#include "lem_device.hpp"
+#include "lem_launch.h"
+
+namespace lem {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// --------------------------------------------------------------- assembly --
+
+// One distinct local operator: box dims and stencil weights of dt*A.
+struct DenseOp {
+  double w0, wW, wE, wS, wN;
+  int Lx, Ly;
+};
+
+__global__ void assemble_kernel(const DenseOp* ops, double* A, int nl) {
+  const int u = blockIdx.y;
+  const DenseOp o = ops[u];
+  double* M = A + (int64_t)u * nl * nl;
+  const int64_t total = (int64_t)nl * nl;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e / nl), c = (int)(e - (int64_t)r * nl);
+    const int ry = r / o.Lx, rx = r - ry * o.Lx;
+    double v = 0.0;
+    if (c == r) v = o.w0;
+    else if (c == r - 1 && rx > 0) v = o.wW;
+    else if (c == r + 1 && rx < o.Lx - 1) v = o.wE;
+    else if (c == r - o.Lx && ry > 0) v = o.wS;
+    else if (c == r + o.Lx && ry < o.Ly - 1) v = o.wN;
+    M[e] = v;
+  }
+}
+
+// Max column sum |.| per matrix (the 1-norm) -> norms[u].
+__global__ void norm1_kernel(const double* A, int nl, double* norms) {
+  const int u = blockIdx.x;
+  const double* M = A + (int64_t)u * nl * nl;
+  __shared__ double red[16];
+  double best = 0.0;
+  for (int c = threadIdx.x; c < nl; c += blockDim.x) {
+    double s = 0.0;
+    for (int r = 0; r < nl; ++r) s += fabs(M[(int64_t)r * nl + c]);
+    best = fmax(best, s);
+  }
+  best = wave_max(best);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) b = fmax(b, red[w]);
+    norms[u] = b;
+  }
+}
+
+// A <- A * 2^-s[u]
+__global__ void scale_pow2_kernel(double* A, int nl, const int* s) {
+  const int u = blockIdx.y;
+  double* M = A + (int64_t)u * nl * nl;
+  const int64_t total = (int64_t)nl * nl;
+  const int e2 = -s[u];
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x)
+    M[e] = ldexp(M[e], e2);
+}
+
+// out = c0 X0 + c1 X1 + c2 X2 + c3 X3 + d I  (any Xi may be null)
+struct LinComb {
+  const double* X[4];
+  double c[4];
+  double d;
+  double* out;
+  int nl;
+  int64_t stride;  // matrix stride of every operand (batched)
+};
+
+__global__ void lincomb_kernel(LinComb p) {
+  const int u = blockIdx.y;
+  const int64_t off = (int64_t)u * p.stride;
+  const int64_t total = (int64_t)p.nl * p.nl;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (p.X[q]) v = fma(p.c[q], p.X[q][off + e], v);
+    const int r = (int)(e / p.nl);
+    if (e - (int64_t)r * p.nl == r) v += p.d;
+    p.out[off + e] = v;
+  }
+}
+
+// P = V + U, Q = V - U (in place: V -> P, U -> Q)
+__global__ void pade_pq_kernel(double* V, double* U, int64_t total) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double v = V[e], u = U[e];
+    V[e] = v + u;
+    U[e] = v - u;
+  }
+}
+
+// ------------------------------------------------------------------ DGEMM --
+// C[u] = A[u] * B[u], row-major nl x nl, FP64 MFMA 16x16x4.  64x64 tile per
+// workgroup of 256 threads; each wave owns a 32x32 quarter (2x2 MFMA tiles).
+// Fragment layouts (16x16x4, f64): lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; accumulator register r of lane l is D[4*(l/16)+r][l%16].
+__global__ __launch_bounds__(256) void dgemm_kernel(const double* A, const double* B,
+                                                    double* C, int nl, int64_t stride) {
+  constexpr int BM = 64, BK = 16;
+  __shared__ double As[BM][BK + 1];
+  __shared__ double Bs[BK][BM + 2];
+  const int u = blockIdx.z;
+  const double* Ab = A + (int64_t)u * stride;
+  const double* Bb = B + (int64_t)u * stride;
+  double* Cb = C + (int64_t)u * stride;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BM;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wr = (wv >> 1) * 32, wc = (wv & 1) * 32;
+  d4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = (d4){0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < nl; k0 += BK) {
+    {  // A tile 64 x 16
+      const int r = tid >> 2, c = (tid & 3) * 4;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int gr = m0 + r, gc = k0 + c + q;
+        As[r][c + q] = (gr < nl && gc < nl) ? Ab[(int64_t)gr * nl + gc] : 0.0;
+      }
+    }
+    {  // B tile 16 x 64
+      const int r = tid >> 4, c = (tid & 15) * 4;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int gr = k0 + r, gc = n0 + c + q;
+        Bs[r][c + q] = (gr < nl && gc < nl) ? Bb[(int64_t)gr * nl + gc] : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      double af[2], bfr[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) af[i] = As[wr + i * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bfr[j] = Bs[kk + (lane >> 4)][wc + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gr = m0 + wr + i * 16 + 4 * (lane >> 4) + r;
+        const int gc = n0 + wc + j * 16 + (lane & 15);
+        if (gr < nl && gc < nl) Cb[(int64_t)gr * nl + gc] = acc[i][j][r];
+      }
+}
+
+// ------------------------------------------------------------- LU solve --
+// Solve Q X = P (batched, nl x nl, right-hand sides P overwritten by X).
+// Column step j: choose the pivot row, swap it into row j in Q and P, store
+// the multipliers l_ij = Q[i][j]/Q[j][j] in Q[i][j]; then eliminate below.
+__global__ __launch_bounds__(256) void lu_pivot_kernel(double* Q, double* P, int nl,
+                                                       int64_t stride, int j) {
+  const int u = blockIdx.x;
+  double* Qb = Q + (int64_t)u * stride;
+  double* Pb = P + (int64_t)u * stride;
+  __shared__ double bv[4];
+  __shared__ int bi[4];
+  __shared__ int sp;
+  const int tid = threadIdx.x;
+  double best = -1.0;
+  int bidx = j;
+  for (int i = j + tid; i < nl; i += 256) {
+    const double a = fabs(Qb[(int64_t)i * nl + j]);
+    if (a > best) { best = a; bidx = i; }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ob = __shfl_xor(best, off, 64);
+    const int oi = __shfl_xor(bidx, off, 64);
+    if (ob > best || (ob == best && oi < bidx)) { best = ob; bidx = oi; }
+  }
+  if ((tid & 63) == 0) { bv[tid >> 6] = best; bi[tid >> 6] = bidx; }
+  __syncthreads();
+  if (tid == 0) {
+    double b = bv[0];
+    int p = bi[0];
+    for (int w = 1; w < 4; ++w)
+      if (bv[w] > b || (bv[w] == b && bi[w] < p)) { b = bv[w]; p = bi[w]; }
+    sp = p;
+  }
+  __syncthreads();
+  const int p = sp;
+  if (p != j) {
+    for (int k = tid; k < 2 * nl; k += 256) {
+      double* M = k < nl ? Qb : Pb;
+      const int kk = k < nl ? k : k - nl;
+      const double t = M[(int64_t)j * nl + kk];
+      M[(int64_t)j * nl + kk] = M[(int64_t)p * nl + kk];
+      M[(int64_t)p * nl + kk] = t;
+    }
+    __syncthreads();
+  }
+  const double inv = 1.0 / Qb[(int64_t)j * nl + j];
+  for (int i = j + 1 + tid; i < nl; i += 256) Qb[(int64_t)i * nl + j] *= inv;
+}
+
+// rows i > j: Q[i][k] -= l_ij Q[j][k] (k > j), P[i][k] -= l_ij P[j][k] (all k)
+__global__ void lu_elim_kernel(double* Q, double* P, int nl, int64_t stride, int j) {
+  const int u = blockIdx.z;
+  double* Qb = Q + (int64_t)u * stride;
+  double* Pb = P + (int64_t)u * stride;
+  const int i = j + 1 + blockIdx.y;
+  if (i >= nl) return;
+  const double l = Qb[(int64_t)i * nl + j];
+  const int qcols = nl - j - 1;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < qcols + nl;
+       c += gridDim.x * blockDim.x) {
+    if (c < qcols) {
+      const int k = j + 1 + c;
+      Qb[(int64_t)i * nl + k] = fma(-l, Qb[(int64_t)j * nl + k], Qb[(int64_t)i * nl + k]);
+    } else {
+      const int k = c - qcols;
+      Pb[(int64_t)i * nl + k] = fma(-l, Pb[(int64_t)j * nl + k], Pb[(int64_t)i * nl + k]);
+    }
+  }
+}
+
+// back substitution step j: rows i < j: P[i][k] -= Q[i][j] * (P[j][k] / Q[j][j])
+// (row j itself is divided by its pivot at the very end).
+__global__ void lu_back_kernel(const double* Q, double* P, int nl, int64_t stride, int j) {
+  const int u = blockIdx.z;
+  const double* Qb = Q + (int64_t)u * stride;
+  double* Pb = P + (int64_t)u * stride;
+  const int i = blockIdx.y;
+  if (i >= j) return;
+  const double f = Qb[(int64_t)i * nl + j] / Qb[(int64_t)j * nl + j];
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nl; k += gridDim.x * blockDim.x)
+    Pb[(int64_t)i * nl + k] = fma(-f, Pb[(int64_t)j * nl + k], Pb[(int64_t)i * nl + k]);
+}
+
+__global__ void lu_diag_kernel(const double* Q, double* P, int nl, int64_t stride) {
+  const int u = blockIdx.z;
+  const double* Qb = Q + (int64_t)u * stride;
+  double* Pb = P + (int64_t)u * stride;
+  const int i = blockIdx.y;
+  const double inv = 1.0 / Qb[(int64_t)i * nl + i];
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nl; k += gridDim.x * blockDim.x)
+    Pb[(int64_t)i * nl + k] *= inv;
+}
+
+// ------------------------------------------------------------------- pack --
+// Core rows of R (nl x nl) -> fragment-ordered operands.  Rows R_core x cols
+// K = nl are padded to multiples of 16 (rows) and 32 (cols) with zeros.
+//  f64/f32: [rt][kk][lane]        = E[rt*16 + lane%16][kk*4 + lane/16]
+//  bf16   : [piece][rt][ks][lane][e] = piece of E[rt*16 + lane%16][ks*32 + 8*(lane/16) + e]
+struct PackArgs {
+  const double* R;
+  int nl, Lx, h, cx, cy, ndim;
+  int rows, rows_p, cols_p;  // core rows, padded rows, padded cols
+  double* e64;
+  float* e32;
+  __hip_bfloat16* e16;       // 3 pieces
+  double* core_out;          // plain copy of the core rows [rows][nl] (may be null)
+};
+
+__device__ __forceinline__ int core_to_local(int r, int cx, int h, int Lx, int ndim) {
+  if (ndim == 1) return h + r;
+  const int ry = r / cx, rx = r - ry * cx;
+  return (h + ry) * Lx + h + rx;
+}
+
+__global__ void pack_kernel(PackArgs a) {
+  const int64_t total = (int64_t)a.rows_p * a.cols_p;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e / a.cols_p), c = (int)(e - (int64_t)r * a.cols_p);
+    double v = 0.0;
+    if (r < a.rows && c < a.nl) {
+      const int lr = core_to_local(r, a.cx, a.h, a.Lx, a.ndim);
+      v = a.R[(int64_t)lr * a.nl + c];
+      if (a.core_out) a.core_out[(int64_t)r * a.nl + c] = v;
+    }
+    const int rt = r >> 4, ri = r & 15;
+    {  // f64 / f32 fragments (k-step 4)
+      const int kk = c >> 2, kq = c & 3;
+      const int64_t idx = (((int64_t)rt * (a.cols_p >> 2) + kk) << 6) + (kq << 4) + ri;
+      a.e64[idx] = v;
+      a.e32[idx] = (float)v;
+    }
+    {  // bf16 pieces (k-step 32)
+      const int ks = c >> 5, kr = c & 31;
+      const int lane = ri + 16 * (kr >> 3), el = kr & 7;
+      const int64_t idx = ((((int64_t)rt * (a.cols_p >> 5) + ks) << 6) + lane) * 8 + el;
+      const int64_t piece = (int64_t)a.rows_p * a.cols_p;
+      const __hip_bfloat16 hi = __double2bfloat16(v);
+      const double r1 = v - (double)__bfloat162float(hi);
+      const __hip_bfloat16 mid = __double2bfloat16(r1);
+      const double r2 = r1 - (double)__bfloat162float(mid);
+      const __hip_bfloat16 lo = __double2bfloat16(r2);
+      a.e16[idx] = hi;
+      a.e16[piece + idx] = mid;
+      a.e16[2 * piece + idx] = lo;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ apply --
+// Block table entry of the dense apply: box and which stored block it uses.
+struct DBlock {
+  int ox, oy, cx, cy, h, Lx, Ly;
+  int unique;
+};
+
+struct ApplyArgs {
+  const DBlock* blocks;
+  const void* E;        // packed operand (f64, f32 or bf16 pieces)
+  int64_t e_stride;     // elements per stored block (per piece for bf16)
+  const double* x_in;
+  double* x_out;
+  int n, ndim, ns;      // grid side, dimension, ensemble size
+  int rows, rows_p, cols, cols_p;
+  int n_blocks, row_tiles, col_tiles;
+};
+
+__device__ __forceinline__ int64_t dense_gather(const DBlock& b, int l, int n, int ndim) {
+  const int ly = l / b.Lx, lx = l - ly * b.Lx;
+  const int gx = wrap(b.ox - b.h + lx, n);
+  if (ndim == 1) return gx;
+  const int gy = wrap(b.oy - b.h + ly, n);
+  return (int64_t)gy * n + gx;
+}
+
+__device__ __forceinline__ int64_t dense_scatter(const DBlock& b, int r, int n, int ndim) {
+  if (ndim == 1) return b.ox + r;
+  const int ry = r / b.cx, rx = r - ry * b.cx;
+  return (int64_t)(b.oy + ry) * n + b.ox + rx;
+}
+
+// XCD-aware order: consecutive workgroup ids are spread over the 8 XCDs, so
+// give each XCD a contiguous range of (block, row tile) work items; spatially
+// adjacent blocks then share their halo rows in one L2.
+__device__ __forceinline__ int xcd_remap(int bid, int total) {
+  const int per = total / 8, rem = total % 8;
+  const int xcd = bid % 8, idx = bid / 8;
+  return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
+// FP64 / FP32 apply.  Workgroup = 4 waves, tile = (4*WM) core rows x 64
+// states of one block; wave w owns rows [w*WM, (w+1)*WM).  The X chunk of 16
+// local rows x 64 states is gathered into LDS (double buffered); A fragments
+// stream from the packed E (L2-resident: all blocks share it when the
+// operator is translation invariant).
+template <typename T, int WM>
+__global__ __launch_bounds__(256) void apply_mfma_kernel(ApplyArgs a) {
+  constexpr int BN = 64, KC = 16, RT = WM / 16, CT = BN / 16;
+  constexpr int XS = BN + 2;  // padded LDS row
+  __shared__ T Xs[2][KC][XS];
+  typedef typename std::conditional<sizeof(T) == 8, d4, f4>::type acc_t;
+
+  const int total = a.n_blocks * a.row_tiles * a.col_tiles;
+  const int item = xcd_remap(blockIdx.x, total);
+  const int ct0 = item % a.col_tiles;
+  const int rest = item / a.col_tiles;
+  const int rtile = rest % a.row_tiles;
+  const int blk = rest / a.row_tiles;
+  const DBlock b = a.blocks[blk];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int row0 = rtile * 4 * WM + wv * WM;  // first core row of this wave
+  const int col0 = ct0 * BN;
+  const T* E = reinterpret_cast<const T*>(a.E) + (int64_t)b.unique * a.e_stride;
+  const int ksteps = a.cols_p >> 2;
+
+  acc_t acc[RT][CT];
+#pragma unroll
+  for (int i = 0; i < RT; ++i)
+#pragma unroll
+    for (int j = 0; j < CT; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
+
+  // X chunk loader: thread -> (row tid/16, 4 states)
+  const int xr = tid >> 4, xc = (tid & 15) * 4;
+  auto load_x = [&](int k0, double (&v)[4]) {
+    const int l = k0 + xr;
+    if (l < a.cols) {
+      const int64_t g = dense_gather(b, l, a.n, a.ndim);
+      const double* src = a.x_in + g * a.ns + col0 + xc;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = src[q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = 0.0;
+    }
+  };
+  const int nchunks = a.cols_p / KC;
+  double xv[4];
+  load_x(0, xv);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) Xs[0][xr][xc + q] = (T)xv[q];
+  __syncthreads();
+
+  const bool wave_live = row0 < a.rows_p;
+  for (int ch = 0; ch < nchunks; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < nchunks) load_x((ch + 1) * KC, xv);
+    if (wave_live) {
+      T af[4][RT];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+        for (int i = 0; i < RT; ++i) {
+          const int rt = (row0 >> 4) + i;
+          af[kk][i] = E[(((int64_t)rt * ksteps + ch * 4 + kk) << 6) + lane];
+        }
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        T bfr[CT];
+#pragma unroll
+        for (int j = 0; j < CT; ++j) bfr[j] = Xs[buf][kk * 4 + (lane >> 4)][j * 16 + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < RT; ++i)
+#pragma unroll
+          for (int j = 0; j < CT; ++j) {
+            if constexpr (sizeof(T) == 8)
+              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[kk][i], bfr[j], acc[i][j], 0, 0, 0);
+            else
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[kk][i], bfr[j], acc[i][j], 0, 0, 0);
+          }
+      }
+    }
+    if (ch + 1 < nchunks) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Xs[buf ^ 1][xr][xc + q] = (T)xv[q];
+    }
+    __syncthreads();
+  }
+  if (!wave_live) return;
+#pragma unroll
+  for (int i = 0; i < RT; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = row0 + i * 16 + 4 * (lane >> 4) + r;
+      if (row >= a.rows) continue;
+      const int64_t g = dense_scatter(b, row, a.n, a.ndim);
+      double* dst = a.x_out + g * a.ns + col0 + (lane & 15);
+#pragma unroll
+      for (int j = 0; j < CT; ++j) dst[j * 16] = (double)acc[i][j][r];
+    }
+}
+
+// Split-bf16 apply: E = E_hi + E_mid + E_lo and X = X_hi + X_mid + X_lo are
+// multiplied term by term on bf16 MFMA (16x16x32) with float32 accumulation.
+// NT = 3 uses hi*hi + hi*lo' + lo'*hi with 2-piece operands (lo' = mid);
+// NT = 6 adds hi*lo + lo*hi + mid*mid of the 3-piece split.
+// Fragment layout (16x16x32 bf16): lane l supplies A[l%16][8*(l/16) + e] and
+// B[8*(l/16) + e][l%16] for e = 0..7.
+template <int NTERMS, int WM>
+__global__ __launch_bounds__(256) void apply_bf16_kernel(ApplyArgs a) {
+  constexpr int BN = 64, KC = 32, RT = WM / 16, CT = BN / 16;
+  // LDS: 3 pieces of the X chunk, stored per (col, k) so that a lane's 8
+  // consecutive k values are one 16-byte read.
+  __shared__ bf16x8 Xs[3][BN][KC / 8 + 1];
+  const int total = a.n_blocks * a.row_tiles * a.col_tiles;
+  const int item = xcd_remap(blockIdx.x, total);
+  const int ct0 = item % a.col_tiles;
+  const int rest = item / a.col_tiles;
+  const int rtile = rest % a.row_tiles;
+  const int blk = rest / a.row_tiles;
+  const DBlock b = a.blocks[blk];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int row0 = rtile * 4 * WM + wv * WM;
+  const int col0 = ct0 * BN;
+  const bf16x8* E = reinterpret_cast<const bf16x8*>(a.E);
+  const int64_t estride8 = a.e_stride / 8;  // per piece, in 8-element groups
+  const int ksteps = a.cols_p >> 5;
+  const int64_t eoff = (int64_t)b.unique * 3 * estride8;
+
+  f4 acc[RT][CT];
+#pragma unroll
+  for (int i = 0; i < RT; ++i)
+#pragma unroll
+    for (int j = 0; j < CT; ++j) acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
+
+  // chunk loader: 32 local rows x 64 states; thread -> (row tid/8, 8 states)
+  const int xr = tid >> 3, xc = (tid & 7) * 8;
+  const bool wave_live = row0 < a.rows_p;
+  for (int ch = 0; ch < ksteps; ++ch) {
+    {
+      const int l = ch * KC + xr;
+      double v[8];
+      if (l < a.cols) {
+        const int64_t g = dense_gather(b, l, a.n, a.ndim);
+        const double* src = a.x_in + g * a.ns + col0 + xc;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = src[q];
+      } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = 0.0;
+      }
+      __hip_bfloat16* base = reinterpret_cast<__hip_bfloat16*>(&Xs[0][0][0]);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const __hip_bfloat16 hi = __double2bfloat16(v[q]);
+        const double r1 = v[q] - (double)__bfloat162float(hi);
+        const __hip_bfloat16 mid = __double2bfloat16(r1);
+        const double r2 = r1 - (double)__bfloat162float(mid);
+        const __hip_bfloat16 lo = __double2bfloat16(r2);
+        const int col = xc + q;
+        const int64_t e = ((int64_t)col * (KC / 8 + 1) + (xr >> 3)) * 8 + (xr & 7);
+        base[e] = hi;
+        base[(int64_t)BN * (KC / 8 + 1) * 8 + e] = mid;
+        base[2 * (int64_t)BN * (KC / 8 + 1) * 8 + e] = lo;
+      }
+    }
+    __syncthreads();
+    if (wave_live) {
+      bf16x8 bx[3][CT];
+#pragma unroll
+      for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int j = 0; j < CT; ++j) bx[p][j] = Xs[p][j * 16 + (lane & 15)][lane >> 4];
+#pragma unroll
+      for (int i = 0; i < RT; ++i) {
+        const int rt = (row0 >> 4) + i;
+        const int64_t fi = ((int64_t)rt * ksteps + ch) * 64 + lane;
+        const bf16x8 ehi = E[eoff + fi];
+        const bf16x8 emid = E[eoff + estride8 + fi];
+        const bf16x8 elo = E[eoff + 2 * estride8 + fi];
+#pragma unroll
+        for (int j = 0; j < CT; ++j) {
+          f4 c = acc[i][j];
+          // small terms first, the dominant product last
+          if (NTERMS == 6) {
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(emid, bx[1][j], c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(elo, bx[0][j], c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ehi, bx[2][j], c, 0, 0, 0);
+          }
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(emid, bx[0][j], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ehi, bx[1][j], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ehi, bx[0][j], c, 0, 0, 0);
+          acc[i][j] = c;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (!wave_live) return;
+#pragma unroll
+  for (int i = 0; i < RT; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = row0 + i * 16 + 4 * (lane >> 4) + r;
+      if (row >= a.rows) continue;
+      const int64_t g = dense_scatter(b, row, a.n, a.ndim);
+      double* dst = a.x_out + g * a.ns + col0 + (lane & 15);
+#pragma unroll
+      for (int j = 0; j < CT; ++j) dst[j * 16] = (double)acc[i][j][r];
+    }
+}
+
+// Small ensembles (ns not a multiple of 64): one thread per (core row, state)
+// with the plain row-major core block, float64 or float32 arithmetic.
+template <typename T>
+__global__ void apply_simple_kernel(ApplyArgs a, const double* core) {
+  const int64_t total = (int64_t)a.n_blocks * a.rows * a.ns;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int s = (int)(e % a.ns);
+    const int64_t t = e / a.ns;
+    const int row = (int)(t % a.rows);
+    const int blk = (int)(t / a.rows);
+    const DBlock b = a.blocks[blk];
+    const double* Er = core + ((int64_t)b.unique * a.rows + row) * a.cols;
+    T acc = 0;
+    for (int l = 0; l < a.cols; ++l) {
+      const int64_t g = dense_gather(b, l, a.n, a.ndim);
+      acc = fma((T)Er[l], (T)a.x_in[g * a.ns + s], acc);
+    }
+    a.x_out[dense_scatter(b, row, a.n, a.ndim) * a.ns + s] = (double)acc;
+  }
+}
+
+// -------------------------------------------------------------- launchers --
+
+static inline dim3 grid1(int64_t total, int per = 256, int cap = 8192) {
+  int64_t g = (total + per - 1) / per;
+  if (g > cap) g = cap;
+  if (g < 1) g = 1;
+  return dim3((unsigned)g);
+}
+
+hipError_t dense_assemble(const void* ops, double* A, int nl, int nu, hipStream_t st) {
+  dim3 g = grid1((int64_t)nl * nl);
+  g.y = nu;
+  hipLaunchKernelGGL(assemble_kernel, g, dim3(256), 0, st, (const DenseOp*)ops, A, nl);
+  return hipGetLastError();
+}
+
+size_t dense_op_size() { return sizeof(DenseOp); }
+
+void dense_op_fill(void* dst, int i, double w0, double wW, double wE, double wS,
+                   double wN, int Lx, int Ly) {
+  DenseOp* o = (DenseOp*)dst + i;
+  o->w0 = w0; o->wW = wW; o->wE = wE; o->wS = wS; o->wN = wN; o->Lx = Lx; o->Ly = Ly;
+}
+
+hipError_t dense_norm1(const double* A, int nl, int nu, double* norms, hipStream_t st) {
+  hipLaunchKernelGGL(norm1_kernel, dim3(nu), dim3(256), 0, st, A, nl, norms);
+  return hipGetLastError();
+}
+
+hipError_t dense_scale_pow2(double* A, int nl, int nu, const int* s, hipStream_t st) {
+  dim3 g = grid1((int64_t)nl * nl);
+  g.y = nu;
+  hipLaunchKernelGGL(scale_pow2_kernel, g, dim3(256), 0, st, A, nl, s);
+  return hipGetLastError();
+}
+
+hipError_t dense_gemm(const double* A, const double* B, double* C, int nl, int nu,
+                      hipStream_t st) {
+  const int t = (nl + 63) / 64;
+  hipLaunchKernelGGL(dgemm_kernel, dim3(t, t, nu), dim3(256), 0, st, A, B, C, nl,
+                     (int64_t)nl * nl);
+  return hipGetLastError();
+}
+
+hipError_t dense_lincomb(const double* X0, double c0, const double* X1, double c1,
+                         const double* X2, double c2, const double* X3, double c3,
+                         double d, double* out, int nl, int nu, hipStream_t st) {
+  LinComb p;
+  p.X[0] = X0; p.X[1] = X1; p.X[2] = X2; p.X[3] = X3;
+  p.c[0] = c0; p.c[1] = c1; p.c[2] = c2; p.c[3] = c3;
+  p.d = d; p.out = out; p.nl = nl; p.stride = (int64_t)nl * nl;
+  dim3 g = grid1((int64_t)nl * nl);
+  g.y = nu;
+  hipLaunchKernelGGL(lincomb_kernel, g, dim3(256), 0, st, p);
+  return hipGetLastError();
+}
+
+hipError_t dense_pade_pq(double* V, double* U, int64_t total, hipStream_t st) {
+  hipLaunchKernelGGL(pade_pq_kernel, grid1(total), dim3(256), 0, st, V, U, total);
+  return hipGetLastError();
+}
+
+hipError_t dense_solve(double* Q, double* P, int nl, int nu, hipStream_t st) {
+  const int64_t stride = (int64_t)nl * nl;
+  for (int j = 0; j < nl; ++j) {
+    hipLaunchKernelGGL(lu_pivot_kernel, dim3(nu), dim3(256), 0, st, Q, P, nl, stride, j);
+    const int rows = nl - j - 1;
+    if (rows > 0) {
+      const int cols = (nl - j - 1) + nl;
+      hipLaunchKernelGGL(lu_elim_kernel, dim3((cols + 255) / 256, rows, nu), dim3(256), 0, st,
+                         Q, P, nl, stride, j);
+    }
+  }
+  for (int j = nl - 1; j > 0; --j)
+    hipLaunchKernelGGL(lu_back_kernel, dim3((nl + 255) / 256, j, nu), dim3(256), 0, st, Q, P,
+                       nl, stride, j);
+  hipLaunchKernelGGL(lu_diag_kernel, dim3((nl + 255) / 256, nl, nu), dim3(256), 0, st, Q, P,
+                     nl, stride);
+  return hipGetLastError();
+}
+
+hipError_t dense_pack(const double* R, int nl, int Lx, int h, int cx, int cy, int ndim,
+                      int rows, int rows_p, int cols_p, double* e64, float* e32,
+                      void* e16, double* core_out, hipStream_t st) {
+  PackArgs a{R, nl, Lx, h, cx, cy, ndim, rows, rows_p, cols_p, e64, e32,
+             (__hip_bfloat16*)e16, core_out};
+  hipLaunchKernelGGL(pack_kernel, grid1((int64_t)rows_p * cols_p), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+size_t dense_block_size() { return sizeof(DBlock); }
+
+void dense_block_fill(void* dst, int i, int ox, int oy, int cx, int cy, int h, int Lx,
+                      int Ly, int unique) {
+  DBlock* d = (DBlock*)dst + i;
+  d->ox = ox; d->oy = oy; d->cx = cx; d->cy = cy; d->h = h; d->Lx = Lx; d->Ly = Ly;
+  d->unique = unique;
+}
+
+hipError_t dense_apply(int precision, int wm, const void* blocks, const void* E,
+                       int64_t e_stride, const double* core, const double* x_in,
+                       double* x_out, int n, int ndim, int ns, int rows, int rows_p,
+                       int cols, int cols_p, int n_blocks, hipStream_t st) {
+  ApplyArgs a;
+  a.blocks = (const DBlock*)blocks; a.E = E; a.e_stride = e_stride;
+  a.x_in = x_in; a.x_out = x_out; a.n = n; a.ndim = ndim; a.ns = ns;
+  a.rows = rows; a.rows_p = rows_p; a.cols = cols; a.cols_p = cols_p;
+  a.n_blocks = n_blocks;
+  if (ns % 64 != 0) {
+    a.row_tiles = 1; a.col_tiles = 1;
+    const dim3 g = grid1((int64_t)n_blocks * rows * ns, 256, 65535);
+    if (precision == 0)
+      hipLaunchKernelGGL(apply_simple_kernel<double>, g, dim3(256), 0, st, a, core);
+    else if (precision == 1)
+      hipLaunchKernelGGL(apply_simple_kernel<float>, g, dim3(256), 0, st, a, core);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
+  a.col_tiles = ns / 64;
+  a.row_tiles = (rows_p + 4 * wm - 1) / (4 * wm);
+  const dim3 g(n_blocks * a.row_tiles * a.col_tiles);
+  if (precision == 0) {
+    if (wm == 32) hipLaunchKernelGGL((apply_mfma_kernel<double, 32>), g, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((apply_mfma_kernel<double, 64>), g, dim3(256), 0, st, a);
+  } else if (precision == 1) {
+    if (wm == 32) hipLaunchKernelGGL((apply_mfma_kernel<float, 32>), g, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((apply_mfma_kernel<float, 64>), g, dim3(256), 0, st, a);
+  } else if (precision == 2) {
+    if (wm == 32) hipLaunchKernelGGL((apply_bf16_kernel<3, 32>), g, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((apply_bf16_kernel<3, 64>), g, dim3(256), 0, st, a);
+  } else if (precision == 3) {
+    if (wm == 32) hipLaunchKernelGGL((apply_bf16_kernel<6, 32>), g, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((apply_bf16_kernel<6, 64>), g, dim3(256), 0, st, a);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace lem

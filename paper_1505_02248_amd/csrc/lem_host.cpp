@@ -1,0 +1,1128 @@
+// Host side of the LEM library: operator weights, the overlapping partition
+// with decay-bound buffer widths, Krylov calibration, the one-off Pade
+// computation of stored local exponentials, the step loop and the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "lem.h"
+#include "lem_launch.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+lem_status fail(lem_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define LEM_HIP(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(LEM_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));      \
+  } while (0)
+
+#define LEM_TRY(expr)                \
+  do {                               \
+    lem_status s_ = (expr);          \
+    if (s_ != LEM_OK) return s_;     \
+  } while (0)
+
+// Pade [13/13] numerator coefficients (Higham 2005, scaled b_13 = 1).
+constexpr double kB[14] = {64764752532480000.0, 32382376266240000.0, 7771770303897600.0,
+                           1187353796428800.0,  129060195264000.0,   10559470521600.0,
+                           670442572800.0,      33522128640.0,       1323241920.0,
+                           40840800.0,          960960.0,            16380.0,
+                           182.0,               1.0};
+
+// ----------------------------------------------------------- operator ------
+// dt*A of the periodic advection-diffusion operator, centered differences.
+struct Op {
+  int ndim = 1, n = 0;
+  double dx = 0, dt = 0, vel[2] = {0, 0}, nu = 0;
+  bool variable = false;
+  double w[5] = {0, 0, 0, 0, 0};  // w0, wW, wE, wS, wN (constant case)
+  double chx = 0, chy = 0;        // dt*C/2 per axis
+  std::vector<double> mux, muy;   // face mu's (variable case), dt-scaled
+  int64_t N() const { return ndim == 1 ? (int64_t)n : (int64_t)n * n; }
+};
+
+lem_status build_op(const lem_operator* o, double dt, Op* op) {
+  if (!o) return fail(LEM_ERR_INVALID, "operator is NULL");
+  if (o->ndim != 1 && o->ndim != 2) return fail(LEM_ERR_INVALID, "ndim must be 1 or 2");
+  if (o->n < 3) return fail(LEM_ERR_INVALID, "n must be >= 3");
+  if (!(o->dx > 0) || !std::isfinite(o->dx)) return fail(LEM_ERR_INVALID, "dx must be > 0");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(LEM_ERR_INVALID, "dt must be > 0");
+  if (!(o->nu >= 0) && !o->nu_field) return fail(LEM_ERR_INVALID, "nu must be >= 0");
+  op->ndim = o->ndim;
+  op->n = o->n;
+  op->dx = o->dx;
+  op->dt = dt;
+  op->vel[0] = o->vel[0];
+  op->vel[1] = o->ndim == 2 ? o->vel[1] : 0.0;
+  op->nu = o->nu;
+  const double cx = op->vel[0] * dt / o->dx;
+  const double cy = op->vel[1] * dt / o->dx;
+  op->chx = cx / 2.0;
+  op->chy = cy / 2.0;
+  if (!o->nu_field) {
+    const double mu = o->nu * dt / (o->dx * o->dx);
+    op->variable = false;
+    if (o->ndim == 1) {
+      op->w[0] = -(mu + mu);
+      op->w[1] = mu + cx / 2.0;
+      op->w[2] = mu - cx / 2.0;
+      op->w[3] = 0.0;
+      op->w[4] = 0.0;
+    } else {
+      op->w[0] = -(((mu + mu) + mu) + mu);
+      op->w[1] = mu + cx / 2.0;
+      op->w[2] = mu - cx / 2.0;
+      op->w[3] = mu + cy / 2.0;
+      op->w[4] = mu - cy / 2.0;
+    }
+    return LEM_OK;
+  }
+  op->variable = true;
+  const int64_t N = op->N();
+  const int n = op->n;
+  const double s = dt / (2.0 * o->dx * o->dx);
+  op->mux.assign(N, 0.0);
+  op->muy.assign(N, 0.0);
+  for (int64_t g = 0; g < N; ++g) {
+    const double v = o->nu_field[g];
+    if (!(v >= 0) || !std::isfinite(v)) return fail(LEM_ERR_INVALID, "nu_field must be >= 0");
+  }
+  const int ny = op->ndim == 1 ? 1 : n;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < n; ++i) {
+      const int64_t g = (int64_t)j * n + i;
+      const int64_t e = (int64_t)j * n + (i + 1) % n;
+      op->mux[g] = (o->nu_field[g] + o->nu_field[e]) * s;
+      if (op->ndim == 2) {
+        const int64_t t = (int64_t)((j + 1) % n) * n + i;
+        op->muy[g] = (o->nu_field[g] + o->nu_field[t]) * s;
+      }
+    }
+  return LEM_OK;
+}
+
+// Weights of the row of global point (i, j).
+void point_weights(const Op& op, int i, int j, double* w) {
+  if (!op.variable) {
+    for (int q = 0; q < 5; ++q) w[q] = op.w[q];
+    return;
+  }
+  const int n = op.n;
+  const int64_t g = (int64_t)j * n + i;
+  const double me = op.mux[g], mw = op.mux[(int64_t)j * n + (i + n - 1) % n];
+  double mn = 0, ms = 0;
+  if (op.ndim == 2) {
+    mn = op.muy[g];
+    ms = op.muy[(int64_t)((j + n - 1) % n) * n + i];
+  }
+  w[0] = -(((me + mw) + mn) + ms);
+  w[1] = mw + op.chx;
+  w[2] = me - op.chx;
+  w[3] = op.ndim == 2 ? ms + op.chy : 0.0;
+  w[4] = op.ndim == 2 ? mn - op.chy : 0.0;
+}
+
+// ------------------------------------------------------------ halo bound --
+// eps(h) = G * sum_sides |w_s| min_r [(e^phi - 1)/phi] r^-h,
+// phi = w0 + P_s + |w_s| r + |w_sbar| / r   (a Cauchy-estimate bound of the
+// per-step LEM error at the core, Duhamel's formula with the outside values
+// as a source on the box edge; see the library documentation).
+double log_expm1_over(double phi) {
+  if (std::fabs(phi) < 1e-8) return phi / 2.0;
+  if (phi > 0) return phi + std::log1p(-std::exp(-phi)) - std::log(phi);
+  return std::log(-std::expm1(phi)) - std::log(-phi);
+}
+
+double side_log_bound(double ws, double wsb, double w0, double P, int h) {
+  const double b = std::fabs(ws), c = std::fabs(wsb);
+  if (b == 0.0) return -std::numeric_limits<double>::infinity();
+  const double a = w0 + P;
+  auto f = [&](double t) { return log_expm1_over(a + b * std::exp(t) + c * std::exp(-t)) - h * t; };
+  // golden-section search of the convex objective on log r in [-40, 40]
+  const double gr = 0.5 * (std::sqrt(5.0) - 1.0);
+  double lo = -40.0, hi = 40.0;
+  double x1 = hi - gr * (hi - lo), x2 = lo + gr * (hi - lo);
+  double f1 = f(x1), f2 = f(x2);
+  for (int it = 0; it < 200 && hi - lo > 1e-12; ++it) {
+    if (f1 < f2) {
+      hi = x2; x2 = x1; f2 = f1; x1 = hi - gr * (hi - lo); f1 = f(x1);
+    } else {
+      lo = x1; x1 = x2; f1 = f2; x2 = lo + gr * (hi - lo); f2 = f(x2);
+    }
+  }
+  return std::log(b) + std::min(f1, f2);
+}
+
+struct BlockCoef { double aW, aE, aS, aN, w0; };
+
+double eps_bound(const BlockCoef& c, int h, int ndim, double G) {
+  double t[4] = {side_log_bound(c.aW, c.aE, c.w0, c.aS + c.aN, h),
+                 side_log_bound(c.aE, c.aW, c.w0, c.aS + c.aN, h), -INFINITY, -INFINITY};
+  if (ndim == 2) {
+    t[2] = side_log_bound(c.aS, c.aN, c.w0, c.aW + c.aE, h);
+    t[3] = side_log_bound(c.aN, c.aS, c.w0, c.aW + c.aE, h);
+  }
+  double s = 0.0;
+  for (double v : t)
+    if (v > -INFINITY) s += std::exp(v);
+  return G * s;
+}
+
+double growth_factor(const Op& op) {
+  double mx = -INFINITY;
+  const int ny = op.ndim == 1 ? 1 : op.n;
+  double w[5];
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < op.n; ++i) {
+      point_weights(op, i, j, w);
+      mx = std::max(mx, w[0] + std::fabs(w[1]) + std::fabs(w[2]) + std::fabs(w[3]) + std::fabs(w[4]));
+      if (!op.variable) return std::exp(std::max(0.0, mx));
+    }
+  return std::exp(std::max(0.0, mx));
+}
+
+struct Box { int ox, oy, cx, cy, h; };
+
+BlockCoef block_coef(const Op& op, const Box& b, int h) {
+  BlockCoef c{0, 0, 0, 0, -INFINITY};
+  double w[5];
+  if (!op.variable) {
+    c = {std::fabs(op.w[1]), std::fabs(op.w[2]), std::fabs(op.w[3]), std::fabs(op.w[4]), op.w[0]};
+    return c;
+  }
+  const int n = op.n;
+  const int Lx = b.cx + 2 * h, Ly = op.ndim == 2 ? b.cy + 2 * h : 1;
+  for (int ly = 0; ly < Ly; ++ly)
+    for (int lx = 0; lx < Lx; ++lx) {
+      const int gx = ((b.ox - h + lx) % n + n) % n;
+      const int gy = op.ndim == 2 ? ((b.oy - h + ly) % n + n) % n : 0;
+      point_weights(op, gx, gy, w);
+      c.aW = std::max(c.aW, std::fabs(w[1]));
+      c.aE = std::max(c.aE, std::fabs(w[2]));
+      c.aS = std::max(c.aS, std::fabs(w[3]));
+      c.aN = std::max(c.aN, std::fabs(w[4]));
+      c.w0 = std::max(c.w0, w[0]);
+    }
+  return c;
+}
+
+// Smallest h in [h_min, h_max] with eps(h) <= tol (coefficients taken over the
+// box of width h itself); h_max and clamped = true when none qualifies.
+int halo_from_bound(const Op& op, Box b, double tol, int h_min, int h_max, double G,
+                    bool* clamped) {
+  for (int h = h_min; h <= h_max; ++h) {
+    const BlockCoef c = block_coef(op, b, op.variable ? h : 0);
+    if (eps_bound(c, h, op.ndim, G) <= tol) {
+      *clamped = false;
+      return h;
+    }
+  }
+  *clamped = true;
+  return h_max;
+}
+
+}  // namespace
+
+// ================================================================= plan ====
+struct lem_plan_s {
+  Op op;
+  lem_options opt{};
+  int method = 0, ns = 1;
+  int64_t N = 0;
+  std::vector<Box> boxes;
+  int n_clamped = 0;
+  bool dry = false;
+  // Krylov
+  std::vector<int> m, nsub;
+  struct Bucket { int nt, pmax; bool vlds; size_t lds; int first, count; };
+  std::vector<Bucket> buckets;
+  lem::KBlock* d_kb = nullptr;
+  double* d_coef = nullptr;
+  double* d_vwork = nullptr;
+  double* d_diag = nullptr;
+  // dense
+  int U = 0, rows = 0, rows_p = 0, cols = 0, cols_p = 0, wm = 64, squarings = 0;
+  void* d_db = nullptr;
+  double* d_e64 = nullptr;
+  float* d_e32 = nullptr;
+  void* d_e16 = nullptr;
+  double* d_core = nullptr;
+  // global
+  lem::GlobalWork gw{};
+  // shared
+  int* d_status = nullptr;
+  double* d_tmp = nullptr;
+  std::vector<void*> allocs;
+  int64_t bytes_blocks = 0, bytes_work = 0;
+  hipStream_t stream = nullptr;
+  std::map<std::pair<const void*, void*>, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+  double plan_ms = 0;
+
+  ~lem_plan_s() {
+    for (auto& g : graphs) {
+      hipGraphExecDestroy(g.second.second);
+      hipGraphDestroy(g.second.first);
+    }
+    for (void* p : allocs) hipFree(p);
+  }
+};
+
+namespace {
+
+template <typename T>
+lem_status dalloc(lem_plan_s* p, T** out, size_t count, int64_t* account = nullptr) {
+  *out = nullptr;
+  if (count == 0) count = 1;
+  void* ptr = nullptr;
+  hipError_t e = hipMalloc(&ptr, count * sizeof(T));
+  if (e != hipSuccess) {
+    hipGetLastError();
+    return fail(LEM_ERR_NOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+  }
+  p->allocs.push_back(ptr);
+  if (account) *account += (int64_t)(count * sizeof(T));
+  *out = (T*)ptr;
+  return LEM_OK;
+}
+
+void dfree(lem_plan_s* p, void* ptr) {
+  if (!ptr) return;
+  auto it = std::find(p->allocs.begin(), p->allocs.end(), ptr);
+  if (it != p->allocs.end()) p->allocs.erase(it);
+  hipFree(ptr);
+}
+
+lem_status upload(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  LEM_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+  return LEM_OK;
+}
+
+// ------------------------------------------------------------- partition --
+lem_status make_partition(lem_plan_s* p) {
+  const Op& op = p->op;
+  const lem_options& o = p->opt;
+  const int n = op.n;
+  const double G = growth_factor(op);
+  auto pick_halo = [&](Box b) -> int {
+    if (o.halo > 0) return o.halo;
+    bool cl = false;
+    const int h = halo_from_bound(op, b, o.halo_tol, o.halo_min, o.halo_max, G, &cl);
+    if (cl) p->n_clamped++;
+    return h;
+  };
+  if (o.core > 0) {
+    const int c = o.core;
+    if (n % c) return fail(LEM_ERR_INVALID, "core side must divide n");
+    const int nb = n / c;
+    if (op.ndim == 1) {
+      for (int bx = 0; bx < nb; ++bx) p->boxes.push_back({bx * c, 0, c, 1, 0});
+    } else {
+      for (int by = 0; by < nb; ++by)
+        for (int bx = 0; bx < nb; ++bx) p->boxes.push_back({bx * c, by * c, c, c, 0});
+    }
+    // a uniform partition of a constant operator has one halo for all blocks
+    if (!op.variable) {
+      const int h = pick_halo(p->boxes[0]);
+      if (o.halo <= 0 && p->n_clamped) p->n_clamped = (int)p->boxes.size();
+      for (auto& b : p->boxes) b.h = h;
+    } else {
+      for (auto& b : p->boxes) b.h = pick_halo(b);
+    }
+  } else {
+    if (op.ndim != 2 || p->method != LEM_METHOD_KRYLOV)
+      return fail(LEM_ERR_UNSUPPORTED, "uneven cores need the 2D Krylov method");
+    if (n % 64) return fail(LEM_ERR_INVALID, "uneven cores need n divisible by 64");
+    // Per 64x64 tile choose the core side c in {16, 32, 64} with the least
+    // modelled cost: local points per core point, weighted up when the Krylov
+    // basis must stream through device memory instead of staying in LDS.
+    const int cands[3] = {16, 32, 64};
+    const int mguess = std::max(8, std::min(o.krylov_m_max, 30));
+    for (int ty = 0; ty < n / 64; ++ty)
+      for (int tx = 0; tx < n / 64; ++tx) {
+        double best = INFINITY;
+        std::vector<Box> bestb;
+        int best_cl = 0;
+        for (int c : cands) {
+          std::vector<Box> bs;
+          int cl_before = p->n_clamped;
+          for (int by = 0; by < 64 / c; ++by)
+            for (int bx = 0; bx < 64 / c; ++bx) {
+              Box b{tx * 64 + bx * c, ty * 64 + by * c, c, c, 0};
+              b.h = pick_halo(b);
+              bs.push_back(b);
+            }
+          const int cl = p->n_clamped - cl_before;
+          p->n_clamped = cl_before;
+          double cost = 0;
+          for (auto& b : bs) {
+            const int L = c + 2 * b.h;
+            int nt, pm;
+            lem::krylov_config(2, L * L, &nt, &pm);
+            const bool fits = lem::krylov_lds_bytes(nt, mguess, L * L, true) <= 160 * 1024;
+            cost += (double)L * L * (fits ? 1.0 : 2.5);
+          }
+          if (cost < best) { best = cost; bestb = bs; best_cl = cl; }
+        }
+        p->n_clamped += best_cl;
+        p->boxes.insert(p->boxes.end(), bestb.begin(), bestb.end());
+      }
+  }
+  for (auto& b : p->boxes) {
+    const int Lx = b.cx + 2 * b.h;
+    const int Ly = op.ndim == 2 ? b.cy + 2 * b.h : 1;
+    if (Lx >= n || (op.ndim == 2 && Ly >= n))
+      return fail(LEM_ERR_INVALID, "box (core + 2*halo) reaches itself through the periodic wrap;"
+                                   " use a larger grid, a smaller halo or the global method");
+  }
+  return LEM_OK;
+}
+
+// --------------------------------------------------------------- Krylov ----
+lem::KBlock make_kblock(const lem_plan_s* p, const Box& b, int m, int nsub, int ns, int diag) {
+  lem::KBlock k{};
+  const double sc = 1.0 / nsub;
+  const Op& op = p->op;
+  k.w0 = op.w[0] * sc; k.wW = op.w[1] * sc; k.wE = op.w[2] * sc; k.wS = op.w[3] * sc;
+  k.wN = op.w[4] * sc;
+  k.chx = op.chx * sc; k.chy = op.chy * sc; k.sub_scale = sc;
+  k.tol = p->opt.krylov_tol;
+  k.x_off = 0;
+  k.mu_off = op.variable ? 0 : -1;
+  k.v_off = 0;
+  k.n = op.n; k.ndim = op.ndim;
+  k.ox = b.ox; k.oy = b.oy; k.cx = b.cx; k.cy = b.cy; k.h = b.h;
+  k.Lx = b.cx + 2 * b.h; k.Ly = op.ndim == 2 ? b.cy + 2 * b.h : 1;
+  k.m = m; k.nsub = nsub; k.ns = ns; k.diag = diag;
+  return k;
+}
+
+// Groups blocks by launch shape; assigns global-basis offsets. Reorders kb.
+lem_status bucketize(std::vector<lem::KBlock>& kb, std::vector<lem_plan_s::Bucket>& buckets,
+                     int ns, int64_t* vwork_doubles) {
+  struct Key { int nt, pmax; bool vlds; bool operator<(const Key& o) const {
+    return std::tie(nt, pmax, vlds) < std::tie(o.nt, o.pmax, o.vlds); } };
+  std::map<Key, std::vector<int>> groups;
+  std::vector<size_t> need(kb.size());
+  for (size_t i = 0; i < kb.size(); ++i) {
+    const int nloc = kb[i].Lx * kb[i].Ly;
+    int nt, pm;
+    lem::krylov_config(kb[i].ndim, nloc, &nt, &pm);
+    if (nt == 0) return fail(LEM_ERR_UNSUPPORTED, "local box larger than 10240 points");
+    const size_t with_v = lem::krylov_lds_bytes(nt, kb[i].m, nloc, true);
+    const bool vlds = with_v <= 160 * 1024 && pm != 20;
+    need[i] = vlds ? with_v : lem::krylov_lds_bytes(nt, kb[i].m, nloc, false);
+    groups[{nt, pm, vlds}].push_back((int)i);
+  }
+  std::vector<lem::KBlock> out;
+  buckets.clear();
+  int64_t voff = 0;
+  for (auto& g : groups) {
+    lem_plan_s::Bucket bk{g.first.nt, g.first.pmax, g.first.vlds, 0, (int)out.size(),
+                          (int)g.second.size()};
+    for (int i : g.second) {
+      lem::KBlock k = kb[i];
+      bk.lds = std::max(bk.lds, need[i]);
+      if (!g.first.vlds) {
+        k.v_off = voff;
+        voff += (int64_t)(k.m + 1) * k.Lx * k.Ly * ns;
+      }
+      out.push_back(k);
+    }
+    buckets.push_back(bk);
+  }
+  kb.swap(out);
+  *vwork_doubles = voff;
+  return LEM_OK;
+}
+
+lem_status launch_buckets(const lem_plan_s* p, const lem::KBlock* d_kb,
+                          const std::vector<lem_plan_s::Bucket>& bks, int ns, const double* src,
+                          double* dst, double* vwork, double* diag, double* calib, int mode,
+                          hipStream_t st) {
+  for (const auto& b : bks) {
+    hipError_t e = lem::launch_krylov(d_kb + b.first, b.count, ns, b.nt, b.pmax, b.vlds, b.lds,
+                                      src, dst, p->d_coef, vwork, diag, p->d_status, calib,
+                                      mode, st);
+    if (e != hipSuccess)
+      return fail(LEM_ERR_HIP, std::string("Krylov launch: ") + hipGetErrorString(e));
+  }
+  return LEM_OK;
+}
+
+// Choose (m, nsub) from calibration estimates est[sub][j] of one block.
+bool choose_m(const double* est, const std::vector<int>& jl, int nsc, double tol, int mfix,
+              int mcal, int* m, int* nsub) {
+  double best = INFINITY;
+  for (int e = 0; e < nsc; ++e)
+    for (size_t q = 0; q < jl.size(); ++q) {
+      const int j = jl[q];
+      if (mfix > 0 && j != mfix) continue;
+      if (!(est[e * jl.size() + q] <= 0.5 * tol)) continue;
+      const int mm = (mfix > 0) ? j : std::min(j + 2, mcal);
+      const double cost = (double)(1 << e) * (mm + 8);
+      if (cost < best) { best = cost; *m = mm; *nsub = 1 << e; }
+    }
+  return best < INFINITY;
+}
+
+lem_status plan_krylov(lem_plan_s* p, hipStream_t st) {
+  const Op& op = p->op;
+  const lem_options& o = p->opt;
+  const int nb = (int)p->boxes.size();
+  // coefficient arrays
+  if (op.variable) {
+    LEM_TRY(dalloc(p, &p->d_coef, 2 * (size_t)op.N(), &p->bytes_work));
+    LEM_TRY(upload(p->d_coef, op.mux.data(), op.N() * 8, st));
+    LEM_TRY(upload(p->d_coef + op.N(), op.muy.data(), op.N() * 8, st));
+  }
+  // calibration representatives: identical boxes of a constant operator share one
+  std::vector<int> rep(nb, -1);
+  std::vector<int> reps;
+  {
+    std::map<std::tuple<int, int, int, int>, int> seen;
+    for (int i = 0; i < nb; ++i) {
+      const Box& b = p->boxes[i];
+      if (!op.variable) {
+        auto key = std::make_tuple(b.cx, b.cy, b.h, 0);
+        auto it = seen.find(key);
+        if (it != seen.end()) { rep[i] = it->second; continue; }
+        seen[key] = (int)reps.size();
+      }
+      rep[i] = (int)reps.size();
+      reps.push_back(i);
+    }
+  }
+  const int mcal = std::min(std::max(o.krylov_m_max, 4), lem::kMaxKrylov);
+  std::vector<int> jl;
+  for (int j = 2; j <= mcal; ++j) jl.push_back(j);
+  int nsc = 1;
+  while ((1 << nsc) <= o.max_substeps && nsc < 12) ++nsc;
+  // calibration blocks (ns = 1, unscaled weights, m = mcal)
+  std::vector<lem::KBlock> cb;
+  for (size_t r = 0; r < reps.size(); ++r)
+    cb.push_back(make_kblock(p, p->boxes[reps[r]], mcal, 1, 1, (int)r));
+  std::vector<lem_plan_s::Bucket> cbk;
+  int64_t cv = 0;
+  LEM_TRY(bucketize(cb, cbk, 1, &cv));
+  lem::KBlock* d_cb;
+  double *d_probe, *d_cv, *d_calib, *d_cdiag, *d_est;
+  int *d_mcal, *d_jl;
+  int64_t* d_coff;
+  const int64_t cstride = 2 + (int64_t)(mcal + 1) * mcal;
+  const int nr = (int)cb.size();
+  LEM_TRY(dalloc(p, &d_cb, cb.size()));
+  LEM_TRY(dalloc(p, &d_probe, (size_t)op.N()));
+  LEM_TRY(dalloc(p, &d_cv, (size_t)std::max<int64_t>(cv, 1)));
+  LEM_TRY(dalloc(p, &d_calib, (size_t)nr * cstride));
+  LEM_TRY(dalloc(p, &d_cdiag, (size_t)nr));
+  LEM_TRY(dalloc(p, &d_est, (size_t)nr * nsc * jl.size()));
+  LEM_TRY(dalloc(p, &d_mcal, (size_t)nr));
+  LEM_TRY(dalloc(p, &d_jl, jl.size()));
+  LEM_TRY(dalloc(p, &d_coff, (size_t)nr));
+  std::vector<int> mc(nr, mcal);
+  std::vector<int64_t> coff(nr);
+  for (int k = 0; k < nr; ++k) coff[k] = (int64_t)k * cstride;
+  LEM_TRY(upload(d_cb, cb.data(), cb.size() * sizeof(lem::KBlock), st));
+  LEM_TRY(upload(d_mcal, mc.data(), nr * sizeof(int), st));
+  LEM_TRY(upload(d_jl, jl.data(), jl.size() * sizeof(int), st));
+  LEM_TRY(upload(d_coff, coff.data(), nr * sizeof(int64_t), st));
+  LEM_HIP(lem::launch_probe_fill(d_probe, op.N(), 12345u, st));
+  LEM_TRY(launch_buckets(p, d_cb, cbk, 1, d_probe, nullptr, d_cv, d_cdiag, d_calib, 1, st));
+  LEM_HIP(lem::launch_krylov_estimates(d_calib, d_mcal, d_coff, d_jl, (int)jl.size(), nsc,
+                                       d_est, nr, mcal, st));
+  std::vector<double> est((size_t)nr * nsc * jl.size());
+  LEM_HIP(hipMemcpyAsync(est.data(), d_est, est.size() * 8, hipMemcpyDeviceToHost, st));
+  LEM_HIP(hipStreamSynchronize(st));
+  // per representative choice (calibration row r = representative r)
+  std::vector<int> rm(nr), rs(nr);
+  for (int r = 0; r < nr; ++r) {
+    int mm = 0, ss = 0;
+    if (!choose_m(&est[(size_t)r * nsc * jl.size()], jl, nsc, o.krylov_tol, o.krylov_m, mcal,
+                  &mm, &ss))
+      return fail(LEM_ERR_NOT_CONVERGED,
+                  "no Krylov dimension <= " + std::to_string(mcal) + " with <= " +
+                      std::to_string(o.max_substeps) + " sub-steps meets krylov_tol");
+    rm[r] = mm;
+    rs[r] = ss;
+  }
+  for (void* q : {(void*)d_cb, (void*)d_probe, (void*)d_cv, (void*)d_calib, (void*)d_cdiag,
+                  (void*)d_est, (void*)d_mcal, (void*)d_jl, (void*)d_coff})
+    dfree(p, q);
+  // step blocks
+  p->m.resize(nb);
+  p->nsub.resize(nb);
+  std::vector<lem::KBlock> kb;
+  for (int i = 0; i < nb; ++i) {
+    p->m[i] = rm[rep[i]];
+    p->nsub[i] = rs[rep[i]];
+    kb.push_back(make_kblock(p, p->boxes[i], p->m[i], p->nsub[i], p->ns, i));
+  }
+  int64_t vw = 0;
+  LEM_TRY(bucketize(kb, p->buckets, p->ns, &vw));
+  LEM_TRY(dalloc(p, &p->d_kb, kb.size(), &p->bytes_work));
+  LEM_TRY(upload(p->d_kb, kb.data(), kb.size() * sizeof(lem::KBlock), st));
+  LEM_TRY(dalloc(p, &p->d_vwork, (size_t)std::max<int64_t>(vw, 1), &p->bytes_work));
+  LEM_TRY(dalloc(p, &p->d_diag, (size_t)nb * p->ns, &p->bytes_work));
+  LEM_HIP(hipMemsetAsync(p->d_diag, 0, (size_t)nb * p->ns * 8, st));
+  return LEM_OK;
+}
+
+// ---------------------------------------------------------------- dense ----
+lem_status plan_dense(lem_plan_s* p, hipStream_t st) {
+  const Op& op = p->op;
+  if (op.variable)
+    return fail(LEM_ERR_UNSUPPORTED, "stored local exponentials need constant coefficients");
+  if (p->opt.core <= 0) return fail(LEM_ERR_INVALID, "the dense method needs a uniform core");
+  if (p->opt.precision >= LEM_BF16X2 && p->ns % 64)
+    return fail(LEM_ERR_UNSUPPORTED, "bf16 split application needs n_states % 64 == 0");
+  const Box& b0 = p->boxes[0];
+  const int Lx = b0.cx + 2 * b0.h, Ly = op.ndim == 2 ? b0.cy + 2 * b0.h : 1;
+  const int nl = Lx * Ly;
+  // every box of a uniform partition of a constant operator has the same
+  // local operator: one stored block, shared by all
+  p->U = 1;
+  const int U = 1;
+  p->rows = b0.cx * (op.ndim == 2 ? b0.cy : 1);
+  p->cols = nl;
+  p->rows_p = (p->rows + 63) / 64 * 64;
+  p->cols_p = (nl + 31) / 32 * 32;
+  const size_t mat = (size_t)nl * nl * U;
+  double *A, *A2, *A4, *A6, *T, *Ub, *Vb, *d_norm;
+  int* d_s;
+  void* d_ops;
+  LEM_TRY(dalloc(p, &A, mat));
+  LEM_TRY(dalloc(p, &A2, mat));
+  LEM_TRY(dalloc(p, &A4, mat));
+  LEM_TRY(dalloc(p, &A6, mat));
+  LEM_TRY(dalloc(p, &T, mat));
+  LEM_TRY(dalloc(p, &Ub, mat));
+  LEM_TRY(dalloc(p, &Vb, mat));
+  LEM_TRY(dalloc(p, &d_norm, U));
+  LEM_TRY(dalloc(p, &d_s, U));
+  {
+    unsigned char* dp;
+    LEM_TRY(dalloc(p, &dp, lem::dense_op_size() * U));
+    d_ops = dp;
+  }
+  std::vector<unsigned char> hops(lem::dense_op_size() * U);
+  lem::dense_op_fill(hops.data(), 0, op.w[0], op.w[1], op.w[2], op.w[3], op.w[4], Lx, Ly);
+  LEM_TRY(upload(d_ops, hops.data(), hops.size(), st));
+  LEM_HIP(lem::dense_assemble(d_ops, A, nl, U, st));
+  LEM_HIP(lem::dense_norm1(A, nl, U, d_norm, st));
+  std::vector<double> nrm(U);
+  LEM_HIP(hipMemcpyAsync(nrm.data(), d_norm, U * 8, hipMemcpyDeviceToHost, st));
+  LEM_HIP(hipStreamSynchronize(st));
+  std::vector<int> s(U);
+  for (int u = 0; u < U; ++u) {
+    if (!std::isfinite(nrm[u])) return fail(LEM_ERR_INVALID, "non-finite local operator");
+    s[u] = nrm[u] > lem::kTheta13 ? std::min(60, (int)std::ceil(std::log2(nrm[u] / lem::kTheta13))) : 0;
+    p->squarings = std::max(p->squarings, s[u]);
+  }
+  LEM_TRY(upload(d_s, s.data(), U * sizeof(int), st));
+  LEM_HIP(lem::dense_scale_pow2(A, nl, U, d_s, st));
+  LEM_HIP(lem::dense_gemm(A, A, A2, nl, U, st));
+  LEM_HIP(lem::dense_gemm(A2, A2, A4, nl, U, st));
+  LEM_HIP(lem::dense_gemm(A4, A2, A6, nl, U, st));
+  // U = A (A6 (b13 A6 + b11 A4 + b9 A2) + b7 A6 + b5 A4 + b3 A2 + b1 I)
+  LEM_HIP(lem::dense_lincomb(A6, kB[13], A4, kB[11], A2, kB[9], nullptr, 0, 0, T, nl, U, st));
+  LEM_HIP(lem::dense_gemm(A6, T, Ub, nl, U, st));
+  LEM_HIP(lem::dense_lincomb(Ub, 1.0, A6, kB[7], A4, kB[5], A2, kB[3], kB[1], Ub, nl, U, st));
+  LEM_HIP(lem::dense_gemm(A, Ub, T, nl, U, st));  // T = U
+  // V = A6 (b12 A6 + b10 A4 + b8 A2) + b6 A6 + b4 A4 + b2 A2 + b0 I
+  LEM_HIP(lem::dense_lincomb(A6, kB[12], A4, kB[10], A2, kB[8], nullptr, 0, 0, Ub, nl, U, st));
+  LEM_HIP(lem::dense_gemm(A6, Ub, Vb, nl, U, st));
+  LEM_HIP(lem::dense_lincomb(Vb, 1.0, A6, kB[6], A4, kB[4], A2, kB[2], kB[0], Vb, nl, U, st));
+  LEM_HIP(lem::dense_pade_pq(Vb, T, (int64_t)mat, st));  // Vb = P, T = Q
+  LEM_HIP(lem::dense_solve(T, Vb, nl, U, st));           // Vb = Q^-1 P
+  for (int u = 0; u < U; ++u) {
+    double* src = Vb + (size_t)u * nl * nl;
+    double* dst = A2 + (size_t)u * nl * nl;
+    for (int q = 0; q < s[u]; ++q) {
+      LEM_HIP(lem::dense_gemm(src, src, dst, nl, 1, st));
+      std::swap(src, dst);
+    }
+    if (src != Vb + (size_t)u * nl * nl)
+      LEM_HIP(hipMemcpyAsync(Vb + (size_t)u * nl * nl, src, (size_t)nl * nl * 8,
+                             hipMemcpyDeviceToDevice, st));
+  }
+  const size_t es = (size_t)p->rows_p * p->cols_p;
+  LEM_TRY(dalloc(p, &p->d_e64, es * U, &p->bytes_blocks));
+  LEM_TRY(dalloc(p, &p->d_e32, es * U, &p->bytes_blocks));
+  {
+    unsigned short* e16;
+    LEM_TRY(dalloc(p, &e16, es * 3 * U, &p->bytes_blocks));
+    p->d_e16 = e16;
+  }
+  LEM_TRY(dalloc(p, &p->d_core, (size_t)p->rows * nl * U, &p->bytes_blocks));
+  for (int u = 0; u < U; ++u)
+    LEM_HIP(lem::dense_pack(Vb + (size_t)u * nl * nl, nl, Lx, b0.h, b0.cx, op.ndim == 2 ? b0.cy : 1,
+                            op.ndim, p->rows, p->rows_p, p->cols_p, p->d_e64 + u * es,
+                            p->d_e32 + u * es, (unsigned short*)p->d_e16 + u * es * 3,
+                            p->d_core + (size_t)u * p->rows * nl, st));
+  LEM_HIP(hipStreamSynchronize(st));
+  for (void* q : {(void*)A, (void*)A2, (void*)A4, (void*)A6, (void*)T, (void*)Ub, (void*)Vb,
+                  (void*)d_norm, (void*)d_s, d_ops})
+    dfree(p, q);
+  // block table
+  const int nb = (int)p->boxes.size();
+  std::vector<unsigned char> db(lem::dense_block_size() * nb);
+  for (int i = 0; i < nb; ++i) {
+    const Box& b = p->boxes[i];
+    lem::dense_block_fill(db.data(), i, b.ox, b.oy, b.cx, op.ndim == 2 ? b.cy : 1, b.h,
+                          b.cx + 2 * b.h, op.ndim == 2 ? b.cy + 2 * b.h : 1, 0);
+  }
+  {
+    unsigned char* d;
+    LEM_TRY(dalloc(p, &d, db.size(), &p->bytes_work));
+    p->d_db = d;
+  }
+  LEM_TRY(upload(p->d_db, db.data(), db.size(), st));
+  p->wm = p->rows_p >= 256 ? 64 : 32;
+  return LEM_OK;
+}
+
+const void* dense_operand(const lem_plan_s* p) {
+  switch (p->opt.precision) {
+    case LEM_FP64: return p->d_e64;
+    case LEM_FP32: return p->d_e32;
+    default: return p->d_e16;
+  }
+}
+
+// --------------------------------------------------------------- global ----
+lem_status alloc_global(lem_plan_s* p, int m, int ns, int nsub, lem::GlobalWork* w) {
+  const Op& op = p->op;
+  w->N = op.N();
+  w->ns = ns; w->n = op.n; w->ndim = op.ndim; w->m = m; w->nsub = nsub;
+  const double sc = 1.0 / nsub;
+  for (int q = 0; q < 5; ++q) w->w[q] = op.w[q] * sc;
+  w->chx = op.chx * sc; w->chy = op.chy * sc; w->sub_scale = sc;
+  w->mux = op.variable ? p->d_coef : nullptr;
+  w->muy = op.variable ? p->d_coef + op.N() : nullptr;
+  w->tol = p->opt.krylov_tol;
+  w->status = p->d_status;
+  const int64_t tot = w->N * ns;
+  const int G = lem::global_grid(tot, ns);
+  const int K = lem::kMaxKrylov + 1;
+  LEM_TRY(dalloc(p, &w->V, (size_t)(m + 1) * tot, &p->bytes_work));
+  LEM_TRY(dalloc(p, &w->W, (size_t)tot, &p->bytes_work));
+  LEM_TRY(dalloc(p, &w->Wt, (size_t)tot, &p->bytes_work));
+  LEM_TRY(dalloc(p, &w->part, lem::global_part_doubles(G, ns), &p->bytes_work));
+  LEM_TRY(dalloc(p, &w->h1, (size_t)K * ns, &p->bytes_work));
+  LEM_TRY(dalloc(p, &w->h2, (size_t)K * ns, &p->bytes_work));
+  LEM_TRY(dalloc(p, &w->hn, (size_t)K * ns, &p->bytes_work));
+  LEM_TRY(dalloc(p, &w->H, (size_t)ns * (m + 1) * m, &p->bytes_work));
+  LEM_TRY(dalloc(p, &w->f, (size_t)ns * m, &p->bytes_work));
+  LEM_TRY(dalloc(p, &w->beta, (size_t)ns, &p->bytes_work));
+  LEM_TRY(dalloc(p, &w->inv, (size_t)ns, &p->bytes_work));
+  LEM_TRY(dalloc(p, &w->est, (size_t)ns, &p->bytes_work));
+  LEM_TRY(dalloc(p, &w->estsum, (size_t)ns, &p->bytes_work));
+  LEM_HIP(hipMemsetAsync(w->estsum, 0, (size_t)ns * 8, p->stream));
+  return LEM_OK;
+}
+
+void free_global(lem_plan_s* p, lem::GlobalWork* w) {
+  for (void* q : {(void*)w->V, (void*)w->W, (void*)w->Wt, (void*)w->part, (void*)w->h1,
+                  (void*)w->h2, (void*)w->hn, (void*)w->H, (void*)w->f, (void*)w->beta,
+                  (void*)w->inv, (void*)w->est, (void*)w->estsum})
+    dfree(p, q);
+}
+
+lem_status plan_global(lem_plan_s* p, hipStream_t st) {
+  const Op& op = p->op;
+  const lem_options& o = p->opt;
+  if (256 % p->ns != 0)
+    return fail(LEM_ERR_UNSUPPORTED, "the global method needs n_states dividing 256");
+  if (op.variable) {
+    LEM_TRY(dalloc(p, &p->d_coef, 2 * (size_t)op.N(), &p->bytes_work));
+    LEM_TRY(upload(p->d_coef, op.mux.data(), op.N() * 8, st));
+    LEM_TRY(upload(p->d_coef + op.N(), op.muy.data(), op.N() * 8, st));
+  }
+  const int mcal = std::min(std::max(o.krylov_m_max, 4), lem::kMaxKrylov);
+  std::vector<int> jl;
+  for (int j = 2; j <= mcal; ++j) jl.push_back(j);
+  int nsc = 1;
+  while ((1 << nsc) <= o.max_substeps && nsc < 12) ++nsc;
+  lem::GlobalWork cw{};
+  const int64_t before = p->bytes_work;
+  LEM_TRY(alloc_global(p, mcal, 1, 1, &cw));
+  double *d_probe, *d_calib, *d_est;
+  int *d_mcal, *d_jl;
+  int64_t* d_coff;
+  const int64_t cstride = 2 + (int64_t)(mcal + 1) * mcal;
+  LEM_TRY(dalloc(p, &d_probe, (size_t)op.N()));
+  LEM_TRY(dalloc(p, &d_calib, (size_t)cstride));
+  LEM_TRY(dalloc(p, &d_est, (size_t)nsc * jl.size()));
+  LEM_TRY(dalloc(p, &d_mcal, 1));
+  LEM_TRY(dalloc(p, &d_jl, jl.size()));
+  LEM_TRY(dalloc(p, &d_coff, 1));
+  int64_t zero = 0;
+  LEM_TRY(upload(d_mcal, &mcal, sizeof(int), st));
+  LEM_TRY(upload(d_jl, jl.data(), jl.size() * sizeof(int), st));
+  LEM_TRY(upload(d_coff, &zero, sizeof(int64_t), st));
+  LEM_HIP(lem::launch_probe_fill(d_probe, op.N(), 777u, st));
+  LEM_HIP(lem::global_arnoldi(cw, d_probe, d_calib, st));
+  LEM_HIP(lem::launch_krylov_estimates(d_calib, d_mcal, d_coff, d_jl, (int)jl.size(), nsc, d_est,
+                                       1, mcal, st));
+  std::vector<double> est((size_t)nsc * jl.size());
+  LEM_HIP(hipMemcpyAsync(est.data(), d_est, est.size() * 8, hipMemcpyDeviceToHost, st));
+  LEM_HIP(hipStreamSynchronize(st));
+  int mm = 0, ss = 0;
+  const bool ok = choose_m(est.data(), jl, nsc, o.krylov_tol, o.krylov_m, mcal, &mm, &ss);
+  free_global(p, &cw);
+  for (void* q : {(void*)d_probe, (void*)d_calib, (void*)d_est, (void*)d_mcal, (void*)d_jl,
+                  (void*)d_coff})
+    dfree(p, q);
+  p->bytes_work = before;
+  if (!ok)
+    return fail(LEM_ERR_NOT_CONVERGED, "no global Krylov dimension/sub-step pair meets krylov_tol");
+  p->m.assign(1, mm);
+  p->nsub.assign(1, ss);
+  LEM_TRY(alloc_global(p, mm, p->ns, ss, &p->gw));
+  return LEM_OK;
+}
+
+// ----------------------------------------------------------------- step ----
+lem_status run_one(lem_plan_s* p, const double* src, double* dst, hipStream_t st) {
+  switch (p->method) {
+    case LEM_METHOD_KRYLOV:
+      return launch_buckets(p, p->d_kb, p->buckets, p->ns, src, dst, p->d_vwork, p->d_diag,
+                            nullptr, 0, st);
+    case LEM_METHOD_DENSE: {
+      const int64_t es = (int64_t)p->rows_p * p->cols_p;
+      LEM_HIP(lem::dense_apply(p->opt.precision, p->wm, p->d_db, dense_operand(p), es, p->d_core,
+                               src, dst, p->op.n, p->op.ndim, p->ns, p->rows, p->rows_p, p->cols,
+                               p->cols_p, (int)p->boxes.size(), st));
+      return LEM_OK;
+    }
+    default:
+      LEM_HIP(lem::global_step(p->gw, src, dst, st));
+      return LEM_OK;
+  }
+}
+
+lem_status run_step(lem_plan_s* p, const double* src, double* dst, hipStream_t st) {
+  if (!p->opt.use_graph || st == nullptr) return run_one(p, src, dst, st);
+  auto key = std::make_pair((const void*)src, (void*)dst);
+  auto it = p->graphs.find(key);
+  if (it == p->graphs.end()) {
+    hipGraph_t g;
+    hipGraphExec_t ex;
+    LEM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    lem_status s = run_one(p, src, dst, st);
+    hipError_t e = hipStreamEndCapture(st, &g);
+    if (s != LEM_OK) return s;
+    if (e != hipSuccess) return fail(LEM_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      hipGraphDestroy(g);
+      return fail(LEM_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    it = p->graphs.emplace(key, std::make_pair(g, ex)).first;
+  }
+  LEM_HIP(hipGraphLaunch(it->second.second, st));
+  return LEM_OK;
+}
+
+// Times the dense apply at both launch shapes on a scratch state; keeps the faster.
+lem_status autotune_dense(lem_plan_s* p, hipStream_t st) {
+  const int64_t tot = p->N * p->ns;
+  double *a, *b;
+  LEM_TRY(dalloc(p, &a, (size_t)tot));
+  LEM_TRY(dalloc(p, &b, (size_t)tot));
+  LEM_HIP(lem::launch_probe_fill(a, tot, 99u, st));
+  hipEvent_t e0, e1;
+  LEM_HIP(hipEventCreate(&e0));
+  LEM_HIP(hipEventCreate(&e1));
+  float best = INFINITY;
+  int bestwm = p->wm;
+  for (int wm : {32, 64}) {
+    p->wm = wm;
+    LEM_TRY(run_one(p, a, b, st));
+    LEM_HIP(hipEventRecord(e0, st));
+    for (int r = 0; r < 5; ++r) LEM_TRY(run_one(p, a, b, st));
+    LEM_HIP(hipEventRecord(e1, st));
+    LEM_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    LEM_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) { best = ms; bestwm = wm; }
+  }
+  p->wm = bestwm;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  dfree(p, a);
+  dfree(p, b);
+  return LEM_OK;
+}
+
+lem_status check_options(const lem_options* o) {
+  if (!o) return fail(LEM_ERR_INVALID, "options are NULL");
+  if (o->method < 0 || o->method > 2) return fail(LEM_ERR_INVALID, "unknown method");
+  if (o->precision < 0 || o->precision > 3) return fail(LEM_ERR_INVALID, "unknown precision");
+  if (o->precision != LEM_FP64 && o->method != LEM_METHOD_DENSE)
+    return fail(LEM_ERR_UNSUPPORTED, "reduced precision applies to the dense method only");
+  if (o->n_states < 1) return fail(LEM_ERR_INVALID, "n_states must be >= 1");
+  if (o->core < 0 || o->halo < 0) return fail(LEM_ERR_INVALID, "core and halo must be >= 0");
+  if (o->halo == 0 && (o->halo_min < 0 || o->halo_max < o->halo_min || !(o->halo_tol > 0)))
+    return fail(LEM_ERR_INVALID, "decay-bound halo needs 0 <= halo_min <= halo_max, halo_tol > 0");
+  if (o->krylov_m < 0 || o->krylov_m > lem::kMaxKrylov || o->krylov_m_max < 2 ||
+      o->krylov_m_max > lem::kMaxKrylov)
+    return fail(LEM_ERR_INVALID, "Krylov dimension must be in [2, 48]");
+  if (o->max_substeps < 1) return fail(LEM_ERR_INVALID, "max_substeps must be >= 1");
+  if (!(o->krylov_tol > 0)) return fail(LEM_ERR_INVALID, "krylov_tol must be > 0");
+  return LEM_OK;
+}
+
+void fill_info(const lem_plan_s* p, lem_plan_info* in) {
+  std::memset(in, 0, sizeof(*in));
+  in->n_blocks = (int)p->boxes.size();
+  in->n_unique = p->U;
+  in->halo_min = INT32_MAX;
+  in->halo_max = 0;
+  in->n_loc_max = 0;
+  for (const auto& b : p->boxes) {
+    const int64_t nl = (int64_t)(b.cx + 2 * b.h) * (p->op.ndim == 2 ? b.cy + 2 * b.h : 1);
+    in->n_loc_total += nl;
+    in->n_loc_max = std::max<int>(in->n_loc_max, (int)nl);
+    in->halo_min = std::min(in->halo_min, b.h);
+    in->halo_max = std::max(in->halo_max, b.h);
+  }
+  if (p->boxes.empty()) in->halo_min = 0;
+  in->halo_clamped = p->n_clamped;
+  in->m_min = p->m.empty() ? 0 : *std::min_element(p->m.begin(), p->m.end());
+  in->m_max = p->m.empty() ? 0 : *std::max_element(p->m.begin(), p->m.end());
+  in->substeps_max = p->nsub.empty() ? 0 : *std::max_element(p->nsub.begin(), p->nsub.end());
+  in->squarings = p->squarings;
+  in->bytes_blocks = p->bytes_blocks;
+  in->bytes_work = p->bytes_work;
+  in->plan_ms = p->plan_ms;
+  in->tile_config = p->wm;
+}
+
+bool overlap(const void* a, const void* b, size_t bytes) {
+  const char* x = (const char*)a;
+  const char* y = (const char*)b;
+  return x < y + bytes && y < x + bytes;
+}
+
+}  // namespace
+
+// ================================================================ C ABI ====
+extern "C" {
+
+void lem_options_default(lem_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->method = LEM_METHOD_KRYLOV;
+  o->precision = LEM_FP64;
+  o->n_states = 1;
+  o->core = 0;
+  o->halo = 0;
+  o->halo_min = 4;
+  o->halo_max = 64;
+  o->halo_tol = 1e-8;
+  o->krylov_m = 0;
+  o->krylov_m_max = 40;
+  o->max_substeps = 64;
+  o->krylov_tol = 1e-13;
+  o->use_graph = 0;
+  o->autotune = 0;
+  o->dry_run = 0;
+}
+
+lem_status lem_plan(const lem_operator* op, double dt, const lem_options* opt, void* stream,
+                    lem_plan_t* out) {
+  if (!out) return fail(LEM_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  LEM_TRY(check_options(opt));
+  const auto t0 = std::chrono::steady_clock::now();
+  auto p = new lem_plan_s();
+  auto guard = [&](lem_status s) { if (s != LEM_OK) delete p; return s; };
+  p->opt = *opt;
+  p->method = opt->method;
+  p->ns = opt->n_states;
+  p->dry = opt->dry_run != 0;
+  p->stream = (hipStream_t)stream;
+  lem_status s = build_op(op, dt, &p->op);
+  if (s != LEM_OK) return guard(s);
+  p->N = p->op.N();
+  if (p->method == LEM_METHOD_KRYLOV || p->method == LEM_METHOD_DENSE) {
+    if (p->opt.core == 0 && p->method == LEM_METHOD_KRYLOV && p->op.ndim == 1)
+      p->opt.core = std::min(64, p->op.n);
+    if (p->opt.core == p->op.n)
+      return guard(fail(LEM_ERR_INVALID, "a single core covering the grid is the global method"));
+    s = make_partition(p);
+    if (s != LEM_OK) return guard(s);
+  }
+  if (!p->dry) {
+    hipStream_t st = p->stream;
+    s = dalloc(p, &p->d_status, 1);
+    if (s != LEM_OK) return guard(s);
+    if (hipMemsetAsync(p->d_status, 0, sizeof(int), st) != hipSuccess)
+      return guard(fail(LEM_ERR_HIP, "hipMemsetAsync failed"));
+    s = dalloc(p, &p->d_tmp, (size_t)p->N * p->ns, &p->bytes_work);
+    if (s != LEM_OK) return guard(s);
+    if (p->method == LEM_METHOD_KRYLOV) s = plan_krylov(p, st);
+    else if (p->method == LEM_METHOD_DENSE) s = plan_dense(p, st);
+    else s = plan_global(p, st);
+    if (s != LEM_OK) return guard(s);
+    if (p->method == LEM_METHOD_DENSE && opt->autotune && p->ns % 64 == 0) {
+      s = autotune_dense(p, st);
+      if (s != LEM_OK) return guard(s);
+    }
+    if (hipStreamSynchronize(st) != hipSuccess)
+      return guard(fail(LEM_ERR_HIP, "plan synchronization failed"));
+  } else if (p->method == LEM_METHOD_KRYLOV) {
+    p->m.assign(p->boxes.size(), opt->krylov_m);
+    p->nsub.assign(p->boxes.size(), 1);
+  }
+  p->plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *out = p;
+  return LEM_OK;
+}
+
+lem_status lem_step(lem_plan_t p, const double* x_in, double* x_out, int32_t n_steps,
+                    void* stream) {
+  if (!p) return fail(LEM_ERR_INVALID, "plan is NULL");
+  if (p->dry) return fail(LEM_ERR_INVALID, "a dry-run plan cannot step");
+  if (!x_in || !x_out) return fail(LEM_ERR_INVALID, "state pointers must not be NULL");
+  if (n_steps < 1) return fail(LEM_ERR_INVALID, "n_steps must be >= 1");
+  const size_t bytes = (size_t)p->N * p->ns * sizeof(double);
+  if (overlap(x_in, x_out, bytes)) return fail(LEM_ERR_INVALID, "x_in and x_out overlap");
+  hipStream_t st = (hipStream_t)stream;
+  p->stream = st;
+  // last step writes x_out; earlier steps alternate x_out / tmp backwards
+  const double* src = x_in;
+  for (int k = 0; k < n_steps; ++k) {
+    double* dst = ((n_steps - 1 - k) % 2 == 0) ? x_out : p->d_tmp;
+    LEM_TRY(run_step(p, src, dst, st));
+    src = dst;
+  }
+  return LEM_OK;
+}
+
+lem_status lem_global_expmv(const lem_operator* op, double t, const double* x, double* y,
+                            int32_t n_states, double tol, int32_t m_max, void* stream) {
+  lem_options o;
+  lem_options_default(&o);
+  o.method = LEM_METHOD_GLOBAL;
+  o.n_states = n_states;
+  o.krylov_tol = tol;
+  o.krylov_m_max = m_max;
+  lem_plan_t p = nullptr;
+  LEM_TRY(lem_plan(op, t, &o, stream, &p));
+  lem_status s = lem_step(p, x, y, 1, stream);
+  if (s == LEM_OK && hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+    s = fail(LEM_ERR_HIP, "synchronization failed");
+  int st = 0;
+  if (s == LEM_OK && hipMemcpy(&st, p->d_status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+    s = fail(LEM_ERR_HIP, "status copy failed");
+  lem_plan_destroy(p);
+  if (s == LEM_OK && st)
+    s = fail(LEM_ERR_NOT_CONVERGED, "global Krylov estimate above tolerance or non-finite values");
+  return s;
+}
+
+lem_status lem_plan_query(lem_plan_t p, lem_plan_info* info) {
+  if (!p || !info) return fail(LEM_ERR_INVALID, "NULL argument");
+  fill_info(p, info);
+  if (p->dry) return LEM_OK;
+  LEM_HIP(hipStreamSynchronize(p->stream));
+  int st = 0;
+  LEM_HIP(hipMemcpy(&st, p->d_status, sizeof(int), hipMemcpyDeviceToHost));
+  info->device_status = (st & lem::kStatusNonFinite) ? LEM_ERR_NOT_CONVERGED
+                        : (st & lem::kStatusNotConverged) ? LEM_ERR_NOT_CONVERGED : 0;
+  double mx = 0.0;
+  if (p->method == LEM_METHOD_KRYLOV && p->d_diag) {
+    std::vector<double> d(p->boxes.size() * p->ns);
+    LEM_HIP(hipMemcpy(d.data(), p->d_diag, d.size() * 8, hipMemcpyDeviceToHost));
+    for (double v : d) mx = std::max(mx, v);
+  } else if (p->method == LEM_METHOD_GLOBAL && p->gw.estsum) {
+    std::vector<double> d(p->ns);
+    LEM_HIP(hipMemcpy(d.data(), p->gw.estsum, d.size() * 8, hipMemcpyDeviceToHost));
+    for (double v : d) mx = std::max(mx, v);
+  }
+  info->max_estimate = mx;
+  return LEM_OK;
+}
+
+lem_status lem_plan_copy_maps(lem_plan_t p, int32_t* boxes, int32_t* gather, int32_t* scatter) {
+  if (!p) return fail(LEM_ERR_INVALID, "plan is NULL");
+  const int n = p->op.n;
+  const int ndim = p->op.ndim;
+  int64_t gi = 0, si = 0;
+  for (size_t k = 0; k < p->boxes.size(); ++k) {
+    const Box& b = p->boxes[k];
+    if (boxes) {
+      boxes[5 * k + 0] = b.ox; boxes[5 * k + 1] = b.oy; boxes[5 * k + 2] = b.cx;
+      boxes[5 * k + 3] = ndim == 2 ? b.cy : 1; boxes[5 * k + 4] = b.h;
+    }
+    const int Lx = b.cx + 2 * b.h, Ly = ndim == 2 ? b.cy + 2 * b.h : 1;
+    if (gather)
+      for (int ly = 0; ly < Ly; ++ly)
+        for (int lx = 0; lx < Lx; ++lx) {
+          const int gx = ((b.ox - b.h + lx) % n + n) % n;
+          const int gy = ndim == 2 ? ((b.oy - b.h + ly) % n + n) % n : 0;
+          gather[gi++] = gy * n + gx;
+        }
+    if (scatter) {
+      const int cy = ndim == 2 ? b.cy : 1;
+      for (int ry = 0; ry < cy; ++ry)
+        for (int rx = 0; rx < b.cx; ++rx) scatter[si++] = (b.oy + ry) * n + b.ox + rx;
+    }
+  }
+  return LEM_OK;
+}
+
+lem_status lem_plan_copy_krylov(lem_plan_t p, int32_t* m, int32_t* substeps) {
+  if (!p) return fail(LEM_ERR_INVALID, "plan is NULL");
+  if (p->method == LEM_METHOD_DENSE) return fail(LEM_ERR_INVALID, "dense plan has no Krylov data");
+  for (size_t i = 0; i < p->m.size(); ++i) {
+    if (m) m[i] = p->m[i];
+    if (substeps) substeps[i] = p->nsub[i];
+  }
+  return LEM_OK;
+}
+
+lem_status lem_plan_copy_block(lem_plan_t p, int32_t unique, double* out, int32_t* rows,
+                               int32_t* cols) {
+  if (!p) return fail(LEM_ERR_INVALID, "plan is NULL");
+  if (p->method != LEM_METHOD_DENSE || p->dry)
+    return fail(LEM_ERR_INVALID, "only a dense plan stores local exponentials");
+  if (unique < 0 || unique >= p->U) return fail(LEM_ERR_INVALID, "block index out of range");
+  if (rows) *rows = p->rows;
+  if (cols) *cols = p->cols;
+  if (out) {
+    LEM_HIP(hipStreamSynchronize(p->stream));
+    LEM_HIP(hipMemcpy(out, p->d_core + (size_t)unique * p->rows * p->cols,
+                      (size_t)p->rows * p->cols * 8, hipMemcpyDeviceToHost));
+  }
+  return LEM_OK;
+}
+
+lem_status lem_plan_destroy(lem_plan_t p) {
+  if (!p) return LEM_OK;
+  if (!p->dry) hipStreamSynchronize(p->stream);
+  delete p;
+  return LEM_OK;
+}
+
+const char* lem_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,66 @@
+// Host-side entry points of the LEM kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "lem_device.hpp"
+
+namespace lem {
+
+// ---- Krylov LEM step (krylov_lem.hip)
+void krylov_config(int ndim, int nloc, int* nt, int* pmax);
+size_t krylov_lds_bytes(int nt, int m, int nloc, bool vlds);
+hipError_t launch_krylov(const KBlock* blocks, int n_blocks, int ns, int nt, int pmax,
+                         bool vlds, size_t lds, const double* x_in, double* x_out,
+                         const double* coef, double* vwork, double* diag, int* status,
+                         double* calib, int mode, hipStream_t st);
+hipError_t launch_krylov_estimates(const double* calib, const int* mcal, const int64_t* coff,
+                                   const int* jlist, int nj, int n_sub_cand, double* est,
+                                   int n_blocks, int j_max, hipStream_t st);
+hipError_t launch_probe_fill(double* x, int64_t n, uint64_t seed, hipStream_t st);
+
+// ---- dense local exponentials (dense.hip)
+size_t dense_op_size();
+void dense_op_fill(void* dst, int i, double w0, double wW, double wE, double wS, double wN,
+                   int Lx, int Ly);
+hipError_t dense_assemble(const void* ops, double* A, int nl, int nu, hipStream_t st);
+hipError_t dense_norm1(const double* A, int nl, int nu, double* norms, hipStream_t st);
+hipError_t dense_scale_pow2(double* A, int nl, int nu, const int* s, hipStream_t st);
+hipError_t dense_gemm(const double* A, const double* B, double* C, int nl, int nu,
+                      hipStream_t st);
+hipError_t dense_lincomb(const double* X0, double c0, const double* X1, double c1,
+                         const double* X2, double c2, const double* X3, double c3, double d,
+                         double* out, int nl, int nu, hipStream_t st);
+hipError_t dense_pade_pq(double* V, double* U, int64_t total, hipStream_t st);
+hipError_t dense_solve(double* Q, double* P, int nl, int nu, hipStream_t st);
+hipError_t dense_pack(const double* R, int nl, int Lx, int h, int cx, int cy, int ndim,
+                      int rows, int rows_p, int cols_p, double* e64, float* e32, void* e16,
+                      double* core_out, hipStream_t st);
+size_t dense_block_size();
+void dense_block_fill(void* dst, int i, int ox, int oy, int cx, int cy, int h, int Lx, int Ly,
+                      int unique);
+hipError_t dense_apply(int precision, int wm, const void* blocks, const void* E,
+                       int64_t e_stride, const double* core, const double* x_in, double* x_out,
+                       int n, int ndim, int ns, int rows, int rows_p, int cols, int cols_p,
+                       int n_blocks, hipStream_t st);
+
+// ---- global Krylov (global_krylov.hip)
+struct GlobalWork {
+  int64_t N;
+  int ns, n, ndim, m, nsub;
+  double w[5];
+  double chx, chy, sub_scale;
+  const double* mux;
+  const double* muy;
+  double *V, *W, *Wt, *part, *h1, *h2, *hn, *H, *f, *beta, *inv, *est, *estsum;
+  double tol;
+  int* status;
+};
+int global_grid(int64_t total, int ns);
+size_t global_part_doubles(int G, int ns);
+hipError_t global_step(const GlobalWork& w, const double* x, double* y, hipStream_t st);
+hipError_t global_arnoldi(const GlobalWork& w, const double* x, double* calib, hipStream_t st);
+
+}  // namespace lem

@@ -1,0 +1,233 @@
+"""GPU parity of the HIP path against the CPU FP64 oracle (gfx950 only).
+
+Every test runs the library through its C ABI (the ctypes binding) on
+seeded synthetic inputs and compares element by element with the oracle's
+plain definition of the LEM step (exact local exponentials) or with the
+exact global exponential.  Tolerances: index maps bit-exact; float64 paths
+1e-12 relative l2; float32 application 1e-5; split-bf16 application 1e-6
+(3-piece) and 2e-5 (2-piece)."""
+import numpy as np
+import pytest
+
+import lem_inputs as L
+import oracle
+from oracle import expm as E
+from oracle import globalexp as ge
+from oracle import lem as olem
+from oracle import operator as op
+from oracle import partition as P
+from oracle.metrics import rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+import paper_1505_02248_amd as lem  # noqa: E402
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to("cuda")
+
+
+def run(plan, x0, steps=1):
+    xin = dev(x0)
+    xout = torch.empty_like(xin)
+    plan.step(xin, xout, steps)
+    torch.cuda.synchronize()
+    return xout.cpu().numpy()
+
+
+def oracle_lem(p, boxes, x0, steps, **kw):
+    W = op.from_problem(p)
+    bx = [P.Box(*map(int, b)) for b in boxes]
+    return olem.run(op.sparse(W), bx, p.ndim, p.n, x0, steps, **kw)
+
+
+def check_maps(plan, ndim, n):
+    boxes, gather, scatter = plan.maps()
+    bx = [P.Box(*map(int, b)) for b in boxes]
+    P.check_tiling(bx, ndim, n)
+    G, _, S, _ = P.all_maps(bx, ndim, n)
+    assert np.array_equal(gather, G.astype(np.int32))
+    assert np.array_equal(scatter, S.astype(np.int32))
+    return boxes
+
+
+def test_gpu_visible():
+    assert torch.cuda.is_available()
+    lem.load()
+
+
+# ----------------------------------------------------------------- dense --
+
+@pytest.mark.parametrize("case", ["1d", "2d576", "2d2304"])
+def test_pade_block_matches_oracle_expm(case):
+    if case == "1d":
+        p, c, h = L.workload_1d(), 64, 16
+    elif case == "2d576":
+        p, c, h = L.workload_2d_ensemble(n=64, n_states=64), 16, 4
+    else:
+        p, c, h = L.workload_2d_mixed(n=128, n_smooth=64), 32, 8
+    plan = lem.Plan(lem.Operator.from_problem(p), p.dt, method="dense", core=c, halo=h,
+                    n_states=p.states.shape[1])
+    got = plan.block(0)
+    W = op.from_problem(p)
+    box = P.uniform_boxes(p.ndim, p.n, c, h)[0]
+    Aloc = olem.local_matrix(op.sparse(W), P.gather_map(box, p.ndim, p.n))
+    want = E.expm(Aloc)[P.core_local_rows(box, p.ndim)]
+    assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
+
+
+def test_dense_1d_100_steps_fp64():
+    p = L.workload_1d()
+    plan = lem.Plan(lem.Operator.from_problem(p), p.dt, method="dense", core=64, halo=16)
+    boxes = check_maps(plan, 1, p.n)
+    got = run(plan, p.states, 100)
+    want = oracle_lem(p, boxes, p.states[:, 0], 100)
+    assert rel_l2(got[:, 0], want) <= 1e-12
+
+
+@pytest.mark.parametrize("steps", [1, 10])
+def test_dense_2d_ensemble_full_size_fp64(steps):
+    p = L.workload_2d_ensemble()  # 256^2, 64 states, 16x16 cores
+    plan = lem.Plan(lem.Operator.from_problem(p), p.dt, method="dense", core=16, halo=4,
+                    n_states=64)
+    boxes = check_maps(plan, 2, p.n)
+    got = run(plan, p.states, steps)
+    want = oracle_lem(p, boxes, p.states, steps)
+    assert rel_l2(got, want) <= 1e-12
+
+
+def test_dense_2d_ensemble_full_size_fp32():
+    p = L.workload_2d_ensemble()
+    plan = lem.Plan(lem.Operator.from_problem(p), p.dt, method="dense", precision="fp32",
+                    core=16, halo=4, n_states=64)
+    got = run(plan, p.states, 1)
+    want = oracle_lem(p, plan.maps()[0], p.states, 1)
+    assert rel_l2(got, want) <= 1e-5
+
+
+@pytest.mark.parametrize("prec,tol", [("bf16x3", 1e-6), ("bf16x2", 2e-5)])
+def test_dense_split_bf16(prec, tol):
+    p = L.workload_2d_mixed(n=128, n_smooth=64, n_noise=64)  # 2304-point boxes
+    plan = lem.Plan(lem.Operator.from_problem(p), p.dt, method="dense", precision=prec,
+                    core=32, halo=8, n_states=128)
+    got = run(plan, p.states, 1)
+    want = oracle_lem(p, plan.maps()[0], p.states, 1)
+    assert rel_l2(got, want) <= tol
+
+
+def test_dense_ragged_tiles_and_small_ensembles():
+    # 40-point cores + 10-point halos: 40 core rows (pad to 64), 60 columns
+    # (pad to 64); 64 states take the MFMA path, 3 states the plain path
+    n = 1000
+    for ns in (64, 3):
+        p = L.workload_1d(n=n)
+        x0 = np.repeat(p.states, ns, axis=1) * (1.0 + np.arange(ns))[None, :]
+        plan = lem.Plan(lem.Operator.from_problem(p), p.dt, method="dense", core=40, halo=10,
+                        n_states=ns)
+        got = run(plan, x0, 3)
+        want = oracle_lem(p, plan.maps()[0], x0, 3)
+        assert rel_l2(got, want) <= 1e-12, ns
+
+
+# ---------------------------------------------------------------- Krylov --
+
+def test_krylov_1d_100_steps():
+    p = L.workload_1d()
+    plan = lem.Plan(lem.Operator.from_problem(p), p.dt, method="krylov", core=64, halo=16,
+                    krylov_tol=1e-14)
+    boxes = check_maps(plan, 1, p.n)
+    got = run(plan, p.states, 100)
+    want = oracle_lem(p, boxes, p.states[:, 0], 100)
+    assert rel_l2(got[:, 0], want) <= 1e-12
+    q = plan.query()
+    assert q["device_status"] == 0 and q["max_estimate"] <= 1e-14
+
+
+def test_krylov_2d_uniform_ensemble():
+    p = L.workload_2d_ensemble(n=64, n_states=2)
+    plan = lem.Plan(lem.Operator.from_problem(p), p.dt, method="krylov", core=16, halo=4,
+                    n_states=2, krylov_tol=1e-14)
+    got = run(plan, p.states, 2)
+    want = oracle_lem(p, plan.maps()[0], p.states, 2)
+    assert rel_l2(got, want) <= 1e-12
+
+
+def test_krylov_2d_uneven_variable_nu():
+    p = L.workload_2d_variable(n=128)
+    plan = lem.Plan(lem.Operator.from_problem(p), p.dt, method="krylov", core=0, halo=0,
+                    halo_min=4, halo_max=16, halo_tol=1e-8, krylov_tol=1e-14)
+    boxes = check_maps(plan, 2, p.n)
+    got = run(plan, p.states, 1)
+    want = oracle_lem(p, boxes, p.states, 1, krylov_above=2600, krylov_tol=1e-16)
+    assert rel_l2(got, want) <= 1e-12
+
+
+# ---------------------------------------------------------------- global --
+
+def test_global_krylov_1d_and_2d_vs_fourier():
+    p = L.workload_1d()
+    W = op.from_problem(p)
+    plan = lem.Plan(lem.Operator.from_problem(p), p.dt, method="global", krylov_tol=1e-14)
+    got = run(plan, p.states, 3)
+    assert rel_l2(got, ge.fft_steps(W, p.states, 3)) <= 1e-12
+    q = L.workload_2d_ensemble(n=64, n_states=4)
+    Wq = op.from_problem(q)
+    x, y = dev(q.states), torch.empty((q.N * 4,), dtype=torch.float64, device="cuda")
+    lem.global_expmv(lem.Operator.from_problem(q), q.dt, x.reshape(-1), y, n_states=4, tol=1e-14)
+    torch.cuda.synchronize()
+    assert rel_l2(y.cpu().numpy().reshape(q.N, 4), ge.fft_steps(Wq, q.states)) <= 1e-12
+
+
+def test_global_krylov_variable_nu_vs_dense():
+    p = L.workload_2d_variable(n=32)
+    W = op.from_problem(p)
+    plan = lem.Plan(lem.Operator.from_problem(p), p.dt, method="global", krylov_tol=1e-14)
+    got = run(plan, p.states, 1)
+    assert rel_l2(got, ge.dense_step(W, p.states)) <= 1e-12
+
+
+# ------------------------------------------------------------ step logic --
+
+def test_multi_step_equals_repeated_single_steps_bitwise():
+    p = L.workload_2d_ensemble(n=64, n_states=64)
+    plan = lem.Plan(lem.Operator.from_problem(p), p.dt, method="dense", core=16, halo=4,
+                    n_states=64)
+    x = dev(p.states)
+    for k in (1, 2, 3):
+        out = torch.empty_like(x)
+        plan.step(x, out, k)
+        a = x.clone()
+        for _ in range(k):
+            b = torch.empty_like(a)
+            plan.step(a, b, 1)
+            a = b
+        torch.cuda.synchronize()
+        assert torch.equal(out, a), k
+
+
+def test_aliasing_is_rejected():
+    p = L.workload_1d()
+    plan = lem.Plan(lem.Operator.from_problem(p), p.dt, method="dense", core=64, halo=16)
+    x = dev(p.states)
+    with pytest.raises(lem.LemError) as e:
+        plan.step(x, x, 1)
+    assert e.value.status == 1
+
+
+def test_graph_replays_match_eager_bitwise():
+    p = L.workload_1d()
+    s = torch.cuda.Stream()
+    eager = lem.Plan(lem.Operator.from_problem(p), p.dt, method="krylov", core=64, halo=16)
+    graph = lem.Plan(lem.Operator.from_problem(p), p.dt, method="krylov", core=64, halo=16,
+                     use_graph=True, stream=s)
+    x = dev(p.states)
+    ref = torch.empty_like(x)
+    eager.step(x, ref, 5)
+    for rep in range(3):
+        out = torch.empty_like(x)
+        with torch.cuda.stream(s):
+            graph.step(x, out, 5, stream=s)
+        s.synchronize()
+        _ = (x * 2).sum().item()  # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), rep
