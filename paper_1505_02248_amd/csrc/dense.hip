@@ -132,7 +132,8 @@ __global__ void pade_pq_kernel(double* V, double* U, int64_t total) {
 // C[u] = A[u] * B[u], row-major nl x nl, FP64 MFMA 16x16x4.  64x64 tile per
 // workgroup of 256 threads; each wave owns a 32x32 quarter (2x2 MFMA tiles).
 // Fragment layouts (16x16x4, f64): lane l supplies A[l%16][l/16] and
-// B[l/16][l%16]; accumulator register r of lane l is D[4*(l/16)+r][l%16].
+// B[l/16][l%16]; accumulator register r of lane l is D[4*r + l/16][l%16]
+// (the f32 and bf16 forms place it at D[4*(l/16) + r][l%16] instead).
 __global__ __launch_bounds__(256) void dgemm_kernel(const double* A, const double* B,
                                                     double* C, int nl, int64_t stride) {
   constexpr int BM = 64, BK = 16;
@@ -189,7 +190,7 @@ __global__ __launch_bounds__(256) void dgemm_kernel(const double* A, const doubl
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gr = m0 + wr + i * 16 + 4 * (lane >> 4) + r;
+        const int gr = m0 + wr + i * 16 + 4 * r + (lane >> 4);
         const int gc = n0 + wc + j * 16 + (lane & 15);
         if (gr < nl && gc < nl) Cb[(int64_t)gr * nl + gc] = acc[i][j][r];
       }
@@ -480,7 +481,9 @@ __global__ __launch_bounds__(256) void apply_mfma_kernel(ApplyArgs a) {
   for (int i = 0; i < RT; ++i)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int row = row0 + i * 16 + 4 * (lane >> 4) + r;
+      // accumulator row: f64 16x16x4 interleaves rows across registers
+      const int tr = (sizeof(T) == 8) ? 4 * r + (lane >> 4) : 4 * (lane >> 4) + r;
+      const int row = row0 + i * 16 + tr;
       if (row >= a.rows) continue;
       const int64_t g = dense_scatter(b, row, a.n, a.ndim);
       double* dst = a.x_out + g * a.ns + col0 + (lane & 15);

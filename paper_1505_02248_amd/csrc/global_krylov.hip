@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "lem_device.hpp"
 #include "lem_launch.h"
 
@@ -109,9 +111,18 @@ __device__ __forceinline__ void block_partials(double (&v)[K], int cnt, int ns,
   }
 }
 
-__global__ void g_zero_kernel(double* x, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) x[i] = 0.0;
+__global__ void g_zero_kernel(double* x, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = 0.0;
+}
+
+// Clears the Hessenberg matrices (entries below the subdiagonal are never
+// written by the column updates).
+static void zero_h(const GlobalWork& w, hipStream_t st) {
+  const int64_t n = (int64_t)w.ns * (w.m + 1) * w.m;
+  hipLaunchKernelGGL(g_zero_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024)),
+                     dim3(256), 0, st, w.H, n);
 }
 
 // beta, k = m and H per state, for the calibration of (m, sub-steps).
@@ -305,9 +316,11 @@ hipError_t global_step(const GlobalWork& w, const double* x, double* y, hipStrea
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(g_zero_kernel, dim3((w.ns + 255) / 256), dim3(256), 0, st, w.estsum, w.ns);
+  hipLaunchKernelGGL(g_zero_kernel, dim3((w.ns + 255) / 256), dim3(256), 0, st, w.estsum,
+                     (int64_t)w.ns);
   for (int sub = 0; sub < w.nsub; ++sub) {
     const double* src = sub == 0 ? x : y;
+    zero_h(w, st);
     // beta = ||src||, W = src
     hipLaunchKernelGGL(g_norm<1>, dim3(G), dim3(256), 0, st, src, total, w.ns, w.part);
     hipLaunchKernelGGL(g_reduce, dim3(1, w.ns), dim3(256), 0, st, w.part, G, 1, w.ns, w.hn);
@@ -348,6 +361,7 @@ hipError_t global_arnoldi(const GlobalWork& w, const double* x, double* calib, h
   a.op.chx = w.chx; a.op.chy = w.chy; a.op.sub_scale = w.sub_scale;
   a.op.mux = w.mux; a.op.muy = w.muy; a.op.n = w.n; a.op.ndim = w.ndim;
   a.V = w.V; a.W = const_cast<double*>(x); a.Wt = w.Wt; a.part = w.part; a.N = w.N; a.ns = w.ns;
+  zero_h(w, st);
   hipLaunchKernelGGL(g_norm<1>, dim3(G), dim3(256), 0, st, x, total, w.ns, w.part);
   hipLaunchKernelGGL(g_reduce, dim3(1, w.ns), dim3(256), 0, st, w.part, G, 1, w.ns, w.hn);
   hipLaunchKernelGGL(g_beta, dim3((w.ns + 255) / 256), dim3(256), 0, st, w.hn, w.beta, w.inv, w.ns);
