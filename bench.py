@@ -95,6 +95,9 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-global", action="store_true")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="also run one device copy of this many MiB (a reference kernel of "
+                         "known traffic for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
@@ -172,6 +175,16 @@ def main() -> int:
         extras["lem_over_global"] = value / gval
         log(f"global Krylov: {gval:.3e} DOF-steps/s; LEM/global = {value / gval:.1f}x; "
             f"LEM vs global rel l2 after {k} steps = {err:.2e}")
+
+    if args.copy_mb:
+        nbytes = args.copy_mb << 20
+        a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").uniform_()
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        extras["reference_copy_bytes"] = nbytes
+        del a, b
 
     cpu = None
     if not args.no_cpu:
