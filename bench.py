@@ -28,6 +28,18 @@ if ROOT not in sys.path:
 METRIC = "DOF-steps/s, LEM vs global Krylov expmv at rel err ≤1e-6; served p99 latency"
 MFMA_FP64_PEAK_TFLOPS = 78.6
 MFMA_FP32_PEAK_TFLOPS = 157.3
+# HBM bytes per launch of the FP64 apply from rocprofv3 FETCH_SIZE / WRITE_SIZE passes
+# (scaled by a 256 MiB reference copy), valid only for the dense.hip source they were
+# taken on: profiles/apply_fp64_2d256x256x64_h14.md
+TRAFFIC = {"dense.hip": ("8b79c86bcc2b", 157977375)}
+
+
+def measured_traffic():
+    import hashlib
+    src = os.path.join(ROOT, "paper_1505_02248_amd", "csrc", "dense.hip")
+    sha, nbytes = TRAFFIC["dense.hip"]
+    with open(src, "rb") as f:
+        return nbytes if hashlib.sha1(f.read()).hexdigest()[:12] == sha else None
 
 
 def log(*a):
@@ -214,7 +226,7 @@ def main() -> int:
                    "tile_config": q["tile_config"]},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": MFMA_FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / MFMA_FP64_PEAK_TFLOPS,
-                     "traffic": None,
+                     "traffic": measured_traffic(),
                      "kernel": "apply_mfma_kernel<double>", "flops_per_launch": flops,
                      "us_per_launch": kern_ms * 1e3},
         "cpu_baseline": cpu,
