@@ -191,6 +191,94 @@ lem_status lem_plan_copy_block(lem_plan_t plan, int32_t unique, double* out,
 /* Free a plan and everything it owns (waits for its stream).  NULL is ok. */
 lem_status lem_plan_destroy(lem_plan_t plan);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of independent time-stepping requests.
+ *
+ * Each request is one periodic problem (its own operator, dt, step count and
+ * initial state, one ensemble member).  On admission it is planned like
+ * lem_plan (partition with decay-bound buffers, per-block Krylov
+ * calibration) -- or, when no core side keeps the buffer overhead within
+ * max_overhead, as a global Krylov stepper (D = 1) -- and all of its device
+ * memory (state, coefficients, work space) is taken from one pool of
+ * hbm_budget bytes reserved at creation.  Requests are admitted first come,
+ * first served while the pool and max_active allow.  Every lem_server_tick
+ * advances every active request by one step of (5); the local problems of all
+ * active LEM requests run in shared Krylov launches.  Every block's arithmetic
+ * depends only on its own request, so a request's result is the same whether
+ * it runs alone or in a mix.  A server is not thread-safe.
+ * ------------------------------------------------------------------------ */
+typedef struct lem_server_s* lem_server_t;
+
+enum { LEM_REQ_QUEUED = 0, LEM_REQ_ACTIVE = 1, LEM_REQ_DONE = 2, LEM_REQ_FAILED = 3 };
+
+typedef struct {
+  size_t hbm_budget;     /* bytes of device memory for resident requests       */
+  int32_t max_active;    /* requests advanced together, >= 1                  */
+  double halo_tol;       /* decay-bound tolerance per step                     */
+  int32_t halo_min, halo_max;
+  double max_overhead;   /* largest (local points / core points) before a
+                            request falls back to the global method, >= 1    */
+  double krylov_tol;     /* relative Krylov tolerance per step                 */
+  int32_t krylov_m_max;  /* <= 48                                              */
+  int32_t max_substeps;
+  int32_t dry_run;       /* host-only scheduling: no device memory or kernels;
+                            a finished request returns its initial state     */
+} lem_server_options;
+
+typedef struct {
+  int32_t state;         /* LEM_REQ_*                                          */
+  int32_t method;        /* LEM_METHOD_KRYLOV or LEM_METHOD_GLOBAL             */
+  int32_t core, halo;    /* partition (0, 0 for the global method)             */
+  int32_t n_blocks, m_max, substeps_max;
+  int32_t n_steps, steps_done;
+  int64_t bytes;         /* pool bytes held while active                       */
+  double t_submit_ms, t_admit_ms, t_done_ms;  /* ms since server creation      */
+  int32_t error;         /* lem_status of a failed request                     */
+} lem_request_info;
+
+typedef struct {
+  int32_t n_queued, n_active, n_done, n_failed;
+  int64_t ticks;
+  int64_t bytes_in_use, bytes_budget;
+  double dof_steps;      /* grid points x steps advanced so far                */
+  int32_t device_status; /* latched device-side status (0 = fine)              */
+} lem_server_info;
+
+/* Defaults: 8 GiB pool, 256 active, halo tol 1e-8 in [4, 32], overhead 4,
+ * Krylov tol 1e-12, m <= 40, <= 64 sub-steps. */
+void lem_server_options_default(lem_server_options* opt);
+
+/* Reserve the pool and create a server working on `stream`.  Errors:
+ * LEM_ERR_INVALID (options), LEM_ERR_NOMEM (pool). */
+lem_status lem_server_create(const lem_server_options* opt, void* stream, lem_server_t* out);
+
+/* Queue a request: operator *op (copied, including nu_field), step dt,
+ * n_steps >= 1 steps from the HOST state x0_host (N doubles, copied).
+ * Returns its id.  LEM_ERR_BUDGET if its state alone cannot fit the pool;
+ * LEM_ERR_INVALID for a bad operator. */
+lem_status lem_server_submit(lem_server_t s, const lem_operator* op, double dt,
+                             int32_t n_steps, const double* x0_host, uint64_t* id);
+
+/* Admit queued requests, advance every active request by one step, retire
+ * the finished ones (their results are copied to host memory).  Blocks until
+ * the tick's device work is done.  Optional outputs: active / queued counts. */
+lem_status lem_server_tick(lem_server_t s, int32_t* n_active, int32_t* n_queued);
+
+/* State of a request (LEM_REQ_*); LEM_ERR_NOT_FOUND for unknown ids. */
+lem_status lem_server_poll(lem_server_t s, uint64_t id, int32_t* state);
+
+lem_status lem_server_request_info(lem_server_t s, uint64_t id, lem_request_info* info);
+
+/* Copy a finished request's final state (N doubles) to x_host and forget the
+ * request.  LEM_ERR_INVALID while it is not finished; a failed request
+ * returns its error and is forgotten. */
+lem_status lem_server_fetch(lem_server_t s, uint64_t id, double* x_host);
+
+lem_status lem_server_query(lem_server_t s, lem_server_info* info);
+
+/* Wait for the server's stream and free everything it owns.  NULL is ok. */
+lem_status lem_server_destroy(lem_server_t s);
+
 /* Message for the last non-OK status on this thread ("" if none). */
 const char* lem_last_error(void);
 

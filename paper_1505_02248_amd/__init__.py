@@ -249,3 +249,132 @@ def global_expmv(op: Operator, t: float, x, y, n_states: int = 1, tol: float = 1
                                    ctypes.c_void_p(_tensor_ptr(x, N, n_states)),
                                    ctypes.c_void_p(_tensor_ptr(y, N, n_states)), int(n_states),
                                    float(tol), int(m_max), ctypes.c_void_p(_stream_handle(stream))))
+
+
+# ------------------------------------------------------------------ serving --
+
+REQ_STATES = {0: "queued", 1: "active", 2: "done", 3: "failed"}
+
+
+class _ServerOptions(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_active", ctypes.c_int32),
+                ("halo_tol", ctypes.c_double), ("halo_min", ctypes.c_int32),
+                ("halo_max", ctypes.c_int32), ("max_overhead", ctypes.c_double),
+                ("krylov_tol", ctypes.c_double), ("krylov_m_max", ctypes.c_int32),
+                ("max_substeps", ctypes.c_int32), ("dry_run", ctypes.c_int32)]
+
+
+class _RequestInfo(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("method", ctypes.c_int32), ("core", ctypes.c_int32),
+                ("halo", ctypes.c_int32), ("n_blocks", ctypes.c_int32), ("m_max", ctypes.c_int32),
+                ("substeps_max", ctypes.c_int32), ("n_steps", ctypes.c_int32),
+                ("steps_done", ctypes.c_int32), ("bytes", ctypes.c_int64),
+                ("t_submit_ms", ctypes.c_double), ("t_admit_ms", ctypes.c_double),
+                ("t_done_ms", ctypes.c_double), ("error", ctypes.c_int32)]
+
+
+class _ServerInfo(ctypes.Structure):
+    _fields_ = [("n_queued", ctypes.c_int32), ("n_active", ctypes.c_int32),
+                ("n_done", ctypes.c_int32), ("n_failed", ctypes.c_int32),
+                ("ticks", ctypes.c_int64), ("bytes_in_use", ctypes.c_int64),
+                ("bytes_budget", ctypes.c_int64), ("dof_steps", ctypes.c_double),
+                ("device_status", ctypes.c_int32)]
+
+
+def _server_lib():
+    lib = load()
+    if getattr(lib, "_server_ready", False):
+        return lib
+    P, VP = ctypes.POINTER, ctypes.c_void_p
+    lib.lem_server_options_default.argtypes = [P(_ServerOptions)]
+    lib.lem_server_options_default.restype = None
+    lib.lem_server_create.argtypes = [P(_ServerOptions), VP, P(VP)]
+    lib.lem_server_submit.argtypes = [VP, P(_Operator), ctypes.c_double, ctypes.c_int32,
+                                      P(ctypes.c_double), P(ctypes.c_uint64)]
+    lib.lem_server_tick.argtypes = [VP, P(ctypes.c_int32), P(ctypes.c_int32)]
+    lib.lem_server_poll.argtypes = [VP, ctypes.c_uint64, P(ctypes.c_int32)]
+    lib.lem_server_request_info.argtypes = [VP, ctypes.c_uint64, P(_RequestInfo)]
+    lib.lem_server_fetch.argtypes = [VP, ctypes.c_uint64, P(ctypes.c_double)]
+    lib.lem_server_query.argtypes = [VP, P(_ServerInfo)]
+    lib.lem_server_destroy.argtypes = [VP]
+    for name in ("lem_server_create", "lem_server_submit", "lem_server_tick", "lem_server_poll",
+                 "lem_server_request_info", "lem_server_fetch", "lem_server_query",
+                 "lem_server_destroy"):
+        getattr(lib, name).restype = ctypes.c_int
+    lib._server_ready = True
+    return lib
+
+
+class Server:
+    """Continuous-batching LEM server (``lem_server_*``); see include/lem.h."""
+
+    def __init__(self, hbm_budget: int = 8 << 30, max_active: int = 256,
+                 halo_tol: float = 1e-8, halo_min: int = 4, halo_max: int = 32,
+                 max_overhead: float = 4.0, krylov_tol: float = 1e-12,
+                 krylov_m_max: int = 40, max_substeps: int = 64, dry_run: bool = False,
+                 stream=None):
+        lib = _server_lib()
+        o = _ServerOptions()
+        lib.lem_server_options_default(ctypes.byref(o))
+        o.hbm_budget, o.max_active = int(hbm_budget), int(max_active)
+        o.halo_tol, o.halo_min, o.halo_max = halo_tol, halo_min, halo_max
+        o.max_overhead, o.krylov_tol = max_overhead, krylov_tol
+        o.krylov_m_max, o.max_substeps, o.dry_run = krylov_m_max, max_substeps, int(dry_run)
+        h = ctypes.c_void_p()
+        st = 0 if dry_run else _stream_handle(stream)
+        _check(lib.lem_server_create(ctypes.byref(o), ctypes.c_void_p(st), ctypes.byref(h)))
+        self._h = h
+        self._sizes = {}
+
+    def submit(self, op: Operator, dt: float, n_steps: int, x0: np.ndarray) -> int:
+        x0 = np.ascontiguousarray(x0, dtype=np.float64).reshape(-1)
+        if x0.size != op.N:
+            raise ValueError("x0 must have N entries")
+        oc = op._c()
+        rid = ctypes.c_uint64()
+        _check(_server_lib().lem_server_submit(self._h, ctypes.byref(oc), float(dt), int(n_steps),
+                                               x0.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                               ctypes.byref(rid)))
+        self._sizes[rid.value] = op.N
+        return rid.value
+
+    def tick(self):
+        a, q = ctypes.c_int32(), ctypes.c_int32()
+        _check(_server_lib().lem_server_tick(self._h, ctypes.byref(a), ctypes.byref(q)))
+        return a.value, q.value
+
+    def poll(self, rid: int) -> str:
+        st = ctypes.c_int32()
+        _check(_server_lib().lem_server_poll(self._h, rid, ctypes.byref(st)))
+        return REQ_STATES[st.value]
+
+    def request_info(self, rid: int) -> dict:
+        info = _RequestInfo()
+        _check(_server_lib().lem_server_request_info(self._h, rid, ctypes.byref(info)))
+        d = {f: getattr(info, f) for f, _ in _RequestInfo._fields_}
+        d["state"] = REQ_STATES[d["state"]]
+        d["method"] = {v: k for k, v in METHODS.items()}[d["method"]]
+        return d
+
+    def fetch(self, rid: int) -> np.ndarray:
+        out = np.empty(self._sizes[rid], dtype=np.float64)
+        _check(_server_lib().lem_server_fetch(self._h, rid,
+                                              out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        self._sizes.pop(rid, None)
+        return out
+
+    def query(self) -> dict:
+        info = _ServerInfo()
+        _check(_server_lib().lem_server_query(self._h, ctypes.byref(info)))
+        return {f: getattr(info, f) for f, _ in _ServerInfo._fields_}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) and self._h.value:
+            _server_lib().lem_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -63,11 +63,13 @@ __global__ __launch_bounds__(NT) void krylov_lem_kernel(KrylovArgs a) {
   double* EA = piv + NT / 64 + 8;         // m*m
   double* EW = EA + m * m;                // 5*m*m
   double* ER = EW + 5 * m * m;            // m*m
+  const double* x_in = b.xin ? b.xin : a.x_in;
+  double* x_out = b.xout ? b.xout : a.x_out;
   double* V;
   if (VLDS) {
     V = ER + m * m;
   } else {
-    V = a.vwork + b.v_off + (int64_t)s * (m + 1) * nloc;
+    V = (b.vwork ? b.vwork : a.vwork + b.v_off) + (int64_t)s * (m + 1) * nloc;
   }
 
   // Points owned by this thread and their box coordinates.
@@ -81,7 +83,7 @@ __global__ __launch_bounds__(NT) void krylov_lem_kernel(KrylovArgs a) {
     lxs[p] = live[p] ? l - lys[p] * b.Lx : 0;
   }
   const bool varcoef = b.mu_off >= 0;
-  const double* mux = a.coef + (varcoef ? b.mu_off : 0);
+  const double* mux = (b.coef ? b.coef : a.coef) + (varcoef ? b.mu_off : 0);
   const int64_t Ng = (b.ndim == 1) ? b.n : (int64_t)b.n * b.n;
   const double* muy = mux + Ng;
 
@@ -89,7 +91,7 @@ __global__ __launch_bounds__(NT) void krylov_lem_kernel(KrylovArgs a) {
   double cur[PMAX];
 #pragma unroll
   for (int p = 0; p < PMAX; ++p)
-    cur[p] = live[p] ? a.x_in[b.x_off + gather_index(b, lxs[p], lys[p]) * b.ns + s] : 0.0;
+    cur[p] = live[p] ? x_in[b.x_off + gather_index(b, lxs[p], lys[p]) * b.ns + s] : 0.0;
 
   double nrm0 = 0.0;
 #pragma unroll
@@ -248,7 +250,7 @@ __global__ __launch_bounds__(NT) void krylov_lem_kernel(KrylovArgs a) {
     const int64_t g = (b.ndim == 1) ? (int64_t)(b.ox + rx)
                                     : (int64_t)(b.oy + ry) * b.n + (b.ox + rx);
     if (!isfinite(cur[p])) bad = true;
-    a.x_out[b.x_off + g * b.ns + s] = cur[p];
+    x_out[b.x_off + g * b.ns + s] = cur[p];
   }
   if (bad) atomicOr(a.status, kStatusNonFinite);
   if (tid == 0) {

@@ -37,6 +37,13 @@ struct KBlock {
   int32_t m, nsub;            // Krylov dimension, equal sub-steps per step
   int32_t ns;                 // ensemble size (stride of the state arrays)
   int32_t diag;               // index of this block's estimate slot
+  // Optional per-block buffers (null: the launch's arguments).  A serving
+  // launch mixes blocks of independent problems, each with its own state,
+  // coefficients and basis work space.
+  const double* xin;
+  double* xout;
+  const double* coef;
+  double* vwork;
 };
 
 __device__ __forceinline__ int wrap(int a, int n) {
@@ -136,11 +143,13 @@ __device__ __forceinline__ void lds_matmul(const double* A, const double* B,
   __syncthreads();
 }
 
-// R = exp(A) for the m x m matrix A (LDS, row-major, destroyed).  W holds
+// R = exp(A) for the m x m matrix A (LDS, row-major, destroyed); inlined into
+// each kernel (one out-of-line copy shared by two kernels of different LDS
+// layouts is rejected by the gfx950 backend).  W holds
 // 5*m*m doubles of LDS work space, piv at least 2*NT/64 + 4 doubles.  Every
 // thread of the workgroup must call it; R is visible to all on return.
 template <int NT>
-__device__ void expm_small(double* A, int m, double* W, double* R, double* piv) {
+__device__ __forceinline__ void expm_small(double* A, int m, double* W, double* R, double* piv) {
   const int tid = threadIdx.x;
   const int mm = m * m;
   double* A2 = W;

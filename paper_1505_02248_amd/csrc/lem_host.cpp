@@ -8,11 +8,14 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <deque>
 #include <map>
+#include <tuple>
 #include <string>
 #include <utility>
 #include <vector>
 
+#include "arena.h"
 #include "lem.h"
 #include "lem_launch.h"
 
@@ -269,6 +272,8 @@ struct lem_plan_s {
   int* d_status = nullptr;
   double* d_tmp = nullptr;
   std::vector<void*> allocs;
+  lem::Arena* arena = nullptr;  // allocate from a serving pool instead of hipMalloc
+  std::vector<lem::KBlock> kb_host;  // step descriptors (Krylov), bucket order
   int64_t bytes_blocks = 0, bytes_work = 0;
   hipStream_t stream = nullptr;
   std::map<std::pair<const void*, void*>, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
@@ -279,7 +284,10 @@ struct lem_plan_s {
       hipGraphExecDestroy(g.second.second);
       hipGraphDestroy(g.second.first);
     }
-    for (void* p : allocs) hipFree(p);
+    for (void* q : allocs) {
+      if (arena) arena->release(q);
+      else hipFree(q);
+    }
   }
 };
 
@@ -290,10 +298,17 @@ lem_status dalloc(lem_plan_s* p, T** out, size_t count, int64_t* account = nullp
   *out = nullptr;
   if (count == 0) count = 1;
   void* ptr = nullptr;
-  hipError_t e = hipMalloc(&ptr, count * sizeof(T));
-  if (e != hipSuccess) {
-    hipGetLastError();
-    return fail(LEM_ERR_NOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+  if (p->arena) {
+    ptr = p->arena->alloc(count * sizeof(T));
+    if (!ptr)
+      return fail(LEM_ERR_BUDGET, "memory budget exhausted (" + std::to_string(count * sizeof(T)) +
+                                      " bytes requested)");
+  } else {
+    hipError_t e = hipMalloc(&ptr, count * sizeof(T));
+    if (e != hipSuccess) {
+      hipGetLastError();
+      return fail(LEM_ERR_NOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    }
   }
   p->allocs.push_back(ptr);
   if (account) *account += (int64_t)(count * sizeof(T));
@@ -305,7 +320,8 @@ void dfree(lem_plan_s* p, void* ptr) {
   if (!ptr) return;
   auto it = std::find(p->allocs.begin(), p->allocs.end(), ptr);
   if (it != p->allocs.end()) p->allocs.erase(it);
-  hipFree(ptr);
+  if (p->arena) p->arena->release(ptr);
+  else hipFree(ptr);
 }
 
 lem_status upload(void* dst, const void* src, size_t bytes, hipStream_t st) {
@@ -575,6 +591,7 @@ lem_status plan_krylov(lem_plan_s* p, hipStream_t st) {
   }
   int64_t vw = 0;
   LEM_TRY(bucketize(kb, p->buckets, p->ns, &vw));
+  p->kb_host = kb;
   LEM_TRY(dalloc(p, &p->d_kb, kb.size(), &p->bytes_work));
   LEM_TRY(upload(p->d_kb, kb.data(), kb.size() * sizeof(lem::KBlock), st));
   LEM_TRY(dalloc(p, &p->d_vwork, (size_t)std::max<int64_t>(vw, 1), &p->bytes_work));
@@ -921,6 +938,60 @@ bool overlap(const void* a, const void* b, size_t bytes) {
   return x < y + bytes && y < x + bytes;
 }
 
+lem_status create_plan(const lem_operator* op, double dt, const lem_options* opt, void* stream,
+                       lem::Arena* arena, lem_plan_t* out) {
+  if (!out) return fail(LEM_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  LEM_TRY(check_options(opt));
+  const auto t0 = std::chrono::steady_clock::now();
+  auto p = new lem_plan_s();
+  auto guard = [&](lem_status s) { if (s != LEM_OK) delete p; return s; };
+  p->arena = arena;
+  p->opt = *opt;
+  p->method = opt->method;
+  p->ns = opt->n_states;
+  p->dry = opt->dry_run != 0;
+  p->stream = (hipStream_t)stream;
+  lem_status s = build_op(op, dt, &p->op);
+  if (s != LEM_OK) return guard(s);
+  p->N = p->op.N();
+  if (p->method == LEM_METHOD_KRYLOV || p->method == LEM_METHOD_DENSE) {
+    if (p->opt.core == 0 && p->method == LEM_METHOD_KRYLOV && p->op.ndim == 1)
+      p->opt.core = std::min(64, p->op.n);
+    if (p->opt.core == p->op.n)
+      return guard(fail(LEM_ERR_INVALID, "a single core covering the grid is the global method"));
+    s = make_partition(p);
+    if (s != LEM_OK) return guard(s);
+  }
+  if (!p->dry) {
+    hipStream_t st = p->stream;
+    s = dalloc(p, &p->d_status, 1);
+    if (s != LEM_OK) return guard(s);
+    if (hipMemsetAsync(p->d_status, 0, sizeof(int), st) != hipSuccess)
+      return guard(fail(LEM_ERR_HIP, "hipMemsetAsync failed"));
+    if (!arena) {  // serving plans step between the server's own buffers
+      s = dalloc(p, &p->d_tmp, (size_t)p->N * p->ns, &p->bytes_work);
+      if (s != LEM_OK) return guard(s);
+    }
+    if (p->method == LEM_METHOD_KRYLOV) s = plan_krylov(p, st);
+    else if (p->method == LEM_METHOD_DENSE) s = plan_dense(p, st);
+    else s = plan_global(p, st);
+    if (s != LEM_OK) return guard(s);
+    if (p->method == LEM_METHOD_DENSE && opt->autotune && p->ns % 64 == 0) {
+      s = autotune_dense(p, st);
+      if (s != LEM_OK) return guard(s);
+    }
+    if (hipStreamSynchronize(st) != hipSuccess)
+      return guard(fail(LEM_ERR_HIP, "plan synchronization failed"));
+  } else if (p->method == LEM_METHOD_KRYLOV) {
+    p->m.assign(p->boxes.size(), opt->krylov_m);
+    p->nsub.assign(p->boxes.size(), 1);
+  }
+  p->plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *out = p;
+  return LEM_OK;
+}
+
 }  // namespace
 
 // ================================================================ C ABI ====
@@ -948,59 +1019,14 @@ void lem_options_default(lem_options* o) {
 
 lem_status lem_plan(const lem_operator* op, double dt, const lem_options* opt, void* stream,
                     lem_plan_t* out) {
-  if (!out) return fail(LEM_ERR_INVALID, "out is NULL");
-  *out = nullptr;
-  LEM_TRY(check_options(opt));
-  const auto t0 = std::chrono::steady_clock::now();
-  auto p = new lem_plan_s();
-  auto guard = [&](lem_status s) { if (s != LEM_OK) delete p; return s; };
-  p->opt = *opt;
-  p->method = opt->method;
-  p->ns = opt->n_states;
-  p->dry = opt->dry_run != 0;
-  p->stream = (hipStream_t)stream;
-  lem_status s = build_op(op, dt, &p->op);
-  if (s != LEM_OK) return guard(s);
-  p->N = p->op.N();
-  if (p->method == LEM_METHOD_KRYLOV || p->method == LEM_METHOD_DENSE) {
-    if (p->opt.core == 0 && p->method == LEM_METHOD_KRYLOV && p->op.ndim == 1)
-      p->opt.core = std::min(64, p->op.n);
-    if (p->opt.core == p->op.n)
-      return guard(fail(LEM_ERR_INVALID, "a single core covering the grid is the global method"));
-    s = make_partition(p);
-    if (s != LEM_OK) return guard(s);
-  }
-  if (!p->dry) {
-    hipStream_t st = p->stream;
-    s = dalloc(p, &p->d_status, 1);
-    if (s != LEM_OK) return guard(s);
-    if (hipMemsetAsync(p->d_status, 0, sizeof(int), st) != hipSuccess)
-      return guard(fail(LEM_ERR_HIP, "hipMemsetAsync failed"));
-    s = dalloc(p, &p->d_tmp, (size_t)p->N * p->ns, &p->bytes_work);
-    if (s != LEM_OK) return guard(s);
-    if (p->method == LEM_METHOD_KRYLOV) s = plan_krylov(p, st);
-    else if (p->method == LEM_METHOD_DENSE) s = plan_dense(p, st);
-    else s = plan_global(p, st);
-    if (s != LEM_OK) return guard(s);
-    if (p->method == LEM_METHOD_DENSE && opt->autotune && p->ns % 64 == 0) {
-      s = autotune_dense(p, st);
-      if (s != LEM_OK) return guard(s);
-    }
-    if (hipStreamSynchronize(st) != hipSuccess)
-      return guard(fail(LEM_ERR_HIP, "plan synchronization failed"));
-  } else if (p->method == LEM_METHOD_KRYLOV) {
-    p->m.assign(p->boxes.size(), opt->krylov_m);
-    p->nsub.assign(p->boxes.size(), 1);
-  }
-  p->plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  *out = p;
-  return LEM_OK;
+  return create_plan(op, dt, opt, stream, nullptr, out);
 }
 
 lem_status lem_step(lem_plan_t p, const double* x_in, double* x_out, int32_t n_steps,
                     void* stream) {
   if (!p) return fail(LEM_ERR_INVALID, "plan is NULL");
   if (p->dry) return fail(LEM_ERR_INVALID, "a dry-run plan cannot step");
+  if (!p->d_tmp) return fail(LEM_ERR_INVALID, "a serving plan is stepped by its server");
   if (!x_in || !x_out) return fail(LEM_ERR_INVALID, "state pointers must not be NULL");
   if (n_steps < 1) return fail(LEM_ERR_INVALID, "n_steps must be >= 1");
   const size_t bytes = (size_t)p->N * p->ns * sizeof(double);
@@ -1124,5 +1150,438 @@ lem_status lem_plan_destroy(lem_plan_t p) {
 }
 
 const char* lem_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"
+
+// ============================================================== serving ====
+// Continuous batching of independent time-stepping requests.  Each request
+// is planned on admission (partition, decay-bound buffers, Krylov
+// calibration) with all of its device memory taken from one pool of the
+// configured size; every tick advances every active request by one step,
+// with the blocks of all LEM requests in shared Krylov launches (one per
+// launch shape).  Each block's arithmetic depends only on its own request,
+// so results do not depend on what else is in the batch.
+namespace {
+
+struct ServerReq {
+  uint64_t id = 0;
+  int state = LEM_REQ_QUEUED;
+  lem_operator op{};
+  std::vector<double> nu_field;
+  double dt = 0;
+  int n_steps = 0, done = 0;
+  std::vector<double> x0, result;
+  lem_plan_s* plan = nullptr;
+  double* buf[2] = {nullptr, nullptr};
+  int method = LEM_METHOD_KRYLOV, core = 0, halo = 0;
+  int64_t bytes = 0;
+  double t_submit = 0, t_admit = 0, t_done = 0;
+  lem_status error = LEM_OK;
+  int64_t N() const { return op.ndim == 1 ? (int64_t)op.n : (int64_t)op.n * op.n; }
+};
+
+}  // namespace
+
+struct lem_server_s {
+  lem_server_options opt{};
+  hipStream_t st = nullptr;
+  char* pool = nullptr;
+  lem::Arena* arena = nullptr;
+  std::deque<uint64_t> queue;
+  std::map<uint64_t, ServerReq> reqs;
+  std::vector<uint64_t> active;
+  uint64_t next = 1;
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  lem::KBlock* d_table = nullptr;
+  lem::KBlock* h_table = nullptr;
+  double* d_diag = nullptr;
+  int* d_status = nullptr;
+  size_t cap = 0;
+  int64_t ticks = 0;
+  double dof_steps = 0;
+  int n_done = 0, n_failed = 0;
+  int status_seen = 0;
+
+  double now_ms() const {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  ~lem_server_s() {
+    if (!opt.dry_run) hipStreamSynchronize(st);
+    for (auto& kv : reqs) delete kv.second.plan;  // arena ranges die with the pool
+    if (!opt.dry_run) {
+      hipFree(pool);
+      hipFree(d_table);
+      hipFree(d_diag);
+      hipFree(d_status);
+      hipHostFree(h_table);
+    }
+    delete arena;
+  }
+};
+
+namespace {
+
+lem_status server_grow(lem_server_s* s, size_t blocks) {
+  if (blocks <= s->cap) return LEM_OK;
+  size_t cap = std::max<size_t>(blocks, 2 * s->cap);
+  LEM_HIP(hipStreamSynchronize(s->st));
+  hipFree(s->d_table);
+  hipFree(s->d_diag);
+  hipHostFree(s->h_table);
+  s->d_table = nullptr; s->d_diag = nullptr; s->h_table = nullptr;
+  LEM_HIP(hipMalloc(&s->d_table, cap * sizeof(lem::KBlock)));
+  LEM_HIP(hipMalloc(&s->d_diag, cap * sizeof(double)));
+  LEM_HIP(hipHostMalloc(&s->h_table, cap * sizeof(lem::KBlock), hipHostMallocDefault));
+  s->cap = cap;
+  return LEM_OK;
+}
+
+// Partition choice for one request: core side c in {16, 32, 64} (dividing n)
+// with the fewest local points per core point, under the box limits of the
+// Krylov kernel; the global method when no core qualifies or the overhead is
+// above opt.max_overhead.
+void choose_partition(const lem_server_s* s, ServerReq& r, const Op& op) {
+  const double G = growth_factor(op);
+  bool clamped = false;
+  Box b0{0, 0, 16, op.ndim == 2 ? 16 : 1, 0};
+  const int h = halo_from_bound(op, b0, s->opt.halo_tol, s->opt.halo_min, s->opt.halo_max, G,
+                                &clamped);
+  r.method = LEM_METHOD_GLOBAL;
+  r.core = 0;
+  r.halo = 0;
+  if (clamped) return;
+  double best = INFINITY;
+  for (int c : {16, 32, 64}) {
+    if (op.n % c || c + 2 * h >= op.n) continue;
+    const int L = c + 2 * h;
+    const int64_t nloc = op.ndim == 2 ? (int64_t)L * L : L;
+    if (nloc > 10240) continue;
+    const double ov = op.ndim == 2 ? (double)L * L / ((double)c * c) : (double)L / c;
+    if (ov < best) { best = ov; r.core = c; }
+  }
+  if (r.core && best <= s->opt.max_overhead) {
+    r.method = LEM_METHOD_KRYLOV;
+    r.halo = h;
+  } else {
+    r.core = 0;
+  }
+}
+
+// Admission of the queue head; LEM_ERR_BUDGET leaves it queued.
+lem_status server_admit(lem_server_s* s, ServerReq& r) {
+  Op op;
+  LEM_TRY(build_op(&r.op, r.dt, &op));
+  choose_partition(s, r, op);
+  lem_options o;
+  lem_options_default(&o);
+  o.method = r.method;
+  o.n_states = 1;
+  o.core = r.core;
+  o.halo = r.halo;
+  o.krylov_tol = s->opt.krylov_tol;
+  o.krylov_m_max = s->opt.krylov_m_max;
+  o.max_substeps = s->opt.max_substeps;
+  o.dry_run = s->opt.dry_run;
+  const size_t before = s->arena->in_use();
+  lem_plan_t p = nullptr;
+  LEM_TRY(create_plan(&r.op, r.dt, &o, s->st, s->arena, &p));
+  const int64_t N = r.N();
+  for (int q = 0; q < 2; ++q) {
+    r.buf[q] = (double*)s->arena->alloc(N * sizeof(double));
+    if (!r.buf[q]) {
+      s->arena->release(r.buf[0]);
+      r.buf[0] = r.buf[1] = nullptr;
+      delete p;
+      return fail(LEM_ERR_BUDGET, "memory budget exhausted");
+    }
+  }
+  if (!s->opt.dry_run) {
+    hipError_t e = hipMemcpyAsync(r.buf[0], r.x0.data(), N * sizeof(double),
+                                  hipMemcpyHostToDevice, s->st);
+    if (e != hipSuccess) {
+      s->arena->release(r.buf[0]);
+      s->arena->release(r.buf[1]);
+      r.buf[0] = r.buf[1] = nullptr;
+      delete p;
+      return fail(LEM_ERR_HIP, "state upload failed");
+    }
+  }
+  r.plan = p;
+  r.bytes = (int64_t)(s->arena->in_use() - before);
+  r.state = LEM_REQ_ACTIVE;
+  r.t_admit = s->now_ms();
+  return LEM_OK;
+}
+
+void server_release(lem_server_s* s, ServerReq& r) {
+  delete r.plan;  // returns its ranges to the arena
+  r.plan = nullptr;
+  s->arena->release(r.buf[0]);
+  s->arena->release(r.buf[1]);
+  r.buf[0] = r.buf[1] = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+void lem_server_options_default(lem_server_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->hbm_budget = (size_t)8 << 30;
+  o->max_active = 256;
+  o->halo_tol = 1e-8;
+  o->halo_min = 4;
+  o->halo_max = 32;
+  o->max_overhead = 4.0;
+  o->krylov_tol = 1e-12;
+  o->krylov_m_max = 40;
+  o->max_substeps = 64;
+  o->dry_run = 0;
+}
+
+lem_status lem_server_create(const lem_server_options* opt, void* stream, lem_server_t* out) {
+  if (!opt || !out) return fail(LEM_ERR_INVALID, "NULL argument");
+  *out = nullptr;
+  if (opt->hbm_budget < 4096 || opt->max_active < 1 || !(opt->halo_tol > 0) ||
+      opt->halo_min < 0 || opt->halo_max < opt->halo_min || !(opt->max_overhead >= 1) ||
+      !(opt->krylov_tol > 0) || opt->krylov_m_max < 2 || opt->krylov_m_max > lem::kMaxKrylov ||
+      opt->max_substeps < 1)
+    return fail(LEM_ERR_INVALID, "invalid server options");
+  auto s = new lem_server_s();
+  s->opt = *opt;
+  s->st = (hipStream_t)stream;
+  if (opt->dry_run) {
+    s->arena = new lem::Arena((char*)(uintptr_t)4096, opt->hbm_budget);
+  } else {
+    if (hipMalloc(&s->pool, opt->hbm_budget) != hipSuccess) {
+      hipGetLastError();
+      delete s;
+      return fail(LEM_ERR_NOMEM, "could not reserve the serving pool");
+    }
+    s->arena = new lem::Arena(s->pool, opt->hbm_budget);
+    if (hipMalloc(&s->d_status, sizeof(int)) != hipSuccess ||
+        hipMemsetAsync(s->d_status, 0, sizeof(int), s->st) != hipSuccess ||
+        server_grow(s, 4096) != LEM_OK) {
+      delete s;
+      return fail(LEM_ERR_NOMEM, "could not allocate serving tables");
+    }
+  }
+  *out = s;
+  return LEM_OK;
+}
+
+lem_status lem_server_submit(lem_server_t s, const lem_operator* op, double dt, int32_t n_steps,
+                             const double* x0_host, uint64_t* id) {
+  if (!s || !op || !x0_host || !id) return fail(LEM_ERR_INVALID, "NULL argument");
+  if (n_steps < 1) return fail(LEM_ERR_INVALID, "n_steps must be >= 1");
+  Op chk;
+  LEM_TRY(build_op(op, dt, &chk));
+  ServerReq r;
+  r.id = s->next++;
+  r.op = *op;
+  r.dt = dt;
+  r.n_steps = n_steps;
+  const int64_t N = r.N();
+  if ((size_t)(2 * N * sizeof(double)) > s->opt.hbm_budget)
+    return fail(LEM_ERR_BUDGET, "request state alone exceeds the memory budget");
+  if (op->nu_field) {
+    r.nu_field.assign(op->nu_field, op->nu_field + N);
+    r.op.nu_field = r.nu_field.data();
+  }
+  r.x0.assign(x0_host, x0_host + N);
+  r.t_submit = s->now_ms();
+  *id = r.id;
+  auto it = s->reqs.emplace(r.id, std::move(r)).first;
+  if (!it->second.nu_field.empty()) it->second.op.nu_field = it->second.nu_field.data();
+  s->queue.push_back(*id);
+  return LEM_OK;
+}
+
+lem_status lem_server_tick(lem_server_t s, int32_t* n_active, int32_t* n_queued) {
+  if (!s) return fail(LEM_ERR_INVALID, "server is NULL");
+  // 1. admission, first come first served
+  while (!s->queue.empty() && (int)s->active.size() < s->opt.max_active) {
+    ServerReq& r = s->reqs[s->queue.front()];
+    lem_status st = server_admit(s, r);
+    if (st == LEM_ERR_BUDGET) {
+      if (s->active.empty()) {  // cannot fit even alone: fail it
+        r.state = LEM_REQ_FAILED;
+        r.error = st;
+        s->n_failed++;
+        s->queue.pop_front();
+        continue;
+      }
+      break;
+    }
+    s->queue.pop_front();
+    if (st != LEM_OK) {
+      r.state = LEM_REQ_FAILED;
+      r.error = st;
+      s->n_failed++;
+      continue;
+    }
+    s->active.push_back(r.id);
+  }
+  // 2. one step of every active request
+  if (!s->opt.dry_run && !s->active.empty()) {
+    size_t nb = 0;
+    for (uint64_t id : s->active) nb += s->reqs[id].plan->kb_host.size();
+    LEM_TRY(server_grow(s, nb));
+    struct Key { int nt, pmax; bool vlds; bool operator<(const Key& o) const {
+      return std::tie(nt, pmax, vlds) < std::tie(o.nt, o.pmax, o.vlds); } };
+    std::map<Key, std::vector<lem::KBlock>> groups;
+    std::map<Key, size_t> lds;
+    int diag = 0;
+    for (uint64_t id : s->active) {
+      ServerReq& r = s->reqs[id];
+      double* in = r.buf[r.done & 1];
+      double* out = r.buf[(r.done + 1) & 1];
+      if (r.method == LEM_METHOD_GLOBAL) {
+        LEM_TRY(run_step(r.plan, in, out, s->st));
+        continue;
+      }
+      const lem_plan_s* p = r.plan;
+      for (const auto& bk : p->buckets)
+        for (int i = bk.first; i < bk.first + bk.count; ++i) {
+          lem::KBlock k = p->kb_host[i];
+          k.xin = in;
+          k.xout = out;
+          k.coef = p->d_coef;
+          k.vwork = p->d_vwork + k.v_off;
+          k.diag = diag++;
+          Key key{bk.nt, bk.pmax, bk.vlds};
+          groups[key].push_back(k);
+          lds[key] = std::max(lds[key], bk.lds);
+        }
+    }
+    size_t off = 0;
+    for (auto& g : groups) {
+      std::memcpy(s->h_table + off, g.second.data(), g.second.size() * sizeof(lem::KBlock));
+      off += g.second.size();
+    }
+    if (off) LEM_HIP(hipMemcpyAsync(s->d_table, s->h_table, off * sizeof(lem::KBlock),
+                                    hipMemcpyHostToDevice, s->st));
+    off = 0;
+    for (auto& g : groups) {
+      hipError_t e = lem::launch_krylov(s->d_table + off, (int)g.second.size(), 1, g.first.nt,
+                                        g.first.pmax, g.first.vlds, lds[g.first], nullptr,
+                                        nullptr, nullptr, nullptr, s->d_diag, s->d_status,
+                                        nullptr, 0, s->st);
+      if (e != hipSuccess)
+        return fail(LEM_ERR_HIP, std::string("serving launch: ") + hipGetErrorString(e));
+      off += g.second.size();
+    }
+  }
+  // 3. advance counters, retire finished requests
+  std::vector<uint64_t> finished, still;
+  for (uint64_t id : s->active) {
+    ServerReq& r = s->reqs[id];
+    r.done++;
+    s->dof_steps += (double)r.N();
+    if (r.done == r.n_steps) finished.push_back(id);
+    else still.push_back(id);
+  }
+  for (uint64_t id : finished) {
+    ServerReq& r = s->reqs[id];
+    r.result.resize(r.N());
+    if (s->opt.dry_run) {
+      r.result = r.x0;
+    } else {
+      LEM_HIP(hipMemcpyAsync(r.result.data(), r.buf[r.n_steps & 1], r.N() * sizeof(double),
+                             hipMemcpyDeviceToHost, s->st));
+    }
+  }
+  if (!s->opt.dry_run) {
+    LEM_HIP(hipStreamSynchronize(s->st));
+    int st = 0;
+    LEM_HIP(hipMemcpy(&st, s->d_status, sizeof(int), hipMemcpyDeviceToHost));
+    s->status_seen |= st;
+  }
+  const double t = s->now_ms();
+  for (uint64_t id : finished) {
+    ServerReq& r = s->reqs[id];
+    server_release(s, r);
+    r.state = LEM_REQ_DONE;
+    r.t_done = t;
+    s->n_done++;
+  }
+  s->active.swap(still);
+  s->ticks++;
+  if (n_active) *n_active = (int32_t)s->active.size();
+  if (n_queued) *n_queued = (int32_t)s->queue.size();
+  return LEM_OK;
+}
+
+lem_status lem_server_poll(lem_server_t s, uint64_t id, int32_t* state) {
+  if (!s || !state) return fail(LEM_ERR_INVALID, "NULL argument");
+  auto it = s->reqs.find(id);
+  if (it == s->reqs.end()) return fail(LEM_ERR_NOT_FOUND, "unknown request id");
+  *state = it->second.state;
+  return LEM_OK;
+}
+
+lem_status lem_server_request_info(lem_server_t s, uint64_t id, lem_request_info* info) {
+  if (!s || !info) return fail(LEM_ERR_INVALID, "NULL argument");
+  auto it = s->reqs.find(id);
+  if (it == s->reqs.end()) return fail(LEM_ERR_NOT_FOUND, "unknown request id");
+  const ServerReq& r = it->second;
+  std::memset(info, 0, sizeof(*info));
+  info->state = r.state;
+  info->method = r.method;
+  info->core = r.core;
+  info->halo = r.halo;
+  info->n_steps = r.n_steps;
+  info->steps_done = r.done;
+  info->bytes = r.bytes;
+  info->t_submit_ms = r.t_submit;
+  info->t_admit_ms = r.t_admit;
+  info->t_done_ms = r.t_done;
+  info->error = r.error;
+  if (r.plan) {
+    lem_plan_info pi;
+    fill_info(r.plan, &pi);
+    info->n_blocks = pi.n_blocks;
+    info->m_max = pi.m_max;
+    info->substeps_max = pi.substeps_max;
+  }
+  return LEM_OK;
+}
+
+lem_status lem_server_fetch(lem_server_t s, uint64_t id, double* x_host) {
+  if (!s || !x_host) return fail(LEM_ERR_INVALID, "NULL argument");
+  auto it = s->reqs.find(id);
+  if (it == s->reqs.end()) return fail(LEM_ERR_NOT_FOUND, "unknown request id");
+  ServerReq& r = it->second;
+  if (r.state == LEM_REQ_FAILED) {
+    const lem_status e = r.error;
+    s->reqs.erase(it);
+    return fail(e, "request failed");
+  }
+  if (r.state != LEM_REQ_DONE) return fail(LEM_ERR_INVALID, "request is not finished");
+  std::memcpy(x_host, r.result.data(), r.result.size() * sizeof(double));
+  s->reqs.erase(it);
+  return LEM_OK;
+}
+
+lem_status lem_server_query(lem_server_t s, lem_server_info* info) {
+  if (!s || !info) return fail(LEM_ERR_INVALID, "NULL argument");
+  std::memset(info, 0, sizeof(*info));
+  info->n_queued = (int32_t)s->queue.size();
+  info->n_active = (int32_t)s->active.size();
+  info->n_done = s->n_done;
+  info->n_failed = s->n_failed;
+  info->ticks = s->ticks;
+  info->bytes_in_use = (int64_t)s->arena->in_use();
+  info->bytes_budget = (int64_t)s->opt.hbm_budget;
+  info->dof_steps = s->dof_steps;
+  info->device_status = s->status_seen ? LEM_ERR_NOT_CONVERGED : 0;
+  return LEM_OK;
+}
+
+lem_status lem_server_destroy(lem_server_t s) {
+  delete s;
+  return LEM_OK;
+}
 
 }  // extern "C"

@@ -1,0 +1,71 @@
+"""GPU serving: results of co-batched requests equal their results alone
+(bitwise) and the oracle (LEM definition with the request's partition, or
+the exact global exponential for requests served by the global method)."""
+import numpy as np
+import pytest
+
+import lem_inputs as L
+from oracle import globalexp as ge
+from oracle import lem as olem
+from oracle import operator as op
+from oracle import partition as P
+from oracle.metrics import rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+import paper_1505_02248_amd as lem  # noqa: E402
+
+
+def problem(n, nu, mult, seed):
+    x = L.smooth_states_2d(n, 1, seed, n_modes=8, kmax=4)[:, 0]
+    return lem.Operator(2, n, 1.0 / n, (1.0, 0.5), nu), mult / n, x
+
+
+REQS = {"A": (128, 2e-3, 2, 7, 11), "B": (64, 1e-4, 1, 3, 12), "C": (256, 5e-3, 4, 5, 13),
+        "D": (64, 1e-2, 4, 2, 14), "E": (128, 1e-4, 1, 4, 15)}
+
+
+def make_server():
+    return lem.Server(hbm_budget=2 << 30, max_active=16, krylov_tol=1e-14)
+
+
+def run_alone(name):
+    n, nu, mult, steps, seed = REQS[name]
+    o, dt, x = problem(n, nu, mult, seed)
+    s = make_server()
+    rid = s.submit(o, dt, steps, x)
+    while s.poll(rid) != "done":
+        s.tick()
+    info = s.request_info(rid)
+    return s.fetch(rid), info
+
+
+def test_results_alone_equal_results_in_the_mix_and_the_oracle():
+    alone = {k: run_alone(k) for k in REQS}
+    s = make_server()
+    ids = {}
+    order = [("B",), ("A",), (), ("C", "D"), (), ("E",)]
+    for group in order:  # arrivals while others are on the device
+        for k in group:
+            n, nu, mult, steps, seed = REQS[k]
+            o, dt, x = problem(n, nu, mult, seed)
+            ids[k] = s.submit(o, dt, steps, x)
+        s.tick()
+    while any(s.poll(i) != "done" for i in ids.values()):
+        s.tick()
+    assert s.query()["device_status"] == 0
+    for k, rid in ids.items():
+        got = s.fetch(rid)
+        ref, info = alone[k]
+        assert np.array_equal(got, ref), k
+        n, nu, mult, steps, seed = REQS[k]
+        o, dt, x = problem(n, nu, mult, seed)
+        W = op.weights(2, n, 1.0 / n, dt, (1.0, 0.5), nu=nu)
+        if info["method"] == "global":
+            want = ge.fft_steps(W, x, steps)
+        else:
+            boxes = P.uniform_boxes(2, n, info["core"], info["halo"])
+            want = olem.run(op.sparse(W), boxes, 2, n, x, steps)
+        assert rel_l2(got, want) <= 1e-12, (k, info)
+    methods = {k: alone[k][1]["method"] for k in REQS}
+    assert "global" in methods.values() and "krylov" in methods.values()
