@@ -225,6 +225,22 @@ BlockCoef block_coef(const Op& op, const Box& b, int h) {
   return c;
 }
 
+// Largest row sum of |dt*A| over the box of b (with its own halo).
+double block_rho(const Op& op, const Box& b) {
+  double w[5], mx = 0.0;
+  const int n = op.n;
+  const int Lx = b.cx + 2 * b.h, Ly = op.ndim == 2 ? b.cy + 2 * b.h : 1;
+  for (int ly = 0; ly < Ly; ++ly)
+    for (int lx = 0; lx < Lx; ++lx) {
+      const int gx = ((b.ox - b.h + lx) % n + n) % n;
+      const int gy = op.ndim == 2 ? ((b.oy - b.h + ly) % n + n) % n : 0;
+      point_weights(op, gx, gy, w);
+      mx = std::max(mx, std::fabs(w[0]) + std::fabs(w[1]) + std::fabs(w[2]) + std::fabs(w[3]) +
+                            std::fabs(w[4]));
+    }
+  return mx;
+}
+
 // Smallest h in [h_min, h_max] with eps(h) <= tol (coefficients taken over the
 // box of width h itself); h_max and clamped = true when none qualifies.
 int halo_from_bound(const Op& op, Box b, double tol, int h_min, int h_max, double G,
@@ -507,19 +523,31 @@ lem_status plan_krylov(lem_plan_s* p, hipStream_t st) {
     LEM_TRY(upload(p->d_coef, op.mux.data(), op.N() * 8, st));
     LEM_TRY(upload(p->d_coef + op.N(), op.muy.data(), op.N() * 8, st));
   }
-  // calibration representatives: identical boxes of a constant operator share one
+  // Calibration representatives.  Krylov convergence is governed by the
+  // box shape and the norm of dt*A_M: blocks with the same box and a row-sum
+  // norm within the same 15% bucket share one calibration, taken on the
+  // member with the largest norm (the runtime estimate still checks every
+  // block every step).  Identical boxes of a constant operator share one.
   std::vector<int> rep(nb, -1);
   std::vector<int> reps;
   {
     std::map<std::tuple<int, int, int, int>, int> seen;
+    std::vector<double> rho(nb, 0.0);
     for (int i = 0; i < nb; ++i) {
       const Box& b = p->boxes[i];
-      if (!op.variable) {
-        auto key = std::make_tuple(b.cx, b.cy, b.h, 0);
-        auto it = seen.find(key);
-        if (it != seen.end()) { rep[i] = it->second; continue; }
-        seen[key] = (int)reps.size();
+      int bucket = 0;
+      if (op.variable) {
+        rho[i] = block_rho(op, b);
+        bucket = (int)std::floor(std::log(std::max(rho[i], 1e-300)) / std::log(1.15));
       }
+      auto key = std::make_tuple(b.cx, b.cy, b.h, bucket);
+      auto it = seen.find(key);
+      if (it != seen.end()) {
+        rep[i] = it->second;
+        if (rho[i] > rho[reps[it->second]]) reps[it->second] = i;
+        continue;
+      }
+      seen[key] = (int)reps.size();
       rep[i] = (int)reps.size();
       reps.push_back(i);
     }
