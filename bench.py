@@ -423,7 +423,11 @@ def bench_c4(args) -> dict:
     import lem_inputs as L
     import paper_1505_02248_amd as lem
     reqs = L.serving_stream(args.requests)
-    srv = lem.Server(hbm_budget=64 << 30, max_active=512, krylov_tol=1e-10)
+    import torch
+    free, total = torch.cuda.mem_get_info()
+    budget = min(16 << 30, int(free * 0.5))
+    log(f"device memory free {free / 2**30:.1f} GiB of {total / 2**30:.1f} GiB; pool {budget / 2**30:.1f} GiB")
+    srv = lem.Server(hbm_budget=budget, max_active=512, krylov_tol=1e-10)
     pending = list(reqs)
     arrival = {}
     done_t = {}
@@ -458,7 +462,7 @@ def bench_c4(args) -> dict:
     wl = {"workload": f"served Poisson stream ({len(reqs)} requests, 200 req/s) of 2D periodic "
                       "advection-diffusion, n in {64,128,256,512}, nu log-uniform [1e-4,1e-2], "
                       "dt in {1,2,4} dx, 20-200 steps, FP64, continuous batching",
-          "requests": len(reqs), "methods": methods}
+          "requests": len(reqs), "methods": methods, "pool_bytes": budget}
     extras = {"p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
               "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
               "mean_latency_ms": float(lat.mean() * 1e3), "makespan_s": makespan,
