@@ -1,0 +1,549 @@
+// LDS-resident Arnoldi-Krylov LEM step (gfx950).
+//
+// Same mathematics as krylov_lem.hip -- per region M_i of section 3, nsub
+// equal sub-steps of v <- beta V_m exp(H_m) e_1 for the local problem (4),
+// core rows written back (step 3) -- organized so that one workgroup keeps
+// the whole Krylov basis of its box in LDS:
+//   * sweep 1: stencil product on the LDS-resident v_j fused with the first
+//     Gram-Schmidt dots; one reduction;
+//   * sweep 2: first update fused with the re-orthogonalization dots and the
+//     squared norm of the updated vector; one reduction; the norm of the
+//     twice-orthogonalized vector follows from Pythagoras (the second
+//     correction is tiny), with an explicit reduction when cancellation is
+//     severe (near an invariant subspace);
+//   * sweep 3: second update, normalization, store of v_{j+1}.
+// Reductions of up to 32 values use a wave64 butterfly reduce-scatter
+// (about one cross-lane exchange per value instead of six), then one LDS
+// exchange between waves.  exp(H_m) is evaluated by Pade [13/13] scaling and
+// squaring with its matrix products on FP64 MFMA (v_mfma_f64_16x16x4) over
+// 16- or 32-padded tiles in LDS, and a pivoted elimination in LDS.
+#include "lem_device.hpp"
+#include "lem_launch.h"
+
+namespace lem {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+constexpr int kLdsMaxM = 30;  // Krylov dimension limit of this kernel
+
+// LDS layout in doubles; mirrored by krylov_lds_bytes() on the host.
+__host__ __device__ inline int64_t lds_layout(int NT, int m, int nloc, int64_t* off_h,
+                                              int64_t* off_red, int64_t* off_e) {
+  const int mp = m <= 16 ? 16 : 32;
+  int64_t d = (int64_t)(m + 1) * nloc;  // basis
+  *off_h = d;
+  d += (int64_t)(m + 1) * m;            // Hessenberg
+  *off_red = d;
+  d += (int64_t)(NT / 64) * 32 + 64;    // reduction exchange + scalars
+  *off_e = d;
+  d += 7 * (int64_t)mp * mp + 8;        // expm work (A, A2, A4, A6, U, V, R) + pivot
+  return d;
+}
+
+// Butterfly reduce-scatter over the wave: K values per lane in, the wave
+// total of value (lane >> log2(64/K)) out.
+template <int K>
+__device__ __forceinline__ double wave_reduce_scatter(double (&v)[K]) {
+  const int lane = threadIdx.x & 63;
+  int c = K;
+#pragma unroll
+  for (int o = 32; o >= 64 / K; o >>= 1) {
+    const int half = c >> 1;
+    const bool upper = (lane & o) != 0;
+#pragma unroll
+    for (int i = 0; i < K / 2; ++i) {
+      if (i < half) {
+        const double send = upper ? v[i] : v[i + half];
+        const double keep = upper ? v[i + half] : v[i];
+        v[i] = keep + __shfl_xor(send, o, 64);
+      }
+    }
+    c = half;
+  }
+  double r = v[0];
+#pragma unroll
+  for (int o = 32 / K; o >= 1; o >>= 1) r += __shfl_xor(r, o, 64);
+  return r;
+}
+
+// Workgroup sum of cnt <= 32 values (held per thread in v[0..cnt)); after the
+// call every thread can read total(i) = sum_w red[w*32 + i].
+template <int NT>
+__device__ __forceinline__ void wg_reduce32(double (&v)[32], int cnt, double* red) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (cnt <= 8) {
+    double t[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) t[i] = v[i];
+    const double r = wave_reduce_scatter<8>(t);
+    if ((lane & 7) == 0) red[wv * 32 + (lane >> 3)] = r;
+  } else if (cnt <= 16) {
+    double t[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) t[i] = v[i];
+    const double r = wave_reduce_scatter<16>(t);
+    if ((lane & 3) == 0) red[wv * 32 + (lane >> 2)] = r;
+  } else {
+    const double r = wave_reduce_scatter<32>(v);
+    if ((lane & 1) == 0) red[wv * 32 + (lane >> 1)] = r;
+  }
+  __syncthreads();
+}
+
+template <int NT>
+__device__ __forceinline__ double red_total(const double* red, int i) {
+  double s = red[i];
+#pragma unroll
+  for (int w = 1; w < NT / 64; ++w) s += red[w * 32 + i];
+  return s;
+}
+
+// C = A B for mp x mp matrices (mp = 16 or 32) in LDS, row-major, on FP64
+// MFMA.  Waves take 16x16 output tiles round-robin.
+template <int NT>
+__device__ __forceinline__ void mfma_matmul(const double* A, const double* B, double* C,
+                                            int mp) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int tiles = (mp / 16) * (mp / 16);
+  for (int t = wv; t < tiles; t += NT / 64) {
+    const int ti = t / (mp / 16), tj = t - ti * (mp / 16);
+    d4v acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < mp; k0 += 4) {
+      const double a = A[(ti * 16 + (lane & 15)) * mp + k0 + (lane >> 4)];
+      const double bb = B[(k0 + (lane >> 4)) * mp + tj * 16 + (lane & 15)];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      C[(ti * 16 + 4 * r + (lane >> 4)) * mp + tj * 16 + (lane & 15)] = acc[r];
+  }
+  __syncthreads();
+}
+
+// exp(A) for the leading m x m block of the mp x mp matrix A in LDS (padding
+// rows/columns zero).  Work W = 5 mp^2, result R (mp^2), piv >= NT/64 + 4.
+template <int NT>
+__device__ __forceinline__ void expm_mfma(double* A, int m, int mp, double* W, double* R,
+                                          double* piv) {
+  const int tid = threadIdx.x;
+  const int mm = mp * mp;
+  double* A2 = W;
+  double* A4 = W + mm;
+  double* A6 = W + 2 * mm;
+  double* U = W + 3 * mm;
+  double* V = W + 4 * mm;
+  double cs = 0.0;
+  for (int j = tid; j < m; j += NT) {
+    double t = 0.0;
+    for (int i = 0; i < m; ++i) t += fabs(A[i * mp + j]);
+    cs = fmax(cs, t);
+  }
+  cs = wave_max(cs);
+  if (NT > 64) {
+    if ((tid & 63) == 0) piv[tid >> 6] = cs;
+    __syncthreads();
+    cs = 0.0;
+    for (int w = 0; w < NT / 64; ++w) cs = fmax(cs, piv[w]);
+    __syncthreads();
+  }
+  int s = 0;
+  if (cs > kTheta13 && cs < 1e300) s = min(60, (int)ceil(log2(cs / kTheta13)));
+  if (s > 0) {
+    for (int idx = tid; idx < mm; idx += NT) A[idx] = ldexp(A[idx], -s);
+    __syncthreads();
+  }
+  const double* b = kPadeB;
+  mfma_matmul<NT>(A, A, A2, mp);
+  mfma_matmul<NT>(A2, A2, A4, mp);
+  mfma_matmul<NT>(A4, A2, A6, mp);
+  for (int idx = tid; idx < mm; idx += NT)
+    V[idx] = b[13] * A6[idx] + b[11] * A4[idx] + b[9] * A2[idx];
+  __syncthreads();
+  mfma_matmul<NT>(A6, V, U, mp);
+  for (int idx = tid; idx < mm; idx += NT) {
+    const int i = idx / mp, j = idx - i * mp;
+    U[idx] += b[7] * A6[idx] + b[5] * A4[idx] + b[3] * A2[idx] + (i == j ? b[1] : 0.0);
+  }
+  __syncthreads();
+  mfma_matmul<NT>(A, U, R, mp);  // R = U (odd part)
+  for (int idx = tid; idx < mm; idx += NT)
+    U[idx] = b[12] * A6[idx] + b[10] * A4[idx] + b[8] * A2[idx];
+  __syncthreads();
+  mfma_matmul<NT>(A6, U, V, mp);
+  for (int idx = tid; idx < mm; idx += NT) {
+    const int i = idx / mp, j = idx - i * mp;
+    const double v = V[idx] + b[6] * A6[idx] + b[4] * A4[idx] + b[2] * A2[idx] +
+                     (i == j ? b[0] : 0.0);
+    const double u = R[idx];
+    V[idx] = v + u;  // P
+    U[idx] = v - u;  // Q
+  }
+  __syncthreads();
+  // Q X = P on the leading m x m block (padding stays zero / identity-free:
+  // only the leading block is eliminated and used).
+  double* Q = U;
+  double* P = V;
+  double* fac = A;
+  for (int j = 0; j < m; ++j) {
+    if (tid < 64) {
+      double best = -1.0;
+      int bi = j;
+      for (int i = j + tid; i < m; i += 64) {
+        const double a = fabs(Q[i * mp + j]);
+        if (a > best) { best = a; bi = i; }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (tid == 0) piv[0] = (double)bi;
+    }
+    __syncthreads();
+    const int p = (int)piv[0];
+    if (p != j) {
+      for (int k = tid; k < 2 * m; k += NT) {
+        double* M = k < m ? Q : P;
+        const int kk = k < m ? k : k - m;
+        const double t = M[j * mp + kk];
+        M[j * mp + kk] = M[p * mp + kk];
+        M[p * mp + kk] = t;
+      }
+      __syncthreads();
+    }
+    const double inv = 1.0 / Q[j * mp + j];
+    for (int i = j + 1 + tid; i < m; i += NT) fac[i] = Q[i * mp + j] * inv;
+    __syncthreads();
+    const int rows = m - j - 1;
+    const int cols = (m - j - 1) + m;
+    for (int idx = tid; idx < rows * cols; idx += NT) {
+      const int r = j + 1 + idx / cols;
+      const int c = idx % cols;
+      if (c < m - j - 1) {
+        const int k = j + 1 + c;
+        Q[r * mp + k] = fma(-fac[r], Q[j * mp + k], Q[r * mp + k]);
+      } else {
+        const int k = c - (m - j - 1);
+        P[r * mp + k] = fma(-fac[r], P[j * mp + k], P[r * mp + k]);
+      }
+    }
+    __syncthreads();
+  }
+  for (int j = m - 1; j >= 0; --j) {
+    const double inv = 1.0 / Q[j * mp + j];
+    for (int k = tid; k < m; k += NT) P[j * mp + k] *= inv;
+    __syncthreads();
+    for (int idx = tid; idx < j * m; idx += NT) {
+      const int r = idx / m, k = idx - r * m;
+      P[r * mp + k] = fma(-Q[r * mp + j], P[j * mp + k], P[r * mp + k]);
+    }
+    __syncthreads();
+  }
+  // clear the padding of P so that products of the padded tiles are exact
+  for (int idx = tid; idx < mm; idx += NT) {
+    const int i = idx / mp, j = idx - i * mp;
+    if (i >= m || j >= m) P[idx] = 0.0;
+  }
+  __syncthreads();
+  double* src = P;
+  double* dst = A2;
+  for (int q = 0; q < s; ++q) {
+    mfma_matmul<NT>(src, src, dst, mp);
+    double* t = src; src = dst; dst = t;
+  }
+  for (int idx = tid; idx < mm; idx += NT) R[idx] = src[idx];
+  __syncthreads();
+}
+
+template <int NT, int P>
+__global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
+  extern __shared__ double smem[];
+  const int tid = threadIdx.x;
+  const int s = blockIdx.y;
+  const KBlock b = a.blocks[blockIdx.x];
+  const int m = b.m;
+  const int mp = m <= 16 ? 16 : 32;
+  const int nloc = b.Lx * b.Ly;
+  int64_t oh, ored, oe;
+  lds_layout(NT, m, nloc, &oh, &ored, &oe);
+  double* V = smem;
+  double* H = smem + oh;
+  double* red = smem + ored;            // [NT/64][32]
+  double* scal = red + (NT / 64) * 32;  // 64 scalars
+  double* EA = smem + oe;
+  double* EW = EA + mp * mp;
+  double* ER = EW + 5 * mp * mp;
+  double* piv = ER + mp * mp;
+
+  const double* x_in = b.xin ? b.xin : a.x_in;
+  double* x_out = b.xout ? b.xout : a.x_out;
+  const bool varcoef = b.mu_off >= 0;
+  const double* mux = (b.coef ? b.coef : a.coef) + (varcoef ? b.mu_off : 0);
+  const int64_t Ng = (b.ndim == 1) ? b.n : (int64_t)b.n * b.n;
+  const double* muy = mux + Ng;
+
+  int lxs[P], lys[P];
+  bool live[P];
+  double c0[P], cW[P], cE[P], cS[P], cN[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int l = tid + p * NT;
+    live[p] = l < nloc;
+    lys[p] = live[p] ? l / b.Lx : 0;
+    lxs[p] = live[p] ? l - lys[p] * b.Lx : 0;
+    // stencil weights of this point (couplings leaving the box are dropped)
+    double w0 = b.w0, wW = b.wW, wE = b.wE, wS = b.wS, wN = b.wN;
+    if (varcoef && live[p]) {
+      const int gx = wrap(b.ox - b.h + lxs[p], b.n);
+      const int gy = (b.ndim == 1) ? 0 : wrap(b.oy - b.h + lys[p], b.n);
+      const int64_t g = (int64_t)gy * b.n + gx;
+      const double me = mux[g];
+      const double mw = mux[(int64_t)gy * b.n + wrap(gx - 1, b.n)];
+      double mn = 0.0, ms = 0.0;
+      if (b.ndim == 2) {
+        mn = muy[g];
+        ms = muy[(int64_t)wrap(gy - 1, b.n) * b.n + gx];
+      }
+      const double sc = b.sub_scale;
+      w0 = -(me + mw + mn + ms) * sc;
+      wW = fma(mw, sc, b.chx);
+      wE = fma(me, sc, -b.chx);
+      wS = fma(ms, sc, b.chy);
+      wN = fma(mn, sc, -b.chy);
+    }
+    c0[p] = live[p] ? w0 : 0.0;
+    cW[p] = (live[p] && lxs[p] > 0) ? wW : 0.0;
+    cE[p] = (live[p] && lxs[p] < b.Lx - 1) ? wE : 0.0;
+    cS[p] = (live[p] && lys[p] > 0) ? wS : 0.0;
+    cN[p] = (live[p] && lys[p] < b.Ly - 1) ? wN : 0.0;
+  }
+
+  double cur[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p)
+    cur[p] = live[p] ? x_in[b.x_off + gather_index(b, lxs[p], lys[p]) * b.ns + s] : 0.0;
+
+  double vv[32];
+  auto norm2 = [&](const double (&x)[P]) {
+    double t = 0.0;
+#pragma unroll
+    for (int p = 0; p < P; ++p) t = fma(x[p], x[p], t);
+#pragma unroll
+    for (int i = 0; i < 32; ++i) vv[i] = 0.0;
+    vv[0] = t;
+    wg_reduce32<NT>(vv, 1, red);
+    const double r = red_total<NT>(red, 0);
+    __syncthreads();
+    return r;
+  };
+
+  const double beta0 = sqrt(norm2(cur));
+  double worst = 0.0;
+  bool bad = !isfinite(beta0);
+  const int nsub = (a.mode == 1) ? 1 : b.nsub;
+
+  for (int sub = 0; sub < nsub; ++sub) {
+    const double beta = (sub == 0) ? beta0 : sqrt(norm2(cur));
+    if (!(beta > 0.0) || !isfinite(beta)) {
+      if (!isfinite(beta)) bad = true;
+      break;
+    }
+    const double ib = 1.0 / beta;
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+      if (live[p]) V[tid + p * NT] = cur[p] * ib;
+    for (int idx = tid; idx < (m + 1) * m; idx += NT) H[idx] = 0.0;
+    __syncthreads();
+
+    int k = m;
+    for (int j = 0; j < m; ++j) {
+      const double* vj = V + (int64_t)j * nloc;
+      double w[P];
+      // sweep 1: stencil product and first dots
+#pragma unroll
+      for (int i = 0; i < 32; ++i) vv[i] = 0.0;
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        double r = 0.0;
+        if (live[p]) {
+          const int l = tid + p * NT;
+          r = c0[p] * vj[l];
+          if (cW[p] != 0.0) r = fma(cW[p], vj[l - 1], r);
+          if (cE[p] != 0.0) r = fma(cE[p], vj[l + 1], r);
+          if (cS[p] != 0.0) r = fma(cS[p], vj[l - b.Lx], r);
+          if (cN[p] != 0.0) r = fma(cN[p], vj[l + b.Lx], r);
+        }
+        w[p] = r;
+      }
+#pragma unroll
+      for (int i = 0; i < 32; ++i) {
+        if (i <= j) {
+          const double* vi = V + (int64_t)i * nloc;
+          double t = 0.0;
+#pragma unroll
+          for (int p = 0; p < P; ++p)
+            if (live[p]) t = fma(vi[tid + p * NT], w[p], t);
+          vv[i] = t;
+        }
+      }
+      wg_reduce32<NT>(vv, j + 1, red);
+      // sweep 2: first update, second dots and the squared norm
+      for (int i = 0; i <= j; ++i) {
+        const double hi = red_total<NT>(red, i);
+        if (tid == 0) H[i * m + j] = hi;
+        const double* vi = V + (int64_t)i * nloc;
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+          if (live[p]) w[p] = fma(-hi, vi[tid + p * NT], w[p]);
+      }
+      __syncthreads();  // everyone has read red before it is reused
+#pragma unroll
+      for (int i = 0; i < 32; ++i) vv[i] = 0.0;
+#pragma unroll
+      for (int i = 0; i < 32; ++i) {
+        if (i <= j) {
+          const double* vi = V + (int64_t)i * nloc;
+          double t = 0.0;
+#pragma unroll
+          for (int p = 0; p < P; ++p)
+            if (live[p]) t = fma(vi[tid + p * NT], w[p], t);
+          vv[i] = t;
+        }
+      }
+      {
+        double t = 0.0;
+#pragma unroll
+        for (int p = 0; p < P; ++p) t = fma(w[p], w[p], t);
+        // slot j+1 carries the norm (j + 1 <= m - 1 < 31)
+#pragma unroll
+        for (int i = 0; i < 32; ++i)
+          if (i == j + 1) vv[i] = t;
+      }
+      wg_reduce32<NT>(vv, j + 2, red);
+      // sweep 3: second update, norm, store
+      double e2 = 0.0;
+      for (int i = 0; i <= j; ++i) {
+        const double ei = red_total<NT>(red, i);
+        e2 = fma(ei, ei, e2);
+        if (tid == 0) H[i * m + j] += ei;
+        const double* vi = V + (int64_t)i * nloc;
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+          if (live[p]) w[p] = fma(-ei, vi[tid + p * NT], w[p]);
+      }
+      const double n1 = red_total<NT>(red, j + 1);
+      double hn2 = n1 - e2;
+      __syncthreads();
+      if (!(hn2 > 1e-4 * n1)) hn2 = norm2(w);  // severe cancellation: measure
+      const double hn = sqrt(fmax(hn2, 0.0));
+      double hs = 0.0;
+      for (int i = 0; i <= j; ++i) hs = fma(H[i * m + j], H[i * m + j], hs);
+      if (tid == 0) H[(j + 1) * m + j] = hn;
+      if (!(hn > 1e-14 * sqrt(hs + hn * hn))) {  // invariant subspace reached
+        k = j + 1;
+        __syncthreads();
+        break;
+      }
+      const double ih = 1.0 / hn;
+      double* vn = V + (int64_t)(j + 1) * nloc;
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+        if (live[p]) vn[tid + p * NT] = w[p] * ih;
+      __syncthreads();
+    }
+
+    if (a.mode == 1) {
+      double* out = a.calib + ((int64_t)b.diag * b.ns + s) * (2 + (m + 1) * m);
+      for (int idx = tid; idx < (m + 1) * m; idx += NT) out[2 + idx] = H[idx];
+      if (tid == 0) { out[0] = beta; out[1] = (double)k; }
+      return;
+    }
+
+    // exp(H_k) e_1 on MFMA
+    const int kp = k <= 16 ? 16 : 32;
+    for (int idx = tid; idx < kp * kp; idx += NT) {
+      const int i = idx / kp, jj = idx - i * kp;
+      EA[idx] = (i < k && jj < k) ? H[i * m + jj] : 0.0;
+    }
+    __syncthreads();
+    expm_mfma<NT>(EA, k, kp, EW, ER, piv);
+    const double hk = H[k * m + (k - 1)];
+    worst += beta * hk * fabs(ER[(k - 1) * kp]) / beta0;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      if (!live[p]) continue;
+      double acc = 0.0;
+      for (int i = 0; i < k; ++i)
+        acc = fma(ER[i * kp], V[(int64_t)i * nloc + tid + p * NT], acc);
+      cur[p] = beta * acc;
+    }
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    if (!live[p]) continue;
+    const int rx = lxs[p] - b.h;
+    const int ry = (b.ndim == 1) ? lys[p] : lys[p] - b.h;
+    if (rx < 0 || rx >= b.cx || ry < 0 || ry >= b.cy) continue;
+    const int64_t g = (b.ndim == 1) ? (int64_t)(b.ox + rx)
+                                    : (int64_t)(b.oy + ry) * b.n + (b.ox + rx);
+    if (!isfinite(cur[p])) bad = true;
+    x_out[b.x_off + g * b.ns + s] = cur[p];
+  }
+  if (bad) atomicOr(a.status, kStatusNonFinite);
+  if (tid == 0) {
+    a.diag[(int64_t)b.diag * b.ns + s] = worst;
+    if (!(worst <= b.tol)) atomicOr(a.status, kStatusNotConverged);
+  }
+}
+
+// ------------------------------------------------------------------ launch --
+
+size_t krylov_lds_bytes(int nt, int m, int nloc) {
+  int64_t a, b2, c;
+  return (size_t)lds_layout(nt, m, nloc, &a, &b2, &c) * 8;
+}
+
+int krylov_lds_max_m() { return kLdsMaxM; }
+
+// Launch shape of the LDS-resident kernel for a box of nloc points: threads
+// and points per thread; 0 when the box is too large for it.
+void krylov_lds_config(int ndim, int nloc, int* nt, int* pmax) {
+  if (ndim == 1 && nloc <= 128) { *nt = 64; *pmax = 2; return; }
+  if (ndim == 1 && nloc <= 512) { *nt = 64; *pmax = 8; return; }
+  if (nloc <= 1024) { *nt = 256; *pmax = 4; return; }
+  if (nloc <= 2048) { *nt = 256; *pmax = 8; return; }
+  if (nloc <= 4096) { *nt = 256; *pmax = 16; return; }
+  *nt = 0; *pmax = 0;
+}
+
+template <int NT, int P>
+static hipError_t launch_l(const KrylovArgs& a, int ns, size_t lds, hipStream_t st) {
+  auto fn = krylov_lds_kernel<NT, P>;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)fn,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(fn, dim3(a.n_blocks, ns), dim3(NT), lds, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_krylov_lds(const KBlock* blocks, int n_blocks, int ns, int nt, int pmax,
+                             size_t lds, const double* x_in, double* x_out, const double* coef,
+                             double* diag, int* status, double* calib, int mode,
+                             hipStream_t st) {
+  KrylovArgs a{blocks, x_in, x_out, coef, nullptr, diag, status, calib, mode, n_blocks};
+  if (n_blocks == 0) return hipSuccess;
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  if (nt == 64 && pmax == 2) return launch_l<64, 2>(a, ns, lds, st);
+  if (nt == 64 && pmax == 8) return launch_l<64, 8>(a, ns, lds, st);
+  if (nt == 256 && pmax == 4) return launch_l<256, 4>(a, ns, lds, st);
+  if (nt == 256 && pmax == 8) return launch_l<256, 8>(a, ns, lds, st);
+  if (nt == 256 && pmax == 16) return launch_l<256, 16>(a, ns, lds, st);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace lem

@@ -20,18 +20,6 @@
 
 namespace lem {
 
-struct KrylovArgs {
-  const KBlock* blocks;
-  const double* x_in;
-  double* x_out;
-  const double* coef;   // face-mu arrays of variable-coefficient problems
-  double* vwork;        // global-basis work space
-  double* diag;         // per (block, state) relative estimate of the step
-  int* status;          // latched status bits
-  double* calib;        // calibration output (mode 1)
-  int mode;             // 0: step; 1: calibrate (Arnoldi only, write H)
-  int n_blocks;
-};
 
 // LDS layout (doubles), shared with the host sizing routine.
 __host__ __device__ inline int64_t krylov_lds_doubles(int NT, int m, int nloc,

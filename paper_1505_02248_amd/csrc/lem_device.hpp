@@ -46,6 +46,19 @@ struct KBlock {
   double* vwork;
 };
 
+struct KrylovArgs {
+  const KBlock* blocks;
+  const double* x_in;
+  double* x_out;
+  const double* coef;   // face-mu arrays of variable-coefficient problems
+  double* vwork;        // global-basis work space
+  double* diag;         // per (block, state) relative estimate of the step
+  int* status;          // latched status bits
+  double* calib;        // calibration output (mode 1)
+  int mode;             // 0: step; 1: calibrate (Arnoldi only, write H)
+  int n_blocks;
+};
+
 __device__ __forceinline__ int wrap(int a, int n) {
   a %= n;
   return a < 0 ? a + n : a;

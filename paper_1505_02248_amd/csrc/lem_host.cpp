@@ -269,7 +269,7 @@ struct lem_plan_s {
   bool dry = false;
   // Krylov
   std::vector<int> m, nsub;
-  struct Bucket { int nt, pmax; bool vlds; size_t lds; int first, count; };
+  struct Bucket { int variant, nt, pmax; bool vlds; size_t lds; int first, count; };
   std::vector<Bucket> buckets;
   lem::KBlock* d_kb = nullptr;
   double* d_coef = nullptr;
@@ -346,6 +346,8 @@ lem_status upload(void* dst, const void* src, size_t bytes, hipStream_t st) {
 }
 
 // ------------------------------------------------------------- partition --
+double block_cost(int ndim, int nloc, int m, int nsub);
+
 lem_status make_partition(lem_plan_s* p) {
   const Op& op = p->op;
   const lem_options& o = p->opt;
@@ -404,10 +406,7 @@ lem_status make_partition(lem_plan_s* p) {
           double cost = 0;
           for (auto& b : bs) {
             const int L = c + 2 * b.h;
-            int nt, pm;
-            lem::krylov_config(2, L * L, &nt, &pm);
-            const bool fits = lem::krylov_lds_bytes(nt, mguess, L * L, true) <= 160 * 1024;
-            cost += (double)L * L * (fits ? 1.0 : 2.5);
+            cost += block_cost(2, L * L, std::min(mguess, 16), 1);
           }
           if (cost < best) { best = cost; bestb = bs; best_cl = cl; }
         }
@@ -444,33 +443,67 @@ lem::KBlock make_kblock(const lem_plan_s* p, const Box& b, int m, int nsub, int 
   return k;
 }
 
+// Launch shape of one block: the LDS-resident kernel (variant 1) when its
+// whole basis fits in LDS, else the general kernel (variant 0) with the basis
+// in LDS or streamed through device memory.
+struct LaunchKey {
+  int variant, nt, pmax;
+  bool vlds;
+  bool operator<(const LaunchKey& o) const {
+    return std::tie(variant, nt, pmax, vlds) < std::tie(o.variant, o.nt, o.pmax, o.vlds);
+  }
+};
+
+LaunchKey launch_key(int ndim, int nloc, int m, size_t* lds) {
+  int nt, pm;
+  lem::krylov_lds_config(ndim, nloc, &nt, &pm);
+  if (nt && m <= lem::krylov_lds_max_m()) {
+    const size_t need = lem::krylov_lds_bytes(nt, m, nloc);
+    if (need <= 160 * 1024) {
+      *lds = need;
+      return {1, nt, pm, true};
+    }
+  }
+  lem::krylov_config(ndim, nloc, &nt, &pm);
+  if (nt == 0) return {-1, 0, 0, false};
+  const size_t with_v = lem::krylov_lds_bytes(nt, m, nloc, true);
+  const bool vlds = with_v <= 160 * 1024 && pm != 20;
+  *lds = vlds ? with_v : lem::krylov_lds_bytes(nt, m, nloc, false);
+  return {0, nt, pm, vlds};
+}
+
+// Relative cost of one block step with Krylov dimension m and nsub sub-steps:
+// basis work grows like m (orthogonalization) per point and iteration, and a
+// streamed basis costs about four times an LDS-resident one.
+double block_cost(int ndim, int nloc, int m, int nsub) {
+  size_t lds;
+  const LaunchKey k = launch_key(ndim, nloc, m, &lds);
+  if (k.variant < 0) return INFINITY;
+  const double f = k.variant == 1 ? 1.0 : (k.vlds ? 1.5 : 4.0);
+  return f * nsub * (double)nloc * (m * (m + 3.0) + 40.0);
+}
+
 // Groups blocks by launch shape; assigns global-basis offsets. Reorders kb.
 lem_status bucketize(std::vector<lem::KBlock>& kb, std::vector<lem_plan_s::Bucket>& buckets,
                      int ns, int64_t* vwork_doubles) {
-  struct Key { int nt, pmax; bool vlds; bool operator<(const Key& o) const {
-    return std::tie(nt, pmax, vlds) < std::tie(o.nt, o.pmax, o.vlds); } };
-  std::map<Key, std::vector<int>> groups;
+  std::map<LaunchKey, std::vector<int>> groups;
   std::vector<size_t> need(kb.size());
   for (size_t i = 0; i < kb.size(); ++i) {
     const int nloc = kb[i].Lx * kb[i].Ly;
-    int nt, pm;
-    lem::krylov_config(kb[i].ndim, nloc, &nt, &pm);
-    if (nt == 0) return fail(LEM_ERR_UNSUPPORTED, "local box larger than 10240 points");
-    const size_t with_v = lem::krylov_lds_bytes(nt, kb[i].m, nloc, true);
-    const bool vlds = with_v <= 160 * 1024 && pm != 20;
-    need[i] = vlds ? with_v : lem::krylov_lds_bytes(nt, kb[i].m, nloc, false);
-    groups[{nt, pm, vlds}].push_back((int)i);
+    const LaunchKey key = launch_key(kb[i].ndim, nloc, kb[i].m, &need[i]);
+    if (key.variant < 0) return fail(LEM_ERR_UNSUPPORTED, "local box larger than 10240 points");
+    groups[key].push_back((int)i);
   }
   std::vector<lem::KBlock> out;
   buckets.clear();
   int64_t voff = 0;
   for (auto& g : groups) {
-    lem_plan_s::Bucket bk{g.first.nt, g.first.pmax, g.first.vlds, 0, (int)out.size(),
-                          (int)g.second.size()};
+    lem_plan_s::Bucket bk{g.first.variant, g.first.nt, g.first.pmax, g.first.vlds, 0,
+                          (int)out.size(), (int)g.second.size()};
     for (int i : g.second) {
       lem::KBlock k = kb[i];
       bk.lds = std::max(bk.lds, need[i]);
-      if (!g.first.vlds) {
+      if (g.first.variant == 0 && !g.first.vlds) {
         k.v_off = voff;
         voff += (int64_t)(k.m + 1) * k.Lx * k.Ly * ns;
       }
@@ -488,18 +521,22 @@ lem_status launch_buckets(const lem_plan_s* p, const lem::KBlock* d_kb,
                           double* dst, double* vwork, double* diag, double* calib, int mode,
                           hipStream_t st) {
   for (const auto& b : bks) {
-    hipError_t e = lem::launch_krylov(d_kb + b.first, b.count, ns, b.nt, b.pmax, b.vlds, b.lds,
-                                      src, dst, p->d_coef, vwork, diag, p->d_status, calib,
-                                      mode, st);
+    hipError_t e =
+        b.variant == 1
+            ? lem::launch_krylov_lds(d_kb + b.first, b.count, ns, b.nt, b.pmax, b.lds, src, dst,
+                                     p->d_coef, diag, p->d_status, calib, mode, st)
+            : lem::launch_krylov(d_kb + b.first, b.count, ns, b.nt, b.pmax, b.vlds, b.lds, src,
+                                 dst, p->d_coef, vwork, diag, p->d_status, calib, mode, st);
     if (e != hipSuccess)
       return fail(LEM_ERR_HIP, std::string("Krylov launch: ") + hipGetErrorString(e));
   }
   return LEM_OK;
 }
 
-// Choose (m, nsub) from calibration estimates est[sub][j] of one block.
+// Choose (m, nsub) from calibration estimates est[sub][j] of one block: the
+// cheapest pair (block_cost) whose estimate meets half the tolerance.
 bool choose_m(const double* est, const std::vector<int>& jl, int nsc, double tol, int mfix,
-              int mcal, int* m, int* nsub) {
+              int mcal, int ndim, int nloc, int* m, int* nsub) {
   double best = INFINITY;
   for (int e = 0; e < nsc; ++e)
     for (size_t q = 0; q < jl.size(); ++q) {
@@ -507,7 +544,8 @@ bool choose_m(const double* est, const std::vector<int>& jl, int nsc, double tol
       if (mfix > 0 && j != mfix) continue;
       if (!(est[e * jl.size() + q] <= 0.5 * tol)) continue;
       const int mm = (mfix > 0) ? j : std::min(j + 2, mcal);
-      const double cost = (double)(1 << e) * (mm + 8);
+      const double cost = nloc > 0 ? block_cost(ndim, nloc, mm, 1 << e)
+                                   : (double)(1 << e) * (mm + 8);
       if (cost < best) { best = cost; *m = mm; *nsub = 1 << e; }
     }
   return best < INFINITY;
@@ -597,8 +635,10 @@ lem_status plan_krylov(lem_plan_s* p, hipStream_t st) {
   std::vector<int> rm(nr), rs(nr);
   for (int r = 0; r < nr; ++r) {
     int mm = 0, ss = 0;
+    const Box& rb = p->boxes[reps[r]];
+    const int rnloc = (rb.cx + 2 * rb.h) * (op.ndim == 2 ? rb.cy + 2 * rb.h : 1);
     if (!choose_m(&est[(size_t)r * nsc * jl.size()], jl, nsc, o.krylov_tol, o.krylov_m, mcal,
-                  &mm, &ss))
+                  op.ndim, rnloc, &mm, &ss))
       return fail(LEM_ERR_NOT_CONVERGED,
                   "no Krylov dimension <= " + std::to_string(mcal) + " with <= " +
                       std::to_string(o.max_substeps) + " sub-steps meets krylov_tol");
@@ -829,7 +869,8 @@ lem_status plan_global(lem_plan_s* p, hipStream_t st) {
   LEM_HIP(hipMemcpyAsync(est.data(), d_est, est.size() * 8, hipMemcpyDeviceToHost, st));
   LEM_HIP(hipStreamSynchronize(st));
   int mm = 0, ss = 0;
-  const bool ok = choose_m(est.data(), jl, nsc, o.krylov_tol, o.krylov_m, mcal, &mm, &ss);
+  const bool ok =
+      choose_m(est.data(), jl, nsc, o.krylov_tol, o.krylov_m, mcal, op.ndim, 0, &mm, &ss);
   free_global(p, &cw);
   for (void* q : {(void*)d_probe, (void*)d_calib, (void*)d_est, (void*)d_mcal, (void*)d_jl,
                   (void*)d_coff})
@@ -1456,10 +1497,8 @@ lem_status lem_server_tick(lem_server_t s, int32_t* n_active, int32_t* n_queued)
     size_t nb = 0;
     for (uint64_t id : s->active) nb += s->reqs[id].plan->kb_host.size();
     LEM_TRY(server_grow(s, nb));
-    struct Key { int nt, pmax; bool vlds; bool operator<(const Key& o) const {
-      return std::tie(nt, pmax, vlds) < std::tie(o.nt, o.pmax, o.vlds); } };
-    std::map<Key, std::vector<lem::KBlock>> groups;
-    std::map<Key, size_t> lds;
+    std::map<LaunchKey, std::vector<lem::KBlock>> groups;
+    std::map<LaunchKey, size_t> lds;
     int diag = 0;
     for (uint64_t id : s->active) {
       ServerReq& r = s->reqs[id];
@@ -1478,7 +1517,7 @@ lem_status lem_server_tick(lem_server_t s, int32_t* n_active, int32_t* n_queued)
           k.coef = p->d_coef;
           k.vwork = p->d_vwork + k.v_off;
           k.diag = diag++;
-          Key key{bk.nt, bk.pmax, bk.vlds};
+          LaunchKey key{bk.variant, bk.nt, bk.pmax, bk.vlds};
           groups[key].push_back(k);
           lds[key] = std::max(lds[key], bk.lds);
         }
@@ -1492,10 +1531,15 @@ lem_status lem_server_tick(lem_server_t s, int32_t* n_active, int32_t* n_queued)
                                     hipMemcpyHostToDevice, s->st));
     off = 0;
     for (auto& g : groups) {
-      hipError_t e = lem::launch_krylov(s->d_table + off, (int)g.second.size(), 1, g.first.nt,
-                                        g.first.pmax, g.first.vlds, lds[g.first], nullptr,
-                                        nullptr, nullptr, nullptr, s->d_diag, s->d_status,
-                                        nullptr, 0, s->st);
+      const int nb = (int)g.second.size();
+      hipError_t e =
+          g.first.variant == 1
+              ? lem::launch_krylov_lds(s->d_table + off, nb, 1, g.first.nt, g.first.pmax,
+                                       lds[g.first], nullptr, nullptr, nullptr, s->d_diag,
+                                       s->d_status, nullptr, 0, s->st)
+              : lem::launch_krylov(s->d_table + off, nb, 1, g.first.nt, g.first.pmax,
+                                   g.first.vlds, lds[g.first], nullptr, nullptr, nullptr,
+                                   nullptr, s->d_diag, s->d_status, nullptr, 0, s->st);
       if (e != hipSuccess)
         return fail(LEM_ERR_HIP, std::string("serving launch: ") + hipGetErrorString(e));
       off += g.second.size();
