@@ -53,8 +53,12 @@ __device__ __forceinline__ double wave_reduce_scatter(double (&v)[K]) {
 #pragma unroll
     for (int i = 0; i < K / 2; ++i) {
       if (i < half) {
-        const double send = upper ? v[i] : v[i + half];
-        const double keep = upper ? v[i + half] : v[i];
+        double lo = v[i], hi = v[i + half];
+        // keep the selects on register values: folded into an indexed load of
+        // v they would demote the whole array to scratch memory
+        asm volatile("" : "+v"(lo), "+v"(hi));
+        const double send = upper ? lo : hi;
+        const double keep = upper ? hi : lo;
         v[i] = keep + __shfl_xor(send, o, 64);
       }
     }
