@@ -262,6 +262,7 @@ __device__ __forceinline__ void expm_mfma(double* A, int m, int mp, double* W, d
 
 template <int NT, int P>
 __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
+  constexpr int CH = P >= 8 ? 2 : (P >= 4 ? 4 : 8);  // rows per sweep chunk
   extern __shared__ double smem[];
   const int tid = threadIdx.x;
   const int s = blockIdx.y;
@@ -342,6 +343,61 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
     return r;
   };
 
+  // Sweeps over the basis rows 0..j in chunks of CH rows: all loads of a
+  // chunk are in flight before the first use.  Rows past j are clamped to j
+  // (valid data) and enter with a zero coefficient or are discarded.
+  auto dots_chunked = [&](const double* Vb, int nl, int jj, const double (&x)[P],
+                          double (&out)[32]) {
+#pragma unroll
+    for (int c = 0; c < 32 / CH; ++c) {
+      if (c * CH <= jj) {
+        double vals[CH][P];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+          const int i = min(c * CH + q, jj);
+#pragma unroll
+          for (int p = 0; p < P; ++p) vals[q][p] = Vb[(int64_t)i * nl + tid + p * NT];
+        }
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+          double t = 0.0;
+#pragma unroll
+          for (int p = 0; p < P; ++p) t = fma(vals[q][p], x[p], t);
+          out[c * CH + q] = (c * CH + q <= jj) ? t : 0.0;
+        }
+      }
+    }
+  };
+  // w -= sum_{i<=jj} total_i v_i with total_i from the reduction exchange;
+  // records the totals into column jj of H (assign, or add when `second`) and
+  // returns sum total_i^2.
+  auto update_chunked = [&](const double* Vb, int nl, int jj, const double* rd, double* Hm,
+                            int mm, double (&x)[P], bool second) {
+    double ss = 0.0;
+    for (int i0 = 0; i0 <= jj; i0 += CH) {
+      double vals[CH][P], hc[CH];
+#pragma unroll
+      for (int q = 0; q < CH; ++q) {
+        const int i = min(i0 + q, jj);
+        const double t = red_total<NT>(rd, i);
+        hc[q] = (i0 + q <= jj) ? t : 0.0;
+#pragma unroll
+        for (int p = 0; p < P; ++p) vals[q][p] = Vb[(int64_t)i * nl + tid + p * NT];
+      }
+#pragma unroll
+      for (int q = 0; q < CH; ++q) {
+        ss = fma(hc[q], hc[q], ss);
+        if (tid == 0 && i0 + q <= jj) {
+          if (second) Hm[(i0 + q) * mm + jj] += hc[q];
+          else Hm[(i0 + q) * mm + jj] = hc[q];
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p) x[p] = fma(-hc[q], vals[q][p], x[p]);
+      }
+    }
+    return ss;
+  };
+
   const double beta0 = sqrt(norm2(cur));
   double worst = 0.0;
   bool bad = !isfinite(beta0);
@@ -380,41 +436,14 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
         }
         w[p] = r;
       }
-#pragma unroll
-      for (int i = 0; i < 32; ++i) {
-        if (i <= j) {
-          const double* vi = V + (int64_t)i * nloc;
-          double t = 0.0;
-#pragma unroll
-          for (int p = 0; p < P; ++p)
-            if (live[p]) t = fma(vi[tid + p * NT], w[p], t);
-          vv[i] = t;
-        }
-      }
+      dots_chunked(V, nloc, j, w, vv);
       wg_reduce32<NT>(vv, j + 1, red);
       // sweep 2: first update, second dots and the squared norm
-      for (int i = 0; i <= j; ++i) {
-        const double hi = red_total<NT>(red, i);
-        if (tid == 0) H[i * m + j] = hi;
-        const double* vi = V + (int64_t)i * nloc;
-#pragma unroll
-        for (int p = 0; p < P; ++p)
-          if (live[p]) w[p] = fma(-hi, vi[tid + p * NT], w[p]);
-      }
+      update_chunked(V, nloc, j, red, H, m, w, false);
       __syncthreads();  // everyone has read red before it is reused
 #pragma unroll
       for (int i = 0; i < 32; ++i) vv[i] = 0.0;
-#pragma unroll
-      for (int i = 0; i < 32; ++i) {
-        if (i <= j) {
-          const double* vi = V + (int64_t)i * nloc;
-          double t = 0.0;
-#pragma unroll
-          for (int p = 0; p < P; ++p)
-            if (live[p]) t = fma(vi[tid + p * NT], w[p], t);
-          vv[i] = t;
-        }
-      }
+      dots_chunked(V, nloc, j, w, vv);
       {
         double t = 0.0;
 #pragma unroll
@@ -426,16 +455,7 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
       }
       wg_reduce32<NT>(vv, j + 2, red);
       // sweep 3: second update, norm, store
-      double e2 = 0.0;
-      for (int i = 0; i <= j; ++i) {
-        const double ei = red_total<NT>(red, i);
-        e2 = fma(ei, ei, e2);
-        if (tid == 0) H[i * m + j] += ei;
-        const double* vi = V + (int64_t)i * nloc;
-#pragma unroll
-        for (int p = 0; p < P; ++p)
-          if (live[p]) w[p] = fma(-ei, vi[tid + p * NT], w[p]);
-      }
+      const double e2 = update_chunked(V, nloc, j, red, H, m, w, true);
       const double n1 = red_total<NT>(red, j + 1);
       double hn2 = n1 - e2;
       __syncthreads();
@@ -474,13 +494,26 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
     expm_mfma<NT>(EA, k, kp, EW, ER, piv);
     const double hk = H[k * m + (k - 1)];
     worst += beta * hk * fabs(ER[(k - 1) * kp]) / beta0;
+    {
+      double acc[P];
 #pragma unroll
-    for (int p = 0; p < P; ++p) {
-      if (!live[p]) continue;
-      double acc = 0.0;
-      for (int i = 0; i < k; ++i)
-        acc = fma(ER[i * kp], V[(int64_t)i * nloc + tid + p * NT], acc);
-      cur[p] = beta * acc;
+      for (int p = 0; p < P; ++p) acc[p] = 0.0;
+      for (int i0 = 0; i0 < k; i0 += CH) {
+        double vals[CH][P], f[CH];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+          const int i = min(i0 + q, k - 1);
+          f[q] = (i0 + q < k) ? ER[i * kp] : 0.0;
+#pragma unroll
+          for (int p = 0; p < P; ++p) vals[q][p] = V[(int64_t)i * nloc + tid + p * NT];
+        }
+#pragma unroll
+        for (int q = 0; q < CH; ++q)
+#pragma unroll
+          for (int p = 0; p < P; ++p) acc[p] = fma(f[q], vals[q][p], acc[p]);
+      }
+#pragma unroll
+      for (int p = 0; p < P; ++p) cur[p] = live[p] ? beta * acc[p] : 0.0;
     }
     __syncthreads();
   }
@@ -519,8 +552,7 @@ void krylov_lds_config(int ndim, int nloc, int* nt, int* pmax) {
   if (ndim == 1 && nloc <= 512) { *nt = 64; *pmax = 8; return; }
   if (nloc <= 1024) { *nt = 256; *pmax = 4; return; }
   if (nloc <= 2048) { *nt = 256; *pmax = 8; return; }
-  if (nloc <= 4096) { *nt = 256; *pmax = 16; return; }
-  *nt = 0; *pmax = 0;
+  *nt = 0; *pmax = 0;  // larger boxes cannot keep a useful basis in LDS
 }
 
 template <int NT, int P>
@@ -546,7 +578,6 @@ hipError_t launch_krylov_lds(const KBlock* blocks, int n_blocks, int ns, int nt,
   if (nt == 64 && pmax == 8) return launch_l<64, 8>(a, ns, lds, st);
   if (nt == 256 && pmax == 4) return launch_l<256, 4>(a, ns, lds, st);
   if (nt == 256 && pmax == 8) return launch_l<256, 8>(a, ns, lds, st);
-  if (nt == 256 && pmax == 16) return launch_l<256, 16>(a, ns, lds, st);
   return hipErrorInvalidValue;
 }
 
