@@ -101,7 +101,8 @@ typedef struct {
   int32_t halo_max;
   double halo_tol;       /* per-step relative bound the halo must meet      */
   int32_t krylov_m;      /* Krylov dimension; 0 = calibrate per block       */
-  int32_t krylov_m_max;  /* largest dimension allowed (<= 48)               */
+  int32_t krylov_m_max;  /* largest dimension allowed: <= 30 for local
+                            actions, <= 48 for LEM_METHOD_GLOBAL            */
   int32_t max_substeps;  /* largest number of equal sub-steps per step      */
   double krylov_tol;     /* relative tolerance of the Krylov estimate       */
   int32_t use_graph;     /* capture lem_step's launches in a HIP graph      */
@@ -131,7 +132,7 @@ typedef struct {
 typedef struct lem_plan_s* lem_plan_t;
 
 /* Fill *opt with defaults: Krylov, FP64, one state, core 64 (1D) / 32 (2D),
- * decay-bound halo in [4, 64] at tol 1e-8, calibrated m <= 40 at tol 1e-13,
+ * decay-bound halo in [4, 64] at tol 1e-8, calibrated m <= 30 at tol 1e-13,
  * up to 64 sub-steps, no graph, no autotune. */
 void lem_options_default(lem_options* opt);
 
@@ -219,7 +220,7 @@ typedef struct {
   double max_overhead;   /* largest (local points / core points) before a
                             request falls back to the global method, >= 1    */
   double krylov_tol;     /* relative Krylov tolerance per step                 */
-  int32_t krylov_m_max;  /* <= 48                                              */
+  int32_t krylov_m_max;  /* <= 30                                              */
   int32_t max_substeps;
   int32_t dry_run;       /* host-only scheduling: no device memory or kernels;
                             a finished request returns its initial state     */
@@ -245,7 +246,7 @@ typedef struct {
 } lem_server_info;
 
 /* Defaults: 8 GiB pool, 256 active, halo tol 1e-8 in [4, 32], overhead 4,
- * Krylov tol 1e-12, m <= 40, <= 64 sub-steps. */
+ * Krylov tol 1e-12, m <= 30, <= 64 sub-steps. */
 void lem_server_options_default(lem_server_options* opt);
 
 /* Reserve the pool and create a server working on `stream`.  Errors:

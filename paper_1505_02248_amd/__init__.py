@@ -167,7 +167,7 @@ class Plan:
     def __init__(self, op: Operator, dt: float, method: str = "krylov",
                  precision: str = "fp64", n_states: int = 1, core: int = 0,
                  halo: int = 0, halo_min: int = 4, halo_max: int = 64,
-                 halo_tol: float = 1e-8, krylov_m: int = 0, krylov_m_max: int = 40,
+                 halo_tol: float = 1e-8, krylov_m: int = 0, krylov_m_max: int = 30,
                  max_substeps: int = 64, krylov_tol: float = 1e-13,
                  use_graph: bool = False, autotune: bool = False, dry_run: bool = False,
                  stream=None):
@@ -311,7 +311,7 @@ class Server:
     def __init__(self, hbm_budget: int = 8 << 30, max_active: int = 256,
                  halo_tol: float = 1e-8, halo_min: int = 4, halo_max: int = 32,
                  max_overhead: float = 4.0, krylov_tol: float = 1e-12,
-                 krylov_m_max: int = 40, max_substeps: int = 64, dry_run: bool = False,
+                 krylov_m_max: int = 30, max_substeps: int = 64, dry_run: bool = False,
                  stream=None):
         lib = _server_lib()
         o = _ServerOptions()

@@ -1,237 +1,568 @@
 // Batched Arnoldi-Krylov LEM step (gfx950).
 //
-// One workgroup advances one region M_i (one ensemble member) of the
-// overlapping decomposition of section 3 by one time step:
-//   1. gather the local state v = u^n restricted to the box (core + buffer);
-//   2. for each of nsub equal sub-steps, build the Krylov basis V_m of
-//      K_m(dt_sub A_M, v) by Arnoldi (classical Gram-Schmidt with one full
-//      re-orthogonalization pass), the stencil product of the local problem (4)
-//      applied on the box with couplings to outside nodes dropped; then
-//      v <- beta V_m exp(H_m) e_1 (the Krylov action of section 4.3), with
-//      exp(H_m) by Pade scaling and squaring in LDS;
-//   3. write the core rows of v into u^{n+1} (step 3 of section 3).
-// Saad's estimate beta * h_{m+1,m} * |e_m^T exp(H_m) e_1| is computed for
-// every sub-step and latched into the status word when above tolerance.
-//
-// The basis lives in LDS when (m+1) * |M_i| doubles fit next to the Hessenberg
-// work space, and otherwise in a per-block slice of device memory that the
-// workgroup streams (L2/HBM).
+// One workgroup advances one region M_i of the overlapping decomposition of
+// section 3 (one ensemble member) by one step: gather the local state, then
+// for each of nsub equal sub-steps build the Krylov basis of dt_sub * A_M
+// (the local problem (4): the stencil on the box with the couplings to
+// outside nodes dropped) by Arnoldi and set v <- beta V_m exp(H_m) e_1 (the
+// Krylov action of section 4.3); finally write the core rows into the new
+// state (step 3).  Saad's estimate beta h_{m+1,m} |e_m^T exp(H_m) e_1| is
+// accumulated over the sub-steps and latched into the status word when above
+// tolerance.  The basis stays in LDS whenever it fits (the planner chooses
+// the Krylov dimension and sub-step count for that), otherwise it lives in a
+// per-block slice of device memory read through the L2.  Each Arnoldi column
+// takes three sweeps and two reductions:
+//   * sweep 1: stencil product on the LDS-resident v_j fused with the first
+//     Gram-Schmidt dots; one reduction;
+//   * sweep 2: first update fused with the re-orthogonalization dots and the
+//     squared norm of the updated vector; one reduction; the norm of the
+//     twice-orthogonalized vector follows from Pythagoras (the second
+//     correction is tiny), with an explicit reduction when cancellation is
+//     severe (near an invariant subspace);
+//   * sweep 3: second update, normalization, store of v_{j+1}.
+// Reductions of up to 32 values use a wave64 butterfly reduce-scatter
+// (about one cross-lane exchange per value instead of six), then one LDS
+// exchange between waves.  exp(H_m) is evaluated by Pade [13/13] scaling and
+// squaring with its matrix products on FP64 MFMA (v_mfma_f64_16x16x4) over
+// 16- or 32-padded tiles in LDS, and a pivoted elimination in LDS.
+#include <type_traits>
+
 #include "lem_device.hpp"
+#include "lem_launch.h"
 
 namespace lem {
 
+typedef double d4v __attribute__((ext_vector_type(4)));
 
-// LDS layout (doubles), shared with the host sizing routine.
-__host__ __device__ inline int64_t krylov_lds_doubles(int NT, int m, int nloc,
-                                                      bool vlds) {
-  int64_t d = 0;
-  d += (int64_t)(m + 1) * m;      // H
-  d += 2 * (m + 1);               // dot results (two passes)
-  d += (NT / 64) * 8 + 8;         // reduction scratch
-  d += NT / 64 + 8;               // pivot / misc
-  d += 7 * (int64_t)m * m;        // expm: A, W(5), R
-  if (vlds) d += (int64_t)(m + 1) * nloc;
+constexpr int kLdsMaxM = 30;  // Krylov dimension limit of this kernel
+
+// LDS layout in doubles; mirrored by krylov_lds_bytes() on the host.
+__host__ __device__ inline int64_t lds_layout(int NT, int m, int nloc, int64_t* off_h,
+                                              int64_t* off_red, int64_t* off_e) {
+  const int mp = m <= 16 ? 16 : 32;
+  int64_t d = (int64_t)(m + 1) * nloc;  // basis
+  *off_h = d;
+  d += (int64_t)(m + 1) * m;            // Hessenberg
+  *off_red = d;
+  d += (int64_t)(NT / 64) * 32 + 64;    // reduction exchange + scalars
+  *off_e = d;
+  d += 7 * (int64_t)mp * mp + 8;        // expm work (A, A2, A4, A6, U, V, R) + pivot
   return d;
 }
 
-template <int NT, int PMAX, bool VLDS>
-__global__ __launch_bounds__(NT) void krylov_lem_kernel(KrylovArgs a) {
+// Butterfly reduce-scatter over the wave: K values per lane in, the wave
+// total of value (lane >> log2(64/K)) out.
+template <int K>
+__device__ __forceinline__ double wave_reduce_scatter(double (&v)[K]) {
+  const int lane = threadIdx.x & 63;
+  int c = K;
+#pragma unroll
+  for (int o = 32; o >= 64 / K; o >>= 1) {
+    const int half = c >> 1;
+    const bool upper = (lane & o) != 0;
+#pragma unroll
+    for (int i = 0; i < K / 2; ++i) {
+      if (i < half) {
+        double lo = v[i], hi = v[i + half];
+        // keep the selects on register values: folded into an indexed load of
+        // v they would demote the whole array to scratch memory
+        asm volatile("" : "+v"(lo), "+v"(hi));
+        const double send = upper ? lo : hi;
+        const double keep = upper ? hi : lo;
+        v[i] = keep + __shfl_xor(send, o, 64);
+      }
+    }
+    c = half;
+  }
+  double r = v[0];
+#pragma unroll
+  for (int o = 32 / K; o >= 1; o >>= 1) r += __shfl_xor(r, o, 64);
+  return r;
+}
+
+// Workgroup sum of cnt <= 32 values (held per thread in v[0..cnt)); after the
+// call every thread can read total(i) = sum_w red[w*32 + i].
+template <int NT>
+__device__ __forceinline__ void wg_reduce32(double (&v)[32], int cnt, double* red) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (cnt <= 8) {
+    double t[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) t[i] = v[i];
+    const double r = wave_reduce_scatter<8>(t);
+    if ((lane & 7) == 0) red[wv * 32 + (lane >> 3)] = r;
+  } else if (cnt <= 16) {
+    double t[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) t[i] = v[i];
+    const double r = wave_reduce_scatter<16>(t);
+    if ((lane & 3) == 0) red[wv * 32 + (lane >> 2)] = r;
+  } else {
+    const double r = wave_reduce_scatter<32>(v);
+    if ((lane & 1) == 0) red[wv * 32 + (lane >> 1)] = r;
+  }
+  __syncthreads();
+}
+
+template <int NT>
+__device__ __forceinline__ double red_total(const double* red, int i) {
+  double s = red[i];
+#pragma unroll
+  for (int w = 1; w < NT / 64; ++w) s += red[w * 32 + i];
+  return s;
+}
+
+// C = A B for mp x mp matrices (mp = 16 or 32) in LDS, row-major, on FP64
+// MFMA.  Waves take 16x16 output tiles round-robin.
+template <int NT>
+__device__ __forceinline__ void mfma_matmul(const double* A, const double* B, double* C,
+                                            int mp) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int tiles = (mp / 16) * (mp / 16);
+  for (int t = wv; t < tiles; t += NT / 64) {
+    const int ti = t / (mp / 16), tj = t - ti * (mp / 16);
+    d4v acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < mp; k0 += 4) {
+      const double a = A[(ti * 16 + (lane & 15)) * mp + k0 + (lane >> 4)];
+      const double bb = B[(k0 + (lane >> 4)) * mp + tj * 16 + (lane & 15)];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      C[(ti * 16 + 4 * r + (lane >> 4)) * mp + tj * 16 + (lane & 15)] = acc[r];
+  }
+  __syncthreads();
+}
+
+// exp(A) for the leading m x m block of the mp x mp matrix A in LDS (padding
+// rows/columns zero).  Work W = 5 mp^2, result R (mp^2), piv >= NT/64 + 4.
+template <int NT>
+__device__ __forceinline__ void expm_mfma(double* A, int m, int mp, double* W, double* R,
+                                          double* piv) {
+  const int tid = threadIdx.x;
+  const int mm = mp * mp;
+  double* A2 = W;
+  double* A4 = W + mm;
+  double* A6 = W + 2 * mm;
+  double* U = W + 3 * mm;
+  double* V = W + 4 * mm;
+  double cs = 0.0;
+  for (int j = tid; j < m; j += NT) {
+    double t = 0.0;
+    for (int i = 0; i < m; ++i) t += fabs(A[i * mp + j]);
+    cs = fmax(cs, t);
+  }
+  cs = wave_max(cs);
+  if (NT > 64) {
+    if ((tid & 63) == 0) piv[tid >> 6] = cs;
+    __syncthreads();
+    cs = 0.0;
+    for (int w = 0; w < NT / 64; ++w) cs = fmax(cs, piv[w]);
+    __syncthreads();
+  }
+  int s = 0;
+  if (cs > kTheta13 && cs < 1e300) s = min(60, (int)ceil(log2(cs / kTheta13)));
+  if (s > 0) {
+    for (int idx = tid; idx < mm; idx += NT) A[idx] = ldexp(A[idx], -s);
+    __syncthreads();
+  }
+  const double* b = kPadeB;
+  mfma_matmul<NT>(A, A, A2, mp);
+  mfma_matmul<NT>(A2, A2, A4, mp);
+  mfma_matmul<NT>(A4, A2, A6, mp);
+  for (int idx = tid; idx < mm; idx += NT)
+    V[idx] = b[13] * A6[idx] + b[11] * A4[idx] + b[9] * A2[idx];
+  __syncthreads();
+  mfma_matmul<NT>(A6, V, U, mp);
+  for (int idx = tid; idx < mm; idx += NT) {
+    const int i = idx / mp, j = idx - i * mp;
+    U[idx] += b[7] * A6[idx] + b[5] * A4[idx] + b[3] * A2[idx] + (i == j ? b[1] : 0.0);
+  }
+  __syncthreads();
+  mfma_matmul<NT>(A, U, R, mp);  // R = U (odd part)
+  for (int idx = tid; idx < mm; idx += NT)
+    U[idx] = b[12] * A6[idx] + b[10] * A4[idx] + b[8] * A2[idx];
+  __syncthreads();
+  mfma_matmul<NT>(A6, U, V, mp);
+  for (int idx = tid; idx < mm; idx += NT) {
+    const int i = idx / mp, j = idx - i * mp;
+    const double v = V[idx] + b[6] * A6[idx] + b[4] * A4[idx] + b[2] * A2[idx] +
+                     (i == j ? b[0] : 0.0);
+    const double u = R[idx];
+    V[idx] = v + u;  // P
+    U[idx] = v - u;  // Q
+  }
+  __syncthreads();
+  // Q X = P on the leading m x m block (padding stays zero / identity-free:
+  // only the leading block is eliminated and used).
+  double* Q = U;
+  double* P = V;
+  double* fac = A;
+  for (int j = 0; j < m; ++j) {
+    if (tid < 64) {
+      double best = -1.0;
+      int bi = j;
+      for (int i = j + tid; i < m; i += 64) {
+        const double a = fabs(Q[i * mp + j]);
+        if (a > best) { best = a; bi = i; }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (tid == 0) piv[0] = (double)bi;
+    }
+    __syncthreads();
+    const int p = (int)piv[0];
+    if (p != j) {
+      for (int k = tid; k < 2 * m; k += NT) {
+        double* M = k < m ? Q : P;
+        const int kk = k < m ? k : k - m;
+        const double t = M[j * mp + kk];
+        M[j * mp + kk] = M[p * mp + kk];
+        M[p * mp + kk] = t;
+      }
+      __syncthreads();
+    }
+    const double inv = 1.0 / Q[j * mp + j];
+    for (int i = j + 1 + tid; i < m; i += NT) fac[i] = Q[i * mp + j] * inv;
+    __syncthreads();
+    const int rows = m - j - 1;
+    const int cols = (m - j - 1) + m;
+    for (int idx = tid; idx < rows * cols; idx += NT) {
+      const int r = j + 1 + idx / cols;
+      const int c = idx % cols;
+      if (c < m - j - 1) {
+        const int k = j + 1 + c;
+        Q[r * mp + k] = fma(-fac[r], Q[j * mp + k], Q[r * mp + k]);
+      } else {
+        const int k = c - (m - j - 1);
+        P[r * mp + k] = fma(-fac[r], P[j * mp + k], P[r * mp + k]);
+      }
+    }
+    __syncthreads();
+  }
+  for (int j = m - 1; j >= 0; --j) {
+    const double inv = 1.0 / Q[j * mp + j];
+    for (int k = tid; k < m; k += NT) P[j * mp + k] *= inv;
+    __syncthreads();
+    for (int idx = tid; idx < j * m; idx += NT) {
+      const int r = idx / m, k = idx - r * m;
+      P[r * mp + k] = fma(-Q[r * mp + j], P[j * mp + k], P[r * mp + k]);
+    }
+    __syncthreads();
+  }
+  // clear the padding of P so that products of the padded tiles are exact
+  for (int idx = tid; idx < mm; idx += NT) {
+    const int i = idx / mp, j = idx - i * mp;
+    if (i >= m || j >= m) P[idx] = 0.0;
+  }
+  __syncthreads();
+  double* src = P;
+  double* dst = A2;
+  for (int q = 0; q < s; ++q) {
+    mfma_matmul<NT>(src, src, dst, mp);
+    double* t = src; src = dst; dst = t;
+  }
+  for (int idx = tid; idx < mm; idx += NT) R[idx] = src[idx];
+  __syncthreads();
+}
+
+typedef __attribute__((address_space(1))) double gdouble;
+
+// One workgroup per (region, ensemble member).  VLDS: basis in LDS; else in
+// a per-block slice of device memory (read through the L2).  Points per
+// thread P; up to 8 points keep their stencil weights in registers.
+template <int NT, int P, bool VLDS>
+__global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
+  constexpr int CH = P >= 16 ? 1 : (P >= 8 ? 2 : (P >= 4 ? 4 : 8));  // rows per chunk
+  constexpr bool PREW = P <= 8;
+  typedef typename std::conditional<VLDS, double*, gdouble*>::type VPtr;
   extern __shared__ double smem[];
   const int tid = threadIdx.x;
   const int s = blockIdx.y;
   const KBlock b = a.blocks[blockIdx.x];
   const int m = b.m;
+  const int mp = m <= 16 ? 16 : 32;
   const int nloc = b.Lx * b.Ly;
+  int64_t oh, ored, oe;
+  lds_layout(NT, m, VLDS ? nloc : 0, &oh, &ored, &oe);
+  VPtr V;
+  if constexpr (VLDS) {
+    V = smem;
+  } else {
+    double* g = (b.vwork ? b.vwork : a.vwork + b.v_off) + (int64_t)s * (m + 1) * nloc;
+    V = (VPtr)g;
+  }
+  double* H = smem + oh;
+  double* red = smem + ored;  // [NT/64][32]
+  double* EA = smem + oe;
+  double* EW = EA + mp * mp;
+  double* ER = EW + 5 * mp * mp;
+  double* piv = ER + mp * mp;
 
-  double* H = smem;                       // (m+1) x m, H[i*m + j]
-  double* hv = H + (m + 1) * m;           // pass-1 dots
-  double* hv2 = hv + (m + 1);             // pass-2 dots
-  double* red = hv2 + (m + 1);            // (NT/64)*8 + 8
-  double* piv = red + (NT / 64) * 8 + 8;  // NT/64 + 8
-  double* EA = piv + NT / 64 + 8;         // m*m
-  double* EW = EA + m * m;                // 5*m*m
-  double* ER = EW + 5 * m * m;            // m*m
   const double* x_in = b.xin ? b.xin : a.x_in;
   double* x_out = b.xout ? b.xout : a.x_out;
-  double* V;
-  if (VLDS) {
-    V = ER + m * m;
-  } else {
-    V = (b.vwork ? b.vwork : a.vwork + b.v_off) + (int64_t)s * (m + 1) * nloc;
-  }
-
-  // Points owned by this thread and their box coordinates.
-  int lxs[PMAX], lys[PMAX];
-  bool live[PMAX];
-#pragma unroll
-  for (int p = 0; p < PMAX; ++p) {
-    const int l = tid + p * NT;
-    live[p] = l < nloc;
-    lys[p] = live[p] ? l / b.Lx : 0;
-    lxs[p] = live[p] ? l - lys[p] * b.Lx : 0;
-  }
   const bool varcoef = b.mu_off >= 0;
   const double* mux = (b.coef ? b.coef : a.coef) + (varcoef ? b.mu_off : 0);
   const int64_t Ng = (b.ndim == 1) ? b.n : (int64_t)b.n * b.n;
   const double* muy = mux + Ng;
 
-  // 1. gather
-  double cur[PMAX];
+  // Point p of this thread is local index tid + p*NT; its box coordinates
+  // are recomputed where needed (keeping them would cost 2P registers).
+  int li[P];
+  bool live[P];
 #pragma unroll
-  for (int p = 0; p < PMAX; ++p)
-    cur[p] = live[p] ? x_in[b.x_off + gather_index(b, lxs[p], lys[p]) * b.ns + s] : 0.0;
+  for (int p = 0; p < P; ++p) {
+    const int l = tid + p * NT;
+    live[p] = l < nloc;
+    li[p] = live[p] ? l : 0;  // safe index for lanes past the box
+  }
+  auto coords = [&](int p, int& lx, int& ly) {
+    ly = li[p] / b.Lx;
+    lx = li[p] - ly * b.Lx;
+  };
+  // stencil weights of point p (couplings leaving the box are dropped)
+  auto weights = [&](int p, double& w0, double& wW, double& wE, double& wS, double& wN) {
+    int lx, ly;
+    coords(p, lx, ly);
+    w0 = b.w0; wW = b.wW; wE = b.wE; wS = b.wS; wN = b.wN;
+    if (varcoef) {
+      const int gx = wrap(b.ox - b.h + lx, b.n);
+      const int gy = (b.ndim == 1) ? 0 : wrap(b.oy - b.h + ly, b.n);
+      const int64_t g = (int64_t)gy * b.n + gx;
+      const double me = mux[g];
+      const double mw = mux[(int64_t)gy * b.n + wrap(gx - 1, b.n)];
+      double mn = 0.0, ms = 0.0;
+      if (b.ndim == 2) {
+        mn = muy[g];
+        ms = muy[(int64_t)wrap(gy - 1, b.n) * b.n + gx];
+      }
+      const double sc = b.sub_scale;
+      w0 = -(me + mw + mn + ms) * sc;
+      wW = fma(mw, sc, b.chx);
+      wE = fma(me, sc, -b.chx);
+      wS = fma(ms, sc, b.chy);
+      wN = fma(mn, sc, -b.chy);
+    }
+    if (!live[p]) w0 = 0.0;
+    if (!live[p] || lx == 0) wW = 0.0;
+    if (!live[p] || lx == b.Lx - 1) wE = 0.0;
+    if (!live[p] || ly == 0) wS = 0.0;
+    if (!live[p] || ly == b.Ly - 1) wN = 0.0;
+  };
+  double pw[PREW ? P : 1][5];
+  if constexpr (PREW) {
+#pragma unroll
+    for (int p = 0; p < P; ++p) weights(p, pw[p][0], pw[p][1], pw[p][2], pw[p][3], pw[p][4]);
+  }
+  // (dt_sub A_M v)_l at point p, v the basis row starting at vj
+  auto stencil = [&](auto vj, int p) {
+    double w0, wW, wE, wS, wN;
+    if constexpr (PREW) {
+      w0 = pw[p][0]; wW = pw[p][1]; wE = pw[p][2]; wS = pw[p][3]; wN = pw[p][4];
+    } else {
+      weights(p, w0, wW, wE, wS, wN);
+    }
+    const int l = li[p];
+    double r = w0 * vj[l];
+    if (wW != 0.0) r = fma(wW, vj[l - 1], r);
+    if (wE != 0.0) r = fma(wE, vj[l + 1], r);
+    if (wS != 0.0) r = fma(wS, vj[l - b.Lx], r);
+    if (wN != 0.0) r = fma(wN, vj[l + b.Lx], r);
+    return r;
+  };
 
-  double nrm0 = 0.0;
+  double cur[P];
 #pragma unroll
-  for (int p = 0; p < PMAX; ++p) nrm0 = fma(cur[p], cur[p], nrm0);
-  const double beta0 = sqrt(wg_sum1<NT>(nrm0, red));
+  for (int p = 0; p < P; ++p) {
+    int lx, ly;
+    coords(p, lx, ly);
+    cur[p] = live[p] ? x_in[b.x_off + gather_index(b, lx, ly) * b.ns + s] : 0.0;
+  }
+
+  double vv[32];
+  auto norm2 = [&](const double (&x)[P]) {
+    double t = 0.0;
+#pragma unroll
+    for (int p = 0; p < P; ++p) t = fma(x[p], x[p], t);
+#pragma unroll
+    for (int i = 0; i < 32; ++i) vv[i] = 0.0;
+    vv[0] = t;
+    wg_reduce32<NT>(vv, 1, red);
+    const double r = red_total<NT>(red, 0);
+    __syncthreads();
+    return r;
+  };
+  // Sweeps over the basis rows 0..jj in chunks of CH rows: all loads of a
+  // chunk are in flight before the first use.  Rows past jj are clamped to jj
+  // (valid data) and enter with a zero weight or are discarded; lanes past
+  // the box read point 0 and contribute zero.
+  auto dots_chunked = [&](int jj, const double (&x)[P], double (&out)[32]) {
+#pragma unroll 1
+    for (int c0 = 0; c0 <= jj; c0 += CH) {
+      double vals[CH][P];
+#pragma unroll
+      for (int q = 0; q < CH; ++q) {
+        const int i = min(c0 + q, jj);
+#pragma unroll
+        for (int p = 0; p < P; ++p) vals[q][p] = V[(int64_t)i * nloc + li[p]];
+      }
+#pragma unroll
+      for (int q = 0; q < CH; ++q) {
+        double t = 0.0;
+#pragma unroll
+        for (int p = 0; p < P; ++p) t = fma(live[p] ? vals[q][p] : 0.0, x[p], t);
+        // place t at out[c0 + q] with static indices only (a dynamic index
+        // would move `out` to scratch memory)
+#pragma unroll
+        for (int i = 0; i < 32; ++i)
+          if (i == c0 + q && i <= jj) out[i] = t;
+      }
+    }
+  };
+  // x -= sum_{i<=jj} total_i v_i (totals from the reduction exchange); the
+  // totals go to column jj of H (assigned, or added when `second`); returns
+  // sum total_i^2.
+  auto update_chunked = [&](int jj, double (&x)[P], bool second) {
+    double ss = 0.0;
+    for (int i0 = 0; i0 <= jj; i0 += CH) {
+      double vals[CH][P], hc[CH];
+#pragma unroll
+      for (int q = 0; q < CH; ++q) {
+        const int i = min(i0 + q, jj);
+        const double t = red_total<NT>(red, i);
+        hc[q] = (i0 + q <= jj) ? t : 0.0;
+#pragma unroll
+        for (int p = 0; p < P; ++p) vals[q][p] = V[(int64_t)i * nloc + li[p]];
+      }
+#pragma unroll
+      for (int q = 0; q < CH; ++q) {
+        ss = fma(hc[q], hc[q], ss);
+        if (tid == 0 && i0 + q <= jj) {
+          if (second) H[(i0 + q) * m + jj] += hc[q];
+          else H[(i0 + q) * m + jj] = hc[q];
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+          x[p] = fma(-hc[q], live[p] ? vals[q][p] : 0.0, x[p]);
+      }
+    }
+    return ss;
+  };
+  auto store_row = [&](int i, const double (&x)[P], double scale) {
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+      if (live[p]) V[(int64_t)i * nloc + li[p]] = x[p] * scale;
+  };
+
+  const double beta0 = sqrt(norm2(cur));
   double worst = 0.0;
   bool bad = !isfinite(beta0);
-
   const int nsub = (a.mode == 1) ? 1 : b.nsub;
+
   for (int sub = 0; sub < nsub; ++sub) {
-    double beta = beta0;
-    if (sub > 0) {
-      double t = 0.0;
-#pragma unroll
-      for (int p = 0; p < PMAX; ++p) t = fma(cur[p], cur[p], t);
-      beta = sqrt(wg_sum1<NT>(t, red));
-    }
+    const double beta = (sub == 0) ? beta0 : sqrt(norm2(cur));
     if (!(beta > 0.0) || !isfinite(beta)) {
       if (!isfinite(beta)) bad = true;
-      break;  // zero (or broken) local state stays as it is
+      break;
     }
-    const double ib = 1.0 / beta;
-#pragma unroll
-    for (int p = 0; p < PMAX; ++p)
-      if (live[p]) V[tid + p * NT] = cur[p] * ib;
+    store_row(0, cur, 1.0 / beta);
     for (int idx = tid; idx < (m + 1) * m; idx += NT) H[idx] = 0.0;
     __syncthreads();
 
     int k = m;
     for (int j = 0; j < m; ++j) {
-      const double* vj = V + (int64_t)j * nloc;
-      double w[PMAX];
+      double w[P];
+      // sweep 1: stencil product, first dots
 #pragma unroll
-      for (int p = 0; p < PMAX; ++p) {
-        double r = 0.0;
-        if (live[p]) {
-          const int l = tid + p * NT, lx = lxs[p], ly = lys[p];
-          double c0, cW, cE, cS, cN;
-          if (!varcoef) {
-            c0 = b.w0; cW = b.wW; cE = b.wE; cS = b.wS; cN = b.wN;
-          } else {
-            const int gx = wrap(b.ox - b.h + lx, b.n);
-            const int gy = (b.ndim == 1) ? 0 : wrap(b.oy - b.h + ly, b.n);
-            const int64_t g = (int64_t)gy * b.n + gx;
-            const double me = mux[g];
-            const double mw = mux[(int64_t)gy * b.n + wrap(gx - 1, b.n)];
-            double mn = 0.0, ms = 0.0;
-            if (b.ndim == 2) {
-              mn = muy[g];
-              ms = muy[(int64_t)wrap(gy - 1, b.n) * b.n + gx];
-            }
-            const double sc = b.sub_scale;
-            c0 = -(me + mw + mn + ms) * sc;
-            cW = fma(mw, sc, b.chx);
-            cE = fma(me, sc, -b.chx);
-            cS = fma(ms, sc, b.chy);
-            cN = fma(mn, sc, -b.chy);
-          }
-          r = c0 * vj[l];
-          if (lx > 0) r = fma(cW, vj[l - 1], r);
-          if (lx < b.Lx - 1) r = fma(cE, vj[l + 1], r);
-          if (ly > 0) r = fma(cS, vj[l - b.Lx], r);
-          if (ly < b.Ly - 1) r = fma(cN, vj[l + b.Lx], r);
-        }
-        w[p] = r;
+      for (int p = 0; p < P; ++p) w[p] = stencil(V + (int64_t)j * nloc, p);
+#pragma unroll
+      for (int i = 0; i < 32; ++i) vv[i] = 0.0;
+      dots_chunked(j, w, vv);
+      wg_reduce32<NT>(vv, j + 1, red);
+      // sweep 2: first update, second dots and the squared norm
+      update_chunked(j, w, false);
+      __syncthreads();  // everyone has read red before it is reused
+#pragma unroll
+      for (int i = 0; i < 32; ++i) vv[i] = 0.0;
+      dots_chunked(j, w, vv);
+      {
+        double t = 0.0;
+#pragma unroll
+        for (int p = 0; p < P; ++p) t = fma(w[p], w[p], t);
+#pragma unroll
+        for (int i = 0; i < 32; ++i)
+          if (i == j + 1) vv[i] = t;  // slot j+1 carries the norm (j + 1 <= 30)
       }
-      // Two classical Gram-Schmidt passes.
-      for (int pass = 0; pass < 2; ++pass) {
-        double* dots = pass == 0 ? hv : hv2;
-        for (int i0 = 0; i0 <= j; i0 += 8) {
-          const int cnt = min(8, j + 1 - i0);
-          double part[8];
-#pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            double t = 0.0;
-            if (q < cnt) {
-              const double* vi = V + (int64_t)(i0 + q) * nloc;
-#pragma unroll
-              for (int p = 0; p < PMAX; ++p)
-                if (live[p]) t = fma(vi[tid + p * NT], w[p], t);
-            }
-            part[q] = t;
-          }
-          wg_sum<NT, 8>(part, cnt, red, dots + i0);
-        }
-        for (int i = 0; i <= j; ++i) {
-          const double hi = dots[i];
-          const double* vi = V + (int64_t)i * nloc;
-#pragma unroll
-          for (int p = 0; p < PMAX; ++p)
-            if (live[p]) w[p] = fma(-hi, vi[tid + p * NT], w[p]);
-        }
-      }
-      double t = 0.0;
-#pragma unroll
-      for (int p = 0; p < PMAX; ++p) t = fma(w[p], w[p], t);
-      const double hn = sqrt(wg_sum1<NT>(t, red));
+      wg_reduce32<NT>(vv, j + 2, red);
+      // sweep 3: second update, norm, store
+      const double e2 = update_chunked(j, w, true);
+      const double n1 = red_total<NT>(red, j + 1);
+      double hn2 = n1 - e2;
+      __syncthreads();
+      if (!(hn2 > 1e-4 * n1)) hn2 = norm2(w);  // severe cancellation: measure
+      const double hn = sqrt(fmax(hn2, 0.0));
       double hs = 0.0;
-      for (int i = 0; i <= j; ++i) {
-        const double hij = hv[i] + hv2[i];
-        hs = fma(hij, hij, hs);
-        if (tid == 0) H[i * m + j] = hij;
-      }
+      for (int i = 0; i <= j; ++i) hs = fma(H[i * m + j], H[i * m + j], hs);
       if (tid == 0) H[(j + 1) * m + j] = hn;
-      if (!(hn > 1e-14 * sqrt(hs + hn * hn))) {  // happy breakdown (or zero)
+      if (!(hn > 1e-14 * sqrt(hs + hn * hn))) {  // invariant subspace reached
         k = j + 1;
         __syncthreads();
         break;
       }
-      const double ih = 1.0 / hn;
-      double* vn = V + (int64_t)(j + 1) * nloc;
-#pragma unroll
-      for (int p = 0; p < PMAX; ++p)
-        if (live[p]) vn[tid + p * NT] = w[p] * ih;
+      store_row(j + 1, w, 1.0 / hn);
       __syncthreads();
     }
 
     if (a.mode == 1) {
-      // Calibration: export beta, k and H.
       double* out = a.calib + ((int64_t)b.diag * b.ns + s) * (2 + (m + 1) * m);
       for (int idx = tid; idx < (m + 1) * m; idx += NT) out[2 + idx] = H[idx];
       if (tid == 0) { out[0] = beta; out[1] = (double)k; }
       return;
     }
 
-    // exp(H_k) e_1
-    for (int idx = tid; idx < k * k; idx += NT) {
-      const int i = idx / k, jj = idx - i * k;
-      EA[idx] = H[i * m + jj];
+    // exp(H_k) e_1 on MFMA
+    const int kp = k <= 16 ? 16 : 32;
+    for (int idx = tid; idx < kp * kp; idx += NT) {
+      const int i = idx / kp, jj = idx - i * kp;
+      EA[idx] = (i < k && jj < k) ? H[i * m + jj] : 0.0;
     }
     __syncthreads();
-    expm_small<NT>(EA, k, EW, ER, piv);
+    expm_mfma<NT>(EA, k, kp, EW, ER, piv);
     const double hk = H[k * m + (k - 1)];
-    const double est = beta * hk * fabs(ER[(k - 1) * k]) / beta0;
-    worst += est;  // the step's estimate is the sum over its sub-steps
-    // v <- beta V_k f
+    worst += beta * hk * fabs(ER[(k - 1) * kp]) / beta0;
+    {
+      double acc[P];
 #pragma unroll
-    for (int p = 0; p < PMAX; ++p) {
-      if (!live[p]) continue;
-      double acc = 0.0;
-      for (int i = 0; i < k; ++i)
-        acc = fma(ER[i * k], V[(int64_t)i * nloc + tid + p * NT], acc);
-      cur[p] = beta * acc;
+      for (int p = 0; p < P; ++p) acc[p] = 0.0;
+      for (int i0 = 0; i0 < k; i0 += CH) {
+        double vals[CH][P], f[CH];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+          const int i = min(i0 + q, k - 1);
+          f[q] = (i0 + q < k) ? ER[i * kp] : 0.0;
+#pragma unroll
+          for (int p = 0; p < P; ++p) vals[q][p] = V[(int64_t)i * nloc + li[p]];
+        }
+#pragma unroll
+        for (int q = 0; q < CH; ++q)
+#pragma unroll
+          for (int p = 0; p < P; ++p) acc[p] = fma(f[q], live[p] ? vals[q][p] : 0.0, acc[p]);
+      }
+#pragma unroll
+      for (int p = 0; p < P; ++p) cur[p] = live[p] ? beta * acc[p] : 0.0;
     }
     __syncthreads();
   }
 
-  // 3. core overwrite
 #pragma unroll
-  for (int p = 0; p < PMAX; ++p) {
+  for (int p = 0; p < P; ++p) {
     if (!live[p]) continue;
-    const int lx = lxs[p], ly = lys[p];
+    int lx, ly;
+    coords(p, lx, ly);
     const int rx = lx - b.h;
     const int ry = (b.ndim == 1) ? ly : ly - b.h;
     if (rx < 0 || rx >= b.cx || ry < 0 || ry >= b.cy) continue;
@@ -247,76 +578,30 @@ __global__ __launch_bounds__(NT) void krylov_lem_kernel(KrylovArgs a) {
   }
 }
 
-// Calibration estimates: for block `item / (nj * ns_cand)`, Krylov dimension
-// j = jlist[...] and sub-step count nsub = 2^e, the relative estimate of one
-// full step: nsub * h_{j+1,j}/nsub * |e_j^T exp(H_j / nsub) e_1|.
-struct EstArgs {
-  const double* calib;  // per block: beta, k, H ((mc+1) x mc)
-  const int* mcal;      // per block calibration dimension mc
-  const int64_t* coff;  // per block offset into calib
-  const int* jlist;     // candidate dimensions
-  int nj;
-  int n_sub_cand;       // candidates nsub = 1, 2, 4, ..., 2^(n_sub_cand-1)
-  double* est;          // [block][sub][j]
-};
-
-template <int NT>
-__global__ __launch_bounds__(NT) void krylov_estimate_kernel(EstArgs a) {
-  extern __shared__ double smem[];
-  const int item = blockIdx.x;
-  const int per = a.nj * a.n_sub_cand;
-  const int blk = item / per;
-  const int r = item - blk * per;
-  const int e = r / a.nj;
-  const int j = a.jlist[r - e * a.nj];
-  const int mc = a.mcal[blk];
-  const double* c = a.calib + a.coff[blk];
-  const int k = (int)c[1];
-  double* out = a.est + item;
-  if (j > mc) { if (threadIdx.x == 0) *out = INFINITY; return; }
-  if (j > k) { if (threadIdx.x == 0) *out = 0.0; return; }  // invariant subspace
-  const double* Hc = c + 2;
-  const double inv = ldexp(1.0, -e);
-  double* EA = smem;
-  double* EW = EA + j * j;
-  double* ER = EW + 5 * j * j;
-  double* piv = ER + j * j;
-  for (int idx = threadIdx.x; idx < j * j; idx += NT) {
-    const int i = idx / j, q = idx - i * j;
-    EA[idx] = Hc[i * mc + q] * inv;
-  }
-  __syncthreads();
-  expm_small<NT>(EA, j, EW, ER, piv);
-  if (threadIdx.x == 0) {
-    // h_{j+1,j} of dt*A is scaled by 1/nsub like H; the estimate of one
-    // sub-step relative to beta, times nsub sub-steps, is h_{j+1,j} |f_j|.
-    const double hk = Hc[j * mc + (j - 1)];
-    *out = hk * fabs(ER[(j - 1) * j]);
-  }
-}
-
-// Pseudo-random probe for calibration: a counter-based hash per (block, point),
-// uniform in [-1, 1).  Only used to size the Krylov dimension.
-__global__ void probe_fill_kernel(double* x, int64_t n, uint64_t seed) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  uint64_t z = (uint64_t)i + seed * 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  z ^= z >> 31;
-  x[i] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
-}
-
-}  // namespace lem
-
 // ------------------------------------------------------------------ launch --
-#include "lem_launch.h"
 
-namespace lem {
+size_t krylov_lds_bytes(int nt, int m, int nloc, bool vlds) {
+  int64_t a, b2, c;
+  return (size_t)lds_layout(nt, m, vlds ? nloc : 0, &a, &b2, &c) * 8;
+}
 
-template <int NT, int PMAX, bool VLDS>
-static hipError_t launch_k(const KrylovArgs& a, int ns, size_t lds, hipStream_t st) {
-  auto fn = krylov_lem_kernel<NT, PMAX, VLDS>;
+int krylov_lds_max_m() { return kLdsMaxM; }
+
+// Launch shape for a box of nloc points: threads and points per thread.
+void krylov_lds_config(int ndim, int nloc, int* nt, int* pmax) {
+  if (ndim == 1 && nloc <= 128) { *nt = 64; *pmax = 2; return; }
+  if (ndim == 1 && nloc <= 512) { *nt = 64; *pmax = 8; return; }
+  if (nloc <= 1024) { *nt = 256; *pmax = 4; return; }
+  if (nloc <= 2048) { *nt = 256; *pmax = 8; return; }
+  if (nloc <= 4096) { *nt = 256; *pmax = 16; return; }
+  if (nloc <= 6144) { *nt = 512; *pmax = 12; return; }
+  if (nloc <= 10240) { *nt = 512; *pmax = 20; return; }
+  *nt = 0; *pmax = 0;
+}
+
+template <int NT, int P, bool VLDS>
+static hipError_t launch_l(const KrylovArgs& a, int ns, size_t lds, hipStream_t st) {
+  auto fn = krylov_lds_kernel<NT, P, VLDS>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)fn,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -326,61 +611,28 @@ static hipError_t launch_k(const KrylovArgs& a, int ns, size_t lds, hipStream_t 
   return hipGetLastError();
 }
 
-// Launch shape for a local box of nloc points: workgroup size and the
-// per-thread point count (template instantiation) that covers it.
-void krylov_config(int ndim, int nloc, int* nt, int* pmax) {
-  if (ndim == 1 && nloc <= 128) { *nt = 64; *pmax = 2; return; }
-  if (ndim == 1 && nloc <= 512) { *nt = 64; *pmax = 8; return; }
-  if (nloc <= 1024) { *nt = 256; *pmax = 4; return; }
-  if (nloc <= 4096) { *nt = 256; *pmax = 16; return; }
-  if (nloc <= 10240) { *nt = 512; *pmax = 20; return; }
-  *nt = 0; *pmax = 0;
-}
-
-size_t krylov_lds_bytes(int nt, int m, int nloc, bool vlds) {
-  return (size_t)krylov_lds_doubles(nt, m, nloc, vlds) * 8;
-}
-
-hipError_t launch_krylov(const KBlock* blocks, int n_blocks, int ns, int nt, int pmax,
-                         bool vlds, size_t lds, const double* x_in, double* x_out,
-                         const double* coef, double* vwork, double* diag, int* status,
-                         double* calib, int mode, hipStream_t st) {
+hipError_t launch_krylov_lds(const KBlock* blocks, int n_blocks, int ns, int nt, int pmax,
+                             bool vlds, size_t lds, const double* x_in, double* x_out,
+                             const double* coef, double* vwork, double* diag, int* status,
+                             double* calib, int mode, hipStream_t st) {
   KrylovArgs a{blocks, x_in, x_out, coef, vwork, diag, status, calib, mode, n_blocks};
   if (n_blocks == 0) return hipSuccess;
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  if (nt == 64 && pmax == 2)
-    return vlds ? launch_k<64, 2, true>(a, ns, lds, st) : launch_k<64, 2, false>(a, ns, lds, st);
-  if (nt == 64 && pmax == 8)
-    return vlds ? launch_k<64, 8, true>(a, ns, lds, st) : launch_k<64, 8, false>(a, ns, lds, st);
-  if (nt == 256 && pmax == 4)
-    return vlds ? launch_k<256, 4, true>(a, ns, lds, st) : launch_k<256, 4, false>(a, ns, lds, st);
-  if (nt == 256 && pmax == 16)
-    return vlds ? launch_k<256, 16, true>(a, ns, lds, st) : launch_k<256, 16, false>(a, ns, lds, st);
-  if (nt == 512 && pmax == 20 && !vlds) return launch_k<512, 20, false>(a, ns, lds, st);
-  return hipErrorInvalidValue;
-}
-
-hipError_t launch_krylov_estimates(const double* calib, const int* mcal,
-                                   const int64_t* coff, const int* jlist, int nj,
-                                   int n_sub_cand, double* est, int n_blocks,
-                                   int j_max, hipStream_t st) {
-  EstArgs a{calib, mcal, coff, jlist, nj, n_sub_cand, est};
-  const size_t lds = (size_t)(7 * j_max * j_max + 16) * 8;
-  auto fn = krylov_estimate_kernel<256>;
-  if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)fn,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
+  if (vlds) {
+    if (nt == 64 && pmax == 2) return launch_l<64, 2, true>(a, ns, lds, st);
+    if (nt == 64 && pmax == 8) return launch_l<64, 8, true>(a, ns, lds, st);
+    if (nt == 256 && pmax == 4) return launch_l<256, 4, true>(a, ns, lds, st);
+    if (nt == 256 && pmax == 8) return launch_l<256, 8, true>(a, ns, lds, st);
+    return hipErrorInvalidValue;
   }
-  hipLaunchKernelGGL(fn, dim3(n_blocks * nj * n_sub_cand), dim3(256), lds, st, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_probe_fill(double* x, int64_t n, uint64_t seed, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(probe_fill_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
-                     x, n, seed);
-  return hipGetLastError();
+  if (nt == 64 && pmax == 2) return launch_l<64, 2, false>(a, ns, lds, st);
+  if (nt == 64 && pmax == 8) return launch_l<64, 8, false>(a, ns, lds, st);
+  if (nt == 256 && pmax == 4) return launch_l<256, 4, false>(a, ns, lds, st);
+  if (nt == 256 && pmax == 8) return launch_l<256, 8, false>(a, ns, lds, st);
+  if (nt == 256 && pmax == 16) return launch_l<256, 16, false>(a, ns, lds, st);
+  if (nt == 512 && pmax == 12) return launch_l<512, 12, false>(a, ns, lds, st);
+  if (nt == 512 && pmax == 20) return launch_l<512, 20, false>(a, ns, lds, st);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace lem

@@ -457,19 +457,14 @@ struct LaunchKey {
 LaunchKey launch_key(int ndim, int nloc, int m, size_t* lds) {
   int nt, pm;
   lem::krylov_lds_config(ndim, nloc, &nt, &pm);
-  if (nt && m <= lem::krylov_lds_max_m()) {
-    const size_t need = lem::krylov_lds_bytes(nt, m, nloc);
-    if (need <= 160 * 1024) {
-      *lds = need;
-      return {1, nt, pm, true};
-    }
-  }
-  lem::krylov_config(ndim, nloc, &nt, &pm);
-  if (nt == 0) return {-1, 0, 0, false};
+  if (nt == 0 || m > lem::krylov_lds_max_m()) return {-1, 0, 0, false};
   const size_t with_v = lem::krylov_lds_bytes(nt, m, nloc, true);
-  const bool vlds = with_v <= 160 * 1024 && pm != 20;
-  *lds = vlds ? with_v : lem::krylov_lds_bytes(nt, m, nloc, false);
-  return {0, nt, pm, vlds};
+  if (pm <= 8 && with_v <= 160 * 1024) {
+    *lds = with_v;
+    return {1, nt, pm, true};
+  }
+  *lds = lem::krylov_lds_bytes(nt, m, nloc, false);
+  return {1, nt, pm, false};
 }
 
 // Relative cost of one block step with Krylov dimension m and nsub sub-steps:
@@ -479,7 +474,7 @@ double block_cost(int ndim, int nloc, int m, int nsub) {
   size_t lds;
   const LaunchKey k = launch_key(ndim, nloc, m, &lds);
   if (k.variant < 0) return INFINITY;
-  const double f = k.variant == 1 ? 1.0 : (k.vlds ? 1.5 : 4.0);
+  const double f = k.vlds ? 1.0 : 4.0;
   return f * nsub * (double)nloc * (m * (m + 3.0) + 40.0);
 }
 
@@ -503,7 +498,7 @@ lem_status bucketize(std::vector<lem::KBlock>& kb, std::vector<lem_plan_s::Bucke
     for (int i : g.second) {
       lem::KBlock k = kb[i];
       bk.lds = std::max(bk.lds, need[i]);
-      if (g.first.variant == 0 && !g.first.vlds) {
+      if (!g.first.vlds) {
         k.v_off = voff;
         voff += (int64_t)(k.m + 1) * k.Lx * k.Ly * ns;
       }
@@ -521,12 +516,9 @@ lem_status launch_buckets(const lem_plan_s* p, const lem::KBlock* d_kb,
                           double* dst, double* vwork, double* diag, double* calib, int mode,
                           hipStream_t st) {
   for (const auto& b : bks) {
-    hipError_t e =
-        b.variant == 1
-            ? lem::launch_krylov_lds(d_kb + b.first, b.count, ns, b.nt, b.pmax, b.lds, src, dst,
-                                     p->d_coef, diag, p->d_status, calib, mode, st)
-            : lem::launch_krylov(d_kb + b.first, b.count, ns, b.nt, b.pmax, b.vlds, b.lds, src,
-                                 dst, p->d_coef, vwork, diag, p->d_status, calib, mode, st);
+    hipError_t e = lem::launch_krylov_lds(d_kb + b.first, b.count, ns, b.nt, b.pmax, b.vlds,
+                                          b.lds, src, dst, p->d_coef, vwork, diag, p->d_status,
+                                          calib, mode, st);
     if (e != hipSuccess)
       return fail(LEM_ERR_HIP, std::string("Krylov launch: ") + hipGetErrorString(e));
   }
@@ -967,9 +959,9 @@ lem_status check_options(const lem_options* o) {
   if (o->core < 0 || o->halo < 0) return fail(LEM_ERR_INVALID, "core and halo must be >= 0");
   if (o->halo == 0 && (o->halo_min < 0 || o->halo_max < o->halo_min || !(o->halo_tol > 0)))
     return fail(LEM_ERR_INVALID, "decay-bound halo needs 0 <= halo_min <= halo_max, halo_tol > 0");
-  if (o->krylov_m < 0 || o->krylov_m > lem::kMaxKrylov || o->krylov_m_max < 2 ||
-      o->krylov_m_max > lem::kMaxKrylov)
-    return fail(LEM_ERR_INVALID, "Krylov dimension must be in [2, 48]");
+  const int mlim = o->method == LEM_METHOD_GLOBAL ? lem::kMaxKrylov : lem::krylov_lds_max_m();
+  if (o->krylov_m < 0 || o->krylov_m > mlim || o->krylov_m_max < 2 || o->krylov_m_max > mlim)
+    return fail(LEM_ERR_INVALID, "Krylov dimension must be in [2, " + std::to_string(mlim) + "]");
   if (o->max_substeps < 1) return fail(LEM_ERR_INVALID, "max_substeps must be >= 1");
   if (!(o->krylov_tol > 0)) return fail(LEM_ERR_INVALID, "krylov_tol must be > 0");
   return LEM_OK;
@@ -1078,7 +1070,7 @@ void lem_options_default(lem_options* o) {
   o->halo_max = 64;
   o->halo_tol = 1e-8;
   o->krylov_m = 0;
-  o->krylov_m_max = 40;
+  o->krylov_m_max = 30;
   o->max_substeps = 64;
   o->krylov_tol = 1e-13;
   o->use_graph = 0;
@@ -1404,7 +1396,7 @@ void lem_server_options_default(lem_server_options* o) {
   o->halo_max = 32;
   o->max_overhead = 4.0;
   o->krylov_tol = 1e-12;
-  o->krylov_m_max = 40;
+  o->krylov_m_max = 30;
   o->max_substeps = 64;
   o->dry_run = 0;
 }
@@ -1414,7 +1406,8 @@ lem_status lem_server_create(const lem_server_options* opt, void* stream, lem_se
   *out = nullptr;
   if (opt->hbm_budget < 4096 || opt->max_active < 1 || !(opt->halo_tol > 0) ||
       opt->halo_min < 0 || opt->halo_max < opt->halo_min || !(opt->max_overhead >= 1) ||
-      !(opt->krylov_tol > 0) || opt->krylov_m_max < 2 || opt->krylov_m_max > lem::kMaxKrylov ||
+      !(opt->krylov_tol > 0) || opt->krylov_m_max < 2 ||
+      opt->krylov_m_max > lem::krylov_lds_max_m() ||
       opt->max_substeps < 1)
     return fail(LEM_ERR_INVALID, "invalid server options");
   auto s = new lem_server_s();
@@ -1532,14 +1525,10 @@ lem_status lem_server_tick(lem_server_t s, int32_t* n_active, int32_t* n_queued)
     off = 0;
     for (auto& g : groups) {
       const int nb = (int)g.second.size();
-      hipError_t e =
-          g.first.variant == 1
-              ? lem::launch_krylov_lds(s->d_table + off, nb, 1, g.first.nt, g.first.pmax,
-                                       lds[g.first], nullptr, nullptr, nullptr, s->d_diag,
-                                       s->d_status, nullptr, 0, s->st)
-              : lem::launch_krylov(s->d_table + off, nb, 1, g.first.nt, g.first.pmax,
-                                   g.first.vlds, lds[g.first], nullptr, nullptr, nullptr,
-                                   nullptr, s->d_diag, s->d_status, nullptr, 0, s->st);
+      hipError_t e = lem::launch_krylov_lds(s->d_table + off, nb, 1, g.first.nt, g.first.pmax,
+                                            g.first.vlds, lds[g.first], nullptr, nullptr,
+                                            nullptr, nullptr, s->d_diag, s->d_status, nullptr, 0,
+                                            s->st);
       if (e != hipSuccess)
         return fail(LEM_ERR_HIP, std::string("serving launch: ") + hipGetErrorString(e));
       off += g.second.size();

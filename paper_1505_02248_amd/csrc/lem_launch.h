@@ -9,25 +9,20 @@
 
 namespace lem {
 
-// ---- Krylov LEM step (krylov_lem.hip)
-void krylov_config(int ndim, int nloc, int* nt, int* pmax);
-size_t krylov_lds_bytes(int nt, int m, int nloc, bool vlds);
-hipError_t launch_krylov(const KBlock* blocks, int n_blocks, int ns, int nt, int pmax,
-                         bool vlds, size_t lds, const double* x_in, double* x_out,
-                         const double* coef, double* vwork, double* diag, int* status,
-                         double* calib, int mode, hipStream_t st);
+// ---- Krylov calibration (krylov_calib.hip)
 hipError_t launch_krylov_estimates(const double* calib, const int* mcal, const int64_t* coff,
                                    const int* jlist, int nj, int n_sub_cand, double* est,
                                    int n_blocks, int j_max, hipStream_t st);
 hipError_t launch_probe_fill(double* x, int64_t n, uint64_t seed, hipStream_t st);
 
-// ---- LDS-resident Krylov LEM step (krylov_lds.hip)
-size_t krylov_lds_bytes(int nt, int m, int nloc);
+// ---- Krylov LEM step (krylov_lem.hip)
+size_t krylov_lds_bytes(int nt, int m, int nloc, bool vlds);
 int krylov_lds_max_m();
 void krylov_lds_config(int ndim, int nloc, int* nt, int* pmax);
 hipError_t launch_krylov_lds(const KBlock* blocks, int n_blocks, int ns, int nt, int pmax,
-                             size_t lds, const double* x_in, double* x_out, const double* coef,
-                             double* diag, int* status, double* calib, int mode, hipStream_t st);
+                             bool vlds, size_t lds, const double* x_in, double* x_out,
+                             const double* coef, double* vwork, double* diag, int* status,
+                             double* calib, int mode, hipStream_t st);
 
 // ---- dense local exponentials (dense.hip)
 size_t dense_op_size();
