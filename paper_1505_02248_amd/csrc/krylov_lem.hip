@@ -320,12 +320,12 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
     live[p] = l < nloc;
     li[p] = live[p] ? l : 0;  // safe index for lanes past the box
   }
-  auto coords = [&](int p, int& lx, int& ly) {
+  auto coords = [&](int p, int& lx, int& ly) __attribute__((always_inline)) {
     ly = li[p] / b.Lx;
     lx = li[p] - ly * b.Lx;
   };
   // stencil weights of point p (couplings leaving the box are dropped)
-  auto weights = [&](int p, double& w0, double& wW, double& wE, double& wS, double& wN) {
+  auto weights = [&](int p, double& w0, double& wW, double& wE, double& wS, double& wN) __attribute__((always_inline)) {
     int lx, ly;
     coords(p, lx, ly);
     w0 = b.w0; wW = b.wW; wE = b.wE; wS = b.wS; wN = b.wN;
@@ -359,7 +359,7 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
     for (int p = 0; p < P; ++p) weights(p, pw[p][0], pw[p][1], pw[p][2], pw[p][3], pw[p][4]);
   }
   // (dt_sub A_M v)_l at point p, v the basis row starting at vj
-  auto stencil = [&](auto vj, int p) {
+  auto stencil = [&](auto vj, int p) __attribute__((always_inline)) {
     double w0, wW, wE, wS, wN;
     if constexpr (PREW) {
       w0 = pw[p][0]; wW = pw[p][1]; wE = pw[p][2]; wS = pw[p][3]; wN = pw[p][4];
@@ -384,7 +384,7 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
   }
 
   double vv[32];
-  auto norm2 = [&](const double (&x)[P]) {
+  auto norm2 = [&](const double (&x)[P]) __attribute__((always_inline)) {
     double t = 0.0;
 #pragma unroll
     for (int p = 0; p < P; ++p) t = fma(x[p], x[p], t);
@@ -400,33 +400,34 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
   // chunk are in flight before the first use.  Rows past jj are clamped to jj
   // (valid data) and enter with a zero weight or are discarded; lanes past
   // the box read point 0 and contribute zero.
-  auto dots_chunked = [&](int jj, const double (&x)[P], double (&out)[32]) {
-#pragma unroll 1
-    for (int c0 = 0; c0 <= jj; c0 += CH) {
-      double vals[CH][P];
+  auto dots_chunked = [&](int jj, const double (&x)[P], double (&out)[32]) __attribute__((always_inline)) {
 #pragma unroll
-      for (int q = 0; q < CH; ++q) {
-        const int i = min(c0 + q, jj);
+    for (int c = 0; c < (VLDS ? 32 / CH : 0); ++c) {
+      if (c * CH <= jj) {
+        // keeps the loads of later chunks from being hoisted above this one
+        // (which would multiply the live registers)
+        asm volatile("" ::: "memory");
+        double vals[CH][P];
 #pragma unroll
-        for (int p = 0; p < P; ++p) vals[q][p] = V[(int64_t)i * nloc + li[p]];
-      }
+        for (int q = 0; q < CH; ++q) {
+          const int i = min(c * CH + q, jj);
 #pragma unroll
-      for (int q = 0; q < CH; ++q) {
-        double t = 0.0;
+          for (int p = 0; p < P; ++p) vals[q][p] = V[(int64_t)i * nloc + li[p]];
+        }
 #pragma unroll
-        for (int p = 0; p < P; ++p) t = fma(live[p] ? vals[q][p] : 0.0, x[p], t);
-        // place t at out[c0 + q] with static indices only (a dynamic index
-        // would move `out` to scratch memory)
+        for (int q = 0; q < CH; ++q) {
+          double t = 0.0;
 #pragma unroll
-        for (int i = 0; i < 32; ++i)
-          if (i == c0 + q && i <= jj) out[i] = t;
+          for (int p = 0; p < P; ++p) t = fma(live[p] ? vals[q][p] : 0.0, x[p], t);
+          out[c * CH + q] = (c * CH + q <= jj) ? t : 0.0;
+        }
       }
     }
   };
   // x -= sum_{i<=jj} total_i v_i (totals from the reduction exchange); the
   // totals go to column jj of H (assigned, or added when `second`); returns
   // sum total_i^2.
-  auto update_chunked = [&](int jj, double (&x)[P], bool second) {
+  auto update_chunked = [&](int jj, double (&x)[P], bool second) __attribute__((always_inline)) {
     double ss = 0.0;
     for (int i0 = 0; i0 <= jj; i0 += CH) {
       double vals[CH][P], hc[CH];
@@ -452,7 +453,61 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
     }
     return ss;
   };
-  auto store_row = [&](int i, const double (&x)[P], double scale) {
+  // Totals of <v_i, x> for i <= jj (and, with `norm`, of <x, x> in slot
+  // jj + 1), readable through red_total afterwards.  LDS-resident bases reduce
+  // all values at once with the butterfly; streamed bases (many points per
+  // thread) reduce row by row across the wave and store the wave totals at
+  // dynamic LDS slots, which keeps no 32-value register array alive.
+  auto reduce_dots = [&](int jj, const double (&x)[P], bool norm) __attribute__((always_inline)) {
+    if constexpr (VLDS) {
+#pragma unroll
+      for (int i = 0; i < 32; ++i) vv[i] = 0.0;
+      dots_chunked(jj, x, vv);
+      int cnt = jj + 1;
+      if (norm) {
+        double t = 0.0;
+#pragma unroll
+        for (int p = 0; p < P; ++p) t = fma(x[p], x[p], t);
+        // the norm goes to the last slot of the butterfly width (a static
+        // index: a store at jj + 1 would be an indexed store into scratch)
+        if (jj + 2 <= 8) { vv[7] = t; cnt = 8; }
+        else if (jj + 2 <= 16) { vv[15] = t; cnt = 16; }
+        else { vv[31] = t; cnt = 32; }
+      }
+      wg_reduce32<NT>(vv, cnt, red);
+      return norm ? cnt - 1 : -1;
+    } else {
+      const int lane = tid & 63, wv = tid >> 6;
+#pragma unroll 1
+      for (int i0 = 0; i0 <= jj; i0 += CH) {
+        double vals[CH][P];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+          const int i = min(i0 + q, jj);
+#pragma unroll
+          for (int p = 0; p < P; ++p) vals[q][p] = V[(int64_t)i * nloc + li[p]];
+        }
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+          double t = 0.0;
+#pragma unroll
+          for (int p = 0; p < P; ++p) t = fma(live[p] ? vals[q][p] : 0.0, x[p], t);
+          t = wave_sum(t);
+          if (lane == 0 && i0 + q <= jj) red[wv * 32 + i0 + q] = t;
+        }
+      }
+      if (norm) {
+        double t = 0.0;
+#pragma unroll
+        for (int p = 0; p < P; ++p) t = fma(x[p], x[p], t);
+        t = wave_sum(t);
+        if (lane == 0) red[wv * 32 + jj + 1] = t;
+      }
+      __syncthreads();
+      return norm ? jj + 1 : -1;
+    }
+  };
+  auto store_row = [&](int i, const double (&x)[P], double scale) __attribute__((always_inline)) {
 #pragma unroll
     for (int p = 0; p < P; ++p)
       if (live[p]) V[(int64_t)i * nloc + li[p]] = x[p] * scale;
@@ -479,28 +534,14 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
       // sweep 1: stencil product, first dots
 #pragma unroll
       for (int p = 0; p < P; ++p) w[p] = stencil(V + (int64_t)j * nloc, p);
-#pragma unroll
-      for (int i = 0; i < 32; ++i) vv[i] = 0.0;
-      dots_chunked(j, w, vv);
-      wg_reduce32<NT>(vv, j + 1, red);
+      reduce_dots(j, w, false);
       // sweep 2: first update, second dots and the squared norm
       update_chunked(j, w, false);
       __syncthreads();  // everyone has read red before it is reused
-#pragma unroll
-      for (int i = 0; i < 32; ++i) vv[i] = 0.0;
-      dots_chunked(j, w, vv);
-      {
-        double t = 0.0;
-#pragma unroll
-        for (int p = 0; p < P; ++p) t = fma(w[p], w[p], t);
-#pragma unroll
-        for (int i = 0; i < 32; ++i)
-          if (i == j + 1) vv[i] = t;  // slot j+1 carries the norm (j + 1 <= 30)
-      }
-      wg_reduce32<NT>(vv, j + 2, red);
+      const int nslot = reduce_dots(j, w, true);  // totals 0..j and the squared norm
       // sweep 3: second update, norm, store
       const double e2 = update_chunked(j, w, true);
-      const double n1 = red_total<NT>(red, j + 1);
+      const double n1 = red_total<NT>(red, nslot);
       double hn2 = n1 - e2;
       __syncthreads();
       if (!(hn2 > 1e-4 * n1)) hn2 = norm2(w);  // severe cancellation: measure
@@ -594,9 +635,7 @@ void krylov_lds_config(int ndim, int nloc, int* nt, int* pmax) {
   if (nloc <= 1024) { *nt = 256; *pmax = 4; return; }
   if (nloc <= 2048) { *nt = 256; *pmax = 8; return; }
   if (nloc <= 4096) { *nt = 256; *pmax = 16; return; }
-  if (nloc <= 6144) { *nt = 512; *pmax = 12; return; }
-  if (nloc <= 10240) { *nt = 512; *pmax = 20; return; }
-  *nt = 0; *pmax = 0;
+  *nt = 0; *pmax = 0;  // larger boxes would spill registers: not supported
 }
 
 template <int NT, int P, bool VLDS>
@@ -630,8 +669,6 @@ hipError_t launch_krylov_lds(const KBlock* blocks, int n_blocks, int ns, int nt,
   if (nt == 256 && pmax == 4) return launch_l<256, 4, false>(a, ns, lds, st);
   if (nt == 256 && pmax == 8) return launch_l<256, 8, false>(a, ns, lds, st);
   if (nt == 256 && pmax == 16) return launch_l<256, 16, false>(a, ns, lds, st);
-  if (nt == 512 && pmax == 12) return launch_l<512, 12, false>(a, ns, lds, st);
-  if (nt == 512 && pmax == 20) return launch_l<512, 20, false>(a, ns, lds, st);
   return hipErrorInvalidValue;
 }
 

@@ -486,7 +486,7 @@ lem_status bucketize(std::vector<lem::KBlock>& kb, std::vector<lem_plan_s::Bucke
   for (size_t i = 0; i < kb.size(); ++i) {
     const int nloc = kb[i].Lx * kb[i].Ly;
     const LaunchKey key = launch_key(kb[i].ndim, nloc, kb[i].m, &need[i]);
-    if (key.variant < 0) return fail(LEM_ERR_UNSUPPORTED, "local box larger than 10240 points");
+    if (key.variant < 0) return fail(LEM_ERR_UNSUPPORTED, "local box larger than 4096 points");
     groups[key].push_back((int)i);
   }
   std::vector<lem::KBlock> out;
@@ -1316,7 +1316,7 @@ void choose_partition(const lem_server_s* s, ServerReq& r, const Op& op) {
     if (op.n % c || c + 2 * h >= op.n) continue;
     const int L = c + 2 * h;
     const int64_t nloc = op.ndim == 2 ? (int64_t)L * L : L;
-    if (nloc > 10240) continue;
+    if (nloc > 4096) continue;
     const double ov = op.ndim == 2 ? (double)L * L / ((double)c * c) : (double)L / c;
     if (ov < best) { best = ov; r.core = c; }
   }
