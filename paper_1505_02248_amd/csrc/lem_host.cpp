@@ -1246,6 +1246,7 @@ struct ServerReq {
 struct lem_server_s {
   lem_server_options opt{};
   hipStream_t st = nullptr;
+  bool own_stream = false;
   char* pool = nullptr;
   lem::Arena* arena = nullptr;
   std::deque<uint64_t> queue;
@@ -1275,6 +1276,7 @@ struct lem_server_s {
       hipFree(d_diag);
       hipFree(d_status);
       hipHostFree(h_table);
+      if (own_stream) hipStreamDestroy(st);
     }
     delete arena;
   }
@@ -1343,6 +1345,8 @@ lem_status server_admit(lem_server_s* s, ServerReq& r) {
   o.krylov_m_max = s->opt.krylov_m_max;
   o.max_substeps = s->opt.max_substeps;
   o.dry_run = s->opt.dry_run;
+  // a global step is a long chain of small launches: replay it from a graph
+  o.use_graph = r.method == LEM_METHOD_GLOBAL ? 1 : 0;
   const size_t before = s->arena->in_use();
   lem_plan_t p = nullptr;
   LEM_TRY(create_plan(&r.op, r.dt, &o, s->st, s->arena, &p));
@@ -1413,6 +1417,15 @@ lem_status lem_server_create(const lem_server_options* opt, void* stream, lem_se
   auto s = new lem_server_s();
   s->opt = *opt;
   s->st = (hipStream_t)stream;
+  if (!opt->dry_run && s->st == nullptr) {
+    // a stream of its own (default priority) so that steps can be replayed
+    // from captured graphs, which the legacy null stream does not allow
+    if (hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking) != hipSuccess) {
+      delete s;
+      return fail(LEM_ERR_HIP, "could not create the serving stream");
+    }
+    s->own_stream = true;
+  }
   if (opt->dry_run) {
     s->arena = new lem::Arena((char*)(uintptr_t)4096, opt->hbm_budget);
   } else {
