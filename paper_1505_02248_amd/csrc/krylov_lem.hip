@@ -347,11 +347,14 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
       wS = fma(ms, sc, b.chy);
       wN = fma(mn, sc, -b.chy);
     }
-    if (!live[p]) w0 = 0.0;
-    if (!live[p] || lx == 0) wW = 0.0;
-    if (!live[p] || lx == b.Lx - 1) wE = 0.0;
-    if (!live[p] || ly == 0) wS = 0.0;
-    if (!live[p] || ly == b.Ly - 1) wN = 0.0;
+    if (!live[p]) w0 = wW = wE = wS = wN = 0.0;
+    if (!b.periodic) {
+      if (lx == 0) wW = 0.0;
+      if (lx == b.Lx - 1) wE = 0.0;
+      if (ly == 0) wS = 0.0;
+      if (ly == b.Ly - 1) wN = 0.0;
+    }
+    if (b.ndim == 1) wS = wN = 0.0;
   };
   double pw[PREW ? P : 1][5];
   if constexpr (PREW) {
@@ -367,11 +370,20 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
       weights(p, w0, wW, wE, wS, wN);
     }
     const int l = li[p];
+    int lW = l - 1, lE = l + 1, lS = l - b.Lx, lN = l + b.Lx;
+    if (b.periodic) {  // neighbours wrap around the whole-grid box
+      int lx, ly;
+      coords(p, lx, ly);
+      if (lx == 0) lW += b.Lx;
+      if (lx == b.Lx - 1) lE -= b.Lx;
+      if (ly == 0) lS += nloc;
+      if (ly == b.Ly - 1) lN -= nloc;
+    }
     double r = w0 * vj[l];
-    if (wW != 0.0) r = fma(wW, vj[l - 1], r);
-    if (wE != 0.0) r = fma(wE, vj[l + 1], r);
-    if (wS != 0.0) r = fma(wS, vj[l - b.Lx], r);
-    if (wN != 0.0) r = fma(wN, vj[l + b.Lx], r);
+    if (wW != 0.0) r = fma(wW, vj[lW], r);
+    if (wE != 0.0) r = fma(wE, vj[lE], r);
+    if (wS != 0.0) r = fma(wS, vj[lS], r);
+    if (wN != 0.0) r = fma(wN, vj[lN], r);
     return r;
   };
 

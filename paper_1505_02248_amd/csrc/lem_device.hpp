@@ -37,6 +37,9 @@ struct KBlock {
   int32_t m, nsub;            // Krylov dimension, equal sub-steps per step
   int32_t ns;                 // ensemble size (stride of the state arrays)
   int32_t diag;               // index of this block's estimate slot
+  int32_t periodic;           // 1: the box is the whole grid and keeps the
+                              // periodic coupling (no decomposition, D = 1)
+  int32_t pad_;
   // Optional per-block buffers (null: the launch's arguments).  A serving
   // launch mixes blocks of independent problems, each with its own state,
   // coefficients and basis work space.

@@ -263,6 +263,7 @@ struct lem_plan_s {
   Op op;
   lem_options opt{};
   int method = 0, ns = 1;
+  bool global_box = false;  // global method run as one periodic Krylov box
   int64_t N = 0;
   std::vector<Box> boxes;
   int n_clamped = 0;
@@ -440,6 +441,7 @@ lem::KBlock make_kblock(const lem_plan_s* p, const Box& b, int m, int nsub, int 
   k.ox = b.ox; k.oy = b.oy; k.cx = b.cx; k.cy = b.cy; k.h = b.h;
   k.Lx = b.cx + 2 * b.h; k.Ly = op.ndim == 2 ? b.cy + 2 * b.h : 1;
   k.m = m; k.nsub = nsub; k.ns = ns; k.diag = diag;
+  k.periodic = (b.cx == op.n && b.h == 0) ? 1 : 0;
   return k;
 }
 
@@ -878,7 +880,7 @@ lem_status plan_global(lem_plan_s* p, hipStream_t st) {
 
 // ----------------------------------------------------------------- step ----
 lem_status run_one(lem_plan_s* p, const double* src, double* dst, hipStream_t st) {
-  switch (p->method) {
+  switch (p->global_box ? LEM_METHOD_KRYLOV : p->method) {
     case LEM_METHOD_KRYLOV:
       return launch_buckets(p, p->d_kb, p->buckets, p->ns, src, dst, p->d_vwork, p->d_diag,
                             nullptr, 0, st);
@@ -1016,6 +1018,12 @@ lem_status create_plan(const lem_operator* op, double dt, const lem_options* opt
   lem_status s = build_op(op, dt, &p->op);
   if (s != LEM_OK) return guard(s);
   p->N = p->op.N();
+  if (p->method == LEM_METHOD_GLOBAL && p->N <= 4096 && p->opt.krylov_m_max <= lem::krylov_lds_max_m()) {
+    // the whole grid fits one box: the global method is the Krylov step on
+    // a single box that keeps the periodic coupling (D = 1)
+    p->global_box = true;
+    p->boxes.push_back({0, 0, p->op.n, p->op.ndim == 2 ? p->op.n : 1, 0});
+  }
   if (p->method == LEM_METHOD_KRYLOV || p->method == LEM_METHOD_DENSE) {
     if (p->opt.core == 0 && p->method == LEM_METHOD_KRYLOV && p->op.ndim == 1)
       p->opt.core = std::min(64, p->op.n);
@@ -1034,7 +1042,7 @@ lem_status create_plan(const lem_operator* op, double dt, const lem_options* opt
       s = dalloc(p, &p->d_tmp, (size_t)p->N * p->ns, &p->bytes_work);
       if (s != LEM_OK) return guard(s);
     }
-    if (p->method == LEM_METHOD_KRYLOV) s = plan_krylov(p, st);
+    if (p->method == LEM_METHOD_KRYLOV || p->global_box) s = plan_krylov(p, st);
     else if (p->method == LEM_METHOD_DENSE) s = plan_dense(p, st);
     else s = plan_global(p, st);
     if (s != LEM_OK) return guard(s);
@@ -1136,7 +1144,7 @@ lem_status lem_plan_query(lem_plan_t p, lem_plan_info* info) {
   info->device_status = (st & lem::kStatusNonFinite) ? LEM_ERR_NOT_CONVERGED
                         : (st & lem::kStatusNotConverged) ? LEM_ERR_NOT_CONVERGED : 0;
   double mx = 0.0;
-  if (p->method == LEM_METHOD_KRYLOV && p->d_diag) {
+  if ((p->method == LEM_METHOD_KRYLOV || p->global_box) && p->d_diag) {
     std::vector<double> d(p->boxes.size() * p->ns);
     LEM_HIP(hipMemcpy(d.data(), p->d_diag, d.size() * 8, hipMemcpyDeviceToHost));
     for (double v : d) mx = std::max(mx, v);
@@ -1502,6 +1510,7 @@ lem_status lem_server_tick(lem_server_t s, int32_t* n_active, int32_t* n_queued)
   if (!s->opt.dry_run && !s->active.empty()) {
     size_t nb = 0;
     for (uint64_t id : s->active) nb += s->reqs[id].plan->kb_host.size();
+    nb = std::max<size_t>(nb, 1);
     LEM_TRY(server_grow(s, nb));
     std::map<LaunchKey, std::vector<lem::KBlock>> groups;
     std::map<LaunchKey, size_t> lds;
@@ -1510,7 +1519,7 @@ lem_status lem_server_tick(lem_server_t s, int32_t* n_active, int32_t* n_queued)
       ServerReq& r = s->reqs[id];
       double* in = r.buf[r.done & 1];
       double* out = r.buf[(r.done + 1) & 1];
-      if (r.method == LEM_METHOD_GLOBAL) {
+      if (r.plan->kb_host.empty()) {  // whole-grid Krylov launches of its own
         LEM_TRY(run_step(r.plan, in, out, s->st));
         continue;
       }
