@@ -21,6 +21,10 @@ SOURCES = ["krylov_lem.hip", "krylov_calib.hip", "dense.hip", "global_krylov.hip
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # MFMA accumulators in ordinary VGPRs: without this the allocator
+         # keeps loop-carried accumulators in VGPRs and copies them to AGPRs
+         # around every MFMA chain.
+         "-mllvm", "-amdgpu-mfma-vgpr-form",
          "-I" + CSRC, "-I" + INCLUDE, "-Wno-unused-result"]
 
 

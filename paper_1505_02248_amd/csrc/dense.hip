@@ -391,7 +391,10 @@ __device__ __forceinline__ int xcd_remap(int bid, int total) {
 // states of one block; wave w owns rows [w*WM, (w+1)*WM).  The X chunk of 16
 // local rows x 64 states is gathered into LDS (double buffered); A fragments
 // stream from the packed E (L2-resident: all blocks share it when the
-// operator is translation invariant).
+// operator is translation invariant).  Both operands of chunk c+1 are
+// requested before the MFMAs of chunk c are issued, A first, so the MFMAs of
+// chunk c never wait on the (possibly HBM-missing) gather of chunk c+1 and
+// the A fragments arrive while the matrix cores are busy.
 template <typename T, int WM>
 __global__ __launch_bounds__(256) void apply_mfma_kernel(ApplyArgs a) {
   constexpr int BN = 64, KC = 16, RT = WM / 16, CT = BN / 16;
@@ -409,8 +412,12 @@ __global__ __launch_bounds__(256) void apply_mfma_kernel(ApplyArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int row0 = rtile * 4 * WM + wv * WM;  // first core row of this wave
   const int col0 = ct0 * BN;
-  const T* E = reinterpret_cast<const T*>(a.E) + (int64_t)b.unique * a.e_stride;
   const int ksteps = a.cols_p >> 2;
+  const bool wave_live = row0 < a.rows_p;
+  // this wave's first fragment: row tile row0/16, k-step 0, this lane
+  const T* Ew = reinterpret_cast<const T*>(a.E) + (int64_t)b.unique * a.e_stride +
+                ((int64_t)(wave_live ? row0 >> 4 : 0) * ksteps << 6) + lane;
+  const int64_t rt_stride = (int64_t)ksteps << 6;
 
   acc_t acc[RT][CT];
 #pragma unroll
@@ -420,6 +427,13 @@ __global__ __launch_bounds__(256) void apply_mfma_kernel(ApplyArgs a) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
 
+  auto load_a = [&](int ch, T (&af)[4][RT]) {
+    const T* src = Ew + ((int64_t)ch << 8);  // 4 k-steps of 64 lanes per chunk
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+      for (int i = 0; i < RT; ++i) af[kk][i] = src[i * rt_stride + (kk << 6)];
+  };
   // X chunk loader: thread -> (row tid/16, 4 states)
   const int xr = tid >> 4, xc = (tid & 15) * 4;
   auto load_x = [&](int k0, double (&v)[4]) {
@@ -435,25 +449,20 @@ __global__ __launch_bounds__(256) void apply_mfma_kernel(ApplyArgs a) {
     }
   };
   const int nchunks = a.cols_p / KC;
+  T af[4][RT], an[4][RT];
+  if (wave_live) load_a(0, af);
   double xv[4];
   load_x(0, xv);
 #pragma unroll
   for (int q = 0; q < 4; ++q) Xs[0][xr][xc + q] = (T)xv[q];
   __syncthreads();
 
-  const bool wave_live = row0 < a.rows_p;
   for (int ch = 0; ch < nchunks; ++ch) {
     const int buf = ch & 1;
-    if (ch + 1 < nchunks) load_x((ch + 1) * KC, xv);
+    const bool more = ch + 1 < nchunks;
+    if (more && wave_live) load_a(ch + 1, an);
+    if (more) load_x((ch + 1) * KC, xv);
     if (wave_live) {
-      T af[4][RT];
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-        for (int i = 0; i < RT; ++i) {
-          const int rt = (row0 >> 4) + i;
-          af[kk][i] = E[(((int64_t)rt * ksteps + ch * 4 + kk) << 6) + lane];
-        }
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         T bfr[CT];
@@ -470,11 +479,15 @@ __global__ __launch_bounds__(256) void apply_mfma_kernel(ApplyArgs a) {
           }
       }
     }
-    if (ch + 1 < nchunks) {
+    if (more) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) Xs[buf ^ 1][xr][xc + q] = (T)xv[q];
     }
     __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+      for (int i = 0; i < RT; ++i) af[kk][i] = an[kk][i];
   }
   if (!wave_live) return;
 #pragma unroll
