@@ -387,19 +387,30 @@ __device__ __forceinline__ int xcd_remap(int bid, int total) {
   return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
 }
 
-// FP64 / FP32 apply.  Workgroup = 4 waves, tile = (4*WM) core rows x 64
-// states of one block; wave w owns rows [w*WM, (w+1)*WM).  The X chunk of 16
-// local rows x 64 states is gathered into LDS (double buffered); A fragments
-// stream from the packed E (L2-resident: all blocks share it when the
-// operator is translation invariant).  Both operands of chunk c+1 are
-// requested before the MFMAs of chunk c are issued, A first, so the MFMAs of
-// chunk c never wait on the (possibly HBM-missing) gather of chunk c+1 and
-// the A fragments arrive while the matrix cores are busy.
-template <typename T, int WM>
-__global__ __launch_bounds__(256) void apply_mfma_kernel(ApplyArgs a) {
-  constexpr int BN = 64, KC = 16, RT = WM / 16, CT = BN / 16;
-  constexpr int XS = BN + 2;  // padded LDS row
-  __shared__ T Xs[2][KC][XS];
+// FP64 / FP32 apply.  Workgroup = NW waves, tile = (NW*WM) core rows x 64
+// states of one block; wave w owns rows [w*WM, (w+1)*WM).  The K loop runs
+// over chunks of KC local rows:
+//  * A fragments (packed E, L2-resident when all blocks share one stored
+//    block) are prefetched one chunk ahead into registers;
+//  * the gathered X rows of chunk c+2 are loaded into registers while chunk c
+//    is multiplied, and written to the LDS stage of chunk c+1 after it, so a
+//    gather has two chunks of MFMA time to arrive (two LDS stages, one
+//    barrier per chunk);
+//  * the B fragments of k-step kk+1 are read from LDS before the MFMAs of kk.
+// Every load is unconditional (indices clamped: the padded columns of E are
+// zero, so a clamped X row contributes nothing), which keeps the loop body
+// free of branches around memory operations and lets the compiler count
+// outstanding loads exactly.  The loop is unrolled by two so that register
+// sets and LDS stages are addressed statically.  Lane l of a B fragment holds
+// states 4*(l%16) .. 4*(l%16)+3 (one 32-byte LDS read, one 32-byte store).
+template <typename T, int WM, int KC, int NW>
+__global__ __launch_bounds__(64 * NW) void apply_mfma_kernel(ApplyArgs a) {
+  constexpr int BN = 64, RT = WM / 16, CT = 4, KK = KC / 4;
+  constexpr int XS = BN + 4;            // padded LDS row (keeps 32-byte alignment)
+  constexpr int EPT = KC * BN / (64 * NW);  // X elements per thread per chunk
+  constexpr int TPR = BN / EPT;         // threads per X row
+  static_assert(EPT >= 1 && BN % EPT == 0, "X chunk does not tile the workgroup");
+  __shared__ T Xs0[KC][XS], Xs1[KC][XS];
   typedef typename std::conditional<sizeof(T) == 8, d4, f4>::type acc_t;
 
   const int total = a.n_blocks * a.row_tiles * a.col_tiles;
@@ -410,14 +421,17 @@ __global__ __launch_bounds__(256) void apply_mfma_kernel(ApplyArgs a) {
   const int blk = rest / a.row_tiles;
   const DBlock b = a.blocks[blk];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int row0 = rtile * 4 * WM + wv * WM;  // first core row of this wave
+  const int row0 = rtile * NW * WM + wv * WM;  // first core row of this wave
   const int col0 = ct0 * BN;
   const int ksteps = a.cols_p >> 2;
   const bool wave_live = row0 < a.rows_p;
-  // this wave's first fragment: row tile row0/16, k-step 0, this lane
+  // this wave's first fragment (row tile row0/16, k-step 0, this lane); waves
+  // past the padded rows read row tile 0 and discard it
   const T* Ew = reinterpret_cast<const T*>(a.E) + (int64_t)b.unique * a.e_stride +
                 ((int64_t)(wave_live ? row0 >> 4 : 0) * ksteps << 6) + lane;
   const int64_t rt_stride = (int64_t)ksteps << 6;
+  const int nchunks = a.cols_p / KC;
+  const int last = nchunks - 1;
 
   acc_t acc[RT][CT];
 #pragma unroll
@@ -427,68 +441,74 @@ __global__ __launch_bounds__(256) void apply_mfma_kernel(ApplyArgs a) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
 
-  auto load_a = [&](int ch, T (&af)[4][RT]) {
-    const T* src = Ew + ((int64_t)ch << 8);  // 4 k-steps of 64 lanes per chunk
+  auto load_a = [&](int ch, T (&af)[KK][RT]) {
+    const T* src = Ew + ((int64_t)ch * KK << 6);
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk)
+    for (int kk = 0; kk < KK; ++kk)
 #pragma unroll
       for (int i = 0; i < RT; ++i) af[kk][i] = src[i * rt_stride + (kk << 6)];
   };
-  // X chunk loader: thread -> (row tid/16, 4 states)
-  const int xr = tid >> 4, xc = (tid & 15) * 4;
-  auto load_x = [&](int k0, double (&v)[4]) {
-    const int l = k0 + xr;
-    if (l < a.cols) {
-      const int64_t g = dense_gather(b, l, a.n, a.ndim);
-      const double* src = a.x_in + g * a.ns + col0 + xc;
+  const int xr = tid / TPR, xc = (tid % TPR) * EPT;
+  auto load_x = [&](int ch, double (&v)[EPT]) {
+    int l = ch * KC + xr;
+    l = l < a.cols ? l : a.cols - 1;
+    const int64_t g = dense_gather(b, l, a.n, a.ndim);
+    const double* src = a.x_in + g * a.ns + col0 + xc;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) v[q] = src[q];
-    } else {
+    for (int q = 0; q < EPT; ++q) v[q] = src[q];
+  };
+  auto store_x = [&](const double (&v)[EPT], T (*X)[XS]) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) v[q] = 0.0;
+    for (int q = 0; q < EPT; ++q) X[xr][xc + q] = (T)v[q];
+  };
+  auto mfma_chunk = [&](T (&af)[KK][RT], T (*X)[XS]) {
+    T bb[2][CT];
+    auto rd = [&](int kk, T (&bfr)[CT]) {
+      const T* p = &X[kk * 4 + (lane >> 4)][(lane & 15) * 4];
+#pragma unroll
+      for (int j = 0; j < CT; ++j) bfr[j] = p[j];
+    };
+    rd(0, bb[0]);
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk) {
+      if (kk + 1 < KK) rd(kk + 1, bb[(kk + 1) & 1]);
+      __builtin_amdgcn_sched_barrier(0);  // keep the next reads ahead of these MFMAs
+#pragma unroll
+      for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int j = 0; j < CT; ++j) {
+          if constexpr (sizeof(T) == 8)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[kk][i], bb[kk & 1][j], acc[i][j], 0, 0, 0);
+          else
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[kk][i], bb[kk & 1][j], acc[i][j], 0, 0, 0);
+        }
     }
   };
-  const int nchunks = a.cols_p / KC;
-  T af[4][RT], an[4][RT];
-  if (wave_live) load_a(0, af);
-  double xv[4];
-  load_x(0, xv);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) Xs[0][xr][xc + q] = (T)xv[q];
-  __syncthreads();
-
-  for (int ch = 0; ch < nchunks; ++ch) {
-    const int buf = ch & 1;
-    const bool more = ch + 1 < nchunks;
-    if (more && wave_live) load_a(ch + 1, an);
-    if (more) load_x((ch + 1) * KC, xv);
-    if (wave_live) {
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        T bfr[CT];
-#pragma unroll
-        for (int j = 0; j < CT; ++j) bfr[j] = Xs[buf][kk * 4 + (lane >> 4)][j * 16 + (lane & 15)];
-#pragma unroll
-        for (int i = 0; i < RT; ++i)
-#pragma unroll
-          for (int j = 0; j < CT; ++j) {
-            if constexpr (sizeof(T) == 8)
-              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[kk][i], bfr[j], acc[i][j], 0, 0, 0);
-            else
-              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[kk][i], bfr[j], acc[i][j], 0, 0, 0);
-          }
-      }
-    }
-    if (more) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) Xs[buf ^ 1][xr][xc + q] = (T)xv[q];
-    }
+  // chunk c: multiply (acur, Xc); prefetch A of c+1 into anext and X of c+2
+  // into xcur; then stage X of c+1 (xnext, loaded one chunk earlier) into Xn
+  auto step = [&](int c, T (&acur)[KK][RT], T (&anext)[KK][RT], T (*Xc)[XS], T (*Xn)[XS],
+                  double (&xcur)[EPT], double (&xnext)[EPT]) {
+    load_a(c + 1 < last ? c + 1 : last, anext);
+    load_x(c + 2 < last ? c + 2 : last, xcur);
+    if (wave_live) mfma_chunk(acur, Xc);
+    store_x(xnext, Xn);
     __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-      for (int i = 0; i < RT; ++i) af[kk][i] = an[kk][i];
+  };
+
+  T a0[KK][RT], a1[KK][RT];
+  double x0[EPT], x1[EPT];
+  load_a(0, a0);
+  load_x(0, x0);
+  load_x(last < 1 ? last : 1, x1);
+  store_x(x0, Xs0);
+  __syncthreads();
+  int c = 0;
+  for (; c + 1 < nchunks; c += 2) {
+    step(c, a0, a1, Xs0, Xs1, x0, x1);
+    step(c + 1, a1, a0, Xs1, Xs0, x1, x0);
   }
+  if (c < nchunks) step(c, a0, a1, Xs0, Xs1, x0, x1);
+
   if (!wave_live) return;
 #pragma unroll
   for (int i = 0; i < RT; ++i)
@@ -499,9 +519,9 @@ __global__ __launch_bounds__(256) void apply_mfma_kernel(ApplyArgs a) {
       const int row = row0 + i * 16 + tr;
       if (row >= a.rows) continue;
       const int64_t g = dense_scatter(b, row, a.n, a.ndim);
-      double* dst = a.x_out + g * a.ns + col0 + (lane & 15);
+      double* dst = a.x_out + g * a.ns + col0 + (lane & 15) * 4;
 #pragma unroll
-      for (int j = 0; j < CT; ++j) dst[j * 16] = (double)acc[i][j][r];
+      for (int j = 0; j < CT; ++j) dst[j] = (double)acc[i][j][r];
     }
 }
 
@@ -736,7 +756,7 @@ void dense_block_fill(void* dst, int i, int ox, int oy, int cx, int cy, int h, i
   d->unique = unique;
 }
 
-hipError_t dense_apply(int precision, int wm, const void* blocks, const void* E,
+hipError_t dense_apply(int precision, int cfg, const void* blocks, const void* E,
                        int64_t e_stride, const double* core, const double* x_in,
                        double* x_out, int n, int ndim, int ns, int rows, int rows_p,
                        int cols, int cols_p, int n_blocks, hipStream_t st) {
@@ -757,15 +777,28 @@ hipError_t dense_apply(int precision, int wm, const void* blocks, const void* E,
     return hipGetLastError();
   }
   a.col_tiles = ns / 64;
+  if (precision == 0 || precision == 1) {
+    // tile shapes (rows per wave, K chunk, waves per workgroup)
+    static const int shapes[kApplyConfigs][3] = {{32, 16, 4}, {32, 32, 4}, {32, 32, 8}, {64, 32, 4}};
+    if (cfg < 0 || cfg >= kApplyConfigs) return hipErrorInvalidValue;
+    const int wm = shapes[cfg][0], nw = shapes[cfg][2];
+    a.row_tiles = (rows_p + nw * wm - 1) / (nw * wm);
+    const dim3 g(n_blocks * a.row_tiles * a.col_tiles), blk(64 * nw);
+#define LEM_APPLY(T)                                                                         \
+    switch (cfg) {                                                                           \
+      case 0: hipLaunchKernelGGL((apply_mfma_kernel<T, 32, 16, 4>), g, blk, 0, st, a); break; \
+      case 1: hipLaunchKernelGGL((apply_mfma_kernel<T, 32, 32, 4>), g, blk, 0, st, a); break; \
+      case 2: hipLaunchKernelGGL((apply_mfma_kernel<T, 32, 32, 8>), g, blk, 0, st, a); break; \
+      default: hipLaunchKernelGGL((apply_mfma_kernel<T, 64, 32, 4>), g, blk, 0, st, a); break; \
+    }
+    if (precision == 0) { LEM_APPLY(double) } else { LEM_APPLY(float) }
+#undef LEM_APPLY
+    return hipGetLastError();
+  }
+  const int wm = (cfg & 1) ? 64 : 32;
   a.row_tiles = (rows_p + 4 * wm - 1) / (4 * wm);
   const dim3 g(n_blocks * a.row_tiles * a.col_tiles);
-  if (precision == 0) {
-    if (wm == 32) hipLaunchKernelGGL((apply_mfma_kernel<double, 32>), g, dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((apply_mfma_kernel<double, 64>), g, dim3(256), 0, st, a);
-  } else if (precision == 1) {
-    if (wm == 32) hipLaunchKernelGGL((apply_mfma_kernel<float, 32>), g, dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((apply_mfma_kernel<float, 64>), g, dim3(256), 0, st, a);
-  } else if (precision == 2) {
+  if (precision == 2) {
     if (wm == 32) hipLaunchKernelGGL((apply_bf16_kernel<3, 32>), g, dim3(256), 0, st, a);
     else hipLaunchKernelGGL((apply_bf16_kernel<3, 64>), g, dim3(256), 0, st, a);
   } else if (precision == 3) {

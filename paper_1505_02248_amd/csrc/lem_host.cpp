@@ -277,7 +277,7 @@ struct lem_plan_s {
   double* d_vwork = nullptr;
   double* d_diag = nullptr;
   // dense
-  int U = 0, rows = 0, rows_p = 0, cols = 0, cols_p = 0, wm = 64, squarings = 0;
+  int U = 0, rows = 0, rows_p = 0, cols = 0, cols_p = 0, tile = 0, squarings = 0;
   void* d_db = nullptr;
   double* d_e64 = nullptr;
   float* d_e32 = nullptr;
@@ -772,7 +772,8 @@ lem_status plan_dense(lem_plan_s* p, hipStream_t st) {
     p->d_db = d;
   }
   LEM_TRY(upload(p->d_db, db.data(), db.size(), st));
-  p->wm = p->rows_p >= 256 ? 64 : 32;
+  // default tile shape of the apply kernel (the autotuner may replace it)
+  p->tile = p->opt.precision == LEM_FP32 ? 2 : p->opt.precision == LEM_FP64 ? 0 : (p->rows_p >= 256 ? 1 : 0);
   return LEM_OK;
 }
 
@@ -886,7 +887,7 @@ lem_status run_one(lem_plan_s* p, const double* src, double* dst, hipStream_t st
                             nullptr, 0, st);
     case LEM_METHOD_DENSE: {
       const int64_t es = (int64_t)p->rows_p * p->cols_p;
-      LEM_HIP(lem::dense_apply(p->opt.precision, p->wm, p->d_db, dense_operand(p), es, p->d_core,
+      LEM_HIP(lem::dense_apply(p->opt.precision, p->tile, p->d_db, dense_operand(p), es, p->d_core,
                                src, dst, p->op.n, p->op.ndim, p->ns, p->rows, p->rows_p, p->cols,
                                p->cols_p, (int)p->boxes.size(), st));
       return LEM_OK;
@@ -931,9 +932,10 @@ lem_status autotune_dense(lem_plan_s* p, hipStream_t st) {
   LEM_HIP(hipEventCreate(&e0));
   LEM_HIP(hipEventCreate(&e1));
   float best = INFINITY;
-  int bestwm = p->wm;
-  for (int wm : {32, 64}) {
-    p->wm = wm;
+  int besttile = p->tile;
+  const int ntile = p->opt.precision <= LEM_FP32 ? lem::kApplyConfigs : 2;
+  for (int tile = 0; tile < ntile; ++tile) {
+    p->tile = tile;
     LEM_TRY(run_one(p, a, b, st));
     LEM_HIP(hipEventRecord(e0, st));
     for (int r = 0; r < 5; ++r) LEM_TRY(run_one(p, a, b, st));
@@ -941,9 +943,9 @@ lem_status autotune_dense(lem_plan_s* p, hipStream_t st) {
     LEM_HIP(hipEventSynchronize(e1));
     float ms = 0;
     LEM_HIP(hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best) { best = ms; bestwm = wm; }
+    if (ms < best) { best = ms; besttile = tile; }
   }
-  p->wm = bestwm;
+  p->tile = besttile;
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   dfree(p, a);
@@ -992,7 +994,7 @@ void fill_info(const lem_plan_s* p, lem_plan_info* in) {
   in->bytes_blocks = p->bytes_blocks;
   in->bytes_work = p->bytes_work;
   in->plan_ms = p->plan_ms;
-  in->tile_config = p->wm;
+  in->tile_config = p->tile;
 }
 
 bool overlap(const void* a, const void* b, size_t bytes) {
