@@ -30,18 +30,21 @@ if ROOT not in sys.path:
 METRIC = "DOF-steps/s, LEM vs global Krylov expmv at rel err ≤1e-6; served p99 latency"
 MFMA_FP64_PEAK_TFLOPS = 78.6
 MFMA_FP32_PEAK_TFLOPS = 157.3
-# HBM bytes per launch of the FP64 apply from rocprofv3 FETCH_SIZE / WRITE_SIZE passes
-# (scaled by a 256 MiB reference copy), valid only for the dense.hip source they were
-# taken on: profiles/apply_fp64_2d256x256x64_h14.md
-TRAFFIC = {"dense.hip": ("8b79c86bcc2b", 157977375)}
+# HBM bytes per launch of the FP64 apply at the bench workload, per tile shape
+# (autotuner id), from rocprofv3 FETCH_SIZE / WRITE_SIZE passes scaled by a
+# 256 MiB reference copy; valid only for the dense.hip source they were taken
+# on: profiles/apply_fp64_2d256x256x64_h14.md
+TRAFFIC = {"dense.hip": ("2c76b609a2a7", {0: 147102726, 1: 146209507, 2: 158012682, 3: 158041504})}
 
 
-def measured_traffic():
+def measured_traffic(tile):
     import hashlib
     src = os.path.join(ROOT, "paper_1505_02248_amd", "csrc", "dense.hip")
-    sha, nbytes = TRAFFIC["dense.hip"]
+    sha, per_tile = TRAFFIC["dense.hip"]
     with open(src, "rb") as f:
-        return nbytes if hashlib.sha1(f.read()).hexdigest()[:12] == sha else None
+        if hashlib.sha1(f.read()).hexdigest()[:12] != sha:
+            return None
+    return per_tile.get(tile)
 
 
 def log(*a):
@@ -244,7 +247,7 @@ def bench_c1(args) -> dict:
                    "tile_config": q["tile_config"]},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": MFMA_FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / MFMA_FP64_PEAK_TFLOPS,
-                     "traffic": measured_traffic(),
+                     "traffic": measured_traffic(q["tile_config"]),
                      "kernel": "apply_mfma_kernel<double>", "flops_per_launch": flops,
                      "us_per_launch": kern_ms * 1e3},
         "cpu_baseline": cpu,
