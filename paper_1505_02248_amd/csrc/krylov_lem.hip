@@ -44,7 +44,7 @@ __host__ __device__ inline int64_t lds_layout(int NT, int m, int nloc, int64_t* 
   *off_h = d;
   d += (int64_t)(m + 1) * m;            // Hessenberg
   *off_red = d;
-  d += (int64_t)(NT / 64) * 32 + 64;    // reduction exchange + scalars
+  d += (int64_t)(NT / 64) * 64 + 64;    // reduction exchange + scalars
   *off_e = d;
   d += 7 * (int64_t)mp * mp + 8;        // expm work (A, A2, A4, A6, U, V, R) + pivot
   return d;
@@ -109,6 +109,15 @@ __device__ __forceinline__ double red_total(const double* red, int i) {
   double s = red[i];
 #pragma unroll
   for (int w = 1; w < NT / 64; ++w) s += red[w * 32 + i];
+  return s;
+}
+
+// Same with 64 slots per wave (the paired dots of the streamed Arnoldi).
+template <int NT>
+__device__ __forceinline__ double red_total64(const double* red, int i) {
+  double s = red[i];
+#pragma unroll
+  for (int w = 1; w < NT / 64; ++w) s += red[w * 64 + i];
   return s;
 }
 
@@ -321,8 +330,10 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
     li[p] = live[p] ? l : 0;  // safe index for lanes past the box
   }
   auto coords = [&](int p, int& lx, int& ly) __attribute__((always_inline)) {
-    ly = li[p] / b.Lx;
-    lx = li[p] - ly * b.Lx;
+    int l = li[p];
+    if constexpr (!PREW) asm volatile("" : "+v"(l));  // recompute per use: no hoisting
+    ly = l / b.Lx;
+    lx = l - ly * b.Lx;
   };
   // stencil weights of point p (couplings leaving the box are dropped)
   auto weights = [&](int p, double& w0, double& wW, double& wE, double& wS, double& wN) __attribute__((always_inline)) {
@@ -330,6 +341,9 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
     coords(p, lx, ly);
     w0 = b.w0; wW = b.wW; wE = b.wE; wS = b.wS; wN = b.wN;
     if (varcoef) {
+      int opq = 0;
+      if constexpr (!PREW) asm volatile("" : "+s"(opq));  // recompute per use: no hoisting
+      lx += opq;
       const int gx = wrap(b.ox - b.h + lx, b.n);
       const int gy = (b.ndim == 1) ? 0 : wrap(b.oy - b.h + ly, b.n);
       const int64_t g = (int64_t)gy * b.n + gx;
@@ -541,33 +555,192 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
     __syncthreads();
 
     int k = m;
-    for (int j = 0; j < m; ++j) {
-      double w[P];
-      // sweep 1: stencil product, first dots
-#pragma unroll
-      for (int p = 0; p < P; ++p) w[p] = stencil(V + (int64_t)j * nloc, p);
-      reduce_dots(j, w, false);
-      // sweep 2: first update, second dots and the squared norm
-      update_chunked(j, w, false);
-      __syncthreads();  // everyone has read red before it is reused
-      const int nslot = reduce_dots(j, w, true);  // totals 0..j and the squared norm
-      // sweep 3: second update, norm, store
-      const double e2 = update_chunked(j, w, true);
-      const double n1 = red_total<NT>(red, nslot);
-      double hn2 = n1 - e2;
-      __syncthreads();
-      if (!(hn2 > 1e-4 * n1)) hn2 = norm2(w);  // severe cancellation: measure
-      const double hn = sqrt(fmax(hn2, 0.0));
-      double hs = 0.0;
-      for (int i = 0; i <= j; ++i) hs = fma(H[i * m + j], H[i * m + j], hs);
-      if (tid == 0) H[(j + 1) * m + j] = hn;
-      if (!(hn > 1e-14 * sqrt(hs + hn * hn))) {  // invariant subspace reached
-        k = j + 1;
+    if constexpr (VLDS) {
+      for (int j = 0; j < m; ++j) {
+        double w[P];
+        // sweep 1: stencil product, first dots
+  #pragma unroll
+        for (int p = 0; p < P; ++p) w[p] = stencil(V + (int64_t)j * nloc, p);
+        reduce_dots(j, w, false);
+        // sweep 2: first update, second dots and the squared norm
+        update_chunked(j, w, false);
+        __syncthreads();  // everyone has read red before it is reused
+        const int nslot = reduce_dots(j, w, true);  // totals 0..j and the squared norm
+        // sweep 3: second update, norm, store
+        const double e2 = update_chunked(j, w, true);
+        const double n1 = red_total<NT>(red, nslot);
+        double hn2 = n1 - e2;
         __syncthreads();
-        break;
+        if (!(hn2 > 1e-4 * n1)) hn2 = norm2(w);  // severe cancellation: measure
+        const double hn = sqrt(fmax(hn2, 0.0));
+        double hs = 0.0;
+        for (int i = 0; i <= j; ++i) hs = fma(H[i * m + j], H[i * m + j], hs);
+        if (tid == 0) H[(j + 1) * m + j] = hn;
+        if (!(hn > 1e-14 * sqrt(hs + hn * hn))) {  // invariant subspace reached
+          k = j + 1;
+          __syncthreads();
+          break;
+        }
+        store_row(j + 1, w, 1.0 / hn);
+        __syncthreads();
       }
-      store_row(j + 1, w, 1.0 / hn);
-      __syncthreads();
+    } else {
+      // Streamed basis: Arnoldi with delayed re-orthogonalization (DCGS2:
+      // Swirydowicz et al. 2021; Bielich et al. 2022).  Row j of V holds u_j,
+      // the new direction projected once.  Column j fuses, in one sweep over
+      // the rows i < j, the re-orthogonalization dots s = V^T u_j with the
+      // projection dots z = V^T w of w = A u_j, then one update sweep forms
+      //   v_j = (u_j - V s) / nu,   nu = |u_j - V s|  (measured),
+      //   u_{j+1} = (w - V z - (v_j^T w) v_j) / nu
+      // so every row is read twice per column instead of four times.  The
+      // Hessenberg column j-1 is completed with s and nu (u_j = nu v_j + V s),
+      // and column j is (V_j^T w - Hbar_{j-1} s) / nu, the projections of
+      // A v_j = (w - A V_{j-1} s) / nu.  Column m-1 is completed by a last
+      // pass without a new direction.
+      const int lane = tid & 63, wv = tid >> 6;
+      double u[P];
+      const double ib = 1.0 / beta;  // row 0 holds cur * ib (store_row)
+#pragma unroll
+      for (int p = 0; p < P; ++p) u[p] = live[p] ? cur[p] * ib : 0.0;
+      for (int j = 0; j <= m; ++j) {
+        const bool last = j == m;
+        double w[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) w[p] = last ? 0.0 : stencil(V + (int64_t)j * nloc, p);
+        // sweep A: s_i at slot i, z_i at slot 32 + i, |u|^2 at 31, u^T w at 63
+#pragma unroll 1
+        for (int i0 = 0; i0 < j; i0 += CH) {
+          double vals[CH][P];
+#pragma unroll
+          for (int q = 0; q < CH; ++q) {
+            const int i = min(i0 + q, j - 1);
+#pragma unroll
+            for (int p = 0; p < P; ++p) vals[q][p] = V[(int64_t)i * nloc + li[p]];
+          }
+#pragma unroll
+          for (int q = 0; q < CH; ++q) {
+            double ts = 0.0, tz = 0.0;
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+              const double vq = live[p] ? vals[q][p] : 0.0;
+              ts = fma(vq, u[p], ts);
+              tz = fma(vq, w[p], tz);
+            }
+            ts = wave_sum(ts);
+            tz = wave_sum(tz);
+            if (lane == 0 && i0 + q < j) {
+              red[wv * 64 + i0 + q] = ts;
+              red[wv * 64 + 32 + i0 + q] = tz;
+            }
+          }
+        }
+        {
+          double ta = 0.0, tb = 0.0;
+#pragma unroll
+          for (int p = 0; p < P; ++p) {
+            ta = fma(u[p], u[p], ta);
+            tb = fma(u[p], w[p], tb);
+          }
+          ta = wave_sum(ta);
+          tb = wave_sum(tb);
+          if (lane == 0) {
+            red[wv * 64 + 31] = ta;
+            red[wv * 64 + 63] = tb;
+          }
+        }
+        __syncthreads();
+        // sweep B: vt = u - V s, y = w - V z, and |vt|^2 (slot 30)
+        double vt[P], y[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) { vt[p] = u[p]; y[p] = w[p]; }
+        double sz = 0.0;
+#pragma unroll 1
+        for (int i0 = 0; i0 < j; i0 += CH) {
+          double vals[CH][P], sc[CH], zc[CH];
+#pragma unroll
+          for (int q = 0; q < CH; ++q) {
+            const int i = min(i0 + q, j - 1);
+            const bool ok = i0 + q < j;
+            sc[q] = ok ? red_total64<NT>(red, i) : 0.0;
+            zc[q] = ok ? red_total64<NT>(red, 32 + i) : 0.0;
+#pragma unroll
+            for (int p = 0; p < P; ++p) vals[q][p] = V[(int64_t)i * nloc + li[p]];
+          }
+#pragma unroll
+          for (int q = 0; q < CH; ++q) {
+            sz = fma(sc[q], zc[q], sz);
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+              const double vq = live[p] ? vals[q][p] : 0.0;
+              vt[p] = fma(-sc[q], vq, vt[p]);
+              y[p] = fma(-zc[q], vq, y[p]);
+            }
+          }
+        }
+        {
+          double tn = 0.0;
+#pragma unroll
+          for (int p = 0; p < P; ++p) tn = fma(vt[p], vt[p], tn);
+          tn = wave_sum(tn);
+          if (lane == 0) red[wv * 64 + 30] = tn;
+        }
+        __syncthreads();
+        const double nu = sqrt(fmax(red_total64<NT>(red, 30), 0.0));
+        const double bw = red_total64<NT>(red, 63);  // u^T w
+        // complete column j-1: H[i][j-1] += s_i, H[j][j-1] = nu
+        bool brk = false;
+        if (j > 0) {
+          double hs = 0.0;
+          for (int i = 0; i < j; ++i) {
+            const double hij = H[i * m + j - 1] + red_total64<NT>(red, i);
+            hs = fma(hij, hij, hs);
+          }
+          brk = !(nu > 1e-14 * sqrt(hs + nu * nu));  // invariant subspace reached
+        } else {
+          brk = !(nu > 0.0);
+        }
+        __syncthreads();  // every thread has read column j-1 before it is rewritten
+        // thread i <= j: corrected H[i][j-1], and (unless stopping) the new
+        // column H[i][j] = (z_i - t_i) / nu with t = Hbar_{j-1} s (the
+        // corrected Hessenberg of columns < j), H[j][j] = (v_j^T w - t_j) / nu
+        const double cj = (bw - sz) / nu;  // v_j^T w
+        if (tid <= j) {
+          const int i = tid;
+          double hcorr = 0.0;
+          if (j > 0) {
+            hcorr = (i < j) ? H[i * m + j - 1] + red_total64<NT>(red, i) : nu;
+          }
+          if (!last && !brk) {
+            double t = 0.0;
+            for (int l = (i > 0 ? i - 1 : 0); l < j; ++l) {
+              const double hil = (l == j - 1) ? hcorr : H[i * m + l];
+              t = fma(hil, red_total64<NT>(red, l), t);
+            }
+            const double num = (i < j) ? red_total64<NT>(red, 32 + i) : cj;
+            H[i * m + j] = (num - t) / nu;
+          }
+          if (j > 0) H[i * m + j - 1] = hcorr;
+        }
+        if (brk || last) {
+          k = j > 0 ? j : 0;
+          __syncthreads();
+          break;
+        }
+        // v_j and u_{j+1}
+        const double inv = 1.0 / nu, cc = cj * inv;
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+          const double vj = vt[p] * inv;
+          u[p] = (y[p] - cc * vt[p]) * inv;
+          if (live[p]) {
+            V[(int64_t)j * nloc + li[p]] = vj;
+            V[(int64_t)(j + 1) * nloc + li[p]] = u[p];
+          } else {
+            u[p] = 0.0;
+          }
+        }
+        __syncthreads();
+      }
     }
 
     if (a.mode == 1) {

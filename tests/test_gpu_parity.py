@@ -162,6 +162,23 @@ def test_krylov_2d_uneven_variable_nu():
     assert rel_l2(got, want) <= 1e-12
 
 
+@pytest.mark.parametrize("core,halo,m", [(32, 16, 30), (16, 8, 30), (16, 8, 12)])
+def test_krylov_streamed_bases(core, halo, m):
+    # boxes whose basis does not fit in LDS (1024 and 4096 points at m = 30)
+    # take the streamed Arnoldi; m = 12 on 32x32 boxes stays LDS-resident
+    p = L.workload_2d_variable(n=128)
+    plan = lem.Plan(lem.Operator.from_problem(p), p.dt, method="krylov", core=core, halo=halo,
+                    krylov_m=m, krylov_m_max=m, max_substeps=8, krylov_tol=1e-13)
+    boxes = check_maps(plan, 2, p.n)
+    q = plan.query()
+    basis = q["n_blocks"] * (m + 1) * (core + 2 * halo) ** 2 * 8  # all bases streamed
+    assert (q["bytes_work"] >= basis) == (m == 30)
+    got = run(plan, p.states, 2)
+    want = oracle_lem(p, boxes, p.states, 2, krylov_above=500, krylov_tol=1e-16)
+    assert rel_l2(got, want) <= 1e-12
+    assert q["device_status"] == 0
+
+
 # ---------------------------------------------------------------- global --
 
 def test_global_krylov_1d_and_2d_vs_fourier():
