@@ -286,7 +286,7 @@ typedef __attribute__((address_space(1))) double gdouble;
 // thread P; up to 8 points keep their stencil weights in registers.
 template <int NT, int P, bool VLDS>
 __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
-  constexpr int CH = P >= 16 ? 1 : (P >= 8 ? 2 : (P >= 4 ? 4 : 8));  // rows per chunk
+  constexpr int CH = P >= 16 ? 2 : (P >= 8 ? 2 : (P >= 4 ? 4 : 8));  // rows per chunk
   constexpr bool PREW = P <= 8;
   typedef typename std::conditional<VLDS, double*, gdouble*>::type VPtr;
   extern __shared__ double smem[];
@@ -323,17 +323,20 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
   // are recomputed where needed (keeping them would cost 2P registers).
   int li[P];
   bool live[P];
+  int xy[P];  // box coordinates, lx | ly << 16 (one division per point, once)
 #pragma unroll
   for (int p = 0; p < P; ++p) {
     const int l = tid + p * NT;
     live[p] = l < nloc;
     li[p] = live[p] ? l : 0;  // safe index for lanes past the box
+    const int ly = li[p] / b.Lx;
+    xy[p] = (li[p] - ly * b.Lx) | (ly << 16);
   }
   auto coords = [&](int p, int& lx, int& ly) __attribute__((always_inline)) {
-    int l = li[p];
-    if constexpr (!PREW) asm volatile("" : "+v"(l));  // recompute per use: no hoisting
-    ly = l / b.Lx;
-    lx = l - ly * b.Lx;
+    int c = xy[p];
+    if constexpr (!PREW) asm volatile("" : "+v"(c));  // recompute per use: no hoisting
+    lx = c & 0xffff;
+    ly = c >> 16;
   };
   // stencil weights of point p (couplings leaving the box are dropped)
   auto weights = [&](int p, double& w0, double& wW, double& wE, double& wS, double& wN) __attribute__((always_inline)) {
@@ -383,7 +386,8 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
     } else {
       weights(p, w0, wW, wE, wS, wN);
     }
-    const int l = li[p];
+    int l = li[p];
+    if constexpr (!PREW) asm volatile("" : "+v"(l));  // neighbour offsets per use: no hoisting
     int lW = l - 1, lE = l + 1, lS = l - b.Lx, lN = l + b.Lx;
     if (b.periodic) {  // neighbours wrap around the whole-grid box
       int lx, ly;
@@ -607,32 +611,45 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
         double w[P];
 #pragma unroll
         for (int p = 0; p < P; ++p) w[p] = last ? 0.0 : stencil(V + (int64_t)j * nloc, p);
-        // sweep A: s_i at slot i, z_i at slot 32 + i, |u|^2 at 31, u^T w at 63
+        // sweep A: s_i at slot i, z_i at slot 32 + i, |u|^2 at 31, u^T w at 63.
+        // Rows go in groups of GR; the 2*GR partial sums of a group are
+        // reduced across the wave at once by the butterfly reduce-scatter
+        // (lane l ends with the total of value l / (32 / GR)).
+        constexpr int GR = P >= 16 ? 4 : 8;
 #pragma unroll 1
-        for (int i0 = 0; i0 < j; i0 += CH) {
-          double vals[CH][P];
+        for (int i0 = 0; i0 < j; i0 += GR) {
+          double t[2 * GR];
 #pragma unroll
-          for (int q = 0; q < CH; ++q) {
-            const int i = min(i0 + q, j - 1);
+          for (int q = 0; q < 2 * GR; ++q) t[q] = 0.0;
 #pragma unroll
-            for (int p = 0; p < P; ++p) vals[q][p] = V[(int64_t)i * nloc + li[p]];
-          }
+          for (int q0 = 0; q0 < GR; q0 += CH) {
+            // keeps the loads of later rows from being hoisted above these
+            asm volatile("" ::: "memory");
+            double vals[CH][P];
 #pragma unroll
-          for (int q = 0; q < CH; ++q) {
-            double ts = 0.0, tz = 0.0;
+            for (int q = 0; q < CH; ++q) {
+              const int i = min(i0 + q0 + q, j - 1);
 #pragma unroll
-            for (int p = 0; p < P; ++p) {
-              const double vq = live[p] ? vals[q][p] : 0.0;
-              ts = fma(vq, u[p], ts);
-              tz = fma(vq, w[p], tz);
+              for (int p = 0; p < P; ++p) vals[q][p] = V[(int64_t)i * nloc + li[p]];
             }
-            ts = wave_sum(ts);
-            tz = wave_sum(tz);
-            if (lane == 0 && i0 + q < j) {
-              red[wv * 64 + i0 + q] = ts;
-              red[wv * 64 + 32 + i0 + q] = tz;
+#pragma unroll
+            for (int q = 0; q < CH; ++q) {
+              double ts = 0.0, tz = 0.0;
+#pragma unroll
+              for (int p = 0; p < P; ++p) {
+                const double vq = live[p] ? vals[q][p] : 0.0;
+                ts = fma(vq, u[p], ts);
+                tz = fma(vq, w[p], tz);
+              }
+              const bool ok = i0 + q0 + q < j;
+              t[q0 + q] = ok ? ts : 0.0;
+              t[GR + q0 + q] = ok ? tz : 0.0;
             }
           }
+          const double r = wave_reduce_scatter<2 * GR>(t);
+          constexpr int LPV = 32 / GR;  // lanes per value
+          const int v = lane / LPV, row = i0 + (v % GR);
+          if (lane % LPV == 0 && row < j) red[wv * 64 + (v < GR ? row : 32 + row)] = r;
         }
         {
           double ta = 0.0, tb = 0.0;

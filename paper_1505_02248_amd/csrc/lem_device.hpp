@@ -63,6 +63,10 @@ struct KrylovArgs {
 };
 
 __device__ __forceinline__ int wrap(int a, int n) {
+  // callers are almost always within one period of the range: no division
+  if (a >= 0 && a < n) return a;
+  if (a < 0 && a >= -n) return a + n;
+  if (a >= n && a < 2 * n) return a - n;
   a %= n;
   return a < 0 ? a + n : a;
 }
