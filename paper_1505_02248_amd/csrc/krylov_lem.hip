@@ -287,6 +287,7 @@ typedef __attribute__((address_space(1))) double gdouble;
 template <int NT, int P, bool VLDS>
 __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
   constexpr int CH = P >= 16 ? 2 : (P >= 8 ? 2 : (P >= 4 ? 4 : 8));  // rows per chunk
+  constexpr int CHS = CH;  // rows per load batch of the streamed sweeps
   constexpr bool PREW = P <= 8;
   typedef typename std::conditional<VLDS, double*, gdouble*>::type VPtr;
   extern __shared__ double smem[];
@@ -622,18 +623,18 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
 #pragma unroll
           for (int q = 0; q < 2 * GR; ++q) t[q] = 0.0;
 #pragma unroll
-          for (int q0 = 0; q0 < GR; q0 += CH) {
+          for (int q0 = 0; q0 < GR; q0 += CHS) {
             // keeps the loads of later rows from being hoisted above these
             asm volatile("" ::: "memory");
-            double vals[CH][P];
+            double vals[CHS][P];
 #pragma unroll
-            for (int q = 0; q < CH; ++q) {
+            for (int q = 0; q < CHS; ++q) {
               const int i = min(i0 + q0 + q, j - 1);
 #pragma unroll
               for (int p = 0; p < P; ++p) vals[q][p] = V[(int64_t)i * nloc + li[p]];
             }
 #pragma unroll
-            for (int q = 0; q < CH; ++q) {
+            for (int q = 0; q < CHS; ++q) {
               double ts = 0.0, tz = 0.0;
 #pragma unroll
               for (int p = 0; p < P; ++p) {
@@ -672,10 +673,10 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
         for (int p = 0; p < P; ++p) { vt[p] = u[p]; y[p] = w[p]; }
         double sz = 0.0;
 #pragma unroll 1
-        for (int i0 = 0; i0 < j; i0 += CH) {
-          double vals[CH][P], sc[CH], zc[CH];
+        for (int i0 = 0; i0 < j; i0 += CHS) {
+          double vals[CHS][P], sc[CHS], zc[CHS];
 #pragma unroll
-          for (int q = 0; q < CH; ++q) {
+          for (int q = 0; q < CHS; ++q) {
             const int i = min(i0 + q, j - 1);
             const bool ok = i0 + q < j;
             sc[q] = ok ? red_total64<NT>(red, i) : 0.0;
@@ -684,7 +685,7 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
             for (int p = 0; p < P; ++p) vals[q][p] = V[(int64_t)i * nloc + li[p]];
           }
 #pragma unroll
-          for (int q = 0; q < CH; ++q) {
+          for (int q = 0; q < CHS; ++q) {
             sz = fma(sc[q], zc[q], sz);
 #pragma unroll
             for (int p = 0; p < P; ++p) {
