@@ -23,7 +23,25 @@ def phi1_action(B: np.ndarray, b: np.ndarray) -> np.ndarray:
     return expm(Z)[:n, n]
 
 
+def phi1_matrix(B: np.ndarray) -> np.ndarray:
+    """phi_1(B), the top-right block of expm([[B, I], [0, 0]])."""
+    n = B.shape[0]
+    Z = np.zeros((2 * n, 2 * n), dtype=B.dtype)
+    Z[:n, :n] = B
+    Z[:n, n:] = np.eye(n)
+    return expm(Z)[:n, n:]
+
+
+def phi1_scalar(z):
+    """phi_1(z) = (e^z - 1)/z elementwise (real or complex), phi_1(0) = 1."""
+    z = np.asarray(z)
+    out = np.ones(z.shape, dtype=np.result_type(z, 1.0))
+    nz = z != 0
+    out[nz] = np.expm1(z[nz]) / z[nz]
+    return out
+
+
 def exp_euler_step(B: np.ndarray, v: np.ndarray, g: np.ndarray | None = None):
-    """v + phi_1(B)(B v + dt g) with B = dt*A_M (g already in rate units)."""
+    """v + phi_1(B)(B v + dtg) with B = dt*A_M and dtg = dt times the forcing."""
     r = B @ v if g is None else B @ v + g
     return v + phi1_action(B, r)

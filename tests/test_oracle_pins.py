@@ -306,6 +306,101 @@ def test_exp_euler_form_equals_exp_form():
     assert abs(PHI.phi1_action(z, np.array([1.0]))[0] * 0.7 - math.expm1(0.7)) < 1e-15
 
 
+# ------------------------------------------------------------ forcing ----
+# Update (5) of section 3 with a forcing g constant over the step:
+# exp(dt A_M) v + phi_1(dt A_M)(dt g_M).
+
+def _smooth_field(W, seed):
+    rng = np.random.default_rng(seed)
+    n = W.n
+    x = np.arange(n) / n
+    if W.ndim == 1:
+        return np.cos(2 * np.pi * 3 * x + rng.uniform(0, 6.3)) + 0.3
+    X, Y = np.meshgrid(x, x)
+    return (np.cos(2 * np.pi * (2 * X + Y) + rng.uniform(0, 6.3)) + 0.3).reshape(-1)
+
+
+def test_phi1_closed_form_scalar_and_matrix():
+    # phi_1(z) = (e^z - 1)/z on scalars, including z -> 0 and complex z
+    z = np.array([0.0, 1e-9, -3.5, 2.0 + 1.0j])
+    want = np.array([1.0, 1.0 + 5e-10, (math.exp(-3.5) - 1) / -3.5,
+                     (np.exp(2.0 + 1.0j) - 1) / (2.0 + 1.0j)])
+    assert np.abs(PHI.phi1_scalar(z) - want).max() < 1e-15
+    # on a diagonalizable matrix: V phi_1(D) V^{-1}
+    rng = np.random.default_rng(5)
+    V = rng.standard_normal((6, 6)) + 3 * np.eye(6)
+    d = np.array([-4.0, -1.0, -0.1, 0.0, 0.5, 1.5])
+    B = V @ np.diag(d) @ np.linalg.inv(V)
+    want = V @ np.diag(PHI.phi1_scalar(d)) @ np.linalg.inv(V)
+    assert np.abs(PHI.phi1_matrix(B) - want).max() < 1e-12
+
+
+def test_forcing_constant_field_grows_linearly():
+    # A annihilates constants (rows of the periodic stencil sum to zero), so
+    # u = c, g = k gives exactly u(t + dt) = c + dt k on the global problem
+    for ndim, n in [(1, 64), (2, 16)]:
+        W = op.weights(ndim, n, 1.0 / n, 4.0 / n, (1.0, 0.5), nu=5e-3)
+        u = np.full(W.N, 0.75)
+        dtg = np.full(W.N, 0.2)
+        assert np.abs(ge.fft_steps(W, u, 3, dtg) - (0.75 + 3 * 0.2)).max() < 1e-14
+        assert np.abs(ge.dense_step(W, u, dtg) - 0.95).max() < 1e-13
+
+
+def test_forced_steady_state_is_preserved():
+    # with dt g = -dt A u*, u* is a fixed point of the exact step
+    for ndim, n in [(1, 128), (2, 32)]:
+        W = op.weights(ndim, n, 1.0 / n, 2.0 / n, (1.0, 0.5), nu=2e-3)
+        us = _smooth_field(W, 7)
+        dtg = -op.apply(W, us)
+        assert rel_l2(ge.fft_steps(W, us, 5, dtg), us) < 1e-13
+        if W.N <= 2048:
+            assert rel_l2(ge.dense_step(W, us, dtg), us) < 1e-13
+        assert rel_l2(ge.krylov_step(W, us, dtg=dtg), us) < 1e-13
+
+
+def test_forced_single_domain_lem_equals_fft_and_mass_balance():
+    # one box holding the whole periodic grid: LEM with forcing is the global
+    # exponential-Euler step; the total grows by dt * sum(g) exactly
+    for ndim, n in [(1, 64), (2, 16)]:
+        W = op.weights(ndim, n, 1.0 / n, 4.0 / n, (1.0, 0.5), nu=5e-3)
+        rng = np.random.default_rng(11)
+        u = rng.standard_normal((W.N, 2))
+        dtg = rng.standard_normal((W.N, 2)) * 0.1
+        boxes = [P.Box(0, 0, n, n if ndim == 2 else 1, 0)]
+        got = lem.step(op.sparse(W), boxes, ndim, n, u, dtg=dtg)
+        assert rel_l2(got, ge.fft_steps(W, u, 1, dtg)) < 1e-14
+        assert np.abs(got.sum(0) - (u.sum(0) + dtg.sum(0))).max() < 1e-11
+
+
+def test_forced_lem_superposition_and_krylov_route():
+    # the forced local update is affine: LEM(u, g) = LEM(u, 0) + LEM(0, g); the
+    # augmented Krylov route agrees with the dense phi_1 route
+    p = L.workload_2d_variable(n=32)
+    W = op.from_problem(p)
+    A = op.sparse(W)
+    boxes = P.uniform_boxes(2, 32, 16, 4)
+    u = p.states
+    dtg = 0.05 * _smooth_field(W, 3)
+    full = lem.step(A, boxes, 2, 32, u, dtg=dtg)
+    parts = lem.step(A, boxes, 2, 32, u) + lem.step(A, boxes, 2, 32, 0 * u, dtg=dtg)
+    assert rel_l2(full, parts) < 1e-14
+    kry = lem.step(A, boxes, 2, 32, u, dtg=dtg, krylov_above=100, krylov_tol=1e-16)
+    assert rel_l2(kry, full) < 1e-13
+
+
+def test_forced_lem_converges_to_global_with_halo():
+    p = L.workload_1d()
+    W = op.from_problem(p)
+    A = op.sparse(W)
+    u0 = p.states[:, 0]
+    dtg = p.dt * (0.5 + _smooth_field(W, 2))
+    ref = ge.fft_steps(W, u0, 10, dtg)
+    errs = [rel_l2(lem.run(A, P.uniform_boxes(1, p.n, 64, h), 1, p.n, u0, 10, dtg=dtg), ref)
+            for h in (4, 12, 20, 28)]
+    assert all(b < a / 10 for a, b in zip(errs, errs[1:]))
+    assert errs[-1] < 1e-10
+
+
 def test_nonnegative_local_exponential_when_mu_ge_half_c():
     p = L.workload_1d()
     W = op.from_problem(p)  # C = 4, mu = 4.096 >= C/2
