@@ -88,6 +88,14 @@ typedef struct {
   double vel[2];           /* constant velocity (vel[1] ignored in 1D)        */
   double nu;               /* constant diffusivity >= 0 (if nu_field == NULL) */
   const double* nu_field;  /* optional per-node diffusivity, host, or NULL    */
+  const double* forcing;   /* optional source g of du/dt = A u + g, constant in
+                              time (rate units): host, N x n_states with the
+                              state index fastest, copied at plan time; NULL
+                              for g = 0.  A step is then the exponential-Euler
+                              update (5) of section 3 with g_M, i.e.
+                              exp(dt A_M) v + phi_1(dt A_M)(dt g_M), and the
+                              global method takes exp(dt A) u + phi_1(dt A)(dt g).
+                              Not accepted by the server (LEM_ERR_UNSUPPORTED). */
 } lem_operator;
 
 typedef struct {

@@ -40,7 +40,8 @@ class LemError(RuntimeError):
 class _Operator(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int32), ("n", ctypes.c_int32), ("dx", ctypes.c_double),
                 ("vel", ctypes.c_double * 2), ("nu", ctypes.c_double),
-                ("nu_field", ctypes.POINTER(ctypes.c_double))]
+                ("nu_field", ctypes.POINTER(ctypes.c_double)),
+                ("forcing", ctypes.POINTER(ctypes.c_double))]
 
 
 class _Options(ctypes.Structure):
@@ -124,11 +125,13 @@ class Operator:
     centered finite differences on n (1D) or n x n (2D) points."""
 
     def __init__(self, ndim: int, n: int, dx: float, vel=(1.0, 0.0), nu: float = 0.0,
-                 nu_field: Optional[np.ndarray] = None):
+                 nu_field: Optional[np.ndarray] = None, forcing: Optional[np.ndarray] = None):
         self.ndim, self.n, self.dx = int(ndim), int(n), float(dx)
         self.vel = (float(vel[0]), float(vel[1]) if len(vel) > 1 else 0.0)
         self.nu = float(nu)
         self.nu_field = None if nu_field is None else np.ascontiguousarray(nu_field, dtype=np.float64).reshape(-1)
+        # source g of du/dt = A u + g (rate units), shape (N,) or (N, n_states)
+        self.forcing = None if forcing is None else np.ascontiguousarray(forcing, dtype=np.float64)
 
     @property
     def N(self) -> int:
@@ -149,6 +152,12 @@ class Operator:
             o.nu_field = self.nu_field.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         else:
             o.nu_field = None
+        if self.forcing is not None:
+            if self.forcing.shape[0] != self.N:
+                raise ValueError("forcing must have N rows")
+            o.forcing = self.forcing.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        else:
+            o.forcing = None
         return o
 
 
@@ -182,6 +191,8 @@ class Plan:
         o.krylov_tol = krylov_tol
         o.use_graph, o.autotune, o.dry_run = int(use_graph), int(autotune), int(dry_run)
         self.op, self.dt, self.n_states, self.method = op, float(dt), int(n_states), method
+        if op.forcing is not None and op.forcing.size != op.N * int(n_states):
+            raise ValueError("forcing must hold N x n_states values")
         self._op_c = op._c()
         h = ctypes.c_void_p()
         st = 0 if dry_run else _stream_handle(stream)
@@ -242,8 +253,11 @@ class Plan:
 
 def global_expmv(op: Operator, t: float, x, y, n_states: int = 1, tol: float = 1e-13,
                  m_max: int = 40, stream=None) -> None:
-    """y = exp(t A) x on the whole grid (``lem_global_expmv``)."""
+    """y = exp(t A) x (+ phi_1(t A)(t g) with a forcing) on the whole grid
+    (``lem_global_expmv``)."""
     N = op.N
+    if op.forcing is not None and op.forcing.size != N * int(n_states):
+        raise ValueError("forcing must hold N x n_states values")
     oc = op._c()
     _check(load().lem_global_expmv(ctypes.byref(oc), float(t),
                                    ctypes.c_void_p(_tensor_ptr(x, N, n_states)),

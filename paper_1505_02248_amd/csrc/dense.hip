@@ -362,6 +362,7 @@ struct ApplyArgs {
   int n, ndim, ns;      // grid side, dimension, ensemble size
   int rows, rows_p, cols, cols_p;
   int n_blocks, row_tiles, col_tiles;
+  const double* bias;   // added to every output (forced steps), or null
 };
 
 __device__ __forceinline__ int64_t dense_gather(const DBlock& b, int l, int n, int ndim) {
@@ -519,9 +520,15 @@ __global__ __launch_bounds__(64 * NW) void apply_mfma_kernel(ApplyArgs a) {
       const int row = row0 + i * 16 + tr;
       if (row >= a.rows) continue;
       const int64_t g = dense_scatter(b, row, a.n, a.ndim);
-      double* dst = a.x_out + g * a.ns + col0 + (lane & 15) * 4;
+      const int64_t o = g * a.ns + col0 + (lane & 15) * 4;
+      double* dst = a.x_out + o;
+      if (a.bias) {
 #pragma unroll
-      for (int j = 0; j < CT; ++j) dst[j] = (double)acc[i][j][r];
+        for (int j = 0; j < CT; ++j) dst[j] = (double)acc[i][j][r] + a.bias[o + j];
+      } else {
+#pragma unroll
+        for (int j = 0; j < CT; ++j) dst[j] = (double)acc[i][j][r];
+      }
     }
 }
 
@@ -629,9 +636,11 @@ __global__ __launch_bounds__(256) void apply_bf16_kernel(ApplyArgs a) {
       const int row = row0 + i * 16 + 4 * (lane >> 4) + r;
       if (row >= a.rows) continue;
       const int64_t g = dense_scatter(b, row, a.n, a.ndim);
-      double* dst = a.x_out + g * a.ns + col0 + (lane & 15);
+      const int64_t o = g * a.ns + col0 + (lane & 15);
+      double* dst = a.x_out + o;
 #pragma unroll
-      for (int j = 0; j < CT; ++j) dst[j * 16] = (double)acc[i][j][r];
+      for (int j = 0; j < CT; ++j)
+        dst[j * 16] = (double)acc[i][j][r] + (a.bias ? a.bias[o + j * 16] : 0.0);
     }
 }
 
@@ -653,7 +662,8 @@ __global__ void apply_simple_kernel(ApplyArgs a, const double* core) {
       const int64_t g = dense_gather(b, l, a.n, a.ndim);
       acc = fma((T)Er[l], (T)a.x_in[g * a.ns + s], acc);
     }
-    a.x_out[dense_scatter(b, row, a.n, a.ndim) * a.ns + s] = (double)acc;
+    const int64_t o = dense_scatter(b, row, a.n, a.ndim) * a.ns + s;
+    a.x_out[o] = (double)acc + (a.bias ? a.bias[o] : 0.0);
   }
 }
 
@@ -670,6 +680,39 @@ hipError_t dense_assemble(const void* ops, double* A, int nl, int nu, hipStream_
   dim3 g = grid1((int64_t)nl * nl);
   g.y = nu;
   hipLaunchKernelGGL(assemble_kernel, g, dim3(256), 0, st, (const DenseOp*)ops, A, nl);
+  return hipGetLastError();
+}
+
+// [[dt A_M, I], [0, 0]] (size 2 nl): its exponential holds phi_1(dt A_M) in
+// the top-right block (the forcing term of update (5)).
+__global__ void assemble_aug_kernel(const DenseOp* ops, double* A, int nl) {
+  const int u = blockIdx.y;
+  const DenseOp o = ops[u];
+  const int n2 = 2 * nl;
+  double* M = A + (int64_t)u * n2 * n2;
+  const int64_t total = (int64_t)n2 * n2;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e / n2), c = (int)(e - (int64_t)r * n2);
+    double v = 0.0;
+    if (r < nl && c >= nl) {
+      v = (c - nl == r) ? 1.0 : 0.0;
+    } else if (r < nl) {
+      const int ry = r / o.Lx, rx = r - ry * o.Lx;
+      if (c == r) v = o.w0;
+      else if (c == r - 1 && rx > 0) v = o.wW;
+      else if (c == r + 1 && rx < o.Lx - 1) v = o.wE;
+      else if (c == r - o.Lx && ry > 0) v = o.wS;
+      else if (c == r + o.Lx && ry < o.Ly - 1) v = o.wN;
+    }
+    M[e] = v;
+  }
+}
+
+hipError_t dense_assemble_aug(const void* ops, double* A, int nl, int nu, hipStream_t st) {
+  dim3 g = grid1((int64_t)4 * nl * nl);
+  g.y = nu;
+  hipLaunchKernelGGL(assemble_aug_kernel, g, dim3(256), 0, st, (const DenseOp*)ops, A, nl);
   return hipGetLastError();
 }
 
@@ -759,8 +802,9 @@ void dense_block_fill(void* dst, int i, int ox, int oy, int cx, int cy, int h, i
 hipError_t dense_apply(int precision, int cfg, const void* blocks, const void* E,
                        int64_t e_stride, const double* core, const double* x_in,
                        double* x_out, int n, int ndim, int ns, int rows, int rows_p,
-                       int cols, int cols_p, int n_blocks, hipStream_t st) {
+                       int cols, int cols_p, int n_blocks, const double* bias, hipStream_t st) {
   ApplyArgs a;
+  a.bias = bias;
   a.blocks = (const DBlock*)blocks; a.E = E; a.e_stride = e_stride;
   a.x_in = x_in; a.x_out = x_out; a.n = n; a.ndim = ndim; a.ns = ns;
   a.rows = rows; a.rows_p = rows_p; a.cols = cols; a.cols_p = cols_p;

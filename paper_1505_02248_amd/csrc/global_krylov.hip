@@ -1,4 +1,6 @@
-// Global Krylov action exp(dt A) u on the whole periodic grid (gfx950).
+// Global Krylov action exp(dt A) u on the whole periodic grid (gfx950); with
+// a forcing g constant over the step, the action of the augmented matrix
+// [[dt A, dt g], [0, 0]] on [u; 1] (one extra coordinate per state).
 //
 // This is the "standard exponential method" with a single domain (D = 1) that
 // the paper compares LEM against, computed by the Krylov method of Saad
@@ -25,10 +27,17 @@ struct GlobalOp {
   const double* mux;          // face-mu arrays (dt-scaled), or null
   const double* muy;
   int n, ndim;
+  // forced step: point Npts is the augmented coordinate of [[dt A, dt g],
+  // [0, 0]] (zero row); its column is gscale * g
+  int aug;
+  int64_t Npts;
+  double gscale;
+  const double* force;
 };
 
 __device__ __forceinline__ double gstencil(const GlobalOp& o, const double* X, int64_t pt,
                                            int ns, int s) {
+  if (o.aug && pt == o.Npts) return 0.0;
   const int n = o.n;
   int64_t gx, gy;
   if (o.ndim == 1) { gx = pt; gy = 0; } else { gy = pt / n; gx = pt - gy * n; }
@@ -57,7 +66,22 @@ __device__ __forceinline__ double gstencil(const GlobalOp& o, const double* X, i
     r = fma(cS, X[(ym * n + gx) * ns + s], r);
     r = fma(cN, X[(yp * n + gx) * ns + s], r);
   }
+  if (o.aug) r = fma(o.gscale * o.force[pt * ns + s], X[o.Npts * ns + s], r);
   return r;
+}
+
+// Augmented state [x; 1] (forced steps) and back.
+__global__ void g_aug_in(const double* x, double* xa, int64_t nx, int ns) {
+  const int64_t total = nx + ns;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x)
+    xa[e] = e < nx ? x[e] : 1.0;
+}
+
+__global__ void g_copy(const double* a, double* b, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    b[e] = a[e];
 }
 
 struct GArgs {
@@ -300,16 +324,32 @@ size_t global_part_doubles(int G, int ns) { return (size_t)G * (kMaxKrylov + 1) 
 // One global step (nsub sub-steps of Arnoldi of dimension m) on x -> y.
 // Work: V ((m+1) N ns), W, Wt (N ns each), part, h1, h2, hn (small),
 // H (ns (m+1) m), f (ns m), beta, inv, est (ns).
-hipError_t global_step(const GlobalWork& w, const double* x, double* y, hipStream_t st) {
-  const int64_t total = w.N * w.ns;
+static void fill_op(const GlobalWork& w, GlobalOp& o, bool forced) {
+  o.w0 = w.w[0]; o.wW = w.w[1]; o.wE = w.w[2]; o.wS = w.w[3]; o.wN = w.w[4];
+  o.chx = w.chx; o.chy = w.chy; o.sub_scale = w.sub_scale;
+  o.mux = w.mux; o.muy = w.muy; o.n = w.n; o.ndim = w.ndim;
+  o.aug = forced ? 1 : 0;
+  o.Npts = w.N;
+  o.gscale = w.gscale;
+  o.force = w.force;
+}
+
+hipError_t global_step(const GlobalWork& w, const double* x, double* y_out, hipStream_t st) {
+  const bool forced = w.force != nullptr;
+  const int64_t Na = w.N + (forced ? 1 : 0);  // points (plus the augmented coordinate)
+  const int64_t total = Na * w.ns;
   const int G = global_grid(total, w.ns);
   const int m = w.m;
   constexpr int K = kMaxKrylov + 1;
   GArgs a;
-  a.op.w0 = w.w[0]; a.op.wW = w.w[1]; a.op.wE = w.w[2]; a.op.wS = w.w[3]; a.op.wN = w.w[4];
-  a.op.chx = w.chx; a.op.chy = w.chy; a.op.sub_scale = w.sub_scale;
-  a.op.mux = w.mux; a.op.muy = w.muy; a.op.n = w.n; a.op.ndim = w.ndim;
-  a.V = w.V; a.W = w.W; a.Wt = w.Wt; a.part = w.part; a.N = w.N; a.ns = w.ns;
+  fill_op(w, a.op, forced);
+  a.V = w.V; a.W = w.W; a.Wt = w.Wt; a.part = w.part; a.N = Na; a.ns = w.ns;
+  double* y = y_out;
+  if (forced) {  // work on [x; 1]
+    hipLaunchKernelGGL(g_aug_in, dim3(G), dim3(256), 0, st, x, w.xa, w.N * w.ns, w.ns);
+    x = w.xa;
+    y = w.ya;
+  }
   const size_t lds = (size_t)(7 * m * m + 16) * 8;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)g_expm,
@@ -346,6 +386,7 @@ hipError_t global_step(const GlobalWork& w, const double* x, double* y, hipStrea
   }
   hipLaunchKernelGGL(g_check, dim3((w.ns + 255) / 256), dim3(256), 0, st, w.estsum, w.ns, w.tol,
                      w.status);
+  if (forced) hipLaunchKernelGGL(g_copy, dim3(G), dim3(256), 0, st, y, y_out, w.N * w.ns);
   return hipGetLastError();
 }
 
@@ -357,9 +398,7 @@ hipError_t global_arnoldi(const GlobalWork& w, const double* x, double* calib, h
   const int m = w.m;
   constexpr int K = kMaxKrylov + 1;
   GArgs a;
-  a.op.w0 = w.w[0]; a.op.wW = w.w[1]; a.op.wE = w.w[2]; a.op.wS = w.w[3]; a.op.wN = w.w[4];
-  a.op.chx = w.chx; a.op.chy = w.chy; a.op.sub_scale = w.sub_scale;
-  a.op.mux = w.mux; a.op.muy = w.muy; a.op.n = w.n; a.op.ndim = w.ndim;
+  fill_op(w, a.op, false);  // calibration runs on the unforced operator
   a.V = w.V; a.W = const_cast<double*>(x); a.Wt = w.Wt; a.part = w.part; a.N = w.N; a.ns = w.ns;
   zero_h(w, st);
   hipLaunchKernelGGL(g_norm<1>, dim3(G), dim3(256), 0, st, x, total, w.ns, w.part);

@@ -20,6 +20,11 @@
 //     correction is tiny), with an explicit reduction when cancellation is
 //     severe (near an invariant subspace);
 //   * sweep 3: second update, normalization, store of v_{j+1}.
+// A forcing g, constant over the step, enters update (5) of section 3 as
+// exp(dt A_M) v + phi_1(dt A_M)(dt g_M): that is the exponential of the
+// augmented matrix [[dt A_M, dt g_M], [0, 0]] applied to [v; 1], so a forced
+// block carries one extra coordinate (held at 1 by a zero row; its column is
+// dt_sub g_M) and everything else is unchanged.
 // Reductions of up to 32 values use a wave64 butterfly reduce-scatter
 // (about one cross-lane exchange per value instead of six), then one LDS
 // exchange between waves.  exp(H_m) is evaluated by Pade [13/13] scaling and
@@ -37,10 +42,10 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 constexpr int kLdsMaxM = 30;  // Krylov dimension limit of this kernel
 
 // LDS layout in doubles; mirrored by krylov_lds_bytes() on the host.
-__host__ __device__ inline int64_t lds_layout(int NT, int m, int nloc, int64_t* off_h,
+__host__ __device__ inline int64_t lds_layout(int NT, int m, int nloc, int aug, int64_t* off_h,
                                               int64_t* off_red, int64_t* off_e) {
   const int mp = m <= 16 ? 16 : 32;
-  int64_t d = (int64_t)(m + 1) * nloc;  // basis
+  int64_t d = (int64_t)(m + 1 + aug) * nloc;  // basis (+ the forcing column row)
   *off_h = d;
   d += (int64_t)(m + 1) * m;            // Hessenberg
   *off_red = d;
@@ -296,14 +301,15 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
   const KBlock b = a.blocks[blockIdx.x];
   const int m = b.m;
   const int mp = m <= 16 ? 16 : 32;
-  const int nloc = b.Lx * b.Ly;
+  const int nloc = b.Lx * b.Ly;   // points of the box
+  const int nlv = nloc + b.aug;    // basis row length (plus the augmented coordinate)
   int64_t oh, ored, oe;
-  lds_layout(NT, m, VLDS ? nloc : 0, &oh, &ored, &oe);
+  lds_layout(NT, m, VLDS ? nlv : 0, b.aug, &oh, &ored, &oe);
   VPtr V;
   if constexpr (VLDS) {
     V = smem;
   } else {
-    double* g = (b.vwork ? b.vwork : a.vwork + b.v_off) + (int64_t)s * (m + 1) * nloc;
+    double* g = (b.vwork ? b.vwork : a.vwork + b.v_off) + (int64_t)s * (m + 1 + b.aug) * nlv;
     V = (VPtr)g;
   }
   double* H = smem + oh;
@@ -328,7 +334,7 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
 #pragma unroll
   for (int p = 0; p < P; ++p) {
     const int l = tid + p * NT;
-    live[p] = l < nloc;
+    live[p] = l < nlv;
     li[p] = live[p] ? l : 0;  // safe index for lanes past the box
     const int ly = li[p] / b.Lx;
     xy[p] = (li[p] - ly * b.Lx) | (ly << 16);
@@ -365,7 +371,7 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
       wS = fma(ms, sc, b.chy);
       wN = fma(mn, sc, -b.chy);
     }
-    if (!live[p]) w0 = wW = wE = wS = wN = 0.0;
+    if (!live[p] || li[p] == nloc) w0 = wW = wE = wS = wN = 0.0;  // the augmented row is zero
     if (!b.periodic) {
       if (lx == 0) wW = 0.0;
       if (lx == b.Lx - 1) wE = 0.0;
@@ -374,6 +380,20 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
     }
     if (b.ndim == 1) wS = wN = 0.0;
   };
+  // Forced steps: the augmented column dt_sub g_M (zero on the augmented
+  // row) is kept as row m+1 of the basis storage, written once here.
+  VPtr Fcol = V + (int64_t)(m + 1) * nlv;
+  if (b.aug) {
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      if (!live[p]) continue;
+      int lx, ly;
+      coords(p, lx, ly);
+      Fcol[li[p]] = li[p] == nloc ? 0.0
+                    : b.gscale * b.force[b.x_off + gather_index(b, lx, ly) * b.ns + s];
+    }
+    __syncthreads();
+  }
   double pw[PREW ? P : 1][5];
   if constexpr (PREW) {
 #pragma unroll
@@ -405,13 +425,22 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
     if (wN != 0.0) r = fma(wN, vj[lN], r);
     return r;
   };
+  // forced steps: w += (augmented column) x (augmented coordinate of row j)
+  auto add_forcing = [&](int j, double (&w)[P]) __attribute__((always_inline)) {
+    if (!b.aug) return;
+    const double ve = V[(int64_t)j * nlv + nloc];
+#pragma unroll
+    for (int p = 0; p < P; ++p) w[p] = fma(Fcol[li[p]], ve, w[p]);
+  };
 
   double cur[P];
 #pragma unroll
   for (int p = 0; p < P; ++p) {
     int lx, ly;
     coords(p, lx, ly);
-    cur[p] = live[p] ? x_in[b.x_off + gather_index(b, lx, ly) * b.ns + s] : 0.0;
+    cur[p] = !live[p] ? 0.0
+             : li[p] == nloc ? 1.0  // the augmented coordinate starts (and stays) at 1
+                             : x_in[b.x_off + gather_index(b, lx, ly) * b.ns + s];
   }
 
   double vv[32];
@@ -443,7 +472,7 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
         for (int q = 0; q < CH; ++q) {
           const int i = min(c * CH + q, jj);
 #pragma unroll
-          for (int p = 0; p < P; ++p) vals[q][p] = V[(int64_t)i * nloc + li[p]];
+          for (int p = 0; p < P; ++p) vals[q][p] = V[(int64_t)i * nlv + li[p]];
         }
 #pragma unroll
         for (int q = 0; q < CH; ++q) {
@@ -468,7 +497,7 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
         const double t = red_total<NT>(red, i);
         hc[q] = (i0 + q <= jj) ? t : 0.0;
 #pragma unroll
-        for (int p = 0; p < P; ++p) vals[q][p] = V[(int64_t)i * nloc + li[p]];
+        for (int p = 0; p < P; ++p) vals[q][p] = V[(int64_t)i * nlv + li[p]];
       }
 #pragma unroll
       for (int q = 0; q < CH; ++q) {
@@ -516,7 +545,7 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
         for (int q = 0; q < CH; ++q) {
           const int i = min(i0 + q, jj);
 #pragma unroll
-          for (int p = 0; p < P; ++p) vals[q][p] = V[(int64_t)i * nloc + li[p]];
+          for (int p = 0; p < P; ++p) vals[q][p] = V[(int64_t)i * nlv + li[p]];
         }
 #pragma unroll
         for (int q = 0; q < CH; ++q) {
@@ -541,7 +570,7 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
   auto store_row = [&](int i, const double (&x)[P], double scale) __attribute__((always_inline)) {
 #pragma unroll
     for (int p = 0; p < P; ++p)
-      if (live[p]) V[(int64_t)i * nloc + li[p]] = x[p] * scale;
+      if (live[p]) V[(int64_t)i * nlv + li[p]] = x[p] * scale;
   };
 
   const double beta0 = sqrt(norm2(cur));
@@ -565,7 +594,8 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
         double w[P];
         // sweep 1: stencil product, first dots
   #pragma unroll
-        for (int p = 0; p < P; ++p) w[p] = stencil(V + (int64_t)j * nloc, p);
+        for (int p = 0; p < P; ++p) w[p] = stencil(V + (int64_t)j * nlv, p);
+        add_forcing(j, w);
         reduce_dots(j, w, false);
         // sweep 2: first update, second dots and the squared norm
         update_chunked(j, w, false);
@@ -611,7 +641,8 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
         const bool last = j == m;
         double w[P];
 #pragma unroll
-        for (int p = 0; p < P; ++p) w[p] = last ? 0.0 : stencil(V + (int64_t)j * nloc, p);
+        for (int p = 0; p < P; ++p) w[p] = last ? 0.0 : stencil(V + (int64_t)j * nlv, p);
+        if (!last) add_forcing(j, w);
         // sweep A: s_i at slot i, z_i at slot 32 + i, |u|^2 at 31, u^T w at 63.
         // Rows go in groups of GR; the 2*GR partial sums of a group are
         // reduced across the wave at once by the butterfly reduce-scatter
@@ -631,7 +662,7 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
             for (int q = 0; q < CHS; ++q) {
               const int i = min(i0 + q0 + q, j - 1);
 #pragma unroll
-              for (int p = 0; p < P; ++p) vals[q][p] = V[(int64_t)i * nloc + li[p]];
+              for (int p = 0; p < P; ++p) vals[q][p] = V[(int64_t)i * nlv + li[p]];
             }
 #pragma unroll
             for (int q = 0; q < CHS; ++q) {
@@ -682,7 +713,7 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
             sc[q] = ok ? red_total64<NT>(red, i) : 0.0;
             zc[q] = ok ? red_total64<NT>(red, 32 + i) : 0.0;
 #pragma unroll
-            for (int p = 0; p < P; ++p) vals[q][p] = V[(int64_t)i * nloc + li[p]];
+            for (int p = 0; p < P; ++p) vals[q][p] = V[(int64_t)i * nlv + li[p]];
           }
 #pragma unroll
           for (int q = 0; q < CHS; ++q) {
@@ -751,8 +782,8 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
           const double vj = vt[p] * inv;
           u[p] = (y[p] - cc * vt[p]) * inv;
           if (live[p]) {
-            V[(int64_t)j * nloc + li[p]] = vj;
-            V[(int64_t)(j + 1) * nloc + li[p]] = u[p];
+            V[(int64_t)j * nlv + li[p]] = vj;
+            V[(int64_t)(j + 1) * nlv + li[p]] = u[p];
           } else {
             u[p] = 0.0;
           }
@@ -789,7 +820,7 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
           const int i = min(i0 + q, k - 1);
           f[q] = (i0 + q < k) ? ER[i * kp] : 0.0;
 #pragma unroll
-          for (int p = 0; p < P; ++p) vals[q][p] = V[(int64_t)i * nloc + li[p]];
+          for (int p = 0; p < P; ++p) vals[q][p] = V[(int64_t)i * nlv + li[p]];
         }
 #pragma unroll
         for (int q = 0; q < CH; ++q)
@@ -824,9 +855,9 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
 
 // ------------------------------------------------------------------ launch --
 
-size_t krylov_lds_bytes(int nt, int m, int nloc, bool vlds) {
+size_t krylov_lds_bytes(int nt, int m, int nloc, bool vlds, int aug) {
   int64_t a, b2, c;
-  return (size_t)lds_layout(nt, m, vlds ? nloc : 0, &a, &b2, &c) * 8;
+  return (size_t)lds_layout(nt, m, vlds ? nloc : 0, aug, &a, &b2, &c) * 8;
 }
 
 int krylov_lds_max_m() { return kLdsMaxM; }

@@ -39,7 +39,10 @@ struct KBlock {
   int32_t diag;               // index of this block's estimate slot
   int32_t periodic;           // 1: the box is the whole grid and keeps the
                               // periodic coupling (no decomposition, D = 1)
-  int32_t pad_;
+  int32_t aug;                // 1: forced step, the box carries one extra
+                              // (augmented) coordinate after its Lx*Ly points
+  double gscale;              // dt_sub: scales the forcing to the sub-step
+  const double* force;        // forcing g (rate units), N x ns, or null
   // Optional per-block buffers (null: the launch's arguments).  A serving
   // launch mixes blocks of independent problems, each with its own state,
   // coefficients and basis work space.

@@ -283,6 +283,12 @@ struct lem_plan_s {
   float* d_e32 = nullptr;
   void* d_e16 = nullptr;
   double* d_core = nullptr;
+  // forcing (du/dt = A u + g, g constant in time): device copy of g and, for
+  // the dense method, the per-step term phi_1(dt A_M)(dt g_M) assembled over
+  // the cores
+  bool forced = false;
+  double* d_force = nullptr;
+  double* d_bias = nullptr;
   // global
   lem::GlobalWork gw{};
   // shared
@@ -407,7 +413,7 @@ lem_status make_partition(lem_plan_s* p) {
           double cost = 0;
           for (auto& b : bs) {
             const int L = c + 2 * b.h;
-            cost += block_cost(2, L * L, std::min(mguess, 16), 1);
+            cost += block_cost(2, L * L + (p->forced ? 1 : 0), std::min(mguess, 16), 1);
           }
           if (cost < best) { best = cost; bestb = bs; best_cl = cl; }
         }
@@ -426,8 +432,12 @@ lem_status make_partition(lem_plan_s* p) {
 }
 
 // --------------------------------------------------------------- Krylov ----
-lem::KBlock make_kblock(const lem_plan_s* p, const Box& b, int m, int nsub, int ns, int diag) {
+lem::KBlock make_kblock(const lem_plan_s* p, const Box& b, int m, int nsub, int ns, int diag,
+                        bool forced = false) {
   lem::KBlock k{};
+  k.aug = forced ? 1 : 0;
+  k.gscale = p->op.dt / nsub;
+  k.force = forced ? p->d_force : nullptr;
   const double sc = 1.0 / nsub;
   const Op& op = p->op;
   k.w0 = op.w[0] * sc; k.wW = op.w[1] * sc; k.wE = op.w[2] * sc; k.wS = op.w[3] * sc;
@@ -456,16 +466,18 @@ struct LaunchKey {
   }
 };
 
-LaunchKey launch_key(int ndim, int nloc, int m, size_t* lds) {
+// nloc counts the basis row (box points plus the augmented coordinate of a
+// forced step, aug = 1).
+LaunchKey launch_key(int ndim, int nloc, int m, size_t* lds, int aug = 0) {
   int nt, pm;
   lem::krylov_lds_config(ndim, nloc, &nt, &pm);
   if (nt == 0 || m > lem::krylov_lds_max_m()) return {-1, 0, 0, false};
-  const size_t with_v = lem::krylov_lds_bytes(nt, m, nloc, true);
+  const size_t with_v = lem::krylov_lds_bytes(nt, m, nloc, true, aug);
   if (pm <= 8 && with_v <= 160 * 1024) {
     *lds = with_v;
     return {1, nt, pm, true};
   }
-  *lds = lem::krylov_lds_bytes(nt, m, nloc, false);
+  *lds = lem::krylov_lds_bytes(nt, m, nloc, false, aug);
   return {1, nt, pm, false};
 }
 
@@ -486,9 +498,10 @@ lem_status bucketize(std::vector<lem::KBlock>& kb, std::vector<lem_plan_s::Bucke
   std::map<LaunchKey, std::vector<int>> groups;
   std::vector<size_t> need(kb.size());
   for (size_t i = 0; i < kb.size(); ++i) {
-    const int nloc = kb[i].Lx * kb[i].Ly;
-    const LaunchKey key = launch_key(kb[i].ndim, nloc, kb[i].m, &need[i]);
-    if (key.variant < 0) return fail(LEM_ERR_UNSUPPORTED, "local box larger than 4096 points");
+    const int nloc = kb[i].Lx * kb[i].Ly + kb[i].aug;  // basis row (plus augmented coordinate)
+    const LaunchKey key = launch_key(kb[i].ndim, nloc, kb[i].m, &need[i], kb[i].aug);
+    if (key.variant < 0)
+      return fail(LEM_ERR_UNSUPPORTED, "local box larger than 4096 points (4095 when forced)");
     groups[key].push_back((int)i);
   }
   std::vector<lem::KBlock> out;
@@ -502,7 +515,7 @@ lem_status bucketize(std::vector<lem::KBlock>& kb, std::vector<lem_plan_s::Bucke
       bk.lds = std::max(bk.lds, need[i]);
       if (!g.first.vlds) {
         k.v_off = voff;
-        voff += (int64_t)(k.m + 1) * k.Lx * k.Ly * ns;
+        voff += (int64_t)(k.m + 1 + k.aug) * (k.Lx * k.Ly + k.aug) * ns;
       }
       out.push_back(k);
     }
@@ -630,7 +643,7 @@ lem_status plan_krylov(lem_plan_s* p, hipStream_t st) {
   for (int r = 0; r < nr; ++r) {
     int mm = 0, ss = 0;
     const Box& rb = p->boxes[reps[r]];
-    const int rnloc = (rb.cx + 2 * rb.h) * (op.ndim == 2 ? rb.cy + 2 * rb.h : 1);
+    const int rnloc = (rb.cx + 2 * rb.h) * (op.ndim == 2 ? rb.cy + 2 * rb.h : 1) + (p->forced ? 1 : 0);
     if (!choose_m(&est[(size_t)r * nsc * jl.size()], jl, nsc, o.krylov_tol, o.krylov_m, mcal,
                   op.ndim, rnloc, &mm, &ss))
       return fail(LEM_ERR_NOT_CONVERGED,
@@ -649,7 +662,7 @@ lem_status plan_krylov(lem_plan_s* p, hipStream_t st) {
   for (int i = 0; i < nb; ++i) {
     p->m[i] = rm[rep[i]];
     p->nsub[i] = rs[rep[i]];
-    kb.push_back(make_kblock(p, p->boxes[i], p->m[i], p->nsub[i], p->ns, i));
+    kb.push_back(make_kblock(p, p->boxes[i], p->m[i], p->nsub[i], p->ns, i, p->forced));
   }
   int64_t vw = 0;
   LEM_TRY(bucketize(kb, p->buckets, p->ns, &vw));
@@ -663,7 +676,110 @@ lem_status plan_krylov(lem_plan_s* p, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------- dense ----
-lem_status plan_dense(lem_plan_s* p, hipStream_t st) {
+// exp of the U assembled nl x nl matrices in A (overwritten) into R, by
+// Pade [13/13] with scaling and squaring in float64 (Higham 2005): the powers,
+// both polynomials and the squarings on FP64 MFMA, Q R = P by pivoted LU.
+lem_status dense_expm(lem_plan_s* p, double* A, double* R, int nl, int U, hipStream_t st,
+                      int* smax) {
+  const size_t mat = (size_t)nl * nl * U;
+  double *A2, *A4, *A6, *T, *Ub, *d_norm;
+  int* d_s;
+  LEM_TRY(dalloc(p, &A2, mat));
+  LEM_TRY(dalloc(p, &A4, mat));
+  LEM_TRY(dalloc(p, &A6, mat));
+  LEM_TRY(dalloc(p, &T, mat));
+  LEM_TRY(dalloc(p, &Ub, mat));
+  LEM_TRY(dalloc(p, &d_norm, U));
+  LEM_TRY(dalloc(p, &d_s, U));
+  LEM_HIP(lem::dense_norm1(A, nl, U, d_norm, st));
+  std::vector<double> nrm(U);
+  LEM_HIP(hipMemcpyAsync(nrm.data(), d_norm, U * 8, hipMemcpyDeviceToHost, st));
+  LEM_HIP(hipStreamSynchronize(st));
+  std::vector<int> s(U);
+  for (int u = 0; u < U; ++u) {
+    if (!std::isfinite(nrm[u])) return fail(LEM_ERR_INVALID, "non-finite local operator");
+    s[u] = nrm[u] > lem::kTheta13 ? std::min(60, (int)std::ceil(std::log2(nrm[u] / lem::kTheta13))) : 0;
+    *smax = std::max(*smax, s[u]);
+  }
+  LEM_TRY(upload(d_s, s.data(), U * sizeof(int), st));
+  LEM_HIP(lem::dense_scale_pow2(A, nl, U, d_s, st));
+  LEM_HIP(lem::dense_gemm(A, A, A2, nl, U, st));
+  LEM_HIP(lem::dense_gemm(A2, A2, A4, nl, U, st));
+  LEM_HIP(lem::dense_gemm(A4, A2, A6, nl, U, st));
+  // U = A (A6 (b13 A6 + b11 A4 + b9 A2) + b7 A6 + b5 A4 + b3 A2 + b1 I)
+  LEM_HIP(lem::dense_lincomb(A6, kB[13], A4, kB[11], A2, kB[9], nullptr, 0, 0, T, nl, U, st));
+  LEM_HIP(lem::dense_gemm(A6, T, Ub, nl, U, st));
+  LEM_HIP(lem::dense_lincomb(Ub, 1.0, A6, kB[7], A4, kB[5], A2, kB[3], kB[1], Ub, nl, U, st));
+  LEM_HIP(lem::dense_gemm(A, Ub, T, nl, U, st));  // T = U
+  // V = A6 (b12 A6 + b10 A4 + b8 A2) + b6 A6 + b4 A4 + b2 A2 + b0 I
+  LEM_HIP(lem::dense_lincomb(A6, kB[12], A4, kB[10], A2, kB[8], nullptr, 0, 0, Ub, nl, U, st));
+  LEM_HIP(lem::dense_gemm(A6, Ub, R, nl, U, st));
+  LEM_HIP(lem::dense_lincomb(R, 1.0, A6, kB[6], A4, kB[4], A2, kB[2], kB[0], R, nl, U, st));
+  LEM_HIP(lem::dense_pade_pq(R, T, (int64_t)mat, st));  // R = P, T = Q
+  LEM_HIP(lem::dense_solve(T, R, nl, U, st));           // R = Q^-1 P
+  for (int u = 0; u < U; ++u) {
+    double* src = R + (size_t)u * nl * nl;
+    double* dst = A2 + (size_t)u * nl * nl;
+    for (int q = 0; q < s[u]; ++q) {
+      LEM_HIP(lem::dense_gemm(src, src, dst, nl, 1, st));
+      std::swap(src, dst);
+    }
+    if (src != R + (size_t)u * nl * nl)
+      LEM_HIP(hipMemcpyAsync(R + (size_t)u * nl * nl, src, (size_t)nl * nl * 8,
+                             hipMemcpyDeviceToDevice, st));
+  }
+  LEM_HIP(hipStreamSynchronize(st));
+  for (void* q : {(void*)A2, (void*)A4, (void*)A6, (void*)T, (void*)Ub, (void*)d_norm, (void*)d_s})
+    dfree(p, q);
+  return LEM_OK;
+}
+
+// The forcing term of a dense-method step, phi_1(dt A_M)(dt g_M) on every core,
+// into p->d_bias: phi_1(dt A_M) is the top-right block of the exponential of
+// [[dt A_M, I], [0, 0]]; its core rows are applied to dt g by the apply kernel.
+lem_status dense_forcing_term(lem_plan_s* p, const void* d_ops, const double* host_g,
+                              hipStream_t st) {
+  const Op& op = p->op;
+  const Box& b0 = p->boxes[0];
+  const int Lx = b0.cx + 2 * b0.h, Ly = op.ndim == 2 ? b0.cy + 2 * b0.h : 1;
+  const int nl = Lx * Ly, n2 = 2 * nl;
+  double *Aa, *Ra, *Phi;
+  LEM_TRY(dalloc(p, &Aa, (size_t)n2 * n2));
+  LEM_TRY(dalloc(p, &Ra, (size_t)n2 * n2));
+  LEM_HIP(lem::dense_assemble_aug(d_ops, Aa, nl, 1, st));
+  int sq = 0;
+  LEM_TRY(dense_expm(p, Aa, Ra, n2, 1, st, &sq));
+  dfree(p, Aa);
+  LEM_TRY(dalloc(p, &Phi, (size_t)nl * nl));
+  LEM_HIP(hipMemcpy2DAsync(Phi, (size_t)nl * 8, Ra + nl, (size_t)n2 * 8, (size_t)nl * 8, nl,
+                           hipMemcpyDeviceToDevice, st));
+  dfree(p, Ra);
+  const size_t es = (size_t)p->rows_p * p->cols_p;
+  double *e64, *core, *dtg;
+  float* e32;
+  unsigned short* e16;
+  LEM_TRY(dalloc(p, &e64, es));
+  LEM_TRY(dalloc(p, &e32, es));
+  LEM_TRY(dalloc(p, &e16, es * 3));
+  LEM_TRY(dalloc(p, &core, (size_t)p->rows * nl));
+  LEM_HIP(lem::dense_pack(Phi, nl, Lx, b0.h, b0.cx, op.ndim == 2 ? b0.cy : 1, op.ndim, p->rows,
+                          p->rows_p, p->cols_p, e64, e32, e16, core, st));
+  const size_t tot = (size_t)p->N * p->ns;
+  std::vector<double> hg(tot);
+  for (size_t e = 0; e < tot; ++e) hg[e] = op.dt * host_g[e];
+  LEM_TRY(dalloc(p, &dtg, tot));
+  LEM_TRY(upload(dtg, hg.data(), tot * 8, st));
+  LEM_TRY(dalloc(p, &p->d_bias, tot, &p->bytes_work));
+  LEM_HIP(lem::dense_apply(LEM_FP64, 0, p->d_db, e64, (int64_t)es, core, dtg, p->d_bias, op.n,
+                           op.ndim, p->ns, p->rows, p->rows_p, p->cols, p->cols_p,
+                           (int)p->boxes.size(), nullptr, st));
+  LEM_HIP(hipStreamSynchronize(st));
+  for (void* q : {(void*)Phi, (void*)e64, (void*)e32, (void*)e16, (void*)core, (void*)dtg})
+    dfree(p, q);
+  return LEM_OK;
+}
+
+lem_status plan_dense(lem_plan_s* p, hipStream_t st, const double* host_g) {
   const Op& op = p->op;
   if (op.variable)
     return fail(LEM_ERR_UNSUPPORTED, "stored local exponentials need constant coefficients");
@@ -682,18 +798,10 @@ lem_status plan_dense(lem_plan_s* p, hipStream_t st) {
   p->rows_p = (p->rows + 63) / 64 * 64;
   p->cols_p = (nl + 31) / 32 * 32;
   const size_t mat = (size_t)nl * nl * U;
-  double *A, *A2, *A4, *A6, *T, *Ub, *Vb, *d_norm;
-  int* d_s;
+  double *A, *Vb;
   void* d_ops;
   LEM_TRY(dalloc(p, &A, mat));
-  LEM_TRY(dalloc(p, &A2, mat));
-  LEM_TRY(dalloc(p, &A4, mat));
-  LEM_TRY(dalloc(p, &A6, mat));
-  LEM_TRY(dalloc(p, &T, mat));
-  LEM_TRY(dalloc(p, &Ub, mat));
   LEM_TRY(dalloc(p, &Vb, mat));
-  LEM_TRY(dalloc(p, &d_norm, U));
-  LEM_TRY(dalloc(p, &d_s, U));
   {
     unsigned char* dp;
     LEM_TRY(dalloc(p, &dp, lem::dense_op_size() * U));
@@ -703,43 +811,7 @@ lem_status plan_dense(lem_plan_s* p, hipStream_t st) {
   lem::dense_op_fill(hops.data(), 0, op.w[0], op.w[1], op.w[2], op.w[3], op.w[4], Lx, Ly);
   LEM_TRY(upload(d_ops, hops.data(), hops.size(), st));
   LEM_HIP(lem::dense_assemble(d_ops, A, nl, U, st));
-  LEM_HIP(lem::dense_norm1(A, nl, U, d_norm, st));
-  std::vector<double> nrm(U);
-  LEM_HIP(hipMemcpyAsync(nrm.data(), d_norm, U * 8, hipMemcpyDeviceToHost, st));
-  LEM_HIP(hipStreamSynchronize(st));
-  std::vector<int> s(U);
-  for (int u = 0; u < U; ++u) {
-    if (!std::isfinite(nrm[u])) return fail(LEM_ERR_INVALID, "non-finite local operator");
-    s[u] = nrm[u] > lem::kTheta13 ? std::min(60, (int)std::ceil(std::log2(nrm[u] / lem::kTheta13))) : 0;
-    p->squarings = std::max(p->squarings, s[u]);
-  }
-  LEM_TRY(upload(d_s, s.data(), U * sizeof(int), st));
-  LEM_HIP(lem::dense_scale_pow2(A, nl, U, d_s, st));
-  LEM_HIP(lem::dense_gemm(A, A, A2, nl, U, st));
-  LEM_HIP(lem::dense_gemm(A2, A2, A4, nl, U, st));
-  LEM_HIP(lem::dense_gemm(A4, A2, A6, nl, U, st));
-  // U = A (A6 (b13 A6 + b11 A4 + b9 A2) + b7 A6 + b5 A4 + b3 A2 + b1 I)
-  LEM_HIP(lem::dense_lincomb(A6, kB[13], A4, kB[11], A2, kB[9], nullptr, 0, 0, T, nl, U, st));
-  LEM_HIP(lem::dense_gemm(A6, T, Ub, nl, U, st));
-  LEM_HIP(lem::dense_lincomb(Ub, 1.0, A6, kB[7], A4, kB[5], A2, kB[3], kB[1], Ub, nl, U, st));
-  LEM_HIP(lem::dense_gemm(A, Ub, T, nl, U, st));  // T = U
-  // V = A6 (b12 A6 + b10 A4 + b8 A2) + b6 A6 + b4 A4 + b2 A2 + b0 I
-  LEM_HIP(lem::dense_lincomb(A6, kB[12], A4, kB[10], A2, kB[8], nullptr, 0, 0, Ub, nl, U, st));
-  LEM_HIP(lem::dense_gemm(A6, Ub, Vb, nl, U, st));
-  LEM_HIP(lem::dense_lincomb(Vb, 1.0, A6, kB[6], A4, kB[4], A2, kB[2], kB[0], Vb, nl, U, st));
-  LEM_HIP(lem::dense_pade_pq(Vb, T, (int64_t)mat, st));  // Vb = P, T = Q
-  LEM_HIP(lem::dense_solve(T, Vb, nl, U, st));           // Vb = Q^-1 P
-  for (int u = 0; u < U; ++u) {
-    double* src = Vb + (size_t)u * nl * nl;
-    double* dst = A2 + (size_t)u * nl * nl;
-    for (int q = 0; q < s[u]; ++q) {
-      LEM_HIP(lem::dense_gemm(src, src, dst, nl, 1, st));
-      std::swap(src, dst);
-    }
-    if (src != Vb + (size_t)u * nl * nl)
-      LEM_HIP(hipMemcpyAsync(Vb + (size_t)u * nl * nl, src, (size_t)nl * nl * 8,
-                             hipMemcpyDeviceToDevice, st));
-  }
+  LEM_TRY(dense_expm(p, A, Vb, nl, U, st, &p->squarings));
   const size_t es = (size_t)p->rows_p * p->cols_p;
   LEM_TRY(dalloc(p, &p->d_e64, es * U, &p->bytes_blocks));
   LEM_TRY(dalloc(p, &p->d_e32, es * U, &p->bytes_blocks));
@@ -755,9 +827,8 @@ lem_status plan_dense(lem_plan_s* p, hipStream_t st) {
                             p->d_e32 + u * es, (unsigned short*)p->d_e16 + u * es * 3,
                             p->d_core + (size_t)u * p->rows * nl, st));
   LEM_HIP(hipStreamSynchronize(st));
-  for (void* q : {(void*)A, (void*)A2, (void*)A4, (void*)A6, (void*)T, (void*)Ub, (void*)Vb,
-                  (void*)d_norm, (void*)d_s, d_ops})
-    dfree(p, q);
+  for (void* q : {(void*)A, (void*)Vb}) dfree(p, q);
+  // (d_ops is kept until the forcing term is built)
   // block table
   const int nb = (int)p->boxes.size();
   std::vector<unsigned char> db(lem::dense_block_size() * nb);
@@ -772,6 +843,8 @@ lem_status plan_dense(lem_plan_s* p, hipStream_t st) {
     p->d_db = d;
   }
   LEM_TRY(upload(p->d_db, db.data(), db.size(), st));
+  if (p->forced) LEM_TRY(dense_forcing_term(p, d_ops, host_g, st));
+  dfree(p, d_ops);
   // default tile shape of the apply kernel (the autotuner may replace it)
   p->tile = p->opt.precision == LEM_FP32 ? 2 : p->opt.precision == LEM_FP64 ? 0 : (p->rows_p >= 256 ? 1 : 0);
   return LEM_OK;
@@ -786,9 +859,13 @@ const void* dense_operand(const lem_plan_s* p) {
 }
 
 // --------------------------------------------------------------- global ----
-lem_status alloc_global(lem_plan_s* p, int m, int ns, int nsub, lem::GlobalWork* w) {
+lem_status alloc_global(lem_plan_s* p, int m, int ns, int nsub, lem::GlobalWork* w,
+                        bool forced = false) {
   const Op& op = p->op;
   w->N = op.N();
+  w->force = forced ? p->d_force : nullptr;
+  w->gscale = op.dt / nsub;
+  w->xa = w->ya = nullptr;
   w->ns = ns; w->n = op.n; w->ndim = op.ndim; w->m = m; w->nsub = nsub;
   const double sc = 1.0 / nsub;
   for (int q = 0; q < 5; ++q) w->w[q] = op.w[q] * sc;
@@ -797,9 +874,13 @@ lem_status alloc_global(lem_plan_s* p, int m, int ns, int nsub, lem::GlobalWork*
   w->muy = op.variable ? p->d_coef + op.N() : nullptr;
   w->tol = p->opt.krylov_tol;
   w->status = p->d_status;
-  const int64_t tot = w->N * ns;
+  const int64_t tot = (w->N + (forced ? 1 : 0)) * ns;  // plus the augmented coordinate
   const int G = lem::global_grid(tot, ns);
   const int K = lem::kMaxKrylov + 1;
+  if (forced) {
+    LEM_TRY(dalloc(p, &w->xa, (size_t)tot, &p->bytes_work));
+    LEM_TRY(dalloc(p, &w->ya, (size_t)tot, &p->bytes_work));
+  }
   LEM_TRY(dalloc(p, &w->V, (size_t)(m + 1) * tot, &p->bytes_work));
   LEM_TRY(dalloc(p, &w->W, (size_t)tot, &p->bytes_work));
   LEM_TRY(dalloc(p, &w->Wt, (size_t)tot, &p->bytes_work));
@@ -820,8 +901,8 @@ lem_status alloc_global(lem_plan_s* p, int m, int ns, int nsub, lem::GlobalWork*
 void free_global(lem_plan_s* p, lem::GlobalWork* w) {
   for (void* q : {(void*)w->V, (void*)w->W, (void*)w->Wt, (void*)w->part, (void*)w->h1,
                   (void*)w->h2, (void*)w->hn, (void*)w->H, (void*)w->f, (void*)w->beta,
-                  (void*)w->inv, (void*)w->est, (void*)w->estsum})
-    dfree(p, q);
+                  (void*)w->inv, (void*)w->est, (void*)w->estsum, (void*)w->xa, (void*)w->ya})
+    if (q) dfree(p, q);
 }
 
 lem_status plan_global(lem_plan_s* p, hipStream_t st) {
@@ -875,7 +956,7 @@ lem_status plan_global(lem_plan_s* p, hipStream_t st) {
     return fail(LEM_ERR_NOT_CONVERGED, "no global Krylov dimension/sub-step pair meets krylov_tol");
   p->m.assign(1, mm);
   p->nsub.assign(1, ss);
-  LEM_TRY(alloc_global(p, mm, p->ns, ss, &p->gw));
+  LEM_TRY(alloc_global(p, mm, p->ns, ss, &p->gw, p->forced));
   return LEM_OK;
 }
 
@@ -889,7 +970,7 @@ lem_status run_one(lem_plan_s* p, const double* src, double* dst, hipStream_t st
       const int64_t es = (int64_t)p->rows_p * p->cols_p;
       LEM_HIP(lem::dense_apply(p->opt.precision, p->tile, p->d_db, dense_operand(p), es, p->d_core,
                                src, dst, p->op.n, p->op.ndim, p->ns, p->rows, p->rows_p, p->cols,
-                               p->cols_p, (int)p->boxes.size(), st));
+                               p->cols_p, (int)p->boxes.size(), p->d_bias, st));
       return LEM_OK;
     }
     default:
@@ -1020,7 +1101,13 @@ lem_status create_plan(const lem_operator* op, double dt, const lem_options* opt
   lem_status s = build_op(op, dt, &p->op);
   if (s != LEM_OK) return guard(s);
   p->N = p->op.N();
-  if (p->method == LEM_METHOD_GLOBAL && p->N <= 4096 && p->opt.krylov_m_max <= lem::krylov_lds_max_m()) {
+  p->forced = op->forcing != nullptr;
+  if (p->forced) {
+    for (int64_t e = 0; e < p->N * p->ns; ++e)
+      if (!std::isfinite(op->forcing[e])) return guard(fail(LEM_ERR_INVALID, "forcing must be finite"));
+  }
+  if (p->method == LEM_METHOD_GLOBAL && p->N + (p->forced ? 1 : 0) <= 4096 &&
+      p->opt.krylov_m_max <= lem::krylov_lds_max_m()) {
     // the whole grid fits one box: the global method is the Krylov step on
     // a single box that keeps the periodic coupling (D = 1)
     p->global_box = true;
@@ -1044,8 +1131,13 @@ lem_status create_plan(const lem_operator* op, double dt, const lem_options* opt
       s = dalloc(p, &p->d_tmp, (size_t)p->N * p->ns, &p->bytes_work);
       if (s != LEM_OK) return guard(s);
     }
+    if (p->forced) {
+      s = dalloc(p, &p->d_force, (size_t)p->N * p->ns, &p->bytes_work);
+      if (s == LEM_OK) s = upload(p->d_force, op->forcing, (size_t)p->N * p->ns * 8, st);
+      if (s != LEM_OK) return guard(s);
+    }
     if (p->method == LEM_METHOD_KRYLOV || p->global_box) s = plan_krylov(p, st);
-    else if (p->method == LEM_METHOD_DENSE) s = plan_dense(p, st);
+    else if (p->method == LEM_METHOD_DENSE) s = plan_dense(p, st, op->forcing);
     else s = plan_global(p, st);
     if (s != LEM_OK) return guard(s);
     if (p->method == LEM_METHOD_DENSE && opt->autotune && p->ns % 64 == 0) {
@@ -1460,6 +1552,7 @@ lem_status lem_server_submit(lem_server_t s, const lem_operator* op, double dt, 
                              const double* x0_host, uint64_t* id) {
   if (!s || !op || !x0_host || !id) return fail(LEM_ERR_INVALID, "NULL argument");
   if (n_steps < 1) return fail(LEM_ERR_INVALID, "n_steps must be >= 1");
+  if (op->forcing) return fail(LEM_ERR_UNSUPPORTED, "served requests take no forcing");
   Op chk;
   LEM_TRY(build_op(op, dt, &chk));
   ServerReq r;

@@ -16,7 +16,7 @@ hipError_t launch_krylov_estimates(const double* calib, const int* mcal, const i
 hipError_t launch_probe_fill(double* x, int64_t n, uint64_t seed, hipStream_t st);
 
 // ---- Krylov LEM step (krylov_lem.hip)
-size_t krylov_lds_bytes(int nt, int m, int nloc, bool vlds);
+size_t krylov_lds_bytes(int nt, int m, int nloc, bool vlds, int aug);
 int krylov_lds_max_m();
 void krylov_lds_config(int ndim, int nloc, int* nt, int* pmax);
 hipError_t launch_krylov_lds(const KBlock* blocks, int n_blocks, int ns, int nt, int pmax,
@@ -29,6 +29,7 @@ size_t dense_op_size();
 void dense_op_fill(void* dst, int i, double w0, double wW, double wE, double wS, double wN,
                    int Lx, int Ly);
 hipError_t dense_assemble(const void* ops, double* A, int nl, int nu, hipStream_t st);
+hipError_t dense_assemble_aug(const void* ops, double* A, int nl, int nu, hipStream_t st);
 hipError_t dense_norm1(const double* A, int nl, int nu, double* norms, hipStream_t st);
 hipError_t dense_scale_pow2(double* A, int nl, int nu, const int* s, hipStream_t st);
 hipError_t dense_gemm(const double* A, const double* B, double* C, int nl, int nu,
@@ -50,7 +51,7 @@ constexpr int kApplyConfigs = 4;
 hipError_t dense_apply(int precision, int cfg, const void* blocks, const void* E,
                        int64_t e_stride, const double* core, const double* x_in, double* x_out,
                        int n, int ndim, int ns, int rows, int rows_p, int cols, int cols_p,
-                       int n_blocks, hipStream_t st);
+                       int n_blocks, const double* bias, hipStream_t st);
 
 // ---- global Krylov (global_krylov.hip)
 struct GlobalWork {
@@ -63,6 +64,11 @@ struct GlobalWork {
   double *V, *W, *Wt, *part, *h1, *h2, *hn, *H, *f, *beta, *inv, *est, *estsum;
   double tol;
   int* status;
+  // forced steps (force != null): dt_sub scale of the forcing, and the
+  // augmented input/output states ((N + 1) x ns each)
+  const double* force;
+  double gscale;
+  double *xa, *ya;
 };
 int global_grid(int64_t total, int ns);
 size_t global_part_doubles(int G, int ns);

@@ -248,3 +248,100 @@ def test_graph_replays_match_eager_bitwise():
         _ = (x * 2).sum().item()  # eager work between replays
         torch.cuda.synchronize()
         assert torch.equal(out, ref), rep
+
+
+# --------------------------------------------------------------- forcing --
+# du/dt = A u + g, g constant in time: update (5) of section 3 with g_M,
+# exp(dt A_M) v + phi_1(dt A_M)(dt g_M) on every region.
+
+def _forcing(p, ns, seed):
+    rng = np.random.default_rng(seed)
+    x = np.arange(p.n) / p.n
+    cols = []
+    for _ in range(ns):
+        kx, ky = rng.integers(1, 4, size=2)
+        ph = rng.uniform(0, 2 * np.pi)
+        if p.ndim == 1:
+            f = np.cos(2 * np.pi * kx * x + ph) + 0.5
+        else:
+            X, Y = np.meshgrid(x, x)
+            f = (np.cos(2 * np.pi * (kx * X + ky * Y) + ph) + 0.5).reshape(-1)
+        cols.append(f)
+    return np.column_stack(cols)
+
+
+def _forced_op(p, g):
+    o = lem.Operator.from_problem(p)
+    return lem.Operator(o.ndim, o.n, o.dx, o.vel, o.nu, o.nu_field, forcing=g)
+
+
+@pytest.mark.parametrize("case", ["1d", "2d64"])
+def test_forced_dense_matches_oracle(case):
+    if case == "1d":
+        p, ns, core, halo, steps = L.workload_1d(n=256), 1, 64, 16, 20
+    else:
+        p, ns, core, halo, steps = L.workload_2d_ensemble(n=64, n_states=64), 64, 16, 6, 3
+    g = _forcing(p, ns, 5)
+    plan = lem.Plan(_forced_op(p, g), p.dt, method="dense", core=core, halo=halo, n_states=ns)
+    boxes = check_maps(plan, p.ndim, p.n)
+    got = run(plan, p.states, steps)
+    want = oracle_lem(p, boxes, p.states, steps, dtg=p.dt * g)
+    assert rel_l2(got.reshape(want.shape), want) <= 1e-12
+
+
+def test_forced_krylov_matches_oracle():
+    p = L.workload_1d(n=256)
+    g = _forcing(p, 1, 6)
+    plan = lem.Plan(_forced_op(p, g), p.dt, method="krylov", core=64, halo=16, krylov_tol=1e-14)
+    boxes = check_maps(plan, 1, p.n)
+    got = run(plan, p.states, 10)
+    want = oracle_lem(p, boxes, p.states[:, 0], 10, dtg=p.dt * g[:, 0])
+    assert rel_l2(got[:, 0], want) <= 1e-12
+    assert plan.query()["device_status"] == 0
+
+
+@pytest.mark.parametrize("core,halo,m", [(16, 8, 30), (16, 6, 12)])
+def test_forced_krylov_variable_nu_streamed_and_lds(core, halo, m):
+    p = L.workload_2d_variable(n=64)
+    g = _forcing(p, 1, 7)
+    plan = lem.Plan(_forced_op(p, g), p.dt, method="krylov", core=core, halo=halo,
+                    krylov_m=m, krylov_m_max=m, max_substeps=8, krylov_tol=1e-13)
+    boxes = check_maps(plan, 2, p.n)
+    got = run(plan, p.states, 2)
+    want = oracle_lem(p, boxes, p.states, 2, krylov_above=300, krylov_tol=1e-16,
+                      dtg=p.dt * g)
+    assert rel_l2(got, want) <= 1e-12
+    assert plan.query()["device_status"] == 0
+
+
+def test_forced_global_box_and_whole_grid_vs_fourier():
+    # 1D n = 1024 runs as one periodic Krylov box; 2D 128^2 on whole-grid kernels
+    for p, ns in [(L.workload_1d(), 1), (L.workload_2d_ensemble(n=128, n_states=2), 2)]:
+        g = _forcing(p, ns, 8)
+        plan = lem.Plan(_forced_op(p, g), p.dt, method="global", n_states=ns, krylov_tol=1e-14)
+        got = run(plan, p.states, 2)
+        W = op.from_problem(p)
+        want = ge.fft_steps(W, p.states, 2, p.dt * g)
+        assert rel_l2(got.reshape(want.shape), want) <= 1e-12
+
+
+def test_forced_graph_replay_and_steady_state():
+    # g = -A u* keeps u* fixed under the global step; LEM keeps it to within
+    # the truncation of the regions; graph replays equal eager steps bitwise
+    p = L.workload_2d_ensemble(n=64, n_states=64)
+    W = op.from_problem(p)
+    us = p.states
+    g = -op.apply(W, us) / p.dt
+    fop = _forced_op(p, np.ascontiguousarray(g))
+    ge_plan = lem.Plan(fop, p.dt, method="global", n_states=64, krylov_tol=1e-14)
+    assert rel_l2(run(ge_plan, us, 3), us) <= 1e-12
+    eager = lem.Plan(fop, p.dt, method="dense", core=16, halo=12, n_states=64)
+    graph = lem.Plan(fop, p.dt, method="dense", core=16, halo=12, n_states=64, use_graph=True)
+    a = run(eager, us, 4)
+    x = dev(us)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        graph.step(x, y, 4)
+    torch.cuda.synchronize()
+    assert np.array_equal(y.cpu().numpy().reshape(a.shape), a)
+    assert rel_l2(a, us) <= 1e-6
