@@ -115,10 +115,11 @@ def parse_args():
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run one device copy of this many MiB (a reference kernel of "
                          "known traffic for scaling HBM counters)")
-    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2", "c3", "c4"],
+    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2", "c3", "c4", "f1"],
                     help="c1 (default): 256^2 x 64 states, dense FP64; c0: 1D 1024; "
                          "c2: 1024^2 lognormal nu, uneven Krylov; c3: 512^2 x 128 states, "
-                         "mixed precision; c4: served Poisson stream")
+                         "mixed precision; c4: served Poisson stream; f1: c1 with a "
+                         "constant source g (exponential-Euler step with forcing)")
     ap.add_argument("--requests", type=int, default=300)
     return ap.parse_args()
 
@@ -131,7 +132,7 @@ def main() -> int:
               "which is not implemented here)", file=sys.stderr)
         return 2
     fn = {"c1": bench_c1, "c0": bench_c0, "c2": bench_c2, "c3": bench_c3,
-          "c4": bench_c4}[args.workload]
+          "c4": bench_c4, "f1": bench_f1}[args.workload]
     out = fn(args)
     print(json.dumps(out), flush=True)
     return 0
@@ -268,6 +269,70 @@ def _line(args, workload: dict, value, unit, steps, wall, dtype, extras, rooflin
             "higher_is_better": higher, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
             "data": "synthetic", "config": workload, "roofline": roofline, "cpu_baseline": None,
             "extras": extras}
+
+
+def bench_f1(args) -> dict:
+    """256^2 x 64 states of du/dt = A u + g with a constant smooth source per
+    state: the exponential-Euler update (5) with g_M on every region (dense,
+    FP64), against the forced global Krylov step on the same GPU."""
+    import torch
+    import lem_inputs as L
+    import paper_1505_02248_amd as lem
+    torch.cuda.init()
+    p = L.workload_2d_ensemble()
+    ns = p.states.shape[1]
+    g = L.source_fields_2d(p.n, ns, seed=9)
+    base = lem.Operator.from_problem(p)
+    opr = lem.Operator(base.ndim, base.n, base.dx, base.vel, base.nu, base.nu_field, forcing=g)
+    N = p.N
+    x = torch.from_numpy(p.states.copy()).to("cuda")
+    y = torch.empty_like(x)
+    log("planning forced LEM (dense, fp64, decay-bound halo)")
+    plan = lem.Plan(opr, p.dt, method="dense", core=16, halo=0, halo_min=4, halo_max=32,
+                    halo_tol=args.halo_tol, n_states=ns, autotune=True)
+    q = plan.query()
+    h = q["halo_max"]
+    nloc = (16 + 2 * h) ** 2
+    plan.step(x, y, args.warmup)
+    torch.cuda.synchronize()
+    wall, ev_ms = timed_steps(plan, x, y, args.steps, torch)
+    value = N * ns * args.steps / wall
+    kern_ms = ev_ms / args.steps
+    flops = 2.0 * nloc * N * ns
+    achieved = flops / (kern_ms * 1e-3) / 1e12
+    extras = {}
+    if not args.no_global:
+        ref_plan = lem.Plan(opr, p.dt, method="global", n_states=ns, krylov_tol=1e-13)
+        k = args.acc_steps
+        gref = torch.empty_like(x)
+        ref_plan.step(x, gref, k)
+        yl = torch.empty_like(x)
+        plan.step(x, yl, k)
+        torch.cuda.synchronize()
+        extras["lem_vs_global_rel_l2"] = (torch.linalg.norm(yl - gref) / torch.linalg.norm(gref)).item()
+        extras["acc_steps"] = k
+        gplan = lem.Plan(opr, p.dt, method="global", n_states=ns, krylov_tol=1e-8)
+        gq = gplan.query()
+        gplan.step(x, gref, 1)
+        gw, _ = timed_steps(gplan, x, gref, args.global_steps, torch)
+        gval = N * ns * args.global_steps / gw
+        extras["global_krylov"] = {"value": gval, "ms_per_step": 1e3 * gw / args.global_steps,
+                                   "m": gq["m_max"], "substeps": gq["substeps_max"]}
+        extras["lem_over_global"] = value / gval
+    log(f"forced LEM h={h}: {value:.3e} DOF-steps/s, {kern_ms * 1e3:.1f} us/step, "
+        f"{achieved:.1f} TFLOP/s; {extras}")
+    workload = {"workload": "2D 256x256 periodic advection-diffusion with a constant smooth "
+                            "source per state (du/dt = A u + g), velocity (1,0.5), nu=1e-3, "
+                            "dt=2dx, 64 states, 16x16 cores, exponential-Euler LEM step with "
+                            "stored exp and phi_1 terms (fp64)",
+                "grid": [p.n, p.n], "n_states": ns, "core": 16, "halo": h,
+                "halo_rule": f"decay bound {args.halo_tol:g}/step", "n_loc": nloc,
+                "plan_ms": q["plan_ms"], "tile_config": q["tile_config"]}
+    roof = {"bound": "mfma", "achieved": achieved, "peak": MFMA_FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / MFMA_FP64_PEAK_TFLOPS, "traffic": None,
+            "kernel": "apply_mfma_kernel<double> (with the forcing term)",
+            "flops_per_launch": flops, "us_per_launch": kern_ms * 1e3}
+    return _line(args, workload, value, "DOF-steps/s", args.steps, wall, "f64", extras, roof)
 
 
 def bench_c0(args) -> dict:

@@ -105,6 +105,14 @@ def smooth_states_2d(n: int, n_states: int, seed: int, n_modes: int = 16,
     return out
 
 
+def source_fields_2d(n: int, n_states: int, seed: int, n_modes: int = 4, kmax: int = 4,
+                     mean: float = 0.5) -> np.ndarray:
+    """Sources g for du/dt = A u + g: per state, ``mean`` plus a unit-RMS sum of
+    ``n_modes`` smooth cosines (wavevectors in [-kmax, kmax]^2), drawn like
+    smooth_states_2d.  Returns shape (n*n, n_states)."""
+    return mean + smooth_states_2d(n, n_states, seed, n_modes=n_modes, kmax=kmax)
+
+
 def white_noise_states(N: int, n_states: int, seed: int) -> np.ndarray:
     """iid N(0,1) states, shape (N, n_states) (rough stress inputs)."""
     rng = np.random.default_rng(seed)

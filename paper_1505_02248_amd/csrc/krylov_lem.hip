@@ -289,7 +289,7 @@ typedef __attribute__((address_space(1))) double gdouble;
 // One workgroup per (region, ensemble member).  VLDS: basis in LDS; else in
 // a per-block slice of device memory (read through the L2).  Points per
 // thread P; up to 8 points keep their stencil weights in registers.
-template <int NT, int P, bool VLDS>
+template <int NT, int P, bool VLDS, bool AUG>
 __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
   constexpr int CH = P >= 16 ? 2 : (P >= 8 ? 2 : (P >= 4 ? 4 : 8));  // rows per chunk
   constexpr int CHS = CH;  // rows per load batch of the streamed sweeps
@@ -302,14 +302,14 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
   const int m = b.m;
   const int mp = m <= 16 ? 16 : 32;
   const int nloc = b.Lx * b.Ly;   // points of the box
-  const int nlv = nloc + b.aug;    // basis row length (plus the augmented coordinate)
+  const int nlv = nloc + (AUG ? 1 : 0);  // basis row length (plus the augmented coordinate)
   int64_t oh, ored, oe;
-  lds_layout(NT, m, VLDS ? nlv : 0, b.aug, &oh, &ored, &oe);
+  lds_layout(NT, m, VLDS ? nlv : 0, AUG ? 1 : 0, &oh, &ored, &oe);
   VPtr V;
   if constexpr (VLDS) {
     V = smem;
   } else {
-    double* g = (b.vwork ? b.vwork : a.vwork + b.v_off) + (int64_t)s * (m + 1 + b.aug) * nlv;
+    double* g = (b.vwork ? b.vwork : a.vwork + b.v_off) + (int64_t)s * (m + 1 + (AUG ? 1 : 0)) * nlv;
     V = (VPtr)g;
   }
   double* H = smem + oh;
@@ -371,7 +371,7 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
       wS = fma(ms, sc, b.chy);
       wN = fma(mn, sc, -b.chy);
     }
-    if (!live[p] || li[p] == nloc) w0 = wW = wE = wS = wN = 0.0;  // the augmented row is zero
+    if (!live[p] || (AUG && li[p] == nloc)) w0 = wW = wE = wS = wN = 0.0;  // augmented row: zero
     if (!b.periodic) {
       if (lx == 0) wW = 0.0;
       if (lx == b.Lx - 1) wE = 0.0;
@@ -383,7 +383,7 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
   // Forced steps: the augmented column dt_sub g_M (zero on the augmented
   // row) is kept as row m+1 of the basis storage, written once here.
   VPtr Fcol = V + (int64_t)(m + 1) * nlv;
-  if (b.aug) {
+  if constexpr (AUG) {
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       if (!live[p]) continue;
@@ -427,7 +427,7 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
   };
   // forced steps: w += (augmented column) x (augmented coordinate of row j)
   auto add_forcing = [&](int j, double (&w)[P]) __attribute__((always_inline)) {
-    if (!b.aug) return;
+    if constexpr (!AUG) return;
     const double ve = V[(int64_t)j * nlv + nloc];
 #pragma unroll
     for (int p = 0; p < P; ++p) w[p] = fma(Fcol[li[p]], ve, w[p]);
@@ -439,7 +439,7 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
     int lx, ly;
     coords(p, lx, ly);
     cur[p] = !live[p] ? 0.0
-             : li[p] == nloc ? 1.0  // the augmented coordinate starts (and stays) at 1
+             : (AUG && li[p] == nloc) ? 1.0  // the augmented coordinate starts (and stays) at 1
                              : x_in[b.x_off + gather_index(b, lx, ly) * b.ns + s];
   }
 
@@ -872,9 +872,9 @@ void krylov_lds_config(int ndim, int nloc, int* nt, int* pmax) {
   *nt = 0; *pmax = 0;  // larger boxes would spill registers: not supported
 }
 
-template <int NT, int P, bool VLDS>
+template <int NT, int P, bool VLDS, bool AUG>
 static hipError_t launch_l(const KrylovArgs& a, int ns, size_t lds, hipStream_t st) {
-  auto fn = krylov_lds_kernel<NT, P, VLDS>;
+  auto fn = krylov_lds_kernel<NT, P, VLDS, AUG>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)fn,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -884,26 +884,33 @@ static hipError_t launch_l(const KrylovArgs& a, int ns, size_t lds, hipStream_t 
   return hipGetLastError();
 }
 
+template <bool AUG>
+static hipError_t launch_shape(const KrylovArgs& a, int ns, int nt, int pmax, bool vlds,
+                               size_t lds, hipStream_t st) {
+  if (vlds) {
+    if (nt == 64 && pmax == 2) return launch_l<64, 2, true, AUG>(a, ns, lds, st);
+    if (nt == 64 && pmax == 8) return launch_l<64, 8, true, AUG>(a, ns, lds, st);
+    if (nt == 256 && pmax == 4) return launch_l<256, 4, true, AUG>(a, ns, lds, st);
+    if (nt == 256 && pmax == 8) return launch_l<256, 8, true, AUG>(a, ns, lds, st);
+    return hipErrorInvalidValue;
+  }
+  if (nt == 64 && pmax == 2) return launch_l<64, 2, false, AUG>(a, ns, lds, st);
+  if (nt == 64 && pmax == 8) return launch_l<64, 8, false, AUG>(a, ns, lds, st);
+  if (nt == 256 && pmax == 4) return launch_l<256, 4, false, AUG>(a, ns, lds, st);
+  if (nt == 256 && pmax == 8) return launch_l<256, 8, false, AUG>(a, ns, lds, st);
+  if (nt == 256 && pmax == 16) return launch_l<256, 16, false, AUG>(a, ns, lds, st);
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_krylov_lds(const KBlock* blocks, int n_blocks, int ns, int nt, int pmax,
                              bool vlds, size_t lds, const double* x_in, double* x_out,
                              const double* coef, double* vwork, double* diag, int* status,
-                             double* calib, int mode, hipStream_t st) {
+                             double* calib, int mode, bool aug, hipStream_t st) {
   KrylovArgs a{blocks, x_in, x_out, coef, vwork, diag, status, calib, mode, n_blocks};
   if (n_blocks == 0) return hipSuccess;
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  if (vlds) {
-    if (nt == 64 && pmax == 2) return launch_l<64, 2, true>(a, ns, lds, st);
-    if (nt == 64 && pmax == 8) return launch_l<64, 8, true>(a, ns, lds, st);
-    if (nt == 256 && pmax == 4) return launch_l<256, 4, true>(a, ns, lds, st);
-    if (nt == 256 && pmax == 8) return launch_l<256, 8, true>(a, ns, lds, st);
-    return hipErrorInvalidValue;
-  }
-  if (nt == 64 && pmax == 2) return launch_l<64, 2, false>(a, ns, lds, st);
-  if (nt == 64 && pmax == 8) return launch_l<64, 8, false>(a, ns, lds, st);
-  if (nt == 256 && pmax == 4) return launch_l<256, 4, false>(a, ns, lds, st);
-  if (nt == 256 && pmax == 8) return launch_l<256, 8, false>(a, ns, lds, st);
-  if (nt == 256 && pmax == 16) return launch_l<256, 16, false>(a, ns, lds, st);
-  return hipErrorInvalidValue;
+  return aug ? launch_shape<true>(a, ns, nt, pmax, vlds, lds, st)
+             : launch_shape<false>(a, ns, nt, pmax, vlds, lds, st);
 }
 
 }  // namespace lem

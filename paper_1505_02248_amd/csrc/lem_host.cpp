@@ -473,12 +473,13 @@ LaunchKey launch_key(int ndim, int nloc, int m, size_t* lds, int aug = 0) {
   lem::krylov_lds_config(ndim, nloc, &nt, &pm);
   if (nt == 0 || m > lem::krylov_lds_max_m()) return {-1, 0, 0, false};
   const size_t with_v = lem::krylov_lds_bytes(nt, m, nloc, true, aug);
+  const int variant = aug ? 2 : 1;  // 2: kernels with the augmented coordinate
   if (pm <= 8 && with_v <= 160 * 1024) {
     *lds = with_v;
-    return {1, nt, pm, true};
+    return {variant, nt, pm, true};
   }
   *lds = lem::krylov_lds_bytes(nt, m, nloc, false, aug);
-  return {1, nt, pm, false};
+  return {variant, nt, pm, false};
 }
 
 // Relative cost of one block step with Krylov dimension m and nsub sub-steps:
@@ -533,7 +534,7 @@ lem_status launch_buckets(const lem_plan_s* p, const lem::KBlock* d_kb,
   for (const auto& b : bks) {
     hipError_t e = lem::launch_krylov_lds(d_kb + b.first, b.count, ns, b.nt, b.pmax, b.vlds,
                                           b.lds, src, dst, p->d_coef, vwork, diag, p->d_status,
-                                          calib, mode, st);
+                                          calib, mode, b.variant == 2, st);
     if (e != hipSuccess)
       return fail(LEM_ERR_HIP, std::string("Krylov launch: ") + hipGetErrorString(e));
   }
@@ -1645,7 +1646,7 @@ lem_status lem_server_tick(lem_server_t s, int32_t* n_active, int32_t* n_queued)
       hipError_t e = lem::launch_krylov_lds(s->d_table + off, nb, 1, g.first.nt, g.first.pmax,
                                             g.first.vlds, lds[g.first], nullptr, nullptr,
                                             nullptr, nullptr, s->d_diag, s->d_status, nullptr, 0,
-                                            s->st);
+                                            false, s->st);
       if (e != hipSuccess)
         return fail(LEM_ERR_HIP, std::string("serving launch: ") + hipGetErrorString(e));
       off += g.second.size();

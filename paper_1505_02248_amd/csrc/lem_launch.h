@@ -22,7 +22,7 @@ void krylov_lds_config(int ndim, int nloc, int* nt, int* pmax);
 hipError_t launch_krylov_lds(const KBlock* blocks, int n_blocks, int ns, int nt, int pmax,
                              bool vlds, size_t lds, const double* x_in, double* x_out,
                              const double* coef, double* vwork, double* diag, int* status,
-                             double* calib, int mode, hipStream_t st);
+                             double* calib, int mode, bool aug, hipStream_t st);
 
 // ---- dense local exponentials (dense.hip)
 size_t dense_op_size();
