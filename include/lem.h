@@ -168,8 +168,8 @@ lem_status lem_step(lem_plan_t plan, const double* x_in, double* x_out,
                     int32_t n_steps, void* stream);
 
 /* y = exp(t A) x on the whole grid (no decomposition) by the Krylov method
- * of section 4.3, for n_states ensemble members; device arrays, may not
- * overlap.  Allocates and frees its own work space (a plan with
+ * of section 4.3, for n_states ensemble members (with op->forcing set:
+ * y = exp(t A) x + phi_1(t A)(t g)); device arrays, may not overlap.  Allocates and frees its own work space (a plan with
  * LEM_METHOD_GLOBAL avoids that for repeated use).  Synchronous. */
 lem_status lem_global_expmv(const lem_operator* op, double t, const double* x,
                             double* y, int32_t n_states, double tol,
