@@ -1350,6 +1350,12 @@ struct lem_server_s {
   lem_server_options opt{};
   hipStream_t st = nullptr;
   bool own_stream = false;
+  // Requests served by the whole-grid global method are chains of small
+  // dependent launches; independent requests run on side streams (default
+  // priority) so that their chains overlap.
+  static constexpr int kSide = 4;
+  hipStream_t side[kSide] = {};
+  hipEvent_t ev_fork = nullptr, ev_join[kSide] = {};
   char* pool = nullptr;
   lem::Arena* arena = nullptr;
   std::deque<uint64_t> queue;
@@ -1379,6 +1385,11 @@ struct lem_server_s {
       hipFree(d_diag);
       hipFree(d_status);
       hipHostFree(h_table);
+      for (int k = 0; k < kSide; ++k) {
+        if (side[k]) hipStreamDestroy(side[k]);
+        if (ev_join[k]) hipEventDestroy(ev_join[k]);
+      }
+      if (ev_fork) hipEventDestroy(ev_fork);
       if (own_stream) hipStreamDestroy(st);
     }
     delete arena;
@@ -1538,6 +1549,14 @@ lem_status lem_server_create(const lem_server_options* opt, void* stream, lem_se
       return fail(LEM_ERR_NOMEM, "could not reserve the serving pool");
     }
     s->arena = new lem::Arena(s->pool, opt->hbm_budget);
+    bool ok = hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming) == hipSuccess;
+    for (int k = 0; ok && k < lem_server_s::kSide; ++k)
+      ok = hipStreamCreateWithFlags(&s->side[k], hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&s->ev_join[k], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+      delete s;
+      return fail(LEM_ERR_HIP, "could not create the serving side streams");
+    }
     if (hipMalloc(&s->d_status, sizeof(int)) != hipSuccess ||
         hipMemsetAsync(s->d_status, 0, sizeof(int), s->st) != hipSuccess ||
         server_grow(s, 4096) != LEM_OK) {
@@ -1610,13 +1629,17 @@ lem_status lem_server_tick(lem_server_t s, int32_t* n_active, int32_t* n_queued)
     LEM_TRY(server_grow(s, nb));
     std::map<LaunchKey, std::vector<lem::KBlock>> groups;
     std::map<LaunchKey, size_t> lds;
-    int diag = 0;
+    int diag = 0, n_side = 0;
+    LEM_HIP(hipEventRecord(s->ev_fork, s->st));  // states uploaded at admission
     for (uint64_t id : s->active) {
       ServerReq& r = s->reqs[id];
       double* in = r.buf[r.done & 1];
       double* out = r.buf[(r.done + 1) & 1];
       if (r.plan->kb_host.empty()) {  // whole-grid Krylov launches of its own
-        LEM_TRY(run_step(r.plan, in, out, s->st));
+        hipStream_t ss = s->side[n_side % lem_server_s::kSide];
+        if (n_side < lem_server_s::kSide) LEM_HIP(hipStreamWaitEvent(ss, s->ev_fork, 0));
+        ++n_side;
+        LEM_TRY(run_step(r.plan, in, out, ss));
         continue;
       }
       const lem_plan_s* p = r.plan;
@@ -1650,6 +1673,11 @@ lem_status lem_server_tick(lem_server_t s, int32_t* n_active, int32_t* n_queued)
       if (e != hipSuccess)
         return fail(LEM_ERR_HIP, std::string("serving launch: ") + hipGetErrorString(e));
       off += g.second.size();
+    }
+    // the retiring copies below (on the serving stream) follow the side streams
+    for (int k = 0; k < std::min(n_side, lem_server_s::kSide); ++k) {
+      LEM_HIP(hipEventRecord(s->ev_join[k], s->side[k]));
+      LEM_HIP(hipStreamWaitEvent(s->st, s->ev_join[k], 0));
     }
   }
   // 3. advance counters, retire finished requests
