@@ -538,12 +538,23 @@ __global__ __launch_bounds__(64 * NW) void apply_mfma_kernel(ApplyArgs a) {
 // NT = 6 adds hi*lo + lo*hi + mid*mid of the 3-piece split.
 // Fragment layout (16x16x32 bf16): lane l supplies A[l%16][8*(l/16) + e] and
 // B[8*(l/16) + e][l%16] for e = 0..7.
+//
+// The gathered row offsets of the box are tabulated in LDS once.  Thread t
+// stages column t % 64 of k-group t / 64 (8 consecutive local rows) of the
+// next chunk: eight coalesced loads, the split into pieces (float conversions:
+// any bf16 close to the value serves as a piece, the residuals are exact), and
+// one 16-byte LDS store per piece, into the LDS stage the MFMAs are not
+// reading (one barrier per chunk).  A fragments are prefetched one chunk ahead.
+__device__ __forceinline__ __bf16 bf16_near(double v) { return (__bf16)(float)v; }
+__device__ __forceinline__ double bf16_val(__bf16 h) { return (double)(float)h; }
+
 template <int NTERMS, int WM>
 __global__ __launch_bounds__(256) void apply_bf16_kernel(ApplyArgs a) {
   constexpr int BN = 64, KC = 32, RT = WM / 16, CT = BN / 16;
-  // LDS: 3 pieces of the X chunk, stored per (col, k) so that a lane's 8
-  // consecutive k values are one 16-byte read.
-  __shared__ bf16x8 Xs[3][BN][KC / 8 + 1];
+  constexpr int NP = NTERMS == 6 ? 3 : 2;  // operand pieces in use
+  constexpr int KG = KC / 8 + 1;           // padded k-groups per LDS column
+  __shared__ bf16x8 Xs[2][NP][BN][KG];
+  extern __shared__ int64_t goff[];        // gathered row offsets (cols_p)
   const int total = a.n_blocks * a.row_tiles * a.col_tiles;
   const int item = xcd_remap(blockIdx.x, total);
   const int ct0 = item % a.col_tiles;
@@ -557,7 +568,14 @@ __global__ __launch_bounds__(256) void apply_bf16_kernel(ApplyArgs a) {
   const bf16x8* E = reinterpret_cast<const bf16x8*>(a.E);
   const int64_t estride8 = a.e_stride / 8;  // per piece, in 8-element groups
   const int ksteps = a.cols_p >> 5;
-  const int64_t eoff = (int64_t)b.unique * 3 * estride8;
+  const bool wave_live = row0 < a.rows_p;
+  const int rtw = wave_live ? row0 >> 4 : 0;
+  const bf16x8* Ew = E + (int64_t)b.unique * 3 * estride8 + (int64_t)rtw * ksteps * 64 + lane;
+  for (int l = tid; l < a.cols_p; l += 256) {
+    const int lc = l < a.cols ? l : a.cols - 1;  // padded columns of E are zero
+    goff[l] = dense_gather(b, lc, a.n, a.ndim) * a.ns + col0;
+  }
+  __syncthreads();
 
   f4 acc[RT][CT];
 #pragma unroll
@@ -565,69 +583,80 @@ __global__ __launch_bounds__(256) void apply_bf16_kernel(ApplyArgs a) {
 #pragma unroll
     for (int j = 0; j < CT; ++j) acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
 
-  // chunk loader: 32 local rows x 64 states; thread -> (row tid/8, 8 states)
-  const int xr = tid >> 3, xc = (tid & 7) * 8;
-  const bool wave_live = row0 < a.rows_p;
-  for (int ch = 0; ch < ksteps; ++ch) {
-    {
-      const int l = ch * KC + xr;
-      double v[8];
-      if (l < a.cols) {
-        const int64_t g = dense_gather(b, l, a.n, a.ndim);
-        const double* src = a.x_in + g * a.ns + col0 + xc;
+  auto load_a = [&](int ch, bf16x8 (&ea)[NP][RT]) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = src[q];
-      } else {
+    for (int p = 0; p < NP; ++p)
 #pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = 0.0;
-      }
-      __hip_bfloat16* base = reinterpret_cast<__hip_bfloat16*>(&Xs[0][0][0]);
+      for (int i = 0; i < RT; ++i)
+        ea[p][i] = Ew[p * estride8 + ((int64_t)i * ksteps + ch) * 64];
+  };
+  const int xc = tid & 63, xg = tid >> 6;
+  auto load_x = [&](int ch, double (&v)[8]) {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const __hip_bfloat16 hi = __double2bfloat16(v[q]);
-        const double r1 = v[q] - (double)__bfloat162float(hi);
-        const __hip_bfloat16 mid = __double2bfloat16(r1);
-        const double r2 = r1 - (double)__bfloat162float(mid);
-        const __hip_bfloat16 lo = __double2bfloat16(r2);
-        const int col = xc + q;
-        const int64_t e = ((int64_t)col * (KC / 8 + 1) + (xr >> 3)) * 8 + (xr & 7);
-        base[e] = hi;
-        base[(int64_t)BN * (KC / 8 + 1) * 8 + e] = mid;
-        base[2 * (int64_t)BN * (KC / 8 + 1) * 8 + e] = lo;
-      }
+    for (int e = 0; e < 8; ++e) v[e] = a.x_in[goff[ch * KC + xg * 8 + e] + xc];
+  };
+  auto store_x = [&](const double (&v)[8], int buf) {
+    bf16x8 pc[NP];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const __bf16 hi = bf16_near(v[e]);
+      const double r1 = v[e] - bf16_val(hi);
+      const __bf16 mid = bf16_near(r1);
+      pc[0][e] = hi;
+      pc[1][e] = mid;
+      if constexpr (NP == 3) pc[2][e] = bf16_near(r1 - bf16_val(mid));
     }
-    __syncthreads();
-    if (wave_live) {
-      bf16x8 bx[3][CT];
 #pragma unroll
-      for (int p = 0; p < 3; ++p)
+    for (int p = 0; p < NP; ++p) Xs[buf][p][xc][xg] = pc[p];
+  };
+  auto mfma_chunk = [&](const bf16x8 (&ea)[NP][RT], int buf) {
+    bf16x8 bx[NP][CT];
 #pragma unroll
-        for (int j = 0; j < CT; ++j) bx[p][j] = Xs[p][j * 16 + (lane & 15)][lane >> 4];
+    for (int p = 0; p < NP; ++p)
 #pragma unroll
-      for (int i = 0; i < RT; ++i) {
-        const int rt = (row0 >> 4) + i;
-        const int64_t fi = ((int64_t)rt * ksteps + ch) * 64 + lane;
-        const bf16x8 ehi = E[eoff + fi];
-        const bf16x8 emid = E[eoff + estride8 + fi];
-        const bf16x8 elo = E[eoff + 2 * estride8 + fi];
+      for (int j = 0; j < CT; ++j) bx[p][j] = Xs[buf][p][j * 16 + (lane & 15)][lane >> 4];
 #pragma unroll
-        for (int j = 0; j < CT; ++j) {
-          f4 c = acc[i][j];
-          // small terms first, the dominant product last
-          if (NTERMS == 6) {
-            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(emid, bx[1][j], c, 0, 0, 0);
-            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(elo, bx[0][j], c, 0, 0, 0);
-            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ehi, bx[2][j], c, 0, 0, 0);
-          }
-          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(emid, bx[0][j], c, 0, 0, 0);
-          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ehi, bx[1][j], c, 0, 0, 0);
-          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ehi, bx[0][j], c, 0, 0, 0);
-          acc[i][j] = c;
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+      for (int j = 0; j < CT; ++j) {
+        f4 c = acc[i][j];
+        // small terms first, the dominant product last
+        if constexpr (NTERMS == 6) {
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ea[1][i], bx[1][j], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ea[2][i], bx[0][j], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ea[0][i], bx[2][j], c, 0, 0, 0);
         }
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ea[1][i], bx[0][j], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ea[0][i], bx[1][j], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ea[0][i], bx[0][j], c, 0, 0, 0);
+        acc[i][j] = c;
       }
-    }
+  };
+  const int last = ksteps - 1;
+  bf16x8 ea0[NP][RT], ea1[NP][RT];
+  double xv[8];
+  load_a(0, ea0);
+  load_x(0, xv);
+  store_x(xv, 0);
+  __syncthreads();
+  // chunk c in stage c & 1: prefetch A of c+1 and X of c+1, multiply, then
+  // split and stage X of c+1 into the other stage; loads are unconditional
+  // (clamped) so the loop body has no branches around memory operations
+  auto step = [&](int c, const bf16x8 (&ecur)[NP][RT], bf16x8 (&enext)[NP][RT]) {
+    const int cn = c + 1 < last ? c + 1 : last;
+    load_a(cn, enext);
+    load_x(cn, xv);
+    if (wave_live) mfma_chunk(ecur, c & 1);
+    store_x(xv, (c + 1) & 1);
     __syncthreads();
+  };
+  int c = 0;
+  for (; c + 1 < ksteps; c += 2) {
+    step(c, ea0, ea1);
+    step(c + 1, ea1, ea0);
   }
+  if (c < ksteps) step(c, ea0, ea1);
+
   if (!wave_live) return;
 #pragma unroll
   for (int i = 0; i < RT; ++i)
@@ -842,12 +871,14 @@ hipError_t dense_apply(int precision, int cfg, const void* blocks, const void* E
   const int wm = (cfg & 1) ? 64 : 32;
   a.row_tiles = (rows_p + 4 * wm - 1) / (4 * wm);
   const dim3 g(n_blocks * a.row_tiles * a.col_tiles);
+  const size_t gl = (size_t)cols_p * sizeof(int64_t);  // gathered row offsets
+  if (gl > 64 * 1024) return hipErrorInvalidValue;
   if (precision == 2) {
-    if (wm == 32) hipLaunchKernelGGL((apply_bf16_kernel<3, 32>), g, dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((apply_bf16_kernel<3, 64>), g, dim3(256), 0, st, a);
+    if (wm == 32) hipLaunchKernelGGL((apply_bf16_kernel<3, 32>), g, dim3(256), gl, st, a);
+    else hipLaunchKernelGGL((apply_bf16_kernel<3, 64>), g, dim3(256), gl, st, a);
   } else if (precision == 3) {
-    if (wm == 32) hipLaunchKernelGGL((apply_bf16_kernel<6, 32>), g, dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((apply_bf16_kernel<6, 64>), g, dim3(256), 0, st, a);
+    if (wm == 32) hipLaunchKernelGGL((apply_bf16_kernel<6, 32>), g, dim3(256), gl, st, a);
+    else hipLaunchKernelGGL((apply_bf16_kernel<6, 64>), g, dim3(256), gl, st, a);
   } else {
     return hipErrorInvalidValue;
   }
