@@ -25,6 +25,8 @@ decomposition approach to exponential time integration of PDEs"):
                 via the discrete Fourier symbol for periodic constant
                 coefficients, dense expm or the Krylov action otherwise
   phi.py        phi_1 and the exponential-Euler form of update (5)
+  rosenbrock.py exponential Rosenbrock-Euler LEM for Burgers (sections 3, 4.2)
+                with a Jacobian frozen between refreshes
   metrics.py    relative l2 / l-infinity errors
 """
-from . import operator, partition, halo, expm, krylov, lem, globalexp, phi, metrics  # noqa: F401
+from . import operator, partition, halo, expm, krylov, lem, globalexp, phi, metrics, rosenbrock  # noqa: F401

@@ -18,6 +18,7 @@ from oracle import lem
 from oracle import operator as op
 from oracle import partition as P
 from oracle import phi as PHI
+from oracle import rosenbrock as ROS
 from oracle.metrics import rel_l2, rel_linf
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -399,6 +400,70 @@ def test_forced_lem_converges_to_global_with_halo():
             for h in (4, 12, 20, 28)]
     assert all(b < a / 10 for a, b in zip(errs, errs[1:]))
     assert errs[-1] < 1e-10
+
+
+# --------------------------------------------- exponential Rosenbrock ----
+# Burgers u_t = -(u^2/2)_x + nu u_xx (section 4.2), exponential
+# Rosenbrock-Euler steps u + dt phi_1(dt J) F(u) with J frozen between
+# refreshes (sections 3 and 4).
+
+def _gauss(n, L, amp=1.0, x0=3.0):
+    x = np.arange(n) * (L / n)
+    return amp * np.exp(-(x - x0) ** 2)
+
+
+def test_burgers_jacobian_is_the_derivative_of_F():
+    # F is quadratic, so the central difference is exact up to rounding
+    n, dx, nu = 64, 10.0 / 64, 0.05
+    rng = np.random.default_rng(4)
+    u, d = rng.standard_normal(n), rng.standard_normal(n)
+    eps = 1e-3
+    fd = (ROS.burgers_F(u + eps * d, dx, nu) - ROS.burgers_F(u - eps * d, dx, nu)) / (2 * eps)
+    assert np.abs(fd - ROS.burgers_J(u, dx, nu) @ d).max() < 1e-9
+    # at a constant state c the Jacobian is the linear advection-diffusion
+    # operator with speed c (an independently written stencil)
+    c = 0.7
+    W = op.weights(1, n, dx, 1.0, (c, 0.0), nu=nu)
+    assert np.abs((ROS.burgers_J(np.full(n, c), dx, nu) - op.sparse(W)).toarray()).max() < 1e-12
+    # and constant states are steady: F(c) = 0, so every step keeps them
+    u1 = ROS.ere_global_run(np.full(n, c), dx, nu, 0.1, 3)
+    assert np.abs(u1 - c).max() < 1e-14
+
+
+def test_exponential_rosenbrock_euler_is_second_order():
+    n, L, nu = 128, 10.0, 0.05
+    dx = L / n
+    u0 = _gauss(n, L)
+    T = 0.8
+    ref = ROS.rk4_reference(u0, dx, nu, T, 4000)
+    errs = [rel_l2(ROS.ere_global_run(u0, dx, nu, T / s, s), ref) for s in (8, 16, 32)]
+    rates = [math.log2(a / b) for a, b in zip(errs, errs[1:])]
+    assert all(1.8 < r < 2.3 for r in rates), rates
+
+
+def test_exponential_rosenbrock_conserves_mass_globally():
+    # sum(F) = 0 and 1^T J = 0 for the periodic conservative stencil, so the
+    # total is kept exactly, with a fresh or a frozen Jacobian
+    n, L, nu = 100, 10.0, 0.05
+    dx = L / n
+    u0 = _gauss(n, L) + 0.2
+    for K in (1, 4):
+        u = ROS.ere_global_run(u0, dx, nu, 0.05, 9, refresh=K)
+        assert abs(u.sum() - u0.sum()) < 1e-11
+
+
+def test_lem_rosenbrock_single_domain_and_halo_convergence():
+    n, L, nu, dt = 200, 10.0, 0.05, 0.05
+    dx = L / n
+    rng = np.random.default_rng(2)
+    u0 = np.column_stack([_gauss(n, L, 1.0, 3.0), _gauss(n, L, 0.6, 5.5) + 0.1])
+    glob = ROS.ere_global_run(u0, dx, nu, dt, 10, refresh=5)
+    one = ROS.ere_lem_run(u0, [P.Box(0, 0, n, 1, 0)], n, dx, nu, dt, 10, refresh=5)
+    assert rel_l2(one, glob) < 1e-13
+    errs = [rel_l2(ROS.ere_lem_run(u0, P.uniform_boxes(1, n, 25, h), n, dx, nu, dt, 10, refresh=5), glob)
+            for h in (2, 4, 8, 16)]
+    assert all(b < a / 5 for a, b in zip(errs, errs[1:])), errs
+    assert errs[-1] < 1e-13
 
 
 def test_nonnegative_local_exponential_when_mu_ge_half_c():
