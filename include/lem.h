@@ -60,7 +60,9 @@ enum {
   LEM_METHOD_DENSE = 1,   /* stored local exponentials by Pade scaling and
                              squaring, applied as matrix products (sections 3
                              and 4: "computed only at the first time step")  */
-  LEM_METHOD_GLOBAL = 2   /* no decomposition (D = 1): global Krylov action  */
+  LEM_METHOD_GLOBAL = 2,  /* no decomposition (D = 1): global Krylov action  */
+  LEM_METHOD_ROSENBROCK = 3 /* exponential Rosenbrock-Euler for Burgers; plans
+                               come from lem_ere_plan only                    */
 };
 
 /* Arithmetic used to apply stored local exponentials (dense method only). */
@@ -166,6 +168,29 @@ lem_status lem_plan(const lem_operator* op, double dt, const lem_options* opt,
  * through a plan-owned buffer.  Asynchronous on `stream`. */
 lem_status lem_step(lem_plan_t plan, const double* x_in, double* x_out,
                     int32_t n_steps, void* stream);
+
+/* Viscous Burgers u_t = -(u^2/2)_x + nu u_xx on a periodic 1D grid of n >= 3
+ * points (section 4.2), centered differences. */
+typedef struct {
+  int32_t n;
+  double dx;   /* > 0 */
+  double nu;   /* >= 0 */
+} lem_burgers;
+
+/* Plan exponential Rosenbrock-Euler LEM steps (sections 3 and 4):
+ *   u^{n+1} = u^n + dt phi_1(dt J_M) F(u^n)_M on every region, core rows,
+ * J_M the principal submatrix on the box of the Jacobian of F, frozen at the
+ * state of the last refresh and refreshed every `refresh` >= 1 steps (the
+ * first lem_step refreshes).  Cores of `core` points (dividing n) with
+ * buffers of `halo` points per side; core = n with halo = 0 is the global
+ * method (D = 1, periodic coupling kept).  A refresh computes phi_1 of the
+ * augmented matrices [[dt J_M, I], [0, 0]] of every (block, member) by Pade
+ * [13/13] in float64 on the device (and synchronizes the stream); a step is
+ * F on the grid and one contraction per core row.  lem_step, lem_plan_query,
+ * lem_plan_copy_maps and lem_plan_destroy apply; no graphs, no serving.
+ * Errors: LEM_ERR_INVALID (bad sizes), LEM_ERR_NOMEM, LEM_ERR_HIP. */
+lem_status lem_ere_plan(const lem_burgers* op, double dt, int32_t n_states, int32_t core,
+                        int32_t halo, int32_t refresh, void* stream, lem_plan_t* out);
 
 /* y = exp(t A) x on the whole grid (no decomposition) by the Krylov method
  * of section 4.3, for n_states ensemble members (with op->forcing set:

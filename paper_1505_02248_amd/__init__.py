@@ -84,6 +84,7 @@ def load() -> ctypes.CDLL:
     lib.lem_plan.argtypes = [P(_Operator), D, P(_Options), VP, P(VP)]
     lib.lem_step.argtypes = [VP, VP, VP, I32, VP]
     lib.lem_global_expmv.argtypes = [P(_Operator), D, VP, VP, I32, D, I32, VP]
+    lib.lem_ere_plan.argtypes = [P(_Burgers), D, I32, I32, I32, I32, VP, P(VP)]
     lib.lem_plan_query.argtypes = [VP, P(_Info)]
     lib.lem_plan_copy_maps.argtypes = [VP, P(I32), P(I32), P(I32)]
     lib.lem_plan_copy_krylov.argtypes = [VP, P(I32), P(I32)]
@@ -249,6 +250,32 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class _Burgers(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("dx", ctypes.c_double), ("nu", ctypes.c_double)]
+
+
+class _Grid1D:
+    def __init__(self, n: int):
+        self.N = int(n)
+
+
+class ErePlan(Plan):
+    """Exponential Rosenbrock-Euler LEM steps for periodic viscous Burgers
+    (``lem_ere_plan``); step/query/maps as for ``Plan``."""
+
+    def __init__(self, n: int, dx: float, nu: float, dt: float, n_states: int = 1,
+                 core: int = 50, halo: int = 15, refresh: int = 5, stream=None):
+        lib = load()
+        b = _Burgers()
+        b.n, b.dx, b.nu = int(n), float(dx), float(nu)
+        self.op, self.dt, self.n_states, self.method = _Grid1D(n), float(dt), int(n_states), "rosenbrock"
+        h = ctypes.c_void_p()
+        _check(lib.lem_ere_plan(ctypes.byref(b), self.dt, int(n_states), int(core), int(halo),
+                                int(refresh), ctypes.c_void_p(_stream_handle(stream)),
+                                ctypes.byref(h)))
+        self._h = h
 
 
 def global_expmv(op: Operator, t: float, x, y, n_states: int = 1, tol: float = 1e-13,

@@ -289,6 +289,16 @@ struct lem_plan_s {
   bool forced = false;
   double* d_force = nullptr;
   double* d_bias = nullptr;
+  // exponential Rosenbrock-Euler (Burgers): Jacobian refresh every ere_refresh
+  // steps; phi_1 core rows per (block, member); augmented matrices and the
+  // Pade work space kept between refreshes
+  double ere_dx = 0, ere_nu = 0;
+  int ere_refresh = 1, ere_nl = 0, ere_rows = 0;
+  int64_t ere_count = 0;
+  void* d_ere_boxes = nullptr;
+  double *d_ere_A = nullptr, *d_ere_R = nullptr, *d_phi = nullptr, *d_f = nullptr;
+  std::vector<double*> ere_work;  // A2, A4, A6, T, Ub, norms; plus the squaring counts
+  int* d_ere_s = nullptr;
   // global
   lem::GlobalWork gw{};
   // shared
@@ -681,17 +691,23 @@ lem_status plan_krylov(lem_plan_s* p, hipStream_t st) {
 // Pade [13/13] with scaling and squaring in float64 (Higham 2005): the powers,
 // both polynomials and the squarings on FP64 MFMA, Q R = P by pivoted LU.
 lem_status dense_expm(lem_plan_s* p, double* A, double* R, int nl, int U, hipStream_t st,
-                      int* smax) {
+                      int* smax, const std::vector<double*>* work = nullptr, int* work_s = nullptr) {
   const size_t mat = (size_t)nl * nl * U;
   double *A2, *A4, *A6, *T, *Ub, *d_norm;
   int* d_s;
-  LEM_TRY(dalloc(p, &A2, mat));
-  LEM_TRY(dalloc(p, &A4, mat));
-  LEM_TRY(dalloc(p, &A6, mat));
-  LEM_TRY(dalloc(p, &T, mat));
-  LEM_TRY(dalloc(p, &Ub, mat));
-  LEM_TRY(dalloc(p, &d_norm, U));
-  LEM_TRY(dalloc(p, &d_s, U));
+  if (work) {  // caller-owned work space (kept between calls)
+    A2 = (*work)[0]; A4 = (*work)[1]; A6 = (*work)[2]; T = (*work)[3]; Ub = (*work)[4];
+    d_norm = (*work)[5];
+    d_s = work_s;
+  } else {
+    LEM_TRY(dalloc(p, &A2, mat));
+    LEM_TRY(dalloc(p, &A4, mat));
+    LEM_TRY(dalloc(p, &A6, mat));
+    LEM_TRY(dalloc(p, &T, mat));
+    LEM_TRY(dalloc(p, &Ub, mat));
+    LEM_TRY(dalloc(p, &d_norm, U));
+    LEM_TRY(dalloc(p, &d_s, U));
+  }
   LEM_HIP(lem::dense_norm1(A, nl, U, d_norm, st));
   std::vector<double> nrm(U);
   LEM_HIP(hipMemcpyAsync(nrm.data(), d_norm, U * 8, hipMemcpyDeviceToHost, st));
@@ -730,8 +746,31 @@ lem_status dense_expm(lem_plan_s* p, double* A, double* R, int nl, int U, hipStr
                              hipMemcpyDeviceToDevice, st));
   }
   LEM_HIP(hipStreamSynchronize(st));
-  for (void* q : {(void*)A2, (void*)A4, (void*)A6, (void*)T, (void*)Ub, (void*)d_norm, (void*)d_s})
-    dfree(p, q);
+  if (!work)
+    for (void* q : {(void*)A2, (void*)A4, (void*)A6, (void*)T, (void*)Ub, (void*)d_norm, (void*)d_s})
+      dfree(p, q);
+  return LEM_OK;
+}
+
+// ----------------------------------------------------- exponential Rosenbrock
+// phi_1(dt J_M) of every (block, member) at the state x (Jacobian refresh).
+lem_status ere_refresh(lem_plan_s* p, const double* x, hipStream_t st) {
+  const int nb = (int)p->boxes.size(), U = nb * p->ns, n2 = 2 * p->ere_nl;
+  LEM_HIP(lem::ere_assemble(x, p->d_ere_boxes, nb, p->ns, p->ere_nl, p->op.n, p->op.dt,
+                            p->ere_dx, p->ere_nu, p->d_ere_A, st));
+  int sq = 0;
+  LEM_TRY(dense_expm(p, p->d_ere_A, p->d_ere_R, n2, U, st, &sq, &p->ere_work, p->d_ere_s));
+  p->squarings = std::max(p->squarings, sq);
+  LEM_HIP(lem::ere_extract(p->d_ere_R, p->d_ere_boxes, nb, p->ns, p->ere_nl, p->ere_rows,
+                           p->d_phi, st));
+  return LEM_OK;
+}
+
+lem_status ere_run_one(lem_plan_s* p, const double* src, double* dst, hipStream_t st) {
+  if (p->ere_count % p->ere_refresh == 0) LEM_TRY(ere_refresh(p, src, st));
+  LEM_HIP(lem::ere_step(src, p->d_f, p->d_phi, p->d_ere_boxes, (int)p->boxes.size(), p->ns,
+                        p->ere_nl, p->ere_rows, p->op.n, p->op.dt, p->ere_dx, p->ere_nu, dst, st));
+  p->ere_count++;
   return LEM_OK;
 }
 
@@ -963,6 +1002,7 @@ lem_status plan_global(lem_plan_s* p, hipStream_t st) {
 
 // ----------------------------------------------------------------- step ----
 lem_status run_one(lem_plan_s* p, const double* src, double* dst, hipStream_t st) {
+  if (p->method == LEM_METHOD_ROSENBROCK) return ere_run_one(p, src, dst, st);
   switch (p->global_box ? LEM_METHOD_KRYLOV : p->method) {
     case LEM_METHOD_KRYLOV:
       return launch_buckets(p, p->d_kb, p->buckets, p->ns, src, dst, p->d_vwork, p->d_diag,
@@ -1204,6 +1244,82 @@ lem_status lem_step(lem_plan_t p, const double* x_in, double* x_out, int32_t n_s
     LEM_TRY(run_step(p, src, dst, st));
     src = dst;
   }
+  return LEM_OK;
+}
+
+lem_status lem_ere_plan(const lem_burgers* op, double dt, int32_t n_states, int32_t core,
+                        int32_t halo, int32_t refresh, void* stream, lem_plan_t* out) {
+  if (!op || !out) return fail(LEM_ERR_INVALID, "NULL argument");
+  *out = nullptr;
+  if (op->n < 3) return fail(LEM_ERR_INVALID, "n must be >= 3");
+  if (!(op->dx > 0) || !std::isfinite(op->dx)) return fail(LEM_ERR_INVALID, "dx must be > 0");
+  if (!(op->nu >= 0) || !std::isfinite(op->nu)) return fail(LEM_ERR_INVALID, "nu must be >= 0");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(LEM_ERR_INVALID, "dt must be > 0");
+  if (n_states < 1 || refresh < 1) return fail(LEM_ERR_INVALID, "n_states, refresh must be >= 1");
+  if (core < 1 || op->n % core != 0 || halo < 0)
+    return fail(LEM_ERR_INVALID, "core must divide n and halo be >= 0");
+  const bool whole = core == op->n && halo == 0;
+  if (!whole && core + 2 * halo >= op->n)
+    return fail(LEM_ERR_INVALID, "a box must be smaller than the grid (or core = n, halo = 0)");
+  const auto t0 = std::chrono::steady_clock::now();
+  auto p = new lem_plan_s();
+  auto guard = [&](lem_status s) { if (s != LEM_OK) delete p; return s; };
+  lem_options_default(&p->opt);
+  p->opt.method = LEM_METHOD_ROSENBROCK;
+  p->opt.n_states = n_states;
+  p->opt.core = core;
+  p->opt.halo = halo;
+  p->method = LEM_METHOD_ROSENBROCK;
+  p->ns = n_states;
+  p->stream = (hipStream_t)stream;
+  p->op.ndim = 1;
+  p->op.n = op->n;
+  p->op.dx = op->dx;
+  p->op.dt = dt;
+  p->op.nu = op->nu;
+  p->N = op->n;
+  p->ere_dx = op->dx;
+  p->ere_nu = op->nu;
+  p->ere_refresh = refresh;
+  p->ere_nl = core + 2 * halo;
+  p->ere_rows = core;
+  const int nb = op->n / core;
+  for (int b = 0; b < nb; ++b) p->boxes.push_back({b * core, 0, core, 1, halo});
+  hipStream_t st = p->stream;
+  const int nl = p->ere_nl, n2 = 2 * nl, U = nb * n_states;
+  const size_t mat = (size_t)n2 * n2 * U;
+  std::vector<unsigned char> hb(lem::ere_box_size() * nb);
+  for (int b = 0; b < nb; ++b) lem::ere_box_fill(hb.data(), b, b * core, halo, core, whole ? 1 : 0);
+  lem_status s = dalloc(p, &p->d_status, 1);
+  if (s == LEM_OK && hipMemsetAsync(p->d_status, 0, sizeof(int), st) != hipSuccess)
+    s = fail(LEM_ERR_HIP, "hipMemsetAsync failed");
+  if (s == LEM_OK) s = dalloc(p, &p->d_tmp, (size_t)p->N * p->ns, &p->bytes_work);
+  if (s == LEM_OK) {
+    unsigned char* d;
+    s = dalloc(p, &d, hb.size(), &p->bytes_work);
+    p->d_ere_boxes = d;
+  }
+  if (s == LEM_OK) s = upload(p->d_ere_boxes, hb.data(), hb.size(), st);
+  if (s == LEM_OK) s = dalloc(p, &p->d_ere_A, mat, &p->bytes_work);
+  if (s == LEM_OK) s = dalloc(p, &p->d_ere_R, mat, &p->bytes_work);
+  for (int q = 0; q < 5 && s == LEM_OK; ++q) {
+    double* w;
+    s = dalloc(p, &w, mat, &p->bytes_work);
+    p->ere_work.push_back(w);
+  }
+  if (s == LEM_OK) {
+    double* w;
+    s = dalloc(p, &w, (size_t)U, &p->bytes_work);
+    p->ere_work.push_back(w);
+  }
+  if (s == LEM_OK) s = dalloc(p, &p->d_ere_s, (size_t)U, &p->bytes_work);
+  if (s == LEM_OK) s = dalloc(p, &p->d_phi, (size_t)nb * core * nl * n_states, &p->bytes_blocks);
+  if (s == LEM_OK) s = dalloc(p, &p->d_f, (size_t)p->N * p->ns, &p->bytes_work);
+  if (s == LEM_OK && hipStreamSynchronize(st) != hipSuccess)
+    s = fail(LEM_ERR_HIP, "plan synchronization failed");
+  if (s != LEM_OK) return guard(s);
+  p->plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *out = p;
   return LEM_OK;
 }
 

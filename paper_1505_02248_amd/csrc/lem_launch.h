@@ -53,6 +53,17 @@ hipError_t dense_apply(int precision, int cfg, const void* blocks, const void* E
                        int n, int ndim, int ns, int rows, int rows_p, int cols, int cols_p,
                        int n_blocks, const double* bias, hipStream_t st);
 
+// ---- exponential Rosenbrock-Euler LEM for Burgers (rosenbrock.hip)
+size_t ere_box_size();
+void ere_box_fill(void* dst, int i, int ox, int h, int cx, int whole);
+hipError_t ere_assemble(const double* x, const void* boxes, int nb, int ns, int nl, int n,
+                        double dt, double dx, double nu, double* A, hipStream_t st);
+hipError_t ere_extract(const double* R, const void* boxes, int nb, int ns, int nl, int rows,
+                       double* Phi, hipStream_t st);
+hipError_t ere_step(const double* x, double* f, const double* Phi, const void* boxes, int nb,
+                    int ns, int nl, int rows, int n, double dt, double dx, double nu, double* y,
+                    hipStream_t st);
+
 // ---- global Krylov (global_krylov.hip)
 struct GlobalWork {
   int64_t N;

@@ -16,6 +16,7 @@ from oracle import globalexp as ge
 from oracle import lem as olem
 from oracle import operator as op
 from oracle import partition as P
+from oracle import rosenbrock as ROS
 from oracle.metrics import rel_l2
 
 pytestmark = pytest.mark.gpu
@@ -345,3 +346,31 @@ def test_forced_graph_replay_and_steady_state():
     torch.cuda.synchronize()
     assert np.array_equal(y.cpu().numpy().reshape(a.shape), a)
     assert rel_l2(a, us) <= 1e-6
+
+
+# -------------------------------------------------- exponential Rosenbrock --
+# Burgers u_t = -(u^2/2)_x + nu u_xx (section 4.2): u + dt phi_1(dt J_M) F(u)_M
+# per region, J frozen between refreshes (sections 3 and 4).
+
+def _burgers_states(n, L, ns, seed):
+    rng = np.random.default_rng(seed)
+    x = np.arange(n) * (L / n)
+    amp = rng.uniform(0.5, 1.5, ns)
+    x0 = rng.uniform(2.0, 8.0, ns)
+    return np.column_stack([amp[k] * np.exp(-(x - x0[k]) ** 2) for k in range(ns)])
+
+
+@pytest.mark.parametrize("core,halo,refresh,ns", [(25, 8, 5, 2), (200, 0, 3, 2), (50, 15, 5, 64)])
+def test_rosenbrock_lem_matches_oracle(core, halo, refresh, ns):
+    n, L, nu = 200, 10.0, 0.05
+    dx = L / n
+    dt = dx  # Courant number ~1 for |u| ~ 1, mu = 2
+    u0 = _burgers_states(n, L, ns, 3)
+    plan = lem.ErePlan(n, dx, nu, dt, n_states=ns, core=core, halo=halo, refresh=refresh)
+    steps = 12
+    got = run(plan, u0, steps)
+    boxes = [P.Box(b * core, 0, core, 1, halo) for b in range(n // core)]
+    want = ROS.ere_lem_run(u0, boxes, n, dx, nu, dt, steps, refresh=refresh)
+    assert rel_l2(got, want) <= 1e-12
+    if core == n:  # D = 1: the global method conserves the total exactly
+        assert np.abs(got.sum(0) - u0.sum(0)).max() <= 1e-10
