@@ -115,11 +115,12 @@ def parse_args():
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run one device copy of this many MiB (a reference kernel of "
                          "known traffic for scaling HBM counters)")
-    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2", "c3", "c4", "f1"],
+    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2", "c3", "c4", "f1", "f2"],
                     help="c1 (default): 256^2 x 64 states, dense FP64; c0: 1D 1024; "
                          "c2: 1024^2 lognormal nu, uneven Krylov; c3: 512^2 x 128 states, "
                          "mixed precision; c4: served Poisson stream; f1: c1 with a "
-                         "constant source g (exponential-Euler step with forcing)")
+                         "constant source g (exponential-Euler step with forcing); f2: "
+                         "Burgers by exponential Rosenbrock-Euler LEM")
     ap.add_argument("--requests", type=int, default=300)
     return ap.parse_args()
 
@@ -132,7 +133,7 @@ def main() -> int:
               "which is not implemented here)", file=sys.stderr)
         return 2
     fn = {"c1": bench_c1, "c0": bench_c0, "c2": bench_c2, "c3": bench_c3,
-          "c4": bench_c4, "f1": bench_f1}[args.workload]
+          "c4": bench_c4, "f1": bench_f1, "f2": bench_f2}[args.workload]
     out = fn(args)
     print(json.dumps(out), flush=True)
     return 0
@@ -333,6 +334,52 @@ def bench_f1(args) -> dict:
             "kernel": "apply_mfma_kernel<double> (with the forcing term)",
             "flops_per_launch": flops, "us_per_launch": kern_ms * 1e3}
     return _line(args, workload, value, "DOF-steps/s", args.steps, wall, "f64", extras, roof)
+
+
+def bench_f2(args) -> dict:
+    """Viscous Burgers (nu = 0.05) on 400 cells of [0, 10), dt = dx (Courant ~1,
+    mu = 2), 256 Gaussian members, T = 5 (200 steps): exponential
+    Rosenbrock-Euler LEM with 8 regions of 50 cells and 15-cell buffers, the
+    Jacobian and local phi_1 matrices refreshed every 5 steps, against the same
+    method on one region (D = 1) on the same GPU."""
+    import numpy as np
+    import torch
+    import lem_inputs as L
+    import paper_1505_02248_amd as lem
+    torch.cuda.init()
+    n, Lx, nu, ns, steps, K = 400, 10.0, 0.05, 256, 200, 5
+    dx = Lx / n
+    dt = dx
+    u0 = L.gaussian_members(n, Lx, ns, seed=11)
+    x = torch.from_numpy(u0).to("cuda")
+    out = {}
+    for label, core, halo in [("lem_d8_b15", 50, 15), ("global_d1", n, 0)]:
+        plan = lem.ErePlan(n, dx, nu, dt, n_states=ns, core=core, halo=halo, refresh=K)
+        y = torch.empty_like(x)
+        plan.step(x, y, K)  # warm-up (one refresh cycle)
+        torch.cuda.synchronize()
+        plan2 = lem.ErePlan(n, dx, nu, dt, n_states=ns, core=core, halo=halo, refresh=K)
+        t0 = time.perf_counter()
+        plan2.step(x, y, steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out[label] = {"wall_s": wall, "dof_steps_per_s": n * ns * steps / wall, "state": y.clone()}
+        log(f"{label}: {n * ns * steps / wall:.3e} DOF-steps/s, {1e3 * wall / steps:.3f} ms/step")
+    a, g = out["lem_d8_b15"]["state"], out["global_d1"]["state"]
+    err = (torch.linalg.norm(a - g) / torch.linalg.norm(g)).item()
+    mass = (g.sum(0) - x.sum(0)).abs().max().item()
+    value = out["lem_d8_b15"]["dof_steps_per_s"]
+    extras = {"lem_vs_global_rel_l2": err, "global_mass_drift": mass,
+              "global_d1": {"dof_steps_per_s": out["global_d1"]["dof_steps_per_s"],
+                            "ms_per_step": 1e3 * out["global_d1"]["wall_s"] / steps},
+              "lem_over_global": value / out["global_d1"]["dof_steps_per_s"]}
+    workload = {"workload": "1D periodic viscous Burgers (nu=0.05) on 400 cells of [0,10), dt=dx, "
+                            "256 Gaussian members, 200 steps (T=5); exponential Rosenbrock-Euler LEM, "
+                            "8 regions of 50 cells, 15-cell buffers, Jacobian and local phi_1 matrices "
+                            "refreshed every 5 steps (fp64)",
+                "n": n, "n_states": ns, "core": 50, "halo": 15, "refresh": K}
+    return _line(args, workload, value, "DOF-steps/s", steps, out["lem_d8_b15"]["wall_s"], "f64",
+                 extras)
 
 
 def bench_c0(args) -> dict:

@@ -113,6 +113,18 @@ def source_fields_2d(n: int, n_states: int, seed: int, n_modes: int = 4, kmax: i
     return mean + smooth_states_2d(n, n_states, seed, n_modes=n_modes, kmax=kmax)
 
 
+def gaussian_members(n: int, length: float, n_states: int, seed: int) -> np.ndarray:
+    """Gaussian bumps a exp(-(x - x0)^2) on n cells of [0, length) (the
+    Burgers initial datum of section 4.2), per member a ~ U(0.5, 1.5) and
+    x0 ~ U(0.2, 0.8) * length (draw order: a, x0).  Shape (n, n_states)."""
+    rng = np.random.default_rng(seed)
+    x = np.arange(n) * (length / n)
+    a = rng.uniform(0.5, 1.5, n_states)
+    x0 = rng.uniform(0.2 * length, 0.8 * length, n_states)
+    return np.ascontiguousarray(np.column_stack([a[k] * np.exp(-(x - x0[k]) ** 2)
+                                                 for k in range(n_states)]))
+
+
 def white_noise_states(N: int, n_states: int, seed: int) -> np.ndarray:
     """iid N(0,1) states, shape (N, n_states) (rough stress inputs)."""
     rng = np.random.default_rng(seed)
