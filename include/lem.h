@@ -130,7 +130,9 @@ typedef struct {
   int32_t halo_clamped;    /* blocks whose decay-bound halo hit halo_max      */
   int32_t m_min, m_max;    /* Krylov dimensions used                          */
   int32_t substeps_max;
-  int32_t squarings;       /* Pade squarings of the largest dense block       */
+  int32_t squarings;       /* Pade squarings of the largest dense block; for
+                              Rosenbrock boxes of <= 80 points, the most
+                              phi_1 doublings at the last refresh           */
   int64_t bytes_blocks;    /* device bytes of stored local exponentials       */
   int64_t bytes_work;      /* device bytes of work space                      */
   int32_t device_status;   /* latched device-side lem_status (0 = fine)       */
@@ -183,9 +185,11 @@ typedef struct {
  * state of the last refresh and refreshed every `refresh` >= 1 steps (the
  * first lem_step refreshes).  Cores of `core` points (dividing n) with
  * buffers of `halo` points per side; core = n with halo = 0 is the global
- * method (D = 1, periodic coupling kept).  A refresh computes phi_1 of the
- * augmented matrices [[dt J_M, I], [0, 0]] of every (block, member) by Pade
- * [13/13] in float64 on the device (and synchronizes the stream); a step is
+ * method (D = 1, periodic coupling kept).  A refresh computes phi_1(dt J_M)
+ * of every (block, member) in float64 on the device: for boxes of at most 80
+ * points in one launch (Taylor polynomial of degree 16 on dt J_M / 2^s, then
+ * s doublings, asynchronous); for larger boxes from the augmented matrices
+ * [[dt J_M, I], [0, 0]] by Pade [13/13] (synchronizes the stream); a step is
  * F on the grid and one contraction per core row.  lem_step, lem_plan_query,
  * lem_plan_copy_maps and lem_plan_destroy apply; no graphs, no serving.
  * Errors: LEM_ERR_INVALID (bad sizes), LEM_ERR_NOMEM, LEM_ERR_HIP. */

@@ -294,6 +294,7 @@ struct lem_plan_s {
   // Pade work space kept between refreshes
   double ere_dx = 0, ere_nu = 0;
   int ere_refresh = 1, ere_nl = 0, ere_rows = 0;
+  bool ere_small = false;  // phi_1 by the one-workgroup LDS kernel (no Pade work space)
   int64_t ere_count = 0;
   void* d_ere_boxes = nullptr;
   double *d_ere_A = nullptr, *d_ere_R = nullptr, *d_phi = nullptr, *d_f = nullptr;
@@ -756,6 +757,11 @@ lem_status dense_expm(lem_plan_s* p, double* A, double* R, int nl, int U, hipStr
 // phi_1(dt J_M) of every (block, member) at the state x (Jacobian refresh).
 lem_status ere_refresh(lem_plan_s* p, const double* x, hipStream_t st) {
   const int nb = (int)p->boxes.size(), U = nb * p->ns, n2 = 2 * p->ere_nl;
+  if (p->ere_small) {
+    LEM_HIP(lem::ere_phi1(x, p->d_ere_boxes, nb, p->ns, p->ere_nl, p->ere_rows, p->op.n, p->op.dt,
+                          p->ere_dx, p->ere_nu, p->d_phi, p->d_ere_s, p->d_status, st));
+    return LEM_OK;
+  }
   LEM_HIP(lem::ere_assemble(x, p->d_ere_boxes, nb, p->ns, p->ere_nl, p->op.n, p->op.dt,
                             p->ere_dx, p->ere_nu, p->d_ere_A, st));
   int sq = 0;
@@ -1300,17 +1306,23 @@ lem_status lem_ere_plan(const lem_burgers* op, double dt, int32_t n_states, int3
     p->d_ere_boxes = d;
   }
   if (s == LEM_OK) s = upload(p->d_ere_boxes, hb.data(), hb.size(), st);
-  if (s == LEM_OK) s = dalloc(p, &p->d_ere_A, mat, &p->bytes_work);
-  if (s == LEM_OK) s = dalloc(p, &p->d_ere_R, mat, &p->bytes_work);
-  for (int q = 0; q < 5 && s == LEM_OK; ++q) {
-    double* w;
-    s = dalloc(p, &w, mat, &p->bytes_work);
-    p->ere_work.push_back(w);
-  }
-  if (s == LEM_OK) {
-    double* w;
-    s = dalloc(p, &w, (size_t)U, &p->bytes_work);
-    p->ere_work.push_back(w);
+  // boxes of up to ere_phi1_max_n() points: phi_1 per (block, member) in one
+  // LDS-resident launch; larger ones: the batched Pade pipeline on the
+  // augmented matrices [[dt J_M, I], [0, 0]]
+  p->ere_small = nl <= lem::ere_phi1_max_n();
+  if (!p->ere_small) {
+    if (s == LEM_OK) s = dalloc(p, &p->d_ere_A, mat, &p->bytes_work);
+    if (s == LEM_OK) s = dalloc(p, &p->d_ere_R, mat, &p->bytes_work);
+    for (int q = 0; q < 5 && s == LEM_OK; ++q) {
+      double* w;
+      s = dalloc(p, &w, mat, &p->bytes_work);
+      p->ere_work.push_back(w);
+    }
+    if (s == LEM_OK) {
+      double* w;
+      s = dalloc(p, &w, (size_t)U, &p->bytes_work);
+      p->ere_work.push_back(w);
+    }
   }
   if (s == LEM_OK) s = dalloc(p, &p->d_ere_s, (size_t)U, &p->bytes_work);
   if (s == LEM_OK) s = dalloc(p, &p->d_phi, (size_t)nb * core * nl * n_states, &p->bytes_blocks);
@@ -1354,6 +1366,11 @@ lem_status lem_plan_query(lem_plan_t p, lem_plan_info* info) {
   LEM_HIP(hipMemcpy(&st, p->d_status, sizeof(int), hipMemcpyDeviceToHost));
   info->device_status = (st & lem::kStatusNonFinite) ? LEM_ERR_NOT_CONVERGED
                         : (st & lem::kStatusNotConverged) ? LEM_ERR_NOT_CONVERGED : 0;
+  if (p->ere_small && p->ere_count > 0) {  // doublings taken at the last refresh
+    std::vector<int> sq(p->boxes.size() * p->ns);
+    LEM_HIP(hipMemcpy(sq.data(), p->d_ere_s, sq.size() * sizeof(int), hipMemcpyDeviceToHost));
+    for (int v : sq) info->squarings = std::max(info->squarings, v);
+  }
   double mx = 0.0;
   if ((p->method == LEM_METHOD_KRYLOV || p->global_box) && p->d_diag) {
     std::vector<double> d(p->boxes.size() * p->ns);

@@ -60,6 +60,10 @@ hipError_t ere_assemble(const double* x, const void* boxes, int nb, int ns, int 
                         double dt, double dx, double nu, double* A, hipStream_t st);
 hipError_t ere_extract(const double* R, const void* boxes, int nb, int ns, int nl, int rows,
                        double* Phi, hipStream_t st);
+int ere_phi1_max_n();
+hipError_t ere_phi1(const double* x, const void* boxes, int nb, int ns, int nl, int rows, int n,
+                    double dt, double dx, double nu, double* Phi, int* sq_out, int* status,
+                    hipStream_t st);
 hipError_t ere_step(const double* x, double* f, const double* Phi, const void* boxes, int nb,
                     int ns, int nl, int rows, int n, double dt, double dx, double nu, double* y,
                     hipStream_t st);

@@ -118,6 +118,145 @@ __global__ void ere_apply_kernel(const double* __restrict__ x, const double* __r
   }
 }
 
+// phi_1(dt J_M) for boxes of nl <= 80 points, one workgroup per (block,
+// member), everything in LDS: W = dt J_M / 2^s with |W|_1 <= 1/2, F = phi_1(W)
+// by its Taylor polynomial of degree 16 (Horner), E = e^W = I + W F, then s
+// doublings phi_1(2W) = phi_1(W)(e^W + I)/2, e^{2W} = (e^W)^2.  Products on
+// FP64 MFMA (16x16x4) over 16-padded tiles (row stride mp + 1 against LDS
+// bank conflicts); each product is formed in registers before it overwrites
+// its operand.  Writes the core rows of F into Phi[blk][row][l][s] and the
+// number of doublings into sq_out[blk * ns + s].
+typedef double d4e __attribute__((ext_vector_type(4)));
+constexpr int kPhiMaxN = 80;   // LDS: three 80x80 float64 matrices
+constexpr int kPhiTiles = 7;   // output tiles per wave (25 tiles, 4 waves)
+
+template <int NT>
+__device__ __forceinline__ void tiles_product(const double* A, const double* B, int mp, int ld,
+                                              d4e (&acc)[kPhiTiles]) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nt = mp / 16, tiles = nt * nt;
+#pragma unroll
+  for (int q = 0; q < kPhiTiles; ++q) {
+    acc[q] = (d4e){0.0, 0.0, 0.0, 0.0};
+    const int t = wv + q * (NT / 64);
+    if (t < tiles) {
+      const int ti = t / nt, tj = t - ti * nt;
+      for (int k0 = 0; k0 < mp; k0 += 4) {
+        const double a = A[(ti * 16 + (lane & 15)) * ld + k0 + (lane >> 4)];
+        const double b = B[(k0 + (lane >> 4)) * ld + tj * 16 + (lane & 15)];
+        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[q], 0, 0, 0);
+      }
+    }
+  }
+}
+
+// C(i, j) = f(i, j, product(i, j)) for this thread's product entries
+template <int NT, typename Fn>
+__device__ __forceinline__ void tiles_store(const d4e (&acc)[kPhiTiles], int mp, Fn f) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nt = mp / 16, tiles = nt * nt;
+#pragma unroll
+  for (int q = 0; q < kPhiTiles; ++q) {
+    const int t = wv + q * (NT / 64);
+    if (t < tiles) {
+      const int ti = t / nt, tj = t - ti * nt;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) f(ti * 16 + 4 * r + (lane >> 4), tj * 16 + (lane & 15), acc[q][r]);
+    }
+  }
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void ere_phi1_kernel(const double* __restrict__ x,
+                                                      const EreBox* boxes, int ns, int nl,
+                                                      int rows, int n, double dt, double dx,
+                                                      double nu, double* Phi, int* sq_out,
+                                                      int* status) {
+  extern __shared__ double sm[];
+  const int mp = (nl + 15) / 16 * 16, mm = mp * mp, ld = mp + 1, ms = mp * ld;
+  double* W = sm;
+  double* F = sm + ms;
+  double* E = sm + 2 * ms;
+  double* red = sm + 3 * ms;  // NT/64 partial maxima
+  const int tid = threadIdx.x;
+  const int blk = blockIdx.x / ns, s = blockIdx.x - blk * ns;
+  const EreBox b = boxes[blk];
+  const double d = nu / (dx * dx), a = 1.0 / (2.0 * dx);
+  // W = dt J_M (zero padding)
+  for (int e = tid; e < mm; e += NT) {
+    const int r = e / mp, c = e - r * mp;
+    double v = 0.0;
+    if (r < nl && c < nl) {
+      const int lm = r > 0 ? r - 1 : (b.whole ? nl - 1 : -1);
+      const int lp = r < nl - 1 ? r + 1 : (b.whole ? 0 : -1);
+      if (c == r) v = -2.0 * d;
+      else if (c == lm) v = x[(int64_t)ere_wrap(b.ox - b.h + lm, n) * ns + s] * a + d;
+      else if (c == lp) v = -x[(int64_t)ere_wrap(b.ox - b.h + lp, n) * ns + s] * a + d;
+      v *= dt;
+    }
+    W[r * ld + c] = v;
+  }
+  __syncthreads();
+  // s = ceil(log2(|W|_1 / 0.5))
+  double cs = 0.0;
+  for (int c = tid; c < mp; c += NT) {
+    double t = 0.0;
+    for (int r = 0; r < mp; ++r) t += fabs(W[r * ld + c]);
+    cs = fmax(cs, t);
+  }
+  for (int off = 32; off > 0; off >>= 1) cs = fmax(cs, __shfl_xor(cs, off, 64));
+  if ((tid & 63) == 0) red[tid >> 6] = cs;
+  __syncthreads();
+  double nrm = 0.0;
+  for (int w = 0; w < NT / 64; ++w) nrm = fmax(nrm, red[w]);
+  int sq = 0;
+  if (nrm > 0.5 && nrm < 1e300) sq = min(40, (int)ceil(log2(nrm / 0.5)));
+  if (tid == 0) {
+    sq_out[blockIdx.x] = sq;
+    if (!(nrm < 1e300)) atomicOr(status, kStatusNonFinite);
+  }
+  const double scale = ldexp(1.0, -sq);
+  for (int e = tid; e < mm; e += NT) {
+    const int r = e / mp, c = e - r * mp;
+    W[r * ld + c] *= scale;
+    // Horner start: F = I / 17!
+    F[r * ld + c] = (r == c) ? 2.8114572543455207632e-15 : 0.0;
+  }
+  __syncthreads();
+  // F <- W F + I/(k+1)!  for k = 15 .. 0  (1/(k+1)! by repeated division)
+  double inv_fact = 2.8114572543455207632e-15 * 17.0;  // 1/16!
+  d4e acc[kPhiTiles];
+  for (int k = 15; k >= 0; --k) {
+    tiles_product<NT>(W, F, mp, ld, acc);
+    __syncthreads();
+    const double cdiag = inv_fact;  // 1/(k+1)!
+    tiles_store<NT>(acc, mp, [&](int i, int j, double v) { F[i * ld + j] = v + (i == j ? cdiag : 0.0); });
+    __syncthreads();
+    inv_fact *= (double)(k + 1);
+  }
+  // E = I + W F
+  tiles_product<NT>(W, F, mp, ld, acc);
+  tiles_store<NT>(acc, mp, [&](int i, int j, double v) { E[i * ld + j] = v + (i == j ? 1.0 : 0.0); });
+  __syncthreads();
+  // doublings
+  for (int q = 0; q < sq; ++q) {
+    tiles_product<NT>(F, E, mp, ld, acc);  // F e^W
+    __syncthreads();
+    tiles_store<NT>(acc, mp, [&](int i, int j, double v) { F[i * ld + j] = 0.5 * (v + F[i * ld + j]); });
+    __syncthreads();
+    tiles_product<NT>(E, E, mp, ld, acc);
+    __syncthreads();
+    tiles_store<NT>(acc, mp, [&](int i, int j, double v) { E[i * ld + j] = v; });
+    __syncthreads();
+  }
+  // core rows of F
+  const int64_t base = (int64_t)blk * rows * nl * ns;
+  for (int e = tid; e < rows * nl; e += NT) {
+    const int row = e / nl, l = e - row * nl;
+    Phi[base + ((int64_t)row * nl + l) * ns + s] = F[(b.h + row) * ld + l];
+  }
+}
+
 static inline dim3 ere_grid(int64_t total) {
   int64_t g = (total + 255) / 256;
   if (g > 16384) g = 16384;
@@ -126,6 +265,27 @@ static inline dim3 ere_grid(int64_t total) {
 }
 
 size_t ere_box_size() { return sizeof(EreBox); }
+
+int ere_phi1_max_n() { return kPhiMaxN; }
+
+hipError_t ere_phi1(const double* x, const void* boxes, int nb, int ns, int nl, int rows, int n,
+                    double dt, double dx, double nu, double* Phi, int* sq_out, int* status,
+                    hipStream_t st) {
+  if (nl < 3 || nl > kPhiMaxN) return hipErrorInvalidValue;
+  const int mp = (nl + 15) / 16 * 16;
+  const size_t lds = ((size_t)3 * mp * (mp + 1) + 8) * sizeof(double);
+  static bool attr = false;
+  if (!attr) {
+    const hipError_t e = hipFuncSetAttribute((const void*)ere_phi1_kernel<256>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)(((size_t)3 * kPhiMaxN * (kPhiMaxN + 1) + 8) * 8));
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL(ere_phi1_kernel<256>, dim3((unsigned)(nb * ns)), dim3(256), lds, st, x,
+                     (const EreBox*)boxes, ns, nl, rows, n, dt, dx, nu, Phi, sq_out, status);
+  return hipGetLastError();
+}
 
 void ere_box_fill(void* dst, int i, int ox, int h, int cx, int whole) {
   EreBox* b = (EreBox*)dst + i;

@@ -360,9 +360,12 @@ def _burgers_states(n, L, ns, seed):
     return np.column_stack([amp[k] * np.exp(-(x - x0[k]) ** 2) for k in range(ns)])
 
 
-@pytest.mark.parametrize("core,halo,refresh,ns", [(25, 8, 5, 2), (200, 0, 3, 2), (50, 15, 5, 64)])
-def test_rosenbrock_lem_matches_oracle(core, halo, refresh, ns):
-    n, L, nu = 200, 10.0, 0.05
+# boxes of 41 and 80 points and the 60-point whole grid take the one-launch
+# LDS phi_1 kernel; the 200-point whole grid takes the Pade pipeline
+@pytest.mark.parametrize("n,core,halo,refresh,ns", [(200, 25, 8, 5, 2), (200, 200, 0, 3, 2),
+                                                    (200, 50, 15, 5, 64), (60, 60, 0, 4, 3)])
+def test_rosenbrock_lem_matches_oracle(n, core, halo, refresh, ns):
+    L, nu = 10.0 * n / 200, 0.05
     dx = L / n
     dt = dx  # Courant number ~1 for |u| ~ 1, mu = 2
     u0 = _burgers_states(n, L, ns, 3)
