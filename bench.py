@@ -34,7 +34,7 @@ MFMA_FP32_PEAK_TFLOPS = 157.3
 # (autotuner id), from rocprofv3 FETCH_SIZE / WRITE_SIZE passes scaled by a
 # 256 MiB reference copy; valid only for the dense.hip source they were taken
 # on: profiles/apply_fp64_2d256x256x64_h14.md
-TRAFFIC = {"dense.hip": ("2c76b609a2a7", {0: 147102726, 1: 146209507, 2: 158012682, 3: 158041504})}
+TRAFFIC = {"dense.hip": ("c2607c071c0c", {0: 147884412, 1: 145228480, 2: 158008490, 3: 158090398})}
 
 
 def measured_traffic(tile):
@@ -112,6 +112,7 @@ def parse_args():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-global", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the float32 leg of c1")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run one device copy of this many MiB (a reference kernel of "
                          "known traffic for scaling HBM counters)")
@@ -171,13 +172,14 @@ def bench_c1(args) -> dict:
         f"{achieved:.1f} TFLOP/s")
 
     extras = {}
-    # float32 application of the same blocks
-    plan32 = lem.Plan(opr, p.dt, method="dense", precision="fp32", core=16, halo=h,
-                      n_states=ns, autotune=True)
-    plan32.step(x, y, args.warmup)
-    w32, e32 = timed_steps(plan32, x, y, args.steps, torch)
-    extras["lem_fp32"] = {"value": N * ns * args.steps / w32, "us_per_step": 1e3 * e32 / args.steps,
-                          "tflops": flops / (e32 / args.steps * 1e-3) / 1e12}
+    if not args.no_fp32:  # float32 application of the same blocks
+        plan32 = lem.Plan(opr, p.dt, method="dense", precision="fp32", core=16, halo=h,
+                          n_states=ns, autotune=True)
+        plan32.step(x, y, args.warmup)
+        w32, e32 = timed_steps(plan32, x, y, args.steps, torch)
+        extras["lem_fp32"] = {"value": N * ns * args.steps / w32,
+                              "us_per_step": 1e3 * e32 / args.steps,
+                              "tflops": flops / (e32 / args.steps * 1e-3) / 1e12}
 
     # accuracy against the exact global exponential (global Krylov, tol 1e-13)
     acc = {}

@@ -119,72 +119,101 @@ __global__ void ere_apply_kernel(const double* __restrict__ x, const double* __r
 }
 
 // phi_1(dt J_M) for boxes of nl <= 80 points, one workgroup per (block,
-// member), everything in LDS: W = dt J_M / 2^s with |W|_1 <= 1/2, F = phi_1(W)
-// by its Taylor polynomial of degree 16 (Horner), E = e^W = I + W F, then s
-// doublings phi_1(2W) = phi_1(W)(e^W + I)/2, e^{2W} = (e^W)^2.  Products on
-// FP64 MFMA (16x16x4) over 16-padded tiles (row stride mp + 1 against LDS
-// bank conflicts); each product is formed in registers before it overwrites
-// its operand.  Writes the core rows of F into Phi[blk][row][l][s] and the
-// number of doublings into sq_out[blk * ns + s].
+// member), all in LDS.  With W = dt J_M / 2^s scaled to |W|_1 <= 1:
+//   F = phi_1(W) = sum_{k<=17} W^k / (k+1)!   (remainder below 1/19! ~ 8e-18),
+// evaluated Paterson-Stockmeyer style as a polynomial in W^2 whose
+// coefficients are c_{2j} I + c_{2j+1} W (nine products instead of 17), then
+// E = e^W = I + W F and s doublings
+//   phi_1(2W) = phi_1(W) (e^W + I) / 2,   e^{2W} = (e^W)^2
+// (the last squaring is not needed).  Products on FP64 MFMA (16x16x4) over
+// 16-padded tiles, row stride MP + 1 against LDS bank conflicts; every product
+// is formed in registers and written after a barrier, so it may overwrite an
+// operand.  Writes the core rows of F into Phi[blk][row][l][s] and s into
+// sq_out[blk * ns + s].
 typedef double d4e __attribute__((ext_vector_type(4)));
-constexpr int kPhiMaxN = 80;   // LDS: three 80x80 float64 matrices
-constexpr int kPhiTiles = 7;   // output tiles per wave (25 tiles, 4 waves)
+constexpr int kPhiMaxN = 80;  // LDS: three 80 x 81 float64 matrices
+constexpr int kPhiNT = 512;   // 8 waves: two per SIMD
 
-template <int NT>
-__device__ __forceinline__ void tiles_product(const double* A, const double* B, int mp, int ld,
-                                              d4e (&acc)[kPhiTiles]) {
+struct InvFact {
+  double c[18];  // c[k] = 1 / (k+1)!
+  constexpr InvFact() : c() {
+    double v = 1.0;
+    for (int k = 0; k < 18; ++k) { v /= (double)(k + 1); c[k] = v; }
+  }
+};
+constexpr InvFact kInvFact;
+
+template <int MP, int NT>
+struct PhiTiles {
+  static constexpr int nt = MP / 16, tiles = nt * nt, nw = NT / 64;
+  static constexpr int tq = (tiles + nw - 1) / nw;  // tiles per wave (last may be absent)
+  static constexpr int ld = MP + 1;
+};
+
+// acc[q] = (A B) on this wave's output tiles t = wave + q * nw
+template <int MP, int NT>
+__device__ __forceinline__ void phi_product(const double* A, const double* B,
+                                            d4e (&acc)[PhiTiles<MP, NT>::tq]) {
+  using T = PhiTiles<MP, NT>;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int nt = mp / 16, tiles = nt * nt;
+  const bool last = wv + (T::tq - 1) * T::nw < T::tiles;
+  int ar[T::tq], bc[T::tq];
 #pragma unroll
-  for (int q = 0; q < kPhiTiles; ++q) {
+  for (int q = 0; q < T::tq; ++q) {
+    const int t = wv + q * T::nw, ti = t / T::nt, tj = t - ti * T::nt;
+    ar[q] = (ti * 16 + (lane & 15)) * T::ld + (lane >> 4);
+    bc[q] = (lane >> 4) * T::ld + tj * 16 + (lane & 15);
     acc[q] = (d4e){0.0, 0.0, 0.0, 0.0};
-    const int t = wv + q * (NT / 64);
-    if (t < tiles) {
-      const int ti = t / nt, tj = t - ti * nt;
-      for (int k0 = 0; k0 < mp; k0 += 4) {
-        const double a = A[(ti * 16 + (lane & 15)) * ld + k0 + (lane >> 4)];
-        const double b = B[(k0 + (lane >> 4)) * ld + tj * 16 + (lane & 15)];
+  }
+#pragma unroll
+  for (int k0 = 0; k0 < MP; k0 += 4) {
+#pragma unroll
+    for (int q = 0; q < T::tq; ++q) {
+      if (q < T::tq - 1 || last) {
+        const double a = A[ar[q] + k0];
+        const double b = B[bc[q] + k0 * T::ld];
         acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[q], 0, 0, 0);
       }
     }
   }
 }
 
-// C(i, j) = f(i, j, product(i, j)) for this thread's product entries
-template <int NT, typename Fn>
-__device__ __forceinline__ void tiles_store(const d4e (&acc)[kPhiTiles], int mp, Fn f) {
+// f(i, j, (A B)(i, j)) over this thread's entries of the product
+template <int MP, int NT, typename Fn>
+__device__ __forceinline__ void phi_store(const d4e (&acc)[PhiTiles<MP, NT>::tq], Fn f) {
+  using T = PhiTiles<MP, NT>;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int nt = mp / 16, tiles = nt * nt;
+  const bool last = wv + (T::tq - 1) * T::nw < T::tiles;
 #pragma unroll
-  for (int q = 0; q < kPhiTiles; ++q) {
-    const int t = wv + q * (NT / 64);
-    if (t < tiles) {
-      const int ti = t / nt, tj = t - ti * nt;
+  for (int q = 0; q < T::tq; ++q) {
+    if (q < T::tq - 1 || last) {
+      const int t = wv + q * T::nw, ti = t / T::nt, tj = t - ti * T::nt;
 #pragma unroll
       for (int r = 0; r < 4; ++r) f(ti * 16 + 4 * r + (lane >> 4), tj * 16 + (lane & 15), acc[q][r]);
     }
   }
 }
 
-template <int NT>
+template <int MP, int NT>
 __global__ __launch_bounds__(NT) void ere_phi1_kernel(const double* __restrict__ x,
                                                       const EreBox* boxes, int ns, int nl,
                                                       int rows, int n, double dt, double dx,
                                                       double nu, double* Phi, int* sq_out,
                                                       int* status) {
+  using T = PhiTiles<MP, NT>;
+  constexpr int ld = T::ld, ms = MP * ld;
   extern __shared__ double sm[];
-  const int mp = (nl + 15) / 16 * 16, mm = mp * mp, ld = mp + 1, ms = mp * ld;
   double* W = sm;
-  double* F = sm + ms;
-  double* E = sm + 2 * ms;
+  double* W2 = sm + ms;  // W^2, later e^W
+  double* F = sm + 2 * ms;
   double* red = sm + 3 * ms;  // NT/64 partial maxima
   const int tid = threadIdx.x;
   const int blk = blockIdx.x / ns, s = blockIdx.x - blk * ns;
   const EreBox b = boxes[blk];
   const double d = nu / (dx * dx), a = 1.0 / (2.0 * dx);
   // W = dt J_M (zero padding)
-  for (int e = tid; e < mm; e += NT) {
-    const int r = e / mp, c = e - r * mp;
+  for (int e = tid; e < MP * MP; e += NT) {
+    const int r = e / MP, c = e - r * MP;
     double v = 0.0;
     if (r < nl && c < nl) {
       const int lm = r > 0 ? r - 1 : (b.whole ? nl - 1 : -1);
@@ -197,11 +226,11 @@ __global__ __launch_bounds__(NT) void ere_phi1_kernel(const double* __restrict__
     W[r * ld + c] = v;
   }
   __syncthreads();
-  // s = ceil(log2(|W|_1 / 0.5))
+  // s = ceil(log2 |W|_1)
   double cs = 0.0;
-  for (int c = tid; c < mp; c += NT) {
+  for (int c = tid; c < MP; c += NT) {
     double t = 0.0;
-    for (int r = 0; r < mp; ++r) t += fabs(W[r * ld + c]);
+    for (int r = 0; r < MP; ++r) t += fabs(W[r * ld + c]);
     cs = fmax(cs, t);
   }
   for (int off = 32; off > 0; off >>= 1) cs = fmax(cs, __shfl_xor(cs, off, 64));
@@ -210,44 +239,50 @@ __global__ __launch_bounds__(NT) void ere_phi1_kernel(const double* __restrict__
   double nrm = 0.0;
   for (int w = 0; w < NT / 64; ++w) nrm = fmax(nrm, red[w]);
   int sq = 0;
-  if (nrm > 0.5 && nrm < 1e300) sq = min(40, (int)ceil(log2(nrm / 0.5)));
+  if (nrm > 1.0 && nrm < 1e300) sq = min(40, (int)ceil(log2(nrm)));
   if (tid == 0) {
     sq_out[blockIdx.x] = sq;
     if (!(nrm < 1e300)) atomicOr(status, kStatusNonFinite);
   }
   const double scale = ldexp(1.0, -sq);
-  for (int e = tid; e < mm; e += NT) {
-    const int r = e / mp, c = e - r * mp;
+  for (int e = tid; e < MP * MP; e += NT) {
+    const int r = e / MP, c = e - r * MP;
     W[r * ld + c] *= scale;
-    // Horner start: F = I / 17!
-    F[r * ld + c] = (r == c) ? 2.8114572543455207632e-15 : 0.0;
   }
   __syncthreads();
-  // F <- W F + I/(k+1)!  for k = 15 .. 0  (1/(k+1)! by repeated division)
-  double inv_fact = 2.8114572543455207632e-15 * 17.0;  // 1/16!
-  d4e acc[kPhiTiles];
-  for (int k = 15; k >= 0; --k) {
-    tiles_product<NT>(W, F, mp, ld, acc);
-    __syncthreads();
-    const double cdiag = inv_fact;  // 1/(k+1)!
-    tiles_store<NT>(acc, mp, [&](int i, int j, double v) { F[i * ld + j] = v + (i == j ? cdiag : 0.0); });
-    __syncthreads();
-    inv_fact *= (double)(k + 1);
-  }
-  // E = I + W F
-  tiles_product<NT>(W, F, mp, ld, acc);
-  tiles_store<NT>(acc, mp, [&](int i, int j, double v) { E[i * ld + j] = v + (i == j ? 1.0 : 0.0); });
+  d4e acc[T::tq], acc2[T::tq];
+  // W2 = W W;  F = c16 I + c17 W
+  phi_product<MP, NT>(W, W, acc);
+  phi_store<MP, NT>(acc, [&](int i, int j, double v) {
+    W2[i * ld + j] = v;
+    F[i * ld + j] = kInvFact.c[17] * W[i * ld + j] + (i == j ? kInvFact.c[16] : 0.0);
+  });
   __syncthreads();
-  // doublings
-  for (int q = 0; q < sq; ++q) {
-    tiles_product<NT>(F, E, mp, ld, acc);  // F e^W
+  // F <- F W^2 + c_{2j} I + c_{2j+1} W,  j = 7 .. 0
+#pragma unroll
+  for (int j = 7; j >= 0; --j) {
+    phi_product<MP, NT>(F, W2, acc);
     __syncthreads();
-    tiles_store<NT>(acc, mp, [&](int i, int j, double v) { F[i * ld + j] = 0.5 * (v + F[i * ld + j]); });
+    phi_store<MP, NT>(acc, [&](int i, int c, double v) {
+      F[i * ld + c] = v + kInvFact.c[2 * j + 1] * W[i * ld + c] + (i == c ? kInvFact.c[2 * j] : 0.0);
+    });
     __syncthreads();
-    tiles_product<NT>(E, E, mp, ld, acc);
+  }
+  if (sq > 0) {
+    double* E = W2;
+    // E = I + W F (W^2 is no longer read)
+    phi_product<MP, NT>(W, F, acc);
+    phi_store<MP, NT>(acc, [&](int i, int j, double v) { E[i * ld + j] = v + (i == j ? 1.0 : 0.0); });
     __syncthreads();
-    tiles_store<NT>(acc, mp, [&](int i, int j, double v) { E[i * ld + j] = v; });
-    __syncthreads();
+    for (int q = 0; q < sq; ++q) {
+      const bool square = q + 1 < sq;  // wave-uniform
+      phi_product<MP, NT>(F, E, acc);  // F e^W
+      if (square) phi_product<MP, NT>(E, E, acc2);
+      __syncthreads();
+      phi_store<MP, NT>(acc, [&](int i, int j, double v) { F[i * ld + j] = 0.5 * (v + F[i * ld + j]); });
+      if (square) phi_store<MP, NT>(acc2, [&](int i, int j, double v) { E[i * ld + j] = v; });
+      __syncthreads();
+    }
   }
   // core rows of F
   const int64_t base = (int64_t)blk * rows * nl * ns;
@@ -255,6 +290,23 @@ __global__ __launch_bounds__(NT) void ere_phi1_kernel(const double* __restrict__
     const int row = e / nl, l = e - row * nl;
     Phi[base + ((int64_t)row * nl + l) * ns + s] = F[(b.h + row) * ld + l];
   }
+}
+
+template <int MP>
+static hipError_t launch_phi1(const double* x, const void* boxes, int nb, int ns, int nl,
+                              int rows, int n, double dt, double dx, double nu, double* Phi,
+                              int* sq_out, int* status, hipStream_t st) {
+  const size_t lds = ((size_t)3 * MP * (MP + 1) + kPhiNT / 64) * sizeof(double);
+  static bool attr = false;
+  if (!attr) {
+    const hipError_t e = hipFuncSetAttribute((const void*)ere_phi1_kernel<MP, kPhiNT>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL((ere_phi1_kernel<MP, kPhiNT>), dim3((unsigned)(nb * ns)), dim3(kPhiNT), lds,
+                     st, x, (const EreBox*)boxes, ns, nl, rows, n, dt, dx, nu, Phi, sq_out, status);
+  return hipGetLastError();
 }
 
 static inline dim3 ere_grid(int64_t total) {
@@ -271,20 +323,14 @@ int ere_phi1_max_n() { return kPhiMaxN; }
 hipError_t ere_phi1(const double* x, const void* boxes, int nb, int ns, int nl, int rows, int n,
                     double dt, double dx, double nu, double* Phi, int* sq_out, int* status,
                     hipStream_t st) {
-  if (nl < 3 || nl > kPhiMaxN) return hipErrorInvalidValue;
-  const int mp = (nl + 15) / 16 * 16;
-  const size_t lds = ((size_t)3 * mp * (mp + 1) + 8) * sizeof(double);
-  static bool attr = false;
-  if (!attr) {
-    const hipError_t e = hipFuncSetAttribute((const void*)ere_phi1_kernel<256>,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                                             (int)(((size_t)3 * kPhiMaxN * (kPhiMaxN + 1) + 8) * 8));
-    if (e != hipSuccess) return e;
-    attr = true;
+  if (nl < 3 || nl > kPhiMaxN || nb < 1 || ns < 1) return hipErrorInvalidValue;
+  switch ((nl + 15) / 16) {
+    case 1: return launch_phi1<16>(x, boxes, nb, ns, nl, rows, n, dt, dx, nu, Phi, sq_out, status, st);
+    case 2: return launch_phi1<32>(x, boxes, nb, ns, nl, rows, n, dt, dx, nu, Phi, sq_out, status, st);
+    case 3: return launch_phi1<48>(x, boxes, nb, ns, nl, rows, n, dt, dx, nu, Phi, sq_out, status, st);
+    case 4: return launch_phi1<64>(x, boxes, nb, ns, nl, rows, n, dt, dx, nu, Phi, sq_out, status, st);
+    default: return launch_phi1<80>(x, boxes, nb, ns, nl, rows, n, dt, dx, nu, Phi, sq_out, status, st);
   }
-  hipLaunchKernelGGL(ere_phi1_kernel<256>, dim3((unsigned)(nb * ns)), dim3(256), lds, st, x,
-                     (const EreBox*)boxes, ns, nl, rows, n, dt, dx, nu, Phi, sq_out, status);
-  return hipGetLastError();
 }
 
 void ere_box_fill(void* dst, int i, int ox, int h, int cx, int whole) {
