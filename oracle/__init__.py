@@ -27,6 +27,8 @@ decomposition approach to exponential time integration of PDEs"):
   phi.py        phi_1 and the exponential-Euler form of update (5)
   rosenbrock.py exponential Rosenbrock-Euler LEM for Burgers (sections 3, 4.2)
                 with a Jacobian frozen between refreshes
+  schrodinger.py LEM for the 1D Schroedinger equation with a harmonic
+                potential (section 4.1), complex local exponentials
   metrics.py    relative l2 / l-infinity errors
 """
-from . import operator, partition, halo, expm, krylov, lem, globalexp, phi, metrics, rosenbrock  # noqa: F401
+from . import operator, partition, halo, expm, krylov, lem, globalexp, phi, metrics, rosenbrock, schrodinger  # noqa: F401

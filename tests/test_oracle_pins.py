@@ -19,6 +19,7 @@ from oracle import operator as op
 from oracle import partition as P
 from oracle import phi as PHI
 from oracle import rosenbrock as ROS
+from oracle import schrodinger as SCH
 from oracle.metrics import rel_l2, rel_linf
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -560,3 +561,79 @@ def test_halo_rule_and_tie_acceptance():
     assert not clamped and H.eps(co, h, 1) <= 1e-6 < H.eps(co, h - 1, 1)
     assert H.accepts(co, 1, 1e-6, 4, h) and not H.accepts(co, 1, 1e-6, 4, h + 1)
     assert H.halo_width(co, 1, 1e-30, 4, 10) == (10, True)
+
+
+# --------------------------------------------------------- Schroedinger ----
+
+def test_schrodinger_propagator_matches_eigendecomposition():
+    """exp(-i dt H) of the oracle (complex Pade) against V exp(-i dt Lambda) V^T
+    from the symmetric eigendecomposition of H, a different route."""
+    n, Lx, kappa = 64, 10.0, 10.0
+    dx = Lx / n
+    dt = 4.0 * dx * dx
+    H = SCH.hamiltonian(n, Lx, kappa).toarray()
+    assert np.array_equal(H, H.T)
+    lam, V = np.linalg.eigh(H)
+    want = (V * np.exp(-1j * dt * lam)) @ V.T
+    got = SCH.global_propagator(n, Lx, kappa, dt)
+    assert np.abs(got - want).max() <= 1e-12
+    # unitary: the global step conserves the l2 norm
+    c = SCH.coherent_state(SCH.grid(n, Lx), kappa, 1.0, 2.0)
+    assert abs(np.linalg.norm(got @ c) - np.linalg.norm(c)) <= 1e-12 * np.linalg.norm(c)
+
+
+def test_schrodinger_free_plane_wave_closed_form():
+    """kappa = 0: a discrete plane wave exp(i k x_j), k = 2 pi m / L, is an
+    eigenvector of H with eigenvalue (1 - cos(k dx)) / dx^2."""
+    n, Lx = 48, 10.0
+    dx = Lx / n
+    dt = 0.3
+    x = SCH.grid(n, Lx)
+    for m in (0, 1, 5, n // 2 - 1):
+        k = 2 * np.pi * m / Lx
+        c0 = np.exp(1j * k * x)
+        lam = (1.0 - np.cos(k * dx)) / (dx * dx)
+        got = SCH.global_run(c0, Lx, 0.0, dt, 3)
+        assert np.abs(got - np.exp(-3j * dt * lam) * c0).max() <= 1e-11
+
+
+def _phase_aligned_rel(a, ref):
+    ph = np.vdot(ref, a)
+    return np.linalg.norm(a - ref * ph / abs(ph)) / np.linalg.norm(a)
+
+
+def test_schrodinger_coherent_state_second_order_in_space():
+    """The semi-discrete solution of a coherent state follows the continuous
+    one (Gaussian of fixed width whose centre moves as x0 cos(sqrt(kappa) t))
+    with the O(dx^2) error of centered differences: halving dx divides the
+    error at T = 0.5 by about 4."""
+    Lx, kappa, T = 10.0, 10.0, 0.5
+    errs = []
+    for n in (100, 200):
+        dx = Lx / n
+        steps = 50
+        dt = T / steps
+        x = SCH.grid(n, Lx)
+        c = SCH.global_run(SCH.coherent_state(x, kappa, 1.0), Lx, kappa, dt, steps)
+        errs.append(_phase_aligned_rel(c, SCH.coherent_state_exact(x, kappa, 1.0, T)))
+    assert errs[1] < 0.05
+    assert 3.5 < errs[0] / errs[1] < 4.5
+
+
+def test_schrodinger_lem_single_domain_and_halo_convergence():
+    """D = 1 (core = n, halo = 0) is the global method; with D > 1 the LEM
+    error against it falls as the buffer widens."""
+    n, Lx, kappa = 120, 10.0, 10.0
+    dx = Lx / n
+    dt = 2 * 4 * dx * dx  # mu = 4
+    x = SCH.grid(n, Lx)
+    c0 = np.column_stack([SCH.coherent_state(x, kappa, 1.0), SCH.coherent_state(x, kappa, -2.0, 3.0)])
+    g = SCH.global_run(c0, Lx, kappa, dt, 6)
+
+    def crel(a, b):
+        return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+    assert crel(SCH.lem_run(c0, Lx, kappa, dt, 6, n, 0), g) <= 1e-13
+    errs = [crel(SCH.lem_run(c0, Lx, kappa, dt, 6, 30, h), g) for h in (4, 8, 12, 16, 20)]
+    assert all(b < a for a, b in zip(errs, errs[1:]))
+    assert errs[0] > 1e-2 and errs[-1] < 1e-6
