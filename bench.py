@@ -116,12 +116,13 @@ def parse_args():
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run one device copy of this many MiB (a reference kernel of "
                          "known traffic for scaling HBM counters)")
-    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2", "c3", "c4", "f1", "f2"],
+    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2", "c3", "c4", "f1", "f2", "f3"],
                     help="c1 (default): 256^2 x 64 states, dense FP64; c0: 1D 1024; "
                          "c2: 1024^2 lognormal nu, uneven Krylov; c3: 512^2 x 128 states, "
                          "mixed precision; c4: served Poisson stream; f1: c1 with a "
                          "constant source g (exponential-Euler step with forcing); f2: "
-                         "Burgers by exponential Rosenbrock-Euler LEM")
+                         "Burgers by exponential Rosenbrock-Euler LEM; f3: Schroedinger with a "
+                         "harmonic potential (complex blocks in real form)")
     ap.add_argument("--requests", type=int, default=300)
     return ap.parse_args()
 
@@ -134,7 +135,7 @@ def main() -> int:
               "which is not implemented here)", file=sys.stderr)
         return 2
     fn = {"c1": bench_c1, "c0": bench_c0, "c2": bench_c2, "c3": bench_c3,
-          "c4": bench_c4, "f1": bench_f1, "f2": bench_f2}[args.workload]
+          "c4": bench_c4, "f1": bench_f1, "f2": bench_f2, "f3": bench_f3}[args.workload]
     out = fn(args)
     print(json.dumps(out), flush=True)
     return 0
@@ -382,6 +383,100 @@ def bench_f2(args) -> dict:
                 "n": n, "n_states": ns, "core": 50, "halo": 15, "refresh": K}
     return _line(args, workload, value, "DOF-steps/s", steps, out["lem_d8_b15"]["wall_s"], "f64",
                  extras)
+
+
+def bench_f3(args) -> dict:
+    """1D Schroedinger with a harmonic potential (kappa = 10) on 400 points of
+    [-5, 5), T = 1, 4096 Gaussian wave packets: LEM with stored complex local
+    exponentials (4 regions of 100 points) at the two settings of the paper's
+    Schroedinger table, mu = 2 with 20-point buffers and mu = 4 with 25, against
+    the global method (D = 1) on the same GPU; the complex blocks are applied
+    in real form on FP64 MFMA."""
+    import numpy as np
+    import torch
+    import lem_inputs as L
+    import paper_1505_02248_amd as lem
+    torch.cuda.init()
+    n, Lx, kappa, ns, T = 400, 10.0, 10.0, 4096, 1.0
+    dx = Lx / n
+    c0 = L.gaussian_wavepackets(n, Lx, kappa, ns, seed=13)
+    x = lem.SchrodingerPlan.to_real_form(torch.from_numpy(c0)).to("cuda")
+    y = torch.empty_like(x)
+    runs = {}
+    for mu, B in ((2, 20), (4, 25)):
+        dt = 2 * mu * dx * dx
+        steps = int(round(T / dt))
+        for D, core, halo in ((4, 100, B), (1, n, 0)):
+            t0 = time.perf_counter()
+            plan = lem.SchrodingerPlan(n, Lx, kappa, dt, n_states=ns, core=core, halo=halo,
+                                       autotune=True)
+            torch.cuda.synchronize()
+            t_plan = time.perf_counter() - t0
+            plan.step(x, y, args.warmup)
+            torch.cuda.synchronize()
+            wall, ev_ms = timed_steps(plan, x, y, steps, torch)
+            q = plan.query()
+            key = f"mu{mu}_B{B}_D{D}"
+            runs[key] = {"dof_steps_per_s": n * ns * steps / wall, "ms_per_step": 1e3 * wall / steps,
+                         "us_per_launch": 1e3 * ev_ms / steps, "plan_s": t_plan, "steps": steps,
+                         "time_to_solution_s": t_plan + wall, "squarings": q["squarings"],
+                         "tile": q["tile_config"], "state": y.clone()}
+            log(f"{key}: {runs[key]['dof_steps_per_s']:.3e} DOF-steps/s, "
+                f"{runs[key]['us_per_launch']:.1f} us/step, plan {t_plan:.3f} s")
+    extras = {}
+    for mu, B in ((2, 20), (4, 25)):
+        a, g = runs[f"mu{mu}_B{B}_D4"], runs[f"mu{mu}_B{B}_D1"]
+        err = (torch.linalg.norm(a["state"] - g["state"]) / torch.linalg.norm(g["state"])).item()
+        extras[f"mu{mu}_B{B}"] = {
+            "lem_d4": {k: v for k, v in a.items() if k != "state"},
+            "global_d1": {k: v for k, v in g.items() if k != "state"},
+            "lem_vs_global_rel_l2": err,
+            "lem_over_global_steps": a["dof_steps_per_s"] / g["dof_steps_per_s"],
+            "lem_over_global_time_to_solution": g["time_to_solution_s"] / a["time_to_solution_s"]}
+    head = runs["mu2_B20_D4"]
+    rows, cols, nb = 200, 2 * (100 + 2 * 20), 4
+    flops = 2.0 * rows * cols * nb * ns
+    achieved = flops / (head["us_per_launch"] * 1e-6) / 1e12
+    roof = {"bound": "mfma", "achieved": achieved, "peak": MFMA_FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / MFMA_FP64_PEAK_TFLOPS, "traffic": None,
+            "kernel": "apply_mfma_kernel<double>", "flops_per_launch": flops,
+            "us_per_launch": head["us_per_launch"]}
+    workload = {"workload": "1D Schroedinger c_t = (i/2) c_xx - i (kappa/2) x^2 c, kappa=10, 400 "
+                            "points of [-5,5), T=1, 4096 Gaussian wave packets; LEM with stored "
+                            "complex local exponentials (fp64 Pade, real form), 4 regions of 100 "
+                            "points, mu=2 (dt=4dx^2, 400 steps), 20-point buffers",
+                "n": n, "n_states": ns, "core": 100, "halo": 20, "mu": 2}
+    steps = head["steps"]
+    line = _line(args, workload, head["dof_steps_per_s"], "DOF-steps/s", steps,
+                 head["ms_per_step"] * steps / 1e3, "f64", extras, roofline=roof)
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline_schrodinger(c0[:, :64], Lx, kappa, 4 * dx * dx, 100, 20,
+                                                        args.cpu_seconds)
+    return line
+
+
+def cpu_baseline_schrodinger(c0, Lx, kappa, dt, core, halo, budget_s):
+    """The oracle's complex LEM steps (numpy) on a sample of members."""
+    from oracle import schrodinger as SCH
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    n, k = c0.shape
+    t0 = time.perf_counter()
+    SCH.lem_blocks(n, Lx, kappa, dt, core, halo)  # local exponentials (excluded below)
+    t_blocks = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    SCH.lem_run(c0, Lx, kappa, dt, 50, core, halo)
+    per_step = max((time.perf_counter() - t0 - t_blocks) / 50, 1e-6)
+    steps = int(min(4000, max(50, budget_s / per_step)))
+    t0 = time.perf_counter()
+    SCH.lem_run(c0, Lx, kappa, dt, steps, core, halo)
+    el = max(time.perf_counter() - t0 - t_blocks, 1e-9)
+    return {"value": n * k * steps / el, "unit": "DOF-steps/s", "cores": int(cores),
+            "kind": "oracle", "sample": f"{steps} LEM steps of {k} members (local exponentials "
+            f"excluded)"}
 
 
 def bench_c0(args) -> dict:

@@ -196,6 +196,34 @@ typedef struct {
 lem_status lem_ere_plan(const lem_burgers* op, double dt, int32_t n_states, int32_t core,
                         int32_t halo, int32_t refresh, void* stream, lem_plan_t* out);
 
+/* 1D Schroedinger equation with a harmonic potential (section 4.1):
+ *   c_t = (i/2) c_xx - i (kappa/2) x^2 c on n >= 3 points x_j = -L/2 + j L/n,
+ * periodic, centered differences. */
+typedef struct {
+  int32_t n;
+  double L;      /* > 0 */
+  double kappa;  /* >= 0 */
+} lem_schrodinger;
+
+/* Plan LEM steps of the Schroedinger problem with stored complex local
+ * exponentials exp(-i dt H_M) (sections 3 and 4.1), cores of `core` nodes
+ * (dividing n) and `halo` buffer nodes per side; core = n with halo = 0 is
+ * the global method (D = 1, periodic coupling kept).  The complex state is
+ * carried in real form, interleaved per node: x[(2 j + c) * n_states + s] is
+ * the real (c = 0) or imaginary (c = 1) part of member s at node j, float64,
+ * device memory owned by the caller (2 n n_states doubles).  Every region has
+ * its own block (the potential varies); the blocks are the exponentials of
+ * the real forms dt [[0, H_M], [-H_M, 0]] by Pade [13/13] on the device, and
+ * a step is the dense method's MFMA application on a grid of 2n real
+ * unknowns (lem_plan_query reports that doubled geometry).  autotune != 0
+ * times the apply tile shapes when n_states % 64 == 0.  lem_step,
+ * lem_plan_query and lem_plan_destroy apply.  Errors: LEM_ERR_INVALID
+ * (sizes, dt, L, kappa), LEM_ERR_UNSUPPORTED (boxes above 2048 nodes),
+ * LEM_ERR_NOMEM, LEM_ERR_HIP. */
+lem_status lem_schrodinger_plan(const lem_schrodinger* op, double dt, int32_t n_states,
+                                int32_t core, int32_t halo, int32_t autotune, void* stream,
+                                lem_plan_t* out);
+
 /* y = exp(t A) x on the whole grid (no decomposition) by the Krylov method
  * of section 4.3, for n_states ensemble members (with op->forcing set:
  * y = exp(t A) x + phi_1(t A)(t g)); device arrays, may not overlap.  Allocates and frees its own work space (a plan with

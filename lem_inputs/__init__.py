@@ -125,6 +125,22 @@ def gaussian_members(n: int, length: float, n_states: int, seed: int) -> np.ndar
                                                  for k in range(n_states)]))
 
 
+def gaussian_wavepackets(n: int, length: float, kappa: float, n_states: int,
+                         seed: int) -> np.ndarray:
+    """Complex Gaussian wave packets exp(-sqrt(kappa) (x - x0)^2 / 2 + i p0 x)
+    on the n points x_j = -length/2 + j length/n (the Schroedinger initial
+    datum of section 4.1, oscillator ground-state width), per member
+    x0 ~ U(-2, 2) and p0 ~ U(-3, 3) (draw order: x0, p0).  Shape
+    (n, n_states), complex128."""
+    rng = np.random.default_rng(seed)
+    x = -0.5 * length + np.arange(n) * (length / n)
+    x0 = rng.uniform(-2.0, 2.0, n_states)
+    p0 = rng.uniform(-3.0, 3.0, n_states)
+    w = np.sqrt(kappa)
+    return np.ascontiguousarray(np.column_stack(
+        [np.exp(-0.5 * w * (x - x0[k]) ** 2 + 1j * p0[k] * x) for k in range(n_states)]))
+
+
 def white_noise_states(N: int, n_states: int, seed: int) -> np.ndarray:
     """iid N(0,1) states, shape (N, n_states) (rough stress inputs)."""
     rng = np.random.default_rng(seed)

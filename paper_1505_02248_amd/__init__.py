@@ -85,6 +85,7 @@ def load() -> ctypes.CDLL:
     lib.lem_step.argtypes = [VP, VP, VP, I32, VP]
     lib.lem_global_expmv.argtypes = [P(_Operator), D, VP, VP, I32, D, I32, VP]
     lib.lem_ere_plan.argtypes = [P(_Burgers), D, I32, I32, I32, I32, VP, P(VP)]
+    lib.lem_schrodinger_plan.argtypes = [P(_Schrodinger), D, I32, I32, I32, I32, VP, P(VP)]
     lib.lem_plan_query.argtypes = [VP, P(_Info)]
     lib.lem_plan_copy_maps.argtypes = [VP, P(I32), P(I32), P(I32)]
     lib.lem_plan_copy_krylov.argtypes = [VP, P(I32), P(I32)]
@@ -256,6 +257,10 @@ class _Burgers(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("dx", ctypes.c_double), ("nu", ctypes.c_double)]
 
 
+class _Schrodinger(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("L", ctypes.c_double), ("kappa", ctypes.c_double)]
+
+
 class _Grid1D:
     def __init__(self, n: int):
         self.N = int(n)
@@ -276,6 +281,42 @@ class ErePlan(Plan):
                                 int(refresh), ctypes.c_void_p(_stream_handle(stream)),
                                 ctypes.byref(h)))
         self._h = h
+
+
+class SchrodingerPlan(Plan):
+    """LEM steps of the 1D Schroedinger equation with a harmonic potential
+    (``lem_schrodinger_plan``).  States are real tensors of shape
+    (2 n, n_states) holding the complex field interleaved per node (real
+    part at row 2 j, imaginary part at row 2 j + 1); ``to_real_form`` and
+    ``from_real_form`` convert from and to complex (n, n_states) tensors.
+    ``query``/``maps`` report the doubled grid of 2 n real unknowns."""
+
+    def __init__(self, n: int, L: float, kappa: float, dt: float, n_states: int = 1,
+                 core: int = 100, halo: int = 20, autotune: bool = False, stream=None):
+        lib = load()
+        o = _Schrodinger()
+        o.n, o.L, o.kappa = int(n), float(L), float(kappa)
+        self.n = int(n)
+        self.op, self.dt, self.n_states, self.method = _Grid1D(2 * n), float(dt), int(n_states), "dense"
+        h = ctypes.c_void_p()
+        _check(lib.lem_schrodinger_plan(ctypes.byref(o), self.dt, int(n_states), int(core),
+                                        int(halo), 1 if autotune else 0,
+                                        ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(h)))
+        self._h = h
+
+    @staticmethod
+    def to_real_form(c):
+        """complex (n, ns) torch tensor -> float64 (2 n, ns), interleaved per node."""
+        import torch
+        n, ns = c.shape
+        return torch.view_as_real(c.to(torch.complex128)).permute(0, 2, 1).contiguous().reshape(2 * n, ns)
+
+    @staticmethod
+    def from_real_form(x):
+        """float64 (2 n, ns) interleaved per node -> complex128 (n, ns)."""
+        import torch
+        n2, ns = x.shape
+        return torch.view_as_complex(x.reshape(n2 // 2, 2, ns).permute(0, 2, 1).contiguous())
 
 
 def global_expmv(op: Operator, t: float, x, y, n_states: int = 1, tol: float = 1e-13,

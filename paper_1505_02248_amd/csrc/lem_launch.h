@@ -53,6 +53,12 @@ hipError_t dense_apply(int precision, int cfg, const void* blocks, const void* E
                        int n, int ndim, int ns, int rows, int rows_p, int cols, int cols_p,
                        int n_blocks, const double* bias, hipStream_t st);
 
+// ---- Schroedinger with a harmonic potential, real form (schrodinger.hip)
+size_t sch_box_size();
+void sch_box_fill(void* dst, int i, int ox, int h, int whole);
+hipError_t sch_assemble(const void* boxes, int nb, int nl, int n, double L, double kappa,
+                        double dt, double* A, hipStream_t st);
+
 // ---- exponential Rosenbrock-Euler LEM for Burgers (rosenbrock.hip)
 size_t ere_box_size();
 void ere_box_fill(void* dst, int i, int ox, int h, int cx, int whole);
@@ -61,9 +67,11 @@ hipError_t ere_assemble(const double* x, const void* boxes, int nb, int ns, int 
 hipError_t ere_extract(const double* R, const void* boxes, int nb, int ns, int nl, int rows,
                        double* Phi, hipStream_t st);
 int ere_phi1_max_n();
+// phi_1 core rows of every (block, member) for boxes of <= ere_phi1_max_n()
+// points; P (nb * ns * rows * nl doubles) is work space, Phi the step layout.
 hipError_t ere_phi1(const double* x, const void* boxes, int nb, int ns, int nl, int rows, int n,
-                    double dt, double dx, double nu, double* Phi, int* sq_out, int* status,
-                    hipStream_t st);
+                    double dt, double dx, double nu, double* P, double* Phi, int* sq_out,
+                    int* status, hipStream_t st);
 hipError_t ere_step(const double* x, double* f, const double* Phi, const void* boxes, int nb,
                     int ns, int nl, int rows, int n, double dt, double dx, double nu, double* y,
                     hipStream_t st);

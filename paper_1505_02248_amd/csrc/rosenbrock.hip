@@ -119,26 +119,29 @@ __global__ void ere_apply_kernel(const double* __restrict__ x, const double* __r
 }
 
 // phi_1(dt J_M) for boxes of nl <= 80 points, one workgroup per (block,
-// member), all in LDS.  With W = dt J_M / 2^s scaled to |W|_1 <= 1:
-//   F = phi_1(W) = sum_{k<=17} W^k / (k+1)!   (remainder below 1/19! ~ 8e-18),
-// evaluated Paterson-Stockmeyer style as a polynomial in W^2 whose
-// coefficients are c_{2j} I + c_{2j+1} W (nine products instead of 17), then
-// E = e^W = I + W F and s doublings
+// member).  J_M is tridiagonal (periodic tridiagonal on the whole grid), so a
+// product W X costs three FMAs per entry.  With W = dt J_M / 2^s scaled to
+// |W|_1 <= 4:
+//   F = phi_1(W) = sum_{k<=30} W^k / (k+1)!   (remainder below 4^31/32! ~ 2e-17)
+// by Horner, F <- W F + I/(k+1)!, with F held in registers (each thread owns
+// one column and MP/8 consecutive rows; the rows next to a thread's segment
+// are exchanged through LDS), then E = e^W = I + W F and s doublings
 //   phi_1(2W) = phi_1(W) (e^W + I) / 2,   e^{2W} = (e^W)^2
-// (the last squaring is not needed).  Products on FP64 MFMA (16x16x4) over
-// 16-padded tiles, row stride MP + 1 against LDS bank conflicts; every product
-// is formed in registers and written after a barrier, so it may overwrite an
-// operand.  Writes the core rows of F into Phi[blk][row][l][s] and s into
-// sq_out[blk * ns + s].
+// (the last squaring is not needed): dense products on FP64 MFMA (16x16x4)
+// over 16-padded tiles, row stride MP + 1 against LDS bank conflicts; every
+// product is formed in registers and written after a barrier, so it may
+// overwrite an operand.  Writes the core rows of F, contiguous per matrix,
+// into P[blk * ns + s][row][l] and s into sq_out[blk * ns + s].
 typedef double d4e __attribute__((ext_vector_type(4)));
-constexpr int kPhiMaxN = 80;  // LDS: three 80 x 81 float64 matrices
-constexpr int kPhiNT = 512;   // 8 waves: two per SIMD
+constexpr int kPhiMaxN = 80;   // LDS: two 80 x 81 float64 matrices
+constexpr int kPhiDeg = 30;    // Taylor degree
+constexpr double kPhiTheta = 4.0;
 
 struct InvFact {
-  double c[18];  // c[k] = 1 / (k+1)!
+  double c[kPhiDeg + 1];  // c[k] = 1 / (k+1)!
   constexpr InvFact() : c() {
     double v = 1.0;
-    for (int k = 0; k < 18; ++k) { v /= (double)(k + 1); c[k] = v; }
+    for (int k = 0; k <= kPhiDeg; ++k) { v /= (double)(k + 1); c[k] = v; }
   }
 };
 constexpr InvFact kInvFact;
@@ -194,44 +197,87 @@ __device__ __forceinline__ void phi_store(const d4e (&acc)[PhiTiles<MP, NT>::tq]
   }
 }
 
-template <int MP, int NT>
-__global__ __launch_bounds__(NT) void ere_phi1_kernel(const double* __restrict__ x,
-                                                      const EreBox* boxes, int ns, int nl,
-                                                      int rows, int n, double dt, double dx,
-                                                      double nu, double* Phi, int* sq_out,
-                                                      int* status) {
+// Banded product on the register segment: out[m] = (W X)(r0 + m, j) + cdiag
+// on the diagonal, X given by this thread's xs[] plus the exchanged rows.
+template <int RS, int MP>
+__device__ __forceinline__ void band_step(const double (&xs)[RS], double (&out)[RS],
+                                          const double* wl, const double* wd, const double* wu,
+                                          const int* im, const int* ip, double* xch, double* lastrow,
+                                          int r0, int seg, int j, int nl, double cdiag) {
+  // publish this segment's first and last rows and, if held here, row nl - 1
+  xch[seg * MP + j] = xs[0];
+  xch[(8 + seg) * MP + j] = xs[RS - 1];
+#pragma unroll
+  for (int m = 0; m < RS; ++m)
+    if (r0 + m == nl - 1) lastrow[j] = xs[m];
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < RS; ++m) {
+    const int i = r0 + m;
+    double v = (i == j) ? cdiag : 0.0;
+    if (i < nl) {
+      const int a = im[i], c = ip[i];
+      double up = 0.0, dn = 0.0;
+      if (a >= 0) up = (a == i - 1) ? (m > 0 ? xs[m > 0 ? m - 1 : 0] : xch[(8 + seg - 1) * MP + j])
+                                    : lastrow[j];
+      if (c >= 0) dn = (c == i + 1) ? (m < RS - 1 ? xs[m < RS - 1 ? m + 1 : 0] : xch[(seg + 1) * MP + j])
+                                    : xch[j];  // wrap to row 0: first row of segment 0
+      v += wl[i] * up + wd[i] * xs[m] + wu[i] * dn;
+    }
+    out[m] = v;
+  }
+}
+
+template <int MP>
+__global__ __launch_bounds__(8 * MP) void ere_phi1_kernel(const double* __restrict__ x,
+                                                          const EreBox* boxes, int ns, int nl,
+                                                          int rows, int n, double dt, double dx,
+                                                          double nu, double* P, int* sq_out,
+                                                          int* status) {
+  constexpr int NT = 8 * MP, RS = MP / 8;
   using T = PhiTiles<MP, NT>;
   constexpr int ld = T::ld, ms = MP * ld;
   extern __shared__ double sm[];
-  double* W = sm;
-  double* W2 = sm + ms;  // W^2, later e^W
-  double* F = sm + 2 * ms;
-  double* red = sm + 3 * ms;  // NT/64 partial maxima
+  double* F = sm;
+  double* E = sm + ms;
+  double* wl = sm + 2 * ms;  // W(i, im[i]), W(i, i), W(i, ip[i])
+  double* wd = wl + MP;
+  double* wu = wd + MP;
+  double* xch = wu + MP;            // [parity][top 0..7 | bottom 8..15][MP]
+  double* lastrow = xch + 32 * MP;  // [parity][MP]
+  double* red = lastrow + 2 * MP;   // NT/64 partial maxima
+  int* im = (int*)(red + NT / 64);
+  int* ip = im + MP;
   const int tid = threadIdx.x;
+  const int j = tid % MP, seg = tid / MP, r0 = seg * RS;
   const int blk = blockIdx.x / ns, s = blockIdx.x - blk * ns;
   const EreBox b = boxes[blk];
   const double d = nu / (dx * dx), a = 1.0 / (2.0 * dx);
-  // W = dt J_M (zero padding)
-  for (int e = tid; e < MP * MP; e += NT) {
-    const int r = e / MP, c = e - r * MP;
-    double v = 0.0;
-    if (r < nl && c < nl) {
-      const int lm = r > 0 ? r - 1 : (b.whole ? nl - 1 : -1);
-      const int lp = r < nl - 1 ? r + 1 : (b.whole ? 0 : -1);
-      if (c == r) v = -2.0 * d;
-      else if (c == lm) v = x[(int64_t)ere_wrap(b.ox - b.h + lm, n) * ns + s] * a + d;
-      else if (c == lp) v = -x[(int64_t)ere_wrap(b.ox - b.h + lp, n) * ns + s] * a + d;
-      v *= dt;
+  // bands of dt J_M
+  if (tid < MP) {
+    const int r = tid;
+    int lm = -1, lp = -1;
+    double vl = 0.0, vd = 0.0, vu = 0.0;
+    if (r < nl) {
+      lm = r > 0 ? r - 1 : (b.whole ? nl - 1 : -1);
+      lp = r < nl - 1 ? r + 1 : (b.whole ? 0 : -1);
+      vd = -2.0 * d * dt;
+      if (lm >= 0) vl = (x[(int64_t)ere_wrap(b.ox - b.h + lm, n) * ns + s] * a + d) * dt;
+      if (lp >= 0) vu = (-x[(int64_t)ere_wrap(b.ox - b.h + lp, n) * ns + s] * a + d) * dt;
     }
-    W[r * ld + c] = v;
+    wl[r] = vl; wd[r] = vd; wu[r] = vu; im[r] = lm; ip[r] = lp;
   }
   __syncthreads();
-  // s = ceil(log2 |W|_1)
+  // |W|_1: column c collects wd[c] and the off-diagonals of the rows that point at c
   double cs = 0.0;
-  for (int c = tid; c < MP; c += NT) {
-    double t = 0.0;
-    for (int r = 0; r < MP; ++r) t += fabs(W[r * ld + c]);
-    cs = fmax(cs, t);
+  if (tid < MP) {
+    const int c = tid;
+    double t = fabs(wd[c]);
+    for (int r = 0; r < nl; ++r) {
+      if (im[r] == c) t += fabs(wl[r]);
+      if (ip[r] == c) t += fabs(wu[r]);
+    }
+    cs = t;
   }
   for (int off = 32; off > 0; off >>= 1) cs = fmax(cs, __shfl_xor(cs, off, 64));
   if ((tid & 63) == 0) red[tid >> 6] = cs;
@@ -239,73 +285,95 @@ __global__ __launch_bounds__(NT) void ere_phi1_kernel(const double* __restrict__
   double nrm = 0.0;
   for (int w = 0; w < NT / 64; ++w) nrm = fmax(nrm, red[w]);
   int sq = 0;
-  if (nrm > 1.0 && nrm < 1e300) sq = min(40, (int)ceil(log2(nrm)));
+  if (nrm > kPhiTheta && nrm < 1e300) sq = min(40, (int)ceil(log2(nrm / kPhiTheta)));
   if (tid == 0) {
     sq_out[blockIdx.x] = sq;
     if (!(nrm < 1e300)) atomicOr(status, kStatusNonFinite);
   }
+  __syncthreads();  // every thread has read the bands' norm
   const double scale = ldexp(1.0, -sq);
-  for (int e = tid; e < MP * MP; e += NT) {
-    const int r = e / MP, c = e - r * MP;
-    W[r * ld + c] *= scale;
-  }
-  __syncthreads();
-  d4e acc[T::tq], acc2[T::tq];
-  // W2 = W W;  F = c16 I + c17 W
-  phi_product<MP, NT>(W, W, acc);
-  phi_store<MP, NT>(acc, [&](int i, int j, double v) {
-    W2[i * ld + j] = v;
-    F[i * ld + j] = kInvFact.c[17] * W[i * ld + j] + (i == j ? kInvFact.c[16] : 0.0);
-  });
-  __syncthreads();
-  // F <- F W^2 + c_{2j} I + c_{2j+1} W,  j = 7 .. 0
+  if (tid < MP) { wl[tid] *= scale; wd[tid] *= scale; wu[tid] *= scale; }
+  // Horner: F = I/(q+1)!, then F <- W F + I/(k+1)! for k = q-1 .. 0
+  double f[RS], g[RS];
 #pragma unroll
-  for (int j = 7; j >= 0; --j) {
-    phi_product<MP, NT>(F, W2, acc);
-    __syncthreads();
-    phi_store<MP, NT>(acc, [&](int i, int c, double v) {
-      F[i * ld + c] = v + kInvFact.c[2 * j + 1] * W[i * ld + c] + (i == c ? kInvFact.c[2 * j] : 0.0);
-    });
-    __syncthreads();
+  for (int m = 0; m < RS; ++m) f[m] = (r0 + m == j) ? kInvFact.c[kPhiDeg] : 0.0;
+  int par = 0;
+  for (int k = kPhiDeg - 1; k >= 0; --k) {
+    band_step<RS, MP>(f, g, wl, wd, wu, im, ip, xch + par * 16 * MP, lastrow + par * MP, r0, seg,
+                      j, nl, kInvFact.c[k]);
+#pragma unroll
+    for (int m = 0; m < RS; ++m) f[m] = g[m];
+    par ^= 1;
   }
+#pragma unroll
+  for (int m = 0; m < RS; ++m) F[(r0 + m) * ld + j] = f[m];
   if (sq > 0) {
-    double* E = W2;
-    // E = I + W F (W^2 is no longer read)
-    phi_product<MP, NT>(W, F, acc);
-    phi_store<MP, NT>(acc, [&](int i, int j, double v) { E[i * ld + j] = v + (i == j ? 1.0 : 0.0); });
+    // E = I + W F
+    band_step<RS, MP>(f, g, wl, wd, wu, im, ip, xch + par * 16 * MP, lastrow + par * MP, r0, seg,
+                      j, nl, 1.0);
+#pragma unroll
+    for (int m = 0; m < RS; ++m) E[(r0 + m) * ld + j] = g[m];
     __syncthreads();
+    d4e acc[T::tq], acc2[T::tq];
     for (int q = 0; q < sq; ++q) {
       const bool square = q + 1 < sq;  // wave-uniform
       phi_product<MP, NT>(F, E, acc);  // F e^W
       if (square) phi_product<MP, NT>(E, E, acc2);
       __syncthreads();
-      phi_store<MP, NT>(acc, [&](int i, int j, double v) { F[i * ld + j] = 0.5 * (v + F[i * ld + j]); });
-      if (square) phi_store<MP, NT>(acc2, [&](int i, int j, double v) { E[i * ld + j] = v; });
+      phi_store<MP, NT>(acc, [&](int i, int c, double v) { F[i * ld + c] = 0.5 * (v + F[i * ld + c]); });
+      if (square) phi_store<MP, NT>(acc2, [&](int i, int c, double v) { E[i * ld + c] = v; });
       __syncthreads();
     }
+  } else {
+    __syncthreads();
   }
-  // core rows of F
-  const int64_t base = (int64_t)blk * rows * nl * ns;
+  // core rows of F (coalesced: one contiguous rows x nl block per matrix)
+  double* out = P + (int64_t)blockIdx.x * rows * nl;
   for (int e = tid; e < rows * nl; e += NT) {
     const int row = e / nl, l = e - row * nl;
-    Phi[base + ((int64_t)row * nl + l) * ns + s] = F[(b.h + row) * ld + l];
+    out[e] = F[(b.h + row) * ld + l];
+  }
+}
+
+// Phi[blk][k][s] = P[blk * ns + s][k] for k < K: per block a (ns x K) -> (K x ns)
+// transpose through 32 x 32 LDS tiles (so the step reads Phi member-fastest).
+__global__ __launch_bounds__(256) void ere_transpose_kernel(const double* __restrict__ P, int ns,
+                                                            int K, double* __restrict__ Phi) {
+  __shared__ double t[32][33];
+  const int blk = blockIdx.z;
+  const int k0 = blockIdx.x * 32, s0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const double* in = P + (int64_t)blk * ns * K;
+  double* o = Phi + (int64_t)blk * K * ns;
+#pragma unroll
+  for (int r = 0; r < 32; r += 8) {
+    const int sm = s0 + ty + r, k = k0 + tx;
+    if (sm < ns && k < K) t[ty + r][tx] = in[(int64_t)sm * K + k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 32; r += 8) {
+    const int k = k0 + ty + r, sm = s0 + tx;
+    if (sm < ns && k < K) o[(int64_t)k * ns + sm] = t[tx][ty + r];
   }
 }
 
 template <int MP>
 static hipError_t launch_phi1(const double* x, const void* boxes, int nb, int ns, int nl,
-                              int rows, int n, double dt, double dx, double nu, double* Phi,
+                              int rows, int n, double dt, double dx, double nu, double* P,
                               int* sq_out, int* status, hipStream_t st) {
-  const size_t lds = ((size_t)3 * MP * (MP + 1) + kPhiNT / 64) * sizeof(double);
+  constexpr int NT = 8 * MP;
+  const size_t lds = ((size_t)2 * MP * (MP + 1) + 3 * MP + 34 * MP + NT / 64) * sizeof(double) +
+                     2 * MP * sizeof(int);
   static bool attr = false;
   if (!attr) {
-    const hipError_t e = hipFuncSetAttribute((const void*)ere_phi1_kernel<MP, kPhiNT>,
+    const hipError_t e = hipFuncSetAttribute((const void*)ere_phi1_kernel<MP>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL((ere_phi1_kernel<MP, kPhiNT>), dim3((unsigned)(nb * ns)), dim3(kPhiNT), lds,
-                     st, x, (const EreBox*)boxes, ns, nl, rows, n, dt, dx, nu, Phi, sq_out, status);
+  hipLaunchKernelGGL(ere_phi1_kernel<MP>, dim3((unsigned)(nb * ns)), dim3(NT), lds, st, x,
+                     (const EreBox*)boxes, ns, nl, rows, n, dt, dx, nu, P, sq_out, status);
   return hipGetLastError();
 }
 
@@ -321,16 +389,23 @@ size_t ere_box_size() { return sizeof(EreBox); }
 int ere_phi1_max_n() { return kPhiMaxN; }
 
 hipError_t ere_phi1(const double* x, const void* boxes, int nb, int ns, int nl, int rows, int n,
-                    double dt, double dx, double nu, double* Phi, int* sq_out, int* status,
-                    hipStream_t st) {
-  if (nl < 3 || nl > kPhiMaxN || nb < 1 || ns < 1) return hipErrorInvalidValue;
+                    double dt, double dx, double nu, double* P, double* Phi, int* sq_out,
+                    int* status, hipStream_t st) {
+  if (nl < 3 || nl > kPhiMaxN || nb < 1 || ns < 1 || rows < 1 || rows > nl)
+    return hipErrorInvalidValue;
+  hipError_t e;
   switch ((nl + 15) / 16) {
-    case 1: return launch_phi1<16>(x, boxes, nb, ns, nl, rows, n, dt, dx, nu, Phi, sq_out, status, st);
-    case 2: return launch_phi1<32>(x, boxes, nb, ns, nl, rows, n, dt, dx, nu, Phi, sq_out, status, st);
-    case 3: return launch_phi1<48>(x, boxes, nb, ns, nl, rows, n, dt, dx, nu, Phi, sq_out, status, st);
-    case 4: return launch_phi1<64>(x, boxes, nb, ns, nl, rows, n, dt, dx, nu, Phi, sq_out, status, st);
-    default: return launch_phi1<80>(x, boxes, nb, ns, nl, rows, n, dt, dx, nu, Phi, sq_out, status, st);
+    case 1: e = launch_phi1<16>(x, boxes, nb, ns, nl, rows, n, dt, dx, nu, P, sq_out, status, st); break;
+    case 2: e = launch_phi1<32>(x, boxes, nb, ns, nl, rows, n, dt, dx, nu, P, sq_out, status, st); break;
+    case 3: e = launch_phi1<48>(x, boxes, nb, ns, nl, rows, n, dt, dx, nu, P, sq_out, status, st); break;
+    case 4: e = launch_phi1<64>(x, boxes, nb, ns, nl, rows, n, dt, dx, nu, P, sq_out, status, st); break;
+    default: e = launch_phi1<80>(x, boxes, nb, ns, nl, rows, n, dt, dx, nu, P, sq_out, status, st); break;
   }
+  if (e != hipSuccess) return e;
+  const int K = rows * nl;
+  hipLaunchKernelGGL(ere_transpose_kernel, dim3((unsigned)((K + 31) / 32), (unsigned)((ns + 31) / 32),
+                     (unsigned)nb), dim3(256), 0, st, P, ns, K, Phi);
+  return hipGetLastError();
 }
 
 void ere_box_fill(void* dst, int i, int ox, int h, int cx, int whole) {

@@ -17,6 +17,7 @@ from oracle import lem as olem
 from oracle import operator as op
 from oracle import partition as P
 from oracle import rosenbrock as ROS
+from oracle import schrodinger as SCH
 from oracle.metrics import rel_l2
 
 pytestmark = pytest.mark.gpu
@@ -377,3 +378,28 @@ def test_rosenbrock_lem_matches_oracle(n, core, halo, refresh, ns):
     assert rel_l2(got, want) <= 1e-12
     if core == n:  # D = 1: the global method conserves the total exactly
         assert np.abs(got.sum(0) - u0.sum(0)).max() <= 1e-10
+
+
+# 1D Schroedinger with a harmonic potential: complex local exponentials in
+# real form on the doubled grid (per-region blocks), against the complex oracle
+@pytest.mark.parametrize("n,core,halo,ns,steps", [(200, 50, 10, 64, 5), (120, 40, 12, 3, 4),
+                                                  (60, 60, 0, 5, 3), (400, 100, 20, 128, 3)])
+def test_schrodinger_lem_matches_oracle(n, core, halo, ns, steps):
+    import torch
+    Lx, kappa = 10.0, 10.0
+    dx = Lx / n
+    dt = 2 * 2 * dx * dx  # mu = 2 with nu = 1/2
+    c0 = L.gaussian_wavepackets(n, Lx, kappa, ns, seed=5)
+    plan = lem.SchrodingerPlan(n, Lx, kappa, dt, n_states=ns, core=core, halo=halo,
+                               autotune=(ns % 64 == 0))
+    x = lem.SchrodingerPlan.to_real_form(torch.from_numpy(c0)).to("cuda")
+    y = torch.empty_like(x)
+    plan.step(x, y, steps)
+    torch.cuda.synchronize()
+    got = lem.SchrodingerPlan.from_real_form(y.cpu()).numpy()
+    want = SCH.lem_run(c0, Lx, kappa, dt, steps, core, halo)
+    assert np.linalg.norm(got - want) / np.linalg.norm(want) <= 1e-12
+    q = plan.query()
+    assert q["n_blocks"] == n // core and q["device_status"] == 0
+    if core == n:  # the global step is unitary
+        assert np.abs(np.linalg.norm(got, axis=0) - np.linalg.norm(c0, axis=0)).max() <= 1e-10
