@@ -32,6 +32,10 @@ class Problem:
     nu_field  per-node diffusivity, shape (n,) or (n, n) [y, x], float64
     states    initial states, shape (N, n_states) with N = n**ndim, DOF
               index j*n + i (x fastest), ensemble index fastest in memory
+    vel_faces optional face velocities replacing ``vel``, shape (ndim, ny, n):
+              a_x on the east face (i+1/2, j) of every node, a_y on its north
+              face (i, j+1/2)
+    dy        y spacing when it differs from dx (anisotropic mesh), else None
     """
 
     ndim: int
@@ -43,6 +47,8 @@ class Problem:
     nu_field: Optional[np.ndarray]
     states: np.ndarray
     meta: dict = field(default_factory=dict)
+    vel_faces: Optional[np.ndarray] = None
+    dy: Optional[float] = None
 
     @property
     def N(self) -> int:
@@ -214,6 +220,57 @@ def workload_2d_variable(n: int = 1024, seed: int = 2,
     st = smooth_states_2d(n, 1, seed + 100)
     return Problem(2, n, dx, dt_over_dx * dx, (1.0, 0.0), None, nuf, st,
                    meta={"name": "adv-diff-2d-lognormal", "seed": seed})
+
+
+def vortex_faces(n: int, speed: float = 1.0, height: float = 1.0) -> np.ndarray:
+    """Face velocities of a single periodic vortex on [0, 1) x [0, height),
+    n x n nodes (dx = 1/n, dy = height/n), from the stream function
+    psi(x, y) = (speed height / pi) sin^2(pi x) sin^2(pi y / height) sampled at
+    the cell corners (i+1/2, j+1/2):
+        a_x(i+1/2, j) = (psi(i+1/2, j+1/2) - psi(i+1/2, j-1/2)) / dy,
+        a_y(i, j+1/2) = -(psi(i+1/2, j+1/2) - psi(i-1/2, j+1/2)) / dx,
+    so the discrete divergence of the faces vanishes (up to rounding); the
+    flow turns about the centre like a solid body near it.  Shape (2, n, n)."""
+    dx, dy = 1.0 / n, height / n
+    xc = (np.arange(n) + 0.5) * dx
+    yc = (np.arange(n) + 0.5) * dy
+    psi = (speed * height / np.pi) * np.outer(np.sin(np.pi * yc / height) ** 2,
+                                             np.sin(np.pi * xc) ** 2)  # [j, i] at (i+1/2, j+1/2)
+    ax = (psi - np.roll(psi, 1, axis=0)) / dy
+    ay = -(psi - np.roll(psi, 1, axis=1)) / dx
+    return np.ascontiguousarray(np.stack([ax, ay]))
+
+
+def gaussian_blobs_2d(n: int, n_states: int, seed: int, height: float = 1.0) -> np.ndarray:
+    """Periodic Gaussian blobs on [0, 1) x [0, height): per member a centre
+    (U(0.2, 0.8), U(0.2, 0.8) height) and a width U(0.04, 0.1) in units of the
+    box side (draw order: cx, cy, width).  Shape (n*n, n_states)."""
+    rng = np.random.default_rng(seed)
+    cx = rng.uniform(0.2, 0.8, n_states)
+    cy = rng.uniform(0.2, 0.8, n_states)
+    w = rng.uniform(0.04, 0.1, n_states)
+    x = np.arange(n) / n
+    y = np.arange(n) / n
+    out = np.empty((n * n, n_states))
+    for k in range(n_states):
+        dxp = np.minimum(np.abs(x - cx[k]), 1 - np.abs(x - cx[k]))
+        dyp = np.minimum(np.abs(y - cy[k]), 1 - np.abs(y - cy[k]))
+        out[:, k] = np.exp(-(dyp[:, None] ** 2 + dxp[None, :] ** 2) / (2 * w[k] ** 2)).reshape(-1)
+    return out
+
+
+def workload_2d_vortex(n: int = 512, n_states: int = 16, seed: int = 5, courant: float = 2.0,
+                       nu: float = 1e-4) -> Problem:
+    """2D advection-diffusion -div(a c) + nu lap c (eq. ibv2d) with the single
+    periodic vortex of ``vortex_faces`` (unit peak speed scale), constant nu,
+    dt = courant * dx / max|a|, Gaussian blobs."""
+    dx = 1.0 / n
+    F = vortex_faces(n)
+    amax = float(np.abs(F).max())
+    st = gaussian_blobs_2d(n, n_states, seed)
+    return Problem(2, n, dx, courant * dx / amax, (0.0, 0.0), nu, None, st,
+                   meta={"name": "adv-diff-2d-vortex", "seed": seed, "courant": courant},
+                   vel_faces=F)
 
 
 @dataclass

@@ -22,6 +22,20 @@ conservative flux form d/dx(nu du/dx) with the arithmetic mean on faces:
 so that w_E(i) = mu_{i+1/2} - C/2, w_W(i) = mu_{i-1/2} + C/2 and
 w_0(i) = -(sum of the face mu's of node i).  Columns of dt*A then sum to zero
 (the scheme conserves mass), which the constant case also satisfies.
+
+A variable velocity enters in the conservative form -div(a c) of eq. ibv2d
+(section 4.3) with centered face fluxes a_{i+1/2} (c_i + c_{i+1}) / 2: given
+the face velocities a_x(i+1/2, j) and a_y(i, j+1/2), with
+alpha_{i+1/2} = dt a_x(i+1/2, j) / (2 dx) (and alpha on y faces with dy),
+
+    w_E = mu_e - alpha_e,  w_W = mu_w + alpha_w,  (likewise S, N)
+    w_0 = -(mu_e + mu_w + mu_n + mu_s) - (alpha_e - alpha_w + alpha_n - alpha_s).
+
+Columns still sum to zero for any face velocities; rows sum to zero (constant
+states are steady) when the discrete divergence of the faces vanishes, as it
+does exactly for faces taken from a stream function.  The y spacing dy may
+differ from dx (anisotropic meshes, section 4.3); then C_y = a_y dt / dy and
+mu_y = nu dt / dy^2.
 """
 from __future__ import annotations
 
@@ -53,38 +67,59 @@ class Weights:
 
 
 def weights(ndim: int, n: int, dx: float, dt: float, vel, nu=None,
-            nu_field=None) -> Weights:
-    """Weights of dt*A for the periodic advection-diffusion operator."""
+            nu_field=None, vel_faces=None, dy=None) -> Weights:
+    """Weights of dt*A for the periodic advection-diffusion operator.
+
+    vel_faces (optional, replaces vel): array of shape (ndim, ny, n), a_x on
+    the east face of each node and, in 2D, a_y on its north face.  dy: y
+    spacing (default dx)."""
     ny = 1 if ndim == 1 else n
     shape = (ny, n)
-    cx = vel[0] * dt / dx
-    cy = (vel[1] * dt / dx) if ndim == 2 else 0.0
+    dy = dx if dy is None else dy
     if nu_field is None:
         mu = nu * dt / (dx * dx)
+        muy = nu * dt / (dy * dy)
         mu_e = np.full(shape, mu)   # face (i+1/2, j)
         mu_w = np.full(shape, mu)   # face (i-1/2, j)
-        mu_n = np.full(shape, mu if ndim == 2 else 0.0)
-        mu_s = np.full(shape, mu if ndim == 2 else 0.0)
+        mu_n = np.full(shape, muy if ndim == 2 else 0.0)
+        mu_s = np.full(shape, muy if ndim == 2 else 0.0)
     else:
         f = np.asarray(nu_field, dtype=np.float64).reshape(shape)
         s = dt / (2.0 * dx * dx)
+        sy = dt / (2.0 * dy * dy)
         mu_e = (f + np.roll(f, -1, axis=1)) * s
         mu_w = (f + np.roll(f, 1, axis=1)) * s
         if ndim == 2:
-            mu_n = (f + np.roll(f, -1, axis=0)) * s
-            mu_s = (f + np.roll(f, 1, axis=0)) * s
+            mu_n = (f + np.roll(f, -1, axis=0)) * sy
+            mu_s = (f + np.roll(f, 1, axis=0)) * sy
         else:
             mu_n = np.zeros(shape)
             mu_s = np.zeros(shape)
-    wW = mu_w + cx / 2.0
-    wE = mu_e - cx / 2.0
+    if vel_faces is None:
+        cx = vel[0] * dt / dx
+        cy = (vel[1] * dt / dy) if ndim == 2 else 0.0
+        al_e = al_w = np.full(shape, cx / 2.0)
+        al_n = al_s = np.full(shape, cy / 2.0)
+    else:
+        F = np.asarray(vel_faces, dtype=np.float64).reshape((ndim,) + shape)
+        al_e = F[0] * (dt / (2.0 * dx))
+        al_w = np.roll(al_e, 1, axis=1)
+        if ndim == 2:
+            al_n = F[1] * (dt / (2.0 * dy))
+            al_s = np.roll(al_n, 1, axis=0)
+        else:
+            al_n = al_s = np.zeros(shape)
+    wW = mu_w + al_w
+    wE = mu_e - al_e
     if ndim == 2:
-        wS = mu_s + cy / 2.0
-        wN = mu_n - cy / 2.0
+        wS = mu_s + al_s
+        wN = mu_n - al_n
     else:
         wS = np.zeros(shape)
         wN = np.zeros(shape)
     w0 = -(mu_e + mu_w + mu_n + mu_s)
+    if vel_faces is not None:
+        w0 = w0 - ((al_e - al_w) + (al_n - al_s))
     return Weights(ndim, n, w0, wW, wE, wS, wN)
 
 
@@ -127,4 +162,5 @@ def dense(W: Weights) -> np.ndarray:
 
 def from_problem(p) -> Weights:
     """Weights for a ``lem_inputs.Problem``."""
-    return weights(p.ndim, p.n, p.dx, p.dt, p.vel, nu=p.nu, nu_field=p.nu_field)
+    return weights(p.ndim, p.n, p.dx, p.dt, p.vel, nu=p.nu, nu_field=p.nu_field,
+                   vel_faces=getattr(p, "vel_faces", None), dy=getattr(p, "dy", None))

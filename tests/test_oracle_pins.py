@@ -637,3 +637,89 @@ def test_schrodinger_lem_single_domain_and_halo_convergence():
     errs = [crel(SCH.lem_run(c0, Lx, kappa, dt, 6, 30, h), g) for h in (4, 8, 12, 16, 20)]
     assert all(b < a for a, b in zip(errs, errs[1:]))
     assert errs[0] > 1e-2 and errs[-1] < 1e-6
+
+
+# ------------------------------------------- variable velocity, anisotropy ----
+
+def test_vortex_advection_is_skew_steady_and_norm_preserving():
+    """Centered conservative advection by face velocities taken from a stream
+    function: dt*A is skew-symmetric (so exp(dt A) is orthogonal), rows sum
+    to zero (the discrete divergence vanishes: constants are steady) and
+    columns sum to zero (mass)."""
+    n = 20
+    dx = 1.0 / n
+    F = L.vortex_faces(n, speed=1.3)
+    A = op.dense(op.weights(2, n, dx, 2.0 * dx, (0.0, 0.0), nu=0.0, vel_faces=F))
+    scale = np.abs(A).max()
+    assert np.abs(A + A.T).max() <= 1e-14 * scale
+    assert np.abs(A.sum(axis=1)).max() <= 1e-13 * scale
+    assert np.abs(A.sum(axis=0)).max() <= 1e-13 * scale
+    u = L.gaussian_blobs_2d(n, 3, seed=1)
+    v = E.expm(A) @ u
+    assert np.abs(np.linalg.norm(v, axis=0) / np.linalg.norm(u, axis=0) - 1).max() <= 1e-12
+    # with diffusion the l2 norm decays and the mass stays
+    Ad = op.dense(op.weights(2, n, dx, 2.0 * dx, (0.0, 0.0), nu=1e-2, vel_faces=F))
+    w = E.expm(Ad) @ u
+    assert np.all(np.linalg.norm(w, axis=0) < np.linalg.norm(u, axis=0))
+    assert np.abs(w.sum(0) - u.sum(0)).max() <= 1e-12 * np.abs(u.sum(0)).max()
+
+
+def test_vortex_turns_a_blob_about_the_centre():
+    """psi = (1/pi) sin^2(pi x) sin^2(pi y) turns counter-clockwise about the
+    centre with angular velocity omega(r) = sin(2 pi r) / r on the horizontal
+    axis (2 pi at the centre): a small blob started at distance r0 to the
+    right of the centre is, after the time of a quarter turn at omega(r0),
+    above the centre (angle pi/2) at the same distance, within the
+    discretization, shear and blob-size errors."""
+    n = 96
+    dx = 1.0 / n
+    F = L.vortex_faces(n)
+    r0, sig = 0.08, 0.02
+    omega = np.sin(2 * np.pi * r0) / r0
+    T = 0.5 * np.pi / omega
+    steps = 40
+    A = op.sparse(op.weights(2, n, dx, T / steps, (0.0, 0.0), nu=0.0, vel_faces=F))
+    x = np.arange(n) / n
+    X, Y = np.meshgrid(x, x)
+    u = np.exp(-((X - 0.5 - r0) ** 2 + (Y - 0.5) ** 2) / (2 * sig ** 2)).reshape(-1)
+    from scipy.sparse.linalg import expm_multiply
+    v = expm_multiply(A, u, start=0, stop=steps, num=2, endpoint=True)[-1]
+    m = v.sum()
+    cx = (v * X.reshape(-1)).sum() / m - 0.5
+    cy = (v * Y.reshape(-1)).sum() / m - 0.5
+    assert abs(np.arctan2(cy, cx) - np.pi / 2) < 0.06
+    assert abs(np.hypot(cx, cy) - r0) < 0.006
+
+
+def test_anisotropic_fourier_mode_closed_form():
+    """dy != dx: a discrete Fourier mode exp(i (kx x + ky y)) is an
+    eigenvector of the constant-coefficient operator with eigenvalue
+    -4 nu sin^2(kx dx/2)/dx^2 - 4 nu sin^2(ky dy/2)/dy^2
+    - i (a_x sin(kx dx)/dx + a_y sin(ky dy)/dy)."""
+    n = 16
+    dx, dy = 1.0 / n, 0.01 / n
+    nu, vel, dt = 1e-4, (0.7, 0.02), 0.5 * (1.0 / n)
+    A = op.dense(op.weights(2, n, dx, dt, vel, nu=nu, dy=dy))
+    x = np.arange(n) * dx
+    y = np.arange(n) * dy
+    X, Y = np.meshgrid(x, y)
+    for m, l in ((1, 0), (0, 1), (3, 2), (5, 7)):
+        kx, ky = 2 * np.pi * m, 2 * np.pi * l / (n * dy)
+        u = np.exp(1j * (kx * X + ky * Y)).reshape(-1)
+        lam = (-4 * nu * np.sin(kx * dx / 2) ** 2 / dx ** 2 - 4 * nu * np.sin(ky * dy / 2) ** 2 / dy ** 2
+               - 1j * (vel[0] * np.sin(kx * dx) / dx + vel[1] * np.sin(ky * dy) / dy))
+        got = E.expm(A) @ u
+        want = np.exp(dt * lam) * u
+        assert np.abs(got - want).max() <= 1e-11
+
+
+def test_vortex_lem_converges_to_global_with_halo():
+    n = 24
+    dx = 1.0 / n
+    F = L.vortex_faces(n)
+    A = op.sparse(op.weights(2, n, dx, 1.5 * dx, (0.0, 0.0), nu=1e-3, vel_faces=F))
+    u = L.gaussian_blobs_2d(n, 2, seed=3)
+    g = E.expm(A.toarray()) @ u
+    errs = [rel_l2(lem.step(A, P.uniform_boxes(2, n, 8, h), 2, n, u), g) for h in (1, 2, 4, 7)]
+    assert all(b < a for a, b in zip(errs, errs[1:]))
+    assert errs[-1] < 1e-5
