@@ -98,6 +98,16 @@ typedef struct {
                               exp(dt A_M) v + phi_1(dt A_M)(dt g_M), and the
                               global method takes exp(dt A) u + phi_1(dt A)(dt g).
                               Not accepted by the server (LEM_ERR_UNSUPPORTED). */
+  const double* vel_faces; /* optional face velocities replacing vel (which must
+                              then be zero): host, ndim x N doubles, a_x on the
+                              east face (i+1/2, j) of node j*n + i, then (2D)
+                              a_y on its north face (i, j+1/2); the advection
+                              is taken in the conservative form -div(a c) of
+                              eq. ibv2d (section 4.3) with centered face
+                              fluxes.  Krylov and global methods only (the
+                              dense method and the server reject it).       */
+  double dy;               /* y spacing of an anisotropic 2D mesh (section
+                              4.3); 0 means dy = dx                         */
 } lem_operator;
 
 typedef struct {

@@ -41,7 +41,8 @@ class _Operator(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int32), ("n", ctypes.c_int32), ("dx", ctypes.c_double),
                 ("vel", ctypes.c_double * 2), ("nu", ctypes.c_double),
                 ("nu_field", ctypes.POINTER(ctypes.c_double)),
-                ("forcing", ctypes.POINTER(ctypes.c_double))]
+                ("forcing", ctypes.POINTER(ctypes.c_double)),
+                ("vel_faces", ctypes.POINTER(ctypes.c_double)), ("dy", ctypes.c_double)]
 
 
 class _Options(ctypes.Structure):
@@ -124,16 +125,23 @@ def _stream_handle(stream) -> Optional[int]:
 
 class Operator:
     """Periodic advection-diffusion operator of the model problem (eq. (2)),
-    centered finite differences on n (1D) or n x n (2D) points."""
+    centered finite differences on n (1D) or n x n (2D) points.  ``vel_faces``
+    (shape (ndim, ny, n), replacing ``vel``) gives face velocities for the
+    conservative form of eq. ibv2d; ``dy`` the y spacing of an anisotropic
+    mesh (None: dx)."""
 
     def __init__(self, ndim: int, n: int, dx: float, vel=(1.0, 0.0), nu: float = 0.0,
-                 nu_field: Optional[np.ndarray] = None, forcing: Optional[np.ndarray] = None):
+                 nu_field: Optional[np.ndarray] = None, forcing: Optional[np.ndarray] = None,
+                 vel_faces: Optional[np.ndarray] = None, dy: Optional[float] = None):
         self.ndim, self.n, self.dx = int(ndim), int(n), float(dx)
         self.vel = (float(vel[0]), float(vel[1]) if len(vel) > 1 else 0.0)
         self.nu = float(nu)
         self.nu_field = None if nu_field is None else np.ascontiguousarray(nu_field, dtype=np.float64).reshape(-1)
         # source g of du/dt = A u + g (rate units), shape (N,) or (N, n_states)
         self.forcing = None if forcing is None else np.ascontiguousarray(forcing, dtype=np.float64)
+        self.vel_faces = (None if vel_faces is None
+                          else np.ascontiguousarray(vel_faces, dtype=np.float64).reshape(-1))
+        self.dy = 0.0 if dy is None else float(dy)
 
     @property
     def N(self) -> int:
@@ -141,7 +149,8 @@ class Operator:
 
     @classmethod
     def from_problem(cls, p) -> "Operator":
-        return cls(p.ndim, p.n, p.dx, p.vel, p.nu if p.nu is not None else 0.0, p.nu_field)
+        return cls(p.ndim, p.n, p.dx, p.vel, p.nu if p.nu is not None else 0.0, p.nu_field,
+                   vel_faces=getattr(p, "vel_faces", None), dy=getattr(p, "dy", None))
 
     def _c(self) -> _Operator:
         o = _Operator()
@@ -160,6 +169,13 @@ class Operator:
             o.forcing = self.forcing.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         else:
             o.forcing = None
+        if self.vel_faces is not None:
+            if self.vel_faces.size != self.ndim * self.N:
+                raise ValueError("vel_faces must have ndim x N entries")
+            o.vel_faces = self.vel_faces.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        else:
+            o.vel_faces = None
+        o.dy = self.dy
         return o
 
 

@@ -26,6 +26,8 @@ struct GlobalOp {
   double chx, chy, sub_scale; // variable-nu form
   const double* mux;          // face-mu arrays (dt-scaled), or null
   const double* muy;
+  const double* ax;           // face velocity coefficients (dt a / (2 dx)), or null
+  const double* ay;
   int n, ndim;
   // forced step: point Npts is the augmented coordinate of [[dt A, dt g],
   // [0, 0]] (zero row); its column is gscale * g
@@ -53,10 +55,25 @@ __device__ __forceinline__ double gstencil(const GlobalOp& o, const double* X, i
     }
     const double sc = o.sub_scale;
     c0 = -(me + mw + mn + ms) * sc;
-    cW = fma(mw, sc, o.chx);
-    cE = fma(me, sc, -o.chx);
-    cS = fma(ms, sc, o.chy);
-    cN = fma(mn, sc, -o.chy);
+    if (o.ax) {  // conservative centered advection by face velocities
+      const double ae = o.ax[gy * n + gx] * sc, aw = o.ax[gy * n + xm] * sc;
+      double an = 0.0, as = 0.0;
+      if (o.ndim == 2) {
+        const int64_t ym = (gy == 0) ? n - 1 : gy - 1;
+        an = o.ay[gy * n + gx] * sc;
+        as = o.ay[ym * n + gx] * sc;
+      }
+      c0 -= (ae - aw) + (an - as);
+      cW = fma(mw, sc, aw);
+      cE = fma(me, sc, -ae);
+      cS = fma(ms, sc, as);
+      cN = fma(mn, sc, -an);
+    } else {
+      cW = fma(mw, sc, o.chx);
+      cE = fma(me, sc, -o.chx);
+      cS = fma(ms, sc, o.chy);
+      cN = fma(mn, sc, -o.chy);
+    }
   }
   double r = c0 * X[pt * ns + s];
   r = fma(cW, X[(gy * n + xm) * ns + s], r);
@@ -327,7 +344,7 @@ size_t global_part_doubles(int G, int ns) { return (size_t)G * (kMaxKrylov + 1) 
 static void fill_op(const GlobalWork& w, GlobalOp& o, bool forced) {
   o.w0 = w.w[0]; o.wW = w.w[1]; o.wE = w.w[2]; o.wS = w.w[3]; o.wN = w.w[4];
   o.chx = w.chx; o.chy = w.chy; o.sub_scale = w.sub_scale;
-  o.mux = w.mux; o.muy = w.muy; o.n = w.n; o.ndim = w.ndim;
+  o.mux = w.mux; o.muy = w.muy; o.ax = w.ax; o.ay = w.ay; o.n = w.n; o.ndim = w.ndim;
   o.aug = forced ? 1 : 0;
   o.Npts = w.N;
   o.gscale = w.gscale;

@@ -366,10 +366,25 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
       }
       const double sc = b.sub_scale;
       w0 = -(me + mw + mn + ms) * sc;
-      wW = fma(mw, sc, b.chx);
-      wE = fma(me, sc, -b.chx);
-      wS = fma(ms, sc, b.chy);
-      wN = fma(mn, sc, -b.chy);
+      if (b.varvel) {  // conservative centered advection by face velocities
+        const double* axf = mux + 2 * Ng;
+        const double ae = axf[g] * sc, aw = axf[(int64_t)gy * b.n + wrap(gx - 1, b.n)] * sc;
+        double an = 0.0, as = 0.0;
+        if (b.ndim == 2) {
+          an = axf[Ng + g] * sc;
+          as = axf[Ng + (int64_t)wrap(gy - 1, b.n) * b.n + gx] * sc;
+        }
+        w0 -= (ae - aw) + (an - as);
+        wW = fma(mw, sc, aw);
+        wE = fma(me, sc, -ae);
+        wS = fma(ms, sc, as);
+        wN = fma(mn, sc, -an);
+      } else {
+        wW = fma(mw, sc, b.chx);
+        wE = fma(me, sc, -b.chx);
+        wS = fma(ms, sc, b.chy);
+        wN = fma(mn, sc, -b.chy);
+      }
     }
     if (!live[p] || (AUG && li[p] == nloc)) w0 = wW = wE = wS = wN = 0.0;  // augmented row: zero
     if (!b.periodic) {

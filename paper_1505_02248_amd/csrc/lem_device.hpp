@@ -41,6 +41,9 @@ struct KBlock {
                               // periodic coupling (no decomposition, D = 1)
   int32_t aug;                // 1: forced step, the box carries one extra
                               // (augmented) coordinate after its Lx*Ly points
+  int32_t varvel;             // 1: face velocities follow the face mu's in the
+                              // coefficient arrays (ax at mu_off + 2N, ay at
+                              // mu_off + 3N; conservative centered advection)
   double gscale;              // dt_sub: scales the forcing to the sub-step
   const double* force;        // forcing g (rate units), N x ns, or null
   // Optional per-block buffers (null: the launch's arguments).  A serving

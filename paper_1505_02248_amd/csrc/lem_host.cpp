@@ -52,11 +52,13 @@ constexpr double kB[14] = {64764752532480000.0, 32382376266240000.0, 77717703038
 // dt*A of the periodic advection-diffusion operator, centered differences.
 struct Op {
   int ndim = 1, n = 0;
-  double dx = 0, dt = 0, vel[2] = {0, 0}, nu = 0;
+  double dx = 0, dy = 0, dt = 0, vel[2] = {0, 0}, nu = 0;
   bool variable = false;
+  bool varvel = false;             // face velocities (conservative advection)
   double w[5] = {0, 0, 0, 0, 0};  // w0, wW, wE, wS, wN (constant case)
   double chx = 0, chy = 0;        // dt*C/2 per axis
   std::vector<double> mux, muy;   // face mu's (variable case), dt-scaled
+  std::vector<double> ax, ay;     // face dt*a/(2 dx), dt*a/(2 dy) (varvel)
   int64_t N() const { return ndim == 1 ? (int64_t)n : (int64_t)n * n; }
 };
 
@@ -67,19 +69,24 @@ lem_status build_op(const lem_operator* o, double dt, Op* op) {
   if (!(o->dx > 0) || !std::isfinite(o->dx)) return fail(LEM_ERR_INVALID, "dx must be > 0");
   if (!(dt > 0) || !std::isfinite(dt)) return fail(LEM_ERR_INVALID, "dt must be > 0");
   if (!(o->nu >= 0) && !o->nu_field) return fail(LEM_ERR_INVALID, "nu must be >= 0");
+  if (!(o->dy >= 0) || !std::isfinite(o->dy)) return fail(LEM_ERR_INVALID, "dy must be >= 0");
   op->ndim = o->ndim;
   op->n = o->n;
   op->dx = o->dx;
+  op->dy = (o->ndim == 2 && o->dy > 0) ? o->dy : o->dx;
   op->dt = dt;
   op->vel[0] = o->vel[0];
   op->vel[1] = o->ndim == 2 ? o->vel[1] : 0.0;
   op->nu = o->nu;
+  if (o->vel_faces && (op->vel[0] != 0.0 || op->vel[1] != 0.0))
+    return fail(LEM_ERR_INVALID, "vel must be zero when vel_faces is given");
   const double cx = op->vel[0] * dt / o->dx;
-  const double cy = op->vel[1] * dt / o->dx;
+  const double cy = op->vel[1] * dt / op->dy;
   op->chx = cx / 2.0;
   op->chy = cy / 2.0;
-  if (!o->nu_field) {
+  if (!o->nu_field && !o->vel_faces) {
     const double mu = o->nu * dt / (o->dx * o->dx);
+    const double muy = o->nu * dt / (op->dy * op->dy);
     op->variable = false;
     if (o->ndim == 1) {
       op->w[0] = -(mu + mu);
@@ -88,11 +95,11 @@ lem_status build_op(const lem_operator* o, double dt, Op* op) {
       op->w[3] = 0.0;
       op->w[4] = 0.0;
     } else {
-      op->w[0] = -(((mu + mu) + mu) + mu);
+      op->w[0] = -(((mu + mu) + muy) + muy);
       op->w[1] = mu + cx / 2.0;
       op->w[2] = mu - cx / 2.0;
-      op->w[3] = mu + cy / 2.0;
-      op->w[4] = mu - cy / 2.0;
+      op->w[3] = muy + cy / 2.0;
+      op->w[4] = muy - cy / 2.0;
     }
     return LEM_OK;
   }
@@ -100,23 +107,42 @@ lem_status build_op(const lem_operator* o, double dt, Op* op) {
   const int64_t N = op->N();
   const int n = op->n;
   const double s = dt / (2.0 * o->dx * o->dx);
+  const double sy = dt / (2.0 * op->dy * op->dy);
   op->mux.assign(N, 0.0);
   op->muy.assign(N, 0.0);
-  for (int64_t g = 0; g < N; ++g) {
-    const double v = o->nu_field[g];
-    if (!(v >= 0) || !std::isfinite(v)) return fail(LEM_ERR_INVALID, "nu_field must be >= 0");
+  if (o->nu_field) {
+    for (int64_t g = 0; g < N; ++g) {
+      const double v = o->nu_field[g];
+      if (!(v >= 0) || !std::isfinite(v)) return fail(LEM_ERR_INVALID, "nu_field must be >= 0");
+    }
+  } else if (!(o->nu >= 0) || !std::isfinite(o->nu)) {
+    return fail(LEM_ERR_INVALID, "nu must be >= 0");
   }
+  auto nu_at = [&](int64_t g) { return o->nu_field ? o->nu_field[g] : o->nu; };
   const int ny = op->ndim == 1 ? 1 : n;
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < n; ++i) {
       const int64_t g = (int64_t)j * n + i;
       const int64_t e = (int64_t)j * n + (i + 1) % n;
-      op->mux[g] = (o->nu_field[g] + o->nu_field[e]) * s;
+      op->mux[g] = (nu_at(g) + nu_at(e)) * s;
       if (op->ndim == 2) {
         const int64_t t = (int64_t)((j + 1) % n) * n + i;
-        op->muy[g] = (o->nu_field[g] + o->nu_field[t]) * s;
+        op->muy[g] = (nu_at(g) + nu_at(t)) * sy;
       }
     }
+  if (o->vel_faces) {
+    op->varvel = true;
+    op->chx = op->chy = 0.0;
+    op->ax.assign(N, 0.0);
+    op->ay.assign(N, 0.0);
+    for (int64_t g = 0; g < N; ++g) {
+      const double a = o->vel_faces[g];
+      const double b = op->ndim == 2 ? o->vel_faces[N + g] : 0.0;
+      if (!std::isfinite(a) || !std::isfinite(b)) return fail(LEM_ERR_INVALID, "vel_faces must be finite");
+      op->ax[g] = a * (dt / (2.0 * o->dx));
+      op->ay[g] = b * (dt / (2.0 * op->dy));
+    }
+  }
   return LEM_OK;
 }
 
@@ -139,6 +165,19 @@ void point_weights(const Op& op, int i, int j, double* w) {
   w[2] = me - op.chx;
   w[3] = op.ndim == 2 ? ms + op.chy : 0.0;
   w[4] = op.ndim == 2 ? mn - op.chy : 0.0;
+  if (op.varvel) {  // conservative centered advection by face velocities
+    const double ae = op.ax[g], aw = op.ax[(int64_t)j * n + (i + n - 1) % n];
+    double an = 0, as = 0;
+    if (op.ndim == 2) {
+      an = op.ay[g];
+      as = op.ay[(int64_t)((j + n - 1) % n) * n + i];
+    }
+    w[0] -= (ae - aw) + (an - as);
+    w[1] = mw + aw;
+    w[2] = me - ae;
+    w[3] = op.ndim == 2 ? ms + as : 0.0;
+    w[4] = op.ndim == 2 ? mn - an : 0.0;
+  }
 }
 
 // ------------------------------------------------------------ halo bound --
@@ -443,6 +482,21 @@ lem_status make_partition(lem_plan_s* p) {
 }
 
 // --------------------------------------------------------------- Krylov ----
+// Face coefficient arrays of a variable operator: mux, muy, then (face
+// velocities) ax, ay, N doubles each.
+lem_status upload_coef(lem_plan_s* p, hipStream_t st) {
+  const Op& op = p->op;
+  const size_t N = (size_t)op.N();
+  LEM_TRY(dalloc(p, &p->d_coef, (op.varvel ? 4 : 2) * N, &p->bytes_work));
+  LEM_TRY(upload(p->d_coef, op.mux.data(), N * 8, st));
+  LEM_TRY(upload(p->d_coef + N, op.muy.data(), N * 8, st));
+  if (op.varvel) {
+    LEM_TRY(upload(p->d_coef + 2 * N, op.ax.data(), N * 8, st));
+    LEM_TRY(upload(p->d_coef + 3 * N, op.ay.data(), N * 8, st));
+  }
+  return LEM_OK;
+}
+
 lem::KBlock make_kblock(const lem_plan_s* p, const Box& b, int m, int nsub, int ns, int diag,
                         bool forced = false) {
   lem::KBlock k{};
@@ -457,6 +511,7 @@ lem::KBlock make_kblock(const lem_plan_s* p, const Box& b, int m, int nsub, int 
   k.tol = p->opt.krylov_tol;
   k.x_off = 0;
   k.mu_off = op.variable ? 0 : -1;
+  k.varvel = op.varvel ? 1 : 0;
   k.v_off = 0;
   k.n = op.n; k.ndim = op.ndim;
   k.ox = b.ox; k.oy = b.oy; k.cx = b.cx; k.cy = b.cy; k.h = b.h;
@@ -575,11 +630,7 @@ lem_status plan_krylov(lem_plan_s* p, hipStream_t st) {
   const lem_options& o = p->opt;
   const int nb = (int)p->boxes.size();
   // coefficient arrays
-  if (op.variable) {
-    LEM_TRY(dalloc(p, &p->d_coef, 2 * (size_t)op.N(), &p->bytes_work));
-    LEM_TRY(upload(p->d_coef, op.mux.data(), op.N() * 8, st));
-    LEM_TRY(upload(p->d_coef + op.N(), op.muy.data(), op.N() * 8, st));
-  }
+  if (op.variable) LEM_TRY(upload_coef(p, st));
   // Calibration representatives.  Krylov convergence is governed by the
   // box shape and the norm of dt*A_M: blocks with the same box and a row-sum
   // norm within the same 15% bucket share one calibration, taken on the
@@ -919,6 +970,8 @@ lem_status alloc_global(lem_plan_s* p, int m, int ns, int nsub, lem::GlobalWork*
   w->chx = op.chx * sc; w->chy = op.chy * sc; w->sub_scale = sc;
   w->mux = op.variable ? p->d_coef : nullptr;
   w->muy = op.variable ? p->d_coef + op.N() : nullptr;
+  w->ax = op.varvel ? p->d_coef + 2 * op.N() : nullptr;
+  w->ay = op.varvel ? p->d_coef + 3 * op.N() : nullptr;
   w->tol = p->opt.krylov_tol;
   w->status = p->d_status;
   const int64_t tot = (w->N + (forced ? 1 : 0)) * ns;  // plus the augmented coordinate
@@ -957,11 +1010,7 @@ lem_status plan_global(lem_plan_s* p, hipStream_t st) {
   const lem_options& o = p->opt;
   if (256 % p->ns != 0)
     return fail(LEM_ERR_UNSUPPORTED, "the global method needs n_states dividing 256");
-  if (op.variable) {
-    LEM_TRY(dalloc(p, &p->d_coef, 2 * (size_t)op.N(), &p->bytes_work));
-    LEM_TRY(upload(p->d_coef, op.mux.data(), op.N() * 8, st));
-    LEM_TRY(upload(p->d_coef + op.N(), op.muy.data(), op.N() * 8, st));
-  }
+  if (op.variable) LEM_TRY(upload_coef(p, st));
   const int mcal = std::min(std::max(o.krylov_m_max, 4), lem::kMaxKrylov);
   std::vector<int> jl;
   for (int j = 2; j <= mcal; ++j) jl.push_back(j);
@@ -1148,6 +1197,8 @@ lem_status create_plan(const lem_operator* op, double dt, const lem_options* opt
   p->stream = (hipStream_t)stream;
   lem_status s = build_op(op, dt, &p->op);
   if (s != LEM_OK) return guard(s);
+  if (p->method == LEM_METHOD_DENSE && p->op.variable)
+    return guard(fail(LEM_ERR_UNSUPPORTED, "stored local exponentials need constant coefficients"));
   p->N = p->op.N();
   p->forced = op->forcing != nullptr;
   if (p->forced) {
@@ -1809,6 +1860,7 @@ lem_status lem_server_submit(lem_server_t s, const lem_operator* op, double dt, 
   if (!s || !op || !x0_host || !id) return fail(LEM_ERR_INVALID, "NULL argument");
   if (n_steps < 1) return fail(LEM_ERR_INVALID, "n_steps must be >= 1");
   if (op->forcing) return fail(LEM_ERR_UNSUPPORTED, "served requests take no forcing");
+  if (op->vel_faces) return fail(LEM_ERR_UNSUPPORTED, "served requests take no face velocities");
   Op chk;
   LEM_TRY(build_op(op, dt, &chk));
   ServerReq r;

@@ -84,6 +84,8 @@ struct GlobalWork {
   double chx, chy, sub_scale;
   const double* mux;
   const double* muy;
+  const double* ax;   // face velocity coefficients (conservative advection), or null
+  const double* ay;
   double *V, *W, *Wt, *part, *h1, *h2, *hn, *H, *f, *beta, *inv, *est, *estsum;
   double tol;
   int* status;

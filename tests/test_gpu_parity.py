@@ -403,3 +403,44 @@ def test_schrodinger_lem_matches_oracle(n, core, halo, ns, steps):
     assert q["n_blocks"] == n // core and q["device_status"] == 0
     if core == n:  # the global step is unitary
         assert np.abs(np.linalg.norm(got, axis=0) - np.linalg.norm(c0, axis=0)).max() <= 1e-10
+
+
+# variable divergence-free velocity (face velocities, conservative form of
+# eq. ibv2d) and anisotropic spacing: Krylov LEM and the global method
+def _vortex_problem(n, ns, courant, height):
+    p = L.workload_2d_vortex(n=n, n_states=ns, courant=courant)
+    if height != 1.0:
+        p.vel_faces = L.vortex_faces(n, height=height)
+        p.dy = p.dx * height
+    return p
+
+
+@pytest.mark.parametrize("n,ns,core,courant,height", [(64, 2, 16, 2.0, 1.0), (64, 3, 16, 1.0, 0.25),
+                                                      (96, 1, 32, 4.0, 1.0)])
+def test_krylov_vortex_faces(n, ns, core, courant, height):
+    p = _vortex_problem(n, ns, courant, height)
+    plan = lem.Plan(lem.Operator.from_problem(p), p.dt, method="krylov", core=core, halo=0,
+                    halo_min=2, halo_max=16, halo_tol=1e-8, n_states=ns, krylov_tol=1e-14)
+    boxes = check_maps(plan, 2, p.n)
+    got = run(plan, p.states, 2)
+    want = oracle_lem(p, boxes, p.states, 2, krylov_above=2600, krylov_tol=1e-16)
+    assert rel_l2(got, want) <= 1e-12
+    assert plan.query()["device_status"] == 0
+
+
+@pytest.mark.parametrize("height", [1.0, 0.25])
+def test_global_krylov_vortex_vs_dense(height):
+    p = _vortex_problem(32, 2, 3.0, height)
+    W = op.from_problem(p)
+    plan = lem.Plan(lem.Operator.from_problem(p), p.dt, method="global", n_states=2,
+                    krylov_tol=1e-14)
+    got = run(plan, p.states, 1)
+    assert rel_l2(got, ge.dense_step(W, p.states)) <= 1e-12
+    # whole-grid kernels (grid above the periodic-box limit)
+    p2 = _vortex_problem(96, 2, 3.0, height)
+    W2 = op.from_problem(p2)
+    plan2 = lem.Plan(lem.Operator.from_problem(p2), p2.dt, method="global", n_states=2,
+                     krylov_tol=1e-14)
+    got2 = run(plan2, p2.states, 1)
+    want2 = ge.krylov_step(W2, p2.states, m=60, tol=1e-16)
+    assert rel_l2(got2, want2) <= 1e-11

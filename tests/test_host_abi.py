@@ -111,3 +111,40 @@ def test_dry_plan_cannot_step_and_reports_sizes():
     assert st == 1
     p.close()
     assert lib.lem_plan_destroy(None) == 0
+
+
+@pytest.mark.parametrize("height", [1.0, 0.25])
+def test_vortex_faces_partition_and_halos_match_oracle(height):
+    """Face velocities (and an anisotropic dy): the host planner's per-block
+    decay-bound halos are accepted by the oracle's rule on the same weights."""
+    p = L.workload_2d_vortex(n=128, n_states=1, courant=2.0)
+    if height != 1.0:
+        p.vel_faces = L.vortex_faces(p.n, height=height)
+        p.dy = p.dx * height
+    W = op.from_problem(p)
+    G = H.growth_factor(W)
+    plan = lem.Plan(lem.Operator.from_problem(p), p.dt, core=16, halo=0, halo_min=2,
+                    halo_max=24, halo_tol=1e-8, dry_run=True)
+    boxes, gather, scatter = plan.maps()
+    Go, So = _oracle_maps(boxes, 2, p.n)
+    assert np.array_equal(gather, Go.astype(np.int32))
+    assert np.array_equal(scatter, So.astype(np.int32))
+    info = plan.query()
+    for b in boxes:
+        box = P.Box(*map(int, b))
+        co = H.block_coefficients(W, box, 2)
+        if box.h == 24 and H.eps(co, 24, 2, G) > 1e-8:
+            continue
+        assert H.accepts(co, 2, 1e-8, 2, box.h, G), box
+    assert info["halo_min"] < info["halo_max"]  # the vortex is slow near its centre
+
+
+def test_face_velocity_errors():
+    n = 16
+    F = L.vortex_faces(n)
+    with pytest.raises(lem.LemError):
+        lem.Plan(lem.Operator(2, n, 1 / n, (1.0, 0.0), 1e-3, vel_faces=F), 1 / n, core=8, halo=2,
+                 dry_run=True)  # vel must be zero with face velocities
+    with pytest.raises(lem.LemError):
+        lem.Plan(lem.Operator(2, n, 1 / n, (0.0, 0.0), 1e-3, vel_faces=F), 1 / n, method="dense",
+                 core=8, halo=2, dry_run=True)
