@@ -129,6 +129,12 @@ typedef struct {
   int32_t autotune;      /* time candidate launch shapes at plan time       */
   int32_t dry_run;       /* 1: build partition and maps on the host only;
                             no device memory is touched (lem_step fails)     */
+  int32_t columns;       /* 2D Krylov: column-wise decomposition (section
+                            4.3): cores of core x n points spanning whole
+                            columns, buffers of halo points across the
+                            columns only, the periodic coupling along the
+                            columns kept inside every box; exported boxes
+                            then read (ox, 0, core, n, h)                   */
 } lem_options;
 
 typedef struct {

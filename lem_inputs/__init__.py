@@ -273,6 +273,25 @@ def workload_2d_vortex(n: int = 512, n_states: int = 16, seed: int = 5, courant:
                    vel_faces=F)
 
 
+def workload_2d_columns(n: int = 128, n_states: int = 64, seed: int = 7, aspect: float = 16.0,
+                        courant_x: float = 0.8, mu_y: float = 6.0) -> Problem:
+    """Anisotropic mesh for column-wise decompositions (section 4.3): n x n
+    nodes on [0, 1) x [0, 1/aspect) (dy = dx / aspect), the single vortex of
+    ``vortex_faces`` flattened to that height, horizontal Courant number
+    ``courant_x`` and vertical diffusion number nu dt / dy^2 = ``mu_y``
+    (stiff in the vertical only), Gaussian blobs."""
+    dx = 1.0 / n
+    dy = dx / aspect
+    F = vortex_faces(n, height=1.0 / aspect)
+    dt = courant_x * dx / float(np.abs(F[0]).max())
+    nu = mu_y * dy * dy / dt
+    st = gaussian_blobs_2d(n, n_states, seed, height=1.0 / aspect)
+    return Problem(2, n, dx, dt, (0.0, 0.0), nu, None, st,
+                   meta={"name": "adv-diff-2d-anisotropic-columns", "seed": seed,
+                         "aspect": aspect, "courant_x": courant_x, "mu_y": mu_y},
+                   vel_faces=F, dy=dy)
+
+
 @dataclass
 class Request:
     """One served time-stepping request."""

@@ -76,33 +76,35 @@ def growth_factor(W) -> float:
     return math.exp(max(0.0, float(s.max())))
 
 
-def eps(coeffs, h: int, ndim: int, G: float = 1.0) -> float:
-    """The bound eps(h) for one block, given its coefficient maxima."""
+def eps(coeffs, h: int, ndim: int, G: float = 1.0, cut_y: bool = True) -> float:
+    """The bound eps(h) for one block, given its coefficient maxima.  A box
+    that spans the whole y axis (column-wise decomposition, cut_y False) has
+    no buffer edge across y, so only its x sides contribute."""
     aW, aE, aS, aN, w0 = coeffs
     terms = [side_log_bound(aW, aE, w0, aS + aN, h),
              side_log_bound(aE, aW, w0, aS + aN, h)]
-    if ndim == 2:
+    if ndim == 2 and cut_y:
         terms += [side_log_bound(aS, aN, w0, aW + aE, h),
                   side_log_bound(aN, aS, w0, aW + aE, h)]
     return G * sum(math.exp(t) for t in terms if t > -math.inf)
 
 
 def halo_width(coeffs, ndim: int, tol: float, h_min: int, h_max: int,
-               G: float = 1.0):
+               G: float = 1.0, cut_y: bool = True):
     """Smallest h >= h_min with eps(h) <= tol, clamped at h_max.
 
     Returns (h, clamped) where clamped is True when even h_max misses tol.
     """
     for h in range(h_min, h_max + 1):
-        if eps(coeffs, h, ndim, G) <= tol:
+        if eps(coeffs, h, ndim, G, cut_y) <= tol:
             return h, False
     return h_max, True
 
 
 def accepts(coeffs, ndim: int, tol: float, h_min: int, h: int,
-            G: float = 1.0, rel: float = 1e-12) -> bool:
+            G: float = 1.0, rel: float = 1e-12, cut_y: bool = True) -> bool:
     """Tie-tolerant check that h is the halo-rule answer: eps(h) <= tol and
     either h = h_min or eps(h - 1) > tol (both up to a relative ``rel``)."""
-    if eps(coeffs, h, ndim, G) > tol * (1.0 + rel):
+    if eps(coeffs, h, ndim, G, cut_y) > tol * (1.0 + rel):
         return False
-    return h == h_min or eps(coeffs, h - 1, ndim, G) > tol * (1.0 - rel)
+    return h == h_min or eps(coeffs, h - 1, ndim, G, cut_y) > tol * (1.0 - rel)

@@ -85,7 +85,7 @@ def step(A_sparse, boxes, ndim: int, n: int, u: np.ndarray,
     for b in boxes:
         G = P.gather_map(b, ndim, n)
         S = P.scatter_map(b, ndim, n)
-        rows = P.core_local_rows(b, ndim)
+        rows = P.core_local_rows(b, ndim, n)
         A_loc_sp = A_sparse[G][:, G]
         if krylov_above and len(G) > krylov_above:
             for c in range(U.shape[1]):

@@ -17,6 +17,12 @@ sends core row r = ry * cx + rx to the global DOF (oy + ry) * n + (ox + rx).
 A box must not reach itself through the wrap (Lx < n, Ly < n) unless it is
 the whole domain (the D = 1 case: core = grid, h = 0), where the local
 operator keeps the periodic coupling and LEM equals the global method.
+
+A core that spans a whole axis has no buffer along that axis and keeps the
+periodic coupling along it: the column-wise decompositions of section 4.3
+(cores of c x n points, buffers of h only across the columns).  Then the
+principal submatrix on the box already contains the wrap-around couplings of
+that axis, because both of their end points belong to the box.
 """
 from __future__ import annotations
 
@@ -33,9 +39,19 @@ class Box(NamedTuple):
     h: int
 
 
-def box_dims(b: Box, ndim: int):
-    Lx = b.cx + 2 * b.h
-    Ly = (b.cy + 2 * b.h) if ndim == 2 else 1
+def box_halos(b: Box, ndim: int, n: int | None = None):
+    """Buffer widths (hx, hy): none along an axis the core spans whole."""
+    hx = 0 if (n is not None and b.cx == n) else b.h
+    if ndim == 1:
+        return hx, 0
+    hy = 0 if (n is not None and b.cy == n) else b.h
+    return hx, hy
+
+
+def box_dims(b: Box, ndim: int, n: int | None = None):
+    hx, hy = box_halos(b, ndim, n)
+    Lx = b.cx + 2 * hx
+    Ly = (b.cy + 2 * hy) if ndim == 2 else 1
     return Lx, Ly
 
 
@@ -49,33 +65,43 @@ def uniform_boxes(ndim: int, n: int, c: int, h: int) -> List[Box]:
     return [Box(bx * c, by * c, c, c, h) for by in range(nb) for bx in range(nb)]
 
 
+def column_boxes(n: int, c: int, h: int) -> List[Box]:
+    """Column-wise 2D decomposition: cores of c x n points (whole columns),
+    buffers of h points across the columns only."""
+    if n % c:
+        raise ValueError("core width must divide the grid side")
+    return [Box(bx * c, 0, c, n, h) for bx in range(n // c)]
+
+
 def validate(b: Box, ndim: int, n: int) -> None:
-    Lx, Ly = box_dims(b, ndim)
+    Lx, Ly = box_dims(b, ndim, n)
     whole = (b.cx == n and b.h == 0 and (ndim == 1 or b.cy == n))
     if whole:
         return
-    if Lx >= n or (ndim == 2 and Ly >= n):
+    if (b.cx < n and Lx >= n) or (ndim == 2 and b.cy < n and Ly >= n):
         raise ValueError("box reaches itself through the periodic wrap")
 
 
 def gather_map(b: Box, ndim: int, n: int) -> np.ndarray:
     validate(b, ndim, n)
-    Lx, Ly = box_dims(b, ndim)
+    Lx, Ly = box_dims(b, ndim, n)
+    hx, hy = box_halos(b, ndim, n)
     lx = np.arange(Lx)
-    gx = (b.ox - b.h + lx) % n
+    gx = (b.ox - hx + lx) % n
     if ndim == 1:
         return gx.astype(np.int64)
     ly = np.arange(Ly)
-    gy = (b.oy - b.h + ly) % n
+    gy = (b.oy - hy + ly) % n
     return (gy[:, None] * n + gx[None, :]).reshape(-1).astype(np.int64)
 
 
-def core_local_rows(b: Box, ndim: int) -> np.ndarray:
-    Lx, _ = box_dims(b, ndim)
-    rx = np.arange(b.cx) + b.h
+def core_local_rows(b: Box, ndim: int, n: int | None = None) -> np.ndarray:
+    Lx, _ = box_dims(b, ndim, n)
+    hx, hy = box_halos(b, ndim, n)
+    rx = np.arange(b.cx) + hx
     if ndim == 1:
         return rx.astype(np.int64)
-    ry = np.arange(b.cy) + b.h
+    ry = np.arange(b.cy) + hy
     return (ry[:, None] * Lx + rx[None, :]).reshape(-1).astype(np.int64)
 
 

@@ -355,7 +355,7 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
       if constexpr (!PREW) asm volatile("" : "+s"(opq));  // recompute per use: no hoisting
       lx += opq;
       const int gx = wrap(b.ox - b.h + lx, b.n);
-      const int gy = (b.ndim == 1) ? 0 : wrap(b.oy - b.h + ly, b.n);
+      const int gy = (b.ndim == 1) ? 0 : wrap(b.oy - b.hy + ly, b.n);
       const int64_t g = (int64_t)gy * b.n + gx;
       const double me = mux[g];
       const double mw = mux[(int64_t)gy * b.n + wrap(gx - 1, b.n)];
@@ -387,9 +387,11 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
       }
     }
     if (!live[p] || (AUG && li[p] == nloc)) w0 = wW = wE = wS = wN = 0.0;  // augmented row: zero
-    if (!b.periodic) {
+    if (!(b.periodic & 1)) {
       if (lx == 0) wW = 0.0;
       if (lx == b.Lx - 1) wE = 0.0;
+    }
+    if (!(b.periodic & 2)) {
       if (ly == 0) wS = 0.0;
       if (ly == b.Ly - 1) wN = 0.0;
     }
@@ -425,13 +427,17 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
     int l = li[p];
     if constexpr (!PREW) asm volatile("" : "+v"(l));  // neighbour offsets per use: no hoisting
     int lW = l - 1, lE = l + 1, lS = l - b.Lx, lN = l + b.Lx;
-    if (b.periodic) {  // neighbours wrap around the whole-grid box
+    if (b.periodic) {  // neighbours wrap along the axes the box spans whole
       int lx, ly;
       coords(p, lx, ly);
-      if (lx == 0) lW += b.Lx;
-      if (lx == b.Lx - 1) lE -= b.Lx;
-      if (ly == 0) lS += nloc;
-      if (ly == b.Ly - 1) lN -= nloc;
+      if (b.periodic & 1) {
+        if (lx == 0) lW += b.Lx;
+        if (lx == b.Lx - 1) lE -= b.Lx;
+      }
+      if (b.periodic & 2) {
+        if (ly == 0) lS += nloc;
+        if (ly == b.Ly - 1) lN -= nloc;
+      }
     }
     double r = w0 * vj[l];
     if (wW != 0.0) r = fma(wW, vj[lW], r);
@@ -854,7 +860,7 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
     int lx, ly;
     coords(p, lx, ly);
     const int rx = lx - b.h;
-    const int ry = (b.ndim == 1) ? ly : ly - b.h;
+    const int ry = (b.ndim == 1) ? ly : ly - b.hy;
     if (rx < 0 || rx >= b.cx || ry < 0 || ry >= b.cy) continue;
     const int64_t g = (b.ndim == 1) ? (int64_t)(b.ox + rx)
                                     : (int64_t)(b.oy + ry) * b.n + (b.ox + rx);

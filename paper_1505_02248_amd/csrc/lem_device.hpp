@@ -37,10 +37,13 @@ struct KBlock {
   int32_t m, nsub;            // Krylov dimension, equal sub-steps per step
   int32_t ns;                 // ensemble size (stride of the state arrays)
   int32_t diag;               // index of this block's estimate slot
-  int32_t periodic;           // 1: the box is the whole grid and keeps the
-                              // periodic coupling (no decomposition, D = 1)
+  int32_t periodic;           // bit 0 (1): the core spans the whole x axis,
+                              // bit 1 (2): the whole y axis; the box keeps the
+                              // periodic coupling along such an axis and has
+                              // no buffer across it (D = 1: both bits)
   int32_t aug;                // 1: forced step, the box carries one extra
                               // (augmented) coordinate after its Lx*Ly points
+  int32_t hy;                 // buffer width along y (h is the one along x)
   int32_t varvel;             // 1: face velocities follow the face mu's in the
                               // coefficient arrays (ax at mu_off + 2N, ay at
                               // mu_off + 3N; conservative centered advection)
@@ -81,7 +84,7 @@ __device__ __forceinline__ int wrap(int a, int n) {
 __device__ __forceinline__ int64_t gather_index(const KBlock& b, int lx, int ly) {
   const int gx = wrap(b.ox - b.h + lx, b.n);
   if (b.ndim == 1) return gx;
-  const int gy = wrap(b.oy - b.h + ly, b.n);
+  const int gy = wrap(b.oy - b.hy + ly, b.n);
   return (int64_t)gy * b.n + gx;
 }
 

@@ -213,10 +213,10 @@ double side_log_bound(double ws, double wsb, double w0, double P, int h) {
 
 struct BlockCoef { double aW, aE, aS, aN, w0; };
 
-double eps_bound(const BlockCoef& c, int h, int ndim, double G) {
+double eps_bound(const BlockCoef& c, int h, int ndim, double G, bool cut_y = true) {
   double t[4] = {side_log_bound(c.aW, c.aE, c.w0, c.aS + c.aN, h),
                  side_log_bound(c.aE, c.aW, c.w0, c.aS + c.aN, h), -INFINITY, -INFINITY};
-  if (ndim == 2) {
+  if (ndim == 2 && cut_y) {
     t[2] = side_log_bound(c.aS, c.aN, c.w0, c.aW + c.aE, h);
     t[3] = side_log_bound(c.aN, c.aS, c.w0, c.aW + c.aE, h);
   }
@@ -241,6 +241,14 @@ double growth_factor(const Op& op) {
 
 struct Box { int ox, oy, cx, cy, h; };
 
+// Buffer widths per axis: none along an axis the core spans whole (column-
+// wise decompositions, and the D = 1 box), which keeps the periodic coupling
+// along that axis inside the box.
+inline int box_hx(const Box& b, int n) { return b.cx == n ? 0 : b.h; }
+inline int box_hy(const Box& b, int n, int ndim) { return ndim == 2 ? (b.cy == n ? 0 : b.h) : 0; }
+inline int box_lx(const Box& b, int n) { return b.cx + 2 * box_hx(b, n); }
+inline int box_ly(const Box& b, int n, int ndim) { return ndim == 2 ? b.cy + 2 * box_hy(b, n, ndim) : 1; }
+
 BlockCoef block_coef(const Op& op, const Box& b, int h) {
   BlockCoef c{0, 0, 0, 0, -INFINITY};
   double w[5];
@@ -249,11 +257,14 @@ BlockCoef block_coef(const Op& op, const Box& b, int h) {
     return c;
   }
   const int n = op.n;
-  const int Lx = b.cx + 2 * h, Ly = op.ndim == 2 ? b.cy + 2 * h : 1;
+  Box bh = b;
+  bh.h = h;
+  const int hx = box_hx(bh, n), hy = box_hy(bh, n, op.ndim);
+  const int Lx = box_lx(bh, n), Ly = box_ly(bh, n, op.ndim);
   for (int ly = 0; ly < Ly; ++ly)
     for (int lx = 0; lx < Lx; ++lx) {
-      const int gx = ((b.ox - h + lx) % n + n) % n;
-      const int gy = op.ndim == 2 ? ((b.oy - h + ly) % n + n) % n : 0;
+      const int gx = ((b.ox - hx + lx) % n + n) % n;
+      const int gy = op.ndim == 2 ? ((b.oy - hy + ly) % n + n) % n : 0;
       point_weights(op, gx, gy, w);
       c.aW = std::max(c.aW, std::fabs(w[1]));
       c.aE = std::max(c.aE, std::fabs(w[2]));
@@ -268,11 +279,12 @@ BlockCoef block_coef(const Op& op, const Box& b, int h) {
 double block_rho(const Op& op, const Box& b) {
   double w[5], mx = 0.0;
   const int n = op.n;
-  const int Lx = b.cx + 2 * b.h, Ly = op.ndim == 2 ? b.cy + 2 * b.h : 1;
+  const int hx = box_hx(b, n), hy = box_hy(b, n, op.ndim);
+  const int Lx = box_lx(b, n), Ly = box_ly(b, n, op.ndim);
   for (int ly = 0; ly < Ly; ++ly)
     for (int lx = 0; lx < Lx; ++lx) {
-      const int gx = ((b.ox - b.h + lx) % n + n) % n;
-      const int gy = op.ndim == 2 ? ((b.oy - b.h + ly) % n + n) % n : 0;
+      const int gx = ((b.ox - hx + lx) % n + n) % n;
+      const int gy = op.ndim == 2 ? ((b.oy - hy + ly) % n + n) % n : 0;
       point_weights(op, gx, gy, w);
       mx = std::max(mx, std::fabs(w[0]) + std::fabs(w[1]) + std::fabs(w[2]) + std::fabs(w[3]) +
                             std::fabs(w[4]));
@@ -286,7 +298,7 @@ int halo_from_bound(const Op& op, Box b, double tol, int h_min, int h_max, doubl
                     bool* clamped) {
   for (int h = h_min; h <= h_max; ++h) {
     const BlockCoef c = block_coef(op, b, op.variable ? h : 0);
-    if (eps_bound(c, h, op.ndim, G) <= tol) {
+    if (eps_bound(c, h, op.ndim, G, !(op.ndim == 2 && b.cy == op.n)) <= tol) {
       *clamped = false;
       return h;
     }
@@ -421,7 +433,9 @@ lem_status make_partition(lem_plan_s* p) {
     const int c = o.core;
     if (n % c) return fail(LEM_ERR_INVALID, "core side must divide n");
     const int nb = n / c;
-    if (op.ndim == 1) {
+    if (o.columns) {  // cores of c x n: whole columns, buffers across columns only
+      for (int bx = 0; bx < nb; ++bx) p->boxes.push_back({bx * c, 0, c, n, 0});
+    } else if (op.ndim == 1) {
       for (int bx = 0; bx < nb; ++bx) p->boxes.push_back({bx * c, 0, c, 1, 0});
     } else {
       for (int by = 0; by < nb; ++by)
@@ -472,9 +486,9 @@ lem_status make_partition(lem_plan_s* p) {
       }
   }
   for (auto& b : p->boxes) {
-    const int Lx = b.cx + 2 * b.h;
-    const int Ly = op.ndim == 2 ? b.cy + 2 * b.h : 1;
-    if (Lx >= n || (op.ndim == 2 && Ly >= n))
+    const int Lx = box_lx(b, n);
+    const int Ly = box_ly(b, n, op.ndim);
+    if ((b.cx < n && Lx >= n) || (op.ndim == 2 && b.cy < n && Ly >= n))
       return fail(LEM_ERR_INVALID, "box (core + 2*halo) reaches itself through the periodic wrap;"
                                    " use a larger grid, a smaller halo or the global method");
   }
@@ -514,10 +528,11 @@ lem::KBlock make_kblock(const lem_plan_s* p, const Box& b, int m, int nsub, int 
   k.varvel = op.varvel ? 1 : 0;
   k.v_off = 0;
   k.n = op.n; k.ndim = op.ndim;
-  k.ox = b.ox; k.oy = b.oy; k.cx = b.cx; k.cy = b.cy; k.h = b.h;
-  k.Lx = b.cx + 2 * b.h; k.Ly = op.ndim == 2 ? b.cy + 2 * b.h : 1;
+  k.ox = b.ox; k.oy = b.oy; k.cx = b.cx; k.cy = b.cy;
+  k.h = box_hx(b, op.n); k.hy = box_hy(b, op.n, op.ndim);
+  k.Lx = box_lx(b, op.n); k.Ly = box_ly(b, op.n, op.ndim);
   k.m = m; k.nsub = nsub; k.ns = ns; k.diag = diag;
-  k.periodic = (b.cx == op.n && b.h == 0) ? 1 : 0;
+  k.periodic = (b.cx == op.n ? 1 : 0) | (op.ndim == 2 && b.cy == op.n ? 2 : 0);
   return k;
 }
 
@@ -706,7 +721,7 @@ lem_status plan_krylov(lem_plan_s* p, hipStream_t st) {
   for (int r = 0; r < nr; ++r) {
     int mm = 0, ss = 0;
     const Box& rb = p->boxes[reps[r]];
-    const int rnloc = (rb.cx + 2 * rb.h) * (op.ndim == 2 ? rb.cy + 2 * rb.h : 1) + (p->forced ? 1 : 0);
+    const int rnloc = box_lx(rb, op.n) * box_ly(rb, op.n, op.ndim) + (p->forced ? 1 : 0);
     if (!choose_m(&est[(size_t)r * nsc * jl.size()], jl, nsc, o.krylov_tol, o.krylov_m, mcal,
                   op.ndim, rnloc, &mm, &ss))
       return fail(LEM_ERR_NOT_CONVERGED,
@@ -1146,6 +1161,8 @@ lem_status check_options(const lem_options* o) {
     return fail(LEM_ERR_INVALID, "Krylov dimension must be in [2, " + std::to_string(mlim) + "]");
   if (o->max_substeps < 1) return fail(LEM_ERR_INVALID, "max_substeps must be >= 1");
   if (!(o->krylov_tol > 0)) return fail(LEM_ERR_INVALID, "krylov_tol must be > 0");
+  if (o->columns && (o->method != LEM_METHOD_KRYLOV || o->core <= 0))
+    return fail(LEM_ERR_UNSUPPORTED, "column-wise cores need the Krylov method and a core width");
   return LEM_OK;
 }
 
@@ -1157,7 +1174,7 @@ void fill_info(const lem_plan_s* p, lem_plan_info* in) {
   in->halo_max = 0;
   in->n_loc_max = 0;
   for (const auto& b : p->boxes) {
-    const int64_t nl = (int64_t)(b.cx + 2 * b.h) * (p->op.ndim == 2 ? b.cy + 2 * b.h : 1);
+    const int64_t nl = (int64_t)box_lx(b, p->op.n) * box_ly(b, p->op.n, p->op.ndim);
     in->n_loc_total += nl;
     in->n_loc_max = std::max<int>(in->n_loc_max, (int)nl);
     in->halo_min = std::min(in->halo_min, b.h);
@@ -1550,12 +1567,13 @@ lem_status lem_plan_copy_maps(lem_plan_t p, int32_t* boxes, int32_t* gather, int
       boxes[5 * k + 0] = b.ox; boxes[5 * k + 1] = b.oy; boxes[5 * k + 2] = b.cx;
       boxes[5 * k + 3] = ndim == 2 ? b.cy : 1; boxes[5 * k + 4] = b.h;
     }
-    const int Lx = b.cx + 2 * b.h, Ly = ndim == 2 ? b.cy + 2 * b.h : 1;
+    const int hx = box_hx(b, n), hy = box_hy(b, n, ndim);
+    const int Lx = box_lx(b, n), Ly = box_ly(b, n, ndim);
     if (gather)
       for (int ly = 0; ly < Ly; ++ly)
         for (int lx = 0; lx < Lx; ++lx) {
-          const int gx = ((b.ox - b.h + lx) % n + n) % n;
-          const int gy = ndim == 2 ? ((b.oy - b.h + ly) % n + n) % n : 0;
+          const int gx = ((b.ox - hx + lx) % n + n) % n;
+          const int gy = ndim == 2 ? ((b.oy - hy + ly) % n + n) % n : 0;
           gather[gi++] = gy * n + gx;
         }
     if (scatter) {

@@ -444,3 +444,19 @@ def test_global_krylov_vortex_vs_dense(height):
     got2 = run(plan2, p2.states, 1)
     want2 = ge.krylov_step(W2, p2.states, m=60, tol=1e-16)
     assert rel_l2(got2, want2) <= 1e-11
+
+
+# column-wise decomposition on an anisotropic mesh (section 4.3): whole
+# columns with buffers across columns only, vertical wrap kept in every box
+@pytest.mark.parametrize("n,core,ns", [(64, 8, 2), (96, 12, 3)])
+def test_krylov_column_partition(n, core, ns):
+    p = L.workload_2d_columns(n=n, n_states=ns)
+    plan = lem.Plan(lem.Operator.from_problem(p), p.dt, method="krylov", core=core, halo=0,
+                    halo_min=2, halo_max=12, halo_tol=1e-8, n_states=ns, columns=True,
+                    krylov_tol=1e-14)
+    boxes = check_maps(plan, 2, p.n)
+    assert np.all(boxes[:, 3] == n)
+    got = run(plan, p.states, 2)
+    want = oracle_lem(p, boxes, p.states, 2, krylov_above=4096, krylov_tol=1e-16)
+    assert rel_l2(got, want) <= 1e-12
+    assert plan.query()["device_status"] == 0

@@ -148,3 +148,25 @@ def test_face_velocity_errors():
     with pytest.raises(lem.LemError):
         lem.Plan(lem.Operator(2, n, 1 / n, (0.0, 0.0), 1e-3, vel_faces=F), 1 / n, method="dense",
                  core=8, halo=2, dry_run=True)
+
+
+def test_column_partition_maps_and_halos_match_oracle():
+    p = L.workload_2d_columns(n=128, n_states=1)
+    W = op.from_problem(p)
+    G = H.growth_factor(W)
+    plan = lem.Plan(lem.Operator.from_problem(p), p.dt, core=16, halo=0, halo_min=2,
+                    halo_max=24, halo_tol=1e-8, columns=True, dry_run=True)
+    boxes, gather, scatter = plan.maps()
+    assert boxes.shape == (8, 5) and np.all(boxes[:, 3] == 128) and np.all(boxes[:, 1] == 0)
+    Go, So = _oracle_maps(boxes, 2, p.n)
+    assert np.array_equal(gather, Go.astype(np.int32))
+    assert np.array_equal(scatter, So.astype(np.int32))
+    for b in boxes:
+        box = P.Box(*map(int, b))
+        co = H.block_coefficients(W, box, 2)
+        assert H.accepts(co, 2, 1e-8, 2, box.h, G, cut_y=False), box
+    q = plan.query()
+    assert q["n_loc_max"] == (16 + 2 * q["halo_max"]) * 128
+    with pytest.raises(lem.LemError):  # column-wise cores are a Krylov feature
+        lem.Plan(lem.Operator.from_problem(p), p.dt, method="dense", core=16, halo=4,
+                 columns=True, dry_run=True)

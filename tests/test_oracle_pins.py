@@ -723,3 +723,45 @@ def test_vortex_lem_converges_to_global_with_halo():
     errs = [rel_l2(lem.step(A, P.uniform_boxes(2, n, 8, h), 2, n, u), g) for h in (1, 2, 4, 7)]
     assert all(b < a for a, b in zip(errs, errs[1:]))
     assert errs[-1] < 1e-5
+
+
+def test_column_boxes_keep_the_vertical_wrap():
+    """Column-wise decomposition (cores of c x n): with no coupling across
+    columns (vertical advection-diffusion only, a_x = 0 and the x part of the
+    diffusion switched off by a huge dx) the columns decouple, so column LEM
+    with h = 0 equals the global exponential exactly -- which requires the
+    periodic vertical couplings inside every column box."""
+    n = 24
+    dx, dy = 1e6, 1.0 / n
+    W = op.weights(2, n, dx, 0.9 * dy, (0.0, 1.0), nu=2e-3, dy=dy)
+    assert np.abs(W.wW).max() < 1e-12 and np.abs(W.wE).max() < 1e-12
+    A = op.sparse(W)
+    u = L.gaussian_blobs_2d(n, 2, seed=4)
+    g = E.expm(A.toarray()) @ u
+    boxes = P.column_boxes(n, 6, 0)
+    P.check_tiling(boxes, 2, n)
+    assert rel_l2(lem.step(A, boxes, 2, n, u), g) <= 1e-13
+    # a square decomposition of the same problem cuts the columns and is not exact
+    assert rel_l2(lem.step(A, P.uniform_boxes(2, n, 6, 2), 2, n, u), g) > 1e-6
+
+
+def test_column_lem_converges_with_horizontal_buffer():
+    """Anisotropic mesh (dy = dx / 8), large vertical Courant number, column
+    boxes with buffers only across columns: the error falls with h, and the
+    bound without y cuts dominates it."""
+    n = 32
+    dx, dy = 1.0 / n, 1.0 / (8 * n)
+    F = L.vortex_faces(n, height=1.0 / 8)
+    W = op.weights(2, n, dx, 0.5 * dx, (0.0, 0.0), nu=1e-5, vel_faces=F, dy=dy)
+    A = op.sparse(W)
+    u = L.gaussian_blobs_2d(n, 2, seed=6)
+    g = E.expm(A.toarray()) @ u
+    G = H.growth_factor(W)
+    errs = []
+    for h in (1, 2, 4, 6):
+        boxes = P.column_boxes(n, 8, h)
+        errs.append(rel_l2(lem.step(A, boxes, 2, n, u), g))
+        co = H.block_coefficients(W, boxes[1], 2)
+        assert H.eps(co, h, 2, G, cut_y=False) >= errs[-1] * 0.5
+    assert all(b < a for a, b in zip(errs, errs[1:]))
+    assert errs[-1] < 1e-6
