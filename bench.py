@@ -116,13 +116,14 @@ def parse_args():
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run one device copy of this many MiB (a reference kernel of "
                          "known traffic for scaling HBM counters)")
-    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2", "c3", "c4", "f1", "f2", "f3"],
+    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2", "c3", "c4", "f1", "f2", "f3", "f4"],
                     help="c1 (default): 256^2 x 64 states, dense FP64; c0: 1D 1024; "
                          "c2: 1024^2 lognormal nu, uneven Krylov; c3: 512^2 x 128 states, "
                          "mixed precision; c4: served Poisson stream; f1: c1 with a "
                          "constant source g (exponential-Euler step with forcing); f2: "
                          "Burgers by exponential Rosenbrock-Euler LEM; f3: Schroedinger with a "
-                         "harmonic potential (complex blocks in real form)")
+                         "harmonic potential (complex blocks in real form); f4: variable "
+                         "vortex velocity and anisotropic column-wise cores (Krylov)")
     ap.add_argument("--requests", type=int, default=300)
     return ap.parse_args()
 
@@ -135,7 +136,8 @@ def main() -> int:
               "which is not implemented here)", file=sys.stderr)
         return 2
     fn = {"c1": bench_c1, "c0": bench_c0, "c2": bench_c2, "c3": bench_c3,
-          "c4": bench_c4, "f1": bench_f1, "f2": bench_f2, "f3": bench_f3}[args.workload]
+          "c4": bench_c4, "f1": bench_f1, "f2": bench_f2, "f3": bench_f3,
+            "f4": bench_f4}[args.workload]
     out = fn(args)
     print(json.dumps(out), flush=True)
     return 0
@@ -477,6 +479,104 @@ def cpu_baseline_schrodinger(c0, Lx, kappa, dt, core, halo, budget_s):
     return {"value": n * k * steps / el, "unit": "DOF-steps/s", "cores": int(cores),
             "kind": "oracle", "sample": f"{steps} LEM steps of {k} members (local exponentials "
             f"excluded)"}
+
+
+def bench_f4(args) -> dict:
+    """Variable divergence-free velocity and anisotropic column-wise
+    decompositions (eq. ibv2d, section 4.3), Krylov local actions:
+    (A) 512^2 single periodic vortex, Courant 2, nu = 1e-4, 16 Gaussian blobs,
+        16^2 cores with decay-bound buffers, against the global Krylov method;
+    (B) 128^2 anisotropic mesh (dy = dx/16), horizontal Courant 0.8, vertical
+        diffusion number 6, 64 blobs: column-wise cores (8 columns wide) against
+        square 16^2 cores and the global method."""
+    import torch
+    import lem_inputs as L
+    import paper_1505_02248_amd as lem
+    torch.cuda.init()
+    stream = torch.cuda.Stream()
+    steps = min(args.steps, 40)
+    out = {}
+
+    def timed(plan, x, k):
+        y = torch.empty_like(x)
+        plan.step(x, y, 2, stream=stream)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        plan.step(x, y, k, stream=stream)
+        stream.synchronize()
+        return (time.perf_counter() - t0) / k
+
+    def err_vs(plan, ref, x, k):
+        y = torch.empty_like(x)
+        plan.step(x, y, k, stream=stream)
+        stream.synchronize()
+        return _rel(y, ref, torch)
+
+    with torch.cuda.stream(stream):
+        # (A) vortex, square cores
+        p = L.workload_2d_vortex(n=512, n_states=16, courant=2.0)
+        opr = lem.Operator.from_problem(p)
+        ns = p.states.shape[1]
+        x = torch.from_numpy(p.states.copy()).to("cuda")
+        t0 = time.perf_counter()
+        plan = lem.Plan(opr, p.dt, method="krylov", core=16, halo=0, halo_min=2, halo_max=24,
+                        halo_tol=1e-8, n_states=ns, krylov_tol=1e-10, use_graph=True,
+                        stream=stream)
+        plan_s = time.perf_counter() - t0
+        q = plan.query()
+        t_lem = timed(plan, x, steps)
+        gplan = lem.Plan(opr, p.dt, method="global", n_states=ns, krylov_tol=1e-10, stream=stream)
+        gq = gplan.query()
+        t_glob = timed(gplan, x, 3)
+        ref = torch.empty_like(x)
+        lem.Plan(opr, p.dt, method="global", n_states=ns, krylov_tol=1e-13, stream=stream).step(
+            x, ref, 3, stream=stream)
+        errA = err_vs(plan, ref, x, 3)
+        valA = p.N * ns / t_lem
+        log(f"vortex LEM: {valA:.3e} DOF-steps/s ({1e3 * t_lem:.2f} ms/step), global "
+            f"{p.N * ns / t_glob:.3e} ({1e3 * t_glob:.2f} ms/step), err {errA:.2e}")
+        out["vortex"] = {"lem_dof_steps_per_s": valA, "lem_ms_per_step": 1e3 * t_lem,
+                         "global_dof_steps_per_s": p.N * ns / t_glob,
+                         "global_ms_per_step": 1e3 * t_glob, "lem_over_global": t_glob / t_lem,
+                         "lem_rel_l2_vs_global_after_3_steps": errA,
+                         "halo_range": [q["halo_min"], q["halo_max"]],
+                         "halo_clamped_blocks": q["halo_clamped"],
+                         "m_range": [q["m_min"], q["m_max"]], "substeps_max": q["substeps_max"],
+                         "global_m": gq["m_max"], "global_substeps": gq["substeps_max"],
+                         "plan_s": plan_s}
+        # (B) anisotropic mesh: column-wise against square cores
+        pb = L.workload_2d_columns(n=128, n_states=64)
+        ob = lem.Operator.from_problem(pb)
+        nsb = pb.states.shape[1]
+        xb = torch.from_numpy(pb.states.copy()).to("cuda")
+        refb = torch.empty_like(xb)
+        lem.Plan(ob, pb.dt, method="global", n_states=nsb, krylov_tol=1e-13, stream=stream).step(
+            xb, refb, 3, stream=stream)
+        res = {}
+        for label, kw in (("columns", dict(core=8, columns=True)), ("square", dict(core=16))):
+            pl = lem.Plan(ob, pb.dt, method="krylov", halo=0, halo_min=2, halo_max=24,
+                          halo_tol=1e-8, n_states=nsb, krylov_tol=1e-10, use_graph=True,
+                          stream=stream, **kw)
+            qb = pl.query()
+            t = timed(pl, xb, steps)
+            res[label] = {"dof_steps_per_s": pb.N * nsb / t, "ms_per_step": 1e3 * t,
+                          "rel_l2_vs_global_after_3_steps": err_vs(pl, refb, xb, 3),
+                          "n_blocks": qb["n_blocks"], "halo_range": [qb["halo_min"], qb["halo_max"]],
+                          "halo_clamped_blocks": qb["halo_clamped"], "n_loc_max": qb["n_loc_max"],
+                          "m_range": [qb["m_min"], qb["m_max"]],
+                          "substeps_max": qb["substeps_max"]}
+            log(f"anisotropic {label}: {res[label]}")
+        gb = lem.Plan(ob, pb.dt, method="global", n_states=nsb, krylov_tol=1e-10, stream=stream)
+        tg = timed(gb, xb, 3)
+        res["global"] = {"dof_steps_per_s": pb.N * nsb / tg, "ms_per_step": 1e3 * tg,
+                         "m": gb.query()["m_max"], "substeps": gb.query()["substeps_max"]}
+        out["anisotropic_columns"] = res
+    wl = {"workload": "2D 512x512 periodic advection-diffusion -div(a c) + nu lap c, single "
+                      "divergence-free vortex (face velocities from a stream function), Courant 2, "
+                      "nu=1e-4, 16 Gaussian blobs; Krylov LEM on 16^2 cores, decay-bound buffers "
+                      "2-24 (1e-8/step), calibrated m, HIP graph per step, FP64",
+          "n": 512, "n_states": 16, "core": 16}
+    return _line(args, wl, valA, "DOF-steps/s", steps, t_lem * steps, "f64", out)
 
 
 def bench_c0(args) -> dict:

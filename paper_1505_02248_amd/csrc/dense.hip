@@ -327,9 +327,9 @@ __global__ void pack_kernel(PackArgs a) {
       const int kk = c >> 2, kq = c & 3;
       const int64_t idx = (((int64_t)rt * (a.cols_p >> 2) + kk) << 6) + (kq << 4) + ri;
       a.e64[idx] = v;
-      a.e32[idx] = (float)v;
+      if (a.e32) a.e32[idx] = (float)v;
     }
-    {  // bf16 pieces (k-step 32)
+    if (a.e16) {  // bf16 pieces (k-step 32)
       const int ks = c >> 5, kr = c & 31;
       const int lane = ri + 16 * (kr >> 3), el = kr & 7;
       const int64_t idx = ((((int64_t)rt * (a.cols_p >> 5) + ks) << 6) + lane) * 8 + el;
@@ -709,6 +709,76 @@ hipError_t dense_assemble(const void* ops, double* A, int nl, int nu, hipStream_
   dim3 g = grid1((int64_t)nl * nl);
   g.y = nu;
   hipLaunchKernelGGL(assemble_kernel, g, dim3(256), 0, st, (const DenseOp*)ops, A, nl);
+  return hipGetLastError();
+}
+
+// Local matrices of a variable-coefficient operator (face diffusion numbers
+// mux, muy and, with face velocities, ax, ay, all dt-scaled): dt*A_M of every
+// box in [u0, u0 + count), one workgroup per row.  The row weights are those
+// of the conservative form (section 4.3), couplings leaving the box dropped.
+struct VarOp {
+  const double* mux;
+  const double* muy;
+  const double* ax;  // null: constant velocity (chx, chy)
+  const double* ay;
+  double chx, chy;
+  int n, ndim;
+};
+
+struct VarBox {
+  int ox, oy, h, Lx, Ly;
+};
+
+__global__ void var_assemble_kernel(VarOp o, const VarBox* boxes, int nl, double* A) {
+  const int u = blockIdx.y, r = blockIdx.x;
+  const VarBox b = boxes[u];
+  const int n = o.n;
+  const int ry = r / b.Lx, rx = r - ry * b.Lx;
+  const int gx = wrap(b.ox - b.h + rx, n);
+  const int gy = o.ndim == 2 ? wrap(b.oy - b.h + ry, n) : 0;
+  const int64_t g = (int64_t)gy * n + gx, gw = (int64_t)gy * n + wrap(gx - 1, n);
+  const double me = o.mux[g], mw = o.mux[gw];
+  double mn = 0.0, ms = 0.0, an = 0.0, as = 0.0;
+  const int64_t gs = (int64_t)wrap(gy - 1, n) * n + gx;
+  if (o.ndim == 2) { mn = o.muy[g]; ms = o.muy[gs]; }
+  double w0 = -(me + mw + mn + ms), wW, wE, wS = 0.0, wN = 0.0;
+  if (o.ax) {
+    const double ae = o.ax[g], aw = o.ax[gw];
+    if (o.ndim == 2) { an = o.ay[g]; as = o.ay[gs]; }
+    w0 -= (ae - aw) + (an - as);
+    wW = mw + aw;
+    wE = me - ae;
+    if (o.ndim == 2) { wS = ms + as; wN = mn - an; }
+  } else {
+    wW = mw + o.chx;
+    wE = me - o.chx;
+    if (o.ndim == 2) { wS = ms + o.chy; wN = mn - o.chy; }
+  }
+  double* row = A + ((int64_t)u * nl + r) * nl;
+  for (int c = threadIdx.x; c < nl; c += blockDim.x) {
+    double v = 0.0;
+    if (c == r) v = w0;
+    else if (c == r - 1 && rx > 0) v = wW;
+    else if (c == r + 1 && rx < b.Lx - 1) v = wE;
+    else if (c == r - b.Lx && ry > 0) v = wS;
+    else if (c == r + b.Lx && ry < b.Ly - 1) v = wN;
+    row[c] = v;
+  }
+}
+
+size_t dense_varbox_size() { return sizeof(VarBox); }
+
+void dense_varbox_fill(void* dst, int i, int ox, int oy, int h, int Lx, int Ly) {
+  VarBox* b = (VarBox*)dst + i;
+  b->ox = ox; b->oy = oy; b->h = h; b->Lx = Lx; b->Ly = Ly;
+}
+
+hipError_t dense_assemble_var(const double* mux, const double* muy, const double* ax,
+                              const double* ay, double chx, double chy, int n, int ndim,
+                              const void* boxes, int count, int nl, double* A, hipStream_t st) {
+  VarOp o{mux, muy, ax, ay, chx, chy, n, ndim};
+  hipLaunchKernelGGL(var_assemble_kernel, dim3((unsigned)nl, (unsigned)count), dim3(256), 0, st,
+                     o, (const VarBox*)boxes, nl, A);
   return hipGetLastError();
 }
 

@@ -892,10 +892,102 @@ lem_status dense_forcing_term(lem_plan_s* p, const void* d_ops, const double* ho
   return LEM_OK;
 }
 
+// Variable coefficients: every region has its own local operator, so every
+// region gets its own stored block (the HBM holds them all: 3.8 GB for 1024
+// blocks of 256 x 1792 in FP64).  All boxes take the largest buffer width of
+// the partition (one block shape).  The blocks are assembled from the face
+// arrays and exponentiated in chunks that bound the Pade work space.
+lem_status plan_dense_variable(lem_plan_s* p, hipStream_t st) {
+  const Op& op = p->op;
+  int h = 0;
+  for (const Box& b : p->boxes) h = std::max(h, b.h);
+  for (Box& b : p->boxes) b.h = h;
+  const Box& b0 = p->boxes[0];
+  const int Lx = b0.cx + 2 * h, Ly = op.ndim == 2 ? b0.cy + 2 * h : 1;
+  const int nl = Lx * Ly, nb = (int)p->boxes.size();
+  p->U = nb;
+  p->rows = b0.cx * (op.ndim == 2 ? b0.cy : 1);
+  p->cols = nl;
+  p->rows_p = (p->rows + 63) / 64 * 64;
+  p->cols_p = (nl + 31) / 32 * 32;
+  LEM_TRY(upload_coef(p, st));
+  const size_t es = (size_t)p->rows_p * p->cols_p;
+  LEM_TRY(dalloc(p, &p->d_e64, es * nb, &p->bytes_blocks));
+  if (p->opt.precision == LEM_FP32) LEM_TRY(dalloc(p, &p->d_e32, es * nb, &p->bytes_blocks));
+  if (p->ns % 64) LEM_TRY(dalloc(p, &p->d_core, (size_t)p->rows * nl * nb, &p->bytes_blocks));
+  // chunk of blocks per Pade batch: seven nl x nl matrices each, within ~24 GB
+  const size_t per = (size_t)nl * nl * 8;
+  const int chunk = (int)std::max<size_t>(1, std::min<size_t>(nb, (size_t)(24ull << 30) / (7 * per)));
+  double *A = nullptr, *Vb = nullptr;
+  std::vector<double*> work;
+  int* work_s = nullptr;
+  unsigned char* dvb = nullptr;
+  auto cleanup = [&]() {
+    for (void* q : {(void*)A, (void*)Vb, (void*)work_s, (void*)dvb})
+      if (q) dfree(p, q);
+    for (double* w : work) dfree(p, w);
+  };
+  lem_status s = dalloc(p, &A, (size_t)chunk * nl * nl);
+  if (s == LEM_OK) s = dalloc(p, &Vb, (size_t)chunk * nl * nl);
+  for (int q = 0; q < 5 && s == LEM_OK; ++q) {
+    double* w;
+    s = dalloc(p, &w, (size_t)chunk * nl * nl);
+    if (s == LEM_OK) work.push_back(w);
+  }
+  if (s == LEM_OK) {
+    double* w;
+    s = dalloc(p, &w, (size_t)chunk);
+    if (s == LEM_OK) work.push_back(w);
+  }
+  if (s == LEM_OK) s = dalloc(p, &work_s, (size_t)chunk);
+  if (s == LEM_OK) s = dalloc(p, &dvb, lem::dense_varbox_size() * nb);
+  std::vector<unsigned char> hvb(lem::dense_varbox_size() * nb);
+  for (int i = 0; i < nb; ++i) {
+    const Box& b = p->boxes[i];
+    lem::dense_varbox_fill(hvb.data(), i, b.ox, b.oy, h, Lx, Ly);
+  }
+  if (s == LEM_OK) s = upload(dvb, hvb.data(), hvb.size(), st);
+  const size_t N = (size_t)op.N();
+  for (int u0 = 0; u0 < nb && s == LEM_OK; u0 += chunk) {
+    const int cnt = std::min(chunk, nb - u0);
+    if (lem::dense_assemble_var(p->d_coef, p->d_coef + N, op.varvel ? p->d_coef + 2 * N : nullptr,
+                                op.varvel ? p->d_coef + 3 * N : nullptr, op.chx, op.chy, op.n,
+                                op.ndim, dvb + lem::dense_varbox_size() * u0, cnt, nl, A,
+                                st) != hipSuccess) {
+      s = fail(LEM_ERR_HIP, "variable assembly failed");
+      break;
+    }
+    s = dense_expm(p, A, Vb, nl, cnt, st, &p->squarings, &work, work_s);
+    for (int u = u0; u < u0 + cnt && s == LEM_OK; ++u)
+      if (lem::dense_pack(Vb + (size_t)(u - u0) * nl * nl, nl, Lx, h, b0.cx,
+                          op.ndim == 2 ? b0.cy : 1, op.ndim, p->rows, p->rows_p, p->cols_p,
+                          p->d_e64 + u * es, p->d_e32 ? p->d_e32 + u * es : nullptr, nullptr,
+                          p->d_core ? p->d_core + (size_t)u * p->rows * nl : nullptr,
+                          st) != hipSuccess)
+        s = fail(LEM_ERR_HIP, "block packing failed");
+  }
+  if (s == LEM_OK && hipStreamSynchronize(st) != hipSuccess)
+    s = fail(LEM_ERR_HIP, "plan synchronization failed");
+  cleanup();
+  if (s != LEM_OK) return s;
+  std::vector<unsigned char> db(lem::dense_block_size() * nb);
+  for (int i = 0; i < nb; ++i) {
+    const Box& b = p->boxes[i];
+    lem::dense_block_fill(db.data(), i, b.ox, b.oy, b.cx, op.ndim == 2 ? b.cy : 1, h, Lx, Ly, i);
+  }
+  {
+    unsigned char* d;
+    LEM_TRY(dalloc(p, &d, db.size(), &p->bytes_work));
+    p->d_db = d;
+  }
+  LEM_TRY(upload(p->d_db, db.data(), db.size(), st));
+  p->tile = p->opt.precision == LEM_FP32 ? 2 : 0;
+  return LEM_OK;
+}
+
 lem_status plan_dense(lem_plan_s* p, hipStream_t st, const double* host_g) {
   const Op& op = p->op;
-  if (op.variable)
-    return fail(LEM_ERR_UNSUPPORTED, "stored local exponentials need constant coefficients");
+  if (op.variable) return plan_dense_variable(p, st);
   if (p->opt.core <= 0) return fail(LEM_ERR_INVALID, "the dense method needs a uniform core");
   if (p->opt.precision >= LEM_BF16X2 && p->ns % 64)
     return fail(LEM_ERR_UNSUPPORTED, "bf16 split application needs n_states % 64 == 0");
@@ -1214,8 +1306,10 @@ lem_status create_plan(const lem_operator* op, double dt, const lem_options* opt
   p->stream = (hipStream_t)stream;
   lem_status s = build_op(op, dt, &p->op);
   if (s != LEM_OK) return guard(s);
-  if (p->method == LEM_METHOD_DENSE && p->op.variable)
-    return guard(fail(LEM_ERR_UNSUPPORTED, "stored local exponentials need constant coefficients"));
+  if (p->method == LEM_METHOD_DENSE && p->op.variable &&
+      (p->forced || opt->precision >= LEM_BF16X2 || opt->core <= 0))
+    return guard(fail(LEM_ERR_UNSUPPORTED, "variable-coefficient stored blocks take a uniform core, "
+                                           "FP64 or FP32 and no forcing"));
   p->N = p->op.N();
   p->forced = op->forcing != nullptr;
   if (p->forced) {

@@ -29,6 +29,12 @@ size_t dense_op_size();
 void dense_op_fill(void* dst, int i, double w0, double wW, double wE, double wS, double wN,
                    int Lx, int Ly);
 hipError_t dense_assemble(const void* ops, double* A, int nl, int nu, hipStream_t st);
+// variable coefficients: dt*A_M of count boxes from the face arrays
+size_t dense_varbox_size();
+void dense_varbox_fill(void* dst, int i, int ox, int oy, int h, int Lx, int Ly);
+hipError_t dense_assemble_var(const double* mux, const double* muy, const double* ax,
+                              const double* ay, double chx, double chy, int n, int ndim,
+                              const void* boxes, int count, int nl, double* A, hipStream_t st);
 hipError_t dense_assemble_aug(const void* ops, double* A, int nl, int nu, hipStream_t st);
 hipError_t dense_norm1(const double* A, int nl, int nu, double* norms, hipStream_t st);
 hipError_t dense_scale_pow2(double* A, int nl, int nu, const int* s, hipStream_t st);

@@ -460,3 +460,30 @@ def test_krylov_column_partition(n, core, ns):
     want = oracle_lem(p, boxes, p.states, 2, krylov_above=4096, krylov_tol=1e-16)
     assert rel_l2(got, want) <= 1e-12
     assert plan.query()["device_status"] == 0
+
+
+# stored blocks for variable coefficients: one block per region (vortex faces,
+# lognormal nu), FP64 and FP32 application, MFMA and plain paths
+@pytest.mark.parametrize("work,ns,precision,tol", [("vortex", 64, "fp64", 1e-12),
+                                                   ("vortex", 3, "fp64", 1e-12),
+                                                   ("lognormal", 64, "fp32", 1e-5),
+                                                   ("columns", 64, "fp64", 1e-12)])
+def test_dense_variable_coefficients(work, ns, precision, tol):
+    if work == "vortex":
+        p = L.workload_2d_vortex(n=64, n_states=ns, courant=2.0)
+        core, halo = 16, 6
+    elif work == "lognormal":
+        p = L.workload_2d_variable(n=64)
+        p.states = L.smooth_states_2d(64, ns, 21)
+        core, halo = 16, 4
+    else:  # anisotropic mesh, square cores
+        p = L.workload_2d_columns(n=64, n_states=ns)
+        core, halo = 16, 8
+    plan = lem.Plan(lem.Operator.from_problem(p), p.dt, method="dense", precision=precision,
+                    core=core, halo=halo, n_states=ns, autotune=(ns % 64 == 0))
+    q = plan.query()
+    assert q["n_unique"] == q["n_blocks"] == (64 // core) ** 2
+    boxes = check_maps(plan, 2, p.n)
+    got = run(plan, p.states, 2)
+    want = oracle_lem(p, boxes, p.states, 2)
+    assert rel_l2(got, want) <= tol

@@ -147,7 +147,10 @@ def test_face_velocity_errors():
                  dry_run=True)  # vel must be zero with face velocities
     with pytest.raises(lem.LemError):
         lem.Plan(lem.Operator(2, n, 1 / n, (0.0, 0.0), 1e-3, vel_faces=F), 1 / n, method="dense",
-                 core=8, halo=2, dry_run=True)
+                 core=0, halo=2, dry_run=True)  # stored blocks need a uniform core
+    with pytest.raises(lem.LemError):
+        lem.Plan(lem.Operator(2, n, 1 / n, (0.0, 0.0), 1e-3, vel_faces=F), 1 / n, method="dense",
+                 precision="bf16x3", core=8, halo=2, n_states=64, dry_run=True)
 
 
 def test_column_partition_maps_and_halos_match_oracle():
