@@ -483,12 +483,14 @@ def cpu_baseline_schrodinger(c0, Lx, kappa, dt, core, halo, budget_s):
 
 def bench_f4(args) -> dict:
     """Variable divergence-free velocity and anisotropic column-wise
-    decompositions (eq. ibv2d, section 4.3), Krylov local actions:
-    (A) 512^2 single periodic vortex, Courant 2, nu = 1e-4, 16 Gaussian blobs,
-        16^2 cores with decay-bound buffers, against the global Krylov method;
+    decompositions (eq. ibv2d, section 4.3):
+    (A) 512^2 single periodic vortex, Courant 2, nu = 1e-4, 64 Gaussian blobs,
+        16^2 cores with decay-bound buffers: LEM with one stored block per region
+        (FP64 MFMA), LEM with Krylov local actions (uneven cores), and the global
+        Krylov method;
     (B) 128^2 anisotropic mesh (dy = dx/16), horizontal Courant 0.8, vertical
-        diffusion number 6, 64 blobs: column-wise cores (8 columns wide) against
-        square 16^2 cores and the global method."""
+        diffusion number 6, 64 blobs: Krylov LEM on column-wise cores (8 columns
+        wide) against square 16^2 cores and the global method."""
     import torch
     import lem_inputs as L
     import paper_1505_02248_amd as lem
@@ -501,10 +503,14 @@ def bench_f4(args) -> dict:
         y = torch.empty_like(x)
         plan.step(x, y, 2, stream=stream)
         stream.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
+        e0.record(stream)
         plan.step(x, y, k, stream=stream)
+        e1.record(stream)
         stream.synchronize()
-        return (time.perf_counter() - t0) / k
+        return (time.perf_counter() - t0) / k, e0.elapsed_time(e1) / k
 
     def err_vs(plan, ref, x, k):
         y = torch.empty_like(x)
@@ -513,37 +519,49 @@ def bench_f4(args) -> dict:
         return _rel(y, ref, torch)
 
     with torch.cuda.stream(stream):
-        # (A) vortex, square cores
-        p = L.workload_2d_vortex(n=512, n_states=16, courant=2.0)
+        # (A) vortex
+        p = L.workload_2d_vortex(n=512, n_states=64, courant=2.0)
         opr = lem.Operator.from_problem(p)
         ns = p.states.shape[1]
         x = torch.from_numpy(p.states.copy()).to("cuda")
-        t0 = time.perf_counter()
-        plan = lem.Plan(opr, p.dt, method="krylov", core=16, halo=0, halo_min=2, halo_max=24,
-                        halo_tol=1e-8, n_states=ns, krylov_tol=1e-10, use_graph=True,
-                        stream=stream)
-        plan_s = time.perf_counter() - t0
-        q = plan.query()
-        t_lem = timed(plan, x, steps)
-        gplan = lem.Plan(opr, p.dt, method="global", n_states=ns, krylov_tol=1e-10, stream=stream)
-        gq = gplan.query()
-        t_glob = timed(gplan, x, 3)
         ref = torch.empty_like(x)
         lem.Plan(opr, p.dt, method="global", n_states=ns, krylov_tol=1e-13, stream=stream).step(
             x, ref, 3, stream=stream)
-        errA = err_vs(plan, ref, x, 3)
-        valA = p.N * ns / t_lem
-        log(f"vortex LEM: {valA:.3e} DOF-steps/s ({1e3 * t_lem:.2f} ms/step), global "
-            f"{p.N * ns / t_glob:.3e} ({1e3 * t_glob:.2f} ms/step), err {errA:.2e}")
-        out["vortex"] = {"lem_dof_steps_per_s": valA, "lem_ms_per_step": 1e3 * t_lem,
-                         "global_dof_steps_per_s": p.N * ns / t_glob,
-                         "global_ms_per_step": 1e3 * t_glob, "lem_over_global": t_glob / t_lem,
-                         "lem_rel_l2_vs_global_after_3_steps": errA,
-                         "halo_range": [q["halo_min"], q["halo_max"]],
-                         "halo_clamped_blocks": q["halo_clamped"],
-                         "m_range": [q["m_min"], q["m_max"]], "substeps_max": q["substeps_max"],
-                         "global_m": gq["m_max"], "global_substeps": gq["substeps_max"],
-                         "plan_s": plan_s}
+        log("planning stored blocks per region (vortex, 1024 blocks)")
+        t0 = time.perf_counter()
+        dplan = lem.Plan(opr, p.dt, method="dense", core=16, halo=0, halo_min=2, halo_max=24,
+                         halo_tol=1e-8, n_states=ns, autotune=True, stream=stream)
+        stream.synchronize()
+        dplan_s = time.perf_counter() - t0
+        dq = dplan.query()
+        t_dense, ev_dense = timed(dplan, x, steps)
+        err_dense = err_vs(dplan, ref, x, 3)
+        log(f"vortex stored-block LEM: {1e3 * t_dense:.3f} ms/step, plan {dplan_s:.1f} s, "
+            f"err {err_dense:.2e}")
+        kplan = lem.Plan(opr, p.dt, method="krylov", core=0, halo=0, halo_min=2, halo_max=16,
+                         halo_tol=1e-8, n_states=ns, krylov_tol=1e-10, use_graph=True,
+                         stream=stream)
+        kq = kplan.query()
+        t_kry, _ = timed(kplan, x, max(3, steps // 8))
+        err_kry = err_vs(kplan, ref, x, 3)
+        gplan = lem.Plan(opr, p.dt, method="global", n_states=ns, krylov_tol=1e-10, stream=stream)
+        gq = gplan.query()
+        t_glob, _ = timed(gplan, x, 3)
+        log(f"vortex Krylov LEM {1e3 * t_kry:.2f} ms/step, global {1e3 * t_glob:.2f} ms/step")
+        nloc = (16 + 2 * dq["halo_max"]) ** 2
+        flops = 2.0 * nloc * 256 * ns * dq["n_blocks"]
+        out["vortex"] = {
+            "stored_blocks": {"ms_per_step": 1e3 * t_dense, "us_per_launch": 1e3 * ev_dense,
+                              "plan_s": dplan_s, "halo": dq["halo_max"], "n_blocks": dq["n_blocks"],
+                              "bytes_blocks": dq["bytes_blocks"], "tile": dq["tile_config"],
+                              "rel_l2_vs_global_after_3_steps": err_dense},
+            "krylov_lem": {"ms_per_step": 1e3 * t_kry, "halo_range": [kq["halo_min"], kq["halo_max"]],
+                           "m_range": [kq["m_min"], kq["m_max"]], "substeps_max": kq["substeps_max"],
+                           "n_blocks": kq["n_blocks"], "rel_l2_vs_global_after_3_steps": err_kry},
+            "global": {"ms_per_step": 1e3 * t_glob, "m": gq["m_max"], "substeps": gq["substeps_max"]},
+            "stored_over_global_per_step": t_glob / t_dense,
+            "krylov_lem_over_global_per_step": t_glob / t_kry,
+            "break_even_steps_vs_global": dplan_s / max(t_glob - t_dense, 1e-12)}
         # (B) anisotropic mesh: column-wise against square cores
         pb = L.workload_2d_columns(n=128, n_states=64)
         ob = lem.Operator.from_problem(pb)
@@ -558,7 +576,7 @@ def bench_f4(args) -> dict:
                           halo_tol=1e-8, n_states=nsb, krylov_tol=1e-10, use_graph=True,
                           stream=stream, **kw)
             qb = pl.query()
-            t = timed(pl, xb, steps)
+            t, _ = timed(pl, xb, steps)
             res[label] = {"dof_steps_per_s": pb.N * nsb / t, "ms_per_step": 1e3 * t,
                           "rel_l2_vs_global_after_3_steps": err_vs(pl, refb, xb, 3),
                           "n_blocks": qb["n_blocks"], "halo_range": [qb["halo_min"], qb["halo_max"]],
@@ -567,16 +585,22 @@ def bench_f4(args) -> dict:
                           "substeps_max": qb["substeps_max"]}
             log(f"anisotropic {label}: {res[label]}")
         gb = lem.Plan(ob, pb.dt, method="global", n_states=nsb, krylov_tol=1e-10, stream=stream)
-        tg = timed(gb, xb, 3)
+        tg, _ = timed(gb, xb, 3)
         res["global"] = {"dof_steps_per_s": pb.N * nsb / tg, "ms_per_step": 1e3 * tg,
                          "m": gb.query()["m_max"], "substeps": gb.query()["substeps_max"]}
         out["anisotropic_columns"] = res
+    achieved = flops / (ev_dense * 1e-3) / 1e12
+    roof = {"bound": "mfma", "achieved": achieved, "peak": MFMA_FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / MFMA_FP64_PEAK_TFLOPS, "traffic": None,
+            "kernel": "apply_mfma_kernel<double> (one stored block per region)",
+            "flops_per_launch": flops, "us_per_launch": 1e3 * ev_dense}
     wl = {"workload": "2D 512x512 periodic advection-diffusion -div(a c) + nu lap c, single "
                       "divergence-free vortex (face velocities from a stream function), Courant 2, "
-                      "nu=1e-4, 16 Gaussian blobs; Krylov LEM on 16^2 cores, decay-bound buffers "
-                      "2-24 (1e-8/step), calibrated m, HIP graph per step, FP64",
-          "n": 512, "n_states": 16, "core": 16}
-    return _line(args, wl, valA, "DOF-steps/s", steps, t_lem * steps, "f64", out)
+                      "nu=1e-4, 64 Gaussian blobs; LEM with one stored FP64 block per 16^2 core "
+                      "(1024 blocks, buffers from the decay bound at 1e-8/step), FP64 MFMA apply",
+          "n": 512, "n_states": 64, "core": 16, "halo": dq["halo_max"]}
+    value = p.N * ns / t_dense
+    return _line(args, wl, value, "DOF-steps/s", steps, t_dense * steps, "f64", out, roofline=roof)
 
 
 def bench_c0(args) -> dict:
