@@ -34,7 +34,7 @@ MFMA_FP32_PEAK_TFLOPS = 157.3
 # (autotuner id), from rocprofv3 FETCH_SIZE / WRITE_SIZE passes scaled by a
 # 256 MiB reference copy; valid only for the dense.hip source they were taken
 # on: profiles/apply_fp64_2d256x256x64_h14.md
-TRAFFIC = {"dense.hip": ("c2607c071c0c", {0: 147884412, 1: 145228480, 2: 158008490, 3: 158090398})}
+TRAFFIC = {"dense.hip": ("a610543f9231", {0: 147981202, 1: 144917753, 2: 158014203, 3: 158095087})}
 
 
 def measured_traffic(tile):
