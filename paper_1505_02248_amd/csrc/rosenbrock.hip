@@ -199,11 +199,15 @@ __device__ __forceinline__ void phi_store(const d4e (&acc)[PhiTiles<MP, NT>::tq]
 
 // Banded product on the register segment: out[m] = (W X)(r0 + m, j) + cdiag
 // on the diagonal, X given by this thread's xs[] plus the exchanged rows.
+// cl/cd/cu[m] are the entries W(i, i-1), W(i, i), W(i, i+1) of row i = r0 + m
+// (i-1 and i+1 taken cyclically on the whole-grid box; zero where the box
+// drops the coupling).
 template <int RS, int MP>
 __device__ __forceinline__ void band_step(const double (&xs)[RS], double (&out)[RS],
-                                          const double* wl, const double* wd, const double* wu,
-                                          const int* im, const int* ip, double* xch, double* lastrow,
-                                          int r0, int seg, int j, int nl, double cdiag) {
+                                          const double (&cl)[RS], const double (&cd)[RS],
+                                          const double (&cu)[RS], double* xch, double* lastrow,
+                                          int r0, int seg, int j, int nl, bool whole,
+                                          double cdiag) {
   // publish this segment's first and last rows and, if held here, row nl - 1
   xch[seg * MP + j] = xs[0];
   xch[(8 + seg) * MP + j] = xs[RS - 1];
@@ -211,18 +215,17 @@ __device__ __forceinline__ void band_step(const double (&xs)[RS], double (&out)[
   for (int m = 0; m < RS; ++m)
     if (r0 + m == nl - 1) lastrow[j] = xs[m];
   __syncthreads();
+  const double prev = seg > 0 ? xch[(8 + seg - 1) * MP + j] : (whole ? lastrow[j] : 0.0);
+  const double next = seg < 7 ? xch[(seg + 1) * MP + j] : 0.0;
+  const double first = whole ? xch[j] : 0.0;  // row 0 (first row of segment 0)
 #pragma unroll
   for (int m = 0; m < RS; ++m) {
     const int i = r0 + m;
     double v = (i == j) ? cdiag : 0.0;
     if (i < nl) {
-      const int a = im[i], c = ip[i];
-      double up = 0.0, dn = 0.0;
-      if (a >= 0) up = (a == i - 1) ? (m > 0 ? xs[m > 0 ? m - 1 : 0] : xch[(8 + seg - 1) * MP + j])
-                                    : lastrow[j];
-      if (c >= 0) dn = (c == i + 1) ? (m < RS - 1 ? xs[m < RS - 1 ? m + 1 : 0] : xch[(seg + 1) * MP + j])
-                                    : xch[j];  // wrap to row 0: first row of segment 0
-      v += wl[i] * up + wd[i] * xs[m] + wu[i] * dn;
+      const double up = m > 0 ? xs[m > 0 ? m - 1 : 0] : prev;
+      const double dn = (i == nl - 1) ? first : (m < RS - 1 ? xs[m < RS - 1 ? m + 1 : 0] : next);
+      v += cl[m] * up + cd[m] * xs[m] + cu[m] * dn;
     }
     out[m] = v;
   }
@@ -246,8 +249,6 @@ __global__ __launch_bounds__(8 * MP) void ere_phi1_kernel(const double* __restri
   double* xch = wu + MP;            // [parity][top 0..7 | bottom 8..15][MP]
   double* lastrow = xch + 32 * MP;  // [parity][MP]
   double* red = lastrow + 2 * MP;   // NT/64 partial maxima
-  int* im = (int*)(red + NT / 64);
-  int* ip = im + MP;
   const int tid = threadIdx.x;
   const int j = tid % MP, seg = tid / MP, r0 = seg * RS;
   const int blk = blockIdx.x / ns, s = blockIdx.x - blk * ns;
@@ -265,18 +266,20 @@ __global__ __launch_bounds__(8 * MP) void ere_phi1_kernel(const double* __restri
       if (lm >= 0) vl = (x[(int64_t)ere_wrap(b.ox - b.h + lm, n) * ns + s] * a + d) * dt;
       if (lp >= 0) vu = (-x[(int64_t)ere_wrap(b.ox - b.h + lp, n) * ns + s] * a + d) * dt;
     }
-    wl[r] = vl; wd[r] = vd; wu[r] = vu; im[r] = lm; ip[r] = lp;
+    wl[r] = vl; wd[r] = vd; wu[r] = vu;
   }
   __syncthreads();
-  // |W|_1: column c collects wd[c] and the off-diagonals of the rows that point at c
+  // |W|_1: column c holds W(c, c), W(c-1, c) = wu[c-1], W(c+1, c) = wl[c+1] and,
+  // on the whole-grid box, the wrap-around entries W(nl-1, 0) = wu[nl-1] and
+  // W(0, nl-1) = wl[0] (zero elsewhere)
   double cs = 0.0;
   if (tid < MP) {
     const int c = tid;
     double t = fabs(wd[c]);
-    for (int r = 0; r < nl; ++r) {
-      if (im[r] == c) t += fabs(wl[r]);
-      if (ip[r] == c) t += fabs(wu[r]);
-    }
+    if (c >= 1 && c < nl) t += fabs(wu[c - 1]);
+    if (c + 1 < nl) t += fabs(wl[c + 1]);
+    if (c == 0) t += fabs(wu[nl - 1]);
+    if (c == nl - 1) t += fabs(wl[0]);
     cs = t;
   }
   for (int off = 32; off > 0; off >>= 1) cs = fmax(cs, __shfl_xor(cs, off, 64));
@@ -290,17 +293,24 @@ __global__ __launch_bounds__(8 * MP) void ere_phi1_kernel(const double* __restri
     sq_out[blockIdx.x] = sq;
     if (!(nrm < 1e300)) atomicOr(status, kStatusNonFinite);
   }
-  __syncthreads();  // every thread has read the bands' norm
   const double scale = ldexp(1.0, -sq);
-  if (tid < MP) { wl[tid] *= scale; wd[tid] *= scale; wu[tid] *= scale; }
+  // this thread's rows of W = dt J_M / 2^s, in registers for the whole recursion
+  double cl[RS], cd[RS], cu[RS];
+#pragma unroll
+  for (int m = 0; m < RS; ++m) {
+    cl[m] = wl[r0 + m] * scale;
+    cd[m] = wd[r0 + m] * scale;
+    cu[m] = wu[r0 + m] * scale;
+  }
+  const bool whole = b.whole != 0;
   // Horner: F = I/(q+1)!, then F <- W F + I/(k+1)! for k = q-1 .. 0
   double f[RS], g[RS];
 #pragma unroll
   for (int m = 0; m < RS; ++m) f[m] = (r0 + m == j) ? kInvFact.c[kPhiDeg] : 0.0;
   int par = 0;
   for (int k = kPhiDeg - 1; k >= 0; --k) {
-    band_step<RS, MP>(f, g, wl, wd, wu, im, ip, xch + par * 16 * MP, lastrow + par * MP, r0, seg,
-                      j, nl, kInvFact.c[k]);
+    band_step<RS, MP>(f, g, cl, cd, cu, xch + par * 16 * MP, lastrow + par * MP, r0, seg, j, nl,
+                      whole, kInvFact.c[k]);
 #pragma unroll
     for (int m = 0; m < RS; ++m) f[m] = g[m];
     par ^= 1;
@@ -309,8 +319,8 @@ __global__ __launch_bounds__(8 * MP) void ere_phi1_kernel(const double* __restri
   for (int m = 0; m < RS; ++m) F[(r0 + m) * ld + j] = f[m];
   if (sq > 0) {
     // E = I + W F
-    band_step<RS, MP>(f, g, wl, wd, wu, im, ip, xch + par * 16 * MP, lastrow + par * MP, r0, seg,
-                      j, nl, 1.0);
+    band_step<RS, MP>(f, g, cl, cd, cu, xch + par * 16 * MP, lastrow + par * MP, r0, seg, j, nl,
+                      whole, 1.0);
 #pragma unroll
     for (int m = 0; m < RS; ++m) E[(r0 + m) * ld + j] = g[m];
     __syncthreads();
@@ -363,8 +373,7 @@ static hipError_t launch_phi1(const double* x, const void* boxes, int nb, int ns
                               int rows, int n, double dt, double dx, double nu, double* P,
                               int* sq_out, int* status, hipStream_t st) {
   constexpr int NT = 8 * MP;
-  const size_t lds = ((size_t)2 * MP * (MP + 1) + 3 * MP + 34 * MP + NT / 64) * sizeof(double) +
-                     2 * MP * sizeof(int);
+  const size_t lds = ((size_t)2 * MP * (MP + 1) + 3 * MP + 34 * MP + NT / 64) * sizeof(double);
   static bool attr = false;
   if (!attr) {
     const hipError_t e = hipFuncSetAttribute((const void*)ere_phi1_kernel<MP>,
