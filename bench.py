@@ -32,17 +32,25 @@ MFMA_FP64_PEAK_TFLOPS = 78.6
 MFMA_FP32_PEAK_TFLOPS = 157.3
 # HBM bytes per launch of the FP64 apply at the bench workload, per tile shape
 # (autotuner id), from rocprofv3 FETCH_SIZE / WRITE_SIZE passes scaled by a
-# 256 MiB reference copy; valid only for the dense.hip source they were taken
-# on: profiles/apply_fp64_2d256x256x64_h14.md
-TRAFFIC = {"dense.hip": ("a610543f9231", {0: 147981202, 1: 144917753, 2: 158014203, 3: 158095087})}
+# 256 MiB reference copy (profiles/apply_fp64_2d256x256x64_h14.md); valid only
+# for the apply kernel source they were taken on: the text of dense.hip from
+# its apply section to the split-bf16 kernel, plus its tile-shape table.
+TRAFFIC = {"apply": ("43b501ee8d5a", {0: 147981202, 1: 144917753, 2: 158014203, 3: 158095087})}
+
+
+def _apply_source_key(text: str) -> str:
+    import hashlib
+    i0 = text.index("// ------------------------------------------------------------------ apply --")
+    i1 = text.index("// Split-bf16 apply")
+    shapes = [ln for ln in text.splitlines() if "static const int shapes[kApplyConfigs][3]" in ln]
+    return hashlib.sha1((text[i0:i1] + "\n".join(shapes)).encode()).hexdigest()[:12]
 
 
 def measured_traffic(tile):
-    import hashlib
     src = os.path.join(ROOT, "paper_1505_02248_amd", "csrc", "dense.hip")
-    sha, per_tile = TRAFFIC["dense.hip"]
-    with open(src, "rb") as f:
-        if hashlib.sha1(f.read()).hexdigest()[:12] != sha:
+    key, per_tile = TRAFFIC["apply"]
+    with open(src) as f:
+        if _apply_source_key(f.read()) != key:
             return None
     return per_tile.get(tile)
 
@@ -530,7 +538,8 @@ def bench_f4(args) -> dict:
         log("planning stored blocks per region (vortex, 1024 blocks)")
         t0 = time.perf_counter()
         dplan = lem.Plan(opr, p.dt, method="dense", core=16, halo=0, halo_min=2, halo_max=24,
-                         halo_tol=1e-8, n_states=ns, autotune=True, stream=stream)
+                         halo_tol=1e-8, n_states=ns, autotune=True, expm="taylor",
+                         stream=stream)
         stream.synchronize()
         dplan_s = time.perf_counter() - t0
         dq = dplan.query()
@@ -597,7 +606,8 @@ def bench_f4(args) -> dict:
     wl = {"workload": "2D 512x512 periodic advection-diffusion -div(a c) + nu lap c, single "
                       "divergence-free vortex (face velocities from a stream function), Courant 2, "
                       "nu=1e-4, 64 Gaussian blobs; LEM with one stored FP64 block per 16^2 core "
-                      "(1024 blocks, buffers from the decay bound at 1e-8/step), FP64 MFMA apply",
+                      "(1024 blocks, buffers from the decay bound at 1e-8/step, exponentials by "
+                      "the GEMM-only Taylor pipeline), FP64 MFMA apply",
           "n": 512, "n_states": 64, "core": 16, "halo": dq["halo_max"]}
     value = p.N * ns / t_dense
     return _line(args, wl, value, "DOF-steps/s", steps, t_dense * steps, "f64", out, roofline=roof)

@@ -54,6 +54,15 @@ typedef enum {
   LEM_ERR_NOT_FOUND = 7       /* unknown request id                           */
 } lem_status;
 
+/* Algorithm for the stored local exponentials (dense method, plan time). */
+enum {
+  LEM_EXPM_PADE = 0,   /* scaling and squaring with the Pade [13/13] approximant
+                          (sections 3 and 4), denominator solved by pivoted LU */
+  LEM_EXPM_TAYLOR = 1  /* scaling and squaring with the degree-18 Taylor
+                          polynomial in Paterson-Stockmeyer form: GEMMs only
+                          (faster plans for many distinct blocks)          */
+};
+
 /* Method used for the local exponential actions. */
 enum {
   LEM_METHOD_KRYLOV = 0,  /* Arnoldi-Krylov action per block (section 4.3)     */
@@ -129,6 +138,7 @@ typedef struct {
   int32_t autotune;      /* time candidate launch shapes at plan time       */
   int32_t dry_run;       /* 1: build partition and maps on the host only;
                             no device memory is touched (lem_step fails)     */
+  int32_t expm;          /* LEM_EXPM_PADE (default) or LEM_EXPM_TAYLOR      */
   int32_t columns;       /* 2D Krylov: column-wise decomposition (section
                             4.3): cores of core x n points spanning whole
                             columns, buffers of halo points across the
@@ -203,9 +213,10 @@ typedef struct {
  * buffers of `halo` points per side; core = n with halo = 0 is the global
  * method (D = 1, periodic coupling kept).  A refresh computes phi_1(dt J_M)
  * of every (block, member) in float64 on the device: for boxes of at most 80
- * points in one launch (Taylor polynomial of degree 16 on dt J_M / 2^s, then
- * s doublings, asynchronous); for larger boxes from the augmented matrices
- * [[dt J_M, I], [0, 0]] by Pade [13/13] (synchronizes the stream); a step is
+ * points in one launch (Taylor polynomial of degree 30 on dt J_M / 2^s, then
+ * s doublings, asynchronous); for larger boxes from the exponentials of the
+ * augmented matrices [[dt J_M, I], [0, 0]] by the GEMM-only Taylor pipeline
+ * of LEM_EXPM_TAYLOR (synchronizes the stream); a step is
  * F on the grid and one contraction per core row.  lem_step, lem_plan_query,
  * lem_plan_copy_maps and lem_plan_destroy apply; no graphs, no serving.
  * Errors: LEM_ERR_INVALID (bad sizes), LEM_ERR_NOMEM, LEM_ERR_HIP. */

@@ -53,7 +53,8 @@ class _Options(ctypes.Structure):
                 ("krylov_m", ctypes.c_int32), ("krylov_m_max", ctypes.c_int32),
                 ("max_substeps", ctypes.c_int32), ("krylov_tol", ctypes.c_double),
                 ("use_graph", ctypes.c_int32), ("autotune", ctypes.c_int32),
-                ("dry_run", ctypes.c_int32), ("columns", ctypes.c_int32)]
+                ("dry_run", ctypes.c_int32), ("expm", ctypes.c_int32),
+                ("columns", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -197,7 +198,7 @@ class Plan:
                  halo_tol: float = 1e-8, krylov_m: int = 0, krylov_m_max: int = 30,
                  max_substeps: int = 64, krylov_tol: float = 1e-13,
                  use_graph: bool = False, autotune: bool = False, dry_run: bool = False,
-                 columns: bool = False, stream=None):
+                 columns: bool = False, expm: str = "pade", stream=None):
         lib = load()
         o = _Options()
         lib.lem_options_default(ctypes.byref(o))
@@ -209,6 +210,7 @@ class Plan:
         o.krylov_tol = krylov_tol
         o.use_graph, o.autotune, o.dry_run = int(use_graph), int(autotune), int(dry_run)
         o.columns = int(columns)
+        o.expm = {"pade": 0, "taylor": 1}[expm]
         self.op, self.dt, self.n_states, self.method = op, float(dt), int(n_states), method
         if op.forcing is not None and op.forcing.size != op.N * int(n_states):
             raise ValueError("forcing must hold N x n_states values")

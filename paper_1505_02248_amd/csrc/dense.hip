@@ -1,17 +1,19 @@
 // Dense local exponentials and their application (gfx950).
 //
 // Sections 3 and 4 of the paper store the local matrices exp(dt A_{M_i}) (or
-// phi) of small subdomains, computed once by scaling and squaring (with a Pade
-// approximant there), and reuse them every step.  Here:
+// phi) of small subdomains, computed once by Pade approximation with scaling
+// and squaring, and reuse them every step.  Here:
 //
 //  plan time (float64 throughout):
 //   assemble_kernel     dense dt*A_M of every distinct local operator
 //   var_assemble_kernel the same from face arrays (variable coefficients)
 //   dgemm_kernel        batched C = A B on FP64 MFMA (v_mfma_f64_16x16x4):
-//                       the powers X^2, X^3, X^4 of the scaled matrix, the
-//                       Paterson-Stockmeyer steps of its Taylor polynomial
-//                       and the squarings (no factorization anywhere)
+//                       the powers and polynomial products of the Pade
+//                       [13/13] approximant (or of the Taylor alternative)
+//                       and the squarings
 //   lincomb_kernel      elementwise linear combinations of those powers
+//   lu_* kernels        Pade: Q X = P by LU with partial pivoting (right-hand
+//                       sides eliminated alongside), then back substitution
 //   pack_kernel         core rows of exp(dt A_M) into MFMA fragment order,
 //                       in float64, float32 and bf16 hi/mid/lo pieces
 //
@@ -118,6 +120,16 @@ __global__ void lincomb_kernel(LinComb p) {
   }
 }
 
+// P = V + U, Q = V - U (in place: V -> P, U -> Q)
+__global__ void pade_pq_kernel(double* V, double* U, int64_t total) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double v = V[e], u = U[e];
+    V[e] = v + u;
+    U[e] = v - u;
+  }
+}
+
 // ------------------------------------------------------------------ DGEMM --
 // C[u] = A[u] * B[u], row-major nl x nl, FP64 MFMA 16x16x4.  64x64 tile per
 // workgroup of 256 threads; each wave owns a 32x32 quarter (2x2 MFMA tiles).
@@ -184,6 +196,100 @@ __global__ __launch_bounds__(256) void dgemm_kernel(const double* A, const doubl
         const int gc = n0 + wc + j * 16 + (lane & 15);
         if (gr < nl && gc < nl) Cb[(int64_t)gr * nl + gc] = acc[i][j][r];
       }
+}
+
+// ------------------------------------------------------------- LU solve --
+// Solve Q X = P (batched, nl x nl, right-hand sides P overwritten by X).
+// Column step j: choose the pivot row, swap it into row j in Q and P, store
+// the multipliers l_ij = Q[i][j]/Q[j][j] in Q[i][j]; then eliminate below.
+__global__ __launch_bounds__(256) void lu_pivot_kernel(double* Q, double* P, int nl,
+                                                       int64_t stride, int j) {
+  const int u = blockIdx.x;
+  double* Qb = Q + (int64_t)u * stride;
+  double* Pb = P + (int64_t)u * stride;
+  __shared__ double bv[4];
+  __shared__ int bi[4];
+  __shared__ int sp;
+  const int tid = threadIdx.x;
+  double best = -1.0;
+  int bidx = j;
+  for (int i = j + tid; i < nl; i += 256) {
+    const double a = fabs(Qb[(int64_t)i * nl + j]);
+    if (a > best) { best = a; bidx = i; }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ob = __shfl_xor(best, off, 64);
+    const int oi = __shfl_xor(bidx, off, 64);
+    if (ob > best || (ob == best && oi < bidx)) { best = ob; bidx = oi; }
+  }
+  if ((tid & 63) == 0) { bv[tid >> 6] = best; bi[tid >> 6] = bidx; }
+  __syncthreads();
+  if (tid == 0) {
+    double b = bv[0];
+    int p = bi[0];
+    for (int w = 1; w < 4; ++w)
+      if (bv[w] > b || (bv[w] == b && bi[w] < p)) { b = bv[w]; p = bi[w]; }
+    sp = p;
+  }
+  __syncthreads();
+  const int p = sp;
+  if (p != j) {
+    for (int k = tid; k < 2 * nl; k += 256) {
+      double* M = k < nl ? Qb : Pb;
+      const int kk = k < nl ? k : k - nl;
+      const double t = M[(int64_t)j * nl + kk];
+      M[(int64_t)j * nl + kk] = M[(int64_t)p * nl + kk];
+      M[(int64_t)p * nl + kk] = t;
+    }
+    __syncthreads();
+  }
+  const double inv = 1.0 / Qb[(int64_t)j * nl + j];
+  for (int i = j + 1 + tid; i < nl; i += 256) Qb[(int64_t)i * nl + j] *= inv;
+}
+
+// rows i > j: Q[i][k] -= l_ij Q[j][k] (k > j), P[i][k] -= l_ij P[j][k] (all k)
+__global__ void lu_elim_kernel(double* Q, double* P, int nl, int64_t stride, int j) {
+  const int u = blockIdx.z;
+  double* Qb = Q + (int64_t)u * stride;
+  double* Pb = P + (int64_t)u * stride;
+  const int i = j + 1 + blockIdx.y;
+  if (i >= nl) return;
+  const double l = Qb[(int64_t)i * nl + j];
+  const int qcols = nl - j - 1;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < qcols + nl;
+       c += gridDim.x * blockDim.x) {
+    if (c < qcols) {
+      const int k = j + 1 + c;
+      Qb[(int64_t)i * nl + k] = fma(-l, Qb[(int64_t)j * nl + k], Qb[(int64_t)i * nl + k]);
+    } else {
+      const int k = c - qcols;
+      Pb[(int64_t)i * nl + k] = fma(-l, Pb[(int64_t)j * nl + k], Pb[(int64_t)i * nl + k]);
+    }
+  }
+}
+
+// back substitution step j: rows i < j: P[i][k] -= Q[i][j] * (P[j][k] / Q[j][j])
+// (row j itself is divided by its pivot at the very end).
+__global__ void lu_back_kernel(const double* Q, double* P, int nl, int64_t stride, int j) {
+  const int u = blockIdx.z;
+  const double* Qb = Q + (int64_t)u * stride;
+  double* Pb = P + (int64_t)u * stride;
+  const int i = blockIdx.y;
+  if (i >= j) return;
+  const double f = Qb[(int64_t)i * nl + j] / Qb[(int64_t)j * nl + j];
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nl; k += gridDim.x * blockDim.x)
+    Pb[(int64_t)i * nl + k] = fma(-f, Pb[(int64_t)j * nl + k], Pb[(int64_t)i * nl + k]);
+}
+
+__global__ void lu_diag_kernel(const double* Q, double* P, int nl, int64_t stride) {
+  const int u = blockIdx.z;
+  const double* Qb = Q + (int64_t)u * stride;
+  double* Pb = P + (int64_t)u * stride;
+  const int i = blockIdx.y;
+  const double inv = 1.0 / Qb[(int64_t)i * nl + i];
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nl; k += gridDim.x * blockDim.x)
+    Pb[(int64_t)i * nl + k] *= inv;
 }
 
 // ------------------------------------------------------------------- pack --
@@ -749,6 +855,30 @@ hipError_t dense_lincomb(const double* X0, double c0, const double* X1, double c
   dim3 g = grid1((int64_t)nl * nl);
   g.y = nu;
   hipLaunchKernelGGL(lincomb_kernel, g, dim3(256), 0, st, p);
+  return hipGetLastError();
+}
+
+hipError_t dense_pade_pq(double* V, double* U, int64_t total, hipStream_t st) {
+  hipLaunchKernelGGL(pade_pq_kernel, grid1(total), dim3(256), 0, st, V, U, total);
+  return hipGetLastError();
+}
+
+hipError_t dense_solve(double* Q, double* P, int nl, int nu, hipStream_t st) {
+  const int64_t stride = (int64_t)nl * nl;
+  for (int j = 0; j < nl; ++j) {
+    hipLaunchKernelGGL(lu_pivot_kernel, dim3(nu), dim3(256), 0, st, Q, P, nl, stride, j);
+    const int rows = nl - j - 1;
+    if (rows > 0) {
+      const int cols = (nl - j - 1) + nl;
+      hipLaunchKernelGGL(lu_elim_kernel, dim3((cols + 255) / 256, rows, nu), dim3(256), 0, st,
+                         Q, P, nl, stride, j);
+    }
+  }
+  for (int j = nl - 1; j > 0; --j)
+    hipLaunchKernelGGL(lu_back_kernel, dim3((nl + 255) / 256, j, nu), dim3(256), 0, st, Q, P,
+                       nl, stride, j);
+  hipLaunchKernelGGL(lu_diag_kernel, dim3((nl + 255) / 256, nl, nu), dim3(256), 0, st, Q, P,
+                     nl, stride);
   return hipGetLastError();
 }
 

@@ -41,6 +41,13 @@ lem_status fail(lem_status s, const std::string& msg) {
     if (s_ != LEM_OK) return s_;     \
   } while (0)
 
+// Pade [13/13] numerator coefficients (Higham 2005, scaled b_13 = 1).
+constexpr double kB[14] = {64764752532480000.0, 32382376266240000.0, 7771770303897600.0,
+                           1187353796428800.0,  129060195264000.0,   10559470521600.0,
+                           670442572800.0,      33522128640.0,       1323241920.0,
+                           40840800.0,          960960.0,            16380.0,
+                           182.0,               1.0};
+
 // ----------------------------------------------------------- operator ------
 // dt*A of the periodic advection-diffusion operator, centered differences.
 struct Op {
@@ -747,6 +754,71 @@ lem_status plan_krylov(lem_plan_s* p, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------- dense ----
+// exp of the U assembled nl x nl matrices in A (overwritten) into R, by
+// Pade [13/13] with scaling and squaring in float64 (Higham 2005): the powers,
+// both polynomials and the squarings on FP64 MFMA, Q R = P by pivoted LU.
+lem_status dense_expm_pade(lem_plan_s* p, double* A, double* R, int nl, int U, hipStream_t st,
+                           int* smax, const std::vector<double*>* work, int* work_s) {
+  const size_t mat = (size_t)nl * nl * U;
+  double *A2, *A4, *A6, *T, *Ub, *d_norm;
+  int* d_s;
+  if (work) {  // caller-owned work space (kept between calls)
+    A2 = (*work)[0]; A4 = (*work)[1]; A6 = (*work)[2]; T = (*work)[3]; Ub = (*work)[4];
+    d_norm = (*work)[5];
+    d_s = work_s;
+  } else {
+    LEM_TRY(dalloc(p, &A2, mat));
+    LEM_TRY(dalloc(p, &A4, mat));
+    LEM_TRY(dalloc(p, &A6, mat));
+    LEM_TRY(dalloc(p, &T, mat));
+    LEM_TRY(dalloc(p, &Ub, mat));
+    LEM_TRY(dalloc(p, &d_norm, U));
+    LEM_TRY(dalloc(p, &d_s, U));
+  }
+  LEM_HIP(lem::dense_norm1(A, nl, U, d_norm, st));
+  std::vector<double> nrm(U);
+  LEM_HIP(hipMemcpyAsync(nrm.data(), d_norm, U * 8, hipMemcpyDeviceToHost, st));
+  LEM_HIP(hipStreamSynchronize(st));
+  std::vector<int> s(U);
+  for (int u = 0; u < U; ++u) {
+    if (!std::isfinite(nrm[u])) return fail(LEM_ERR_INVALID, "non-finite local operator");
+    s[u] = nrm[u] > lem::kTheta13 ? std::min(60, (int)std::ceil(std::log2(nrm[u] / lem::kTheta13))) : 0;
+    *smax = std::max(*smax, s[u]);
+  }
+  LEM_TRY(upload(d_s, s.data(), U * sizeof(int), st));
+  LEM_HIP(lem::dense_scale_pow2(A, nl, U, d_s, st));
+  LEM_HIP(lem::dense_gemm(A, A, A2, nl, U, st));
+  LEM_HIP(lem::dense_gemm(A2, A2, A4, nl, U, st));
+  LEM_HIP(lem::dense_gemm(A4, A2, A6, nl, U, st));
+  // U = A (A6 (b13 A6 + b11 A4 + b9 A2) + b7 A6 + b5 A4 + b3 A2 + b1 I)
+  LEM_HIP(lem::dense_lincomb(A6, kB[13], A4, kB[11], A2, kB[9], nullptr, 0, 0, T, nl, U, st));
+  LEM_HIP(lem::dense_gemm(A6, T, Ub, nl, U, st));
+  LEM_HIP(lem::dense_lincomb(Ub, 1.0, A6, kB[7], A4, kB[5], A2, kB[3], kB[1], Ub, nl, U, st));
+  LEM_HIP(lem::dense_gemm(A, Ub, T, nl, U, st));  // T = U
+  // V = A6 (b12 A6 + b10 A4 + b8 A2) + b6 A6 + b4 A4 + b2 A2 + b0 I
+  LEM_HIP(lem::dense_lincomb(A6, kB[12], A4, kB[10], A2, kB[8], nullptr, 0, 0, Ub, nl, U, st));
+  LEM_HIP(lem::dense_gemm(A6, Ub, R, nl, U, st));
+  LEM_HIP(lem::dense_lincomb(R, 1.0, A6, kB[6], A4, kB[4], A2, kB[2], kB[0], R, nl, U, st));
+  LEM_HIP(lem::dense_pade_pq(R, T, (int64_t)mat, st));  // R = P, T = Q
+  LEM_HIP(lem::dense_solve(T, R, nl, U, st));           // R = Q^-1 P
+  for (int u = 0; u < U; ++u) {
+    double* src = R + (size_t)u * nl * nl;
+    double* dst = A2 + (size_t)u * nl * nl;
+    for (int q = 0; q < s[u]; ++q) {
+      LEM_HIP(lem::dense_gemm(src, src, dst, nl, 1, st));
+      std::swap(src, dst);
+    }
+    if (src != R + (size_t)u * nl * nl)
+      LEM_HIP(hipMemcpyAsync(R + (size_t)u * nl * nl, src, (size_t)nl * nl * 8,
+                             hipMemcpyDeviceToDevice, st));
+  }
+  LEM_HIP(hipStreamSynchronize(st));
+  if (!work)
+    for (void* q : {(void*)A2, (void*)A4, (void*)A6, (void*)T, (void*)Ub, (void*)d_norm, (void*)d_s})
+      dfree(p, q);
+  return LEM_OK;
+}
+
 // exp of the U assembled nl x nl matrices in A (overwritten) into R by
 // scaling and squaring with a Taylor polynomial: with X = A / 2^s scaled to
 // ||X||_1 <= 1, T_18(X) = sum_{k<=18} X^k / k! (truncation below 1/19! ~ 9e-18
@@ -754,8 +826,8 @@ lem_status plan_krylov(lem_plan_s* p, hipStream_t st) {
 // coefficients are c_{4j} I + c_{4j+1} X + c_{4j+2} X^2 + c_{4j+3} X^3 (seven
 // products), then s squarings.  Every product is a batched FP64 MFMA GEMM:
 // no factorization, so no latency-bound pivoting on the device.
-lem_status dense_expm(lem_plan_s* p, double* A, double* R, int nl, int U, hipStream_t st,
-                      int* smax, const std::vector<double*>* work = nullptr, int* work_s = nullptr) {
+lem_status dense_expm_taylor(lem_plan_s* p, double* A, double* R, int nl, int U, hipStream_t st,
+                             int* smax, const std::vector<double*>* work, int* work_s) {
   const size_t mat = (size_t)nl * nl * U;
   double *A2, *A3, *A4, *T, *d_norm;
   int* d_s;
@@ -813,6 +885,14 @@ lem_status dense_expm(lem_plan_s* p, double* A, double* R, int nl, int U, hipStr
     for (void* q : {(void*)A2, (void*)A3, (void*)A4, (void*)T, (void*)d_norm, (void*)d_s})
       dfree(p, q);
   return LEM_OK;
+}
+
+// exp of the U assembled nl x nl matrices in A (overwritten) into R, by the
+// algorithm the plan asks for (Pade [13/13] by default).
+lem_status dense_expm(lem_plan_s* p, double* A, double* R, int nl, int U, hipStream_t st,
+                      int* smax, const std::vector<double*>* work = nullptr, int* work_s = nullptr) {
+  return p->opt.expm == LEM_EXPM_TAYLOR ? dense_expm_taylor(p, A, R, nl, U, st, smax, work, work_s)
+                                        : dense_expm_pade(p, A, R, nl, U, st, smax, work, work_s);
 }
 
 // ----------------------------------------------------- exponential Rosenbrock
@@ -1249,6 +1329,8 @@ lem_status check_options(const lem_options* o) {
     return fail(LEM_ERR_INVALID, "Krylov dimension must be in [2, " + std::to_string(mlim) + "]");
   if (o->max_substeps < 1) return fail(LEM_ERR_INVALID, "max_substeps must be >= 1");
   if (!(o->krylov_tol > 0)) return fail(LEM_ERR_INVALID, "krylov_tol must be > 0");
+  if (o->expm != LEM_EXPM_PADE && o->expm != LEM_EXPM_TAYLOR)
+    return fail(LEM_ERR_INVALID, "unknown local exponential algorithm");
   if (o->columns && (o->method != LEM_METHOD_KRYLOV || o->core <= 0))
     return fail(LEM_ERR_UNSUPPORTED, "column-wise cores need the Krylov method and a core width");
   return LEM_OK;
@@ -1431,6 +1513,7 @@ lem_status lem_ere_plan(const lem_burgers* op, double dt, int32_t n_states, int3
   auto guard = [&](lem_status s) { if (s != LEM_OK) delete p; return s; };
   lem_options_default(&p->opt);
   p->opt.method = LEM_METHOD_ROSENBROCK;
+  p->opt.expm = LEM_EXPM_TAYLOR;  // a refresh of large boxes recurs: GEMM-only pipeline
   p->opt.n_states = n_states;
   p->opt.core = core;
   p->opt.halo = halo;

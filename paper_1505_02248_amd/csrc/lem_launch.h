@@ -43,6 +43,8 @@ hipError_t dense_gemm(const double* A, const double* B, double* C, int nl, int n
 hipError_t dense_lincomb(const double* X0, double c0, const double* X1, double c1,
                          const double* X2, double c2, const double* X3, double c3, double d,
                          double* out, int nl, int nu, hipStream_t st);
+hipError_t dense_pade_pq(double* V, double* U, int64_t total, hipStream_t st);
+hipError_t dense_solve(double* Q, double* P, int nl, int nu, hipStream_t st);
 hipError_t dense_pack(const double* R, int nl, int Lx, int h, int cx, int cy, int ndim,
                       int rows, int rows_p, int cols_p, double* e64, float* e32, void* e16,
                       double* core_out, hipStream_t st);

@@ -60,8 +60,10 @@ def test_gpu_visible():
 
 # ----------------------------------------------------------------- dense --
 
+# stored blocks by Pade [13/13] (default) and by the GEMM-only Taylor pipeline
+@pytest.mark.parametrize("expm", ["pade", "taylor"])
 @pytest.mark.parametrize("case", ["1d", "2d576", "2d2304"])
-def test_pade_block_matches_oracle_expm(case):
+def test_pade_block_matches_oracle_expm(case, expm):
     if case == "1d":
         p, c, h = L.workload_1d(), 64, 16
     elif case == "2d576":
@@ -69,7 +71,7 @@ def test_pade_block_matches_oracle_expm(case):
     else:
         p, c, h = L.workload_2d_mixed(n=128, n_smooth=64), 32, 8
     plan = lem.Plan(lem.Operator.from_problem(p), p.dt, method="dense", core=c, halo=h,
-                    n_states=p.states.shape[1])
+                    n_states=p.states.shape[1], expm=expm)
     got = plan.block(0)
     W = op.from_problem(p)
     box = P.uniform_boxes(p.ndim, p.n, c, h)[0]
@@ -464,11 +466,11 @@ def test_krylov_column_partition(n, core, ns):
 
 # stored blocks for variable coefficients: one block per region (vortex faces,
 # lognormal nu), FP64 and FP32 application, MFMA and plain paths
-@pytest.mark.parametrize("work,ns,precision,tol", [("vortex", 64, "fp64", 1e-12),
-                                                   ("vortex", 3, "fp64", 1e-12),
-                                                   ("lognormal", 64, "fp32", 1e-5),
-                                                   ("columns", 64, "fp64", 1e-12)])
-def test_dense_variable_coefficients(work, ns, precision, tol):
+@pytest.mark.parametrize("work,ns,precision,tol,expm", [("vortex", 64, "fp64", 1e-12, "taylor"),
+                                                        ("vortex", 3, "fp64", 1e-12, "pade"),
+                                                        ("lognormal", 64, "fp32", 1e-5, "pade"),
+                                                        ("columns", 64, "fp64", 1e-12, "taylor")])
+def test_dense_variable_coefficients(work, ns, precision, tol, expm):
     if work == "vortex":
         p = L.workload_2d_vortex(n=64, n_states=ns, courant=2.0)
         core, halo = 16, 6
@@ -480,7 +482,7 @@ def test_dense_variable_coefficients(work, ns, precision, tol):
         p = L.workload_2d_columns(n=64, n_states=ns)
         core, halo = 16, 8
     plan = lem.Plan(lem.Operator.from_problem(p), p.dt, method="dense", precision=precision,
-                    core=core, halo=halo, n_states=ns, autotune=(ns % 64 == 0))
+                    core=core, halo=halo, n_states=ns, autotune=(ns % 64 == 0), expm=expm)
     q = plan.query()
     assert q["n_unique"] == q["n_blocks"] == (64 // core) ** 2
     boxes = check_maps(plan, 2, p.n)
