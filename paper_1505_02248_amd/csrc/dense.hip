@@ -924,7 +924,8 @@ hipError_t dense_apply(int precision, int cfg, const void* blocks, const void* E
   a.col_tiles = ns / 64;
   if (precision == 0 || precision == 1) {
     // tile shapes (rows per wave, K chunk, waves per workgroup)
-    static const int shapes[kApplyConfigs][3] = {{32, 16, 4}, {32, 32, 4}, {32, 32, 8}, {64, 32, 4}};
+    static const int shapes[kApplyConfigs][3] = {{32, 16, 4}, {32, 32, 4}, {32, 32, 8}, {64, 32, 4},
+                                                 {16, 32, 8}, {16, 32, 4}, {16, 16, 8}, {16, 32, 16}};
     if (cfg < 0 || cfg >= kApplyConfigs) return hipErrorInvalidValue;
     const int wm = shapes[cfg][0], nw = shapes[cfg][2];
     a.row_tiles = (rows_p + nw * wm - 1) / (nw * wm);
@@ -934,7 +935,11 @@ hipError_t dense_apply(int precision, int cfg, const void* blocks, const void* E
       case 0: hipLaunchKernelGGL((apply_mfma_kernel<T, 32, 16, 4>), g, blk, 0, st, a); break; \
       case 1: hipLaunchKernelGGL((apply_mfma_kernel<T, 32, 32, 4>), g, blk, 0, st, a); break; \
       case 2: hipLaunchKernelGGL((apply_mfma_kernel<T, 32, 32, 8>), g, blk, 0, st, a); break; \
-      default: hipLaunchKernelGGL((apply_mfma_kernel<T, 64, 32, 4>), g, blk, 0, st, a); break; \
+      case 3: hipLaunchKernelGGL((apply_mfma_kernel<T, 64, 32, 4>), g, blk, 0, st, a); break; \
+      case 4: hipLaunchKernelGGL((apply_mfma_kernel<T, 16, 32, 8>), g, blk, 0, st, a); break; \
+      case 5: hipLaunchKernelGGL((apply_mfma_kernel<T, 16, 32, 4>), g, blk, 0, st, a); break; \
+      case 6: hipLaunchKernelGGL((apply_mfma_kernel<T, 16, 16, 8>), g, blk, 0, st, a); break; \
+      default: hipLaunchKernelGGL((apply_mfma_kernel<T, 16, 32, 16>), g, blk, 0, st, a); break; \
     }
     if (precision == 0) { LEM_APPLY(double) } else { LEM_APPLY(float) }
 #undef LEM_APPLY

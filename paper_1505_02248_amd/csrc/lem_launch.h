@@ -53,7 +53,7 @@ void dense_block_fill(void* dst, int i, int ox, int oy, int cx, int cy, int h, i
                       int unique);
 // Tile shapes of the FP64/FP32 apply (the autotuner times each at plan time);
 // the split-bf16 apply uses cfg & 1 (32 or 64 rows per wave).
-constexpr int kApplyConfigs = 4;
+constexpr int kApplyConfigs = 8;
 hipError_t dense_apply(int precision, int cfg, const void* blocks, const void* E,
                        int64_t e_stride, const double* core, const double* x_in, double* x_out,
                        int n, int ndim, int ns, int rows, int rows_p, int cols, int cols_p,
