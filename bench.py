@@ -35,7 +35,7 @@ MFMA_FP32_PEAK_TFLOPS = 157.3
 # 256 MiB reference copy (profiles/apply_fp64_2d256x256x64_h14.md); valid only
 # for the apply kernel source they were taken on: the text of dense.hip from
 # its apply section to the split-bf16 kernel, plus its tile-shape table.
-TRAFFIC = {"apply": ("43b501ee8d5a", {0: 147981202, 1: 144917753, 2: 158014203, 3: 158095087})}
+TRAFFIC = {"apply": ("03c8d9c2f713", {0: 148060518, 1: 145418921, 2: 158006442, 3: 158094493, 4: 142171189, 5: 141683825, 6: 145681033, 7: 158004399})}
 
 
 def _apply_source_key(text: str) -> str:
