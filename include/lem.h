@@ -175,17 +175,22 @@ typedef struct lem_plan_s* lem_plan_t;
 void lem_options_default(lem_options* opt);
 
 /* Build a plan for steps of size dt of the operator *op (section 3).
- * Partitions the grid into cores with buffers (uniform core side, or uneven
+ * Partitions the grid into cores with buffers (uniform core side, uneven
  * cores with per-block buffer widths from the off-diagonal decay bound of
- * section 2), builds index maps, and for the dense method computes every
- * distinct local exponential exp(dt A_{M_i}) once by Pade [13/13] scaling and
- * squaring in float64 on the device (the paper computes these once, at the
- * first step).  For the Krylov methods, calibrates the Krylov dimension per
- * block on a pseudo-random probe.  Blocks until the plan is ready.
+ * section 2, or column-wise cores), builds index maps, and for the dense
+ * method computes every distinct local exponential exp(dt A_{M_i}) once in
+ * float64 on the device (opt->expm: Pade [13/13] scaling and squaring by
+ * default; the paper computes these once, at the first step).  A constant-
+ * coefficient operator has one block shared by all regions; a variable one
+ * (nu_field or vel_faces) one block per region, every box then taking the
+ * partition's largest buffer width (uniform core, FP64 or FP32, no forcing).
+ * For the Krylov methods, calibrates the Krylov dimension per block on a
+ * pseudo-random probe.  Blocks until the plan is ready.
  * Errors: LEM_ERR_INVALID for a bad operator/options (c must divide n, a box
- * c + 2h must be < n unless it is the whole grid), LEM_ERR_NOMEM, LEM_ERR_HIP,
- * LEM_ERR_NOT_CONVERGED when no (m, sub-step) pair within the limits meets
- * krylov_tol. */
+ * c + 2h must be < n unless it spans the whole axis), LEM_ERR_UNSUPPORTED for
+ * combinations not built (column-wise dense, bf16 with variable coefficients,
+ * ...), LEM_ERR_NOMEM, LEM_ERR_HIP, LEM_ERR_NOT_CONVERGED when no (m,
+ * sub-step) pair within the limits meets krylov_tol. */
 lem_status lem_plan(const lem_operator* op, double dt, const lem_options* opt,
                     void* stream, lem_plan_t* out);
 
