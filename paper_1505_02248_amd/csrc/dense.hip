@@ -365,6 +365,9 @@ struct ApplyArgs {
   int rows, rows_p, cols, cols_p;
   int n_blocks, row_tiles, col_tiles;
   const double* bias;   // added to every output (forced steps), or null
+  const __bf16* xp;     // split-bf16 apply: the state split into pieces once per
+                        // step (piece p of entry e at xp[p * xp_stride + e]), or null
+  int64_t xp_stride;
 };
 
 __device__ __forceinline__ int64_t dense_gather(const DBlock& b, int l, int n, int ndim) {
@@ -550,7 +553,25 @@ __global__ __launch_bounds__(64 * NW) void apply_mfma_kernel(ApplyArgs a) {
 __device__ __forceinline__ __bf16 bf16_near(double v) { return (__bf16)(float)v; }
 __device__ __forceinline__ double bf16_val(__bf16 h) { return (double)(float)h; }
 
-template <int NTERMS, int WM>
+// The state split into bf16 pieces once per step (the apply kernels of every
+// row tile of a block then only gather and pack them): x = hi + mid + lo with
+// hi = bf16(x), mid = bf16(x - hi), lo = bf16(x - hi - mid), the same split
+// the apply performs when no pieces are given.
+__global__ void split_pieces_kernel(const double* __restrict__ x, int64_t total, int np,
+                                    __bf16* __restrict__ P) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double v = x[e];
+    const __bf16 hi = (__bf16)(float)v;
+    const double r1 = v - (double)(float)hi;
+    const __bf16 mid = (__bf16)(float)r1;
+    P[e] = hi;
+    P[total + e] = mid;
+    if (np == 3) P[2 * total + e] = (__bf16)(float)(r1 - (double)(float)mid);
+  }
+}
+
+template <int NTERMS, int WM, bool PRE>
 __global__ __launch_bounds__(256) void apply_bf16_kernel(ApplyArgs a) {
   constexpr int BN = 64, KC = 32, RT = WM / 16, CT = BN / 16;
   constexpr int NP = NTERMS == 6 ? 3 : 2;  // operand pieces in use
@@ -593,23 +614,38 @@ __global__ __launch_bounds__(256) void apply_bf16_kernel(ApplyArgs a) {
         ea[p][i] = Ew[p * estride8 + ((int64_t)i * ksteps + ch) * 64];
   };
   const int xc = tid & 63, xg = tid >> 6;
-  auto load_x = [&](int ch, double (&v)[8]) {
+  // staged X of one chunk: eight local rows of column xc, as float64 values
+  // (split here) or as pieces (split once per step by split_pieces_kernel)
+  typedef typename std::conditional<PRE, bf16x8[NP], double[8]>::type xreg_t;
+  auto load_x = [&](int ch, xreg_t& v) {
+    if constexpr (PRE) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = a.x_in[goff[ch * KC + xg * 8 + e] + xc];
-  };
-  auto store_x = [&](const double (&v)[8], int buf) {
-    bf16x8 pc[NP];
+      for (int p = 0; p < NP; ++p)
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const __bf16 hi = bf16_near(v[e]);
-      const double r1 = v[e] - bf16_val(hi);
-      const __bf16 mid = bf16_near(r1);
-      pc[0][e] = hi;
-      pc[1][e] = mid;
-      if constexpr (NP == 3) pc[2][e] = bf16_near(r1 - bf16_val(mid));
+        for (int e = 0; e < 8; ++e) v[p][e] = a.xp[p * a.xp_stride + goff[ch * KC + xg * 8 + e] + xc];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = a.x_in[goff[ch * KC + xg * 8 + e] + xc];
     }
+  };
+  auto store_x = [&](const xreg_t& v, int buf) {
+    if constexpr (PRE) {
 #pragma unroll
-    for (int p = 0; p < NP; ++p) Xs[buf][p][xc][xg] = pc[p];
+      for (int p = 0; p < NP; ++p) Xs[buf][p][xc][xg] = v[p];
+    } else {
+      bf16x8 pc[NP];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const __bf16 hi = bf16_near(v[e]);
+        const double r1 = v[e] - bf16_val(hi);
+        const __bf16 mid = bf16_near(r1);
+        pc[0][e] = hi;
+        pc[1][e] = mid;
+        if constexpr (NP == 3) pc[2][e] = bf16_near(r1 - bf16_val(mid));
+      }
+#pragma unroll
+      for (int p = 0; p < NP; ++p) Xs[buf][p][xc][xg] = pc[p];
+    }
   };
   auto mfma_chunk = [&](const bf16x8 (&ea)[NP][RT], int buf) {
     bf16x8 bx[NP][CT];
@@ -636,7 +672,7 @@ __global__ __launch_bounds__(256) void apply_bf16_kernel(ApplyArgs a) {
   };
   const int last = ksteps - 1;
   bf16x8 ea0[NP][RT], ea1[NP][RT];
-  double xv[8];
+  xreg_t xv;
   load_a(0, ea0);
   load_x(0, xv);
   store_x(xv, 0);
@@ -903,9 +939,12 @@ void dense_block_fill(void* dst, int i, int ox, int oy, int cx, int cy, int h, i
 hipError_t dense_apply(int precision, int cfg, const void* blocks, const void* E,
                        int64_t e_stride, const double* core, const double* x_in,
                        double* x_out, int n, int ndim, int ns, int rows, int rows_p,
-                       int cols, int cols_p, int n_blocks, const double* bias, hipStream_t st) {
+                       int cols, int cols_p, int n_blocks, const double* bias, hipStream_t st,
+                       const void* xpieces, int64_t n_points) {
   ApplyArgs a;
   a.bias = bias;
+  a.xp = nullptr;
+  a.xp_stride = 0;
   a.blocks = (const DBlock*)blocks; a.E = E; a.e_stride = e_stride;
   a.x_in = x_in; a.x_out = x_out; a.n = n; a.ndim = ndim; a.ns = ns;
   a.rows = rows; a.rows_p = rows_p; a.cols = cols; a.cols_p = cols_p;
@@ -950,15 +989,29 @@ hipError_t dense_apply(int precision, int cfg, const void* blocks, const void* E
   const dim3 g(n_blocks * a.row_tiles * a.col_tiles);
   const size_t gl = (size_t)cols_p * sizeof(int64_t);  // gathered row offsets
   if (gl > 64 * 1024) return hipErrorInvalidValue;
+  if (xpieces) {  // the state was split into pieces by dense_split_pieces
+    a.xp = (const __bf16*)xpieces;
+    a.xp_stride = (int64_t)n_points * ns;
+  }
+#define LEM_BF16(NT_, WM_)                                                                     \
+  if (a.xp) hipLaunchKernelGGL((apply_bf16_kernel<NT_, WM_, true>), g, dim3(256), gl, st, a); \
+  else hipLaunchKernelGGL((apply_bf16_kernel<NT_, WM_, false>), g, dim3(256), gl, st, a);
   if (precision == 2) {
-    if (wm == 32) hipLaunchKernelGGL((apply_bf16_kernel<3, 32>), g, dim3(256), gl, st, a);
-    else hipLaunchKernelGGL((apply_bf16_kernel<3, 64>), g, dim3(256), gl, st, a);
+    if (wm == 32) { LEM_BF16(3, 32) } else { LEM_BF16(3, 64) }
   } else if (precision == 3) {
-    if (wm == 32) hipLaunchKernelGGL((apply_bf16_kernel<6, 32>), g, dim3(256), gl, st, a);
-    else hipLaunchKernelGGL((apply_bf16_kernel<6, 64>), g, dim3(256), gl, st, a);
+    if (wm == 32) { LEM_BF16(6, 32) } else { LEM_BF16(6, 64) }
   } else {
     return hipErrorInvalidValue;
   }
+#undef LEM_BF16
+  return hipGetLastError();
+}
+
+hipError_t dense_split_pieces(const double* x, int64_t total, int np, void* pieces,
+                              hipStream_t st) {
+  if (np != 2 && np != 3) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(split_pieces_kernel, grid1(total), dim3(256), 0, st, x, total, np,
+                     (__bf16*)pieces);
   return hipGetLastError();
 }
 

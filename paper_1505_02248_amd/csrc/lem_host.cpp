@@ -333,6 +333,7 @@ struct lem_plan_s {
   double* d_e64 = nullptr;
   float* d_e32 = nullptr;
   void* d_e16 = nullptr;
+  void* d_xp = nullptr;  // split-bf16: the input state in bf16 pieces, once per step
   double* d_core = nullptr;
   // forcing (du/dt = A u + g, g constant in time): device copy of g and, for
   // the dense method, the per-step term phi_1(dt A_M)(dt g_M) assembled over
@@ -1128,6 +1129,12 @@ lem_status plan_dense(lem_plan_s* p, hipStream_t st, const double* host_g) {
   dfree(p, d_ops);
   // default tile shape of the apply kernel (the autotuner may replace it)
   p->tile = p->opt.precision == LEM_FP32 ? 2 : p->opt.precision == LEM_FP64 ? 0 : (p->rows_p >= 256 ? 1 : 0);
+  if (p->opt.precision >= LEM_BF16X2) {  // pieces of the state, split once per step
+    const int np = p->opt.precision == LEM_BF16X3 ? 3 : 2;
+    unsigned short* xp;
+    LEM_TRY(dalloc(p, &xp, (size_t)np * p->N * p->ns, &p->bytes_work));
+    p->d_xp = xp;
+  }
   return LEM_OK;
 }
 
@@ -1248,9 +1255,12 @@ lem_status run_one(lem_plan_s* p, const double* src, double* dst, hipStream_t st
                             nullptr, 0, st);
     case LEM_METHOD_DENSE: {
       const int64_t es = (int64_t)p->rows_p * p->cols_p;
+      if (p->d_xp)
+        LEM_HIP(lem::dense_split_pieces(src, p->N * p->ns, p->opt.precision == LEM_BF16X3 ? 3 : 2,
+                                        p->d_xp, st));
       LEM_HIP(lem::dense_apply(p->opt.precision, p->tile, p->d_db, dense_operand(p), es, p->d_core,
                                src, dst, p->op.n, p->op.ndim, p->ns, p->rows, p->rows_p, p->cols,
-                               p->cols_p, (int)p->boxes.size(), p->d_bias, st));
+                               p->cols_p, (int)p->boxes.size(), p->d_bias, st, p->d_xp, p->N));
       return LEM_OK;
     }
     default:
