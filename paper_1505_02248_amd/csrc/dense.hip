@@ -366,8 +366,8 @@ struct ApplyArgs {
   int n_blocks, row_tiles, col_tiles;
   const double* bias;   // added to every output (forced steps), or null
   const __bf16* xp;     // split-bf16 apply: the state split into pieces once per
-                        // step (piece p of entry e at xp[p * xp_stride + e]), or null
-  int64_t xp_stride;
+                        // step, interleaved per entry (2 pieces: hi, mid; 3 pieces:
+                        // hi, mid, lo, 0 -- 4 or 8 bytes per entry), or null
 };
 
 __device__ __forceinline__ int64_t dense_gather(const DBlock& b, int l, int n, int ndim) {
@@ -556,18 +556,28 @@ __device__ __forceinline__ double bf16_val(__bf16 h) { return (double)(float)h; 
 // The state split into bf16 pieces once per step (the apply kernels of every
 // row tile of a block then only gather and pack them): x = hi + mid + lo with
 // hi = bf16(x), mid = bf16(x - hi), lo = bf16(x - hi - mid), the same split
-// the apply performs when no pieces are given.
-__global__ void split_pieces_kernel(const double* __restrict__ x, int64_t total, int np,
-                                    __bf16* __restrict__ P) {
+// the apply performs when no pieces are given.  The pieces of an entry are
+// adjacent (one 4- or 8-byte load brings all of them).
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+template <int NP>
+__global__ void split_pieces_kernel(const double* __restrict__ x, int64_t total,
+                                    typename std::conditional<NP == 3, bf16x4, bf16x2>::type* P) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     const double v = x[e];
     const __bf16 hi = (__bf16)(float)v;
     const double r1 = v - (double)(float)hi;
     const __bf16 mid = (__bf16)(float)r1;
-    P[e] = hi;
-    P[total + e] = mid;
-    if (np == 3) P[2 * total + e] = (__bf16)(float)(r1 - (double)(float)mid);
+    if constexpr (NP == 3) {
+      bf16x4 o;
+      o[0] = hi; o[1] = mid; o[2] = (__bf16)(float)(r1 - (double)(float)mid); o[3] = (__bf16)0.0f;
+      P[e] = o;
+    } else {
+      bf16x2 o;
+      o[0] = hi; o[1] = mid;
+      P[e] = o;
+    }
   }
 }
 
@@ -616,13 +626,13 @@ __global__ __launch_bounds__(256) void apply_bf16_kernel(ApplyArgs a) {
   const int xc = tid & 63, xg = tid >> 6;
   // staged X of one chunk: eight local rows of column xc, as float64 values
   // (split here) or as pieces (split once per step by split_pieces_kernel)
-  typedef typename std::conditional<PRE, bf16x8[NP], double[8]>::type xreg_t;
+  typedef typename std::conditional<NP == 3, bf16x4, bf16x2>::type piece_t;
+  typedef typename std::conditional<PRE, piece_t[8], double[8]>::type xreg_t;
   auto load_x = [&](int ch, xreg_t& v) {
     if constexpr (PRE) {
+      const piece_t* xp = reinterpret_cast<const piece_t*>(a.xp);
 #pragma unroll
-      for (int p = 0; p < NP; ++p)
-#pragma unroll
-        for (int e = 0; e < 8; ++e) v[p][e] = a.xp[p * a.xp_stride + goff[ch * KC + xg * 8 + e] + xc];
+      for (int e = 0; e < 8; ++e) v[e] = xp[goff[ch * KC + xg * 8 + e] + xc];
     } else {
 #pragma unroll
       for (int e = 0; e < 8; ++e) v[e] = a.x_in[goff[ch * KC + xg * 8 + e] + xc];
@@ -630,8 +640,13 @@ __global__ __launch_bounds__(256) void apply_bf16_kernel(ApplyArgs a) {
   };
   auto store_x = [&](const xreg_t& v, int buf) {
     if constexpr (PRE) {
+      bf16x8 pc[NP];
 #pragma unroll
-      for (int p = 0; p < NP; ++p) Xs[buf][p][xc][xg] = v[p];
+      for (int e = 0; e < 8; ++e)
+#pragma unroll
+        for (int p = 0; p < NP; ++p) pc[p][e] = v[e][p];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) Xs[buf][p][xc][xg] = pc[p];
     } else {
       bf16x8 pc[NP];
 #pragma unroll
@@ -944,7 +959,7 @@ hipError_t dense_apply(int precision, int cfg, const void* blocks, const void* E
   ApplyArgs a;
   a.bias = bias;
   a.xp = nullptr;
-  a.xp_stride = 0;
+  (void)n_points;
   a.blocks = (const DBlock*)blocks; a.E = E; a.e_stride = e_stride;
   a.x_in = x_in; a.x_out = x_out; a.n = n; a.ndim = ndim; a.ns = ns;
   a.rows = rows; a.rows_p = rows_p; a.cols = cols; a.cols_p = cols_p;
@@ -989,10 +1004,7 @@ hipError_t dense_apply(int precision, int cfg, const void* blocks, const void* E
   const dim3 g(n_blocks * a.row_tiles * a.col_tiles);
   const size_t gl = (size_t)cols_p * sizeof(int64_t);  // gathered row offsets
   if (gl > 64 * 1024) return hipErrorInvalidValue;
-  if (xpieces) {  // the state was split into pieces by dense_split_pieces
-    a.xp = (const __bf16*)xpieces;
-    a.xp_stride = (int64_t)n_points * ns;
-  }
+  if (xpieces) a.xp = (const __bf16*)xpieces;  // split by dense_split_pieces
 #define LEM_BF16(NT_, WM_)                                                                     \
   if (a.xp) hipLaunchKernelGGL((apply_bf16_kernel<NT_, WM_, true>), g, dim3(256), gl, st, a); \
   else hipLaunchKernelGGL((apply_bf16_kernel<NT_, WM_, false>), g, dim3(256), gl, st, a);
@@ -1009,9 +1021,14 @@ hipError_t dense_apply(int precision, int cfg, const void* blocks, const void* E
 
 hipError_t dense_split_pieces(const double* x, int64_t total, int np, void* pieces,
                               hipStream_t st) {
-  if (np != 2 && np != 3) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(split_pieces_kernel, grid1(total), dim3(256), 0, st, x, total, np,
-                     (__bf16*)pieces);
+  if (np == 2)
+    hipLaunchKernelGGL(split_pieces_kernel<2>, grid1(total), dim3(256), 0, st, x, total,
+                       (bf16x2*)pieces);
+  else if (np == 3)
+    hipLaunchKernelGGL(split_pieces_kernel<3>, grid1(total), dim3(256), 0, st, x, total,
+                       (bf16x4*)pieces);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

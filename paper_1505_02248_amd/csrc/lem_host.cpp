@@ -1130,7 +1130,7 @@ lem_status plan_dense(lem_plan_s* p, hipStream_t st, const double* host_g) {
   // default tile shape of the apply kernel (the autotuner may replace it)
   p->tile = p->opt.precision == LEM_FP32 ? 2 : p->opt.precision == LEM_FP64 ? 0 : (p->rows_p >= 256 ? 1 : 0);
   if (p->opt.precision >= LEM_BF16X2) {  // pieces of the state, split once per step
-    const int np = p->opt.precision == LEM_BF16X3 ? 3 : 2;
+    const int np = p->opt.precision == LEM_BF16X3 ? 4 : 2;  // pieces per entry (3 padded to 4)
     unsigned short* xp;
     LEM_TRY(dalloc(p, &xp, (size_t)np * p->N * p->ns, &p->bytes_work));
     p->d_xp = xp;

@@ -96,25 +96,41 @@ __global__ void ere_rhs_kernel(const double* __restrict__ x, double* f, int n, i
   }
 }
 
-// y(core) = x(core) + sum_l Phi[blk][row][l][s] f(gather(l), s): one thread
-// per (block, core row, member), consecutive threads on consecutive members.
-__global__ void ere_apply_kernel(const double* __restrict__ x, const double* __restrict__ f,
-                                 const double* __restrict__ Phi, const EreBox* boxes, int nb,
-                                 int ns, int nl, int rows, int n, double* y) {
-  const int64_t total = (int64_t)nb * rows * ns;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int s = (int)(e % ns);
-    const int64_t t = e / ns;
-    const int row = (int)(t % rows);
-    const int blk = (int)(t / rows);
-    const EreBox b = boxes[blk];
+// y(core) = x(core) + sum_l Phi[blk][row][l][s] f(gather(l), s).  One
+// workgroup per (block, core row, 64 members): wave q of the four sums the
+// local rows l = q, q + 4, ... for its 64 consecutive members (coalesced loads
+// of Phi and f), the four partial sums meet in LDS.
+__global__ __launch_bounds__(256) void ere_apply_kernel(const double* __restrict__ x,
+                                                        const double* __restrict__ f,
+                                                        const double* __restrict__ Phi,
+                                                        const EreBox* boxes, int ns, int nl,
+                                                        int rows, int n, double* y) {
+  __shared__ double part[3][64];
+  const int sch = (ns + 63) / 64;
+  const int64_t t = blockIdx.x / sch;  // block * rows + row
+  const int s = (int)(blockIdx.x - t * sch) * 64 + (threadIdx.x & 63);
+  const int q = threadIdx.x >> 6;
+  const int row = (int)(t % rows);
+  const int blk = (int)(t / rows);
+  const EreBox b = boxes[blk];
+  double acc = 0.0;
+  if (s < ns) {
     const double* ph = Phi + (t * nl) * ns + s;
-    double acc = 0.0;
-    for (int l = 0; l < nl; ++l)
-      acc = fma(ph[(int64_t)l * ns], f[(int64_t)ere_wrap(b.ox - b.h + l, n) * ns + s], acc);
+    double a0 = 0.0, a1 = 0.0;
+    int l = q;
+    for (; l + 4 < nl; l += 8) {
+      a0 = fma(ph[(int64_t)l * ns], f[(int64_t)ere_wrap(b.ox - b.h + l, n) * ns + s], a0);
+      a1 = fma(ph[(int64_t)(l + 4) * ns], f[(int64_t)ere_wrap(b.ox - b.h + l + 4, n) * ns + s], a1);
+    }
+    if (l < nl) a0 = fma(ph[(int64_t)l * ns], f[(int64_t)ere_wrap(b.ox - b.h + l, n) * ns + s], a0);
+    acc = a0 + a1;
+  }
+  if (q > 0) part[q - 1][threadIdx.x & 63] = acc;
+  __syncthreads();
+  if (q == 0 && s < ns) {
+    const int i = threadIdx.x;
     const int64_t o = (int64_t)(b.ox + row) * ns + s;
-    y[o] = x[o] + acc;
+    y[o] = x[o] + ((acc + part[0][i]) + (part[1][i] + part[2][i]));
   }
 }
 
@@ -441,8 +457,9 @@ hipError_t ere_step(const double* x, double* f, const double* Phi, const void* b
                     hipStream_t st) {
   hipLaunchKernelGGL(ere_rhs_kernel, ere_grid((int64_t)n * ns), dim3(256), 0, st, x, f, n, ns, dt,
                      dx, nu);
-  hipLaunchKernelGGL(ere_apply_kernel, ere_grid((int64_t)nb * rows * ns), dim3(256), 0, st, x, f,
-                     Phi, (const EreBox*)boxes, nb, ns, nl, rows, n, y);
+  const int64_t wgs = (int64_t)nb * rows * ((ns + 63) / 64);
+  hipLaunchKernelGGL(ere_apply_kernel, dim3((unsigned)wgs), dim3(256), 0, st, x, f, Phi,
+                     (const EreBox*)boxes, ns, nl, rows, n, y);
   return hipGetLastError();
 }
 
