@@ -489,3 +489,66 @@ def test_dense_variable_coefficients(work, ns, precision, tol, expm):
     got = run(plan, p.states, 2)
     want = oracle_lem(p, boxes, p.states, 2)
     assert rel_l2(got, want) <= tol
+
+
+# ------------------------------------------------------- degenerate cases --
+
+@pytest.mark.parametrize("method,ns", [("dense", 64), ("dense", 1), ("krylov", 2)])
+def test_zero_buffer_is_block_exponential(method, ns):
+    """No buffer (h = 0 from a decay-bound range clamped to [0, 0]): every core
+    evolves alone with the exponential of its own principal submatrix."""
+    p = L.workload_2d_ensemble(n=64, n_states=max(ns, 1))
+    p.states = p.states[:, :ns].copy()
+    plan = lem.Plan(lem.Operator.from_problem(p), p.dt, method=method, core=16, halo=0,
+                    halo_min=0, halo_max=0, n_states=ns, krylov_tol=1e-14)
+    boxes = check_maps(plan, 2, p.n)
+    assert np.all(boxes[:, 4] == 0)
+    got = run(plan, p.states, 2)
+    want = oracle_lem(p, boxes, p.states, 2, krylov_tol=1e-16)
+    assert rel_l2(got, want) <= 1e-12
+
+
+def test_schrodinger_free_particle_plane_waves_on_gpu():
+    """kappa = 0, whole grid (D = 1): discrete plane waves exp(i k x_j) are
+    eigenvectors of H with eigenvalue (1 - cos(k dx)) / dx^2, so each step
+    multiplies them by exp(-i dt lambda) (closed form, no oracle)."""
+    n, Lx, dt, steps = 64, 10.0, 0.02, 5
+    dx = Lx / n
+    x = -0.5 * Lx + np.arange(n) * dx
+    ms = np.array([0, 1, 3, 7, 31])
+    k = 2 * np.pi * ms / Lx
+    c0 = np.exp(1j * np.outer(x, k))
+    plan = lem.SchrodingerPlan(n, Lx, 0.0, dt, n_states=len(ms), core=n, halo=0)
+    xin = lem.SchrodingerPlan.to_real_form(torch.from_numpy(c0)).to("cuda")
+    y = torch.empty_like(xin)
+    plan.step(xin, y, steps)
+    torch.cuda.synchronize()
+    got = lem.SchrodingerPlan.from_real_form(y.cpu()).numpy()
+    lam = (1.0 - np.cos(k * dx)) / (dx * dx)
+    want = c0 * np.exp(-1j * steps * dt * lam)[None, :]
+    assert np.abs(got - want).max() <= 1e-12
+
+
+def test_rosenbrock_inviscid_matches_oracle():
+    """nu = 0 (inviscid Burgers, centered differences) at a small Courant number."""
+    n, Lx = 200, 10.0
+    dx = Lx / n
+    dt = 0.4 * dx
+    u0 = _burgers_states(n, Lx, 3, 8)
+    plan = lem.ErePlan(n, dx, 0.0, dt, n_states=3, core=25, halo=10, refresh=2)
+    got = run(plan, u0, 6)
+    boxes = [P.Box(b * 25, 0, 25, 1, 10) for b in range(n // 25)]
+    want = ROS.ere_lem_run(u0, boxes, n, dx, 0.0, dt, 6, refresh=2)
+    assert rel_l2(got, want) <= 1e-12
+
+
+def test_step_argument_errors():
+    p = L.workload_2d_ensemble(n=64, n_states=64)
+    plan = lem.Plan(lem.Operator.from_problem(p), p.dt, method="dense", core=16, halo=4,
+                    n_states=64)
+    x = dev(p.states)
+    y = torch.empty_like(x)
+    with pytest.raises(lem.LemError):
+        plan.step(x, y, 0)  # n_steps must be >= 1
+    with pytest.raises(ValueError):
+        plan.step(x[:10], y, 1)  # wrong size
