@@ -35,7 +35,7 @@ MFMA_FP32_PEAK_TFLOPS = 157.3
 # 256 MiB reference copy (profiles/apply_fp64_2d256x256x64_h14.md); valid only
 # for the apply kernel source they were taken on: the text of dense.hip from
 # its apply section to the split-bf16 kernel, plus its tile-shape table.
-TRAFFIC = {"apply": ("03c8d9c2f713", {0: 148060518, 1: 145418921, 2: 158006442, 3: 158094493, 4: 142171189, 5: 141683825, 6: 145681033, 7: 158004399})}
+TRAFFIC = {"apply": ("d5a520228ca1", {0: 148002308, 1: 145000329, 2: 158006517, 3: 158089448, 4: 142227697, 5: 141826341, 6: 145872664, 7: 157996283})}
 
 
 def _apply_source_key(text: str) -> str:
