@@ -51,7 +51,8 @@ __host__ __device__ inline int64_t lds_layout(int NT, int m, int nloc, int aug, 
   *off_red = d;
   d += (int64_t)(NT / 64) * 64 + 64;    // reduction exchange + scalars
   *off_e = d;
-  d += 7 * (int64_t)mp * mp + 8;        // expm work (A, A2, A4, A6, U, V, R) + pivot
+  d += 7 * (int64_t)mp * mp;            // expm work (A, A2, A4, A6, U, V, R)
+  d += NT / 64 + 4 > 8 ? NT / 64 + 4 : 8;  // pivot / per-wave maxima of expm_mfma
   return d;
 }
 
@@ -293,7 +294,9 @@ template <int NT, int P, bool VLDS, bool AUG>
 __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
   constexpr int CH = P >= 16 ? 2 : (P >= 8 ? 2 : (P >= 4 ? 4 : 8));  // rows per chunk
   constexpr int CHS = CH;  // rows per load batch of the streamed sweeps
-  constexpr bool PREW = P <= 8;
+  // stencil weights in registers for up to 8 points (not in the wide
+  // streamed shapes, whose register budget is 128 per lane)
+  constexpr bool PREW = P <= 8 && NT <= 256;
   typedef typename std::conditional<VLDS, double*, gdouble*>::type VPtr;
   extern __shared__ double smem[];
   const int tid = threadIdx.x;
@@ -313,7 +316,8 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
     V = (VPtr)g;
   }
   double* H = smem + oh;
-  double* red = smem + ored;  // [NT/64][32]
+  double* red = smem + ored;  // [NT/64][32] (streamed: [NT/64][64])
+  double* tot = red + (NT / 64) * 64;  // 64 workgroup totals (streamed sweeps)
   double* EA = smem + oe;
   double* EW = EA + mp * mp;
   double* ER = EW + 5 * mp * mp;
@@ -719,6 +723,10 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
           }
         }
         __syncthreads();
+        // one thread per slot sums the wave partials, so that the sweeps below
+        // read each total once instead of once per wave
+        if (tid < 64) tot[tid] = red_total64<NT>(red, tid);
+        __syncthreads();
         // sweep B: vt = u - V s, y = w - V z, and |vt|^2 (slot 30)
         double vt[P], y[P];
 #pragma unroll
@@ -731,8 +739,8 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
           for (int q = 0; q < CHS; ++q) {
             const int i = min(i0 + q, j - 1);
             const bool ok = i0 + q < j;
-            sc[q] = ok ? red_total64<NT>(red, i) : 0.0;
-            zc[q] = ok ? red_total64<NT>(red, 32 + i) : 0.0;
+            sc[q] = ok ? tot[i] : 0.0;
+            zc[q] = ok ? tot[32 + i] : 0.0;
 #pragma unroll
             for (int p = 0; p < P; ++p) vals[q][p] = V[(int64_t)i * nlv + li[p]];
           }
@@ -756,13 +764,13 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
         }
         __syncthreads();
         const double nu = sqrt(fmax(red_total64<NT>(red, 30), 0.0));
-        const double bw = red_total64<NT>(red, 63);  // u^T w
+        const double bw = tot[63];  // u^T w
         // complete column j-1: H[i][j-1] += s_i, H[j][j-1] = nu
         bool brk = false;
         if (j > 0) {
           double hs = 0.0;
           for (int i = 0; i < j; ++i) {
-            const double hij = H[i * m + j - 1] + red_total64<NT>(red, i);
+            const double hij = H[i * m + j - 1] + tot[i];
             hs = fma(hij, hij, hs);
           }
           brk = !(nu > 1e-14 * sqrt(hs + nu * nu));  // invariant subspace reached
@@ -778,15 +786,15 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
           const int i = tid;
           double hcorr = 0.0;
           if (j > 0) {
-            hcorr = (i < j) ? H[i * m + j - 1] + red_total64<NT>(red, i) : nu;
+            hcorr = (i < j) ? H[i * m + j - 1] + tot[i] : nu;
           }
           if (!last && !brk) {
             double t = 0.0;
             for (int l = (i > 0 ? i - 1 : 0); l < j; ++l) {
               const double hil = (l == j - 1) ? hcorr : H[i * m + l];
-              t = fma(hil, red_total64<NT>(red, l), t);
+              t = fma(hil, tot[l], t);
             }
-            const double num = (i < j) ? red_total64<NT>(red, 32 + i) : cj;
+            const double num = (i < j) ? tot[32 + i] : cj;
             H[i * m + j] = (num - t) / nu;
           }
           if (j > 0) H[i * m + j - 1] = hcorr;
@@ -889,7 +897,7 @@ void krylov_lds_config(int ndim, int nloc, int* nt, int* pmax) {
   if (ndim == 1 && nloc <= 512) { *nt = 64; *pmax = 8; return; }
   if (nloc <= 1024) { *nt = 256; *pmax = 4; return; }
   if (nloc <= 2048) { *nt = 256; *pmax = 8; return; }
-  if (nloc <= 4096) { *nt = 256; *pmax = 16; return; }
+  if (nloc <= 4096) { *nt = 1024; *pmax = 4; return; }  // streamed basis only
   *nt = 0; *pmax = 0;  // larger boxes would spill registers: not supported
 }
 
@@ -919,7 +927,7 @@ static hipError_t launch_shape(const KrylovArgs& a, int ns, int nt, int pmax, bo
   if (nt == 64 && pmax == 8) return launch_l<64, 8, false, AUG>(a, ns, lds, st);
   if (nt == 256 && pmax == 4) return launch_l<256, 4, false, AUG>(a, ns, lds, st);
   if (nt == 256 && pmax == 8) return launch_l<256, 8, false, AUG>(a, ns, lds, st);
-  if (nt == 256 && pmax == 16) return launch_l<256, 16, false, AUG>(a, ns, lds, st);
+  if (nt == 1024 && pmax == 4) return launch_l<1024, 4, false, AUG>(a, ns, lds, st);
   return hipErrorInvalidValue;
 }
 

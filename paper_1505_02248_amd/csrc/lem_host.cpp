@@ -556,7 +556,7 @@ LaunchKey launch_key(int ndim, int nloc, int m, size_t* lds, int aug = 0) {
   if (nt == 0 || m > lem::krylov_lds_max_m()) return {-1, 0, 0, false};
   const size_t with_v = lem::krylov_lds_bytes(nt, m, nloc, true, aug);
   const int variant = aug ? 2 : 1;  // 2: kernels with the augmented coordinate
-  if (pm <= 8 && with_v <= 160 * 1024) {
+  if (pm <= 8 && nt <= 256 && with_v <= 160 * 1024) {  // wide shapes stream the basis
     *lds = with_v;
     return {variant, nt, pm, true};
   }
@@ -1395,7 +1395,7 @@ lem_status create_plan(const lem_operator* op, double dt, const lem_options* opt
   lem_status s = build_op(op, dt, &p->op);
   if (s != LEM_OK) return guard(s);
   if (p->method == LEM_METHOD_DENSE && p->op.variable &&
-      (p->forced || opt->precision >= LEM_BF16X2 || opt->core <= 0))
+      (op->forcing != nullptr || opt->precision >= LEM_BF16X2 || opt->core <= 0))
     return guard(fail(LEM_ERR_UNSUPPORTED, "variable-coefficient stored blocks take a uniform core, "
                                            "FP64 or FP32 and no forcing"));
   p->N = p->op.N();
@@ -1418,6 +1418,13 @@ lem_status create_plan(const lem_operator* op, double dt, const lem_options* opt
       return guard(fail(LEM_ERR_INVALID, "a single core covering the grid is the global method"));
     s = make_partition(p);
     if (s != LEM_OK) return guard(s);
+  }
+  if (p->method == LEM_METHOD_KRYLOV) {
+    // the Krylov kernels hold a basis row of at most 4096 points (the box
+    // plus the augmented coordinate of a forced step)
+    for (const Box& b : p->boxes)
+      if ((int64_t)box_lx(b, p->op.n) * box_ly(b, p->op.n, p->op.ndim) + (p->forced ? 1 : 0) > 4096)
+        return guard(fail(LEM_ERR_UNSUPPORTED, "local box larger than 4096 points (4095 when forced)"));
   }
   if (!p->dry) {
     hipStream_t st = p->stream;

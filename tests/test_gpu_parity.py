@@ -304,9 +304,11 @@ def test_forced_krylov_matches_oracle():
     assert plan.query()["device_status"] == 0
 
 
-@pytest.mark.parametrize("core,halo,m", [(16, 8, 30), (16, 6, 12)])
-def test_forced_krylov_variable_nu_streamed_and_lds(core, halo, m):
-    p = L.workload_2d_variable(n=64)
+@pytest.mark.parametrize("n,core,halo,m", [(64, 16, 8, 30), (64, 16, 6, 12), (128, 32, 15, 30)])
+def test_forced_krylov_variable_nu_streamed_and_lds(n, core, halo, m):
+    # 1024-point boxes at m = 30 stream their basis (256 threads), 3844-point
+    # boxes take the 1024-thread streamed shape, m = 12 on 28x28 stays in LDS
+    p = L.workload_2d_variable(n=n)
     g = _forcing(p, 1, 7)
     plan = lem.Plan(_forced_op(p, g), p.dt, method="krylov", core=core, halo=halo,
                     krylov_m=m, krylov_m_max=m, max_substeps=8, krylov_tol=1e-13)

@@ -99,6 +99,19 @@ def test_invalid_arguments_are_reported():
     with pytest.raises(lem.LemError) as e:
         lem.Plan(o, 2 / 64, core=16, halo=4, krylov_m_max=60, dry_run=True)
     assert e.value.status == 1
+    # Krylov boxes hold at most 4096 points, one fewer with a forcing (the
+    # augmented coordinate); the check precedes any device work
+    big = lem.Operator(2, 128, 1 / 128, (1.0, 0.5), 1e-3)
+    lem.Plan(big, 2 / 128, method="krylov", core=32, halo=16, dry_run=True)
+    with pytest.raises(lem.LemError) as e:
+        lem.Plan(big, 2 / 128, method="krylov", core=64, halo=8, dry_run=True)
+    assert e.value.status == 6 and "4096" in str(e.value)
+    g = np.ones((128 * 128, 1))
+    forced = lem.Operator(2, 128, 1 / 128, (1.0, 0.5), 1e-3, forcing=g)
+    lem.Plan(forced, 2 / 128, method="krylov", core=32, halo=15, dry_run=True)
+    with pytest.raises(lem.LemError) as e:
+        lem.Plan(forced, 2 / 128, method="krylov", core=32, halo=16, dry_run=True)
+    assert e.value.status == 6 and "4095" in str(e.value)
 
 
 def test_dry_plan_cannot_step_and_reports_sizes():
@@ -154,13 +167,14 @@ def test_face_velocity_errors():
 
 
 def test_column_partition_maps_and_halos_match_oracle():
-    p = L.workload_2d_columns(n=128, n_states=1)
+    # 64 rows: every column box stays within the 4096 points of a Krylov box
+    p = L.workload_2d_columns(n=64, n_states=1)
     W = op.from_problem(p)
     G = H.growth_factor(W)
     plan = lem.Plan(lem.Operator.from_problem(p), p.dt, core=16, halo=0, halo_min=2,
                     halo_max=24, halo_tol=1e-8, columns=True, dry_run=True)
     boxes, gather, scatter = plan.maps()
-    assert boxes.shape == (8, 5) and np.all(boxes[:, 3] == 128) and np.all(boxes[:, 1] == 0)
+    assert boxes.shape == (4, 5) and np.all(boxes[:, 3] == 64) and np.all(boxes[:, 1] == 0)
     Go, So = _oracle_maps(boxes, 2, p.n)
     assert np.array_equal(gather, Go.astype(np.int32))
     assert np.array_equal(scatter, So.astype(np.int32))
@@ -169,7 +183,7 @@ def test_column_partition_maps_and_halos_match_oracle():
         co = H.block_coefficients(W, box, 2)
         assert H.accepts(co, 2, 1e-8, 2, box.h, G, cut_y=False), box
     q = plan.query()
-    assert q["n_loc_max"] == (16 + 2 * q["halo_max"]) * 128
+    assert q["n_loc_max"] == (16 + 2 * q["halo_max"]) * 64
     with pytest.raises(lem.LemError):  # column-wise cores are a Krylov feature
         lem.Plan(lem.Operator.from_problem(p), p.dt, method="dense", core=16, halo=4,
                  columns=True, dry_run=True)
