@@ -307,7 +307,7 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
   const int nloc = b.Lx * b.Ly;   // points of the box
   const int nlv = nloc + (AUG ? 1 : 0);  // basis row length (plus the augmented coordinate)
   int64_t oh, ored, oe;
-  lds_layout(NT, m, VLDS ? nlv : 0, AUG ? 1 : 0, &oh, &ored, &oe);
+  const int64_t ostage = lds_layout(NT, m, VLDS ? nlv : 0, AUG ? 1 : 0, &oh, &ored, &oe);
   VPtr V;
   if constexpr (VLDS) {
     V = smem;
@@ -329,6 +329,31 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
   const double* mux = (b.coef ? b.coef : a.coef) + (varcoef ? b.mu_off : 0);
   const int64_t Ng = (b.ndim == 1) ? b.n : (int64_t)b.n * b.n;
   const double* muy = mux + Ng;
+  // Wide streamed shapes recompute the stencil weights per use; their
+  // diffusion coefficients are staged in LDS once (after the work areas):
+  // cmx[ly][lx + 1] = mu_x at box point (lx, ly) for lx = -1 .. Lx-1 and
+  // cmy[ly + 1][lx] = mu_y for ly = -1 .. Ly-1, wrapped on the periodic grid.
+  const bool stage = !VLDS && NT >= 512 && varcoef && !b.varvel && b.stage;
+  const int sx = b.Lx + 1;
+  double* cmx = smem + ostage;
+  double* cmy = cmx + (int64_t)sx * b.Ly;
+  if (stage) {
+    for (int e = tid; e < sx * b.Ly; e += NT) {
+      const int ly = e / sx, lx = e - ly * sx - 1;
+      const int gx = wrap(b.ox - b.h + lx, b.n);
+      const int gy = (b.ndim == 1) ? 0 : wrap(b.oy - b.hy + ly, b.n);
+      cmx[e] = mux[(int64_t)gy * b.n + gx];
+    }
+    if (b.ndim == 2) {
+      for (int e = tid; e < b.Lx * (b.Ly + 1); e += NT) {
+        const int ly = e / b.Lx - 1, lx = e - (ly + 1) * b.Lx;
+        const int gx = wrap(b.ox - b.h + lx, b.n);
+        const int gy = wrap(b.oy - b.hy + ly, b.n);
+        cmy[e] = muy[(int64_t)gy * b.n + gx];
+      }
+    }
+    __syncthreads();
+  }
 
   // Point p of this thread is local index tid + p*NT; its box coordinates
   // are recomputed where needed (keeping them would cost 2P registers).
@@ -358,25 +383,38 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
       int opq = 0;
       if constexpr (!PREW) asm volatile("" : "+s"(opq));  // recompute per use: no hoisting
       lx += opq;
-      const int gx = wrap(b.ox - b.h + lx, b.n);
-      const int gy = (b.ndim == 1) ? 0 : wrap(b.oy - b.hy + ly, b.n);
-      const int64_t g = (int64_t)gy * b.n + gx;
-      const double me = mux[g];
-      const double mw = mux[(int64_t)gy * b.n + wrap(gx - 1, b.n)];
-      double mn = 0.0, ms = 0.0;
-      if (b.ndim == 2) {
-        mn = muy[g];
-        ms = muy[(int64_t)wrap(gy - 1, b.n) * b.n + gx];
+      double me, mw, mn = 0.0, ms = 0.0;
+      int64_t g = 0, gw = 0, gs = 0;
+      if (stage) {
+        const int sy = min(ly, b.Ly - 1);  // the augmented row reads a valid entry
+        me = cmx[sy * sx + lx + 1];
+        mw = cmx[sy * sx + lx];
+        if (b.ndim == 2) {
+          mn = cmy[(sy + 1) * b.Lx + lx];
+          ms = cmy[sy * b.Lx + lx];
+        }
+      } else {
+        const int gx = wrap(b.ox - b.h + lx, b.n);
+        const int gy = (b.ndim == 1) ? 0 : wrap(b.oy - b.hy + ly, b.n);
+        g = (int64_t)gy * b.n + gx;
+        gw = (int64_t)gy * b.n + wrap(gx - 1, b.n);
+        gs = (int64_t)wrap(gy - 1, b.n) * b.n + gx;
+        me = mux[g];
+        mw = mux[gw];
+        if (b.ndim == 2) {
+          mn = muy[g];
+          ms = muy[gs];
+        }
       }
       const double sc = b.sub_scale;
       w0 = -(me + mw + mn + ms) * sc;
       if (b.varvel) {  // conservative centered advection by face velocities
         const double* axf = mux + 2 * Ng;
-        const double ae = axf[g] * sc, aw = axf[(int64_t)gy * b.n + wrap(gx - 1, b.n)] * sc;
+        const double ae = axf[g] * sc, aw = axf[gw] * sc;
         double an = 0.0, as = 0.0;
         if (b.ndim == 2) {
           an = axf[Ng + g] * sc;
-          as = axf[Ng + (int64_t)wrap(gy - 1, b.n) * b.n + gx] * sc;
+          as = axf[Ng + gs] * sc;
         }
         w0 -= (ae - aw) + (an - as);
         wW = fma(mw, sc, aw);
@@ -887,6 +925,12 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
 size_t krylov_lds_bytes(int nt, int m, int nloc, bool vlds, int aug) {
   int64_t a, b2, c;
   return (size_t)lds_layout(nt, m, vlds ? nloc : 0, aug, &a, &b2, &c) * 8;
+}
+
+size_t krylov_stage_bytes(int nt, bool vlds, bool varcoef, bool varvel, int ndim, int lx,
+                          int ly) {
+  if (vlds || nt < 512 || !varcoef || varvel) return 0;
+  return ((size_t)(lx + 1) * ly + (ndim == 2 ? (size_t)lx * (ly + 1) : 0)) * 8;
 }
 
 int krylov_lds_max_m() { return kLdsMaxM; }

@@ -47,6 +47,8 @@ struct KBlock {
   int32_t varvel;             // 1: face velocities follow the face mu's in the
                               // coefficient arrays (ax at mu_off + 2N, ay at
                               // mu_off + 3N; conservative centered advection)
+  int32_t stage;              // 1: the kernel stages the face mu's of the box
+                              // in LDS (set when the launch reserves the room)
   double gscale;              // dt_sub: scales the forcing to the sub-step
   const double* force;        // forcing g (rate units), N x ns, or null
   // Optional per-block buffers (null: the launch's arguments).  A serving

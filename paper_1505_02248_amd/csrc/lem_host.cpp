@@ -585,6 +585,11 @@ lem_status bucketize(std::vector<lem::KBlock>& kb, std::vector<lem_plan_s::Bucke
     const LaunchKey key = launch_key(kb[i].ndim, nloc, kb[i].m, &need[i], kb[i].aug);
     if (key.variant < 0)
       return fail(LEM_ERR_UNSUPPORTED, "local box larger than 4096 points (4095 when forced)");
+    const size_t stage = lem::krylov_stage_bytes(key.nt, key.vlds, kb[i].mu_off >= 0,
+                                                 kb[i].varvel != 0, kb[i].ndim, kb[i].Lx,
+                                                 kb[i].Ly);
+    kb[i].stage = (stage > 0 && need[i] + stage <= 160 * 1024) ? 1 : 0;
+    if (kb[i].stage) need[i] += stage;
     groups[key].push_back((int)i);
   }
   std::vector<lem::KBlock> out;

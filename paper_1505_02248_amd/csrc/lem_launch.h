@@ -17,6 +17,9 @@ hipError_t launch_probe_fill(double* x, int64_t n, uint64_t seed, hipStream_t st
 
 // ---- Krylov LEM step (krylov_lem.hip)
 size_t krylov_lds_bytes(int nt, int m, int nloc, bool vlds, int aug);
+// extra LDS of the wide streamed shapes for the staged diffusion coefficients
+size_t krylov_stage_bytes(int nt, bool vlds, bool varcoef, bool varvel, int ndim, int lx,
+                          int ly);
 int krylov_lds_max_m();
 void krylov_lds_config(int ndim, int nloc, int* nt, int* pmax);
 hipError_t launch_krylov_lds(const KBlock* blocks, int n_blocks, int ns, int nt, int pmax,
