@@ -321,8 +321,14 @@ struct lem_plan_s {
   bool dry = false;
   // Krylov
   std::vector<int> m, nsub;
-  struct Bucket { int variant, nt, pmax; bool vlds; size_t lds; int first, count; };
+  struct Bucket { int variant, nt, pmax; bool vlds; size_t lds; int first, count; double cost; };
   std::vector<Bucket> buckets;
+  // the step launches the costliest bucket on the caller's stream and the
+  // others on side streams forked from it and joined back (the launches then
+  // share the CUs that one bucket alone leaves idle)
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> ev_join;
+  hipEvent_t ev_fork = nullptr;
   lem::KBlock* d_kb = nullptr;
   double* d_coef = nullptr;
   double* d_vwork = nullptr;
@@ -370,6 +376,9 @@ struct lem_plan_s {
       hipGraphExecDestroy(g.second.second);
       hipGraphDestroy(g.second.first);
     }
+    for (hipStream_t s : side) hipStreamDestroy(s);
+    for (hipEvent_t e : ev_join) hipEventDestroy(e);
+    if (ev_fork) hipEventDestroy(ev_fork);
     for (void* q : allocs) {
       if (arena) arena->release(q);
       else hipFree(q);
@@ -601,6 +610,7 @@ lem_status bucketize(std::vector<lem::KBlock>& kb, std::vector<lem_plan_s::Bucke
     for (int i : g.second) {
       lem::KBlock k = kb[i];
       bk.lds = std::max(bk.lds, need[i]);
+      bk.cost += (double)ns * block_cost(k.ndim, k.Lx * k.Ly + k.aug, k.m, k.nsub);
       if (!g.first.vlds) {
         k.v_off = voff;
         voff += (int64_t)(k.m + 1 + k.aug) * (k.Lx * k.Ly + k.aug) * ns;
@@ -618,12 +628,38 @@ lem_status launch_buckets(const lem_plan_s* p, const lem::KBlock* d_kb,
                           const std::vector<lem_plan_s::Bucket>& bks, int ns, const double* src,
                           double* dst, double* vwork, double* diag, double* calib, int mode,
                           hipStream_t st) {
-  for (const auto& b : bks) {
+  auto launch = [&](const lem_plan_s::Bucket& b, hipStream_t s) -> lem_status {
     hipError_t e = lem::launch_krylov_lds(d_kb + b.first, b.count, ns, b.nt, b.pmax, b.vlds,
                                           b.lds, src, dst, p->d_coef, vwork, diag, p->d_status,
-                                          calib, mode, b.variant == 2, st);
+                                          calib, mode, b.variant == 2, s);
     if (e != hipSuccess)
       return fail(LEM_ERR_HIP, std::string("Krylov launch: ") + hipGetErrorString(e));
+    return LEM_OK;
+  };
+  // calibration launches, single buckets and plans without side streams run
+  // in order on the caller's stream
+  if (mode != 0 || bks.size() < 2 || p->side.empty() || st == nullptr) {
+    for (const auto& b : bks) LEM_TRY(launch(b, st));
+    return LEM_OK;
+  }
+  // blocks write disjoint core rows, estimate slots and basis slices, so the
+  // buckets are independent: fork, launch, join
+  size_t big = 0;
+  for (size_t i = 1; i < bks.size(); ++i)
+    if (bks[i].cost > bks[big].cost) big = i;
+  LEM_HIP(hipEventRecord(p->ev_fork, st));
+  LEM_TRY(launch(bks[big], st));
+  size_t k = 0;
+  for (size_t i = 0; i < bks.size(); ++i) {
+    if (i == big) continue;
+    hipStream_t s = p->side[k % p->side.size()];
+    if (k < p->side.size()) LEM_HIP(hipStreamWaitEvent(s, p->ev_fork, 0));
+    LEM_TRY(launch(bks[i], s));
+    ++k;
+  }
+  for (size_t j = 0; j < std::min(k, p->side.size()); ++j) {
+    LEM_HIP(hipEventRecord(p->ev_join[j], p->side[j]));
+    LEM_HIP(hipStreamWaitEvent(st, p->ev_join[j], 0));
   }
   return LEM_OK;
 }
@@ -751,6 +787,18 @@ lem_status plan_krylov(lem_plan_s* p, hipStream_t st) {
   int64_t vw = 0;
   LEM_TRY(bucketize(kb, p->buckets, p->ns, &vw));
   p->kb_host = kb;
+  if (p->buckets.size() > 1 && !p->arena) {  // serving plans launch through the server
+    const size_t ns_side = std::min<size_t>(p->buckets.size() - 1, 3);
+    LEM_HIP(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+    for (size_t i = 0; i < ns_side; ++i) {
+      hipStream_t s;
+      hipEvent_t e;
+      LEM_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+      p->side.push_back(s);
+      LEM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      p->ev_join.push_back(e);
+    }
+  }
   LEM_TRY(dalloc(p, &p->d_kb, kb.size(), &p->bytes_work));
   LEM_TRY(upload(p->d_kb, kb.data(), kb.size() * sizeof(lem::KBlock), st));
   LEM_TRY(dalloc(p, &p->d_vwork, (size_t)std::max<int64_t>(vw, 1), &p->bytes_work));

@@ -235,12 +235,24 @@ def test_aliasing_is_rejected():
     assert e.value.status == 1
 
 
-def test_graph_replays_match_eager_bitwise():
-    p = L.workload_1d()
+@pytest.mark.parametrize("case", ["1d", "2d_uneven"])
+def test_graph_replays_match_eager_bitwise(case):
+    # 2d_uneven: cores of 16 and 32 with decay-bound halos give several launch
+    # buckets, which the step forks onto side streams and joins in the graph
+    if case == "1d":
+        p = L.workload_1d()
+        kw = dict(core=64, halo=16)
+    else:
+        p = L.workload_2d_variable(n=512)
+        kw = dict(core=0, halo=0, halo_min=4, halo_max=16, halo_tol=1e-8, krylov_tol=1e-12)
     s = torch.cuda.Stream()
-    eager = lem.Plan(lem.Operator.from_problem(p), p.dt, method="krylov", core=64, halo=16)
-    graph = lem.Plan(lem.Operator.from_problem(p), p.dt, method="krylov", core=64, halo=16,
-                     use_graph=True, stream=s)
+    eager = lem.Plan(lem.Operator.from_problem(p), p.dt, method="krylov", **kw)
+    graph = lem.Plan(lem.Operator.from_problem(p), p.dt, method="krylov", use_graph=True,
+                     stream=s, **kw)
+    if case == "2d_uneven":
+        boxes = graph.maps()[0]
+        nloc = (boxes[:, 2] + 2 * boxes[:, 4]) * (boxes[:, 3] + 2 * boxes[:, 4])
+        assert nloc.min() <= 1024 and nloc.max() > 2048  # 256- and 1024-thread launches
     x = dev(p.states)
     ref = torch.empty_like(x)
     eager.step(x, ref, 5)
