@@ -183,6 +183,26 @@ def test_krylov_streamed_bases(core, halo, m):
     assert q["device_status"] == 0
 
 
+# 1D boxes of 2049-4096 points take the 1024-thread streamed shape: constant
+# weights, and variable nu (its face coefficients staged in LDS, 1D layout)
+@pytest.mark.parametrize("variable", [False, True])
+def test_krylov_1d_wide_boxes(variable):
+    n, core, halo = 8192, 2048, 512
+    base = L.workload_1d(n=n, cfl=1.0)
+    # one row of a lognormal field, median 2e-4: |dt A| <= 51 (the constant case: 33)
+    nuf = L.lognormal_field_2d(n, 11, median=2e-4)[0] if variable else None
+    p = L.Problem(1, n, base.dx, base.dt, base.vel, None if variable else base.nu, nuf,
+                  base.states)
+    plan = lem.Plan(lem.Operator.from_problem(p), p.dt, method="krylov", core=core, halo=halo,
+                    krylov_m_max=30, max_substeps=8, krylov_tol=1e-13)
+    boxes = check_maps(plan, 1, p.n)
+    assert np.all(boxes[:, 2] + 2 * boxes[:, 4] == core + 2 * halo)
+    got = run(plan, p.states, 2)
+    want = oracle_lem(p, boxes, p.states, 2, krylov_above=2000, krylov_tol=1e-16)
+    assert rel_l2(got, want) <= 1e-12
+    assert plan.query()["device_status"] == 0
+
+
 # ---------------------------------------------------------------- global --
 
 def test_global_krylov_1d_and_2d_vs_fourier():
