@@ -15,6 +15,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "lem_device.hpp"
 #include "lem_launch.h"
@@ -175,6 +176,12 @@ __global__ void g_export_kernel(const double* H, const double* beta, int m, doub
   if (threadIdx.x == 0) { out[0] = beta[s]; out[1] = (double)m; }
 }
 
+// The passes take K >= j + 1 basis vectors (the launcher picks the smallest
+// of 4, 8, 16, 32, 49).  Every basis load is unconditional, its vector index
+// clamped to a valid one, and rows past the current ones are masked out of
+// the arithmetic afterwards: all K loads of a point are in flight before the
+// first use instead of one guarded load at a time.
+
 // Pass 1: v_j = W * inv (stored into V_j), w = dt A v_j (into Wt), partial
 // dots <v_i, w> for i <= j.
 template <int K>
@@ -188,22 +195,25 @@ __global__ __launch_bounds__(256) void g_spmv_dots(GArgs a) {
   const int64_t e0 = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int s = (int)(e0 % a.ns);
   const double sc = a.inv[s];
-  double* Vj = a.V + (int64_t)a.j * total;
+  const int j = a.j, jl = j > 0 ? j - 1 : 0;  // last stored vector (v_0 when j = 0)
+  double* Vj = a.V + (int64_t)j * total;
   for (int64_t e = e0; e < total; e += stride) {
     const int64_t pt = e / a.ns;
+    double v[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) v[q] = a.V[(int64_t)min(q, jl) * total + e];
     const double vj = a.W[e] * sc;
-    Vj[e] = vj;
     const double w = gstencil(a.op, a.W, pt, a.ns, s) * sc;
+    Vj[e] = vj;  // after the loads: with j = 0 they read this slot (and discard it)
     a.Wt[e] = w;
 #pragma unroll
-    for (int q = 0; q < K; ++q)
-      if (q < a.j) d[q] = fma(a.V[(int64_t)q * total + e], w, d[q]);
-    // q == j uses the value just formed
-#pragma unroll
-    for (int q = 0; q < K; ++q)
-      if (q == a.j) d[q] = fma(vj, w, d[q]);
+    for (int q = 0; q < K; ++q) {
+      // rows i < j from the basis, row j from the value just formed
+      const double vq = q == j ? vj : v[q];
+      d[q] = q <= j ? fma(vq, w, d[q]) : d[q];
+    }
   }
-  block_partials<K>(d, a.j + 1, a.ns, a.part, red);
+  block_partials<K>(d, j + 1, a.ns, a.part, red);
 }
 
 // Update w -= sum_i hco[i] v_i; then either dots <v_i, w> (mode 0) or the
@@ -213,24 +223,41 @@ __global__ __launch_bounds__(256) void g_update(GArgs a, int mode, double* out) 
   __shared__ double red[4 * 8 * 64];
   const int64_t total = a.N * a.ns;
   const int64_t stride = (int64_t)gridDim.x * 256;
-  double d[K];
-#pragma unroll
-  for (int q = 0; q < K; ++q) d[q] = 0.0;
+  double d[K], hc[K];
   const int64_t e0 = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int s = (int)(e0 % a.ns);
+  const int s = (int)(e0 % a.ns);  // fixed over the loop: ns divides the stride
+  const int j = a.j;
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    d[q] = 0.0;
+    hc[q] = q <= j ? a.hco[q * a.ns + s] : 0.0;
+  }
   for (int64_t e = e0; e < total; e += stride) {
+    double v[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) v[q] = a.V[(int64_t)min(q, j) * total + e];
     double w = a.Wt[e];
-    for (int q = 0; q <= a.j; ++q) w = fma(-a.hco[q * a.ns + s], a.V[(int64_t)q * total + e], w);
+#pragma unroll
+    for (int q = 0; q < K; ++q) w = fma(-hc[q], v[q], w);  // hc = 0 past row j
     out[e] = w;
     if (mode == 0) {
 #pragma unroll
-      for (int q = 0; q < K; ++q)
-        if (q <= a.j) d[q] = fma(a.V[(int64_t)q * total + e], w, d[q]);
+      for (int q = 0; q < K; ++q) d[q] = q <= j ? fma(v[q], w, d[q]) : d[q];
     } else {
       d[0] = fma(w, w, d[0]);
     }
   }
-  block_partials<K>(d, mode == 0 ? a.j + 1 : 1, a.ns, a.part, red);
+  block_partials<K>(d, mode == 0 ? j + 1 : 1, a.ns, a.part, red);
+}
+
+// Launches one pass with the smallest K that holds rows 0..j.
+template <typename F>
+static void with_k(int j, F&& f) {
+  if (j + 1 <= 4) f(std::integral_constant<int, 4>());
+  else if (j + 1 <= 8) f(std::integral_constant<int, 8>());
+  else if (j + 1 <= 16) f(std::integral_constant<int, 16>());
+  else if (j + 1 <= 32) f(std::integral_constant<int, 32>());
+  else f(std::integral_constant<int, kMaxKrylov + 1>());
 }
 
 // h[q][s] = sum over workgroups of part[g][q][s]   (grid: (cnt, ns))
@@ -351,13 +378,28 @@ static void fill_op(const GlobalWork& w, GlobalOp& o, bool forced) {
   o.force = w.force;
 }
 
+// The three passes of Arnoldi column j and their reductions (partials are
+// laid out with row stride K of the pass).
+static void column_passes(GArgs& a, int G, int j, const GlobalWork& w, hipStream_t st) {
+  with_k(j, [&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    hipLaunchKernelGGL(g_spmv_dots<K>, dim3(G), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(g_reduce, dim3(j + 1, w.ns), dim3(256), 0, st, w.part, G, K, w.ns, w.h1);
+    a.hco = w.h1;
+    hipLaunchKernelGGL(g_update<K>, dim3(G), dim3(256), 0, st, a, 0, w.Wt);
+    hipLaunchKernelGGL(g_reduce, dim3(j + 1, w.ns), dim3(256), 0, st, w.part, G, K, w.ns, w.h2);
+    a.hco = w.h2;
+    hipLaunchKernelGGL(g_update<K>, dim3(G), dim3(256), 0, st, a, 1, w.W);
+    hipLaunchKernelGGL(g_reduce, dim3(1, w.ns), dim3(256), 0, st, w.part, G, K, w.ns, w.hn);
+  });
+}
+
 hipError_t global_step(const GlobalWork& w, const double* x, double* y_out, hipStream_t st) {
   const bool forced = w.force != nullptr;
   const int64_t Na = w.N + (forced ? 1 : 0);  // points (plus the augmented coordinate)
   const int64_t total = Na * w.ns;
   const int G = global_grid(total, w.ns);
   const int m = w.m;
-  constexpr int K = kMaxKrylov + 1;
   GArgs a;
   fill_op(w, a.op, forced);
   a.V = w.V; a.W = w.W; a.Wt = w.Wt; a.part = w.part; a.N = Na; a.ns = w.ns;
@@ -386,14 +428,7 @@ hipError_t global_step(const GlobalWork& w, const double* x, double* y_out, hipS
     for (int j = 0; j < m; ++j) {
       a.j = j;
       a.inv = w.inv;
-      hipLaunchKernelGGL(g_spmv_dots<K>, dim3(G), dim3(256), 0, st, a);
-      hipLaunchKernelGGL(g_reduce, dim3(j + 1, w.ns), dim3(256), 0, st, w.part, G, K, w.ns, w.h1);
-      a.hco = w.h1;
-      hipLaunchKernelGGL(g_update<K>, dim3(G), dim3(256), 0, st, a, 0, w.Wt);
-      hipLaunchKernelGGL(g_reduce, dim3(j + 1, w.ns), dim3(256), 0, st, w.part, G, K, w.ns, w.h2);
-      a.hco = w.h2;
-      hipLaunchKernelGGL(g_update<K>, dim3(G), dim3(256), 0, st, a, 1, w.W);
-      hipLaunchKernelGGL(g_reduce, dim3(1, w.ns), dim3(256), 0, st, w.part, G, K, w.ns, w.hn);
+      column_passes(a, G, j, w, st);
       hipLaunchKernelGGL(g_finish_column, dim3((w.ns + 255) / 256), dim3(256), 0, st, w.h1,
                          w.h2, w.hn, w.H, w.inv, m, w.ns, j);
       a.W = w.W;
@@ -413,7 +448,6 @@ hipError_t global_arnoldi(const GlobalWork& w, const double* x, double* calib, h
   const int64_t total = w.N * w.ns;
   const int G = global_grid(total, w.ns);
   const int m = w.m;
-  constexpr int K = kMaxKrylov + 1;
   GArgs a;
   fill_op(w, a.op, false);  // calibration runs on the unforced operator
   a.V = w.V; a.W = const_cast<double*>(x); a.Wt = w.Wt; a.part = w.part; a.N = w.N; a.ns = w.ns;
@@ -424,14 +458,7 @@ hipError_t global_arnoldi(const GlobalWork& w, const double* x, double* calib, h
   for (int j = 0; j < m; ++j) {
     a.j = j;
     a.inv = w.inv;
-    hipLaunchKernelGGL(g_spmv_dots<K>, dim3(G), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(g_reduce, dim3(j + 1, w.ns), dim3(256), 0, st, w.part, G, K, w.ns, w.h1);
-    a.hco = w.h1;
-    hipLaunchKernelGGL(g_update<K>, dim3(G), dim3(256), 0, st, a, 0, w.Wt);
-    hipLaunchKernelGGL(g_reduce, dim3(j + 1, w.ns), dim3(256), 0, st, w.part, G, K, w.ns, w.h2);
-    a.hco = w.h2;
-    hipLaunchKernelGGL(g_update<K>, dim3(G), dim3(256), 0, st, a, 1, w.W);
-    hipLaunchKernelGGL(g_reduce, dim3(1, w.ns), dim3(256), 0, st, w.part, G, K, w.ns, w.hn);
+    column_passes(a, G, j, w, st);
     hipLaunchKernelGGL(g_finish_column, dim3((w.ns + 255) / 256), dim3(256), 0, st, w.h1, w.h2,
                        w.hn, w.H, w.inv, m, w.ns, j);
     a.W = w.W;
