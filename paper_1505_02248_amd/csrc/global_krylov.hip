@@ -357,7 +357,7 @@ __global__ void g_check(const double* est, int ns, double tol, int* status) {
 
 int global_grid(int64_t total, int ns) {
   int64_t g = (total + 255) / 256;
-  if (g > 2048) g = 2048;
+  if (g > 1024) g = 1024;  // 4 workgroups per CU: each thread takes several points per reduction
   if (g < 1) g = 1;
   (void)ns;  // ns divides 256, so any grid keeps each thread on one state
   return (int)g;
