@@ -123,6 +123,20 @@ template <int K>
 __device__ __forceinline__ void block_partials(double (&v)[K], int cnt, int ns,
                                                double* part, double* red) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if constexpr (K <= 32) {
+    if (ns == 1) {
+      // one state: reduce-scatter the K values over the wave (lane l ends
+      // with the wave total of value l / (64 / K)), then add the 4 waves
+      const double r = wave_reduce_scatter<K>(v);
+      constexpr int LPV = 64 / K;
+      if (lane % LPV == 0) red[wv * K + lane / LPV] = r;
+      __syncthreads();
+      for (int q = tid; q < cnt; q += 256)
+        part[(int64_t)blockIdx.x * K + q] = red[q] + red[K + q] + red[2 * K + q] + red[3 * K + q];
+      __syncthreads();
+      return;
+    }
+  }
   for (int off = 32; off >= ns && off > 0; off >>= 1) {
 #pragma unroll
     for (int q = 0; q < K; ++q)

@@ -56,36 +56,6 @@ __host__ __device__ inline int64_t lds_layout(int NT, int m, int nloc, int aug, 
   return d;
 }
 
-// Butterfly reduce-scatter over the wave: K values per lane in, the wave
-// total of value (lane >> log2(64/K)) out.
-template <int K>
-__device__ __forceinline__ double wave_reduce_scatter(double (&v)[K]) {
-  const int lane = threadIdx.x & 63;
-  int c = K;
-#pragma unroll
-  for (int o = 32; o >= 64 / K; o >>= 1) {
-    const int half = c >> 1;
-    const bool upper = (lane & o) != 0;
-#pragma unroll
-    for (int i = 0; i < K / 2; ++i) {
-      if (i < half) {
-        double lo = v[i], hi = v[i + half];
-        // keep the selects on register values: folded into an indexed load of
-        // v they would demote the whole array to scratch memory
-        asm volatile("" : "+v"(lo), "+v"(hi));
-        const double send = upper ? lo : hi;
-        const double keep = upper ? hi : lo;
-        v[i] = keep + __shfl_xor(send, o, 64);
-      }
-    }
-    c = half;
-  }
-  double r = v[0];
-#pragma unroll
-  for (int o = 32 / K; o >= 1; o >>= 1) r += __shfl_xor(r, o, 64);
-  return r;
-}
-
 // Workgroup sum of cnt <= 32 values (held per thread in v[0..cnt)); after the
 // call every thread can read total(i) = sum_w red[w*32 + i].
 template <int NT>

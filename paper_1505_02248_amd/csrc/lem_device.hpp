@@ -96,6 +96,36 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Butterfly reduce-scatter over the wave: K values per lane in, the wave
+// total of value (lane >> log2(64/K)) out.
+template <int K>
+__device__ __forceinline__ double wave_reduce_scatter(double (&v)[K]) {
+  const int lane = threadIdx.x & 63;
+  int c = K;
+#pragma unroll
+  for (int o = 32; o >= 64 / K; o >>= 1) {
+    const int half = c >> 1;
+    const bool upper = (lane & o) != 0;
+#pragma unroll
+    for (int i = 0; i < K / 2; ++i) {
+      if (i < half) {
+        double lo = v[i], hi = v[i + half];
+        // keep the selects on register values: folded into an indexed load of
+        // v they would demote the whole array to scratch memory
+        asm volatile("" : "+v"(lo), "+v"(hi));
+        const double send = upper ? lo : hi;
+        const double keep = upper ? hi : lo;
+        v[i] = keep + __shfl_xor(send, o, 64);
+      }
+    }
+    c = half;
+  }
+  double r = v[0];
+#pragma unroll
+  for (int o = 32 / K; o >= 1; o >>= 1) r += __shfl_xor(r, o, 64);
+  return r;
+}
+
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
