@@ -103,10 +103,27 @@ def cpu_baseline(p, boxes, budget_s: float):
         if el >= budget_s or steps >= 200:
             break
     val = p.N * p.states.shape[1] * steps / el
-    return {"value": val, "unit": "DOF-steps/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{steps} full-grid LEM steps (256 blocks x 64 states, numpy float64 "
-                      f"GEMM per block), local expm {t_plan:.2f} s excluded",
-            "seconds": round(el, 3)}
+    out = {"value": val, "unit": "DOF-steps/s", "cores": int(cores), "kind": "oracle",
+           "sample": f"{steps} full-grid LEM steps (256 blocks x 64 states, numpy float64 "
+                     f"GEMM per block), local expm {t_plan:.2f} s excluded",
+           "seconds": round(el, 3)}
+    # the same steps with one BLAS thread (a quarter of the time budget)
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            s1 = 0
+            t0 = time.perf_counter()
+            while True:
+                u = olem.step(A, bx, p.ndim, p.n, u, cache)
+                s1 += 1
+                el1 = time.perf_counter() - t0
+                if el1 >= budget_s / 4 or s1 >= 50:
+                    break
+        out["value_1thread"] = p.N * p.states.shape[1] * s1 / el1
+        out["sample_1thread"] = f"{s1} steps, one BLAS thread"
+    except ImportError:
+        pass
+    return out
 
 
 def parse_args():
