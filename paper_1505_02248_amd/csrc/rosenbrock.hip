@@ -247,7 +247,30 @@ __device__ __forceinline__ void band_step(const double (&xs)[RS], double (&out)[
   }
 }
 
-template <int MP>
+// The same step when the box fills the tile (nl == MP): every row is live, the
+// diagonal of W is one scalar, row nl - 1 is the last row of segment 7, and
+// the identity term enters as an FMA with this thread's 0/1 diagonal mask em
+// (one at the row equal to its column) instead of a compare and two selects.
+template <int RS, int MP>
+__device__ __forceinline__ void band_step_full(const double (&xs)[RS], double (&out)[RS],
+                                               const double (&cl)[RS], double cd,
+                                               const double (&cu)[RS], const double (&em)[RS],
+                                               double* xch, int seg, int j, bool whole,
+                                               double cdiag) {
+  xch[seg * MP + j] = xs[0];
+  xch[(8 + seg) * MP + j] = xs[RS - 1];
+  __syncthreads();
+  const double prev = seg > 0 ? xch[(8 + seg - 1) * MP + j] : (whole ? xch[15 * MP + j] : 0.0);
+  const double next = seg < 7 ? xch[(seg + 1) * MP + j] : (whole ? xch[j] : 0.0);
+#pragma unroll
+  for (int m = 0; m < RS; ++m) {
+    const double up = m > 0 ? xs[m > 0 ? m - 1 : 0] : prev;
+    const double dn = m < RS - 1 ? xs[m < RS - 1 ? m + 1 : 0] : next;
+    out[m] = fma(cl[m], up, fma(cd, xs[m], fma(cu[m], dn, em[m] * cdiag)));
+  }
+}
+
+template <int MP, bool FULL>
 __global__ __launch_bounds__(8 * MP) void ere_phi1_kernel(const double* __restrict__ x,
                                                           const EreBox* boxes, int ns, int nl,
                                                           int rows, int n, double dt, double dx,
@@ -311,32 +334,39 @@ __global__ __launch_bounds__(8 * MP) void ere_phi1_kernel(const double* __restri
   }
   const double scale = ldexp(1.0, -sq);
   // this thread's rows of W = dt J_M / 2^s, in registers for the whole recursion
-  double cl[RS], cd[RS], cu[RS];
+  double cl[RS], cd[RS], cu[RS], em[RS];
 #pragma unroll
   for (int m = 0; m < RS; ++m) {
     cl[m] = wl[r0 + m] * scale;
     cd[m] = wd[r0 + m] * scale;
     cu[m] = wu[r0 + m] * scale;
+    em[m] = (r0 + m == j) ? 1.0 : 0.0;
   }
+  const double cd0 = cd[0];  // full tile: the one diagonal value of W
   const bool whole = b.whole != 0;
-  // Horner: F = I/(q+1)!, then F <- W F + I/(k+1)! for k = q-1 .. 0
+  auto step = [&](const double (&xs)[RS], double (&out)[RS], int par, double cdiag) {
+    if constexpr (FULL)
+      band_step_full<RS, MP>(xs, out, cl, cd0, cu, em, xch + par * 16 * MP, seg, j, whole, cdiag);
+    else
+      band_step<RS, MP>(xs, out, cl, cd, cu, xch + par * 16 * MP, lastrow + par * MP, r0, seg,
+                        j, nl, whole, cdiag);
+  };
+  // Horner: F = I/(q+1)!, then F <- W F + I/(k+1)! for k = q-1 .. 0, in pairs
+  // of steps (f -> g -> f) so that no copies are needed
+  static_assert(kPhiDeg % 2 == 0, "Horner steps are taken in pairs");
   double f[RS], g[RS];
 #pragma unroll
-  for (int m = 0; m < RS; ++m) f[m] = (r0 + m == j) ? kInvFact.c[kPhiDeg] : 0.0;
-  int par = 0;
-  for (int k = kPhiDeg - 1; k >= 0; --k) {
-    band_step<RS, MP>(f, g, cl, cd, cu, xch + par * 16 * MP, lastrow + par * MP, r0, seg, j, nl,
-                      whole, kInvFact.c[k]);
-#pragma unroll
-    for (int m = 0; m < RS; ++m) f[m] = g[m];
-    par ^= 1;
+  for (int m = 0; m < RS; ++m) f[m] = em[m] * kInvFact.c[kPhiDeg];
+  for (int k = kPhiDeg - 1; k >= 1; k -= 2) {
+    step(f, g, 0, kInvFact.c[k]);
+    step(g, f, 1, kInvFact.c[k - 1]);
   }
+  const int par = 0;
 #pragma unroll
   for (int m = 0; m < RS; ++m) F[(r0 + m) * ld + j] = f[m];
   if (sq > 0) {
     // E = I + W F
-    band_step<RS, MP>(f, g, cl, cd, cu, xch + par * 16 * MP, lastrow + par * MP, r0, seg, j, nl,
-                      whole, 1.0);
+    step(f, g, par, 1.0);
 #pragma unroll
     for (int m = 0; m < RS; ++m) E[(r0 + m) * ld + j] = g[m];
     __syncthreads();
@@ -384,22 +414,34 @@ __global__ __launch_bounds__(256) void ere_transpose_kernel(const double* __rest
   }
 }
 
-template <int MP>
-static hipError_t launch_phi1(const double* x, const void* boxes, int nb, int ns, int nl,
+template <int MP, bool FULL>
+static hipError_t launch_phi1_shape(const double* x, const void* boxes, int nb, int ns, int nl,
                               int rows, int n, double dt, double dx, double nu, double* P,
                               int* sq_out, int* status, hipStream_t st) {
   constexpr int NT = 8 * MP;
   const size_t lds = ((size_t)2 * MP * (MP + 1) + 3 * MP + 34 * MP + NT / 64) * sizeof(double);
   static bool attr = false;
   if (!attr) {
-    const hipError_t e = hipFuncSetAttribute((const void*)ere_phi1_kernel<MP>,
+    const hipError_t e = hipFuncSetAttribute((const void*)ere_phi1_kernel<MP, FULL>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL(ere_phi1_kernel<MP>, dim3((unsigned)(nb * ns)), dim3(NT), lds, st, x,
+  hipLaunchKernelGGL((ere_phi1_kernel<MP, FULL>), dim3((unsigned)(nb * ns)), dim3(NT), lds, st, x,
                      (const EreBox*)boxes, ns, nl, rows, n, dt, dx, nu, P, sq_out, status);
   return hipGetLastError();
+}
+
+// boxes that fill the tile (nl == MP) take the specialized Horner step
+template <int MP>
+static hipError_t launch_phi1(const double* x, const void* boxes, int nb, int ns, int nl,
+                              int rows, int n, double dt, double dx, double nu, double* P,
+                              int* sq_out, int* status, hipStream_t st) {
+  if (nl == MP)
+    return launch_phi1_shape<MP, true>(x, boxes, nb, ns, nl, rows, n, dt, dx, nu, P, sq_out,
+                                       status, st);
+  return launch_phi1_shape<MP, false>(x, boxes, nb, ns, nl, rows, n, dt, dx, nu, P, sq_out,
+                                      status, st);
 }
 
 static inline dim3 ere_grid(int64_t total) {

@@ -398,9 +398,12 @@ def _burgers_states(n, L, ns, seed):
 
 
 # boxes of 41 and 80 points and the 60-point whole grid take the one-launch
-# LDS phi_1 kernel; the 200-point whole grid takes the Pade pipeline
+# LDS phi_1 kernel (80-, 64-point boxes and the 64-point whole grid fill its
+# tile exactly: the specialized Horner step); the 200-point whole grid takes
+# the Pade pipeline
 @pytest.mark.parametrize("n,core,halo,refresh,ns", [(200, 25, 8, 5, 2), (200, 200, 0, 3, 2),
-                                                    (200, 50, 15, 5, 64), (60, 60, 0, 4, 3)])
+                                                    (200, 50, 15, 5, 64), (60, 60, 0, 4, 3),
+                                                    (64, 64, 0, 4, 3), (200, 40, 12, 5, 4)])
 def test_rosenbrock_lem_matches_oracle(n, core, halo, refresh, ns):
     L, nu = 10.0 * n / 200, 0.05
     dx = L / n
