@@ -120,7 +120,7 @@ def cpu_baseline(p, boxes, budget_s: float):
                 if el1 >= budget_s / 4 or s1 >= 50:
                     break
         out["value_1thread"] = p.N * p.states.shape[1] * s1 / el1
-        out["sample_1thread"] = f"{s1} steps, one BLAS thread"
+        out["sample_1thread"] = f"{s1} step{'s' if s1 > 1 else ''}, one BLAS thread"
     except ImportError:
         pass
     return out
