@@ -227,6 +227,35 @@ def test_global_krylov_variable_nu_vs_dense():
     assert rel_l2(got, ge.dense_step(W, p.states)) <= 1e-12
 
 
+# One state on whole-grid kernels (the single-state reduce-scatter of the
+# partial sums), on grids of 64 to 1024 workgroups, with and without forcing.
+@pytest.mark.parametrize("case", ["2d128", "2d256", "2d512", "1d16384", "forced2d128", "var96"])
+def test_global_whole_grid_one_state(case):
+    steps = 3
+    if case == "var96":
+        p = L.workload_2d_variable(n=96)
+        W = op.from_problem(p)
+        plan = lem.Plan(lem.Operator.from_problem(p), p.dt, method="global", krylov_tol=1e-14)
+        got = run(plan, p.states, 1)
+        assert rel_l2(got, ge.krylov_step(W, p.states, m=60, tol=1e-16)) <= 1e-11
+        return
+    if case == "1d16384":
+        p = L.workload_1d(n=16384, cfl=1.0)
+    else:
+        p = L.workload_2d_ensemble(n=int(case[-3:]), n_states=1)
+    W = op.from_problem(p)
+    if case == "forced2d128":
+        g = _forcing(p, 1, 8)
+        plan = lem.Plan(_forced_op(p, g), p.dt, method="global", krylov_tol=1e-14)
+        want = ge.fft_steps(W, p.states, steps, p.dt * g)
+    else:
+        plan = lem.Plan(lem.Operator.from_problem(p), p.dt, method="global", krylov_tol=1e-14)
+        want = ge.fft_steps(W, p.states, steps)
+    got = run(plan, p.states, steps)
+    assert rel_l2(got.reshape(want.shape), want) <= 1e-12
+    assert plan.query()["device_status"] == 0
+
+
 # ------------------------------------------------------------ step logic --
 
 def test_multi_step_equals_repeated_single_steps_bitwise():
