@@ -286,7 +286,9 @@ lem_status lem_plan_copy_krylov(lem_plan_t plan, int32_t* m, int32_t* substeps);
 lem_status lem_plan_copy_block(lem_plan_t plan, int32_t unique, double* out,
                                int32_t* rows, int32_t* cols);
 
-/* Free a plan and everything it owns (waits for its stream).  NULL is ok. */
+/* Free a plan and everything it owns.  Waits for the plan's stream and the
+ * side streams its Krylov steps fork onto; steps the caller enqueued on other
+ * streams must have completed.  NULL is ok. */
 lem_status lem_plan_destroy(lem_plan_t plan);
 
 /* ------------------------------------------------------------------------

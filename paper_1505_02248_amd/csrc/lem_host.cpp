@@ -376,7 +376,10 @@ struct lem_plan_s {
       hipGraphExecDestroy(g.second.second);
       hipGraphDestroy(g.second.first);
     }
-    for (hipStream_t s : side) hipStreamDestroy(s);
+    for (hipStream_t s : side) {  // the last step's side launches read plan memory
+      hipStreamSynchronize(s);
+      hipStreamDestroy(s);
+    }
     for (hipEvent_t e : ev_join) hipEventDestroy(e);
     if (ev_fork) hipEventDestroy(ev_fork);
     for (void* q : allocs) {
