@@ -982,6 +982,8 @@ hipError_t dense_apply(int precision, int cfg, const void* blocks, const void* E
                                                  {16, 32, 8}, {16, 32, 4}, {16, 16, 8}, {16, 32, 16}};
     if (cfg < 0 || cfg >= kApplyConfigs) return hipErrorInvalidValue;
     const int wm = shapes[cfg][0], nw = shapes[cfg][2];
+    // a live wave reads wm rows of E: the padded rows must be a multiple of wm
+    if (rows_p % wm != 0) return hipErrorInvalidValue;
     a.row_tiles = (rows_p + nw * wm - 1) / (nw * wm);
     const dim3 g(n_blocks * a.row_tiles * a.col_tiles), blk(64 * nw);
 #define LEM_APPLY(T)                                                                         \
@@ -1000,6 +1002,7 @@ hipError_t dense_apply(int precision, int cfg, const void* blocks, const void* E
     return hipGetLastError();
   }
   const int wm = (cfg & 1) ? 64 : 32;
+  if (rows_p % wm != 0) return hipErrorInvalidValue;
   a.row_tiles = (rows_p + 4 * wm - 1) / (4 * wm);
   const dim3 g(n_blocks * a.row_tiles * a.col_tiles);
   const size_t gl = (size_t)cols_p * sizeof(int64_t);  // gathered row offsets
