@@ -607,6 +607,15 @@ lem_status bucketize(std::vector<lem::KBlock>& kb, std::vector<lem_plan_s::Bucke
   std::vector<lem::KBlock> out;
   buckets.clear();
   int64_t voff = 0;
+  // costliest blocks first within a launch: workgroups are dispatched in
+  // order, so the cheap ones fill the last round instead of the long ones
+  // starting late (every block writes only its own core rows and slots)
+  for (auto& g : groups) {
+    std::vector<double> c(kb.size(), 0.0);
+    for (int i : g.second)
+      c[i] = block_cost(kb[i].ndim, kb[i].Lx * kb[i].Ly + kb[i].aug, kb[i].m, kb[i].nsub);
+    std::stable_sort(g.second.begin(), g.second.end(), [&](int x, int y) { return c[x] > c[y]; });
+  }
   for (auto& g : groups) {
     lem_plan_s::Bucket bk{g.first.variant, g.first.nt, g.first.pmax, g.first.vlds, 0,
                           (int)out.size(), (int)g.second.size()};
