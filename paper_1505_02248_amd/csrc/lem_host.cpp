@@ -2221,6 +2221,11 @@ lem_status lem_server_tick(lem_server_t s, int32_t* n_active, int32_t* n_queued)
     }
     size_t off = 0;
     for (auto& g : groups) {
+      // costliest blocks first (as in a plan's own launches)
+      std::stable_sort(g.second.begin(), g.second.end(), [](const lem::KBlock& x, const lem::KBlock& y) {
+        return block_cost(x.ndim, x.Lx * x.Ly + x.aug, x.m, x.nsub) >
+               block_cost(y.ndim, y.Lx * y.Ly + y.aug, y.m, y.nsub);
+      });
       std::memcpy(s->h_table + off, g.second.data(), g.second.size() * sizeof(lem::KBlock));
       off += g.second.size();
     }
