@@ -739,13 +739,28 @@ __global__ void apply_simple_kernel(ApplyArgs a, const double* core) {
     const int blk = (int)(t / a.rows);
     const DBlock b = a.blocks[blk];
     const double* Er = core + ((int64_t)b.unique * a.rows + row) * a.cols;
-    T acc = 0;
-    for (int l = 0; l < a.cols; ++l) {
-      const int64_t g = dense_gather(b, l, a.n, a.ndim);
-      acc = fma((T)Er[l], (T)a.x_in[g * a.ns + s], acc);
+    // eight independent partial sums: the eight gathered loads of a group are
+    // in flight together instead of one dependent load per term
+    constexpr int U = 8;
+    T acc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[u] = 0;
+    int l = 0;
+    for (; l + U <= a.cols; l += U) {
+      T ev[U], xv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        ev[u] = (T)Er[l + u];
+        xv[u] = (T)a.x_in[dense_gather(b, l + u, a.n, a.ndim) * a.ns + s];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc[u] = fma(ev[u], xv[u], acc[u]);
     }
+    for (; l < a.cols; ++l)
+      acc[0] = fma((T)Er[l], (T)a.x_in[dense_gather(b, l, a.n, a.ndim) * a.ns + s], acc[0]);
+    const T sum = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     const int64_t o = dense_scatter(b, row, a.n, a.ndim) * a.ns + s;
-    a.x_out[o] = (double)acc + (a.bias ? a.bias[o] : 0.0);
+    a.x_out[o] = (double)sum + (a.bias ? a.bias[o] : 0.0);
   }
 }
 
