@@ -726,41 +726,46 @@ __global__ __launch_bounds__(256) void apply_bf16_kernel(ApplyArgs a) {
     }
 }
 
-// Small ensembles (ns not a multiple of 64): one thread per (core row, state)
+// Small ensembles (ns not a multiple of 64): eight lanes per (core row, state)
 // with the plain row-major core block, float64 or float32 arithmetic.
 template <typename T>
 __global__ void apply_simple_kernel(ApplyArgs a, const double* core) {
-  const int64_t total = (int64_t)a.n_blocks * a.rows * a.ns;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
+  // LS lanes per output: lane p of a group takes the terms l = p, p + LS, ...
+  // with four independent partial sums, then the group adds its lanes (groups
+  // are aligned LS-lane slices of a wave, all active or all inactive)
+  constexpr int LS = 8;
+  const int64_t outputs = (int64_t)a.n_blocks * a.rows * a.ns;
+  for (int64_t tt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; tt < outputs * LS;
+       tt += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = tt / LS;
+    const int part = (int)(tt - e * LS);
     const int s = (int)(e % a.ns);
     const int64_t t = e / a.ns;
     const int row = (int)(t % a.rows);
     const int blk = (int)(t / a.rows);
     const DBlock b = a.blocks[blk];
     const double* Er = core + ((int64_t)b.unique * a.rows + row) * a.cols;
-    // eight independent partial sums: the eight gathered loads of a group are
-    // in flight together instead of one dependent load per term
-    constexpr int U = 8;
-    T acc[U];
+    T acc[4] = {0, 0, 0, 0};
+    int l = part;
+    for (; l + 3 * LS < a.cols; l += 4 * LS) {
+      T ev[4], xv[4];
 #pragma unroll
-    for (int u = 0; u < U; ++u) acc[u] = 0;
-    int l = 0;
-    for (; l + U <= a.cols; l += U) {
-      T ev[U], xv[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        ev[u] = (T)Er[l + u];
-        xv[u] = (T)a.x_in[dense_gather(b, l + u, a.n, a.ndim) * a.ns + s];
+      for (int u = 0; u < 4; ++u) {
+        ev[u] = (T)Er[l + u * LS];
+        xv[u] = (T)a.x_in[dense_gather(b, l + u * LS, a.n, a.ndim) * a.ns + s];
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) acc[u] = fma(ev[u], xv[u], acc[u]);
+      for (int u = 0; u < 4; ++u) acc[u] = fma(ev[u], xv[u], acc[u]);
     }
-    for (; l < a.cols; ++l)
+    for (; l < a.cols; l += LS)
       acc[0] = fma((T)Er[l], (T)a.x_in[dense_gather(b, l, a.n, a.ndim) * a.ns + s], acc[0]);
-    const T sum = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-    const int64_t o = dense_scatter(b, row, a.n, a.ndim) * a.ns + s;
-    a.x_out[o] = (double)sum + (a.bias ? a.bias[o] : 0.0);
+    T sum = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+#pragma unroll
+    for (int off = LS / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+    if (part == 0) {
+      const int64_t o = dense_scatter(b, row, a.n, a.ndim) * a.ns + s;
+      a.x_out[o] = (double)sum + (a.bias ? a.bias[o] : 0.0);
+    }
   }
 }
 
@@ -981,7 +986,7 @@ hipError_t dense_apply(int precision, int cfg, const void* blocks, const void* E
   a.n_blocks = n_blocks;
   if (ns % 64 != 0) {
     a.row_tiles = 1; a.col_tiles = 1;
-    const dim3 g = grid1((int64_t)n_blocks * rows * ns, 256, 65535);
+    const dim3 g = grid1((int64_t)n_blocks * rows * ns * 8, 256, 65535);  // 8 lanes per output
     if (precision == 0)
       hipLaunchKernelGGL(apply_simple_kernel<double>, g, dim3(256), 0, st, a, core);
     else if (precision == 1)
