@@ -503,6 +503,65 @@ def test_krylov_fourier_mode_happy_breakdown():
     assert np.abs(got - np.exp(lam) * v).max() < 1e-13
 
 
+def _dst_diffusion_box(mu, n=256, c=64, h=16):
+    """1D pure-diffusion box (C = 0): dt*A_M is symmetric tridiagonal Toeplitz
+    (-2mu, mu) with the DST-I eigenbasis."""
+    dx = 1.0 / n
+    dt = 4 * dx
+    W = op.weights(1, n, dx, dt, (0.0, 0.0), nu=mu * dx * dx / dt)
+    box = P.uniform_boxes(1, n, c, h)[1]
+    A = lem.local_matrix(op.sparse(W), P.gather_map(box, 1, n))
+    m = A.shape[0]
+    j = np.arange(1, m + 1)
+    lam = -2 * mu + 2 * mu * np.cos(j * np.pi / (m + 1))
+    Q = np.sqrt(2.0 / (m + 1)) * np.sin(np.outer(j, j) * np.pi / (m + 1))
+    return A, Q, lam
+
+
+@pytest.mark.parametrize("m,want_sub", [(12, 64), (24, 8), (40, 2)])
+def test_krylov_substeps_match_dst_closed_form(m, want_sub):
+    # ||dt A_M||_1 = 4 mu = 50: a Krylov space of dimension m cannot meet the
+    # tolerance in one step, so the action is taken as a product of equal
+    # sub-steps exp(A) = exp(A/k)^k (section 4.3 with Saad's estimate).  A
+    # sub-step that forgets to scale H, or miscounts the part of the step
+    # already done, misses the closed form by O(1).
+    A, Q, lam = _dst_diffusion_box(12.5)
+    assert abs(np.abs(A).sum(axis=0).max() - 50.0) < 1e-12
+    v = np.random.default_rng(3).standard_normal(A.shape[0])
+    closed = Q @ (np.exp(lam) * (Q @ v))
+    got, info = K.expv(lambda x: A @ x, v, m=m, tol=1e-14, return_info=True)
+    assert info["substeps"] == want_sub
+    assert rel_l2(got, closed) <= 1e-13
+    # the same sub-steps taken by hand from the closed form of each fraction
+    part = v.copy()
+    for _ in range(want_sub):
+        part = Q @ (np.exp(lam / want_sub) * (Q @ part))
+    assert rel_l2(got, part) <= 1e-13
+
+
+def test_krylov_substeps_variable_nu_box_match_dense_pade():
+    # nonsymmetric 2D box (lognormal nu, advection (1, 0.5)) with a norm that
+    # needs several sub-steps at m = 20 and 30; reference: the dense Pade
+    # exponential (pinned against exact rational Taylor series and the DST
+    # closed form above) and, independently, SciPy's expm
+    n = 64
+    dx = 1.0 / n
+    nuf = L.lognormal_field_2d(n, 2) * 4.0
+    W = op.weights(2, n, dx, 2 * dx, (1.0, 0.5), nu_field=nuf)
+    box = P.uniform_boxes(2, n, 16, 4)[5]
+    A = lem.local_matrix(op.sparse(W), P.gather_map(box, 2, n))
+    v = np.random.default_rng(4).standard_normal(A.shape[0])
+    ref = E.expm(A) @ v
+    assert rel_l2(ref, sla.expm(A) @ v) <= 1e-13
+    subs = []
+    for m in (20, 30):
+        got, info = K.expv(lambda x: A @ x, v, m=m, tol=1e-14, return_info=True)
+        subs.append(info["substeps"])
+        assert info["substeps"] > 1
+        assert rel_l2(got, ref) <= 1e-13
+    assert subs[0] > subs[1]  # a larger space takes fewer sub-steps
+
+
 def test_global_krylov_matches_fft_2d():
     q = L.workload_2d_ensemble(n=64, n_states=2)
     W = op.from_problem(q)
