@@ -29,7 +29,9 @@
  *    lem_plan_destroy.  Host arrays passed in are copied during the call.
  *  - Device-side failures (Krylov estimate above tolerance, non-finite
  *    values) are latched in the plan's status word; they are reported by
- *    lem_plan_query (field device_status) after the stream has drained.
+ *    lem_plan_query (field device_status: LEM_ERR_NOT_CONVERGED or
+ *    LEM_ERR_NONFINITE, the latter taking precedence) after the stream has
+ *    drained.  The word stays latched for the life of the plan.
  *  - A plan is not thread-safe: do not call lem_step on one plan from two
  *    threads at once, nor enqueue two steps of one plan on different streams.
  */
@@ -51,7 +53,8 @@ typedef enum {
   LEM_ERR_NOT_CONVERGED = 4,  /* Krylov estimate above tolerance              */
   LEM_ERR_BUDGET = 5,         /* request does not fit the memory budget       */
   LEM_ERR_UNSUPPORTED = 6,    /* valid but not implemented combination        */
-  LEM_ERR_NOT_FOUND = 7       /* unknown request id                           */
+  LEM_ERR_NOT_FOUND = 7,      /* unknown request id                           */
+  LEM_ERR_NONFINITE = 8       /* a step produced non-finite values (NaN/Inf)  */
 } lem_status;
 
 /* Algorithm for the stored local exponentials (dense method, plan time). */
@@ -145,6 +148,15 @@ typedef struct {
                             columns only, the periodic coupling along the
                             columns kept inside every box; exported boxes
                             then read (ox, 0, core, n, h)                   */
+  int32_t tile;          /* dense method, n_states % 64 == 0: launch shape of
+                            the apply; -1 = the default shape (or the
+                            fastest one when autotune is set), 0..7 = that
+                            shape for FP64/FP32 (rows per wave, K chunk,
+                            waves: 32,16,4 / 32,32,4 / 32,32,8 / 64,32,4 /
+                            16,32,8 / 16,32,4 / 16,16,8 / 16,32,16), 0..1
+                            for split bf16 (32 or 64 rows per wave); a shape
+                            that does not fit the block is LEM_ERR_UNSUPPORTED
+                            at plan time                                    */
 } lem_options;
 
 typedef struct {
@@ -171,7 +183,7 @@ typedef struct lem_plan_s* lem_plan_t;
 
 /* Fill *opt with defaults: Krylov, FP64, one state, core 64 (1D) / 32 (2D),
  * decay-bound halo in [4, 64] at tol 1e-8, calibrated m <= 30 at tol 1e-13,
- * up to 64 sub-steps, no graph, no autotune. */
+ * up to 64 sub-steps, no graph, no autotune, default apply shape (tile -1). */
 void lem_options_default(lem_options* opt);
 
 /* Build a plan for steps of size dt of the operator *op (section 3).
@@ -258,8 +270,12 @@ lem_status lem_schrodinger_plan(const lem_schrodinger* op, double dt, int32_t n_
 
 /* y = exp(t A) x on the whole grid (no decomposition) by the Krylov method
  * of section 4.3, for n_states ensemble members (with op->forcing set:
- * y = exp(t A) x + phi_1(t A)(t g)); device arrays, may not overlap.  Allocates and frees its own work space (a plan with
- * LEM_METHOD_GLOBAL avoids that for repeated use).  Synchronous. */
+ * y = exp(t A) x + phi_1(t A)(t g)); device arrays, may not overlap.
+ * Allocates and frees its own work space (a plan with LEM_METHOD_GLOBAL
+ * avoids that for repeated use).  Synchronous.  Returns
+ * LEM_ERR_NOT_CONVERGED when the Krylov estimate stayed above tol and
+ * LEM_ERR_NONFINITE when the result holds NaN or Inf (y is written either
+ * way). */
 lem_status lem_global_expmv(const lem_operator* op, double t, const double* x,
                             double* y, int32_t n_states, double tol,
                             int32_t m_max, void* stream);
@@ -325,6 +341,10 @@ typedef struct {
                             a finished request returns its initial state     */
 } lem_server_options;
 
+/* A request whose step latched a device-side failure (non-finite values or a
+ * Krylov estimate above tolerance) is retired as LEM_REQ_FAILED with error
+ * LEM_ERR_NONFINITE or LEM_ERR_NOT_CONVERGED at the end of that tick; every
+ * request has its own status word, so the others are not affected. */
 typedef struct {
   int32_t state;         /* LEM_REQ_*                                          */
   int32_t method;        /* LEM_METHOD_KRYLOV or LEM_METHOD_GLOBAL             */

@@ -26,7 +26,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "lem.h")
 LEM_OK = 0
 STATUS_NAMES = {0: "LEM_OK", 1: "LEM_ERR_INVALID", 2: "LEM_ERR_NOMEM", 3: "LEM_ERR_HIP",
                 4: "LEM_ERR_NOT_CONVERGED", 5: "LEM_ERR_BUDGET", 6: "LEM_ERR_UNSUPPORTED",
-                7: "LEM_ERR_NOT_FOUND"}
+                7: "LEM_ERR_NOT_FOUND", 8: "LEM_ERR_NONFINITE"}
 METHODS = {"krylov": 0, "dense": 1, "global": 2}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x2": 2, "bf16x3": 3}
 
@@ -54,7 +54,7 @@ class _Options(ctypes.Structure):
                 ("max_substeps", ctypes.c_int32), ("krylov_tol", ctypes.c_double),
                 ("use_graph", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("dry_run", ctypes.c_int32), ("expm", ctypes.c_int32),
-                ("columns", ctypes.c_int32)]
+                ("columns", ctypes.c_int32), ("tile", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -198,7 +198,7 @@ class Plan:
                  halo_tol: float = 1e-8, krylov_m: int = 0, krylov_m_max: int = 30,
                  max_substeps: int = 64, krylov_tol: float = 1e-13,
                  use_graph: bool = False, autotune: bool = False, dry_run: bool = False,
-                 columns: bool = False, expm: str = "pade", stream=None):
+                 columns: bool = False, expm: str = "pade", tile: int = -1, stream=None):
         lib = load()
         o = _Options()
         lib.lem_options_default(ctypes.byref(o))
@@ -210,6 +210,7 @@ class Plan:
         o.krylov_tol = krylov_tol
         o.use_graph, o.autotune, o.dry_run = int(use_graph), int(autotune), int(dry_run)
         o.columns = int(columns)
+        o.tile = int(tile)
         o.expm = {"pade": 0, "taylor": 1}[expm]
         self.op, self.dt, self.n_states, self.method = op, float(dt), int(n_states), method
         if op.forcing is not None and op.forcing.size != op.N * int(n_states):

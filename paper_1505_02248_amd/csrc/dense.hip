@@ -368,7 +368,13 @@ struct ApplyArgs {
   const __bf16* xp;     // split-bf16 apply: the state split into pieces once per
                         // step, interleaved per entry (2 pieces: hi, mid; 3 pieces:
                         // hi, mid, lo, 0 -- 4 or 8 bytes per entry), or null
+  int* status;          // latched status bits (non-finite outputs), or null
 };
+
+// Latches kStatusNonFinite when this lane wrote a non-finite value.
+__device__ __forceinline__ void latch_nonfinite(bool bad, int* status) {
+  if (bad && status) atomicOr(status, kStatusNonFinite);
+}
 
 __device__ __forceinline__ int64_t dense_gather(const DBlock& b, int l, int n, int ndim) {
   const int ly = l / b.Lx, lx = l - ly * b.Lx;
@@ -516,6 +522,7 @@ __global__ __launch_bounds__(64 * NW) void apply_mfma_kernel(ApplyArgs a) {
   if (c < nchunks) step(c, a0, a1, Xs0, Xs1, x0, x1);
 
   if (!wave_live) return;
+  bool bad = false;
 #pragma unroll
   for (int i = 0; i < RT; ++i)
 #pragma unroll
@@ -527,14 +534,14 @@ __global__ __launch_bounds__(64 * NW) void apply_mfma_kernel(ApplyArgs a) {
       const int64_t g = dense_scatter(b, row, a.n, a.ndim);
       const int64_t o = g * a.ns + col0 + (lane & 15) * 4;
       double* dst = a.x_out + o;
-      if (a.bias) {
 #pragma unroll
-        for (int j = 0; j < CT; ++j) dst[j] = (double)acc[i][j][r] + a.bias[o + j];
-      } else {
-#pragma unroll
-        for (int j = 0; j < CT; ++j) dst[j] = (double)acc[i][j][r];
+      for (int j = 0; j < CT; ++j) {
+        const double v = (double)acc[i][j][r] + (a.bias ? a.bias[o + j] : 0.0);
+        bad |= !isfinite(v);
+        dst[j] = v;
       }
     }
+  latch_nonfinite(bad, a.status);
 }
 
 // Split-bf16 apply: E = E_hi + E_mid + E_lo and X = X_hi + X_mid + X_lo are
@@ -711,6 +718,7 @@ __global__ __launch_bounds__(256) void apply_bf16_kernel(ApplyArgs a) {
   if (c < ksteps) step(c, ea0, ea1);
 
   if (!wave_live) return;
+  bool bad = false;
 #pragma unroll
   for (int i = 0; i < RT; ++i)
 #pragma unroll
@@ -721,9 +729,13 @@ __global__ __launch_bounds__(256) void apply_bf16_kernel(ApplyArgs a) {
       const int64_t o = g * a.ns + col0 + (lane & 15);
       double* dst = a.x_out + o;
 #pragma unroll
-      for (int j = 0; j < CT; ++j)
-        dst[j * 16] = (double)acc[i][j][r] + (a.bias ? a.bias[o + j * 16] : 0.0);
+      for (int j = 0; j < CT; ++j) {
+        const double v = (double)acc[i][j][r] + (a.bias ? a.bias[o + j * 16] : 0.0);
+        bad |= !isfinite(v);
+        dst[j * 16] = v;
+      }
     }
+  latch_nonfinite(bad, a.status);
 }
 
 // Small ensembles (ns not a multiple of 64): eight lanes per (core row, state)
@@ -764,7 +776,9 @@ __global__ void apply_simple_kernel(ApplyArgs a, const double* core) {
     for (int off = LS / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
     if (part == 0) {
       const int64_t o = dense_scatter(b, row, a.n, a.ndim) * a.ns + s;
-      a.x_out[o] = (double)sum + (a.bias ? a.bias[o] : 0.0);
+      const double v = (double)sum + (a.bias ? a.bias[o] : 0.0);
+      if (!isfinite(v) && a.status) atomicOr(a.status, kStatusNonFinite);
+      a.x_out[o] = v;
     }
   }
 }
@@ -971,13 +985,32 @@ void dense_block_fill(void* dst, int i, int ox, int oy, int cx, int cy, int h, i
   d->unique = unique;
 }
 
+// tile shapes of the FP64/FP32 apply (rows per wave, K chunk, waves per workgroup)
+static const int kApplyShapes[kApplyConfigs][3] = {{32, 16, 4}, {32, 32, 4}, {32, 32, 8},
+                                                   {64, 32, 4}, {16, 32, 8}, {16, 32, 4},
+                                                   {16, 16, 8}, {16, 32, 16}};
+
+bool dense_apply_supported(int precision, int cfg, int ns, int rows_p, int cols_p) {
+  if (ns % 64 != 0) return precision == 0 || precision == 1;  // small-ensemble kernel
+  if (precision == 0 || precision == 1) {
+    if (cfg < 0 || cfg >= kApplyConfigs) return false;
+    // a live wave reads wm rows of E: the padded rows must be a multiple of wm
+    return rows_p % kApplyShapes[cfg][0] == 0 && cols_p % kApplyShapes[cfg][1] == 0;
+  }
+  if (precision != 2 && precision != 3) return false;
+  if (cfg < 0 || cfg > 1) return false;
+  const int wm = cfg ? 64 : 32;
+  return rows_p % wm == 0 && cols_p % 32 == 0 && (size_t)cols_p * sizeof(int64_t) <= 64 * 1024;
+}
+
 hipError_t dense_apply(int precision, int cfg, const void* blocks, const void* E,
                        int64_t e_stride, const double* core, const double* x_in,
                        double* x_out, int n, int ndim, int ns, int rows, int rows_p,
-                       int cols, int cols_p, int n_blocks, const double* bias, hipStream_t st,
-                       const void* xpieces, int64_t n_points) {
+                       int cols, int cols_p, int n_blocks, const double* bias, int* status,
+                       hipStream_t st, const void* xpieces, int64_t n_points) {
   ApplyArgs a;
   a.bias = bias;
+  a.status = status;
   a.xp = nullptr;
   (void)n_points;
   a.blocks = (const DBlock*)blocks; a.E = E; a.e_stride = e_stride;
@@ -996,14 +1029,9 @@ hipError_t dense_apply(int precision, int cfg, const void* blocks, const void* E
     return hipGetLastError();
   }
   a.col_tiles = ns / 64;
+  if (!dense_apply_supported(precision, cfg, ns, rows_p, cols_p)) return hipErrorInvalidValue;
   if (precision == 0 || precision == 1) {
-    // tile shapes (rows per wave, K chunk, waves per workgroup)
-    static const int shapes[kApplyConfigs][3] = {{32, 16, 4}, {32, 32, 4}, {32, 32, 8}, {64, 32, 4},
-                                                 {16, 32, 8}, {16, 32, 4}, {16, 16, 8}, {16, 32, 16}};
-    if (cfg < 0 || cfg >= kApplyConfigs) return hipErrorInvalidValue;
-    const int wm = shapes[cfg][0], nw = shapes[cfg][2];
-    // a live wave reads wm rows of E: the padded rows must be a multiple of wm
-    if (rows_p % wm != 0) return hipErrorInvalidValue;
+    const int wm = kApplyShapes[cfg][0], nw = kApplyShapes[cfg][2];
     a.row_tiles = (rows_p + nw * wm - 1) / (nw * wm);
     const dim3 g(n_blocks * a.row_tiles * a.col_tiles), blk(64 * nw);
 #define LEM_APPLY(T)                                                                         \
@@ -1022,11 +1050,9 @@ hipError_t dense_apply(int precision, int cfg, const void* blocks, const void* E
     return hipGetLastError();
   }
   const int wm = (cfg & 1) ? 64 : 32;
-  if (rows_p % wm != 0) return hipErrorInvalidValue;
   a.row_tiles = (rows_p + 4 * wm - 1) / (4 * wm);
   const dim3 g(n_blocks * a.row_tiles * a.col_tiles);
   const size_t gl = (size_t)cols_p * sizeof(int64_t);  // gathered row offsets
-  if (gl > 64 * 1024) return hipErrorInvalidValue;
   if (xpieces) a.xp = (const __bf16*)xpieces;  // split by dense_split_pieces
 #define LEM_BF16(NT_, WM_)                                                                     \
   if (a.xp) hipLaunchKernelGGL((apply_bf16_kernel<NT_, WM_, true>), g, dim3(256), gl, st, a); \

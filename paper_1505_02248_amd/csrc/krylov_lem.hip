@@ -883,10 +883,11 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
     if (!isfinite(cur[p])) bad = true;
     x_out[b.x_off + g * b.ns + s] = cur[p];
   }
-  if (bad) atomicOr(a.status, kStatusNonFinite);
+  int* status = b.status ? b.status : a.status;
+  if (bad) atomicOr(status, kStatusNonFinite);
   if (tid == 0) {
     a.diag[(int64_t)b.diag * b.ns + s] = worst;
-    if (!(worst <= b.tol)) atomicOr(a.status, kStatusNotConverged);
+    if (!(worst <= b.tol)) atomicOr(status, isfinite(worst) ? kStatusNotConverged : kStatusNonFinite);
   }
 }
 

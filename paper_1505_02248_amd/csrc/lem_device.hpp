@@ -58,6 +58,7 @@ struct KBlock {
   double* xout;
   const double* coef;
   double* vwork;
+  int* status;                // status word of this block's problem, or null
 };
 
 struct KrylovArgs {

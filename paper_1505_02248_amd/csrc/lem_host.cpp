@@ -17,6 +17,7 @@
 
 #include "arena.h"
 #include "lem.h"
+#include "lem_internal.h"
 #include "lem_launch.h"
 
 namespace {
@@ -1027,7 +1028,7 @@ lem_status dense_forcing_term(lem_plan_s* p, const void* d_ops, const double* ho
   LEM_TRY(dalloc(p, &p->d_bias, tot, &p->bytes_work));
   LEM_HIP(lem::dense_apply(LEM_FP64, 0, p->d_db, e64, (int64_t)es, core, dtg, p->d_bias, op.n,
                            op.ndim, p->ns, p->rows, p->rows_p, p->cols, p->cols_p,
-                           (int)p->boxes.size(), nullptr, st));
+                           (int)p->boxes.size(), nullptr, nullptr, st));
   LEM_HIP(hipStreamSynchronize(st));
   for (void* q : {(void*)Phi, (void*)e64, (void*)e32, (void*)e16, (void*)core, (void*)dtg})
     dfree(p, q);
@@ -1325,7 +1326,8 @@ lem_status run_one(lem_plan_s* p, const double* src, double* dst, hipStream_t st
                                         p->d_xp, st));
       LEM_HIP(lem::dense_apply(p->opt.precision, p->tile, p->d_db, dense_operand(p), es, p->d_core,
                                src, dst, p->op.n, p->op.ndim, p->ns, p->rows, p->rows_p, p->cols,
-                               p->cols_p, (int)p->boxes.size(), p->d_bias, st, p->d_xp, p->N));
+                               p->cols_p, (int)p->boxes.size(), p->d_bias, p->d_status, st,
+                               p->d_xp, p->N));
       return LEM_OK;
     }
     default:
@@ -1357,7 +1359,12 @@ lem_status run_step(lem_plan_s* p, const double* src, double* dst, hipStream_t s
   return LEM_OK;
 }
 
-// Times the dense apply at both launch shapes on a scratch state; keeps the faster.
+// Launch shape of the dense apply: the caller's (opt.tile >= 0, checked
+// against the block), else the fastest one timed at plan time (autotune),
+// else the plan's default.
+lem_status choose_tile(lem_plan_s* p, hipStream_t st);
+
+// Times the dense apply at every launch shape on a scratch state; keeps the fastest.
 lem_status autotune_dense(lem_plan_s* p, hipStream_t st) {
   const int64_t tot = p->N * p->ns;
   double *a, *b;
@@ -1371,9 +1378,8 @@ lem_status autotune_dense(lem_plan_s* p, hipStream_t st) {
   int besttile = p->tile;
   const int ntile = p->opt.precision <= LEM_FP32 ? lem::kApplyConfigs : 2;
   for (int tile = 0; tile < ntile; ++tile) {
+    if (!lem::dense_apply_supported(p->opt.precision, tile, p->ns, p->rows_p, p->cols_p)) continue;
     p->tile = tile;
-    // shapes whose rows per wave do not divide the padded rows are refused
-    // by the apply before anything is enqueued: skip them
     if (run_one(p, a, b, st) != LEM_OK) continue;
     LEM_HIP(hipEventRecord(e0, st));
     for (int r = 0; r < 5; ++r) LEM_TRY(run_one(p, a, b, st));
@@ -1388,6 +1394,20 @@ lem_status autotune_dense(lem_plan_s* p, hipStream_t st) {
   hipEventDestroy(e1);
   dfree(p, a);
   dfree(p, b);
+  // the timing runs wrote the plan's status word: start clean
+  LEM_HIP(hipMemsetAsync(p->d_status, 0, sizeof(int), st));
+  return LEM_OK;
+}
+
+lem_status choose_tile(lem_plan_s* p, hipStream_t st) {
+  if (p->opt.tile >= 0) {
+    if (!lem::dense_apply_supported(p->opt.precision, p->opt.tile, p->ns, p->rows_p, p->cols_p))
+      return fail(LEM_ERR_UNSUPPORTED, "apply tile shape " + std::to_string(p->opt.tile) +
+                                           " does not fit this block and precision");
+    p->tile = p->opt.tile;
+    return LEM_OK;
+  }
+  if (p->opt.autotune && p->ns % 64 == 0) return autotune_dense(p, st);
   return LEM_OK;
 }
 
@@ -1410,6 +1430,8 @@ lem_status check_options(const lem_options* o) {
     return fail(LEM_ERR_INVALID, "unknown local exponential algorithm");
   if (o->columns && (o->method != LEM_METHOD_KRYLOV || o->core <= 0))
     return fail(LEM_ERR_UNSUPPORTED, "column-wise cores need the Krylov method and a core width");
+  if (o->tile < -1 || o->tile >= lem::kApplyConfigs)
+    return fail(LEM_ERR_INVALID, "tile must be -1 or a shape id in [0, 7]");
   return LEM_OK;
 }
 
@@ -1443,6 +1465,13 @@ bool overlap(const void* a, const void* b, size_t bytes) {
   const char* x = (const char*)a;
   const char* y = (const char*)b;
   return x < y + bytes && y < x + bytes;
+}
+
+// lem_status of latched device status bits (non-finite values first).
+int device_status_of(int bits) {
+  return (bits & lem::kStatusNonFinite)     ? LEM_ERR_NONFINITE
+         : (bits & lem::kStatusNotConverged) ? LEM_ERR_NOT_CONVERGED
+                                             : LEM_OK;
 }
 
 lem_status create_plan(const lem_operator* op, double dt, const lem_options* opt, void* stream,
@@ -1512,8 +1541,8 @@ lem_status create_plan(const lem_operator* op, double dt, const lem_options* opt
     else if (p->method == LEM_METHOD_DENSE) s = plan_dense(p, st, op->forcing);
     else s = plan_global(p, st);
     if (s != LEM_OK) return guard(s);
-    if (p->method == LEM_METHOD_DENSE && opt->autotune && p->ns % 64 == 0) {
-      s = autotune_dense(p, st);
+    if (p->method == LEM_METHOD_DENSE) {
+      s = choose_tile(p, st);
       if (s != LEM_OK) return guard(s);
     }
     if (hipStreamSynchronize(st) != hipSuccess)
@@ -1528,6 +1557,64 @@ lem_status create_plan(const lem_operator* op, double dt, const lem_options* opt
 }
 
 }  // namespace
+
+namespace lem {
+
+lem_status set_error(lem_status s, const char* msg) { return fail(s, msg); }
+
+lem_status global_expmv_in(const lem_operator* op, double t, const double* x, double* y,
+                           int32_t n_states, double tol, int32_t m_max, void* stream,
+                           Arena* arena) {
+  if (!op || !x || !y) return fail(LEM_ERR_INVALID, "NULL argument");
+  lem_options o;
+  lem_options_default(&o);
+  o.method = LEM_METHOD_GLOBAL;
+  o.n_states = n_states;
+  o.krylov_tol = tol;
+  o.krylov_m_max = m_max;
+  lem_plan_t p = nullptr;
+  LEM_TRY(create_plan(op, t, &o, stream, arena, &p));
+  const size_t bytes = (size_t)p->N * p->ns * sizeof(double);
+  if (overlap(x, y, bytes)) {
+    delete p;
+    return fail(LEM_ERR_INVALID, "x and y overlap");
+  }
+  hipStream_t st = (hipStream_t)stream;
+  p->stream = st;
+  lem_status s = run_one(p, x, y, st);
+  if (s == LEM_OK && hipStreamSynchronize(st) != hipSuccess)
+    s = fail(LEM_ERR_HIP, "synchronization failed");
+  int bits = 0;
+  if (s == LEM_OK && hipMemcpy(&bits, p->d_status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+    s = fail(LEM_ERR_HIP, "status copy failed");
+  delete p;  // returns its memory (to the arena when one is given)
+  if (s == LEM_OK && bits)
+    s = fail((lem_status)device_status_of(bits), device_status_of(bits) == LEM_ERR_NONFINITE
+                                                     ? "non-finite values in the global Krylov action"
+                                                     : "global Krylov estimate above tolerance");
+  return s;
+}
+
+size_t global_expmv_bound(const lem_operator* op, int32_t n_states, int32_t m_max) {
+  const int64_t N = op->ndim == 1 ? (int64_t)op->n : (int64_t)op->n * op->n;
+  const bool forced = op->forcing != nullptr;
+  const bool variable = op->nu_field != nullptr || op->vel_faces != nullptr;
+  const int64_t ns = std::max(n_states, 1);
+  const int64_t mc = std::min(std::max(m_max, 4), kMaxKrylov);
+  const int64_t K = kMaxKrylov + 1;
+  const int64_t Na = N + (forced ? 1 : 0), tot = Na * ns;
+  // persistent: status word, face coefficients, forcing
+  const int64_t keep = 1 + (variable ? 4 * N : 0) + (forced ? N * ns : 0);
+  // calibration (one state, dimension mc) and the step (n_states, dimension
+  // <= mc) are never allocated at once
+  const int64_t calib = (mc + 3) * Na + (int64_t)global_part_doubles(global_grid(N, 1), 1) +
+                        3 * K + 2 * (mc + 1) * mc + 8 * mc + N + 16;
+  const int64_t step = (mc + 3) * tot + (int64_t)global_part_doubles(global_grid(tot, ns), (int)ns) +
+                       3 * K * ns + ns * (mc + 1) * mc + ns * mc + 4 * ns + (forced ? 2 * tot : 0);
+  return (size_t)(keep + std::max(calib, step)) * sizeof(double) + 64 * 256;
+}
+
+}  // namespace lem
 
 // ================================================================ C ABI ====
 extern "C" {
@@ -1550,6 +1637,7 @@ void lem_options_default(lem_options* o) {
   o->use_graph = 0;
   o->autotune = 0;
   o->dry_run = 0;
+  o->tile = -1;
 }
 
 lem_status lem_plan(const lem_operator* op, double dt, const lem_options* opt, void* stream,
@@ -1754,7 +1842,8 @@ lem_status lem_schrodinger_plan(const lem_schrodinger* op, double dt, int32_t n_
   }
   if (s == LEM_OK) s = upload(p->d_db, db.data(), db.size(), st);
   p->tile = 0;
-  if (s == LEM_OK && autotune && p->ns % 64 == 0) s = autotune_dense(p, st);
+  p->opt.autotune = autotune ? 1 : 0;
+  if (s == LEM_OK) s = choose_tile(p, st);
   if (s == LEM_OK && hipStreamSynchronize(st) != hipSuccess)
     s = fail(LEM_ERR_HIP, "plan synchronization failed");
   if (s != LEM_OK) return guard(s);
@@ -1765,24 +1854,7 @@ lem_status lem_schrodinger_plan(const lem_schrodinger* op, double dt, int32_t n_
 
 lem_status lem_global_expmv(const lem_operator* op, double t, const double* x, double* y,
                             int32_t n_states, double tol, int32_t m_max, void* stream) {
-  lem_options o;
-  lem_options_default(&o);
-  o.method = LEM_METHOD_GLOBAL;
-  o.n_states = n_states;
-  o.krylov_tol = tol;
-  o.krylov_m_max = m_max;
-  lem_plan_t p = nullptr;
-  LEM_TRY(lem_plan(op, t, &o, stream, &p));
-  lem_status s = lem_step(p, x, y, 1, stream);
-  if (s == LEM_OK && hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
-    s = fail(LEM_ERR_HIP, "synchronization failed");
-  int st = 0;
-  if (s == LEM_OK && hipMemcpy(&st, p->d_status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
-    s = fail(LEM_ERR_HIP, "status copy failed");
-  lem_plan_destroy(p);
-  if (s == LEM_OK && st)
-    s = fail(LEM_ERR_NOT_CONVERGED, "global Krylov estimate above tolerance or non-finite values");
-  return s;
+  return lem::global_expmv_in(op, t, x, y, n_states, tol, m_max, stream, nullptr);
 }
 
 lem_status lem_plan_query(lem_plan_t p, lem_plan_info* info) {
@@ -1792,8 +1864,7 @@ lem_status lem_plan_query(lem_plan_t p, lem_plan_info* info) {
   LEM_HIP(hipStreamSynchronize(p->stream));
   int st = 0;
   LEM_HIP(hipMemcpy(&st, p->d_status, sizeof(int), hipMemcpyDeviceToHost));
-  info->device_status = (st & lem::kStatusNonFinite) ? LEM_ERR_NOT_CONVERGED
-                        : (st & lem::kStatusNotConverged) ? LEM_ERR_NOT_CONVERGED : 0;
+  info->device_status = device_status_of(st);
   if (p->ere_small && p->ere_count > 0) {  // doublings taken at the last refresh
     std::vector<int> sq(p->boxes.size() * p->ns);
     LEM_HIP(hipMemcpy(sq.data(), p->d_ere_s, sq.size() * sizeof(int), hipMemcpyDeviceToHost));
@@ -1903,6 +1974,7 @@ struct ServerReq {
   int64_t bytes = 0;
   double t_submit = 0, t_admit = 0, t_done = 0;
   lem_status error = LEM_OK;
+  int slot = -1;  // index of this request's status word while active
   int64_t N() const { return op.ndim == 1 ? (int64_t)op.n : (int64_t)op.n * op.n; }
 };
 
@@ -1928,7 +2000,10 @@ struct lem_server_s {
   lem::KBlock* d_table = nullptr;
   lem::KBlock* h_table = nullptr;
   double* d_diag = nullptr;
-  int* d_status = nullptr;
+  // one status word per active request (slot), so that a failure latched by
+  // one request's kernels is attributed to that request alone
+  int* d_rstatus = nullptr;
+  std::vector<int> h_rstatus, free_slots;
   size_t cap = 0;
   int64_t ticks = 0;
   double dof_steps = 0;
@@ -1945,7 +2020,7 @@ struct lem_server_s {
       hipFree(pool);
       hipFree(d_table);
       hipFree(d_diag);
-      hipFree(d_status);
+      hipFree(d_rstatus);
       hipHostFree(h_table);
       for (int k = 0; k < kSide; ++k) {
         if (side[k]) hipStreamDestroy(side[k]);
@@ -2006,6 +2081,8 @@ void choose_partition(const lem_server_s* s, ServerReq& r, const Op& op) {
   }
 }
 
+void server_release(lem_server_s* s, ServerReq& r);
+
 // Admission of the queue head; LEM_ERR_BUDGET leaves it queued.
 lem_status server_admit(lem_server_s* s, ServerReq& r) {
   Op op;
@@ -2051,10 +2128,24 @@ lem_status server_admit(lem_server_s* s, ServerReq& r) {
   r.bytes = (int64_t)(s->arena->in_use() - before);
   r.state = LEM_REQ_ACTIVE;
   r.t_admit = s->now_ms();
+  if (!s->opt.dry_run) {
+    // the request's kernels latch into its own slot (the global method's
+    // graph, captured at its first step, takes this pointer)
+    r.slot = s->free_slots.back();
+    s->free_slots.pop_back();
+    p->d_status = s->d_rstatus + r.slot;
+    p->gw.status = p->d_status;
+    if (hipMemsetAsync(p->d_status, 0, sizeof(int), s->st) != hipSuccess) {
+      server_release(s, r);
+      return fail(LEM_ERR_HIP, "status reset failed");
+    }
+  }
   return LEM_OK;
 }
 
 void server_release(lem_server_s* s, ServerReq& r) {
+  if (r.slot >= 0) s->free_slots.push_back(r.slot);
+  r.slot = -1;
   delete r.plan;  // returns its ranges to the arena
   r.plan = nullptr;
   s->arena->release(r.buf[0]);
@@ -2119,12 +2210,14 @@ lem_status lem_server_create(const lem_server_options* opt, void* stream, lem_se
       delete s;
       return fail(LEM_ERR_HIP, "could not create the serving side streams");
     }
-    if (hipMalloc(&s->d_status, sizeof(int)) != hipSuccess ||
-        hipMemsetAsync(s->d_status, 0, sizeof(int), s->st) != hipSuccess ||
+    if (hipMalloc(&s->d_rstatus, sizeof(int) * opt->max_active) != hipSuccess ||
+        hipMemsetAsync(s->d_rstatus, 0, sizeof(int) * opt->max_active, s->st) != hipSuccess ||
         server_grow(s, 4096) != LEM_OK) {
       delete s;
       return fail(LEM_ERR_NOMEM, "could not allocate serving tables");
     }
+    s->h_rstatus.assign(opt->max_active, 0);
+    for (int k = opt->max_active - 1; k >= 0; --k) s->free_slots.push_back(k);
   }
   *out = s;
   return LEM_OK;
@@ -2213,6 +2306,7 @@ lem_status lem_server_tick(lem_server_t s, int32_t* n_active, int32_t* n_queued)
           k.xout = out;
           k.coef = p->d_coef;
           k.vwork = p->d_vwork + k.v_off;
+          k.status = s->d_rstatus + r.slot;
           k.diag = diag++;
           LaunchKey key{bk.variant, bk.nt, bk.pmax, bk.vlds};
           groups[key].push_back(k);
@@ -2234,9 +2328,10 @@ lem_status lem_server_tick(lem_server_t s, int32_t* n_active, int32_t* n_queued)
     off = 0;
     for (auto& g : groups) {
       const int nb = (int)g.second.size();
+      // every block carries its request's status word (the launch's own is unused)
       hipError_t e = lem::launch_krylov_lds(s->d_table + off, nb, 1, g.first.nt, g.first.pmax,
                                             g.first.vlds, lds[g.first], nullptr, nullptr,
-                                            nullptr, nullptr, s->d_diag, s->d_status, nullptr, 0,
+                                            nullptr, nullptr, s->d_diag, s->d_rstatus, nullptr, 0,
                                             false, s->st);
       if (e != hipSuccess)
         return fail(LEM_ERR_HIP, std::string("serving launch: ") + hipGetErrorString(e));
@@ -2248,7 +2343,7 @@ lem_status lem_server_tick(lem_server_t s, int32_t* n_active, int32_t* n_queued)
       LEM_HIP(hipStreamWaitEvent(s->st, s->ev_join[k], 0));
     }
   }
-  // 3. advance counters, retire finished requests
+  // 3. advance counters, retire finished and failed requests
   std::vector<uint64_t> finished, still;
   for (uint64_t id : s->active) {
     ServerReq& r = s->reqs[id];
@@ -2269,19 +2364,35 @@ lem_status lem_server_tick(lem_server_t s, int32_t* n_active, int32_t* n_queued)
   }
   if (!s->opt.dry_run) {
     LEM_HIP(hipStreamSynchronize(s->st));
-    int st = 0;
-    LEM_HIP(hipMemcpy(&st, s->d_status, sizeof(int), hipMemcpyDeviceToHost));
-    s->status_seen |= st;
+    LEM_HIP(hipMemcpy(s->h_rstatus.data(), s->d_rstatus, s->h_rstatus.size() * sizeof(int),
+                      hipMemcpyDeviceToHost));
   }
   const double t = s->now_ms();
+  // a request whose kernels latched a failure leaves the batch now
+  auto failed_now = [&](ServerReq& r) {
+    if (r.slot < 0) return false;
+    const int bits = s->h_rstatus[r.slot];
+    if (!bits) return false;
+    s->status_seen |= bits;
+    server_release(s, r);
+    r.state = LEM_REQ_FAILED;
+    r.error = (lem_status)device_status_of(bits);
+    r.t_done = t;
+    s->n_failed++;
+    return true;
+  };
   for (uint64_t id : finished) {
     ServerReq& r = s->reqs[id];
+    if (failed_now(r)) continue;
     server_release(s, r);
     r.state = LEM_REQ_DONE;
     r.t_done = t;
     s->n_done++;
   }
-  s->active.swap(still);
+  std::vector<uint64_t> kept;
+  for (uint64_t id : still)
+    if (!failed_now(s->reqs[id])) kept.push_back(id);
+  s->active.swap(kept);
   s->ticks++;
   if (n_active) *n_active = (int32_t)s->active.size();
   if (n_queued) *n_queued = (int32_t)s->queue.size();
@@ -2350,7 +2461,7 @@ lem_status lem_server_query(lem_server_t s, lem_server_info* info) {
   info->bytes_in_use = (int64_t)s->arena->in_use();
   info->bytes_budget = (int64_t)s->opt.hbm_budget;
   info->dof_steps = s->dof_steps;
-  info->device_status = s->status_seen ? LEM_ERR_NOT_CONVERGED : 0;
+  info->device_status = device_status_of(s->status_seen);
   return LEM_OK;
 }
 

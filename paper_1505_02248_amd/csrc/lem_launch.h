@@ -57,12 +57,16 @@ void dense_block_fill(void* dst, int i, int ox, int oy, int cx, int cy, int h, i
 // Tile shapes of the FP64/FP32 apply (the autotuner times each at plan time);
 // the split-bf16 apply uses cfg & 1 (32 or 64 rows per wave).
 constexpr int kApplyConfigs = 8;
+// Whether tile shape cfg of the apply serves this precision and padded block
+// (cfg is ignored for ensembles that are not a multiple of 64).
+bool dense_apply_supported(int precision, int cfg, int ns, int rows_p, int cols_p);
 // Split-bf16 precisions: xpieces (optional) holds the input state already
 // split into bf16 pieces (dense_split_pieces, n_points x ns entries per piece).
+// status: non-finite outputs latch kStatusNonFinite there (may be null).
 hipError_t dense_apply(int precision, int cfg, const void* blocks, const void* E,
                        int64_t e_stride, const double* core, const double* x_in, double* x_out,
                        int n, int ndim, int ns, int rows, int rows_p, int cols, int cols_p,
-                       int n_blocks, const double* bias, hipStream_t st,
+                       int n_blocks, const double* bias, int* status, hipStream_t st,
                        const void* xpieces = nullptr, int64_t n_points = 0);
 hipError_t dense_split_pieces(const double* x, int64_t total, int np, void* pieces,
                               hipStream_t st);

@@ -69,3 +69,35 @@ def test_results_alone_equal_results_in_the_mix_and_the_oracle():
         assert rel_l2(got, want) <= 1e-12, (k, info)
     methods = {k: alone[k][1]["method"] for k in REQS}
     assert "global" in methods.values() and "krylov" in methods.values()
+
+
+def test_a_nonfinite_request_fails_alone():
+    # NaN copies of a co-batched (Krylov) request and of a global-method one
+    # join the mix: they are retired as failed with LEM_ERR_NONFINITE, and
+    # every other request still equals its result alone
+    alone = {k: run_alone(k) for k in REQS}
+    krylov_k = next(k for k in REQS if alone[k][1]["method"] == "krylov")
+    global_k = next(k for k in REQS if alone[k][1]["method"] == "global")
+    s = make_server()
+    ids, bad = {}, {}
+    for k in REQS:
+        n, nu, mult, steps, seed = REQS[k]
+        o, dt, x = problem(n, nu, mult, seed)
+        ids[k] = s.submit(o, dt, steps, x)
+        if k in (krylov_k, global_k):
+            xb = x.copy()
+            xb[3] = np.nan
+            bad[k] = s.submit(o, dt, steps, xb)
+    live = list(ids.values()) + list(bad.values())
+    while any(s.poll(i) in ("queued", "active") for i in live):
+        s.tick()
+    for k, rid in bad.items():
+        assert s.poll(rid) == "failed", k
+        assert s.request_info(rid)["error"] == 8
+        with pytest.raises(lem.LemError) as e:
+            s.fetch(rid)
+        assert e.value.status == 8
+    assert s.query()["device_status"] == 8
+    for k, rid in ids.items():
+        assert s.poll(rid) == "done", k
+        assert np.array_equal(s.fetch(rid), alone[k][0]), k

@@ -99,6 +99,11 @@ def test_invalid_arguments_are_reported():
     with pytest.raises(lem.LemError) as e:
         lem.Plan(o, 2 / 64, core=16, halo=4, krylov_m_max=60, dry_run=True)
     assert e.value.status == 1
+    for tile in (-2, 8):  # apply launch shapes are -1 (default) or 0..7
+        with pytest.raises(lem.LemError) as e:
+            lem.Plan(o, 2 / 64, method="dense", core=16, halo=4, n_states=64, tile=tile,
+                     dry_run=True)
+        assert e.value.status == 1
     # Krylov boxes hold at most 4096 points, one fewer with a forcing (the
     # augmented coordinate); the check precedes any device work
     big = lem.Operator(2, 128, 1 / 128, (1.0, 0.5), 1e-3)
