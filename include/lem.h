@@ -280,6 +280,20 @@ lem_status lem_global_expmv(const lem_operator* op, double t, const double* x,
                             double* y, int32_t n_states, double tol,
                             int32_t m_max, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * action as lem_global_expmv -- same arguments, calibration, kernels and
+ * result -- with all of its device work space taken from a static per-device
+ * scratch array of 64 MiB instead of hipMalloc/hipFree.  The caller still
+ * passes x and y.  A problem whose work space could exceed the scratch
+ * (roughly (m_max + 3) x N x n_states doubles plus per-point coefficients) is
+ * refused with LEM_ERR_BUDGET before any device work.  Synchronous.  Calls on
+ * one device share the array: calls that overlap in time on one device race
+ * (serialize them); calls on different devices are independent. */
+lem_status lem_global_expmv_static(const lem_operator* op, double t, const double* x,
+                                   double* y, int32_t n_states, double tol, int32_t m_max,
+                                   void* stream);
+
 /* Plan statistics; device_status requires the plan's stream to have drained
  * (this call synchronizes the plan's last stream). */
 lem_status lem_plan_query(lem_plan_t plan, lem_plan_info* info);

@@ -86,6 +86,7 @@ def load() -> ctypes.CDLL:
     lib.lem_plan.argtypes = [P(_Operator), D, P(_Options), VP, P(VP)]
     lib.lem_step.argtypes = [VP, VP, VP, I32, VP]
     lib.lem_global_expmv.argtypes = [P(_Operator), D, VP, VP, I32, D, I32, VP]
+    lib.lem_global_expmv_static.argtypes = [P(_Operator), D, VP, VP, I32, D, I32, VP]
     lib.lem_ere_plan.argtypes = [P(_Burgers), D, I32, I32, I32, I32, VP, P(VP)]
     lib.lem_schrodinger_plan.argtypes = [P(_Schrodinger), D, I32, I32, I32, I32, VP, P(VP)]
     lib.lem_plan_query.argtypes = [VP, P(_Info)]
@@ -94,7 +95,8 @@ def load() -> ctypes.CDLL:
     lib.lem_plan_copy_block.argtypes = [VP, I32, P(D), P(I32), P(I32)]
     lib.lem_plan_destroy.argtypes = [VP]
     lib.lem_last_error.restype = ctypes.c_char_p
-    for name in ("lem_plan", "lem_step", "lem_global_expmv", "lem_plan_query",
+    for name in ("lem_plan", "lem_step", "lem_global_expmv", "lem_global_expmv_static",
+                 "lem_plan_query",
                  "lem_plan_copy_maps", "lem_plan_copy_krylov", "lem_plan_copy_block",
                  "lem_plan_destroy"):
         getattr(lib, name).restype = ctypes.c_int
@@ -351,6 +353,21 @@ def global_expmv(op: Operator, t: float, x, y, n_states: int = 1, tol: float = 1
                                    ctypes.c_void_p(_tensor_ptr(x, N, n_states)),
                                    ctypes.c_void_p(_tensor_ptr(y, N, n_states)), int(n_states),
                                    float(tol), int(m_max), ctypes.c_void_p(_stream_handle(stream))))
+
+
+def global_expmv_static(op: Operator, t: float, x, y, n_states: int = 1, tol: float = 1e-13,
+                        m_max: int = 40, stream=None) -> None:
+    """As ``global_expmv`` but with no device allocation: the work space comes
+    from the library's static per-device scratch (``lem_global_expmv_static``)."""
+    N = op.N
+    if op.forcing is not None and op.forcing.size != N * int(n_states):
+        raise ValueError("forcing must hold N x n_states values")
+    oc = op._c()
+    _check(load().lem_global_expmv_static(ctypes.byref(oc), float(t),
+                                          ctypes.c_void_p(_tensor_ptr(x, N, n_states)),
+                                          ctypes.c_void_p(_tensor_ptr(y, N, n_states)),
+                                          int(n_states), float(tol), int(m_max),
+                                          ctypes.c_void_p(_stream_handle(stream))))
 
 
 # ------------------------------------------------------------------ serving --

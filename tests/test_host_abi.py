@@ -192,3 +192,14 @@ def test_column_partition_maps_and_halos_match_oracle():
     with pytest.raises(lem.LemError):  # column-wise cores are a Krylov feature
         lem.Plan(lem.Operator.from_problem(p), p.dt, method="dense", core=16, halo=4,
                  columns=True, dry_run=True)
+
+
+def test_static_global_expmv_refuses_oversize_before_device_work():
+    # the allocation-free global action checks its work space against the
+    # 64 MiB static scratch before touching the device (no GPU needed here)
+    lib = lem.load()
+    o = lem.Operator(2, 1024, 1 / 1024, (1.0, 0.5), 1e-3)._c()
+    st = lib.lem_global_expmv_static(ctypes.byref(o), 1e-3, None, None, 1, 1e-13, 40, None)
+    assert st == 5 and "64 MiB" in lib.lem_last_error().decode()
+    st = lib.lem_global_expmv_static(None, 1e-3, None, None, 1, 1e-13, 40, None)
+    assert st == 1
