@@ -1,14 +1,17 @@
 """Benchmark of the LEM hot path on one MI355X.
 
-Workload: 2D periodic advection-diffusion on a 256x256 grid (velocity (1, 0.5),
-nu = 1e-3, dt = 2 dx), an ensemble of 64 seeded smooth states, 16x16 cores.
-Local exponentials exp(dt A_M) are computed once (float64 Pade scaling and
-squaring on the GPU, excluded from the timed region and reported as plan
-time) and applied every step as batched FP64 MFMA products with fused gather
-and scatter.  The buffer width comes from the off-diagonal decay bound at
-1e-8 per step, so that the LEM result stays within 1e-6 (relative l2) of the
-exact global exponential over the run; this is checked on the GPU against the
-global Krylov action, which is also timed on the same GPU as the comparator.
+Default workload: 2D periodic advection-diffusion on a 512x512 grid (velocity
+(1, 0.5), nu = 1e-3, dt = 2 dx), an ensemble of 128 seeded smooth states,
+32x32 cores.  Local exponentials exp(dt A_M) are computed once (float64 Pade
+scaling and squaring on the GPU, excluded from the timed region and reported
+as plan time) and applied every step as batched FP64 MFMA products with
+fused gather and scatter.  The buffer width comes from the off-diagonal decay
+bound at 1e-8 per step, so that the LEM result stays within 1e-6 (relative
+l2) of the exact global exponential over the timed run; this is checked on
+the GPU against the global Krylov action at 1e-13, and the global Krylov
+method at 1e-8 per step is timed on the same grid as the comparator.  The
+FP32 and split-bf16 applications of the same blocks, the configured 8-point
+buffer and the 256x256 x 64-state workload are reported as extras.
 
 Prints one JSON line.  A step is one full LEM step (gather, local
 exponential action, core scatter) of the whole grid and ensemble.
@@ -30,25 +33,29 @@ if ROOT not in sys.path:
 METRIC = "DOF-steps/s, LEM vs global Krylov expmv at rel err ≤1e-6; served p99 latency"
 MFMA_FP64_PEAK_TFLOPS = 78.6
 MFMA_FP32_PEAK_TFLOPS = 157.3
-# HBM bytes per launch of the FP64 apply at the bench workload, per tile shape
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+# HBM bytes per launch of the FP64 apply per workload and tile shape
 # (autotuner id), from rocprofv3 FETCH_SIZE / WRITE_SIZE passes scaled by a
-# 256 MiB reference copy (profiles/apply_fp64_2d256x256x64_h14.md); valid only
-# for the apply kernel source they were taken on: the text of dense.hip from
-# its apply section to the split-bf16 kernel, plus its tile-shape table.
-TRAFFIC = {"apply": ("d5a520228ca1", {0: 148002308, 1: 145000329, 2: 158006517, 3: 158089448, 4: 142227697, 5: 141826341, 6: 145872664, 7: 157996283})}
+# 256 MiB reference copy (profiles/apply_fp64_*.md); valid only for the apply
+# kernel source they were taken on: the text of dense.hip from its apply
+# section to the split-bf16 kernel, plus its tile-shape table.
+TRAFFIC = {}
 
 
 def _apply_source_key(text: str) -> str:
     import hashlib
     i0 = text.index("// ------------------------------------------------------------------ apply --")
     i1 = text.index("// Split-bf16 apply")
-    shapes = [ln for ln in text.splitlines() if "static const int shapes[kApplyConfigs][3]" in ln]
-    return hashlib.sha1((text[i0:i1] + "\n".join(shapes)).encode()).hexdigest()[:12]
+    j0 = text.index("kApplyShapes[kApplyConfigs][3] = {")
+    shapes = text[j0:text.index("};", j0)]
+    return hashlib.sha1((text[i0:i1] + shapes).encode()).hexdigest()[:12]
 
 
-def measured_traffic(tile):
+def measured_traffic(workload, tile):
+    if workload not in TRAFFIC:
+        return None
     src = os.path.join(ROOT, "paper_1505_02248_amd", "csrc", "dense.hip")
-    key, per_tile = TRAFFIC["apply"]
+    key, per_tile = TRAFFIC[workload]
     with open(src) as f:
         if _apply_source_key(f.read()) != key:
             return None
@@ -74,52 +81,73 @@ def timed_steps(plan, x, y, k, torch):
     return t1 - t0, e0.elapsed_time(e1)
 
 
-def cpu_baseline(p, boxes, budget_s: float):
-    """The oracle LEM step (numpy float64) on the host cores: first the local
-    exponential (excluded), then whole-grid steps until ~budget_s."""
-    import numpy as np
-    from oracle import lem as olem
-    from oracle import operator as op
-    from oracle import partition as P
+def host_cpu():
+    """(threads BLAS uses, CPU model, logical CPUs) of this host."""
     try:
         from threadpoolctl import threadpool_info
         cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
         cores = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return int(cores), model, os.cpu_count()
+
+
+def cpu_baseline(p, boxes, budget_s: float, sample_blocks: int = 0):
+    """The oracle LEM step (numpy float64) on the host cores: first the local
+    exponential (excluded), then steps of the whole grid -- or of the first
+    ``sample_blocks`` regions (a bounded sample; every region of these
+    translation-invariant workloads costs the same) -- until ~budget_s.  The
+    rate counts core points x states x steps of the regions stepped."""
+    import numpy as np
+    from oracle import lem as olem
+    from oracle import operator as op
+    from oracle import partition as P
+    cores, model, ncpu = host_cpu()
     A = op.sparse(op.from_problem(p))
     bx = [P.Box(*map(int, b)) for b in boxes]
+    if sample_blocks:
+        bx = bx[:sample_blocks]
+    core_pts = sum(b.cx * (b.cy if p.ndim == 2 else 1) for b in bx)
+    ns = p.states.shape[1]
     cache = olem.LocalExpCache()
-    u = p.states.copy()
     t0 = time.perf_counter()
-    u = olem.step(A, bx[:1], p.ndim, p.n, u, cache)  # local exponential, once
+    olem.step(A, bx[:1], p.ndim, p.n, p.states, cache)  # local exponential, once
     t_plan = time.perf_counter() - t0
-    u = p.states.copy()
-    steps = 0
-    t0 = time.perf_counter()
-    while True:
-        u = olem.step(A, bx, p.ndim, p.n, u, cache)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or steps >= 200:
-            break
-    val = p.N * p.states.shape[1] * steps / el
-    out = {"value": val, "unit": "DOF-steps/s", "cores": int(cores), "kind": "oracle",
-           "sample": f"{steps} full-grid LEM steps (256 blocks x 64 states, numpy float64 "
-                     f"GEMM per block), local expm {t_plan:.2f} s excluded",
+
+    def steps_for(limit_s, max_steps):
+        u = p.states.copy()
+        k = 0
+        t0 = time.perf_counter()
+        while True:
+            # a sample steps its regions from the input state each time (the
+            # cores outside the sample are not computed)
+            u = olem.step(A, bx, p.ndim, p.n, p.states if sample_blocks else u, cache)
+            k += 1
+            el = time.perf_counter() - t0
+            if el >= limit_s or k >= max_steps:
+                return k, el
+
+    steps, el = steps_for(budget_s, 200)
+    what = (f"{len(bx)} of {len(boxes)} regions" if sample_blocks else f"all {len(boxes)} regions")
+    out = {"value": core_pts * ns * steps / el, "unit": "DOF-steps/s", "cores": cores,
+           "kind": "oracle", "cpu_model": model, "logical_cpus": ncpu,
+           "sample": f"{steps} LEM steps of {what} x {ns} states (numpy float64, one GEMM per "
+                     f"region), local expm {t_plan:.2f} s excluded",
            "seconds": round(el, 3)}
     # the same steps with one BLAS thread (a quarter of the time budget)
     try:
         from threadpoolctl import threadpool_limits
         with threadpool_limits(limits=1):
-            s1 = 0
-            t0 = time.perf_counter()
-            while True:
-                u = olem.step(A, bx, p.ndim, p.n, u, cache)
-                s1 += 1
-                el1 = time.perf_counter() - t0
-                if el1 >= budget_s / 4 or s1 >= 50:
-                    break
-        out["value_1thread"] = p.N * p.states.shape[1] * s1 / el1
+            s1, el1 = steps_for(budget_s / 4, 50)
+        out["value_1thread"] = core_pts * ns * s1 / el1
         out["sample_1thread"] = f"{s1} step{'s' if s1 > 1 else ''}, one BLAS thread"
     except ImportError:
         pass
@@ -129,22 +157,28 @@ def cpu_baseline(p, boxes, budget_s: float):
 def parse_args():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--halo-tol", type=float, default=1e-8)
     ap.add_argument("--global-steps", type=int, default=10)
-    ap.add_argument("--acc-steps", type=int, default=100)
+    ap.add_argument("--acc-steps", type=int, default=0,
+                    help="steps of the accuracy check against the global method (0: --steps)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-global", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the float32 leg of c1")
+    ap.add_argument("--arms", default="fp32,bf16x3,bf16x2",
+                    help="c3: reduced-precision applications timed beside FP64 (comma list, "
+                         "may be empty)")
+    ap.add_argument("--with-c1", type=int, default=1,
+                    help="c3: also report the 256^2 x 64-state workload (1/0)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run one device copy of this many MiB (a reference kernel of "
                          "known traffic for scaling HBM counters)")
-    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2", "c3", "c4", "f1", "f2", "f3", "f4"],
-                    help="c1 (default): 256^2 x 64 states, dense FP64; c0: 1D 1024; "
-                         "c2: 1024^2 lognormal nu, uneven Krylov; c3: 512^2 x 128 states, "
-                         "mixed precision; c4: served Poisson stream; f1: c1 with a "
+    ap.add_argument("--workload", default="c3", choices=["c0", "c1", "c2", "c3", "c4", "f1", "f2", "f3", "f4"],
+                    help="c3 (default): 512^2 x 128 states, dense FP64 (+ FP32/bf16 arms); "
+                         "c1: 256^2 x 64 states, dense FP64; c0: 1D 1024; "
+                         "c2: 1024^2 lognormal nu, uneven Krylov; c4: served Poisson stream; f1: c1 with a "
                          "constant source g (exponential-Euler step with forcing); f2: "
                          "Burgers by exponential Rosenbrock-Euler LEM; f3: Schroedinger with a "
                          "harmonic potential (complex blocks in real form); f4: variable "
@@ -214,7 +248,7 @@ def bench_c1(args) -> dict:
     if not args.no_global:
         log("global Krylov comparator")
         ref_plan = lem.Plan(opr, p.dt, method="global", n_states=ns, krylov_tol=1e-13)
-        k = args.acc_steps
+        k = args.acc_steps if args.acc_steps > 0 else 100
         g = torch.empty_like(x)
         ref_plan.step(x, g, k)
         yl = torch.empty_like(x)
@@ -279,7 +313,7 @@ def bench_c1(args) -> dict:
                    "tile_config": q["tile_config"]},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": MFMA_FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / MFMA_FP64_PEAK_TFLOPS,
-                     "traffic": measured_traffic(q["tile_config"]),
+                     "traffic": measured_traffic("c1", q["tile_config"]),
                      "kernel": "apply_mfma_kernel<double>", "flops_per_launch": flops,
                      "us_per_launch": kern_ms * 1e3},
         "cpu_baseline": cpu,
@@ -334,7 +368,7 @@ def bench_f1(args) -> dict:
     extras = {}
     if not args.no_global:
         ref_plan = lem.Plan(opr, p.dt, method="global", n_states=ns, krylov_tol=1e-13)
-        k = args.acc_steps
+        k = args.acc_steps if args.acc_steps > 0 else 100
         gref = torch.empty_like(x)
         ref_plan.step(x, gref, k)
         yl = torch.empty_like(x)
@@ -737,47 +771,197 @@ def bench_c2(args) -> dict:
     return _line(args, wl, lem_val, "DOF-steps/s", steps, wall, "f64", extras)
 
 
+def _time_stream(plan, x, y, k, stream, torch):
+    """k steps of plan as one lem_step on `stream`, bracketed by HIP events on
+    that stream: (wall s, event ms)."""
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    plan.step(x, y, k, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, e0.elapsed_time(e1)
+
+
 def bench_c3(args) -> dict:
-    """512^2, 128 states, 32^2 cores: FP64 / FP32 / split-bf16 application."""
+    """512^2 x 128 states, 32^2 cores: stored FP64 Pade blocks applied on FP64
+    MFMA with the decay-bound buffer (the headline), against the global Krylov
+    method on the same grid; FP32 and split-bf16 arms of the same blocks, the
+    configured 8-point buffer and the 256^2 x 64-state workload as extras."""
     import torch
     import lem_inputs as L
     import paper_1505_02248_amd as lem
-    p = L.workload_2d_mixed()
+    torch.cuda.init()
+    p = L.workload_2d_mixed()  # 512^2, 128 smooth states
+    opr = lem.Operator.from_problem(p)
+    ns = p.states.shape[1]
+    N = p.N
+    x = torch.from_numpy(p.states.copy()).to("cuda")
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    arms = [a for a in args.arms.split(",") if a]
+
+    log("planning LEM (dense, fp64, 32^2 cores, decay-bound halo)")
+    plan = lem.Plan(opr, p.dt, method="dense", core=32, halo=0, halo_min=4, halo_max=32,
+                    halo_tol=args.halo_tol, n_states=ns, autotune=True)
+    q = plan.query()
+    h = q["halo_max"]
+    nloc = (32 + 2 * h) ** 2
+    plan.step(x, y, args.warmup)
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} steps (h={h}, tile {q['tile_config']})")
+    wall, ev_ms = _time_stream(plan, x, y, args.steps, stream, torch)
+    value = N * ns * args.steps / wall
+    kern_ms = ev_ms / args.steps
+    flops = 2.0 * 1024 * nloc * 256 * ns  # core rows x local columns x blocks x states
+    achieved = flops / (kern_ms * 1e-3) / 1e12
+    log(f"LEM fp64 h={h}: {value:.3e} DOF-steps/s, {kern_ms * 1e3:.1f} us/step, "
+        f"{achieved:.1f} TFLOP/s ({achieved / MFMA_FP64_PEAK_TFLOPS:.1%} of FP64 MFMA peak)")
+
+    extras = {}
+    peaks = {"fp64": MFMA_FP64_PEAK_TFLOPS, "fp32": MFMA_FP32_PEAK_TFLOPS,
+             "bf16x3": MFMA_BF16_PEAK_TFLOPS, "bf16x2": MFMA_BF16_PEAK_TFLOPS}
+    terms = {"fp64": 1, "fp32": 1, "bf16x3": 6, "bf16x2": 3}
+    y64 = torch.empty_like(x)
+    plan.step(x, y64, 1)
+    for prec in arms:  # the same blocks applied in reduced precision
+        log(f"planning the {prec} arm")
+        pl = lem.Plan(opr, p.dt, method="dense", precision=prec, core=32, halo=h, n_states=ns,
+                      autotune=True)
+        pl.step(x, y, args.warmup)
+        w, e = _time_stream(pl, x, y, args.steps, stream, torch)
+        yp = torch.empty_like(x)
+        pl.step(x, yp, 1)
+        us = 1e3 * e / args.steps
+        extras[f"lem_{prec}"] = {
+            "value": N * ns * args.steps / w, "us_per_step": us,
+            "rel_l2_vs_fp64_one_step": _rel(yp, y64, torch),
+            "tflops_algorithmic": flops / us / 1e6,
+            "mfma_frac": flops * terms[prec] / us / 1e6 / peaks[prec],
+            "tile_config": pl.query()["tile_config"]}
+        log(f"{prec}: {extras[f'lem_{prec}']}")
+        del pl
+
+    acc = {}
+    if not args.no_global:
+        k = args.acc_steps if args.acc_steps > 0 else args.steps
+        log(f"global Krylov reference (tol 1e-13), {k} steps")
+        ref_plan = lem.Plan(opr, p.dt, method="global", n_states=ns, krylov_tol=1e-13)
+        g = torch.empty_like(x)
+        ref_plan.step(x, g, k)
+        yl = torch.empty_like(x)
+        plan.step(x, yl, k)
+        torch.cuda.synchronize()
+        acc["lem_vs_global_rel_l2"] = _rel(yl, g, torch)
+        acc["acc_steps"] = k
+        del ref_plan
+        log("LEM at the configured 8-point buffer")
+        cfg8 = lem.Plan(opr, p.dt, method="dense", core=32, halo=8, n_states=ns, autotune=True)
+        y8 = torch.empty_like(x)
+        cfg8.step(x, y8, k)
+        torch.cuda.synchronize()
+        acc["halo8_vs_global_rel_l2"] = _rel(y8, g, torch)
+        w8, e8 = _time_stream(cfg8, x, y8, args.steps, stream, torch)
+        extras["lem_fp64_halo8"] = {"value": N * ns * args.steps / w8,
+                                    "us_per_step": 1e3 * e8 / args.steps}
+        del cfg8, y8
+        log("global Krylov comparator (tol 1e-8 per step)")
+        gplan = lem.Plan(opr, p.dt, method="global", n_states=ns, krylov_tol=1e-8)
+        gq = gplan.query()
+        gk = torch.empty_like(x)
+        gplan.step(x, gk, k)
+        torch.cuda.synchronize()
+        acc["global_1e-8_vs_global_1e-13_rel_l2"] = _rel(gk, g, torch)
+        gplan.step(x, gk, 1)
+        gw, _ = _time_stream(gplan, x, gk, args.global_steps, stream, torch)
+        gval = N * ns * args.global_steps / gw
+        extras["global_krylov"] = {"value": gval, "ms_per_step": 1e3 * gw / args.global_steps,
+                                   "m": gq["m_max"], "substeps": gq["substeps_max"],
+                                   "tol_per_step": 1e-8}
+        extras["lem_over_global"] = value / gval
+        log(f"global Krylov: {gval:.3e} DOF-steps/s; LEM/global = {value / gval:.1f}x; "
+            f"LEM vs global after {k} steps = {acc['lem_vs_global_rel_l2']:.2e}")
+        del gplan, g, gk, yl
+
+    if args.with_c1:
+        extras["c1_256x256x64"] = _c1_summary(args, torch, lem, L)
+
+    if args.copy_mb:
+        nbytes = args.copy_mb << 20
+        a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").uniform_()
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        extras["reference_copy_bytes"] = nbytes
+        del a, b
+
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(p, plan.maps()[0], args.cpu_seconds, sample_blocks=8)
+
+    return {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DOF-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "2D periodic advection-diffusion 512x512, velocity (1,0.5), "
+                               "nu=1e-3, dt=2dx, 128 smooth states, 32x32 cores, LEM with "
+                               "stored local exponentials (fp64 Pade) applied on FP64 MFMA",
+                   "grid": [512, 512], "n_states": ns, "core": 32, "halo": h,
+                   "halo_rule": f"decay bound {args.halo_tol:g}/step", "n_loc": nloc,
+                   "method": "dense", "plan_ms": q["plan_ms"], "squarings": q["squarings"],
+                   "tile_config": q["tile_config"]},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": MFMA_FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / MFMA_FP64_PEAK_TFLOPS,
+                     "traffic": measured_traffic("c3", q["tile_config"]),
+                     "kernel": "apply_mfma_kernel<double>", "flops_per_launch": flops,
+                     "us_per_launch": kern_ms * 1e3},
+        "cpu_baseline": cpu,
+        "accuracy": acc,
+        "extras": extras,
+    }
+
+
+def _c1_summary(args, torch, lem, L) -> dict:
+    """256^2 x 64 states, 16^2 cores, decay-bound buffer: FP64 apply rate and
+    its error against the global Krylov action after the same steps."""
+    p = L.workload_2d_ensemble()
     opr = lem.Operator.from_problem(p)
     ns = p.states.shape[1]
     x = torch.from_numpy(p.states.copy()).to("cuda")
-    out = {}
-    peaks = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x2": 2500.0}
-    terms = {"fp64": 1, "fp32": 1, "bf16x3": 6, "bf16x2": 3}
-    steps = min(args.steps, 50)
-    for h in (8, 0):
-        ref = None
-        for prec in ("fp64", "fp32", "bf16x3", "bf16x2"):
-            plan = lem.Plan(opr, p.dt, method="dense", precision=prec, core=32, halo=h,
-                            halo_tol=args.halo_tol, halo_max=32, n_states=ns, autotune=True)
-            q = plan.query()
-            hh = q["halo_max"]
-            nloc = (32 + 2 * hh) ** 2
-            y = torch.empty_like(x)
-            plan.step(x, y, 1)
-            torch.cuda.synchronize()
-            if ref is None:
-                ref = y.clone()
-            err = _rel(y, ref, torch)
-            wall, ev = timed_steps(plan, x, y, steps, torch)
-            us = 1e3 * ev / steps
-            fl = 2.0 * nloc * p.N * ns
-            out[f"h{hh}_{prec}"] = {"dof_steps_per_s": p.N * ns * steps / wall, "us_per_step": us,
-                                    "rel_l2_vs_fp64_one_step": err,
-                                    "tflops_algorithmic": fl / us / 1e6,
-                                    "mfma_frac": fl * terms[prec] / us / 1e6 / peaks[prec]}
-            log(f"h={hh} {prec}", out[f"h{hh}_{prec}"])
-    best = out[[k for k in out if k.endswith("fp32") and not k.startswith("h8")][0]]
-    wl = {"workload": "2D 512x512 periodic advection-diffusion, velocity (1,0.5), nu=1e-3, "
-                      "dt=2dx, 128 smooth states, 32x32 cores, stored FP64 Pade blocks applied "
-                      "in FP64/FP32/split bf16 with FP32 accumulation"}
-    return _line(args, wl, best["dof_steps_per_s"], "DOF-steps/s", steps,
-                 best["us_per_step"] * steps * 1e-6, "f32", out)
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    plan = lem.Plan(opr, p.dt, method="dense", core=16, halo=0, halo_min=4, halo_max=32,
+                    halo_tol=args.halo_tol, n_states=ns, autotune=True)
+    q = plan.query()
+    h = q["halo_max"]
+    plan.step(x, y, args.warmup)
+    w, e = _time_stream(plan, x, y, args.steps, stream, torch)
+    flops = 2.0 * 256 * (16 + 2 * h) ** 2 * 256 * ns
+    us = 1e3 * e / args.steps
+    out = {"value": p.N * ns * args.steps / w, "us_per_step": us, "halo": h,
+           "tile_config": q["tile_config"], "mfma_frac": flops / us / 1e6 / MFMA_FP64_PEAK_TFLOPS}
+    if not args.no_global:
+        ref = lem.Plan(opr, p.dt, method="global", n_states=ns, krylov_tol=1e-13)
+        g = torch.empty_like(x)
+        ref.step(x, g, args.steps)
+        plan.step(x, y, args.steps)
+        torch.cuda.synchronize()
+        out["lem_vs_global_rel_l2"] = _rel(y, g, torch)
+    log(f"c1: {out}")
+    return out
 
 
 def bench_c4(args) -> dict:
