@@ -34,12 +34,15 @@ METRIC = "DOF-steps/s, LEM vs global Krylov expmv at rel err ≤1e-6; served p99
 MFMA_FP64_PEAK_TFLOPS = 78.6
 MFMA_FP32_PEAK_TFLOPS = 157.3
 MFMA_BF16_PEAK_TFLOPS = 2500.0
+HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the FP64 apply per workload and tile shape
 # (autotuner id), from rocprofv3 FETCH_SIZE / WRITE_SIZE passes scaled by a
 # 256 MiB reference copy (profiles/apply_fp64_*.md); valid only for the apply
 # kernel source they were taken on: the text of dense.hip from its apply
 # section to the split-bf16 kernel, plus its tile-shape table.
-TRAFFIC = {}
+TRAFFIC = {"c3": ("094c1b2e44e5", {0: 5924491712, 1: 5698362176, 2: 2941001920, 3: 2940792832,
+                                     4: 8905402048, 5: 11436342272, 6: 5166288896,
+                                     7: 2999551104})}
 
 
 def _apply_source_key(text: str) -> str:
@@ -100,7 +103,7 @@ def host_cpu():
     return int(cores), model, os.cpu_count()
 
 
-def cpu_baseline(p, boxes, budget_s: float, sample_blocks: int = 0):
+def cpu_baseline(p, boxes, budget_s: float, sample_blocks: int = 0, **step_kw):
     """The oracle LEM step (numpy float64) on the host cores: first the local
     exponential (excluded), then steps of the whole grid -- or of the first
     ``sample_blocks`` regions (a bounded sample; every region of these
@@ -119,7 +122,7 @@ def cpu_baseline(p, boxes, budget_s: float, sample_blocks: int = 0):
     ns = p.states.shape[1]
     cache = olem.LocalExpCache()
     t0 = time.perf_counter()
-    olem.step(A, bx[:1], p.ndim, p.n, p.states, cache)  # local exponential, once
+    olem.step(A, bx[:1], p.ndim, p.n, p.states, cache, **step_kw)  # local exponential, once
     t_plan = time.perf_counter() - t0
 
     def steps_for(limit_s, max_steps):
@@ -129,7 +132,7 @@ def cpu_baseline(p, boxes, budget_s: float, sample_blocks: int = 0):
         while True:
             # a sample steps its regions from the input state each time (the
             # cores outside the sample are not computed)
-            u = olem.step(A, bx, p.ndim, p.n, p.states if sample_blocks else u, cache)
+            u = olem.step(A, bx, p.ndim, p.n, p.states if sample_blocks else u, cache, **step_kw)
             k += 1
             el = time.perf_counter() - t0
             if el >= limit_s or k >= max_steps:
@@ -137,10 +140,11 @@ def cpu_baseline(p, boxes, budget_s: float, sample_blocks: int = 0):
 
     steps, el = steps_for(budget_s, 200)
     what = (f"{len(bx)} of {len(boxes)} regions" if sample_blocks else f"all {len(boxes)} regions")
+    how = ("the oracle's Krylov action per region" if step_kw.get("krylov_above")
+           else f"one GEMM per region, local expm {t_plan:.2f} s excluded")
     out = {"value": core_pts * ns * steps / el, "unit": "DOF-steps/s", "cores": cores,
            "kind": "oracle", "cpu_model": model, "logical_cpus": ncpu,
-           "sample": f"{steps} LEM steps of {what} x {ns} states (numpy float64, one GEMM per "
-                     f"region), local expm {t_plan:.2f} s excluded",
+           "sample": f"{steps} LEM steps of {what} x {ns} states (numpy float64, {how})",
            "seconds": round(el, 3)}
     # the same steps with one BLAS thread (a quarter of the time budget)
     try:
@@ -183,7 +187,15 @@ def parse_args():
                          "Burgers by exponential Rosenbrock-Euler LEM; f3: Schroedinger with a "
                          "harmonic potential (complex blocks in real form); f4: variable "
                          "vortex velocity and anisotropic column-wise cores (Krylov)")
-    ap.add_argument("--requests", type=int, default=300)
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--warm-requests", type=int, default=200,
+                    help="c4: requests served before the measured ones")
+    ap.add_argument("--krylov-m-max", type=int, default=40,
+                    help="c2/c4: largest local Krylov dimension")
+    ap.add_argument("--max-overhead", type=float, default=9.0,
+                    help="c4: largest local/core point ratio before a request takes the "
+                         "global method")
+    ap.add_argument("--steps-per-tick", type=int, default=4, help="c4: server steps per tick")
     return ap.parse_args()
 
 
@@ -709,7 +721,8 @@ def bench_c0(args) -> dict:
 
 
 def bench_c2(args) -> dict:
-    """2D 1024^2 lognormal nu, uneven cores, decay-bound halos, Krylov LEM."""
+    """2D 1024^2 lognormal nu, uneven cores (16/32/64 per 64^2 tile), decay-bound
+    halos, calibrated Krylov dimensions up to 40, one HIP graph per step."""
     import torch
     import lem_inputs as L
     import paper_1505_02248_amd as lem
@@ -722,20 +735,21 @@ def bench_c2(args) -> dict:
         log("planning uneven Krylov LEM (1024^2)")
         t0 = time.perf_counter()
         plan = lem.Plan(opr, p.dt, method="krylov", core=0, halo=0, halo_min=4, halo_max=16,
-                        halo_tol=1e-8, krylov_tol=1e-10, use_graph=True, stream=stream)
+                        halo_tol=1e-8, krylov_m_max=args.krylov_m_max, krylov_tol=1e-10,
+                        use_graph=True, autotune=True, stream=stream)
         plan_s = time.perf_counter() - t0
         q = plan.query()
         boxes = plan.maps()[0]
+        m_blk, sub_blk = plan.krylov()
         y = torch.empty_like(x)
         plan.step(x, y, 2, stream=stream)
         stream.synchronize()
-        t0 = time.perf_counter()
-        plan.step(x, y, steps, stream=stream)
-        stream.synchronize()
-        wall = time.perf_counter() - t0
+        log(f"timing {steps} steps")
+        wall, ev = _time_stream(plan, x, y, steps, stream, torch)
         q = plan.query()
         lem_val = p.N * steps / wall
-        log(f"LEM: {lem_val:.3e} DOF-steps/s, {1e3 * wall / steps:.2f} ms/step")
+        step_s = ev * 1e-3 / steps
+        log(f"LEM: {lem_val:.3e} DOF-steps/s, {1e3 * step_s:.2f} ms/step")
         # accuracy and the global comparator
         acc_steps = 3
         ref = torch.empty_like(x)
@@ -750,10 +764,8 @@ def bench_c2(args) -> dict:
         g = torch.empty_like(x)
         gplan.step(x, g, 1, stream=stream)
         stream.synchronize()
-        t0 = time.perf_counter()
-        gplan.step(x, g, 3, stream=stream)
-        stream.synchronize()
-        gwall = (time.perf_counter() - t0) / 3
+        gw, _ = _time_stream(gplan, x, g, 3, stream, torch)
+        gwall = gw / 3
     cores = {int(c): int((boxes[:, 2] == c).sum()) for c in np.unique(boxes[:, 2])}
     wl = {"workload": "2D 1024x1024 periodic diffusion-advection, lognormal nu (median 1e-3, "
                       "sigma_log 1), velocity (1,0), dt=dx/4, uneven cores 16-64 per 64^2 tile, "
@@ -761,14 +773,33 @@ def bench_c2(args) -> dict:
                       "HIP graph per step, FP64",
           "n_blocks": q["n_blocks"], "cores": cores, "halo_range": [q["halo_min"], q["halo_max"]],
           "halo_clamped_blocks": q["halo_clamped"], "m_range": [q["m_min"], q["m_max"]],
-          "substeps_max": q["substeps_max"], "plan_s": plan_s}
+          "substeps_max": q["substeps_max"], "n_loc_max": q["n_loc_max"], "plan_s": plan_s}
     extras = {"lem_rel_l2_vs_global_after_3_steps": err, "max_estimate": q["max_estimate"],
               "device_status": q["device_status"],
+              "krylov_bytes_step": q["krylov_bytes_step"],
+              "krylov_bytes_streamed": q["krylov_bytes_streamed"],
+              "m_histogram": {int(k): int((m_blk == k).sum()) for k in np.unique(m_blk)},
               "global_krylov": {"dof_steps_per_s": p.N / gwall, "ms_per_step": 1e3 * gwall,
                                 "m": gq["m_max"], "substeps": gq["substeps_max"]},
               "lem_over_global": lem_val / (p.N / gwall)}
     log(extras)
-    return _line(args, wl, lem_val, "DOF-steps/s", steps, wall, "f64", extras)
+    # every launch of the step overlaps (forked buckets): the algorithmic basis
+    # traffic of the whole step over the step's event time bounds the rate of
+    # the streaming kernels from below
+    achieved = q["krylov_bytes_step"] / step_s / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "Krylov LEM step (all buckets; algorithmic |M| 8 (m(m+1)+3m) nsub B per "
+                      "block and member)",
+            "bytes_per_step": q["krylov_bytes_step"], "us_per_step": step_s * 1e6}
+    line = _line(args, wl, lem_val, "DOF-steps/s", steps, wall, "f64", extras, roofline=roof)
+    if not args.no_cpu:
+        log("cpu baseline (oracle, sampled regions)")
+        bx = boxes[np.argsort(-boxes[:, 2], kind="stable")]  # largest cores first
+        pick = np.concatenate([bx[bx[:, 2] == c][:2] for c in sorted(cores, reverse=True)])
+        line["cpu_baseline"] = cpu_baseline(p, pick, args.cpu_seconds, sample_blocks=len(pick),
+                                            krylov_above=1, krylov_m=40, krylov_tol=1e-10)
+    return line
 
 
 def _time_stream(plan, x, y, k, stream, torch):
@@ -965,22 +996,28 @@ def _c1_summary(args, torch, lem, L) -> dict:
 
 
 def bench_c4(args) -> dict:
-    """Served Poisson stream of independent 2D problems (continuous batching)."""
+    """Served Poisson stream of independent 2D problems (continuous batching):
+    --warm-requests requests, then --requests measured ones, arriving in real
+    time at 200 req/s; latency and throughput over the measured requests."""
     import numpy as np
     import lem_inputs as L
     import paper_1505_02248_amd as lem
-    reqs = L.serving_stream(args.requests)
+    nw, nm = args.warm_requests, args.requests
+    log(f"generating {nw + nm} requests")
+    reqs = L.serving_stream(nw + nm)
     import torch
     free, total = torch.cuda.mem_get_info()
-    budget = min(16 << 30, int(free * 0.5))
-    log(f"device memory free {free / 2**30:.1f} GiB of {total / 2**30:.1f} GiB; pool {budget / 2**30:.1f} GiB")
-    srv = lem.Server(hbm_budget=budget, max_active=512, krylov_tol=1e-10)
+    budget = min(32 << 30, int(free * 0.5))
+    log(f"device memory free {free / 2**30:.1f} GiB of {total / 2**30:.1f} GiB; "
+        f"pool {budget / 2**30:.1f} GiB")
+    srv = lem.Server(hbm_budget=budget, max_active=512, krylov_tol=1e-10,
+                     krylov_m_max=args.krylov_m_max, max_overhead=args.max_overhead,
+                     steps_per_tick=args.steps_per_tick)
     pending = list(reqs)
-    arrival = {}
-    done_t = {}
-    ids = {}
+    ids, done_t, arrival = {}, {}, {}
     t0 = time.perf_counter()
     ticks = 0
+    last_log = t0
     while pending or len(done_t) < len(reqs):
         now = time.perf_counter() - t0
         while pending and pending[0].arrival <= now:
@@ -993,30 +1030,40 @@ def bench_c4(args) -> dict:
         ticks += 1
         now = time.perf_counter() - t0
         for rid in list(ids):
-            if rid not in done_t and srv.poll(rid) == "done":
+            if rid not in done_t and srv.poll(rid) in ("done", "failed"):
                 done_t[rid] = now
+        if time.perf_counter() - last_log > 20:
+            last_log = time.perf_counter()
+            log(f"t={now:.1f}s done {len(done_t)}/{len(reqs)} active {active} queued {queued}")
         if active == 0 and queued == 0 and pending and len(done_t) == len(ids):
             time.sleep(max(0.0, pending[0].arrival - (time.perf_counter() - t0)))
-    makespan = max(done_t.values()) - reqs[0].arrival
-    lat = np.array([done_t[r] - arrival[r] for r in done_t])
+    measured = [rid for rid in ids if ids[rid].rid >= nw]
+    lat = np.array([done_t[r] - arrival[r] for r in measured])
+    first = min(arrival[r] for r in measured)
+    end = max(done_t[r] for r in measured)
+    dof = sum(ids[r].problem.N * ids[r].n_steps for r in measured)
+    val = dof / (end - first)
+    span = max(arrival[r] for r in measured) - first
+    offered = dof / span
     methods = {}
-    for rid in ids:
-        m = srv.request_info(rid)["method"]
-        methods[m] = methods.get(m, 0) + 1
-    dof = sum(r.problem.N * r.n_steps for r in reqs)
-    val = dof / makespan
-    offered = sum(r.problem.N * r.n_steps for r in reqs) / (reqs[-1].arrival - reqs[0].arrival)
-    wl = {"workload": f"served Poisson stream ({len(reqs)} requests, 200 req/s) of 2D periodic "
-                      "advection-diffusion, n in {64,128,256,512}, nu log-uniform [1e-4,1e-2], "
-                      "dt in {1,2,4} dx, 20-200 steps, FP64, continuous batching",
-          "requests": len(reqs), "methods": methods, "pool_bytes": budget}
+    failed = 0
+    for rid in measured:
+        info = srv.request_info(rid)
+        methods[info["method"]] = methods.get(info["method"], 0) + 1
+        failed += info["state"] == "failed"
+    wl = {"workload": f"served Poisson stream ({nw} warm-up + {nm} measured requests, 200 req/s) "
+                      "of 2D periodic advection-diffusion, n in {64,128,256,512}, nu log-uniform "
+                      "[1e-4,1e-2], dt in {1,2,4} dx, 20-200 steps, FP64, continuous batching",
+          "requests": nm, "warm_requests": nw, "methods": methods, "pool_bytes": budget,
+          "max_overhead": args.max_overhead, "steps_per_tick": args.steps_per_tick,
+          "krylov_m_max": args.krylov_m_max}
     extras = {"p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
               "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
-              "mean_latency_ms": float(lat.mean() * 1e3), "makespan_s": makespan,
-              "offered_dof_steps_per_s": offered, "ticks": ticks,
+              "mean_latency_ms": float(lat.mean() * 1e3), "measured_span_s": end - first,
+              "offered_dof_steps_per_s": offered, "ticks": ticks, "failed": failed,
               "device_status": srv.query()["device_status"]}
     log(extras)
-    return _line(args, wl, val, "DOF-steps/s", ticks, makespan, "f64", extras)
+    return _line(args, wl, val, "DOF-steps/s", ticks, end - first, "f64", extras)
 
 
 if __name__ == "__main__":

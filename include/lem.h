@@ -133,7 +133,7 @@ typedef struct {
   int32_t halo_max;
   double halo_tol;       /* per-step relative bound the halo must meet      */
   int32_t krylov_m;      /* Krylov dimension; 0 = calibrate per block       */
-  int32_t krylov_m_max;  /* largest dimension allowed: <= 30 for local
+  int32_t krylov_m_max;  /* largest dimension allowed: <= 40 for local
                             actions, <= 48 for LEM_METHOD_GLOBAL            */
   int32_t max_substeps;  /* largest number of equal sub-steps per step      */
   double krylov_tol;     /* relative tolerance of the Krylov estimate       */
@@ -148,6 +148,11 @@ typedef struct {
                             columns only, the periodic coupling along the
                             columns kept inside every box; exported boxes
                             then read (ox, 0, core, n, h)                   */
+  int32_t core_max;      /* uneven cores (core = 0): largest core side tried
+                            per 64x64 tile, 16, 32 or 64 (0 = 64).  With
+                            autotune set, the planner builds the partitions
+                            with core_max 32 and 64, times a step of each on
+                            a probe state and keeps the faster one          */
   int32_t tile;          /* dense method, n_states % 64 == 0: launch shape of
                             the apply; -1 = the default shape (or the
                             fastest one when autotune is set), 0..7 = that
@@ -177,6 +182,14 @@ typedef struct {
   double max_estimate;     /* largest Krylov error estimate seen (relative)   */
   double plan_ms;          /* wall time of lem_plan                           */
   int32_t tile_config;     /* launch shape chosen (autotuner id)              */
+  double krylov_bytes_step;     /* Krylov methods: algorithmic basis traffic of
+                                   one step, sum over blocks and members of
+                                   |M_i| * 8 * (m (m + 1) + 3 m) * sub-steps
+                                   bytes (each basis row read twice per
+                                   Arnoldi column, classical Gram-Schmidt) */
+  double krylov_bytes_streamed; /* the part of it on blocks whose basis is
+                                   streamed through device memory (the rest
+                                   stays in LDS)                           */
 } lem_plan_info;
 
 typedef struct lem_plan_s* lem_plan_t;
@@ -201,8 +214,9 @@ void lem_options_default(lem_options* opt);
  * Errors: LEM_ERR_INVALID for a bad operator/options (c must divide n, a box
  * c + 2h must be < n unless it spans the whole axis), LEM_ERR_UNSUPPORTED for
  * combinations not built (column-wise dense, bf16 with variable coefficients,
- * ...), LEM_ERR_NOMEM, LEM_ERR_HIP, LEM_ERR_NOT_CONVERGED when no (m,
- * sub-step) pair within the limits meets krylov_tol. */
+ * Krylov boxes above 9216 points -- 9215 with a forcing --, ...),
+ * LEM_ERR_NOMEM, LEM_ERR_HIP, LEM_ERR_NOT_CONVERGED when no (m, sub-step)
+ * pair within the limits meets krylov_tol. */
 lem_status lem_plan(const lem_operator* op, double dt, const lem_options* opt,
                     void* stream, lem_plan_t* out);
 
@@ -332,8 +346,9 @@ lem_status lem_plan_destroy(lem_plan_t plan);
  * memory (state, coefficients, work space) is taken from one pool of
  * hbm_budget bytes reserved at creation.  Requests are admitted first come,
  * first served while the pool and max_active allow.  Every lem_server_tick
- * advances every active request by one step of (5); the local problems of all
- * active LEM requests run in shared Krylov launches.  Every block's arithmetic
+ * advances every active request by steps_per_tick steps of (5) (fewer when
+ * it has fewer left); the local problems of all active LEM requests run in
+ * shared Krylov launches, one set per step.  Every block's arithmetic
  * depends only on its own request, so a request's result is the same whether
  * it runs alone or in a mix.  A server is not thread-safe.
  * ------------------------------------------------------------------------ */
@@ -349,10 +364,14 @@ typedef struct {
   double max_overhead;   /* largest (local points / core points) before a
                             request falls back to the global method, >= 1    */
   double krylov_tol;     /* relative Krylov tolerance per step                 */
-  int32_t krylov_m_max;  /* <= 30                                              */
+  int32_t krylov_m_max;  /* <= 40                                              */
   int32_t max_substeps;
   int32_t dry_run;       /* host-only scheduling: no device memory or kernels;
                             a finished request returns its initial state     */
+  int32_t steps_per_tick; /* steps per tick of every active request, >= 1;
+                            requests are admitted and retired between ticks,
+                            so larger values trade admission latency for
+                            fewer host synchronizations                      */
 } lem_server_options;
 
 /* A request whose step latched a device-side failure (non-finite values or a
@@ -379,7 +398,7 @@ typedef struct {
 } lem_server_info;
 
 /* Defaults: 8 GiB pool, 256 active, halo tol 1e-8 in [4, 32], overhead 4,
- * Krylov tol 1e-12, m <= 30, <= 64 sub-steps. */
+ * Krylov tol 1e-12, m <= 30, <= 64 sub-steps, one step per tick. */
 void lem_server_options_default(lem_server_options* opt);
 
 /* Reserve the pool and create a server working on `stream`.  Errors:
@@ -393,8 +412,9 @@ lem_status lem_server_create(const lem_server_options* opt, void* stream, lem_se
 lem_status lem_server_submit(lem_server_t s, const lem_operator* op, double dt,
                              int32_t n_steps, const double* x0_host, uint64_t* id);
 
-/* Admit queued requests, advance every active request by one step, retire
- * the finished ones (their results are copied to host memory).  Blocks until
+/* Admit queued requests, advance every active request by steps_per_tick
+ * steps (at most the steps it has left), retire the finished ones (their
+ * results are copied to host memory) and the failed ones.  Blocks until
  * the tick's device work is done.  Optional outputs: active / queued counts. */
 lem_status lem_server_tick(lem_server_t s, int32_t* n_active, int32_t* n_queued);
 

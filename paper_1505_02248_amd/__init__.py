@@ -54,7 +54,8 @@ class _Options(ctypes.Structure):
                 ("max_substeps", ctypes.c_int32), ("krylov_tol", ctypes.c_double),
                 ("use_graph", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("dry_run", ctypes.c_int32), ("expm", ctypes.c_int32),
-                ("columns", ctypes.c_int32), ("tile", ctypes.c_int32)]
+                ("columns", ctypes.c_int32), ("core_max", ctypes.c_int32),
+                ("tile", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -66,7 +67,8 @@ class _Info(ctypes.Structure):
                 ("squarings", ctypes.c_int32), ("bytes_blocks", ctypes.c_int64),
                 ("bytes_work", ctypes.c_int64), ("device_status", ctypes.c_int32),
                 ("max_estimate", ctypes.c_double), ("plan_ms", ctypes.c_double),
-                ("tile_config", ctypes.c_int32)]
+                ("tile_config", ctypes.c_int32), ("krylov_bytes_step", ctypes.c_double),
+                ("krylov_bytes_streamed", ctypes.c_double)]
 
 
 _lib = None
@@ -200,7 +202,8 @@ class Plan:
                  halo_tol: float = 1e-8, krylov_m: int = 0, krylov_m_max: int = 30,
                  max_substeps: int = 64, krylov_tol: float = 1e-13,
                  use_graph: bool = False, autotune: bool = False, dry_run: bool = False,
-                 columns: bool = False, expm: str = "pade", tile: int = -1, stream=None):
+                 columns: bool = False, expm: str = "pade", tile: int = -1, core_max: int = 0,
+                 stream=None):
         lib = load()
         o = _Options()
         lib.lem_options_default(ctypes.byref(o))
@@ -213,6 +216,7 @@ class Plan:
         o.use_graph, o.autotune, o.dry_run = int(use_graph), int(autotune), int(dry_run)
         o.columns = int(columns)
         o.tile = int(tile)
+        o.core_max = int(core_max)
         o.expm = {"pade": 0, "taylor": 1}[expm]
         self.op, self.dt, self.n_states, self.method = op, float(dt), int(n_states), method
         if op.forcing is not None and op.forcing.size != op.N * int(n_states):
@@ -380,7 +384,8 @@ class _ServerOptions(ctypes.Structure):
                 ("halo_tol", ctypes.c_double), ("halo_min", ctypes.c_int32),
                 ("halo_max", ctypes.c_int32), ("max_overhead", ctypes.c_double),
                 ("krylov_tol", ctypes.c_double), ("krylov_m_max", ctypes.c_int32),
-                ("max_substeps", ctypes.c_int32), ("dry_run", ctypes.c_int32)]
+                ("max_substeps", ctypes.c_int32), ("dry_run", ctypes.c_int32),
+                ("steps_per_tick", ctypes.c_int32)]
 
 
 class _RequestInfo(ctypes.Structure):
@@ -431,7 +436,7 @@ class Server:
                  halo_tol: float = 1e-8, halo_min: int = 4, halo_max: int = 32,
                  max_overhead: float = 4.0, krylov_tol: float = 1e-12,
                  krylov_m_max: int = 30, max_substeps: int = 64, dry_run: bool = False,
-                 stream=None):
+                 steps_per_tick: int = 1, stream=None):
         lib = _server_lib()
         o = _ServerOptions()
         lib.lem_server_options_default(ctypes.byref(o))
@@ -439,6 +444,7 @@ class Server:
         o.halo_tol, o.halo_min, o.halo_max = halo_tol, halo_min, halo_max
         o.max_overhead, o.krylov_tol = max_overhead, krylov_tol
         o.krylov_m_max, o.max_substeps, o.dry_run = krylov_m_max, max_substeps, int(dry_run)
+        o.steps_per_tick = int(steps_per_tick)
         h = ctypes.c_void_p()
         st = 0 if dry_run else _stream_handle(stream)
         _check(lib.lem_server_create(ctypes.byref(o), ctypes.c_void_p(st), ctypes.byref(h)))

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "liblem.so")
-SOURCES = ["krylov_lem.hip", "krylov_calib.hip", "dense.hip", "global_krylov.hip", "rosenbrock.hip", "schrodinger.hip",
+SOURCES = ["krylov_lem.hip", "krylov_big.hip", "krylov_calib.hip", "dense.hip", "global_krylov.hip", "rosenbrock.hip", "schrodinger.hip",
            "global_static.hip", "lem_host.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -471,6 +471,7 @@ lem_status make_partition(lem_plan_s* p) {
     // modelled cost: local points per core point, weighted up when the Krylov
     // basis must stream through device memory instead of staying in LDS.
     const int cands[3] = {16, 32, 64};
+    const int cmax = o.core_max > 0 ? o.core_max : 64;
     const int mguess = std::max(8, std::min(o.krylov_m_max, 30));
     for (int ty = 0; ty < n / 64; ++ty)
       for (int tx = 0; tx < n / 64; ++tx) {
@@ -478,6 +479,7 @@ lem_status make_partition(lem_plan_s* p) {
         std::vector<Box> bestb;
         int best_cl = 0;
         for (int c : cands) {
+          if (c > cmax) continue;
           std::vector<Box> bs;
           int cl_before = p->n_clamped;
           for (int by = 0; by < 64 / c; ++by)
@@ -550,9 +552,10 @@ lem::KBlock make_kblock(const lem_plan_s* p, const Box& b, int m, int nsub, int 
   return k;
 }
 
-// Launch shape of one block: the LDS-resident kernel (variant 1) when its
-// whole basis fits in LDS, else the general kernel (variant 0) with the basis
-// in LDS or streamed through device memory.
+// Launch shape of one block: the Krylov kernel with its basis in LDS when the
+// whole basis fits there, else with the basis streamed through device memory
+// (variants 1, and 2 with the augmented coordinate); boxes above 4096 points
+// or dimensions above 30 take the large-box kernel (variants 3 and 4).
 struct LaunchKey {
   int variant, nt, pmax;
   bool vlds;
@@ -566,7 +569,12 @@ struct LaunchKey {
 LaunchKey launch_key(int ndim, int nloc, int m, size_t* lds, int aug = 0) {
   int nt, pm;
   lem::krylov_lds_config(ndim, nloc, &nt, &pm);
-  if (nt == 0 || m > lem::krylov_lds_max_m()) return {-1, 0, 0, false};
+  if (nt == 0 || m > lem::krylov_lds_max_m()) {
+    lem::krylov_big_config(nloc, &nt, &pm);
+    if (nt == 0 || m > lem::krylov_big_max_m()) return {-1, 0, 0, false};
+    *lds = lem::krylov_big_lds_bytes(nt, m);
+    return {aug ? 4 : 3, nt, pm, false};
+  }
   const size_t with_v = lem::krylov_lds_bytes(nt, m, nloc, true, aug);
   const int variant = aug ? 2 : 1;  // 2: kernels with the augmented coordinate
   if (pm <= 8 && nt <= 256 && with_v <= 160 * 1024) {  // wide shapes stream the basis
@@ -584,7 +592,8 @@ double block_cost(int ndim, int nloc, int m, int nsub) {
   size_t lds;
   const LaunchKey k = launch_key(ndim, nloc, m, &lds);
   if (k.variant < 0) return INFINITY;
-  const double f = k.vlds ? 1.0 : 4.0;
+  // the large-box kernel reads each direction twice more per column
+  const double f = k.vlds ? 1.0 : (k.variant >= 3 ? 4.5 : 4.0);
   return f * nsub * (double)nloc * (m * (m + 3.0) + 40.0);
 }
 
@@ -597,10 +606,11 @@ lem_status bucketize(std::vector<lem::KBlock>& kb, std::vector<lem_plan_s::Bucke
     const int nloc = kb[i].Lx * kb[i].Ly + kb[i].aug;  // basis row (plus augmented coordinate)
     const LaunchKey key = launch_key(kb[i].ndim, nloc, kb[i].m, &need[i], kb[i].aug);
     if (key.variant < 0)
-      return fail(LEM_ERR_UNSUPPORTED, "local box larger than 4096 points (4095 when forced)");
-    const size_t stage = lem::krylov_stage_bytes(key.nt, key.vlds, kb[i].mu_off >= 0,
-                                                 kb[i].varvel != 0, kb[i].ndim, kb[i].Lx,
-                                                 kb[i].Ly);
+      return fail(LEM_ERR_UNSUPPORTED, "local box larger than 9216 points (9215 when forced)");
+    const size_t stage = key.variant >= 3 ? 0
+                         : lem::krylov_stage_bytes(key.nt, key.vlds, kb[i].mu_off >= 0,
+                                                   kb[i].varvel != 0, kb[i].ndim, kb[i].Lx,
+                                                   kb[i].Ly);
     kb[i].stage = (stage > 0 && need[i] + stage <= 160 * 1024) ? 1 : 0;
     if (kb[i].stage) need[i] += stage;
     groups[key].push_back((int)i);
@@ -627,6 +637,7 @@ lem_status bucketize(std::vector<lem::KBlock>& kb, std::vector<lem_plan_s::Bucke
       if (!g.first.vlds) {
         k.v_off = voff;
         voff += (int64_t)(k.m + 1 + k.aug) * (k.Lx * k.Ly + k.aug) * ns;
+        if (g.first.variant >= 3) voff += lem::krylov_big_pad(g.first.nt, g.first.pmax);
       }
       out.push_back(k);
     }
@@ -637,14 +648,26 @@ lem_status bucketize(std::vector<lem::KBlock>& kb, std::vector<lem_plan_s::Bucke
   return LEM_OK;
 }
 
+// One Krylov launch of a bucket's blocks with the kernel its variant names.
+hipError_t launch_bucket(int variant, const lem::KBlock* blocks, int count, int ns, int nt,
+                         int pmax, bool vlds, size_t lds, const double* src, double* dst,
+                         const double* coef, double* vwork, double* diag, int* status,
+                         double* calib, int mode, hipStream_t s) {
+  if (variant >= 3)
+    return lem::launch_krylov_big(blocks, count, ns, nt, pmax, lds, src, dst, coef, vwork, diag,
+                                  status, calib, mode, variant == 4, s);
+  return lem::launch_krylov_lds(blocks, count, ns, nt, pmax, vlds, lds, src, dst, coef, vwork,
+                                diag, status, calib, mode, variant == 2, s);
+}
+
 lem_status launch_buckets(const lem_plan_s* p, const lem::KBlock* d_kb,
                           const std::vector<lem_plan_s::Bucket>& bks, int ns, const double* src,
                           double* dst, double* vwork, double* diag, double* calib, int mode,
                           hipStream_t st) {
   auto launch = [&](const lem_plan_s::Bucket& b, hipStream_t s) -> lem_status {
-    hipError_t e = lem::launch_krylov_lds(d_kb + b.first, b.count, ns, b.nt, b.pmax, b.vlds,
-                                          b.lds, src, dst, p->d_coef, vwork, diag, p->d_status,
-                                          calib, mode, b.variant == 2, s);
+    hipError_t e = launch_bucket(b.variant, d_kb + b.first, b.count, ns, b.nt, b.pmax, b.vlds,
+                                 b.lds, src, dst, p->d_coef, vwork, diag, p->d_status, calib,
+                                 mode, s);
     if (e != hipSuccess)
       return fail(LEM_ERR_HIP, std::string("Krylov launch: ") + hipGetErrorString(e));
     return LEM_OK;
@@ -1421,7 +1444,7 @@ lem_status check_options(const lem_options* o) {
   if (o->core < 0 || o->halo < 0) return fail(LEM_ERR_INVALID, "core and halo must be >= 0");
   if (o->halo == 0 && (o->halo_min < 0 || o->halo_max < o->halo_min || !(o->halo_tol > 0)))
     return fail(LEM_ERR_INVALID, "decay-bound halo needs 0 <= halo_min <= halo_max, halo_tol > 0");
-  const int mlim = o->method == LEM_METHOD_GLOBAL ? lem::kMaxKrylov : lem::krylov_lds_max_m();
+  const int mlim = o->method == LEM_METHOD_GLOBAL ? lem::kMaxKrylov : lem::krylov_big_max_m();
   if (o->krylov_m < 0 || o->krylov_m > mlim || o->krylov_m_max < 2 || o->krylov_m_max > mlim)
     return fail(LEM_ERR_INVALID, "Krylov dimension must be in [2, " + std::to_string(mlim) + "]");
   if (o->max_substeps < 1) return fail(LEM_ERR_INVALID, "max_substeps must be >= 1");
@@ -1432,6 +1455,8 @@ lem_status check_options(const lem_options* o) {
     return fail(LEM_ERR_UNSUPPORTED, "column-wise cores need the Krylov method and a core width");
   if (o->tile < -1 || o->tile >= lem::kApplyConfigs)
     return fail(LEM_ERR_INVALID, "tile must be -1 or a shape id in [0, 7]");
+  if (o->core_max != 0 && o->core_max != 16 && o->core_max != 32 && o->core_max != 64)
+    return fail(LEM_ERR_INVALID, "core_max must be 0, 16, 32 or 64");
   return LEM_OK;
 }
 
@@ -1459,6 +1484,14 @@ void fill_info(const lem_plan_s* p, lem_plan_info* in) {
   in->bytes_work = p->bytes_work;
   in->plan_ms = p->plan_ms;
   in->tile_config = p->tile;
+  for (const auto& bk : p->buckets)
+    for (int i = bk.first; i < bk.first + bk.count && i < (int)p->kb_host.size(); ++i) {
+      const lem::KBlock& k = p->kb_host[i];
+      const double bytes = (double)p->ns * (k.Lx * k.Ly + k.aug) * 8.0 *
+                           ((double)k.m * (k.m + 1) + 3.0 * k.m) * k.nsub;
+      in->krylov_bytes_step += bytes;
+      if (!bk.vlds) in->krylov_bytes_streamed += bytes;
+    }
 }
 
 bool overlap(const void* a, const void* b, size_t bytes) {
@@ -1474,8 +1507,90 @@ int device_status_of(int bits) {
                                              : LEM_OK;
 }
 
+lem_status create_plan_one(const lem_operator* op, double dt, const lem_options* opt,
+                           void* stream, lem::Arena* arena, lem_plan_t* out);
+
+// Time of one step of a Krylov plan on a probe state (ms, median of three
+// after one warm-up step); buffers from hipMalloc.
+lem_status time_krylov_step(lem_plan_s* p, double* ms) {
+  const int64_t tot = p->N * p->ns;
+  double *a = nullptr, *b = nullptr;
+  hipStream_t st = p->stream;
+  LEM_TRY(dalloc(p, &a, (size_t)tot));
+  LEM_TRY(dalloc(p, &b, (size_t)tot));
+  LEM_HIP(lem::launch_probe_fill(a, tot, 4242u, st));
+  hipEvent_t e[4];
+  for (auto& ev : e) LEM_HIP(hipEventCreate(&ev));
+  lem_status s = run_one(p, a, b, st);
+  for (int r = 0; r < 3 && s == LEM_OK; ++r) {
+    if (hipEventRecord(e[r], st) != hipSuccess) s = fail(LEM_ERR_HIP, "event record failed");
+    if (s == LEM_OK) s = run_one(p, a, b, st);
+  }
+  if (s == LEM_OK && hipEventRecord(e[3], st) != hipSuccess) s = fail(LEM_ERR_HIP, "event record failed");
+  if (s == LEM_OK && hipEventSynchronize(e[3]) != hipSuccess) s = fail(LEM_ERR_HIP, "event sync failed");
+  float t[3] = {0, 0, 0};
+  for (int r = 0; r < 3 && s == LEM_OK; ++r) hipEventElapsedTime(&t[r], e[r], e[r + 1]);
+  std::sort(t, t + 3);
+  *ms = t[1];
+  for (auto& ev : e) hipEventDestroy(ev);
+  dfree(p, a);
+  dfree(p, b);
+  // the timing steps latched into the plan's status word and estimates: start clean
+  if (s == LEM_OK) s = hipMemsetAsync(p->d_status, 0, sizeof(int), st) == hipSuccess
+                           ? LEM_OK : fail(LEM_ERR_HIP, "status reset failed");
+  if (s == LEM_OK && p->d_diag)
+    s = hipMemsetAsync(p->d_diag, 0, p->boxes.size() * p->ns * sizeof(double), st) == hipSuccess
+            ? LEM_OK : fail(LEM_ERR_HIP, "estimate reset failed");
+  return s;
+}
+
+// Uneven Krylov partitions with autotune: the partitions whose largest core is
+// 32 and 64 points are planned and timed on a probe state; the faster is kept.
+// (Boxes of 64^2 cores cut the buffer overhead, but each is one workgroup with
+// a long Arnoldi chain: whether they pay depends on the grid and the CUs.)
 lem_status create_plan(const lem_operator* op, double dt, const lem_options* opt, void* stream,
                        lem::Arena* arena, lem_plan_t* out) {
+  if (!opt || !out || opt->method != LEM_METHOD_KRYLOV || opt->core != 0 || !opt->autotune ||
+      opt->dry_run || arena || opt->core_max == 16)
+    return create_plan_one(op, dt, opt, stream, arena, out);
+  const auto t0 = std::chrono::steady_clock::now();
+  lem_plan_t best = nullptr;
+  double best_ms = INFINITY;
+  for (int cm : {32, 64}) {
+    if (opt->core_max && cm > opt->core_max) continue;
+    lem_options o = *opt;
+    o.core_max = cm;
+    lem_plan_t p = nullptr;
+    lem_status s = create_plan_one(op, dt, &o, stream, arena, &p);
+    if (s == LEM_ERR_UNSUPPORTED) continue;  // boxes past the kernels' limits
+    if (s != LEM_OK) {
+      delete best;
+      return s;
+    }
+    double ms = INFINITY;
+    s = time_krylov_step(p, &ms);
+    if (s != LEM_OK) {
+      delete p;
+      delete best;
+      return s;
+    }
+    if (ms < best_ms) {
+      delete best;
+      best = p;
+      best_ms = ms;
+    } else {
+      delete p;
+    }
+  }
+  if (!best) return create_plan_one(op, dt, opt, stream, arena, out);
+  best->opt.core_max = opt->core_max;
+  best->plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *out = best;
+  return LEM_OK;
+}
+
+lem_status create_plan_one(const lem_operator* op, double dt, const lem_options* opt,
+                           void* stream, lem::Arena* arena, lem_plan_t* out) {
   if (!out) return fail(LEM_ERR_INVALID, "out is NULL");
   *out = nullptr;
   LEM_TRY(check_options(opt));
@@ -1516,11 +1631,12 @@ lem_status create_plan(const lem_operator* op, double dt, const lem_options* opt
     if (s != LEM_OK) return guard(s);
   }
   if (p->method == LEM_METHOD_KRYLOV) {
-    // the Krylov kernels hold a basis row of at most 4096 points (the box
+    // the Krylov kernels hold a basis row of at most 9216 points (the box
     // plus the augmented coordinate of a forced step)
     for (const Box& b : p->boxes)
-      if ((int64_t)box_lx(b, p->op.n) * box_ly(b, p->op.n, p->op.ndim) + (p->forced ? 1 : 0) > 4096)
-        return guard(fail(LEM_ERR_UNSUPPORTED, "local box larger than 4096 points (4095 when forced)"));
+      if ((int64_t)box_lx(b, p->op.n) * box_ly(b, p->op.n, p->op.ndim) + (p->forced ? 1 : 0) >
+          lem::krylov_big_max_n())
+        return guard(fail(LEM_ERR_UNSUPPORTED, "local box larger than 9216 points (9215 when forced)"));
   }
   if (!p->dry) {
     hipStream_t st = p->stream;
@@ -1637,6 +1753,7 @@ void lem_options_default(lem_options* o) {
   o->use_graph = 0;
   o->autotune = 0;
   o->dry_run = 0;
+  o->core_max = 0;
   o->tile = -1;
 }
 
@@ -2069,7 +2186,7 @@ void choose_partition(const lem_server_s* s, ServerReq& r, const Op& op) {
     if (op.n % c || c + 2 * h >= op.n) continue;
     const int L = c + 2 * h;
     const int64_t nloc = op.ndim == 2 ? (int64_t)L * L : L;
-    if (nloc > 4096) continue;
+    if (nloc > lem::krylov_big_max_n()) continue;
     const double ov = op.ndim == 2 ? (double)L * L / ((double)c * c) : (double)L / c;
     if (ov < best) { best = ov; r.core = c; }
   }
@@ -2170,6 +2287,7 @@ void lem_server_options_default(lem_server_options* o) {
   o->krylov_m_max = 30;
   o->max_substeps = 64;
   o->dry_run = 0;
+  o->steps_per_tick = 1;
 }
 
 lem_status lem_server_create(const lem_server_options* opt, void* stream, lem_server_t* out) {
@@ -2178,8 +2296,8 @@ lem_status lem_server_create(const lem_server_options* opt, void* stream, lem_se
   if (opt->hbm_budget < 4096 || opt->max_active < 1 || !(opt->halo_tol > 0) ||
       opt->halo_min < 0 || opt->halo_max < opt->halo_min || !(opt->max_overhead >= 1) ||
       !(opt->krylov_tol > 0) || opt->krylov_m_max < 2 ||
-      opt->krylov_m_max > lem::krylov_lds_max_m() ||
-      opt->max_substeps < 1)
+      opt->krylov_m_max > lem::krylov_big_max_m() ||
+      opt->max_substeps < 1 || opt->steps_per_tick < 1)
     return fail(LEM_ERR_INVALID, "invalid server options");
   auto s = new lem_server_s();
   s->opt = *opt;
@@ -2277,65 +2395,82 @@ lem_status lem_server_tick(lem_server_t s, int32_t* n_active, int32_t* n_queued)
     }
     s->active.push_back(r.id);
   }
-  // 2. one step of every active request
+  // 2. steps_per_tick steps of every active request (at most the steps it
+  // has left).  Whole-grid global requests run their steps on side streams;
+  // the blocks of all LEM requests go into one shared launch per shape and
+  // step, the tables of every step uploaded at once.
+  std::vector<int> take(s->active.size(), 0);
+  for (size_t a = 0; a < s->active.size(); ++a) {
+    const ServerReq& r = s->reqs[s->active[a]];
+    take[a] = std::min(s->opt.steps_per_tick, r.n_steps - r.done);
+  }
   if (!s->opt.dry_run && !s->active.empty()) {
-    size_t nb = 0;
-    for (uint64_t id : s->active) nb += s->reqs[id].plan->kb_host.size();
-    nb = std::max<size_t>(nb, 1);
-    LEM_TRY(server_grow(s, nb));
-    std::map<LaunchKey, std::vector<lem::KBlock>> groups;
-    std::map<LaunchKey, size_t> lds;
-    int diag = 0, n_side = 0;
-    LEM_HIP(hipEventRecord(s->ev_fork, s->st));  // states uploaded at admission
-    for (uint64_t id : s->active) {
-      ServerReq& r = s->reqs[id];
-      double* in = r.buf[r.done & 1];
-      double* out = r.buf[(r.done + 1) & 1];
-      if (r.plan->kb_host.empty()) {  // whole-grid Krylov launches of its own
-        hipStream_t ss = s->side[n_side % lem_server_s::kSide];
-        if (n_side < lem_server_s::kSide) LEM_HIP(hipStreamWaitEvent(ss, s->ev_fork, 0));
-        ++n_side;
-        LEM_TRY(run_step(r.plan, in, out, ss));
-        continue;
-      }
-      const lem_plan_s* p = r.plan;
-      for (const auto& bk : p->buckets)
-        for (int i = bk.first; i < bk.first + bk.count; ++i) {
-          lem::KBlock k = p->kb_host[i];
-          k.xin = in;
-          k.xout = out;
-          k.coef = p->d_coef;
-          k.vwork = p->d_vwork + k.v_off;
-          k.status = s->d_rstatus + r.slot;
-          k.diag = diag++;
-          LaunchKey key{bk.variant, bk.nt, bk.pmax, bk.vlds};
-          groups[key].push_back(k);
-          lds[key] = std::max(lds[key], bk.lds);
-        }
+    int kmax = 0;
+    size_t need = 0;
+    for (size_t a = 0; a < s->active.size(); ++a) {
+      kmax = std::max(kmax, take[a]);
+      need += (size_t)take[a] * s->reqs[s->active[a]].plan->kb_host.size();
     }
+    LEM_TRY(server_grow(s, std::max<size_t>(need, 1)));
+    int n_side = 0;
+    LEM_HIP(hipEventRecord(s->ev_fork, s->st));  // states uploaded at admission
+    for (size_t a = 0; a < s->active.size(); ++a) {
+      ServerReq& r = s->reqs[s->active[a]];
+      if (!r.plan->kb_host.empty()) continue;
+      // whole-grid Krylov launches of its own
+      hipStream_t ss = s->side[n_side % lem_server_s::kSide];
+      if (n_side < lem_server_s::kSide) LEM_HIP(hipStreamWaitEvent(ss, s->ev_fork, 0));
+      ++n_side;
+      for (int k = 0; k < take[a]; ++k)
+        LEM_TRY(run_step(r.plan, r.buf[(r.done + k) & 1], r.buf[(r.done + k + 1) & 1], ss));
+    }
+    struct Launch { LaunchKey key; size_t lds, off; int count; };
+    std::vector<Launch> launches;
     size_t off = 0;
-    for (auto& g : groups) {
-      // costliest blocks first (as in a plan's own launches)
-      std::stable_sort(g.second.begin(), g.second.end(), [](const lem::KBlock& x, const lem::KBlock& y) {
-        return block_cost(x.ndim, x.Lx * x.Ly + x.aug, x.m, x.nsub) >
-               block_cost(y.ndim, y.Lx * y.Ly + y.aug, y.m, y.nsub);
-      });
-      std::memcpy(s->h_table + off, g.second.data(), g.second.size() * sizeof(lem::KBlock));
-      off += g.second.size();
+    int diag = 0;
+    for (int k = 0; k < kmax; ++k) {
+      std::map<LaunchKey, std::vector<lem::KBlock>> groups;
+      std::map<LaunchKey, size_t> lds;
+      for (size_t a = 0; a < s->active.size(); ++a) {
+        ServerReq& r = s->reqs[s->active[a]];
+        if (take[a] <= k || r.plan->kb_host.empty()) continue;
+        const lem_plan_s* p = r.plan;
+        for (const auto& bk : p->buckets)
+          for (int i = bk.first; i < bk.first + bk.count; ++i) {
+            lem::KBlock kb = p->kb_host[i];
+            kb.xin = r.buf[(r.done + k) & 1];
+            kb.xout = r.buf[(r.done + k + 1) & 1];
+            kb.coef = p->d_coef;
+            kb.vwork = p->d_vwork + kb.v_off;
+            kb.status = s->d_rstatus + r.slot;
+            kb.diag = diag++;
+            const LaunchKey key{bk.variant, bk.nt, bk.pmax, bk.vlds};
+            groups[key].push_back(kb);
+            lds[key] = std::max(lds[key], bk.lds);
+          }
+      }
+      for (auto& g : groups) {
+        // costliest blocks first (as in a plan's own launches)
+        std::stable_sort(g.second.begin(), g.second.end(),
+                         [](const lem::KBlock& x, const lem::KBlock& y) {
+                           return block_cost(x.ndim, x.Lx * x.Ly + x.aug, x.m, x.nsub) >
+                                  block_cost(y.ndim, y.Lx * y.Ly + y.aug, y.m, y.nsub);
+                         });
+        std::memcpy(s->h_table + off, g.second.data(), g.second.size() * sizeof(lem::KBlock));
+        launches.push_back({g.first, lds[g.first], off, (int)g.second.size()});
+        off += g.second.size();
+      }
     }
     if (off) LEM_HIP(hipMemcpyAsync(s->d_table, s->h_table, off * sizeof(lem::KBlock),
                                     hipMemcpyHostToDevice, s->st));
-    off = 0;
-    for (auto& g : groups) {
-      const int nb = (int)g.second.size();
+    // launches of step k + 1 follow those of step k on the serving stream
+    for (const Launch& L : launches) {
       // every block carries its request's status word (the launch's own is unused)
-      hipError_t e = lem::launch_krylov_lds(s->d_table + off, nb, 1, g.first.nt, g.first.pmax,
-                                            g.first.vlds, lds[g.first], nullptr, nullptr,
-                                            nullptr, nullptr, s->d_diag, s->d_rstatus, nullptr, 0,
-                                            false, s->st);
+      hipError_t e = launch_bucket(L.key.variant, s->d_table + L.off, L.count, 1, L.key.nt,
+                                   L.key.pmax, L.key.vlds, L.lds, nullptr, nullptr, nullptr,
+                                   nullptr, s->d_diag, s->d_rstatus, nullptr, 0, s->st);
       if (e != hipSuccess)
         return fail(LEM_ERR_HIP, std::string("serving launch: ") + hipGetErrorString(e));
-      off += g.second.size();
     }
     // the retiring copies below (on the serving stream) follow the side streams
     for (int k = 0; k < std::min(n_side, lem_server_s::kSide); ++k) {
@@ -2345,12 +2480,12 @@ lem_status lem_server_tick(lem_server_t s, int32_t* n_active, int32_t* n_queued)
   }
   // 3. advance counters, retire finished and failed requests
   std::vector<uint64_t> finished, still;
-  for (uint64_t id : s->active) {
-    ServerReq& r = s->reqs[id];
-    r.done++;
-    s->dof_steps += (double)r.N();
-    if (r.done == r.n_steps) finished.push_back(id);
-    else still.push_back(id);
+  for (size_t a = 0; a < s->active.size(); ++a) {
+    ServerReq& r = s->reqs[s->active[a]];
+    r.done += take[a];
+    s->dof_steps += (double)r.N() * take[a];
+    if (r.done == r.n_steps) finished.push_back(s->active[a]);
+    else still.push_back(s->active[a]);
   }
   for (uint64_t id : finished) {
     ServerReq& r = s->reqs[id];

@@ -27,6 +27,21 @@ hipError_t launch_krylov_lds(const KBlock* blocks, int n_blocks, int ns, int nt,
                              const double* coef, double* vwork, double* diag, int* status,
                              double* calib, int mode, bool aug, hipStream_t st);
 
+// ---- Krylov LEM step for large boxes / dimensions (krylov_big.hip): basis
+// streamed through device memory, boxes of up to krylov_big_max_n() points
+// (basis row, with the augmented coordinate), m <= krylov_big_max_m()
+int krylov_big_max_m();
+int krylov_big_max_n();
+size_t krylov_big_lds_bytes(int nt, int m);
+// doubles of padding after each block's basis slices (lanes past the box read
+// past a row's end)
+int64_t krylov_big_pad(int nt, int pmax);
+void krylov_big_config(int nloc, int* nt, int* pmax);
+hipError_t launch_krylov_big(const KBlock* blocks, int n_blocks, int ns, int nt, int pmax,
+                             size_t lds, const double* x_in, double* x_out, const double* coef,
+                             double* vwork, double* diag, int* status, double* calib, int mode,
+                             bool aug, hipStream_t st);
+
 // ---- dense local exponentials (dense.hip)
 size_t dense_op_size();
 void dense_op_fill(void* dst, int i, double w0, double wW, double wE, double wS, double wN,

@@ -25,14 +25,15 @@ REQS = {"A": (128, 2e-3, 2, 7, 11), "B": (64, 1e-4, 1, 3, 12), "C": (256, 5e-3, 
         "D": (64, 1e-2, 4, 2, 14), "E": (128, 1e-4, 1, 4, 15)}
 
 
-def make_server():
-    return lem.Server(hbm_budget=2 << 30, max_active=16, krylov_tol=1e-14)
+def make_server(steps_per_tick=1):
+    return lem.Server(hbm_budget=2 << 30, max_active=16, krylov_tol=1e-14,
+                      steps_per_tick=steps_per_tick)
 
 
-def run_alone(name):
+def run_alone(name, steps_per_tick=1):
     n, nu, mult, steps, seed = REQS[name]
     o, dt, x = problem(n, nu, mult, seed)
-    s = make_server()
+    s = make_server(steps_per_tick)
     rid = s.submit(o, dt, steps, x)
     while s.poll(rid) != "done":
         s.tick()
@@ -40,9 +41,12 @@ def run_alone(name):
     return s.fetch(rid), info
 
 
-def test_results_alone_equal_results_in_the_mix_and_the_oracle():
-    alone = {k: run_alone(k) for k in REQS}
-    s = make_server()
+@pytest.mark.parametrize("spt", [1, 3])
+def test_results_alone_equal_results_in_the_mix_and_the_oracle(spt):
+    # spt steps per tick: requests of 2..5 steps finish inside a tick, others
+    # over several ticks; arrivals interleave with the ticks
+    alone = {k: run_alone(k, spt) for k in REQS}
+    s = make_server(spt)
     ids = {}
     order = [("B",), ("A",), (), ("C", "D"), (), ("E",)]
     for group in order:  # arrivals while others are on the device

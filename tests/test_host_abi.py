@@ -104,19 +104,23 @@ def test_invalid_arguments_are_reported():
             lem.Plan(o, 2 / 64, method="dense", core=16, halo=4, n_states=64, tile=tile,
                      dry_run=True)
         assert e.value.status == 1
-    # Krylov boxes hold at most 4096 points, one fewer with a forcing (the
-    # augmented coordinate); the check precedes any device work
-    big = lem.Operator(2, 128, 1 / 128, (1.0, 0.5), 1e-3)
-    lem.Plan(big, 2 / 128, method="krylov", core=32, halo=16, dry_run=True)
+    # Krylov boxes hold at most 9216 points, one fewer with a forcing (the
+    # augmented coordinate), and dimensions up to 40; the checks precede any
+    # device work
+    big = lem.Operator(2, 256, 1 / 256, (1.0, 0.5), 1e-3)
+    lem.Plan(big, 2 / 256, method="krylov", core=64, halo=16, krylov_m_max=40, dry_run=True)
     with pytest.raises(lem.LemError) as e:
-        lem.Plan(big, 2 / 128, method="krylov", core=64, halo=8, dry_run=True)
-    assert e.value.status == 6 and "4096" in str(e.value)
-    g = np.ones((128 * 128, 1))
-    forced = lem.Operator(2, 128, 1 / 128, (1.0, 0.5), 1e-3, forcing=g)
-    lem.Plan(forced, 2 / 128, method="krylov", core=32, halo=15, dry_run=True)
+        lem.Plan(big, 2 / 256, method="krylov", core=64, halo=17, dry_run=True)
+    assert e.value.status == 6 and "9216" in str(e.value)
     with pytest.raises(lem.LemError) as e:
-        lem.Plan(forced, 2 / 128, method="krylov", core=32, halo=16, dry_run=True)
-    assert e.value.status == 6 and "4095" in str(e.value)
+        lem.Plan(big, 2 / 256, method="krylov", core=64, halo=8, krylov_m_max=41, dry_run=True)
+    assert e.value.status == 1
+    g = np.ones((256 * 256, 1))
+    forced = lem.Operator(2, 256, 1 / 256, (1.0, 0.5), 1e-3, forcing=g)
+    lem.Plan(forced, 2 / 256, method="krylov", core=64, halo=15, dry_run=True)
+    with pytest.raises(lem.LemError) as e:
+        lem.Plan(forced, 2 / 256, method="krylov", core=64, halo=16, dry_run=True)
+    assert e.value.status == 6 and "9215" in str(e.value)
 
 
 def test_dry_plan_cannot_step_and_reports_sizes():
