@@ -612,7 +612,7 @@ def bench_f4(args) -> dict:
             f"err {err_dense:.2e}")
         kplan = lem.Plan(opr, p.dt, method="krylov", core=0, halo=0, halo_min=2, halo_max=16,
                          halo_tol=1e-8, n_states=ns, krylov_tol=1e-10, use_graph=True,
-                         stream=stream)
+                         krylov_m_max=args.krylov_m_max, autotune=True, stream=stream)
         kq = kplan.query()
         t_kry, _ = timed(kplan, x, max(3, steps // 8))
         err_kry = err_vs(kplan, ref, x, 3)
@@ -629,7 +629,8 @@ def bench_f4(args) -> dict:
                               "rel_l2_vs_global_after_3_steps": err_dense},
             "krylov_lem": {"ms_per_step": 1e3 * t_kry, "halo_range": [kq["halo_min"], kq["halo_max"]],
                            "m_range": [kq["m_min"], kq["m_max"]], "substeps_max": kq["substeps_max"],
-                           "n_blocks": kq["n_blocks"], "rel_l2_vs_global_after_3_steps": err_kry},
+                           "n_blocks": kq["n_blocks"], "n_loc_max": kq["n_loc_max"],
+                           "plan_ms": kq["plan_ms"], "rel_l2_vs_global_after_3_steps": err_kry},
             "global": {"ms_per_step": 1e3 * t_glob, "m": gq["m_max"], "substeps": gq["substeps_max"]},
             "stored_over_global_per_step": t_glob / t_dense,
             "krylov_lem_over_global_per_step": t_glob / t_kry,
@@ -646,7 +647,7 @@ def bench_f4(args) -> dict:
         for label, kw in (("columns", dict(core=8, columns=True)), ("square", dict(core=16))):
             pl = lem.Plan(ob, pb.dt, method="krylov", halo=0, halo_min=2, halo_max=24,
                           halo_tol=1e-8, n_states=nsb, krylov_tol=1e-10, use_graph=True,
-                          stream=stream, **kw)
+                          krylov_m_max=args.krylov_m_max, stream=stream, **kw)
             qb = pl.query()
             t, _ = timed(pl, xb, steps)
             res[label] = {"dof_steps_per_s": pb.N * nsb / t, "ms_per_step": 1e3 * t,
@@ -1046,11 +1047,16 @@ def bench_c4(args) -> dict:
     span = max(arrival[r] for r in measured) - first
     offered = dof / span
     methods = {}
-    failed = 0
+    failed = []
     for rid in measured:
         info = srv.request_info(rid)
         methods[info["method"]] = methods.get(info["method"], 0) + 1
-        failed += info["state"] == "failed"
+        if info["state"] == "failed":
+            pr = ids[rid].problem
+            failed.append({"n": pr.n, "nu": pr.nu, "dt_over_dx": round(pr.dt / pr.dx),
+                           "steps": ids[rid].n_steps, "method": info["method"],
+                           "error": info["error"], "steps_done": info["steps_done"],
+                           "m_max": info["m_max"], "substeps": info["substeps_max"]})
     wl = {"workload": f"served Poisson stream ({nw} warm-up + {nm} measured requests, 200 req/s) "
                       "of 2D periodic advection-diffusion, n in {64,128,256,512}, nu log-uniform "
                       "[1e-4,1e-2], dt in {1,2,4} dx, 20-200 steps, FP64, continuous batching",
@@ -1060,7 +1066,8 @@ def bench_c4(args) -> dict:
     extras = {"p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
               "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
               "mean_latency_ms": float(lat.mean() * 1e3), "measured_span_s": end - first,
-              "offered_dof_steps_per_s": offered, "ticks": ticks, "failed": failed,
+              "offered_dof_steps_per_s": offered, "ticks": ticks, "failed": len(failed),
+              "failed_requests": failed[:20],
               "device_status": srv.query()["device_status"]}
     log(extras)
     return _line(args, wl, val, "DOF-steps/s", ticks, end - first, "f64", extras)

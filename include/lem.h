@@ -73,8 +73,18 @@ enum {
                              squaring, applied as matrix products (sections 3
                              and 4: "computed only at the first time step")  */
   LEM_METHOD_GLOBAL = 2,  /* no decomposition (D = 1): global Krylov action  */
-  LEM_METHOD_ROSENBROCK = 3 /* exponential Rosenbrock-Euler for Burgers; plans
+  LEM_METHOD_ROSENBROCK = 3, /* exponential Rosenbrock-Euler for Burgers; plans
                                come from lem_ere_plan only                    */
+  LEM_METHOD_KRONECKER = 4  /* stored local exponentials of a 2D constant-
+                               coefficient operator in Kronecker-factored form:
+                               on a rectangular box the local matrix is the
+                               Kronecker sum of two 1D tridiagonal matrices,
+                               so exp(dt A_M) = exp(dt A_y) (x) exp(dt A_x)
+                               exactly and a block's core is
+                               E_y[core,:] X E_x[core,:]^T for the box values
+                               X; the two 1D exponentials are computed once
+                               (opt.expm) -- uniform core, box side
+                               core + 2 halo <= 128, FP64, no forcing       */
 };
 
 /* Arithmetic used to apply stored local exponentials (dense method only). */
@@ -151,15 +161,18 @@ typedef struct {
   int32_t core_max;      /* uneven cores (core = 0): largest core side tried
                             per 64x64 tile, 16, 32 or 64 (0 = 64).  With
                             autotune set, the planner builds the partitions
-                            with core_max 32 and 64, times a step of each on
-                            a probe state and keeps the faster one          */
+                            with core_max 32 and 64, each with the Krylov
+                            dimension capped at 30 and at krylov_m_max,
+                            times a step of each on a probe state and keeps
+                            the fastest                                     */
   int32_t tile;          /* dense method, n_states % 64 == 0: launch shape of
                             the apply; -1 = the default shape (or the
                             fastest one when autotune is set), 0..7 = that
                             shape for FP64/FP32 (rows per wave, K chunk,
                             waves: 32,16,4 / 32,32,4 / 32,32,8 / 64,32,4 /
-                            16,32,8 / 16,32,4 / 16,16,8 / 16,32,16), 0..1
-                            for split bf16 (32 or 64 rows per wave); a shape
+                            16,32,8 / 16,32,4 / 16,16,8 / 16,32,16), 0..3
+                            for split bf16 (rows per wave, waves: 32,4 /
+                            64,4 / 32,8 / 64,8); a shape
                             that does not fit the block is LEM_ERR_UNSUPPORTED
                             at plan time                                    */
 } lem_options;

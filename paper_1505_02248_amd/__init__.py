@@ -27,7 +27,7 @@ LEM_OK = 0
 STATUS_NAMES = {0: "LEM_OK", 1: "LEM_ERR_INVALID", 2: "LEM_ERR_NOMEM", 3: "LEM_ERR_HIP",
                 4: "LEM_ERR_NOT_CONVERGED", 5: "LEM_ERR_BUDGET", 6: "LEM_ERR_UNSUPPORTED",
                 7: "LEM_ERR_NOT_FOUND", 8: "LEM_ERR_NONFINITE"}
-METHODS = {"krylov": 0, "dense": 1, "global": 2}
+METHODS = {"krylov": 0, "dense": 1, "global": 2, "kronecker": 4}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x2": 2, "bf16x3": 3}
 
 

@@ -18,7 +18,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "liblem.so")
 SOURCES = ["krylov_lem.hip", "krylov_big.hip", "krylov_calib.hip", "dense.hip", "global_krylov.hip", "rosenbrock.hip", "schrodinger.hip",
-           "global_static.hip", "lem_host.cpp"]
+           "global_static.hip", "kron.hip", "host_op.cpp", "host_krylov.cpp", "host_dense.cpp",
+           "host_problems.cpp", "host_plan.cpp", "host_server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

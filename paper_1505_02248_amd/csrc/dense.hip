@@ -588,11 +588,13 @@ __global__ void split_pieces_kernel(const double* __restrict__ x, int64_t total,
   }
 }
 
-template <int NTERMS, int WM, bool PRE>
-__global__ __launch_bounds__(256) void apply_bf16_kernel(ApplyArgs a) {
+template <int NTERMS, int WM, int NW, bool PRE>
+__global__ __launch_bounds__(64 * NW) void apply_bf16_kernel(ApplyArgs a) {
   constexpr int BN = 64, KC = 32, RT = WM / 16, CT = BN / 16;
   constexpr int NP = NTERMS == 6 ? 3 : 2;  // operand pieces in use
   constexpr int KG = KC / 8 + 1;           // padded k-groups per LDS column
+  constexpr int KPT = KC / NW;             // staged rows per thread (8 or 4)
+  static_assert(NW == 4 || NW == 8, "four or eight waves");
   __shared__ bf16x8 Xs[2][NP][BN][KG];
   extern __shared__ int64_t goff[];        // gathered row offsets (cols_p)
   const int total = a.n_blocks * a.row_tiles * a.col_tiles;
@@ -603,7 +605,7 @@ __global__ __launch_bounds__(256) void apply_bf16_kernel(ApplyArgs a) {
   const int blk = rest / a.row_tiles;
   const DBlock b = a.blocks[blk];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int row0 = rtile * 4 * WM + wv * WM;
+  const int row0 = rtile * NW * WM + wv * WM;
   const int col0 = ct0 * BN;
   const bf16x8* E = reinterpret_cast<const bf16x8*>(a.E);
   const int64_t estride8 = a.e_stride / 8;  // per piece, in 8-element groups
@@ -611,7 +613,7 @@ __global__ __launch_bounds__(256) void apply_bf16_kernel(ApplyArgs a) {
   const bool wave_live = row0 < a.rows_p;
   const int rtw = wave_live ? row0 >> 4 : 0;
   const bf16x8* Ew = E + (int64_t)b.unique * 3 * estride8 + (int64_t)rtw * ksteps * 64 + lane;
-  for (int l = tid; l < a.cols_p; l += 256) {
+  for (int l = tid; l < a.cols_p; l += 64 * NW) {
     const int lc = l < a.cols ? l : a.cols - 1;  // padded columns of E are zero
     goff[l] = dense_gather(b, lc, a.n, a.ndim) * a.ns + col0;
   }
@@ -631,33 +633,45 @@ __global__ __launch_bounds__(256) void apply_bf16_kernel(ApplyArgs a) {
         ea[p][i] = Ew[p * estride8 + ((int64_t)i * ksteps + ch) * 64];
   };
   const int xc = tid & 63, xg = tid >> 6;
-  // staged X of one chunk: eight local rows of column xc, as float64 values
+  // staged X of one chunk: KPT local rows of column xc, as float64 values
   // (split here) or as pieces (split once per step by split_pieces_kernel)
   typedef typename std::conditional<NP == 3, bf16x4, bf16x2>::type piece_t;
-  typedef typename std::conditional<PRE, piece_t[8], double[8]>::type xreg_t;
+  typedef typename std::conditional<PRE, piece_t[KPT], double[KPT]>::type xreg_t;
   auto load_x = [&](int ch, xreg_t& v) {
     if constexpr (PRE) {
       const piece_t* xp = reinterpret_cast<const piece_t*>(a.xp);
 #pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = xp[goff[ch * KC + xg * 8 + e] + xc];
+      for (int e = 0; e < KPT; ++e) v[e] = xp[goff[ch * KC + xg * KPT + e] + xc];
     } else {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = a.x_in[goff[ch * KC + xg * 8 + e] + xc];
+      for (int e = 0; e < KPT; ++e) v[e] = a.x_in[goff[ch * KC + xg * KPT + e] + xc];
+    }
+  };
+  // rows xg*KPT .. xg*KPT + KPT - 1 of the chunk land in k-group xg*KPT/8
+  // (all of it with eight rows per thread, one half of it with four)
+  auto put = [&](int buf, int p, const bf16x8& v) {
+    if constexpr (KPT == 8) {
+      Xs[buf][p][xc][xg] = v;
+    } else {
+      bf16x4 h4;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) h4[e] = v[e];
+      reinterpret_cast<bf16x4*>(&Xs[buf][p][xc][xg >> 1])[xg & 1] = h4;
     }
   };
   auto store_x = [&](const xreg_t& v, int buf) {
     if constexpr (PRE) {
       bf16x8 pc[NP];
 #pragma unroll
-      for (int e = 0; e < 8; ++e)
+      for (int e = 0; e < KPT; ++e)
 #pragma unroll
         for (int p = 0; p < NP; ++p) pc[p][e] = v[e][p];
 #pragma unroll
-      for (int p = 0; p < NP; ++p) Xs[buf][p][xc][xg] = pc[p];
+      for (int p = 0; p < NP; ++p) put(buf, p, pc[p]);
     } else {
       bf16x8 pc[NP];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
+      for (int e = 0; e < KPT; ++e) {
         const __bf16 hi = bf16_near(v[e]);
         const double r1 = v[e] - bf16_val(hi);
         const __bf16 mid = bf16_near(r1);
@@ -666,7 +680,7 @@ __global__ __launch_bounds__(256) void apply_bf16_kernel(ApplyArgs a) {
         if constexpr (NP == 3) pc[2][e] = bf16_near(r1 - bf16_val(mid));
       }
 #pragma unroll
-      for (int p = 0; p < NP; ++p) Xs[buf][p][xc][xg] = pc[p];
+      for (int p = 0; p < NP; ++p) put(buf, p, pc[p]);
     }
   };
   auto mfma_chunk = [&](const bf16x8 (&ea)[NP][RT], int buf) {
@@ -998,8 +1012,8 @@ bool dense_apply_supported(int precision, int cfg, int ns, int rows_p, int cols_
     return rows_p % kApplyShapes[cfg][0] == 0 && cols_p % kApplyShapes[cfg][1] == 0;
   }
   if (precision != 2 && precision != 3) return false;
-  if (cfg < 0 || cfg > 1) return false;
-  const int wm = cfg ? 64 : 32;
+  if (cfg < 0 || cfg >= kApplyBf16Configs) return false;
+  const int wm = (cfg & 1) ? 64 : 32;
   return rows_p % wm == 0 && cols_p % 32 == 0 && (size_t)cols_p * sizeof(int64_t) <= 64 * 1024;
 }
 
@@ -1049,21 +1063,33 @@ hipError_t dense_apply(int precision, int cfg, const void* blocks, const void* E
 #undef LEM_APPLY
     return hipGetLastError();
   }
-  const int wm = (cfg & 1) ? 64 : 32;
-  a.row_tiles = (rows_p + 4 * wm - 1) / (4 * wm);
+  // split-bf16 shapes: rows per wave 32 (even ids) or 64 (odd), four waves
+  // (ids 0, 1) or eight (ids 2, 3) per workgroup
+  const int wm = (cfg & 1) ? 64 : 32, nw = cfg >= 2 ? 8 : 4;
+  a.row_tiles = (rows_p + nw * wm - 1) / (nw * wm);
   const dim3 g(n_blocks * a.row_tiles * a.col_tiles);
   const size_t gl = (size_t)cols_p * sizeof(int64_t);  // gathered row offsets
   if (xpieces) a.xp = (const __bf16*)xpieces;  // split by dense_split_pieces
-#define LEM_BF16(NT_, WM_)                                                                     \
-  if (a.xp) hipLaunchKernelGGL((apply_bf16_kernel<NT_, WM_, true>), g, dim3(256), gl, st, a); \
-  else hipLaunchKernelGGL((apply_bf16_kernel<NT_, WM_, false>), g, dim3(256), gl, st, a);
+#define LEM_BF16(NT_, WM_, NW_)                                                            \
+  if (a.xp)                                                                                \
+    hipLaunchKernelGGL((apply_bf16_kernel<NT_, WM_, NW_, true>), g, dim3(64 * NW_), gl, st, a); \
+  else                                                                                     \
+    hipLaunchKernelGGL((apply_bf16_kernel<NT_, WM_, NW_, false>), g, dim3(64 * NW_), gl, st, a);
+#define LEM_BF16_SHAPES(NT_)                              \
+  switch (cfg) {                                          \
+    case 0: LEM_BF16(NT_, 32, 4) break;                   \
+    case 1: LEM_BF16(NT_, 64, 4) break;                   \
+    case 2: LEM_BF16(NT_, 32, 8) break;                   \
+    default: LEM_BF16(NT_, 64, 8) break;                  \
+  }
   if (precision == 2) {
-    if (wm == 32) { LEM_BF16(3, 32) } else { LEM_BF16(3, 64) }
+    LEM_BF16_SHAPES(3)
   } else if (precision == 3) {
-    if (wm == 32) { LEM_BF16(6, 32) } else { LEM_BF16(6, 64) }
+    LEM_BF16_SHAPES(6)
   } else {
     return hipErrorInvalidValue;
   }
+#undef LEM_BF16_SHAPES
 #undef LEM_BF16
   return hipGetLastError();
 }

@@ -61,6 +61,18 @@ struct KBlock {
   int* status;                // status word of this block's problem, or null
 };
 
+// One region of the Kronecker-factored dense method: a c x c core with an
+// h-point buffer (box side L = c + 2h) of a 2D constant-coefficient operator
+// on an n x n grid, and the core rows of the two 1D local exponentials.
+struct KronBlock {
+  int32_t ox, oy, c, h, L, n, ns, pad;
+  const double* x_in;   // state of this block's problem (N x ns)
+  double* x_out;
+  const double* ex;     // c x L: rows h..h+c-1 of exp(dt A_x) on the box
+  const double* ey;     // c x L: rows h..h+c-1 of exp(dt A_y)
+  int* status;          // status word of this block's problem, or null
+};
+
 struct KrylovArgs {
   const KBlock* blocks;
   const double* x_in;

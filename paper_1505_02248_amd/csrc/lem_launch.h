@@ -42,6 +42,13 @@ hipError_t launch_krylov_big(const KBlock* blocks, int n_blocks, int ns, int nt,
                              double* vwork, double* diag, int* status, double* calib, int mode,
                              bool aug, hipStream_t st);
 
+// ---- Kronecker-factored local exponentials (kron.hip): one launch over
+// blocks x members (grid y = max_ns), box sides up to kron_max_side()
+int kron_max_side();
+size_t kron_lds_bytes(int L);
+hipError_t launch_kron(const KronBlock* blocks, int n_blocks, int max_ns, int max_L,
+                       const double* x_in, double* x_out, int* status, hipStream_t st);
+
 // ---- dense local exponentials (dense.hip)
 size_t dense_op_size();
 void dense_op_fill(void* dst, int i, double w0, double wW, double wE, double wS, double wN,
@@ -70,8 +77,10 @@ size_t dense_block_size();
 void dense_block_fill(void* dst, int i, int ox, int oy, int cx, int cy, int h, int Lx, int Ly,
                       int unique);
 // Tile shapes of the FP64/FP32 apply (the autotuner times each at plan time);
-// the split-bf16 apply uses cfg & 1 (32 or 64 rows per wave).
+// the split-bf16 apply has four: 32 or 64 rows per wave (cfg & 1), four or
+// eight waves per workgroup (cfg >= 2).
 constexpr int kApplyConfigs = 8;
+constexpr int kApplyBf16Configs = 4;
 // Whether tile shape cfg of the apply serves this precision and padded block
 // (cfg is ignored for ensembles that are not a multiple of 64).
 bool dense_apply_supported(int precision, int cfg, int ns, int rows_p, int cols_p);

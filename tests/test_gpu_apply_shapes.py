@@ -10,8 +10,6 @@ exact local exponentials, sections 3 and 4).
   the benchmark does: FP64 within 1e-12, FP32 and split bf16 (six products)
   within 1e-6.
 * Small ensembles (3 states) in FP32 (the eight-lane kernel)."""
-import functools
-
 import numpy as np
 import pytest
 
@@ -20,6 +18,8 @@ from oracle import lem as olem
 from oracle import operator as op
 from oracle import partition as P
 from oracle.metrics import rel_l2
+from oracle_cache import one_step as oracle_one_step
+from oracle_cache import problem
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -38,21 +38,12 @@ def run(plan, x0, steps=1):
     return xout.cpu().numpy()
 
 
-@functools.lru_cache(maxsize=None)
 def c1_problem():
-    return L.workload_2d_ensemble()  # 256^2, 64 states
+    return problem("c1")  # 256^2, 64 states
 
 
-@functools.lru_cache(maxsize=None)
 def c3_problem():
-    return L.workload_2d_mixed()  # 512^2, 128 states
-
-
-@functools.lru_cache(maxsize=None)
-def oracle_one_step(which, core, h):
-    p = c1_problem() if which == "c1" else c3_problem()
-    boxes = P.uniform_boxes(2, p.n, core, h)
-    return olem.run(op.sparse(op.from_problem(p)), boxes, 2, p.n, p.states, 1)
+    return problem("c3")  # 512^2, 128 states
 
 
 def check_boxes(plan, n, core, h):
@@ -102,6 +93,26 @@ def test_c3_full_size(prec, tol, h):
     print(f"c3 h={h} {prec} tile={plan.query()['tile_config']}: rel l2 {err:.2e}")
     assert err <= tol
     assert plan.query()["device_status"] == 0
+
+
+@pytest.mark.parametrize("tile", range(4))
+def test_c3_every_split_bf16_shape(tile):
+    # rows per wave 32 / 64, four / eight waves per workgroup, six products
+    p = c3_problem()
+    plan = lem.Plan(lem.Operator.from_problem(p), p.dt, method="dense", precision="bf16x3",
+                    core=32, halo=15, n_states=128, tile=tile)
+    assert plan.query()["tile_config"] == tile
+    got = run(plan, p.states)
+    assert rel_l2(got, oracle_one_step("c3", 32, 15)) <= 1e-6
+
+
+@pytest.mark.parametrize("tile", range(4))
+def test_c1_every_split_bf16_shape_three_products(tile):
+    p = c1_problem()
+    plan = lem.Plan(lem.Operator.from_problem(p), p.dt, method="dense", precision="bf16x2",
+                    core=16, halo=14, n_states=64, tile=tile)
+    got = run(plan, p.states)
+    assert rel_l2(got, oracle_one_step("c1", 16, 14)) <= 2e-5
 
 
 def test_fp32_small_ensemble():

@@ -17,12 +17,28 @@ import paper_1505_02248_amd as lem  # noqa: E402
 
 
 def problem(n, nu, mult, seed):
+    # nu < 0: a lognormal field of median |nu| (variable coefficients)
     x = L.smooth_states_2d(n, 1, seed, n_modes=8, kmax=4)[:, 0]
+    if nu < 0:
+        f = L.lognormal_field_2d(n, seed, median=-nu)
+        return lem.Operator(2, n, 1.0 / n, (1.0, 0.5), 0.0, nu_field=f), mult / n, x
     return lem.Operator(2, n, 1.0 / n, (1.0, 0.5), nu), mult / n, x
 
 
+def weights(n, nu, dt, seed):
+    if nu < 0:
+        return op.weights(2, n, 1.0 / n, dt, (1.0, 0.5),
+                          nu_field=L.lognormal_field_2d(n, seed, median=-nu))
+    return op.weights(2, n, 1.0 / n, dt, (1.0, 0.5), nu=nu)
+
+
+# constant coefficients take the Kronecker-factored method when a core fits
+# (A-E), variable ones the Krylov method (F: 64^2 cores, 9216-point boxes);
+# G and H need buffers beyond the cap and take the global method (G on one
+# periodic Krylov box, co-batched; H on the whole-grid kernels)
 REQS = {"A": (128, 2e-3, 2, 7, 11), "B": (64, 1e-4, 1, 3, 12), "C": (256, 5e-3, 4, 5, 13),
-        "D": (64, 1e-2, 4, 2, 14), "E": (128, 1e-4, 1, 4, 15)}
+        "D": (64, 1e-2, 4, 2, 14), "E": (128, 1e-4, 1, 4, 15), "F": (128, -2e-4, 1, 4, 16),
+        "G": (64, 3e-2, 4, 2, 17), "H": (128, 2e-2, 4, 2, 17)}
 
 
 def make_server(steps_per_tick=1):
@@ -35,8 +51,9 @@ def run_alone(name, steps_per_tick=1):
     o, dt, x = problem(n, nu, mult, seed)
     s = make_server(steps_per_tick)
     rid = s.submit(o, dt, steps, x)
-    while s.poll(rid) != "done":
+    while s.poll(rid) in ("queued", "active"):
         s.tick()
+    assert s.poll(rid) == "done", name
     info = s.request_info(rid)
     return s.fetch(rid), info
 
@@ -48,15 +65,16 @@ def test_results_alone_equal_results_in_the_mix_and_the_oracle(spt):
     alone = {k: run_alone(k, spt) for k in REQS}
     s = make_server(spt)
     ids = {}
-    order = [("B",), ("A",), (), ("C", "D"), (), ("E",)]
+    order = [("B",), ("A", "F"), (), ("C", "D", "G"), (), ("E", "H")]
     for group in order:  # arrivals while others are on the device
         for k in group:
             n, nu, mult, steps, seed = REQS[k]
             o, dt, x = problem(n, nu, mult, seed)
             ids[k] = s.submit(o, dt, steps, x)
         s.tick()
-    while any(s.poll(i) != "done" for i in ids.values()):
+    while any(s.poll(i) in ("queued", "active") for i in ids.values()):
         s.tick()
+    assert all(s.poll(i) == "done" for i in ids.values())
     assert s.query()["device_status"] == 0
     for k, rid in ids.items():
         got = s.fetch(rid)
@@ -64,15 +82,16 @@ def test_results_alone_equal_results_in_the_mix_and_the_oracle(spt):
         assert np.array_equal(got, ref), k
         n, nu, mult, steps, seed = REQS[k]
         o, dt, x = problem(n, nu, mult, seed)
-        W = op.weights(2, n, 1.0 / n, dt, (1.0, 0.5), nu=nu)
+        W = weights(n, nu, dt, seed)
         if info["method"] == "global":
             want = ge.fft_steps(W, x, steps)
         else:
             boxes = P.uniform_boxes(2, n, info["core"], info["halo"])
-            want = olem.run(op.sparse(W), boxes, 2, n, x, steps)
+            want = olem.run(op.sparse(W), boxes, 2, n, x, steps, krylov_above=3000,
+                            krylov_m=40, krylov_tol=1e-16)
         assert rel_l2(got, want) <= 1e-12, (k, info)
     methods = {k: alone[k][1]["method"] for k in REQS}
-    assert "global" in methods.values() and "krylov" in methods.values()
+    assert set(methods.values()) == {"global", "krylov", "kronecker"}, methods
 
 
 def test_a_nonfinite_request_fails_alone():
@@ -82,13 +101,14 @@ def test_a_nonfinite_request_fails_alone():
     alone = {k: run_alone(k) for k in REQS}
     krylov_k = next(k for k in REQS if alone[k][1]["method"] == "krylov")
     global_k = next(k for k in REQS if alone[k][1]["method"] == "global")
+    kron_k = next(k for k in REQS if alone[k][1]["method"] == "kronecker")
     s = make_server()
     ids, bad = {}, {}
     for k in REQS:
         n, nu, mult, steps, seed = REQS[k]
         o, dt, x = problem(n, nu, mult, seed)
         ids[k] = s.submit(o, dt, steps, x)
-        if k in (krylov_k, global_k):
+        if k in (krylov_k, global_k, kron_k):
             xb = x.copy()
             xb[3] = np.nan
             bad[k] = s.submit(o, dt, steps, xb)

@@ -193,6 +193,11 @@ def test_column_partition_maps_and_halos_match_oracle():
         assert H.accepts(co, 2, 1e-8, 2, box.h, G, cut_y=False), box
     q = plan.query()
     assert q["n_loc_max"] == (16 + 2 * q["halo_max"]) * 64
+    p128 = L.workload_2d_columns(n=128, n_states=1)
+    with pytest.raises(lem.LemError) as e:  # column boxes above 4096 points are refused
+        lem.Plan(lem.Operator.from_problem(p128), p128.dt, core=16, halo=10, columns=True,
+                 dry_run=True)
+    assert e.value.status == 6 and "4096" in str(e.value)
     with pytest.raises(lem.LemError):  # column-wise cores are a Krylov feature
         lem.Plan(lem.Operator.from_problem(p), p.dt, method="dense", core=16, halo=4,
                  columns=True, dry_run=True)

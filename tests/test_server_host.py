@@ -3,6 +3,7 @@ kernels): admission order, memory budget, slot reuse, limits, errors."""
 import numpy as np
 import pytest
 
+import lem_inputs as L
 import paper_1505_02248_amd as lem
 
 
@@ -69,11 +70,24 @@ def test_oversized_request_rejected_and_invalid_inputs():
 
 
 def test_partition_choice_and_global_fallback():
+    # constant coefficients: Kronecker-factored blocks whenever a core fits
+    # (box side below n and at most 128); variable coefficients: Krylov boxes
+    # within the overhead cap; neither: the global method
     s = lem.Server(hbm_budget=1 << 30, max_active=8, dry_run=True, max_overhead=4.0)
     small = s.submit(op2d(256, nu=1e-3), 2 / 256, 2, np.zeros(256 * 256))
-    wide = s.submit(op2d(64, nu=1e-2), 4 / 64, 2, np.zeros(64 * 64))  # halo too wide for 64^2
+    wide = s.submit(op2d(64, nu=1e-2), 4 / 64, 2, np.zeros(64 * 64))
+    f = L.lognormal_field_2d(256, 16, median=2e-4)
+    var = s.submit(lem.Operator(2, 256, 1 / 256, (1.0, 0.5), 0.0, nu_field=f), 1 / 256, 2,
+                   np.zeros(256 * 256))
+    f = L.lognormal_field_2d(64, 17, median=3e-2)
+    varwide = s.submit(lem.Operator(2, 64, 1 / 64, (1.0, 0.5), 0.0, nu_field=f), 4 / 64, 2,
+                       np.zeros(64 * 64))
     s.tick()
     i1, i2 = s.request_info(small), s.request_info(wide)
-    assert i1["method"] == "krylov" and i1["core"] in (16, 32, 64) and i1["halo"] >= 4
-    assert (i1["core"] + 2 * i1["halo"]) ** 2 <= 4.0 * i1["core"] ** 2
-    assert i2["method"] == "global" and i2["core"] == 0
+    i3, i4 = s.request_info(var), s.request_info(varwide)
+    assert i1["method"] == "kronecker" and i1["core"] in (16, 32, 64) and i1["halo"] >= 4
+    assert i1["core"] + 2 * i1["halo"] < 256
+    assert i2["method"] == "kronecker" and i2["core"] + 2 * i2["halo"] < 64
+    assert i3["method"] == "krylov" and i3["core"] in (16, 32, 64)
+    assert (i3["core"] + 2 * i3["halo"]) ** 2 <= 4.0 * i3["core"] ** 2
+    assert i4["method"] == "global" and i4["core"] == 0
