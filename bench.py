@@ -174,6 +174,8 @@ def parse_args():
     ap.add_argument("--arms", default="fp32,bf16x3,bf16x2",
                     help="c3: reduced-precision applications timed beside FP64 (comma list, "
                          "may be empty)")
+    ap.add_argument("--kron", type=int, default=1,
+                    help="c3: also time the Kronecker-factored local exponentials (1/0)")
     ap.add_argument("--with-c1", type=int, default=1,
                     help="c3: also report the 256^2 x 64-state workload (1/0)")
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -875,6 +877,28 @@ def bench_c3(args) -> dict:
             "tile_config": pl.query()["tile_config"]}
         log(f"{prec}: {extras[f'lem_{prec}']}")
         del pl
+
+    if args.kron:
+        # the same local exponentials in Kronecker-factored form (the box
+        # matrix of a constant-coefficient operator is a Kronecker sum):
+        # two contractions of 2 L^2 c + 2 L c^2 flops per block and member
+        log("planning the Kronecker-factored arm")
+        kp = lem.Plan(opr, p.dt, method="kronecker", core=32, halo=h, n_states=ns)
+        kp.step(x, y, args.warmup)
+        wk, ek = _time_stream(kp, x, y, args.steps, stream, torch)
+        yk = torch.empty_like(x)
+        kp.step(x, yk, 1)
+        L = 32 + 2 * h
+        kflops = (2.0 * L * L * 32 + 2.0 * L * 32 * 32) * 256 * ns
+        kus = 1e3 * ek / args.steps
+        extras["lem_kronecker_fp64"] = {
+            "value": N * ns * args.steps / wk, "us_per_step": kus,
+            "rel_l2_vs_dense_fp64_one_step": _rel(yk, y64, torch),
+            "flops_per_step": kflops, "tflops": kflops / kus / 1e6,
+            "gbs_state": 2.0 * N * ns * 8 / kus / 1e3,
+            "plan_ms": kp.query()["plan_ms"]}
+        log(f"kronecker: {extras['lem_kronecker_fp64']}")
+        del kp
 
     acc = {}
     if not args.no_global:

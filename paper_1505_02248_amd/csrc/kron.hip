@@ -8,7 +8,7 @@
 //     Y = E_y[core rows, :] * X * E_x[core rows, :]^T
 // for the box values X (L x L, y rows, x columns): two small contractions
 // instead of one with the (c^2 x L^2) core block, and the stored data are two
-// c x L matrices.  One workgroup per (block, member): the gathered box in LDS,
+// c x L matrices.  One workgroup per (member, block): the gathered box in LDS,
 // then, per group of 16 core columns, T = X E_x^T (L x 16) in LDS and
 // Y = E_y T written to the core (step 3).
 #include "lem_device.hpp"
@@ -22,6 +22,7 @@ struct KronArgs {
   const double* x_in;  // used when a block carries no state pointers
   double* x_out;
   int* status;         // used when a block carries none
+  int max_ns;          // members per block in the grid (blocks with fewer skip the rest)
 };
 
 constexpr int kKronCols = 16;   // core columns per pass
@@ -34,8 +35,10 @@ __host__ __device__ inline size_t kron_lds_doubles(int L) {
 template <int NT>
 __global__ __launch_bounds__(NT) void kron_apply_kernel(KronArgs a) {
   extern __shared__ double smem[];
-  const KronBlock b = a.blocks[blockIdx.x];
-  const int s = blockIdx.y;
+  // consecutive workgroups take consecutive members of one block: they read
+  // the same cache lines of the member-fastest state
+  const KronBlock b = a.blocks[blockIdx.x / a.max_ns];
+  const int s = blockIdx.x % a.max_ns;
   if (s >= b.ns) return;
   const int L = b.L, c = b.c, h = b.h, n = b.n, ns = b.ns;
   const double* x_in = b.x_in ? b.x_in : a.x_in;
@@ -103,8 +106,8 @@ hipError_t launch_kron(const KronBlock* blocks, int n_blocks, int max_ns, int ma
                                        (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(fn, dim3(n_blocks, max_ns), dim3(256), lds, st,
-                     KronArgs{blocks, n_blocks, x_in, x_out, status});
+  hipLaunchKernelGGL(fn, dim3((unsigned)((int64_t)n_blocks * max_ns)), dim3(256), lds, st,
+                     KronArgs{blocks, n_blocks, x_in, x_out, status, max_ns});
   return hipGetLastError();
 }
 
