@@ -197,6 +197,8 @@ def parse_args():
     ap.add_argument("--max-overhead", type=float, default=9.0,
                     help="c4: largest local/core point ratio before a request takes the "
                          "global method")
+    ap.add_argument("--saturate", type=int, default=1,
+                    help="c4: also time the measured requests submitted all at once (1/0)")
     ap.add_argument("--steps-per-tick", type=int, default=4, help="c4: server steps per tick")
     return ap.parse_args()
 
@@ -713,14 +715,41 @@ def bench_c0(args) -> dict:
                           "rel_l2_vs_global_exact": _rel(y, ref, torch), "halo": q["halo_max"],
                           "m": q["m_max"], "substeps": q["substeps_max"]}
             log(label, res[label])
+            res[label]["_plan"] = plan
     best = max(("lem_krylov_bound", "lem_dense_bound"), key=lambda k: res[k]["dof_steps_per_s"])
+    bplan = res[best]["_plan"]
+    bq = bplan.query()
+    boxes = bplan.maps()[0]
+    # algorithmic bytes of one step of the best form: the Krylov basis traffic
+    # (|M| 8 (m(m+1)+3m) nsub per region) or, for stored blocks, the one
+    # stored core block, the gathered regions and the written cores
+    if best == "lem_krylov_bound":
+        step_bytes = float(bq["krylov_bytes_step"])
+    else:
+        nloc = 64 + 2 * res[best]["halo"]
+        step_bytes = 8.0 * (64 * nloc + len(boxes) * nloc + p.N)
+    us = res[best]["us_per_step"]
+    achieved = step_bytes / (us * 1e-6) / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": f"{best} (whole step, one graph replay; launch-latency bound: 16 "
+                      "regions of 64 points fill 16 of 256 compute units)",
+            "bytes_per_step": step_bytes, "us_per_step": us}
+    for r in res.values():
+        r.pop("_plan", None)
     wl = {"workload": "1D periodic advection-diffusion N=1024, a=1, nu=1e-3, dt=4dx, "
                       "16 cores of 64 points, 100 steps, FP64, HIP graph per step",
           "best_lem": best}
-    return _line(args, wl, res[best]["dof_steps_per_s"], "DOF-steps/s", steps,
+    line = _line(args, wl, res[best]["dof_steps_per_s"], "DOF-steps/s", steps,
                  res[best]["us_per_step"] * steps * 1e-6, "f64",
                  dict(res, lem_over_global=res[best]["dof_steps_per_s"] /
-                      res["global_krylov"]["dof_steps_per_s"]))
+                      res["global_krylov"]["dof_steps_per_s"]), roofline=roof)
+    if not args.no_cpu:
+        log("cpu baseline (oracle, all 16 regions)")
+        kw = ({"krylov_above": 1, "krylov_m": 40, "krylov_tol": 1e-10}
+              if best == "lem_krylov_bound" else {})
+        line["cpu_baseline"] = cpu_baseline(p, boxes, min(args.cpu_seconds, 10.0), **kw)
+    return line
 
 
 def bench_c2(args) -> dict:
@@ -888,13 +917,14 @@ def bench_c3(args) -> dict:
         wk, ek = _time_stream(kp, x, y, args.steps, stream, torch)
         yk = torch.empty_like(x)
         kp.step(x, yk, 1)
-        L = 32 + 2 * h
-        kflops = (2.0 * L * L * 32 + 2.0 * L * 32 * 32) * 256 * ns
+        side = 32 + 2 * h
+        kflops = (2.0 * side * side * 32 + 2.0 * side * 32 * 32) * 256 * ns
         kus = 1e3 * ek / args.steps
         extras["lem_kronecker_fp64"] = {
             "value": N * ns * args.steps / wk, "us_per_step": kus,
             "rel_l2_vs_dense_fp64_one_step": _rel(yk, y64, torch),
             "flops_per_step": kflops, "tflops": kflops / kus / 1e6,
+            "mfma_frac": kflops / kus / 1e6 / MFMA_FP64_PEAK_TFLOPS,
             "gbs_state": 2.0 * N * ns * 8 / kus / 1e3,
             "plan_ms": kp.query()["plan_ms"]}
         log(f"kronecker: {extras['lem_kronecker_fp64']}")
@@ -1093,8 +1123,89 @@ def bench_c4(args) -> dict:
               "offered_dof_steps_per_s": offered, "ticks": ticks, "failed": len(failed),
               "failed_requests": failed[:20],
               "device_status": srv.query()["device_status"]}
+    if args.saturate:
+        # capacity: the measured requests all submitted at once (closed loop)
+        log(f"saturated: {nm} requests submitted at once")
+        sat_ids = {}
+        t0 = time.perf_counter()
+        for r in reqs[nw:]:
+            rid = srv.submit(lem.Operator.from_problem(r.problem), r.problem.dt, r.n_steps,
+                             r.problem.states[:, 0])
+            sat_ids[rid] = r
+        sat_done = {}
+        sat_ticks = 0
+        while len(sat_done) < len(sat_ids):
+            srv.tick()
+            sat_ticks += 1
+            now = time.perf_counter() - t0
+            for rid in sat_ids:
+                if rid not in sat_done and srv.poll(rid) in ("done", "failed"):
+                    sat_done[rid] = now
+        span_s = max(sat_done.values())
+        sat_lat = np.array(list(sat_done.values()))
+        extras["saturated"] = {
+            "dof_steps_per_s": dof / span_s, "seconds": span_s, "ticks": sat_ticks,
+            "p50_completion_ms": float(np.percentile(sat_lat, 50) * 1e3),
+            "p99_completion_ms": float(np.percentile(sat_lat, 99) * 1e3),
+            "failed": sum(srv.poll(r) == "failed" for r in sat_ids)}
     log(extras)
-    return _line(args, wl, val, "DOF-steps/s", ticks, end - first, "f64", extras)
+    # algorithmic state traffic of the served steps: every local method reads
+    # its boxes ((L/c)^2 values per core point) and writes its cores; the
+    # global method reads and writes the state at least once per step
+    byts = 0.0
+    for rid in measured:
+        info, pr = srv.request_info(rid), ids[rid].problem
+        ratio = (((info["core"] + 2 * info["halo"]) / info["core"]) ** 2
+                 if info["core"] else 1.0)
+        byts += 8.0 * pr.N * info["steps_done"] * (ratio + 1.0)
+    achieved = byts / (end - first) / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "all served steps (state read per box + core write per step) over the "
+                      "measured span; arrival-rate bound, not a kernel's own rate",
+            "bytes": byts}
+    line = _line(args, wl, val, "DOF-steps/s", ticks, end - first, "f64", extras, roofline=roof)
+    if not args.no_cpu:
+        log("cpu baseline (oracle, sampled regions of the measured requests)")
+        line["cpu_baseline"] = cpu_baseline_serving(
+            [(ids[r].problem, srv.request_info(r)) for r in measured], min(args.cpu_seconds, 20.0))
+    return line
+
+
+def cpu_baseline_serving(reqs, budget_s: float, regions_per_request: int = 4):
+    """The oracle on the served requests in arrival order, one step each: for
+    a local method the first regions_per_request regions of its partition
+    (Krylov action per region, from the initial state), for the global method
+    the exact step of the whole grid by FFT, until ~budget_s."""
+    from oracle import globalexp as ge
+    from oracle import lem as olem
+    from oracle import operator as op
+    from oracle import partition as P
+    cores, model, ncpu = host_cpu()
+    done, k, t0 = 0, 0, time.perf_counter()
+    sizes = {}
+    for pr, info in reqs:
+        W = op.from_problem(pr)
+        u = pr.states[:, 0]
+        if info["core"]:
+            bx = P.uniform_boxes(2, pr.n, info["core"], info["halo"])[:regions_per_request]
+            olem.step(op.sparse(W), bx, 2, pr.n, u, krylov_above=1, krylov_m=40,
+                      krylov_tol=1e-10)
+            done += len(bx) * info["core"] ** 2
+        else:
+            ge.fft_steps(W, u, 1)
+            done += pr.N
+        k += 1
+        sizes[pr.n] = sizes.get(pr.n, 0) + 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    el = time.perf_counter() - t0
+    return {"value": done / el, "unit": "DOF-steps/s", "cores": cores, "kind": "oracle",
+            "cpu_model": model, "logical_cpus": ncpu,
+            "sample": f"one step of the first {k} measured requests (grid sides {sizes}): "
+                      f"{regions_per_request} regions each by the oracle's Krylov action "
+                      "(numpy float64), or the whole grid by FFT for global-method requests",
+            "seconds": round(el, 3)}
 
 
 if __name__ == "__main__":

@@ -83,7 +83,7 @@ enum {
                                exactly and a block's core is
                                E_y[core,:] X E_x[core,:]^T for the box values
                                X; the two 1D exponentials are computed once
-                               (opt.expm) -- uniform core, box side
+                               (opt.expm) -- uniform core <= 64, box side
                                core + 2 halo <= 128, FP64, no forcing       */
 };
 
@@ -361,7 +361,11 @@ lem_status lem_plan_destroy(lem_plan_t plan);
  * first served while the pool and max_active allow.  Every lem_server_tick
  * advances every active request by steps_per_tick steps of (5) (fewer when
  * it has fewer left); the local problems of all active LEM requests run in
- * shared Krylov launches, one set per step.  Every block's arithmetic
+ * shared launches, one set per step (one Kronecker-factored launch for the
+ * constant-coefficient 2D requests, bucketed Krylov launches for the rest).
+ * The buffer width of a request comes from the decay bound, capped at
+ * halo_max; a request whose bound exceeds the cap, or whose boxes fit
+ * neither kernel, runs the global method.  Every block's arithmetic
  * depends only on its own request, so a request's result is the same whether
  * it runs alone or in a mix.  A server is not thread-safe.
  * ------------------------------------------------------------------------ */
@@ -393,7 +397,7 @@ typedef struct {
  * request has its own status word, so the others are not affected. */
 typedef struct {
   int32_t state;         /* LEM_REQ_*                                          */
-  int32_t method;        /* LEM_METHOD_KRYLOV or LEM_METHOD_GLOBAL             */
+  int32_t method;        /* LEM_METHOD_KRONECKER, _KRYLOV or _GLOBAL           */
   int32_t core, halo;    /* partition (0, 0 for the global method)             */
   int32_t n_blocks, m_max, substeps_max;
   int32_t n_steps, steps_done;
@@ -410,7 +414,9 @@ typedef struct {
   int32_t device_status; /* latched device-side status (0 = fine)              */
 } lem_server_info;
 
-/* Defaults: 8 GiB pool, 256 active, halo tol 1e-8 in [4, 32], overhead 4,
+/* Defaults: 8 GiB pool, 256 active, halo tol 1e-8 in [4, 56] (56: the
+ * widest buffer of a 16-point core in a Kronecker box of side 128; the
+ * Krylov box limit of 9216 points binds earlier), overhead 4,
  * Krylov tol 1e-12, m <= 30, <= 64 sub-steps, one step per tick. */
 void lem_server_options_default(lem_server_options* opt);
 

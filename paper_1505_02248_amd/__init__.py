@@ -433,7 +433,7 @@ class Server:
     """Continuous-batching LEM server (``lem_server_*``); see include/lem.h."""
 
     def __init__(self, hbm_budget: int = 8 << 30, max_active: int = 256,
-                 halo_tol: float = 1e-8, halo_min: int = 4, halo_max: int = 32,
+                 halo_tol: float = 1e-8, halo_min: int = 4, halo_max: int = 56,
                  max_overhead: float = 4.0, krylov_tol: float = 1e-12,
                  krylov_m_max: int = 30, max_substeps: int = 64, dry_run: bool = False,
                  steps_per_tick: int = 1, stream=None):

@@ -389,9 +389,11 @@ lem_status plan_kron(lem_plan_s* p, hipStream_t st) {
                                      "operator, FP64 and no forcing");
   const Box& b0 = p->boxes[0];
   const int c = b0.cx, h = b0.h, L = c + 2 * h;
-  if (L > lem::kron_max_side())
+  if (L > lem::kron_max_side() || c > lem::kron_max_core())
     return fail(LEM_ERR_UNSUPPORTED, "Kronecker-factored boxes are at most " +
-                                         std::to_string(lem::kron_max_side()) + " points per side");
+                                         std::to_string(lem::kron_max_side()) +
+                                         " points per side, cores at most " +
+                                         std::to_string(lem::kron_max_core()));
   const double mux = op.nu * op.dt / (op.dx * op.dx), muy = op.nu * op.dt / (op.dy * op.dy);
   std::vector<double> hA((size_t)2 * L * L, 0.0);
   double* Ax = hA.data();

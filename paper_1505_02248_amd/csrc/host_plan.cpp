@@ -137,8 +137,8 @@ lem_status run_one(lem_plan_s* p, const double* src, double* dst, hipStream_t st
       return LEM_OK;
     }
     case LEM_METHOD_KRONECKER:
-      LEM_HIP(lem::launch_kron(p->d_kron, (int)p->boxes.size(), p->ns, p->kron_L, src, dst,
-                               p->d_status, st));
+      LEM_HIP(lem::launch_kron(p->d_kron, (int)p->boxes.size(), p->ns, p->kron_L,
+                               p->boxes[0].cx, src, dst, p->d_status, st));
       return LEM_OK;
     default:
       LEM_HIP(lem::global_step(p->gw, src, dst, st));
@@ -383,10 +383,13 @@ lem_status create_plan_one(const lem_operator* op, double dt, const lem_options*
     s = make_partition(p);
     if (s != LEM_OK) return guard(s);
   }
-  if (p->method == LEM_METHOD_KRONECKER && 2 * p->boxes[0].h + p->boxes[0].cx > lem::kron_max_side())
+  if (p->method == LEM_METHOD_KRONECKER &&
+      (2 * p->boxes[0].h + p->boxes[0].cx > lem::kron_max_side() ||
+       p->boxes[0].cx > lem::kron_max_core()))
     return guard(fail(LEM_ERR_UNSUPPORTED, "Kronecker-factored boxes are at most " +
                                                std::to_string(lem::kron_max_side()) +
-                                               " points per side"));
+                                               " points per side, cores at most " +
+                                               std::to_string(lem::kron_max_core())));
   if (p->method == LEM_METHOD_KRYLOV && p->opt.columns) {
     // column-wise boxes stay on the kernels of boxes up to 4096 points: a
     // column partition on the large-box kernel's 12-points-per-lane shape

@@ -254,7 +254,7 @@ void lem_server_options_default(lem_server_options* o) {
   o->max_active = 256;
   o->halo_tol = 1e-8;
   o->halo_min = 4;
-  o->halo_max = 32;
+  o->halo_max = 56;
   o->max_overhead = 4.0;
   o->krylov_tol = 1e-12;
   o->krylov_m_max = 30;
@@ -444,19 +444,20 @@ lem_status lem_server_tick(lem_server_t s, int32_t* n_active, int32_t* n_queued)
       if (r.method == LEM_METHOD_KRONECKER) kneed += (size_t)take[a] * r.plan->boxes.size();
     }
     std::vector<std::pair<size_t, int>> klaunch;  // (offset, count) per step
-    std::vector<int> kmaxL;
+    std::vector<int> kmaxL, kmaxC;
     if (kneed) {
       LEM_TRY(server_grow_k(s, kneed));
       size_t koff = 0;
       for (int k = 0; k < kmax; ++k) {
         const size_t k0 = koff;
-        int maxL = 0;
+        int maxL = 0, maxC = 0;
         for (size_t a = 0; a < s->active.size(); ++a) {
           ServerReq& r = s->reqs[s->active[a]];
           if (take[a] <= k || r.method != LEM_METHOD_KRONECKER) continue;
           const lem_plan_s* p = r.plan;
           const int c = p->boxes[0].cx, L = p->kron_L;
           maxL = std::max(maxL, L);
+          maxC = std::max(maxC, c);
           for (const Box& b : p->boxes) {
             lem::KronBlock kb{};
             kb.ox = b.ox; kb.oy = b.oy; kb.c = c; kb.h = b.h; kb.L = L; kb.n = p->op.n; kb.ns = 1;
@@ -470,6 +471,7 @@ lem_status lem_server_tick(lem_server_t s, int32_t* n_active, int32_t* n_queued)
         }
         klaunch.push_back({k0, (int)(koff - k0)});
         kmaxL.push_back(maxL);
+        kmaxC.push_back(maxC);
       }
       LEM_HIP(hipMemcpyAsync(s->d_ktable, s->h_ktable, koff * sizeof(lem::KronBlock),
                              hipMemcpyHostToDevice, s->st));
@@ -477,7 +479,7 @@ lem_status lem_server_tick(lem_server_t s, int32_t* n_active, int32_t* n_queued)
     for (size_t k = 0; k < klaunch.size(); ++k) {
       if (!klaunch[k].second) continue;
       hipError_t e = lem::launch_kron(s->d_ktable + klaunch[k].first, klaunch[k].second, 1,
-                                      kmaxL[k], nullptr, nullptr, s->d_rstatus, s->st);
+                                      kmaxL[k], kmaxC[k], nullptr, nullptr, s->d_rstatus, s->st);
       if (e != hipSuccess)
         return fail(LEM_ERR_HIP, std::string("serving launch: ") + hipGetErrorString(e));
     }

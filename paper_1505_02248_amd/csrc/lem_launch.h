@@ -43,10 +43,11 @@ hipError_t launch_krylov_big(const KBlock* blocks, int n_blocks, int ns, int nt,
                              bool aug, hipStream_t st);
 
 // ---- Kronecker-factored local exponentials (kron.hip): one launch over
-// blocks x members (grid y = max_ns), box sides up to kron_max_side()
+// blocks x member groups, box sides up to kron_max_side(), cores up to
+// kron_max_core(); every block's c, L and ns bounded by max_c, max_L, max_ns
 int kron_max_side();
-size_t kron_lds_bytes(int L);
-hipError_t launch_kron(const KronBlock* blocks, int n_blocks, int max_ns, int max_L,
+int kron_max_core();
+hipError_t launch_kron(const KronBlock* blocks, int n_blocks, int max_ns, int max_L, int max_c,
                        const double* x_in, double* x_out, int* status, hipStream_t st);
 
 // ---- dense local exponentials (dense.hip)

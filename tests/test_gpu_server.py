@@ -33,12 +33,13 @@ def weights(n, nu, dt, seed):
 
 
 # constant coefficients take the Kronecker-factored method when a core fits
-# (A-E), variable ones the Krylov method (F: 64^2 cores, 9216-point boxes);
-# G and H need buffers beyond the cap and take the global method (G on one
-# periodic Krylov box, co-batched; H on the whole-grid kernels)
+# (A-E, and I with a buffer wider than 32 points), variable ones the Krylov
+# method (F: 64^2 cores, 9216-point boxes); G and H have no box that fits and
+# take the global method (G on one periodic Krylov box, co-batched; H, with
+# variable coefficients, on the whole-grid kernels)
 REQS = {"A": (128, 2e-3, 2, 7, 11), "B": (64, 1e-4, 1, 3, 12), "C": (256, 5e-3, 4, 5, 13),
         "D": (64, 1e-2, 4, 2, 14), "E": (128, 1e-4, 1, 4, 15), "F": (128, -2e-4, 1, 4, 16),
-        "G": (64, 3e-2, 4, 2, 17), "H": (128, 2e-2, 4, 2, 17)}
+        "G": (64, 3e-2, 4, 2, 17), "H": (128, -1e-3, 2, 2, 17), "I": (256, 1e-2, 4, 3, 18)}
 
 
 def make_server(steps_per_tick=1):
@@ -65,7 +66,7 @@ def test_results_alone_equal_results_in_the_mix_and_the_oracle(spt):
     alone = {k: run_alone(k, spt) for k in REQS}
     s = make_server(spt)
     ids = {}
-    order = [("B",), ("A", "F"), (), ("C", "D", "G"), (), ("E", "H")]
+    order = [("B",), ("A", "F"), (), ("C", "D", "G"), (), ("E", "H", "I")]
     for group in order:  # arrivals while others are on the device
         for k in group:
             n, nu, mult, steps, seed = REQS[k]
@@ -84,7 +85,7 @@ def test_results_alone_equal_results_in_the_mix_and_the_oracle(spt):
         o, dt, x = problem(n, nu, mult, seed)
         W = weights(n, nu, dt, seed)
         if info["method"] == "global":
-            want = ge.fft_steps(W, x, steps)
+            want = ge.steps(W, x, steps)
         else:
             boxes = P.uniform_boxes(2, n, info["core"], info["halo"])
             want = olem.run(op.sparse(W), boxes, 2, n, x, steps, krylov_above=3000,
@@ -92,6 +93,7 @@ def test_results_alone_equal_results_in_the_mix_and_the_oracle(spt):
         assert rel_l2(got, want) <= 1e-12, (k, info)
     methods = {k: alone[k][1]["method"] for k in REQS}
     assert set(methods.values()) == {"global", "krylov", "kronecker"}, methods
+    assert methods["H"] == "global" and alone["I"][1]["halo"] > 32, alone["I"][1]
 
 
 def test_a_nonfinite_request_fails_alone():

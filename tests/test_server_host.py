@@ -91,3 +91,19 @@ def test_partition_choice_and_global_fallback():
     assert i3["method"] == "krylov" and i3["core"] in (16, 32, 64)
     assert (i3["core"] + 2 * i3["halo"]) ** 2 <= 4.0 * i3["core"] ** 2
     assert i4["method"] == "global" and i4["core"] == 0
+
+
+def test_buffer_cap_decides_between_kronecker_and_global():
+    # a stiff 512^2 request (nu dt / dx^2 about 20) has a decay-bound buffer
+    # of about 45 points: a Kronecker box under the default cap of 56, the
+    # global method under a cap of 32
+    o = op2d(512, nu=1e-2)
+    for cap, method in ((56, "kronecker"), (32, "global")):
+        s = lem.Server(hbm_budget=1 << 30, max_active=8, dry_run=True, halo_max=cap)
+        rid = s.submit(o, 4 / 512, 1, np.zeros(512 * 512))
+        s.tick()
+        info = s.request_info(rid)
+        assert info["method"] == method, (cap, info)
+        if method == "kronecker":
+            assert 32 < info["halo"] <= cap
+            assert info["core"] + 2 * info["halo"] <= 128
