@@ -25,6 +25,19 @@ namespace lem {
 
 typedef double kd4 __attribute__((ext_vector_type(4)));
 
+// State and exponential pointers come from the block table, so the compiler
+// cannot tell their address space and would emit flat accesses, which also
+// count against the LDS wait counter (an LDS wait would then wait for the
+// slab prefetch too).  They always point to device memory: access them as
+// global.
+typedef __attribute__((address_space(1))) double gdouble;
+__device__ __forceinline__ double gload(const double* p, int64_t i) {
+  return ((const gdouble*)p)[i];
+}
+__device__ __forceinline__ void gstore(double* p, int64_t i, double v) {
+  ((gdouble*)p)[i] = v;
+}
+
 struct KronArgs {
   const KronBlock* blocks;
   int n_blocks;
@@ -38,62 +51,156 @@ constexpr int kKronMaxL = 128;  // box side
 constexpr int kKronMaxC = 64;   // core side
 constexpr int kSlab = 16;       // box rows per slab (K of the second contraction)
 
-// LDS doubles for S members: the slab S x 16 x (L rounded to 4, plus one)
-// and T 16 x (c S + 1)
-__host__ __device__ inline int kron_xs(int L) { return ((L + 3) & ~3) + 1; }
+// LDS layout (doubles), chosen so that a wave's fragment reads are 64
+// consecutive doubles (or 16-double runs 128 bytes apart across a half-wave)
+// and its slab stores fall on distinct banks:
+//   X  slab, member s at s XM, box column lx at 16 lx, slab row r at r:
+//      XM = 16 Lk + 16 (Lk = box side rounded up to 16, the K extent of the
+//      first contraction; columns past the box are zero)
+//   T  16 rows (slab rows) of c S values (core column, member), row stride
+//      TS = 16 (mod 32)
+//   Et E_x transposed, box column lx at lx ES, core row rx at rx, ES = 16
+//      (mod 32) >= c rounded up to 16; zero past the core and the box
+__host__ __device__ inline int kron_lk(int L) { return (L + 15) & ~15; }
+__host__ __device__ inline int kron_xm(int L) { return 16 * kron_lk(L) + 16; }
+__host__ __device__ inline int kron_ts(int cs) { return (cs + 15) / 32 * 32 + 16; }
+__host__ __device__ inline int kron_es(int c) { return (c + 15) / 32 * 32 + 16; }
 __host__ __device__ inline size_t kron_lds_doubles(int S, int L, int c) {
-  return (size_t)S * kSlab * kron_xs(L) + (size_t)kSlab * (c * S + 1);
+  return (size_t)S * kron_xm(L) + (size_t)kSlab * kron_ts(c * S) +
+         (size_t)kron_lk(L) * kron_es(c);
+}
+
+// Workgroup id g runs on XCD g % 8; the XCD-contiguous index of g numbers
+// the workgroups of XCD 0 first, then those of XCD 1, ...
+__device__ __forceinline__ int xcd_contiguous(int g, int count) {
+  constexpr int kXcd = 8;
+  const int per = count / kXcd, rem = count % kXcd;
+  const int x = g % kXcd, local = g / kXcd;
+  return x < rem ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
 }
 
 // Fragment layouts (16x16x4, f64): lane l supplies A[l%16][l/16] and
 // B[l/16][l%16]; accumulator register i of lane l is D[4 i + l/16][l%16].
-template <int S, int NW, int MAXT>
-__global__ __launch_bounds__(NW * 64) void kron_mfma_kernel(KronArgs a) {
+// (MINW: waves per SIMD the registers must allow; 4 for the ensemble shape
+// at c <= 32, i.e. two eight-wave workgroups per CU, which LDS allows too)
+template <int S, int NW, int MAXT, int LMAX, int MINW>
+__global__ __launch_bounds__(NW * 64, MINW) void kron_mfma_kernel(KronArgs a) {
+  constexpr int NT = NW * 64;
+  static_assert(NT % (16 * S) == 0, "threads cover whole (member, slab row) sets");
+  constexpr int STEP = NT / (16 * S);    // box columns between a thread's slab values
+  constexpr int GMAX = LMAX / STEP;      // slab values per thread (L <= LMAX)
   extern __shared__ double smem[];
-  const KronBlock b = a.blocks[blockIdx.x / a.chunks];
-  const int s0 = (blockIdx.x % a.chunks) * S;
+  // workgroups are dispatched to the 8 XCDs in turn; renumber them so each
+  // XCD takes a contiguous run of (block, member group) pairs: the groups of
+  // one block read the same cache lines of the member-fastest state, and
+  // neighbouring blocks share buffer rows, in that XCD's L2
+  const int g = xcd_contiguous(blockIdx.x, gridDim.x);
+  const KronBlock b = a.blocks[g / a.chunks];
+  const int s0 = (g % a.chunks) * S;
   if (s0 >= b.ns) return;
   const int sv = min(S, b.ns - s0);
   const int L = b.L, c = b.c, h = b.h, n = b.n, ns = b.ns;
   const double* x_in = b.x_in ? b.x_in : a.x_in;
   double* x_out = b.x_out ? b.x_out : a.x_out;
-  const int Lp = (L + 3) & ~3, XS = Lp + 1;
-  const int cs = c * S, TS = cs + 1;
-  double* X = smem;
-  double* T = smem + (size_t)S * kSlab * XS;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int lr = lane & 15, lk = lane >> 4;
+  const int Lk = kron_lk(L), XM = kron_xm(L);
+  const int cs = c * S, TS = kron_ts(cs), ES = kron_es(c);
   const int ct = (c + 15) >> 4;          // 16-wide tiles of core rows / columns
   const int nt = (cs + 15) >> 4;         // 16-wide tiles of (core column, member)
   const int tiles = ct * nt;             // accumulator tiles of the second contraction
+  double* X = smem;
+  double* T = X + (size_t)S * XM;
+  double* Et = T + (size_t)kSlab * TS;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  // E_x core rows, transposed, into LDS; four loads in flight per thread
+  const int etotal = Lk * ES;
+  for (int e0 = tid; e0 < etotal; e0 += 4 * NT) {
+    double v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = e0 + q * NT;
+      const int lx = e / ES, rx = e - lx * ES;
+      const bool ok = e < etotal && rx < c && lx < L;
+      v[q] = gload(b.ex, ok ? (int64_t)rx * L + lx : 0);
+      v[q] = ok ? v[q] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (e0 + q * NT < etotal) Et[e0 + q * NT] = v[q];
+  }
+
+  // a thread's slab values: member sm, slab row rs, box columns lx0 + i STEP.
+  // Loads are unconditional (from the block's own origin where a value lies
+  // outside the box or the member range) and branch-free, so a thread's loads
+  // of a slab are all in flight together.
+  const int sm = tid % S, rs = (tid / S) & 15, lx0 = tid / (16 * S);
+  const bool member_ok = sm < sv;
+  const int64_t origin = ((int64_t)b.oy * n + b.ox) * ns + s0;
+  auto slab_loads = [&](int ly0, double (&v)[GMAX], bool (&ok)[GMAX]) {
+    const int ly = ly0 + rs;
+    int gy = b.oy - h + ly;
+    gy += gy < 0 ? n : 0;
+    gy -= gy >= n ? n : 0;
+    const int64_t row = (int64_t)gy * n;
+    const bool row_ok = member_ok && ly < L;
+#pragma unroll
+    for (int i = 0; i < GMAX; ++i) {
+      // box offsets lie within one period of the grid (h < n)
+      int gx = b.ox - h + lx0 + i * STEP;
+      gx += gx < 0 ? n : 0;
+      gx -= gx >= n ? n : 0;
+      ok[i] = row_ok && lx0 + i * STEP < L;
+      v[i] = gload(x_in, ok[i] ? (row + gx) * ns + s0 + sm : origin);
+    }
+  };
+  double pre[GMAX];
+  bool pok[GMAX];
+  slab_loads(0, pre, pok);
   kd4 acc[MAXT];
 #pragma unroll
   for (int j = 0; j < MAXT; ++j) acc[j] = (kd4){0.0, 0.0, 0.0, 0.0};
 
   for (int ly0 = 0; ly0 < L; ly0 += kSlab) {
-    // gather the slab, members fastest (S adjacent doubles per point)
-    for (int e = tid; e < kSlab * Lp * S; e += NW * 64) {
-      const int s = e % S, rest = e / S;
-      const int lx = rest % Lp, r = rest / Lp;
-      const int ly = ly0 + r;
-      double v = 0.0;
-      if (ly < L && lx < L && s < sv) {
-        const int gx = wrap(b.ox - h + lx, n), gy = wrap(b.oy - h + ly, n);
-        v = x_in[((int64_t)gy * n + gx) * ns + s0 + s];
-      }
-      X[(s * kSlab + r) * XS + lx] = v;
-    }
+    // store the prefetched slab (columns up to Lk; zero outside the box)
+#pragma unroll
+    for (int i = 0; i < GMAX; ++i)
+      if (lx0 + i * STEP < Lk) X[sm * XM + (lx0 + i * STEP) * 16 + rs] = pok[i] ? pre[i] : 0.0;
     __syncthreads();
-    // first contraction: one (member, 16 core columns) tile per wave at a time
-    for (int u = wave; u < S * ct; u += NW) {
-      const int s = u / ct, rx = (u % ct) * 16 + lr;
-      const double* xr = X + (s * kSlab + lr) * XS + lk;
-      const double* exr = b.ex + (int64_t)rx * L + lk;
-      kd4 t = (kd4){0.0, 0.0, 0.0, 0.0};
-      for (int k0 = 0; k0 < Lp; k0 += 4) {
-        const double bv = (rx < c && k0 + lk < L) ? exr[k0] : 0.0;
-        t = __builtin_amdgcn_mfma_f64_16x16x4f64(xr[k0], bv, t, 0, 0, 0);
+    // E_y fragments of this slab for the resident tiles, issued before the
+    // next slab's loads (the wait for them then leaves those in flight)
+    double ey[MAXT][4];
+#pragma unroll
+    for (int j = 0; j < MAXT; ++j) {
+      const int tt = wave + NW * j;
+      const int ry = (tt / nt) * 16 + lr;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int ly = ly0 + 4 * kk + lk;
+        const bool ok = tt < tiles && ry < c && ly < L;
+        const double v = gload(b.ey, ok ? (int64_t)ry * L + ly : 0);
+        ey[j][kk] = ok ? v : 0.0;
       }
+    }
+    if (ly0 + kSlab < L) slab_loads(ly0 + kSlab, pre, pok);
+    // first contraction: one (member, 16 core columns) tile per wave at a
+    // time, 16 box columns per pass
+    for (int u = wave; u < S * ct; u += NW) {
+      const int s = u / ct, rxt = u % ct;
+      const double* xr = X + s * XM + lk * 16 + lr;
+      const double* er = Et + lk * ES + rxt * 16 + lr;
+      kd4 t = (kd4){0.0, 0.0, 0.0, 0.0};
+      for (int k0 = 0; k0 < Lk; k0 += 16) {
+        double xa[4], eb[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          xa[q] = xr[(k0 + 4 * q) * 16];
+          eb[q] = er[(k0 + 4 * q) * ES];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) t = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[q], eb[q], t, 0, 0, 0);
+      }
+      const int rx = rxt * 16 + lr;
       if (rx < c) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) T[(4 * i + lk) * TS + rx * S + s] = t[i];
@@ -105,18 +212,17 @@ __global__ __launch_bounds__(NW * 64) void kron_mfma_kernel(KronArgs a) {
     for (int j = 0; j < MAXT; ++j) {
       const int tt = wave + NW * j;
       if (tt < tiles) {
-        const int ry = (tt / nt) * 16 + lr, q = (tt % nt) * 16 + lr;
-        const double* eyr = b.ey + (int64_t)ry * L + ly0 + lk;
+        const int q = (tt % nt) * 16 + lr;
 #pragma unroll
-        for (int kk = 0; kk < kSlab; kk += 4) {
-          const double av = (ry < c && ly0 + kk + lk < L) ? eyr[kk] : 0.0;
-          const double bv = q < cs ? T[(kk + lk) * TS + q] : 0.0;
-          acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[j], 0, 0, 0);
+        for (int kk = 0; kk < 4; ++kk) {
+          const double bv = q < cs ? T[(4 * kk + lk) * TS + q] : 0.0;
+          acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ey[j][kk], bv, acc[j], 0, 0, 0);
         }
       }
     }
-    // the next gather writes X only; T is rewritten after the barrier that
-    // follows it, when every wave has left this loop
+    // no barrier here: the next slab's stores write X, which every wave has
+    // finished reading (the barrier above), and T is rewritten only after
+    // the next barrier, when every wave has left this loop
   }
   // core write (step 3)
   bool bad = false;
@@ -133,7 +239,7 @@ __global__ __launch_bounds__(NW * 64) void kron_mfma_kernel(KronArgs a) {
           if (ry < c) {
             const double y = acc[j][i];
             bad |= !isfinite(y);
-            x_out[((int64_t)(b.oy + ry) * n + (b.ox + rx)) * ns + s0 + s] = y;
+            gstore(x_out, ((int64_t)(b.oy + ry) * n + (b.ox + rx)) * ns + s0 + s, y);
           }
         }
       }
@@ -145,13 +251,13 @@ __global__ __launch_bounds__(NW * 64) void kron_mfma_kernel(KronArgs a) {
 int kron_max_side() { return kKronMaxL; }
 int kron_max_core() { return kKronMaxC; }
 
-template <int S, int NW, int MAXT>
+template <int S, int NW, int MAXT, int LMAX, int MINW>
 static hipError_t launch_kron_shape(const KronBlock* blocks, int n_blocks, int max_ns, int max_L,
                                     int max_c, const double* x_in, double* x_out, int* status,
                                     hipStream_t st) {
   const int chunks = (max_ns + S - 1) / S;
   const size_t lds = kron_lds_doubles(S, max_L, max_c) * sizeof(double);
-  auto fn = kron_mfma_kernel<S, NW, MAXT>;
+  auto fn = kron_mfma_kernel<S, NW, MAXT, LMAX, MINW>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
@@ -163,28 +269,28 @@ static hipError_t launch_kron_shape(const KronBlock* blocks, int n_blocks, int m
 }
 
 // Blocks of one launch may differ in core side (<= max_c <= 64), box side
-// (<= max_L <= 128) and member count (<= max_ns).  Ensembles take four members
-// per workgroup (eight waves hold the 4 x 4 x 16 tiles of a 64-point core),
-// single states one (four waves).
+// (<= max_L <= 128) and member count (<= max_ns).  Shapes (members per
+// workgroup S, waves, resident tiles per wave = ceil((c/16)^2 S / waves), box
+// side bound of the prefetch registers):
+//   ensembles, c <= 32, L <= 64:  S = 4, 8 waves, 2 tiles
+//   other ensembles:              S = 2, 8 waves, 4 tiles
+//   single states:                S = 1, 4 waves, 1 tile (c <= 32) or 4
 hipError_t launch_kron(const KronBlock* blocks, int n_blocks, int max_ns, int max_L, int max_c,
                        const double* x_in, double* x_out, int* status, hipStream_t st) {
   if (n_blocks == 0) return hipSuccess;
   if (max_L > kKronMaxL || max_L < 1 || max_ns < 1 || max_c < 1 || max_c > kKronMaxC)
     return hipErrorInvalidValue;
-  // resident tiles per wave: ceil((c/16)^2 S / waves); cores up to 32 need a
-  // quarter of those of 64 (fewer registers, two workgroups per CU)
-  if (max_ns >= 4) {
-    if (max_c <= 32)
-      return launch_kron_shape<4, 8, 2>(blocks, n_blocks, max_ns, max_L, max_c, x_in, x_out,
-                                        status, st);
-    return launch_kron_shape<4, 8, 8>(blocks, n_blocks, max_ns, max_L, max_c, x_in, x_out,
-                                      status, st);
-  }
+  if (max_ns >= 4 && max_c <= 32 && max_L <= 64)
+    return launch_kron_shape<4, 8, 2, 64, 4>(blocks, n_blocks, max_ns, max_L, max_c, x_in, x_out,
+                                          status, st);
+  if (max_ns >= 2)
+    return launch_kron_shape<2, 8, 4, kKronMaxL, 1>(blocks, n_blocks, max_ns, max_L, max_c, x_in,
+                                                 x_out, status, st);
   if (max_c <= 32)
-    return launch_kron_shape<1, 4, 1>(blocks, n_blocks, max_ns, max_L, max_c, x_in, x_out,
-                                      status, st);
-  return launch_kron_shape<1, 4, 4>(blocks, n_blocks, max_ns, max_L, max_c, x_in, x_out, status,
-                                    st);
+    return launch_kron_shape<1, 4, 1, kKronMaxL, 1>(blocks, n_blocks, max_ns, max_L, max_c, x_in,
+                                                 x_out, status, st);
+  return launch_kron_shape<1, 4, 4, kKronMaxL, 1>(blocks, n_blocks, max_ns, max_L, max_c, x_in,
+                                               x_out, status, st);
 }
 
 }  // namespace lem
