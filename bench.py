@@ -798,6 +798,29 @@ def bench_c2(args) -> dict:
         stream.synchronize()
         gw, _ = _time_stream(gplan, x, g, 3, stream, torch)
         gwall = gw / 3
+        # the partitions the autotuner weighs, each planned alone: largest core
+        # 32 or 64 points, Krylov dimension capped at 30 or at krylov_m_max
+        cands = {}
+        for cmax, mcap in ((32, 30), (64, 30), (32, args.krylov_m_max), (64, args.krylov_m_max)):
+            key = f"core_max{cmax}_m{mcap}"
+            if key in cands:
+                continue
+            cp = lem.Plan(opr, p.dt, method="krylov", core=0, halo=0, halo_min=4, halo_max=16,
+                          halo_tol=1e-8, krylov_m_max=mcap, krylov_tol=1e-10, use_graph=True,
+                          core_max=cmax, stream=stream)
+            cy = torch.empty_like(x)
+            cp.step(x, cy, 2, stream=stream)
+            _, cev = _time_stream(cp, x, cy, 10, stream, torch)
+            cp.step(x, cy, acc_steps, stream=stream)
+            stream.synchronize()
+            cq = cp.query()
+            cb = cp.maps()[0]
+            cands[key] = {"ms_per_step": cev / 10, "n_blocks": cq["n_blocks"],
+                          "cores": {int(c): int((cb[:, 2] == c).sum()) for c in np.unique(cb[:, 2])},
+                          "m_range": [cq["m_min"], cq["m_max"]], "n_loc_max": cq["n_loc_max"],
+                          "rel_l2_vs_global_after_3_steps": _rel(cy, ref, torch)}
+            log(key, cands[key])
+            del cp
     cores = {int(c): int((boxes[:, 2] == c).sum()) for c in np.unique(boxes[:, 2])}
     wl = {"workload": "2D 1024x1024 periodic diffusion-advection, lognormal nu (median 1e-3, "
                       "sigma_log 1), velocity (1,0), dt=dx/4, uneven cores 16-64 per 64^2 tile, "
@@ -813,7 +836,8 @@ def bench_c2(args) -> dict:
               "m_histogram": {int(k): int((m_blk == k).sum()) for k in np.unique(m_blk)},
               "global_krylov": {"dof_steps_per_s": p.N / gwall, "ms_per_step": 1e3 * gwall,
                                 "m": gq["m_max"], "substeps": gq["substeps_max"]},
-              "lem_over_global": lem_val / (p.N / gwall)}
+              "lem_over_global": lem_val / (p.N / gwall),
+              "partition_candidates": cands}
     log(extras)
     # every launch of the step overlaps (forked buckets): the algorithmic basis
     # traffic of the whole step over the step's event time bounds the rate of

@@ -60,14 +60,17 @@ constexpr int kSlab = 16;       // box rows per slab (K of the second contractio
 //   T  16 rows (slab rows) of c S values (core column, member), row stride
 //      TS = 16 (mod 32)
 //   Et E_x transposed, box column lx at lx ES, core row rx at rx, ES = 16
-//      (mod 32) >= c rounded up to 16; zero past the core and the box
+//      (mod 32) >= c rounded up to 16; zero past the core and the box.  Only
+//      for member groups (S > 1): a single-state workgroup would stage E_x
+//      for one member's work, so it reads its fragments from the L2 instead
+//      and keeps its LDS small (more workgroups per CU)
 __host__ __device__ inline int kron_lk(int L) { return (L + 15) & ~15; }
 __host__ __device__ inline int kron_xm(int L) { return 16 * kron_lk(L) + 16; }
 __host__ __device__ inline int kron_ts(int cs) { return (cs + 15) / 32 * 32 + 16; }
 __host__ __device__ inline int kron_es(int c) { return (c + 15) / 32 * 32 + 16; }
 __host__ __device__ inline size_t kron_lds_doubles(int S, int L, int c) {
   return (size_t)S * kron_xm(L) + (size_t)kSlab * kron_ts(c * S) +
-         (size_t)kron_lk(L) * kron_es(c);
+         (S > 1 ? (size_t)kron_lk(L) * kron_es(c) : 0);
 }
 
 // Workgroup id g runs on XCD g % 8; the XCD-contiguous index of g numbers
@@ -114,7 +117,8 @@ __global__ __launch_bounds__(NW * 64, MINW) void kron_mfma_kernel(KronArgs a) {
   const int lr = lane & 15, lk = lane >> 4;
 
   // E_x core rows, transposed, into LDS; four loads in flight per thread
-  const int etotal = Lk * ES;
+  constexpr bool kStageE = S > 1;
+  const int etotal = kStageE ? Lk * ES : 0;
   for (int e0 = tid; e0 < etotal; e0 += 4 * NT) {
     double v[4];
 #pragma unroll
@@ -189,18 +193,25 @@ __global__ __launch_bounds__(NW * 64, MINW) void kron_mfma_kernel(KronArgs a) {
       const int s = u / ct, rxt = u % ct;
       const double* xr = X + s * XM + lk * 16 + lr;
       const double* er = Et + lk * ES + rxt * 16 + lr;
+      const int rx = rxt * 16 + lr;
       kd4 t = (kd4){0.0, 0.0, 0.0, 0.0};
       for (int k0 = 0; k0 < Lk; k0 += 16) {
         double xa[4], eb[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           xa[q] = xr[(k0 + 4 * q) * 16];
-          eb[q] = er[(k0 + 4 * q) * ES];
+          if (kStageE) {
+            eb[q] = er[(k0 + 4 * q) * ES];
+          } else {
+            const int lx = k0 + 4 * q + lk;
+            const bool ok = rx < c && lx < L;
+            const double v = gload(b.ex, ok ? (int64_t)rx * L + lx : 0);
+            eb[q] = ok ? v : 0.0;
+          }
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) t = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[q], eb[q], t, 0, 0, 0);
       }
-      const int rx = rxt * 16 + lr;
       if (rx < c) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) T[(4 * i + lk) * TS + rx * S + s] = t[i];
