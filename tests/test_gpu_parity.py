@@ -235,9 +235,14 @@ def test_global_whole_grid_one_state(case):
     if case == "var96":
         p = L.workload_2d_variable(n=96)
         W = op.from_problem(p)
-        plan = lem.Plan(lem.Operator.from_problem(p), p.dt, method="global", krylov_tol=1e-14)
+        # a tighter per-step tolerance than the other cases: Saad's estimate
+        # is not a bound, and this operator is the stiffest of them (nu up to
+        # 35 times its median)
+        plan = lem.Plan(lem.Operator.from_problem(p), p.dt, method="global", krylov_tol=1e-15)
         got = run(plan, p.states, 1)
-        assert rel_l2(got, ge.krylov_step(W, p.states, m=60, tol=1e-16)) <= 1e-11
+        err = rel_l2(got, ge.krylov_step(W, p.states, m=60, tol=1e-16))
+        print(f"var96: rel l2 {err:.2e}")
+        assert err <= 1e-12
         return
     if case == "1d16384":
         p = L.workload_1d(n=16384, cfl=1.0)
@@ -508,10 +513,12 @@ def test_global_krylov_vortex_vs_dense(height):
     p2 = _vortex_problem(96, 2, 3.0, height)
     W2 = op.from_problem(p2)
     plan2 = lem.Plan(lem.Operator.from_problem(p2), p2.dt, method="global", n_states=2,
-                     krylov_tol=1e-14)
+                     krylov_tol=1e-15)
     got2 = run(plan2, p2.states, 1)
     want2 = ge.krylov_step(W2, p2.states, m=60, tol=1e-16)
-    assert rel_l2(got2, want2) <= 1e-11
+    err2 = rel_l2(got2, want2)
+    print(f"vortex whole grid height {height}: rel l2 {err2:.2e}")
+    assert err2 <= 1e-12
 
 
 # column-wise decomposition on an anisotropic mesh (section 4.3): whole
