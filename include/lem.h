@@ -170,9 +170,11 @@ typedef struct {
                             fastest one when autotune is set), 0..7 = that
                             shape for FP64/FP32 (rows per wave, K chunk,
                             waves: 32,16,4 / 32,32,4 / 32,32,8 / 64,32,4 /
-                            16,32,8 / 16,32,4 / 16,16,8 / 16,32,16), 0..3
-                            for split bf16 (rows per wave, waves: 32,4 /
-                            64,4 / 32,8 / 64,8); a shape
+                            16,32,8 / 16,32,4 / 16,16,8 / 16,32,16), 0..4
+                            for split bf16 (rows per wave, waves, states
+                            per workgroup: 32,4,64 / 64,4,64 / 32,8,64 /
+                            64,8,64 / 32,8,128, the last for n_states %
+                            128 == 0); a shape
                             that does not fit the block is LEM_ERR_UNSUPPORTED
                             at plan time                                    */
 } lem_options;

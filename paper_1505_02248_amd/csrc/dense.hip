@@ -588,15 +588,25 @@ __global__ void split_pieces_kernel(const double* __restrict__ x, int64_t total,
   }
 }
 
-template <int NTERMS, int WM, int NW, bool PRE>
+// BN states per workgroup: 64, or 128 (each stored-block fragment then feeds
+// twice the MFMAs, halving the stored-block traffic per product; the gathered
+// row offsets are then kept as 32-bit grid points to leave LDS for two
+// workgroups per CU).
+template <int NTERMS, int WM, int NW, bool PRE, int BN>
 __global__ __launch_bounds__(64 * NW) void apply_bf16_kernel(ApplyArgs a) {
-  constexpr int BN = 64, KC = 32, RT = WM / 16, CT = BN / 16;
+  constexpr int KC = 32, RT = WM / 16, CT = BN / 16;
   constexpr int NP = NTERMS == 6 ? 3 : 2;  // operand pieces in use
   constexpr int KG = KC / 8 + 1;           // padded k-groups per LDS column
-  constexpr int KPT = KC / NW;             // staged rows per thread (8 or 4)
+  constexpr int GROUPS = 64 * NW / BN;     // thread groups staging one column each
+  constexpr int KPT = KC / GROUPS;         // staged rows per thread (8 or 4)
   static_assert(NW == 4 || NW == 8, "four or eight waves");
+  static_assert(KPT == 4 || KPT == 8, "four or eight staged rows per thread");
   __shared__ bf16x8 Xs[2][NP][BN][KG];
-  extern __shared__ int64_t goff[];        // gathered row offsets (cols_p)
+  // gathered rows of the chunk: element offsets g ns + col0 (64 states per
+  // workgroup) or grid points g (128 states; offsets formed at the load)
+  typedef typename std::conditional<BN == 128, int, int64_t>::type goff_t;
+  extern __shared__ int64_t goff_raw[];
+  goff_t* goff = reinterpret_cast<goff_t*>(goff_raw);
   const int total = a.n_blocks * a.row_tiles * a.col_tiles;
   const int item = xcd_remap(blockIdx.x, total);
   const int ct0 = item % a.col_tiles;
@@ -615,7 +625,10 @@ __global__ __launch_bounds__(64 * NW) void apply_bf16_kernel(ApplyArgs a) {
   const bf16x8* Ew = E + (int64_t)b.unique * 3 * estride8 + (int64_t)rtw * ksteps * 64 + lane;
   for (int l = tid; l < a.cols_p; l += 64 * NW) {
     const int lc = l < a.cols ? l : a.cols - 1;  // padded columns of E are zero
-    goff[l] = dense_gather(b, lc, a.n, a.ndim) * a.ns + col0;
+    if constexpr (BN == 128)
+      goff[l] = (int)dense_gather(b, lc, a.n, a.ndim);
+    else
+      goff[l] = dense_gather(b, lc, a.n, a.ndim) * a.ns + col0;
   }
   __syncthreads();
 
@@ -632,19 +645,25 @@ __global__ __launch_bounds__(64 * NW) void apply_bf16_kernel(ApplyArgs a) {
       for (int i = 0; i < RT; ++i)
         ea[p][i] = Ew[p * estride8 + ((int64_t)i * ksteps + ch) * 64];
   };
-  const int xc = tid & 63, xg = tid >> 6;
+  const int xc = tid % BN, xg = tid / BN;
   // staged X of one chunk: KPT local rows of column xc, as float64 values
   // (split here) or as pieces (split once per step by split_pieces_kernel)
   typedef typename std::conditional<NP == 3, bf16x4, bf16x2>::type piece_t;
   typedef typename std::conditional<PRE, piece_t[KPT], double[KPT]>::type xreg_t;
+  auto x_at = [&](int l) -> int64_t {
+    if constexpr (BN == 128)
+      return (int64_t)goff[l] * a.ns + col0 + xc;
+    else
+      return goff[l] + xc;
+  };
   auto load_x = [&](int ch, xreg_t& v) {
     if constexpr (PRE) {
       const piece_t* xp = reinterpret_cast<const piece_t*>(a.xp);
 #pragma unroll
-      for (int e = 0; e < KPT; ++e) v[e] = xp[goff[ch * KC + xg * KPT + e] + xc];
+      for (int e = 0; e < KPT; ++e) v[e] = xp[x_at(ch * KC + xg * KPT + e)];
     } else {
 #pragma unroll
-      for (int e = 0; e < KPT; ++e) v[e] = a.x_in[goff[ch * KC + xg * KPT + e] + xc];
+      for (int e = 0; e < KPT; ++e) v[e] = a.x_in[x_at(ch * KC + xg * KPT + e)];
     }
   };
   // rows xg*KPT .. xg*KPT + KPT - 1 of the chunk land in k-group xg*KPT/8
@@ -1004,7 +1023,8 @@ static const int kApplyShapes[kApplyConfigs][3] = {{32, 16, 4}, {32, 32, 4}, {32
                                                    {64, 32, 4}, {16, 32, 8}, {16, 32, 4},
                                                    {16, 16, 8}, {16, 32, 16}};
 
-bool dense_apply_supported(int precision, int cfg, int ns, int rows_p, int cols_p) {
+bool dense_apply_supported(int precision, int cfg, int ns, int rows_p, int cols_p,
+                           int64_t n_points) {
   if (ns % 64 != 0) return precision == 0 || precision == 1;  // small-ensemble kernel
   if (precision == 0 || precision == 1) {
     if (cfg < 0 || cfg >= kApplyConfigs) return false;
@@ -1013,6 +1033,9 @@ bool dense_apply_supported(int precision, int cfg, int ns, int rows_p, int cols_
   }
   if (precision != 2 && precision != 3) return false;
   if (cfg < 0 || cfg >= kApplyBf16Configs) return false;
+  if (cfg == 4)  // 128 states per workgroup, 32-bit grid points in LDS
+    return ns % 128 == 0 && rows_p % 32 == 0 && cols_p % 32 == 0 &&
+           n_points < ((int64_t)1 << 31) && (size_t)cols_p * sizeof(int) <= 64 * 1024;
   const int wm = (cfg & 1) ? 64 : 32;
   return rows_p % wm == 0 && cols_p % 32 == 0 && (size_t)cols_p * sizeof(int64_t) <= 64 * 1024;
 }
@@ -1026,7 +1049,6 @@ hipError_t dense_apply(int precision, int cfg, const void* blocks, const void* E
   a.bias = bias;
   a.status = status;
   a.xp = nullptr;
-  (void)n_points;
   a.blocks = (const DBlock*)blocks; a.E = E; a.e_stride = e_stride;
   a.x_in = x_in; a.x_out = x_out; a.n = n; a.ndim = ndim; a.ns = ns;
   a.rows = rows; a.rows_p = rows_p; a.cols = cols; a.cols_p = cols_p;
@@ -1043,7 +1065,8 @@ hipError_t dense_apply(int precision, int cfg, const void* blocks, const void* E
     return hipGetLastError();
   }
   a.col_tiles = ns / 64;
-  if (!dense_apply_supported(precision, cfg, ns, rows_p, cols_p)) return hipErrorInvalidValue;
+  if (!dense_apply_supported(precision, cfg, ns, rows_p, cols_p, n_points))
+    return hipErrorInvalidValue;
   if (precision == 0 || precision == 1) {
     const int wm = kApplyShapes[cfg][0], nw = kApplyShapes[cfg][2];
     a.row_tiles = (rows_p + nw * wm - 1) / (nw * wm);
@@ -1063,24 +1086,35 @@ hipError_t dense_apply(int precision, int cfg, const void* blocks, const void* E
 #undef LEM_APPLY
     return hipGetLastError();
   }
-  // split-bf16 shapes: rows per wave 32 (even ids) or 64 (odd), four waves
-  // (ids 0, 1) or eight (ids 2, 3) per workgroup
-  const int wm = (cfg & 1) ? 64 : 32, nw = cfg >= 2 ? 8 : 4;
+  // split-bf16 shapes: rows per wave 32 (ids 0, 2, 4) or 64 (1, 3), four
+  // waves (ids 0, 1) or eight (2, 3, 4) per workgroup, 64 states per
+  // workgroup or 128 (id 4)
+  const int wm = (cfg == 1 || cfg == 3) ? 64 : 32, nw = cfg >= 2 ? 8 : 4;
+  const int bn = cfg == 4 ? 128 : 64;
+  a.col_tiles = ns / bn;
   a.row_tiles = (rows_p + nw * wm - 1) / (nw * wm);
   const dim3 g(n_blocks * a.row_tiles * a.col_tiles);
-  const size_t gl = (size_t)cols_p * sizeof(int64_t);  // gathered row offsets
+  // gathered row offsets (dynamic LDS beside the static X stages)
+  const size_t gl = (size_t)cols_p * (bn == 128 ? sizeof(int) : sizeof(int64_t));
   if (xpieces) a.xp = (const __bf16*)xpieces;  // split by dense_split_pieces
-#define LEM_BF16(NT_, WM_, NW_)                                                            \
-  if (a.xp)                                                                                \
-    hipLaunchKernelGGL((apply_bf16_kernel<NT_, WM_, NW_, true>), g, dim3(64 * NW_), gl, st, a); \
-  else                                                                                     \
-    hipLaunchKernelGGL((apply_bf16_kernel<NT_, WM_, NW_, false>), g, dim3(64 * NW_), gl, st, a);
+#define LEM_BF16(NT_, WM_, NW_, BN_)                                                       \
+  {                                                                                        \
+    auto fn = a.xp ? apply_bf16_kernel<NT_, WM_, NW_, true, BN_>                           \
+                   : apply_bf16_kernel<NT_, WM_, NW_, false, BN_>;                         \
+    if (BN_ == 128) {                                                                      \
+      hipError_t e = hipFuncSetAttribute((const void*)fn,                                  \
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)gl); \
+      if (e != hipSuccess) return e;                                                       \
+    }                                                                                      \
+    hipLaunchKernelGGL(fn, g, dim3(64 * NW_), gl, st, a);                                  \
+  }
 #define LEM_BF16_SHAPES(NT_)                              \
   switch (cfg) {                                          \
-    case 0: LEM_BF16(NT_, 32, 4) break;                   \
-    case 1: LEM_BF16(NT_, 64, 4) break;                   \
-    case 2: LEM_BF16(NT_, 32, 8) break;                   \
-    default: LEM_BF16(NT_, 64, 8) break;                  \
+    case 0: LEM_BF16(NT_, 32, 4, 64) break;               \
+    case 1: LEM_BF16(NT_, 64, 4, 64) break;               \
+    case 2: LEM_BF16(NT_, 32, 8, 64) break;               \
+    case 3: LEM_BF16(NT_, 64, 8, 64) break;               \
+    default: LEM_BF16(NT_, 32, 8, 128) break;             \
   }
   if (precision == 2) {
     LEM_BF16_SHAPES(3)

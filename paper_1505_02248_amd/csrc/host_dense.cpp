@@ -456,7 +456,8 @@ lem_status autotune_dense(lem_plan_s* p, hipStream_t st) {
   int besttile = p->tile;
   const int ntile = p->opt.precision <= LEM_FP32 ? lem::kApplyConfigs : lem::kApplyBf16Configs;
   for (int tile = 0; tile < ntile; ++tile) {
-    if (!lem::dense_apply_supported(p->opt.precision, tile, p->ns, p->rows_p, p->cols_p)) continue;
+    if (!lem::dense_apply_supported(p->opt.precision, tile, p->ns, p->rows_p, p->cols_p, p->N))
+      continue;
     p->tile = tile;
     if (run_one(p, a, b, st) != LEM_OK) continue;
     LEM_HIP(hipEventRecord(e0, st));
@@ -479,7 +480,8 @@ lem_status autotune_dense(lem_plan_s* p, hipStream_t st) {
 
 lem_status choose_tile(lem_plan_s* p, hipStream_t st) {
   if (p->opt.tile >= 0) {
-    if (!lem::dense_apply_supported(p->opt.precision, p->opt.tile, p->ns, p->rows_p, p->cols_p))
+    if (!lem::dense_apply_supported(p->opt.precision, p->opt.tile, p->ns, p->rows_p, p->cols_p,
+                                    p->N))
       return fail(LEM_ERR_UNSUPPORTED, "apply tile shape " + std::to_string(p->opt.tile) +
                                            " does not fit this block and precision");
     p->tile = p->opt.tile;

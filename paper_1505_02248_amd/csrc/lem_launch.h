@@ -78,13 +78,14 @@ size_t dense_block_size();
 void dense_block_fill(void* dst, int i, int ox, int oy, int cx, int cy, int h, int Lx, int Ly,
                       int unique);
 // Tile shapes of the FP64/FP32 apply (the autotuner times each at plan time);
-// the split-bf16 apply has four: 32 or 64 rows per wave (cfg & 1), four or
-// eight waves per workgroup (cfg >= 2).
+// the split-bf16 apply has five: 32 or 64 rows per wave, four or eight waves
+// per workgroup, 64 states per workgroup (ids 0-3) or 128 (id 4).
 constexpr int kApplyConfigs = 8;
-constexpr int kApplyBf16Configs = 4;
+constexpr int kApplyBf16Configs = 5;
 // Whether tile shape cfg of the apply serves this precision and padded block
 // (cfg is ignored for ensembles that are not a multiple of 64).
-bool dense_apply_supported(int precision, int cfg, int ns, int rows_p, int cols_p);
+bool dense_apply_supported(int precision, int cfg, int ns, int rows_p, int cols_p,
+                           int64_t n_points);
 // Split-bf16 precisions: xpieces (optional) holds the input state already
 // split into bf16 pieces (dense_split_pieces, n_points x ns entries per piece).
 // status: non-finite outputs latch kStatusNonFinite there (may be null).

@@ -8,7 +8,7 @@ exact local exponentials, sections 3 and 4).
 * 512^2 x 128 states, 32^2 cores at h = 8 (configured) and h = 15 (decay
   bound, the benchmarked case), with the launch shape the autotuner picks as
   the benchmark does: FP64 within 1e-12, FP32 and split bf16 (six products)
-  within 1e-6.
+  within 1e-6; every split-bf16 shape (the 128-state one included) at h = 15.
 * Small ensembles (3 states) in FP32 (the eight-lane kernel)."""
 import numpy as np
 import pytest
@@ -79,6 +79,11 @@ def test_tile_that_does_not_fit_is_refused():
     with pytest.raises(lem.LemError) as e:
         lem.Plan(o, p.dt, method="dense", core=40, halo=10, n_states=64, tile=8)
     assert e.value.status == 1
+    # 128 states per workgroup at 64 states
+    with pytest.raises(lem.LemError) as e:
+        lem.Plan(o, p.dt, method="dense", precision="bf16x2", core=40, halo=10, n_states=64,
+                 tile=4)
+    assert e.value.status == 6
 
 
 @pytest.mark.parametrize("h", [8, 15])
@@ -95,9 +100,10 @@ def test_c3_full_size(prec, tol, h):
     assert plan.query()["device_status"] == 0
 
 
-@pytest.mark.parametrize("tile", range(4))
+@pytest.mark.parametrize("tile", range(5))
 def test_c3_every_split_bf16_shape(tile):
-    # rows per wave 32 / 64, four / eight waves per workgroup, six products
+    # rows per wave 32 / 64, four / eight waves per workgroup, 64 states per
+    # workgroup (0-3) or 128 (4), six products
     p = c3_problem()
     plan = lem.Plan(lem.Operator.from_problem(p), p.dt, method="dense", precision="bf16x3",
                     core=32, halo=15, n_states=128, tile=tile)
@@ -108,6 +114,8 @@ def test_c3_every_split_bf16_shape(tile):
 
 @pytest.mark.parametrize("tile", range(4))
 def test_c1_every_split_bf16_shape_three_products(tile):
+    # (the 128-state shape needs n_states % 128 == 0: refused at 64 states,
+    # test_tile_that_does_not_fit_is_refused)
     p = c1_problem()
     plan = lem.Plan(lem.Operator.from_problem(p), p.dt, method="dense", precision="bf16x2",
                     core=16, halo=14, n_states=64, tile=tile)
