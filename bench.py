@@ -723,23 +723,36 @@ def bench_c0(args) -> dict:
     # algorithmic bytes of one step of the best form: the Krylov basis traffic
     # (|M| 8 (m(m+1)+3m) nsub per region) or, for stored blocks, the one
     # stored core block, the gathered regions and the written cores
+    us = res[best]["us_per_step"]
     if best == "lem_krylov_bound":
         step_bytes = float(bq["krylov_bytes_step"])
+        achieved = step_bytes / (us * 1e-6) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "kernel": f"{best} (whole step; latency bound: 16 regions of 64 points fill 16 "
+                          "of 256 compute units)",
+                "bytes_per_step": step_bytes, "us_per_step": us}
     else:
+        # one stored block, 16 regions: 2 x 64 rows x |M| columns per region;
+        # with resident steps one workgroup (one CU) runs all 100 steps
         nloc = 64 + 2 * res[best]["halo"]
-        step_bytes = 8.0 * (64 * nloc + len(boxes) * nloc + p.N)
-    us = res[best]["us_per_step"]
-    achieved = step_bytes / (us * 1e-6) / 1e9
-    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "kernel": f"{best} (whole step, one graph replay; launch-latency bound: 16 "
-                      "regions of 64 points fill 16 of 256 compute units)",
-            "bytes_per_step": step_bytes, "us_per_step": us}
+        flops = 2.0 * 64 * nloc * len(boxes)
+        achieved = flops / (us * 1e-6) / 1e12
+        resident = bq.get("resident_steps", 0) == 1
+        roof = {"bound": "mfma", "achieved": achieved, "peak": MFMA_FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / MFMA_FP64_PEAK_TFLOPS, "traffic": None,
+                "kernel": ("dense_resident_kernel (all 100 steps in one launch on one CU: states "
+                           "in LDS, stored-block rows in registers; bound by the per-step MFMA "
+                           "chain, not by the chip's peak)") if resident else
+                          f"{best} (whole step, one graph replay; launch-latency bound)",
+                "flops_per_step": flops, "us_per_step": us,
+                "frac_of_one_cu": achieved / (MFMA_FP64_PEAK_TFLOPS / 256)}
     for r in res.values():
         r.pop("_plan", None)
     wl = {"workload": "1D periodic advection-diffusion N=1024, a=1, nu=1e-3, dt=4dx, "
-                      "16 cores of 64 points, 100 steps, FP64, HIP graph per step",
-          "best_lem": best}
+                      "16 cores of 64 points, 100 steps per call, FP64 (dense: all steps in "
+                      "one launch; Krylov: HIP graph per step)",
+          "best_lem": best, "resident_steps": int(bq.get("resident_steps", 0))}
     line = _line(args, wl, res[best]["dof_steps_per_s"], "DOF-steps/s", steps,
                  res[best]["us_per_step"] * steps * 1e-6, "f64",
                  dict(res, lem_over_global=res[best]["dof_steps_per_s"] /

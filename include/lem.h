@@ -205,6 +205,11 @@ typedef struct {
   double krylov_bytes_streamed; /* the part of it on blocks whose basis is
                                    streamed through device memory (the rest
                                    stays in LDS)                           */
+  int32_t resident_steps;  /* 1: lem_step runs all steps of a call in one
+                              launch (1D dense FP64 plans with one stored
+                              block, cores tiling the grid, core of 4 to
+                              128 and box <= 128 points, two states per
+                              workgroup in LDS)                             */
 } lem_plan_info;
 
 typedef struct lem_plan_s* lem_plan_t;

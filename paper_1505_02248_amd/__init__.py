@@ -68,7 +68,7 @@ class _Info(ctypes.Structure):
                 ("bytes_work", ctypes.c_int64), ("device_status", ctypes.c_int32),
                 ("max_estimate", ctypes.c_double), ("plan_ms", ctypes.c_double),
                 ("tile_config", ctypes.c_int32), ("krylov_bytes_step", ctypes.c_double),
-                ("krylov_bytes_streamed", ctypes.c_double)]
+                ("krylov_bytes_streamed", ctypes.c_double), ("resident_steps", ctypes.c_int32)]
 
 
 _lib = None

@@ -816,6 +816,167 @@ __global__ void apply_simple_kernel(ApplyArgs a, const double* core) {
   }
 }
 
+// ------------------------------------------------------ resident steps --
+// Small 1D problems with one stored block (a translation-invariant operator
+// on cores of `rows` points tiling the grid): every step of a lem_step call
+// in one launch.  A workgroup holds the states of `mpw` members in LDS (two
+// buffers) and runs all steps: per step Y = E[core,:] X_g, where column
+// (block b, member m) of X_g is the box of block b gathered from member m's
+// state, on FP64 MFMA (16x16x4).  Wave w owns core rows 16w .. 16w + 15 and
+// keeps their stored-block fragments in registers for the whole launch;
+// each step is one barrier.  The launch is bound by the MFMA chain of one
+// step (cols / 4 products per column tile), not by launch latency.
+struct ResidentArgs {
+  const double* core;    // rows x cols, row-major
+  const double* bias;    // forcing term per step (N x ns) or null
+  const double* x_in;
+  double* x_out;
+  int* status;
+  int n, ns, rows, cols, nb, h, n_steps, mpw;
+};
+
+constexpr int kResidentMaxCols = 128;  // 32 k-steps of stored-block fragments per lane
+
+// padded LDS index of grid point p: one double after every core, so the 16
+// lanes of a fragment read (16 blocks at the same offset) hit distinct banks
+__device__ __forceinline__ int resident_pad(int p, int rows) { return p + p / rows; }
+
+template <int NW, int KMAX>
+__global__ __launch_bounds__(64 * NW) void dense_resident_kernel(ResidentArgs a) {
+  // KMAX k-steps of 4 columns cover the box (columns past it are zero)
+  extern __shared__ double xs[];  // [2][mpw][padded n]
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int m0 = blockIdx.x * a.mpw, mv = min(a.mpw, a.ns - m0);
+  const int pn = a.n + a.n / a.rows + 1;
+  double* buf0 = xs;
+  double* buf1 = xs + (size_t)a.mpw * pn;
+  // this workgroup's members into LDS (members past ns are zero)
+  for (int e = tid; e < a.mpw * a.n; e += 64 * NW) {
+    const int m = e / a.n, pt = e - m * a.n;
+    buf0[m * pn + resident_pad(pt, a.rows)] = m < mv ? a.x_in[(int64_t)pt * a.ns + m0 + m] : 0.0;
+  }
+  // stored-block fragments of this wave's 16 core rows (zero past the rows
+  // and the columns)
+  const int row = 16 * w + lr;
+  double ek[KMAX];
+#pragma unroll
+  for (int kk = 0; kk < KMAX; ++kk) {
+    const int col = 4 * kk + lk;
+    ek[kk] = (row < a.rows && col < a.cols) ? a.core[(int64_t)row * a.cols + col] : 0.0;
+  }
+  __syncthreads();
+  const float inv_rows = 1.0f / (float)a.rows;
+  const int ncols = a.nb * a.mpw;          // (block, member) columns, block fastest
+  const int ntiles = (ncols + 15) / 16;
+  for (int step = 0; step < a.n_steps; ++step) {
+    const double* cur = (step & 1) ? buf1 : buf0;
+    double* nxt = (step & 1) ? buf0 : buf1;
+    for (int t = 0; t < ntiles; ++t) {
+      const int q = 16 * t + lr;
+      const int b = q % a.nb, m = q / a.nb;
+      const bool qv = q < ncols;
+      const double* xm = cur + (qv ? m : 0) * pn;
+      // box of block b starts h points before its core (periodic); the
+      // padded index p + p / rows takes the quotient in single precision,
+      // exact here: (p + 1/2) / rows is at least 1 / (2 rows) >= 2^-8 from an
+      // integer, above the rounding error of p < 2^14 times a rounded 1/rows
+      int p = b * a.rows - a.h + lk;
+      p += p < 0 ? a.n : 0;
+      // all reads first (always inside the member's state), then the zeros
+      // past the box and the columns: a select right after each read would
+      // wait for it
+      double bv[KMAX];
+#pragma unroll
+      for (int kk = 0; kk < KMAX; ++kk) {
+        bv[kk] = xm[p + (int)(((float)p + 0.5f) * inv_rows)];
+        p += 4;
+        p -= p >= a.n ? a.n : 0;
+      }
+#pragma unroll
+      for (int kk = 0; kk < KMAX; ++kk) bv[kk] = (qv && 4 * kk + lk < a.cols) ? bv[kk] : 0.0;
+      d4 acc = (d4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < KMAX; ++kk)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ek[kk], bv[kk], acc, 0, 0, 0);
+      if (qv) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = 16 * w + 4 * i + lk;
+          if (r < a.rows) {
+            const int pt = b * a.rows + r;
+            const double y = acc[i] + (a.bias ? a.bias[(int64_t)pt * a.ns + m0 + m] : 0.0);
+            nxt[m * pn + resident_pad(pt, a.rows)] = y;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const double* fin = (a.n_steps & 1) ? buf1 : buf0;
+  bool bad = false;
+  for (int e = tid; e < mv * a.n; e += 64 * NW) {
+    const int m = e / a.n, pt = e - m * a.n;
+    const double y = fin[m * pn + resident_pad(pt, a.rows)];
+    bad |= !isfinite(y);
+    a.x_out[(int64_t)pt * a.ns + m0 + m] = y;
+  }
+  latch_nonfinite(bad, a.status);
+}
+
+int dense_resident_members(int n, int ns, int rows, int cols, int nb) {
+  if (rows < 4 || rows > 128 || cols > kResidentMaxCols || n != nb * rows || cols < 1 ||
+      n >= (1 << 14))
+    return 0;
+  const size_t pn = (size_t)n + n / rows + 1;
+  const size_t per = 2 * pn * sizeof(double);  // two buffers of one member
+  const size_t lds_max = 160 * 1024;
+  if (per > lds_max) return 0;
+  // up to 64 (block, member) columns per workgroup, within LDS
+  int mpw = std::max(1, 64 / nb);
+  mpw = std::min<int>(mpw, (int)(lds_max / per));
+  return std::max(1, std::min(mpw, ns));
+}
+
+hipError_t dense_resident_steps(const double* core, const double* bias, const double* x_in,
+                                double* x_out, int* status, int n, int ns, int rows, int cols,
+                                int nb, int h, int n_steps, hipStream_t st) {
+  const int mpw = dense_resident_members(n, ns, rows, cols, nb);
+  if (mpw < 1 || n_steps < 1 || h < 0 || cols != rows + 2 * h) return hipErrorInvalidValue;
+  ResidentArgs a{core, bias, x_in, x_out, status, n, ns, rows, cols, nb, h, n_steps, mpw};
+  const size_t lds = 2 * (size_t)mpw * (n + n / rows + 1) * sizeof(double);
+  const dim3 g((ns + mpw - 1) / mpw);
+  const int nw = (rows + 15) / 16, ks = (cols + 3) / 4;
+#define LEM_RES_K(NW_, K_)                                                                 \
+  {                                                                                        \
+    auto fn = dense_resident_kernel<NW_, K_>;                                              \
+    if (lds > 64 * 1024) {                                                                 \
+      hipError_t e = hipFuncSetAttribute((const void*)fn,                                  \
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+      if (e != hipSuccess) return e;                                                       \
+    }                                                                                      \
+    hipLaunchKernelGGL(fn, g, dim3(64 * NW_), lds, st, a);                                 \
+  }
+#define LEM_RES(NW_)                                                                       \
+  if (ks <= 8) LEM_RES_K(NW_, 8)                                                           \
+  else if (ks <= 16) LEM_RES_K(NW_, 16)                                                    \
+  else if (ks <= 24) LEM_RES_K(NW_, 24)                                                    \
+  else LEM_RES_K(NW_, 32)
+  switch (nw) {
+    case 1: LEM_RES(1) break;
+    case 2: LEM_RES(2) break;
+    case 3: LEM_RES(3) break;
+    case 4: LEM_RES(4) break;
+    case 5: LEM_RES(5) break;
+    case 6: LEM_RES(6) break;
+    case 7: LEM_RES(7) break;
+    default: LEM_RES(8) break;
+  }
+#undef LEM_RES
+#undef LEM_RES_K
+  return hipGetLastError();
+}
+
 // -------------------------------------------------------------- launchers --
 
 static inline dim3 grid1(int64_t total, int per = 256, int cap = 8192) {

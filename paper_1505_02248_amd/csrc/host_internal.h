@@ -133,6 +133,8 @@ struct lem_plan_s {
   lem::KronBlock* d_kron = nullptr;
   double* d_ex = nullptr;
   int kron_L = 0;
+  // small 1D dense plans: all steps of a lem_step call in one launch
+  bool resident = false;
   // global
   lem::GlobalWork gw{};
   // shared

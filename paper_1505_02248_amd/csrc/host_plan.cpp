@@ -146,6 +146,21 @@ lem_status run_one(lem_plan_s* p, const double* src, double* dst, hipStream_t st
   }
 }
 
+// A 1D dense plan with one stored block on cores tiling the grid, small
+// enough for two states per workgroup in LDS, steps in one launch per call.
+bool resident_fits(const lem_plan_s* p) {
+  if (p->method != LEM_METHOD_DENSE || p->op.ndim != 1 || p->opt.precision != LEM_FP64 ||
+      p->U != 1 || !p->d_core || p->boxes.empty())
+    return false;
+  const int rows = p->rows, h = p->boxes[0].h;
+  for (size_t i = 0; i < p->boxes.size(); ++i) {
+    const Box& b = p->boxes[i];
+    if (b.cx != rows || b.h != h || b.ox != (int)i * rows) return false;
+  }
+  if (p->cols != rows + 2 * h || 2 * h + rows > p->op.n) return false;
+  return lem::dense_resident_members(p->op.n, p->ns, rows, p->cols, (int)p->boxes.size()) > 0;
+}
+
 lem_status run_step(lem_plan_s* p, const double* src, double* dst, hipStream_t st) {
   if (!p->opt.use_graph || st == nullptr) return run_one(p, src, dst, st);
   auto key = std::make_pair((const void*)src, (void*)dst);
@@ -220,6 +235,7 @@ void fill_info(const lem_plan_s* p, lem_plan_info* in) {
   in->bytes_work = p->bytes_work;
   in->plan_ms = p->plan_ms;
   in->tile_config = p->tile;
+  in->resident_steps = p->resident ? 1 : 0;
   for (const auto& bk : p->buckets)
     for (int i = bk.first; i < bk.first + bk.count && i < (int)p->kb_host.size(); ++i) {
       const lem::KBlock& k = p->kb_host[i];
@@ -429,6 +445,7 @@ lem_status create_plan_one(const lem_operator* op, double dt, const lem_options*
     if (p->method == LEM_METHOD_DENSE) {
       s = choose_tile(p, st);
       if (s != LEM_OK) return guard(s);
+      p->resident = resident_fits(p);
     }
     if (hipStreamSynchronize(st) != hipSuccess)
       return guard(fail(LEM_ERR_HIP, "plan synchronization failed"));
@@ -545,6 +562,12 @@ lem_status lem_step(lem_plan_t p, const double* x_in, double* x_out, int32_t n_s
   if (overlap(x_in, x_out, bytes)) return fail(LEM_ERR_INVALID, "x_in and x_out overlap");
   hipStream_t st = (hipStream_t)stream;
   p->stream = st;
+  if (p->resident) {
+    LEM_HIP(lem::dense_resident_steps(p->d_core, p->d_bias, x_in, x_out, p->d_status, p->op.n,
+                                      p->ns, p->rows, p->cols, (int)p->boxes.size(),
+                                      p->boxes[0].h, n_steps, st));
+    return LEM_OK;
+  }
   // last step writes x_out; earlier steps alternate x_out / tmp backwards
   const double* src = x_in;
   for (int k = 0; k < n_steps; ++k) {

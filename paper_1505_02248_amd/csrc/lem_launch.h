@@ -94,6 +94,15 @@ hipError_t dense_apply(int precision, int cfg, const void* blocks, const void* E
                        int n, int ndim, int ns, int rows, int rows_p, int cols, int cols_p,
                        int n_blocks, const double* bias, int* status, hipStream_t st,
                        const void* xpieces = nullptr, int64_t n_points = 0);
+// Small 1D problems with one stored block (cores of `rows` points tiling the
+// grid, boxes of cols = rows + 2h): every step of a lem_step call in one
+// launch.  dense_resident_members returns the members per workgroup (0: the
+// problem does not fit: rows outside [4, 128], cols > 128, or two states
+// over LDS).
+int dense_resident_members(int n, int ns, int rows, int cols, int nb);
+hipError_t dense_resident_steps(const double* core, const double* bias, const double* x_in,
+                                double* x_out, int* status, int n, int ns, int rows, int cols,
+                                int nb, int h, int n_steps, hipStream_t st);
 hipError_t dense_split_pieces(const double* x, int64_t total, int np, void* pieces,
                               hipStream_t st);
 
