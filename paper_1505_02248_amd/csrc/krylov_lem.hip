@@ -99,38 +99,60 @@ __device__ __forceinline__ double red_total64(const double* red, int i) {
 
 // C = A B for mp x mp matrices (mp = 16 or 32) in LDS, row-major, on FP64
 // MFMA.  Waves take 16x16 output tiles round-robin.
-template <int NT>
-__device__ __forceinline__ void mfma_matmul(const double* A, const double* B, double* C,
-                                            int mp) {
+// (all LDS reads of a tile are issued before its MFMAs: one wait per tile)
+template <int NT, int MP>
+__device__ __forceinline__ void mfma_matmul_mp(const double* A, const double* B, double* C) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int tiles = (mp / 16) * (mp / 16);
-  for (int t = wv; t < tiles; t += NT / 64) {
-    const int ti = t / (mp / 16), tj = t - ti * (mp / 16);
-    d4v acc = {0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < mp; k0 += 4) {
-      const double a = A[(ti * 16 + (lane & 15)) * mp + k0 + (lane >> 4)];
-      const double bb = B[(k0 + (lane >> 4)) * mp + tj * 16 + (lane & 15)];
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
+  constexpr int TT = MP / 16, KS = MP / 4;
+  for (int t = wv; t < TT * TT; t += NT / 64) {
+    const int ti = t / TT, tj = t - ti * TT;
+    double a[KS], bb[KS];
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      a[k] = A[(ti * 16 + (lane & 15)) * MP + 4 * k + (lane >> 4)];
+      bb[k] = B[(4 * k + (lane >> 4)) * MP + tj * 16 + (lane & 15)];
     }
+    d4v acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < KS; ++k) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[k], bb[k], acc, 0, 0, 0);
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-      C[(ti * 16 + 4 * r + (lane >> 4)) * mp + tj * 16 + (lane & 15)] = acc[r];
+      C[(ti * 16 + 4 * r + (lane >> 4)) * MP + tj * 16 + (lane & 15)] = acc[r];
   }
   __syncthreads();
 }
+template <int NT>
+__device__ __forceinline__ void mfma_matmul(const double* A, const double* B, double* C,
+                                            int mp) {
+  if (mp == 16) mfma_matmul_mp<NT, 16>(A, B, C);
+  else mfma_matmul_mp<NT, 32>(A, B, C);
+}
+
+// 1/k! for the degree-18 Taylor polynomial of exp
+__host__ __device__ constexpr double inv_factorial(int k) {
+  double f = 1.0;
+  for (int i = 2; i <= k; ++i) f *= i;
+  return 1.0 / f;
+}
 
 // exp(A) for the leading m x m block of the mp x mp matrix A in LDS (padding
-// rows/columns zero).  Work W = 5 mp^2, result R (mp^2), piv >= NT/64 + 4.
+// rows/columns zero): scaling so that ||A / 2^s||_1 <= 1, the degree-18 Taylor
+// polynomial (truncation below 1/19! ~ 8e-18 relative) in Paterson-Stockmeyer
+// form -- X^2, X^3, X^4, then a Horner recursion in X^4 over blocks of four
+// terms, seven products in all -- and s squarings, every step an FP64 MFMA
+// product or an elementwise update (no pivoted solve: its chain of per-column
+// barriers dominated the step's end on small boxes).  Work W = 5 mp^2, result
+// R (mp^2); piv >= NT/64 holds the per-wave norm maxima.
 template <int NT>
 __device__ __forceinline__ void expm_mfma(double* A, int m, int mp, double* W, double* R,
                                           double* piv) {
   const int tid = threadIdx.x;
   const int mm = mp * mp;
-  double* A2 = W;
-  double* A4 = W + mm;
-  double* A6 = W + 2 * mm;
-  double* U = W + 3 * mm;
-  double* V = W + 4 * mm;
+  double* X2 = W;
+  double* X3 = W + mm;
+  double* X4 = W + 2 * mm;
+  double* T = W + 3 * mm;
+  double* S = W + 4 * mm;
   double cs = 0.0;
   for (int j = tid; j < m; j += NT) {
     double t = 0.0;
@@ -145,108 +167,34 @@ __device__ __forceinline__ void expm_mfma(double* A, int m, int mp, double* W, d
     for (int w = 0; w < NT / 64; ++w) cs = fmax(cs, piv[w]);
     __syncthreads();
   }
-  int s = 0;
-  if (cs > kTheta13 && cs < 1e300) s = min(60, (int)ceil(log2(cs / kTheta13)));
+  int s = 0;  // a non-finite norm leaves s = 0 (the result is then non-finite too)
+  if (cs > 1.0 && cs < 1e300) s = min(60, (int)ceil(log2(cs)));
   if (s > 0) {
     for (int idx = tid; idx < mm; idx += NT) A[idx] = ldexp(A[idx], -s);
     __syncthreads();
   }
-  const double* b = kPadeB;
-  mfma_matmul<NT>(A, A, A2, mp);
-  mfma_matmul<NT>(A2, A2, A4, mp);
-  mfma_matmul<NT>(A4, A2, A6, mp);
-  for (int idx = tid; idx < mm; idx += NT)
-    V[idx] = b[13] * A6[idx] + b[11] * A4[idx] + b[9] * A2[idx];
+  mfma_matmul<NT>(A, A, X2, mp);
+  mfma_matmul<NT>(X2, A, X3, mp);
+  mfma_matmul<NT>(X2, X2, X4, mp);
+  // block j of four terms: c_4j I + c_4j+1 X + c_4j+2 X^2 + c_4j+3 X^3 (the
+  // identity on the leading block only, so the padding stays zero)
+  auto block = [&](int j, int idx) -> double {
+    const int i = idx / mp, k = idx - i * mp;
+    const double id = (i == k && i < m) ? inv_factorial(4 * j) : 0.0;
+    double v = id + inv_factorial(4 * j + 1) * A[idx] + inv_factorial(4 * j + 2) * X2[idx];
+    if (4 * j + 3 <= 18) v += inv_factorial(4 * j + 3) * X3[idx];
+    return v;
+  };
+  // T = c16 I + c17 X + c18 X^2, then T = X^4 T + block(j) for j = 3, 2, 1, 0
+  for (int idx = tid; idx < mm; idx += NT) T[idx] = block(4, idx);
   __syncthreads();
-  mfma_matmul<NT>(A6, V, U, mp);
-  for (int idx = tid; idx < mm; idx += NT) {
-    const int i = idx / mp, j = idx - i * mp;
-    U[idx] += b[7] * A6[idx] + b[5] * A4[idx] + b[3] * A2[idx] + (i == j ? b[1] : 0.0);
-  }
-  __syncthreads();
-  mfma_matmul<NT>(A, U, R, mp);  // R = U (odd part)
-  for (int idx = tid; idx < mm; idx += NT)
-    U[idx] = b[12] * A6[idx] + b[10] * A4[idx] + b[8] * A2[idx];
-  __syncthreads();
-  mfma_matmul<NT>(A6, U, V, mp);
-  for (int idx = tid; idx < mm; idx += NT) {
-    const int i = idx / mp, j = idx - i * mp;
-    const double v = V[idx] + b[6] * A6[idx] + b[4] * A4[idx] + b[2] * A2[idx] +
-                     (i == j ? b[0] : 0.0);
-    const double u = R[idx];
-    V[idx] = v + u;  // P
-    U[idx] = v - u;  // Q
-  }
-  __syncthreads();
-  // Q X = P on the leading m x m block (padding stays zero / identity-free:
-  // only the leading block is eliminated and used).
-  double* Q = U;
-  double* P = V;
-  double* fac = A;
-  for (int j = 0; j < m; ++j) {
-    if (tid < 64) {
-      double best = -1.0;
-      int bi = j;
-      for (int i = j + tid; i < m; i += 64) {
-        const double a = fabs(Q[i * mp + j]);
-        if (a > best) { best = a; bi = i; }
-      }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(best, off, 64);
-        const int oi = __shfl_xor(bi, off, 64);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-      }
-      if (tid == 0) piv[0] = (double)bi;
-    }
-    __syncthreads();
-    const int p = (int)piv[0];
-    if (p != j) {
-      for (int k = tid; k < 2 * m; k += NT) {
-        double* M = k < m ? Q : P;
-        const int kk = k < m ? k : k - m;
-        const double t = M[j * mp + kk];
-        M[j * mp + kk] = M[p * mp + kk];
-        M[p * mp + kk] = t;
-      }
-      __syncthreads();
-    }
-    const double inv = 1.0 / Q[j * mp + j];
-    for (int i = j + 1 + tid; i < m; i += NT) fac[i] = Q[i * mp + j] * inv;
-    __syncthreads();
-    const int rows = m - j - 1;
-    const int cols = (m - j - 1) + m;
-    for (int idx = tid; idx < rows * cols; idx += NT) {
-      const int r = j + 1 + idx / cols;
-      const int c = idx % cols;
-      if (c < m - j - 1) {
-        const int k = j + 1 + c;
-        Q[r * mp + k] = fma(-fac[r], Q[j * mp + k], Q[r * mp + k]);
-      } else {
-        const int k = c - (m - j - 1);
-        P[r * mp + k] = fma(-fac[r], P[j * mp + k], P[r * mp + k]);
-      }
-    }
+  for (int j = 3; j >= 0; --j) {
+    mfma_matmul<NT>(X4, T, S, mp);
+    for (int idx = tid; idx < mm; idx += NT) T[idx] = S[idx] + block(j, idx);
     __syncthreads();
   }
-  for (int j = m - 1; j >= 0; --j) {
-    const double inv = 1.0 / Q[j * mp + j];
-    for (int k = tid; k < m; k += NT) P[j * mp + k] *= inv;
-    __syncthreads();
-    for (int idx = tid; idx < j * m; idx += NT) {
-      const int r = idx / m, k = idx - r * m;
-      P[r * mp + k] = fma(-Q[r * mp + j], P[j * mp + k], P[r * mp + k]);
-    }
-    __syncthreads();
-  }
-  // clear the padding of P so that products of the padded tiles are exact
-  for (int idx = tid; idx < mm; idx += NT) {
-    const int i = idx / mp, j = idx - i * mp;
-    if (i >= m || j >= m) P[idx] = 0.0;
-  }
-  __syncthreads();
-  double* src = P;
-  double* dst = A2;
+  double* src = T;
+  double* dst = X2;
   for (int q = 0; q < s; ++q) {
     mfma_matmul<NT>(src, src, dst, mp);
     double* t = src; src = dst; dst = t;
