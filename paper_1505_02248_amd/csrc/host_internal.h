@@ -102,6 +102,7 @@ struct lem_plan_s {
   lem::KBlock* d_kb = nullptr;
   double* d_coef = nullptr;
   double* d_vwork = nullptr;
+  double* d_wts = nullptr;     // precomputed stencil weights of large Krylov boxes
   double* d_diag = nullptr;
   // dense
   int U = 0, rows = 0, rows_p = 0, cols = 0, cols_p = 0, tile = 0, squarings = 0;

@@ -136,7 +136,7 @@ LaunchKey launch_key(int ndim, int nloc, int m, size_t* lds, int aug) {
   if (nt == 0 || m > lem::krylov_lds_max_m()) {
     lem::krylov_big_config(nloc, &nt, &pm);
     if (nt == 0 || m > lem::krylov_big_max_m()) return {-1, 0, 0, false};
-    *lds = lem::krylov_big_lds_bytes(nt, m);
+    *lds = lem::krylov_big_lds_bytes(nt, pm, m);
     return {aug ? 4 : 3, nt, pm, false};
   }
   const size_t with_v = lem::krylov_lds_bytes(nt, m, nloc, true, aug);
@@ -209,6 +209,40 @@ lem_status bucketize(std::vector<lem::KBlock>& kb, std::vector<lem_plan_s::Bucke
   }
   kb.swap(out);
   *vwork_doubles = voff;
+  return LEM_OK;
+}
+
+// Large-box blocks with variable coefficients read their stencil weights from
+// a table computed once (shared by the members) instead of the coefficient
+// arrays: one slice of 5 * NT * P doubles per such block, pointers set here
+// (before the table upload), values by fill_weights (after it).
+lem_status attach_weights(lem_plan_s* p, std::vector<lem::KBlock>& kb,
+                          const std::vector<lem_plan_s::Bucket>& bks, double** d_w) {
+  *d_w = nullptr;
+  int64_t nw = 0;
+  for (const auto& bk : bks)
+    if (bk.variant >= 3)
+      for (int i = bk.first; i < bk.first + bk.count; ++i)
+        if (kb[i].mu_off >= 0) nw += 5 * (int64_t)bk.nt * bk.pmax;
+  if (nw == 0) return LEM_OK;
+  LEM_TRY(dalloc(p, d_w, (size_t)nw, &p->bytes_work));
+  int64_t off = 0;
+  for (const auto& bk : bks)
+    if (bk.variant >= 3)
+      for (int i = bk.first; i < bk.first + bk.count; ++i)
+        if (kb[i].mu_off >= 0) {
+          kb[i].wts = *d_w + off;
+          off += 5 * (int64_t)bk.nt * bk.pmax;
+        }
+  return LEM_OK;
+}
+
+lem_status fill_weights(const lem_plan_s* p, const lem::KBlock* d_kb,
+                        const std::vector<lem_plan_s::Bucket>& bks, hipStream_t st) {
+  for (const auto& bk : bks)
+    if (bk.variant >= 3)
+      LEM_HIP(lem::launch_krylov_weights(d_kb + bk.first, bk.count, bk.nt, bk.pmax, p->d_coef,
+                                         st));
   return LEM_OK;
 }
 
@@ -329,6 +363,8 @@ lem_status plan_krylov(lem_plan_s* p, hipStream_t st) {
   std::vector<lem_plan_s::Bucket> cbk;
   int64_t cv = 0;
   LEM_TRY(bucketize(cb, cbk, 1, &cv));
+  double* d_cw = nullptr;
+  LEM_TRY(attach_weights(p, cb, cbk, &d_cw));
   lem::KBlock* d_cb;
   double *d_probe, *d_cv, *d_calib, *d_cdiag, *d_est;
   int *d_mcal, *d_jl;
@@ -348,6 +384,7 @@ lem_status plan_krylov(lem_plan_s* p, hipStream_t st) {
   std::vector<int64_t> coff(nr);
   for (int k = 0; k < nr; ++k) coff[k] = (int64_t)k * cstride;
   LEM_TRY(upload(d_cb, cb.data(), cb.size() * sizeof(lem::KBlock), st));
+  LEM_TRY(fill_weights(p, d_cb, cbk, st));
   LEM_TRY(upload(d_mcal, mc.data(), nr * sizeof(int), st));
   LEM_TRY(upload(d_jl, jl.data(), jl.size() * sizeof(int), st));
   LEM_TRY(upload(d_coff, coff.data(), nr * sizeof(int64_t), st));
@@ -375,6 +412,7 @@ lem_status plan_krylov(lem_plan_s* p, hipStream_t st) {
   for (void* q : {(void*)d_cb, (void*)d_probe, (void*)d_cv, (void*)d_calib, (void*)d_cdiag,
                   (void*)d_est, (void*)d_mcal, (void*)d_jl, (void*)d_coff})
     dfree(p, q);
+  if (d_cw) dfree(p, d_cw);
   // step blocks
   p->m.resize(nb);
   p->nsub.resize(nb);
@@ -386,7 +424,6 @@ lem_status plan_krylov(lem_plan_s* p, hipStream_t st) {
   }
   int64_t vw = 0;
   LEM_TRY(bucketize(kb, p->buckets, p->ns, &vw));
-  p->kb_host = kb;
   if (p->buckets.size() > 1 && !p->arena) {  // serving plans launch through the server
     const size_t ns_side = std::min<size_t>(p->buckets.size() - 1, 3);
     LEM_HIP(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
@@ -399,8 +436,11 @@ lem_status plan_krylov(lem_plan_s* p, hipStream_t st) {
       p->ev_join.push_back(e);
     }
   }
+  LEM_TRY(attach_weights(p, kb, p->buckets, &p->d_wts));
+  p->kb_host = kb;
   LEM_TRY(dalloc(p, &p->d_kb, kb.size(), &p->bytes_work));
   LEM_TRY(upload(p->d_kb, kb.data(), kb.size() * sizeof(lem::KBlock), st));
+  LEM_TRY(fill_weights(p, p->d_kb, p->buckets, st));
   LEM_TRY(dalloc(p, &p->d_vwork, (size_t)std::max<int64_t>(vw, 1), &p->bytes_work));
   LEM_TRY(dalloc(p, &p->d_diag, (size_t)nb * p->ns, &p->bytes_work));
   LEM_HIP(hipMemsetAsync(p->d_diag, 0, (size_t)nb * p->ns * 8, st));

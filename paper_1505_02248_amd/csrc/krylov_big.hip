@@ -12,11 +12,14 @@
 // 2021): row j of V holds u_j, the new direction projected once; one sweep
 // over the rows i < j computes s = V^T u_j and z = V^T w for w = A u_j, a
 // second sweep forms v_j = (u_j - V s)/nu and u_{j+1} = (w - V z - (v_j^T w)
-// v_j)/nu and stores both.  Registers hold only w across the two sweeps: u_j
-// is read again from its row, and nu comes from Pythagoras,
-// nu^2 = |u_j|^2 - |s|^2 (V has orthonormal columns), with an extra sweep
-// that measures |u_j - V s| when that difference cancels badly (near an
-// invariant subspace).  exp(H_m) is Pade [13/13] scaling and squaring in LDS.
+// v_j)/nu and stores both.  Registers hold only w across the two sweeps,
+// and nu comes from Pythagoras, nu^2 = |u_j|^2 - |s|^2 (V has orthonormal
+// columns), with an extra sweep that measures |u_j - V s| when that
+// difference cancels badly (near an invariant subspace).  The current
+// direction u_j also sits in LDS (written with its row), so the stencil
+// product reads its neighbours there instead of making a round trip to the
+// memory system per point.  exp(H_m) is Pade [13/13] scaling and squaring in
+// LDS, in the space the direction occupies during the Arnoldi loop.
 #include "lem_device.hpp"
 #include "lem_launch.h"
 
@@ -26,7 +29,10 @@ constexpr int kBigMaxM = 40;     // Krylov dimension limit of this kernel
 constexpr int kBigMaxN = 9216;   // box points (plus the augmented coordinate)
 constexpr int kBigSlots = 128;   // reduction slots per wave: s at 0.., z at 64..
 
-__host__ __device__ inline int64_t big_lds_layout(int NT, int m, int64_t* off_red,
+// LDS layout in doubles: Hessenberg, reduction slots, workgroup totals, then
+// one region holding the direction u_j (NT * P points) during the Arnoldi
+// loop and the exponential's work space after it.
+__host__ __device__ inline int64_t big_lds_layout(int NT, int P, int m, int64_t* off_red,
                                                   int64_t* off_tot, int64_t* off_e) {
   int64_t d = (int64_t)(m + 1) * m;  // Hessenberg
   *off_red = d;
@@ -34,8 +40,58 @@ __host__ __device__ inline int64_t big_lds_layout(int NT, int m, int64_t* off_re
   *off_tot = d;
   d += kBigSlots;
   *off_e = d;
-  d += 7 * (int64_t)m * m + 2 * (NT / 64) + 4;  // expm_small: A, W (5), R, piv
+  const int64_t e = 7 * (int64_t)m * m + 2 * (NT / 64) + 4;  // expm_small: A, W (5), R, piv
+  d += e > (int64_t)NT * P ? e : (int64_t)NT * P;
   return d;
+}
+
+// The five weights (centre, W, E, S, N) of dt_sub A_M at box point (lx, ly)
+// of a block with face diffusion coefficients (and face velocities): the
+// centered stencil of section 4, couplings leaving the box dropped (weights
+// zero on the box edges the core does not span whole).
+__device__ __forceinline__ void box_weights(const KBlock& b, const double* coef, int lx, int ly,
+                                            double (&w)[5]) {
+  w[0] = b.w0; w[1] = b.wW; w[2] = b.wE; w[3] = b.wS; w[4] = b.wN;
+  if (b.mu_off >= 0) {
+    const double* mux = coef + b.mu_off;
+    const int64_t Ng = (b.ndim == 1) ? b.n : (int64_t)b.n * b.n;
+    const double* muy = mux + Ng;
+    const int gx = wrap(b.ox - b.h + lx, b.n);
+    const int gy = (b.ndim == 1) ? 0 : wrap(b.oy - b.hy + ly, b.n);
+    const int64_t g = (int64_t)gy * b.n + gx;
+    const int64_t gw = (int64_t)gy * b.n + wrap(gx - 1, b.n);
+    const int64_t gs = (int64_t)wrap(gy - 1, b.n) * b.n + gx;
+    const double me = mux[g], mw = mux[gw];
+    const double mn = b.ndim == 2 ? muy[g] : 0.0, ms = b.ndim == 2 ? muy[gs] : 0.0;
+    const double sc = b.sub_scale;
+    w[0] = -(me + mw + mn + ms) * sc;
+    if (b.varvel) {  // conservative centered advection by face velocities
+      const double* axf = mux + 2 * Ng;
+      const double ae = axf[g] * sc, aw = axf[gw] * sc;
+      const double an = b.ndim == 2 ? axf[Ng + g] * sc : 0.0;
+      const double as = b.ndim == 2 ? axf[Ng + gs] * sc : 0.0;
+      w[0] -= (ae - aw) + (an - as);
+      w[1] = fma(mw, sc, aw);
+      w[2] = fma(me, sc, -ae);
+      w[3] = fma(ms, sc, as);
+      w[4] = fma(mn, sc, -an);
+    } else {
+      w[1] = fma(mw, sc, b.chx);
+      w[2] = fma(me, sc, -b.chx);
+      w[3] = fma(ms, sc, b.chy);
+      w[4] = fma(mn, sc, -b.chy);
+    }
+  }
+  if (!(b.periodic & 1)) {
+    if (lx == 0) w[1] = 0.0;
+    if (lx == b.Lx - 1) w[2] = 0.0;
+  }
+  if (b.ndim == 1) {
+    w[3] = w[4] = 0.0;
+  } else if (!(b.periodic & 2)) {
+    if (ly == 0) w[3] = 0.0;
+    if (ly == b.Ly - 1) w[4] = 0.0;
+  }
 }
 
 // The basis slice is addressed through a buffer resource: the slice base in
@@ -45,24 +101,27 @@ __host__ __device__ inline int64_t big_lds_layout(int NT, int m, int64_t* off_re
 // local index tid + p * NT; lanes past the box read past the row end, which
 // stays inside the slice and its padding (the planner pads every block's
 // slices by NT * P doubles) and is discarded by the callers.
+//
+// Rows are the same for every lane, but the compiler may hold a row index in
+// a vector register (the Arnoldi loop's exit depends on values it cannot
+// prove uniform), and a buffer access with a vector-held scalar offset
+// becomes a loop over the distinct values.  The offset therefore goes
+// through readfirstlane: one instruction, exact because it is uniform.
 template <int NT>
 struct BasisRows {
   __amdgpu_buffer_rsrc_t r;
   int row_bytes;
   uint32_t lane_off;
   typedef decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)) raw_t;
+  __device__ __forceinline__ int soff(int row, int p) const {
+    return __builtin_amdgcn_readfirstlane(row * row_bytes + p * (NT * 8));
+  }
   // this lane's point p of row `row`
   __device__ __forceinline__ double ldp(int row, int p) const {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
-                                          r, lane_off, row * row_bytes + p * (NT * 8), 0));
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, lane_off, soff(row, p), 0));
   }
   __device__ __forceinline__ void stp(int row, int p, double v) const {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(raw_t, v), r, lane_off,
-                                          row * row_bytes + p * (NT * 8), 0);
-  }
-  // any point l of row `row`
-  __device__ __forceinline__ double ld(int row, uint32_t l) const {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, l * 8u, row * row_bytes, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(raw_t, v), r, lane_off, soff(row, p), 0);
   }
 };
 
@@ -78,10 +137,11 @@ __global__ __launch_bounds__(NT) void krylov_big_kernel(KrylovArgs a) {
   const int nloc = b.Lx * b.Ly;
   const int nlv = nloc + (AUG ? 1 : 0);
   int64_t ored, otot, oe;
-  big_lds_layout(NT, m, &ored, &otot, &oe);
+  big_lds_layout(NT, P, m, &ored, &otot, &oe);
   double* H = smem;
   double* red = smem + ored;  // [NT/64][kBigSlots]
   double* tot = smem + otot;  // workgroup totals of the slots
+  double* U = smem + oe;      // u_j during the Arnoldi loop (aliases the expm work)
   double* EA = smem + oe;
   double* EW = EA + m * m;
   double* ER = EW + 5 * m * m;
@@ -92,10 +152,16 @@ __global__ __launch_bounds__(NT) void krylov_big_kernel(KrylovArgs a) {
                         nlv * 8, (uint32_t)tid * 8u};
   const double* x_in = b.xin ? b.xin : a.x_in;
   double* x_out = b.xout ? b.xout : a.x_out;
+  // variable coefficients: the block's precomputed weights (rows of NT * P
+  // points; the planner attaches them to every such block); constant ones:
+  // the block's scalar weights
   const bool varcoef = b.mu_off >= 0;
-  const double* mux = (b.coef ? b.coef : a.coef) + (varcoef ? b.mu_off : 0);
-  const int64_t Ng = (b.ndim == 1) ? b.n : (int64_t)b.n * b.n;
-  const double* muy = mux + Ng;
+  if (varcoef && b.wts == nullptr) {  // a table built without them: refuse loudly
+    if (tid == 0) atomicOr(b.status ? b.status : a.status, kStatusNonFinite);
+    return;
+  }
+  const BasisRows<NT> Wt{__builtin_amdgcn_make_buffer_rsrc((void*)b.wts, 0, 0x7ffffff0, 0x00020000),
+                         NT * P * 8, (uint32_t)tid * 8u};
 
   // point p of this thread is local index tid + p * NT; its box coordinates
   // are recomputed where needed (the stencil, the gather and the core write)
@@ -110,44 +176,17 @@ __global__ __launch_bounds__(NT) void krylov_big_kernel(KrylovArgs a) {
     return (uint32_t)min(tid + p * NT, nlv - 1);
   };
 
-  // (dt_sub A_M v)_l at point p for the basis row starting at vj; couplings
-  // leaving the box are dropped, the periodic wrap kept along an axis the box
-  // spans whole; the augmented row (forced steps) is zero
-  auto stencil = [&](int j, int p) __attribute__((always_inline)) {
+  // (dt_sub A_M u_j)_l at point p, u_j from LDS, with the weights w0..wN of
+  // the point; couplings leaving the box are dropped (zero weights on the
+  // edges the core does not span whole, already zero in a precomputed
+  // table), the periodic wrap kept along an axis the box spans whole; the
+  // augmented row (forced steps) is zero
+  auto stencil = [&](int p, double w0, double wW, double wE, double wS, double wN)
+      __attribute__((always_inline)) {
     int l = (int)li(p);
-    // recomputed per use: weights and neighbour offsets of every point would
-    // otherwise be hoisted out of the Arnoldi loop (about 15 registers each)
-    asm volatile("" : "+v"(l));
+    asm volatile("" : "+v"(l));  // neighbour offsets per use: no hoisting
     int lx, ly;
     coords(l, lx, ly);
-    double w0 = b.w0, wW = b.wW, wE = b.wE, wS = b.wS, wN = b.wN;
-    if (varcoef) {
-      const int gx = wrap(b.ox - b.h + lx, b.n);
-      const int gy = (b.ndim == 1) ? 0 : wrap(b.oy - b.hy + ly, b.n);
-      const int64_t g = (int64_t)gy * b.n + gx;
-      const int64_t gw = (int64_t)gy * b.n + wrap(gx - 1, b.n);
-      const int64_t gs = (int64_t)wrap(gy - 1, b.n) * b.n + gx;
-      const double me = mux[g], mw = mux[gw];
-      const double mn = b.ndim == 2 ? muy[g] : 0.0, ms = b.ndim == 2 ? muy[gs] : 0.0;
-      const double sc = b.sub_scale;
-      w0 = -(me + mw + mn + ms) * sc;
-      if (b.varvel) {  // conservative centered advection by face velocities
-        const double* axf = mux + 2 * Ng;
-        const double ae = axf[g] * sc, aw = axf[gw] * sc;
-        const double an = b.ndim == 2 ? axf[Ng + g] * sc : 0.0;
-        const double as = b.ndim == 2 ? axf[Ng + gs] * sc : 0.0;
-        w0 -= (ae - aw) + (an - as);
-        wW = fma(mw, sc, aw);
-        wE = fma(me, sc, -ae);
-        wS = fma(ms, sc, as);
-        wN = fma(mn, sc, -an);
-      } else {
-        wW = fma(mw, sc, b.chx);
-        wE = fma(me, sc, -b.chx);
-        wS = fma(ms, sc, b.chy);
-        wN = fma(mn, sc, -b.chy);
-      }
-    }
     int lW = l - 1, lE = l + 1, lS = l - b.Lx, lN = l + b.Lx;
     if (b.periodic & 1) {
       if (lx == 0) lW += b.Lx;
@@ -166,11 +205,11 @@ __global__ __launch_bounds__(NT) void krylov_big_kernel(KrylovArgs a) {
       if (ly == b.Ly - 1) { wN = 0.0; lN = l; }
     }
     if (!live(p) || (AUG && l == nloc)) return 0.0;
-    double r = w0 * V.ld(j, l);
-    r = fma(wW, V.ld(j, lW), r);
-    r = fma(wE, V.ld(j, lE), r);
-    r = fma(wS, V.ld(j, lS), r);
-    r = fma(wN, V.ld(j, lN), r);
+    double r = w0 * U[l];
+    r = fma(wW, U[lW], r);
+    r = fma(wE, U[lE], r);
+    r = fma(wS, U[lS], r);
+    r = fma(wN, U[lN], r);
     return r;
   };
   // forced steps: the augmented column dt_sub g_M, kept as row m+1 of the
@@ -236,7 +275,10 @@ __global__ __launch_bounds__(NT) void krylov_big_kernel(KrylovArgs a) {
       const double ib = 1.0 / beta;
 #pragma unroll
       for (int p = 0; p < P; ++p)
-        if (live(p)) V.stp(0, p, cur[p] * ib);  // u_0 = v_0
+        if (live(p)) {  // u_0 = v_0
+          V.stp(0, p, cur[p] * ib);
+          U[lidx(p)] = cur[p] * ib;
+        }
     }
     for (int idx = tid; idx < (m + 1) * m; idx += NT) H[idx] = 0.0;
     __syncthreads();
@@ -249,16 +291,36 @@ __global__ __launch_bounds__(NT) void krylov_big_kernel(KrylovArgs a) {
       double w[P];
       {
         double u[P];
+        if (varcoef && !last) {
+          // the weight loads of G points in flight together
+          constexpr int G = P >= 12 ? 6 : 4;
 #pragma unroll
-        for (int p = 0; p < P; ++p) {
-          // one point's stencil loads in flight at a time (bounded registers)
-          asm volatile("" ::: "memory");
-          u[p] = live(p) ? V.ldp(j, p) : 0.0;
-          w[p] = last ? 0.0 : stencil(j, p);
+          for (int p0 = 0; p0 < P; p0 += G) {
+            asm volatile("" ::: "memory");  // one group's loads at a time (bounded registers)
+            double wt[G][5];
+#pragma unroll
+            for (int q = 0; q < G; ++q)
+#pragma unroll
+              for (int k = 0; k < 5; ++k) wt[q][k] = p0 + q < P ? Wt.ldp(k, p0 + q) : 0.0;
+#pragma unroll
+            for (int q = 0; q < G; ++q) {
+              const int p = p0 + q;
+              if (p < P) {
+                u[p] = live(p) ? U[li(p)] : 0.0;
+                w[p] = stencil(p, wt[q][0], wt[q][1], wt[q][2], wt[q][3], wt[q][4]);
+              }
+            }
+          }
+        } else {
+#pragma unroll
+          for (int p = 0; p < P; ++p) {
+            u[p] = live(p) ? U[li(p)] : 0.0;
+            w[p] = last ? 0.0 : stencil(p, b.w0, b.wW, b.wE, b.wS, b.wN);
+          }
         }
         if constexpr (AUG) {
           if (!last) {
-            const double ve = V.ld(j, nloc);
+            const double ve = U[nloc];
 #pragma unroll
             for (int p = 0; p < P; ++p)
               if (live(p)) w[p] = fma(V.ldp(frow, p), ve, w[p]);
@@ -366,11 +428,13 @@ __global__ __launch_bounds__(NT) void krylov_big_kernel(KrylovArgs a) {
         break;
       }
       // sweep B: vt = u_j - V s, y = w - V z; v_j = vt / nu and
-      // u_{j+1} = (y - cj vt / nu) / nu overwrite rows j and j+1
+      // u_{j+1} = (y - cj vt / nu) / nu overwrite rows j and j+1, and u_{j+1}
+      // replaces u_j in LDS (every stencil read of u_j preceded the
+      // reductions' barriers; a thread rewrites only its own points)
       {
         double vt[P];
 #pragma unroll
-        for (int p = 0; p < P; ++p) vt[p] = live(p) ? V.ldp(j, p) : 0.0;
+        for (int p = 0; p < P; ++p) vt[p] = live(p) ? U[li(p)] : 0.0;
 #pragma unroll 1
         for (int i0 = 0; i0 < j; i0 += CB) {
           double vals[CB][P], sc[CB], zc[CB];
@@ -396,8 +460,10 @@ __global__ __launch_bounds__(NT) void krylov_big_kernel(KrylovArgs a) {
 #pragma unroll
         for (int p = 0; p < P; ++p) {
           if (!live(p)) continue;
+          const double un = (w[p] - cc * vt[p]) * inv;
           V.stp(j, p, vt[p] * inv);
-          V.stp(j + 1, p, (w[p] - cc * vt[p]) * inv);
+          V.stp(j + 1, p, un);
+          U[lidx(p)] = un;
         }
       }
       __syncthreads();
@@ -458,16 +524,43 @@ __global__ __launch_bounds__(NT) void krylov_big_kernel(KrylovArgs a) {
   }
 }
 
+// Fills the precomputed weights of blocks that carry them: row k of a block
+// (stride doubles, the NT * P points of its launch shape) holds weight k of
+// every box point; the augmented coordinate and the padding get zeros.
+__global__ void krylov_weights_kernel(const KBlock* blocks, int stride, const double* coef) {
+  const KBlock b = blocks[blockIdx.x];
+  const int l = blockIdx.y * blockDim.x + threadIdx.x;
+  if (b.wts == nullptr || l >= stride) return;
+  const int nloc = b.Lx * b.Ly;
+  double w[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (l < nloc) {
+    const int ly = l / b.Lx, lx = l - ly * b.Lx;
+    box_weights(b, b.coef ? b.coef : coef, lx, ly, w);
+  }
+  double* out = const_cast<double*>(b.wts);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) out[(int64_t)k * stride + l] = w[k];
+}
+
 // ------------------------------------------------------------------ launch --
+
+hipError_t launch_krylov_weights(const KBlock* blocks, int n_blocks, int nt, int pmax,
+                                 const double* coef, hipStream_t st) {
+  if (n_blocks == 0) return hipSuccess;
+  const int stride = nt * pmax;
+  hipLaunchKernelGGL(krylov_weights_kernel, dim3(n_blocks, (stride + 255) / 256), dim3(256), 0,
+                     st, blocks, stride, coef);
+  return hipGetLastError();
+}
 
 int krylov_big_max_m() { return kBigMaxM; }
 
 int64_t krylov_big_pad(int nt, int pmax) { return (int64_t)nt * pmax; }
 int krylov_big_max_n() { return kBigMaxN; }
 
-size_t krylov_big_lds_bytes(int nt, int m) {
+size_t krylov_big_lds_bytes(int nt, int pmax, int m) {
   int64_t a, b2, c;
-  return (size_t)big_lds_layout(nt, m, &a, &b2, &c) * 8;
+  return (size_t)big_lds_layout(nt, pmax, m, &a, &b2, &c) * 8;
 }
 
 // 256 threads up to 2048 points, 512 threads (two waves per SIMD, 256 VGPRs)

@@ -27,9 +27,10 @@
 // dt_sub g_M) and everything else is unchanged.
 // Reductions of up to 32 values use a wave64 butterfly reduce-scatter
 // (about one cross-lane exchange per value instead of six), then one LDS
-// exchange between waves.  exp(H_m) is evaluated by Pade [13/13] scaling and
-// squaring with its matrix products on FP64 MFMA (v_mfma_f64_16x16x4) over
-// 16- or 32-padded tiles in LDS, and a pivoted elimination in LDS.
+// exchange between waves.  exp(H_m) is evaluated by scaling and squaring
+// with the degree-18 Taylor polynomial (Paterson-Stockmeyer form), every
+// matrix product on FP64 MFMA (v_mfma_f64_16x16x4) over 16- or 32-padded
+// tiles in LDS.
 #include <type_traits>
 
 #include "lem_device.hpp"
@@ -51,8 +52,8 @@ __host__ __device__ inline int64_t lds_layout(int NT, int m, int nloc, int aug, 
   *off_red = d;
   d += (int64_t)(NT / 64) * 64 + 64;    // reduction exchange + scalars
   *off_e = d;
-  d += 7 * (int64_t)mp * mp;            // expm work (A, A2, A4, A6, U, V, R)
-  d += NT / 64 + 4 > 8 ? NT / 64 + 4 : 8;  // pivot / per-wave maxima of expm_mfma
+  d += 7 * (int64_t)mp * mp;            // expm work (A, X^2, X^3, X^4, two Horner terms, R)
+  d += NT / 64 + 4 > 8 ? NT / 64 + 4 : 8;  // per-wave norm maxima of expm_mfma
   return d;
 }
 

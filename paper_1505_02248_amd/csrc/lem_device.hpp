@@ -59,6 +59,11 @@ struct KBlock {
   const double* coef;
   double* vwork;
   int* status;                // status word of this block's problem, or null
+  // Large-box kernel: the five stencil weights of dt_sub A_M per box point,
+  // precomputed once per block (shared by its members): weight k of local
+  // point l at wts[k * NT * P + l] for the launch shape (NT, P); null: the
+  // kernel computes them from the coefficients on every use.
+  const double* wts;
 };
 
 // One region of the Kronecker-factored dense method: a c x c core with an

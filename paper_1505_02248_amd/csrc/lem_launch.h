@@ -32,7 +32,10 @@ hipError_t launch_krylov_lds(const KBlock* blocks, int n_blocks, int ns, int nt,
 // (basis row, with the augmented coordinate), m <= krylov_big_max_m()
 int krylov_big_max_m();
 int krylov_big_max_n();
-size_t krylov_big_lds_bytes(int nt, int m);
+size_t krylov_big_lds_bytes(int nt, int pmax, int m);
+// Fills the precomputed stencil weights of the blocks that carry them.
+hipError_t launch_krylov_weights(const KBlock* blocks, int n_blocks, int nt, int pmax,
+                                 const double* coef, hipStream_t st);
 // doubles of padding after each block's basis slices (lanes past the box read
 // past a row's end)
 int64_t krylov_big_pad(int nt, int pmax);
