@@ -42,18 +42,31 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 
 constexpr int kLdsMaxM = 30;  // Krylov dimension limit of this kernel
 
-// LDS layout in doubles; mirrored by krylov_lds_bytes() on the host.
-__host__ __device__ inline int64_t lds_layout(int NT, int m, int nloc, int aug, int64_t* off_h,
-                                              int64_t* off_red, int64_t* off_e) {
+// LDS layout in doubles; mirrored by krylov_lds_bytes() on the host.  An
+// LDS-resident basis (vlds) comes first, followed by the Hessenberg, the
+// reduction exchange and the exponential's work space.  A streamed basis
+// leaves one row in LDS, the current direction u_j for the stencil product,
+// which the exponential's work space reuses after the Arnoldi loop.
+__host__ __device__ inline int64_t lds_layout(int NT, int m, int nloc, bool vlds, int aug,
+                                              int64_t* off_h, int64_t* off_red, int64_t* off_e) {
   const int mp = m <= 16 ? 16 : 32;
-  int64_t d = (int64_t)(m + 1 + aug) * nloc;  // basis (+ the forcing column row)
+  // expm work (A, X^2, X^3, X^4, two Horner terms, R) and per-wave norm maxima
+  const int64_t e = 7 * (int64_t)mp * mp + (NT / 64 + 4 > 8 ? NT / 64 + 4 : 8);
+  int64_t d;
+  if (vlds) {
+    d = (int64_t)(m + 1 + aug) * nloc;  // basis (+ the forcing column row)
+  } else {
+    *off_e = 0;
+    d = e > nloc ? e : nloc;            // u_j, then the expm work
+  }
   *off_h = d;
   d += (int64_t)(m + 1) * m;            // Hessenberg
   *off_red = d;
   d += (int64_t)(NT / 64) * 64 + 64;    // reduction exchange + scalars
-  *off_e = d;
-  d += 7 * (int64_t)mp * mp;            // expm work (A, X^2, X^3, X^4, two Horner terms, R)
-  d += NT / 64 + 4 > 8 ? NT / 64 + 4 : 8;  // per-wave norm maxima of expm_mfma
+  if (vlds) {
+    *off_e = d;
+    d += e;
+  }
   return d;
 }
 
@@ -226,7 +239,7 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
   const int nloc = b.Lx * b.Ly;   // points of the box
   const int nlv = nloc + (AUG ? 1 : 0);  // basis row length (plus the augmented coordinate)
   int64_t oh, ored, oe;
-  const int64_t ostage = lds_layout(NT, m, VLDS ? nlv : 0, AUG ? 1 : 0, &oh, &ored, &oe);
+  const int64_t ostage = lds_layout(NT, m, nlv, VLDS, AUG ? 1 : 0, &oh, &ored, &oe);
   VPtr V;
   if constexpr (VLDS) {
     V = smem;
@@ -238,6 +251,7 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
   double* red = smem + ored;  // [NT/64][32] (streamed: [NT/64][64])
   double* tot = red + (NT / 64) * 64;  // 64 workgroup totals (streamed sweeps)
   double* EA = smem + oe;
+  double* U = smem;  // streamed basis: u_j during the Arnoldi loop (aliases EA)
   double* EW = EA + mp * mp;
   double* ER = EW + 5 * mp * mp;
   double* piv = ER + mp * mp;
@@ -567,6 +581,12 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
       break;
     }
     store_row(0, cur, 1.0 / beta);
+    if constexpr (!VLDS) {
+      const double ib = 1.0 / beta;
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+        if (live[p]) U[li[p]] = cur[p] * ib;
+    }
     for (int idx = tid; idx < (m + 1) * m; idx += NT) H[idx] = 0.0;
     __syncthreads();
 
@@ -623,7 +643,7 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
         const bool last = j == m;
         double w[P];
 #pragma unroll
-        for (int p = 0; p < P; ++p) w[p] = last ? 0.0 : stencil(V + (int64_t)j * nlv, p);
+        for (int p = 0; p < P; ++p) w[p] = last ? 0.0 : stencil(U, p);
         if (!last) add_forcing(j, w);
         // sweep A: s_i at slot i, z_i at slot 32 + i, |u|^2 at 31, u^T w at 63.
         // Rows go in groups of GR; the 2*GR partial sums of a group are
@@ -770,6 +790,7 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
           if (live[p]) {
             V[(int64_t)j * nlv + li[p]] = vj;
             V[(int64_t)(j + 1) * nlv + li[p]] = u[p];
+            U[li[p]] = u[p];  // every stencil read of u_j preceded the barriers above
           } else {
             u[p] = 0.0;
           }
@@ -844,7 +865,7 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
 
 size_t krylov_lds_bytes(int nt, int m, int nloc, bool vlds, int aug) {
   int64_t a, b2, c;
-  return (size_t)lds_layout(nt, m, vlds ? nloc : 0, aug, &a, &b2, &c) * 8;
+  return (size_t)lds_layout(nt, m, nloc, vlds, aug, &a, &b2, &c) * 8;
 }
 
 size_t krylov_stage_bytes(int nt, bool vlds, bool varcoef, bool varvel, int ndim, int lx,
