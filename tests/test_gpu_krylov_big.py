@@ -1,8 +1,9 @@
 """GPU parity of the large-box Krylov kernel against the CPU FP64 oracle:
 Krylov local actions (section 4.3) on boxes above 4096 points -- up to the
 9216 points of a 64^2 core with 16-point buffers -- and with Krylov
-dimensions of 31..40, for constant and lognormal diffusivity, a forcing, one
-and two members, and calibrated dimensions.  The oracle takes every local
+dimensions of 31..40, for constant and lognormal diffusivity, vortex face
+velocities, column-wise boxes on an anisotropic mesh, a forcing, one and two
+members, and calibrated dimensions.  The oracle takes every local
 action of these boxes by its own Krylov method (dense exponentials of 9216^2
 matrices are out of reach on the CPU) at tolerance 1e-16; FP64 bar 1e-12."""
 import numpy as np
@@ -122,3 +123,35 @@ def test_uneven_1024_grid_sampled_blocks():
                      krylov_tol=1e-16)
     rows = np.concatenate([P.scatter_map(b, 2, p.n) for b in sample])
     assert rel_l2(got[rows], want[rows]) <= 1e-12
+
+
+def test_vortex_faces_8464_point_boxes():
+    # face velocities of the single vortex (conservative centered advection):
+    # 64^2 cores with 14-point buffers, the 512 x 18 shape with the stencil
+    # weights precomputed per block and shared by the two members
+    p = L.workload_2d_vortex(n=128, n_states=2, courant=2.0)
+    plan = lem.Plan(lem.Operator.from_problem(p), p.dt, method="krylov", core=64, halo=14,
+                    n_states=2, krylov_m_max=40, max_substeps=16, krylov_tol=1e-13)
+    q = plan.query()
+    assert q["n_loc_max"] == 92 * 92 and q["n_blocks"] == 4
+    got = run(plan, p.states, 2)
+    want = oracle(p, plan, p.states, 2)
+    assert rel_l2(got, want) <= 1e-12
+    assert plan.query()["device_status"] == 0
+
+
+def test_columns_anisotropic_dimension_above_30():
+    # column-wise cores on the anisotropic mesh (vertical wrap kept in every
+    # box, flattened vortex faces) with a fixed dimension of 33: 3456-point
+    # boxes on the 512 x 8 shape of the large-box kernel
+    p = L.workload_2d_columns(n=96, n_states=2)
+    plan = lem.Plan(lem.Operator.from_problem(p), p.dt, method="krylov", core=12, halo=12,
+                    n_states=2, columns=True, krylov_m=33, krylov_m_max=40, max_substeps=16,
+                    krylov_tol=1e-13)
+    m_blk, _ = plan.krylov()
+    assert np.all(m_blk == 33)
+    assert plan.query()["n_loc_max"] == 36 * 96
+    got = run(plan, p.states, 2)
+    want = oracle(p, plan, p.states, 2)
+    assert rel_l2(got, want) <= 1e-12
+    assert plan.query()["device_status"] == 0
