@@ -401,24 +401,27 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
     }
     int l = li[p];
     if constexpr (!PREW) asm volatile("" : "+v"(l));  // neighbour offsets per use: no hoisting
+    // Neighbours wrap along the axes the box spans whole; on the other edges
+    // (zero weight) and for points without couplings (lanes past the box, the
+    // augmented coordinate) they fall back to the point itself, so all five
+    // reads are valid, finite and issued together (a zero weight adds 0).
+    int lx, ly;
+    coords(p, lx, ly);
     int lW = l - 1, lE = l + 1, lS = l - b.Lx, lN = l + b.Lx;
-    if (b.periodic) {  // neighbours wrap along the axes the box spans whole
-      int lx, ly;
-      coords(p, lx, ly);
-      if (b.periodic & 1) {
-        if (lx == 0) lW += b.Lx;
-        if (lx == b.Lx - 1) lE -= b.Lx;
-      }
-      if (b.periodic & 2) {
-        if (ly == 0) lS += nloc;
-        if (ly == b.Ly - 1) lN -= nloc;
-      }
+    if (lx == 0) lW = (b.periodic & 1) ? lW + b.Lx : l;
+    if (lx == b.Lx - 1) lE = (b.periodic & 1) ? lE - b.Lx : l;
+    if (b.ndim == 1) {
+      lS = lN = l;
+    } else {
+      if (ly == 0) lS = (b.periodic & 2) ? lS + nloc : l;
+      if (ly == b.Ly - 1) lN = (b.periodic & 2) ? lN - nloc : l;
     }
+    if (!live[p] || (AUG && l == nloc)) lW = lE = lS = lN = l;
     double r = w0 * vj[l];
-    if (wW != 0.0) r = fma(wW, vj[lW], r);
-    if (wE != 0.0) r = fma(wE, vj[lE], r);
-    if (wS != 0.0) r = fma(wS, vj[lS], r);
-    if (wN != 0.0) r = fma(wN, vj[lN], r);
+    r = fma(wW, vj[lW], r);
+    r = fma(wE, vj[lE], r);
+    r = fma(wS, vj[lS], r);
+    r = fma(wN, vj[lN], r);
     return r;
   };
   // forced steps: w += (augmented column) x (augmented coordinate of row j)
