@@ -247,6 +247,12 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
     double* g = (b.vwork ? b.vwork : a.vwork + b.v_off) + (int64_t)s * (m + 1 + (AUG ? 1 : 0)) * nlv;
     V = (VPtr)g;
   }
+  // A streamed basis is addressed through a buffer resource: the slice base
+  // and the row offset in scalar registers (readfirstlane: the compiler may
+  // hold the uniform row index in a vector register), the point offset per
+  // lane, so the sweeps hold no 64-bit address per load.
+  const __amdgpu_buffer_rsrc_t vrs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)V, 0, 0x7ffffff0, 0x00020000);
   double* H = smem + oh;
   double* red = smem + ored;  // [NT/64][32] (streamed: [NT/64][64])
   double* tot = red + (NT / 64) * 64;  // 64 workgroup totals (streamed sweeps)
@@ -301,6 +307,26 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
     const int ly = li[p] / b.Lx;
     xy[p] = (li[p] - ly * b.Lx) | (ly << 16);
   }
+  // basis row i at this thread's point p (lanes past the box: point 0)
+  auto vld = [&](int i, int p) __attribute__((always_inline)) -> double {
+    if constexpr (VLDS) {
+      return V[(int64_t)i * nlv + li[p]];
+    } else {
+      return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                            vrs, (uint32_t)li[p] * 8u,
+                                            __builtin_amdgcn_readfirstlane(i * nlv * 8), 0));
+    }
+  };
+  auto vst = [&](int i, int p, double v) __attribute__((always_inline)) {
+    if constexpr (VLDS) {
+      V[(int64_t)i * nlv + li[p]] = v;
+    } else {
+      typedef decltype(__builtin_amdgcn_raw_buffer_load_b64(vrs, 0, 0, 0)) raw_t;
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(raw_t, v), vrs,
+                                            (uint32_t)li[p] * 8u,
+                                            __builtin_amdgcn_readfirstlane(i * nlv * 8), 0);
+    }
+  };
   auto coords = [&](int p, int& lx, int& ly) __attribute__((always_inline)) {
     int c = xy[p];
     if constexpr (!PREW) asm volatile("" : "+v"(c));  // recompute per use: no hoisting
@@ -374,15 +400,14 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
   };
   // Forced steps: the augmented column dt_sub g_M (zero on the augmented
   // row) is kept as row m+1 of the basis storage, written once here.
-  VPtr Fcol = V + (int64_t)(m + 1) * nlv;
   if constexpr (AUG) {
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       if (!live[p]) continue;
       int lx, ly;
       coords(p, lx, ly);
-      Fcol[li[p]] = li[p] == nloc ? 0.0
-                    : b.gscale * b.force[b.x_off + gather_index(b, lx, ly) * b.ns + s];
+      vst(m + 1, p, li[p] == nloc ? 0.0
+                    : b.gscale * b.force[b.x_off + gather_index(b, lx, ly) * b.ns + s]);
     }
     __syncthreads();
   }
@@ -429,7 +454,7 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
     if constexpr (!AUG) return;
     const double ve = V[(int64_t)j * nlv + nloc];
 #pragma unroll
-    for (int p = 0; p < P; ++p) w[p] = fma(Fcol[li[p]], ve, w[p]);
+    for (int p = 0; p < P; ++p) w[p] = fma(vld(m + 1, p), ve, w[p]);
   };
 
   double cur[P];
@@ -471,7 +496,7 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
         for (int q = 0; q < CH; ++q) {
           const int i = min(c * CH + q, jj);
 #pragma unroll
-          for (int p = 0; p < P; ++p) vals[q][p] = V[(int64_t)i * nlv + li[p]];
+          for (int p = 0; p < P; ++p) vals[q][p] = vld(i, p);
         }
 #pragma unroll
         for (int q = 0; q < CH; ++q) {
@@ -496,7 +521,7 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
         const double t = red_total<NT>(red, i);
         hc[q] = (i0 + q <= jj) ? t : 0.0;
 #pragma unroll
-        for (int p = 0; p < P; ++p) vals[q][p] = V[(int64_t)i * nlv + li[p]];
+        for (int p = 0; p < P; ++p) vals[q][p] = vld(i, p);
       }
 #pragma unroll
       for (int q = 0; q < CH; ++q) {
@@ -544,7 +569,7 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
         for (int q = 0; q < CH; ++q) {
           const int i = min(i0 + q, jj);
 #pragma unroll
-          for (int p = 0; p < P; ++p) vals[q][p] = V[(int64_t)i * nlv + li[p]];
+          for (int p = 0; p < P; ++p) vals[q][p] = vld(i, p);
         }
 #pragma unroll
         for (int q = 0; q < CH; ++q) {
@@ -569,7 +594,7 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
   auto store_row = [&](int i, const double (&x)[P], double scale) __attribute__((always_inline)) {
 #pragma unroll
     for (int p = 0; p < P; ++p)
-      if (live[p]) V[(int64_t)i * nlv + li[p]] = x[p] * scale;
+      if (live[p]) vst(i, p, x[p] * scale);
   };
 
   const double beta0 = sqrt(norm2(cur));
@@ -652,7 +677,7 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
         // Rows go in groups of GR; the 2*GR partial sums of a group are
         // reduced across the wave at once by the butterfly reduce-scatter
         // (lane l ends with the total of value l / (32 / GR)).
-        constexpr int GR = P >= 16 ? 4 : 8;
+        constexpr int GR = (P >= 16 || NT >= 1024) ? 4 : 8;  // 1024 threads: 128 VGPRs
 #pragma unroll 1
         for (int i0 = 0; i0 < j; i0 += GR) {
           double t[2 * GR];
@@ -667,7 +692,7 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
             for (int q = 0; q < CHS; ++q) {
               const int i = min(i0 + q0 + q, j - 1);
 #pragma unroll
-              for (int p = 0; p < P; ++p) vals[q][p] = V[(int64_t)i * nlv + li[p]];
+              for (int p = 0; p < P; ++p) vals[q][p] = vld(i, p);
             }
 #pragma unroll
             for (int q = 0; q < CHS; ++q) {
@@ -722,7 +747,7 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
             sc[q] = ok ? tot[i] : 0.0;
             zc[q] = ok ? tot[32 + i] : 0.0;
 #pragma unroll
-            for (int p = 0; p < P; ++p) vals[q][p] = V[(int64_t)i * nlv + li[p]];
+            for (int p = 0; p < P; ++p) vals[q][p] = vld(i, p);
           }
 #pragma unroll
           for (int q = 0; q < CHS; ++q) {
@@ -791,8 +816,8 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
           const double vj = vt[p] * inv;
           u[p] = (y[p] - cc * vt[p]) * inv;
           if (live[p]) {
-            V[(int64_t)j * nlv + li[p]] = vj;
-            V[(int64_t)(j + 1) * nlv + li[p]] = u[p];
+            vst(j, p, vj);
+            vst(j + 1, p, u[p]);
             U[li[p]] = u[p];  // every stencil read of u_j preceded the barriers above
           } else {
             u[p] = 0.0;
@@ -830,7 +855,7 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
           const int i = min(i0 + q, k - 1);
           f[q] = (i0 + q < k) ? ER[i * kp] : 0.0;
 #pragma unroll
-          for (int p = 0; p < P; ++p) vals[q][p] = V[(int64_t)i * nlv + li[p]];
+          for (int p = 0; p < P; ++p) vals[q][p] = vld(i, p);
         }
 #pragma unroll
         for (int q = 0; q < CH; ++q)
