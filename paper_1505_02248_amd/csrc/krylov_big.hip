@@ -368,11 +368,9 @@ __global__ __launch_bounds__(NT) void krylov_big_kernel(KrylovArgs a) {
       totals();
       // nu = |u_j - V s| by Pythagoras unless it cancels
       const double uu = tot[62];
-      double ss = 0.0, sz = 0.0;
-      for (int i = 0; i < j; ++i) {
-        ss = fma(tot[i], tot[i], ss);
-        sz = fma(tot[i], tot[64 + i], sz);
-      }
+      // |s|^2 and s^T z, lane i holding row i (every wave sums them itself)
+      const double si = lane < j ? tot[lane] : 0.0, zi = lane < j ? tot[64 + lane] : 0.0;
+      const double ss = wave_sum(si * si), sz = wave_sum(si * zi);
       double nu2 = uu - ss;
       if (!(nu2 > 1e-4 * uu)) {
         // measured: |u_j - V s|^2 (slot 61)
@@ -396,11 +394,9 @@ __global__ __launch_bounds__(NT) void krylov_big_kernel(KrylovArgs a) {
       const double bw = tot[63];
       bool brk;
       if (j > 0) {
-        double hs = 0.0;
-        for (int i = 0; i < j; ++i) {
-          const double hij = H[i * m + j - 1] + tot[i];
-          hs = fma(hij, hij, hs);
-        }
+        // |corrected column j-1|^2, lane i holding row i (every wave sums it)
+        const double hij = lane < j ? H[lane * m + j - 1] + tot[lane] : 0.0;
+        const double hs = wave_sum(hij * hij);
         brk = !(nu > 1e-14 * sqrt(hs + nu * nu));  // invariant subspace reached
       } else {
         brk = !(nu > 0.0);
@@ -412,11 +408,20 @@ __global__ __launch_bounds__(NT) void krylov_big_kernel(KrylovArgs a) {
         double hcorr = 0.0;
         if (j > 0) hcorr = (i < j) ? H[i * m + j - 1] + tot[i] : nu;
         if (!last && !brk) {
-          double t = 0.0;
-          for (int l = (i > 0 ? i - 1 : 0); l < j; ++l) {
-            const double hil = (l == j - 1) ? hcorr : H[i * m + l];
-            t = fma(hil, tot[l], t);
+          // four partial sums: the loads of four terms in flight together
+          auto hl = [&](int l) __attribute__((always_inline)) {
+            return (l == j - 1) ? hcorr : H[i * m + l];
+          };
+          double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+          int l = i > 0 ? i - 1 : 0;
+          for (; l + 3 < j; l += 4) {
+            t0 = fma(hl(l), tot[l], t0);
+            t1 = fma(hl(l + 1), tot[l + 1], t1);
+            t2 = fma(hl(l + 2), tot[l + 2], t2);
+            t3 = fma(hl(l + 3), tot[l + 3], t3);
           }
+          for (; l < j; ++l) t0 = fma(hl(l), tot[l], t0);
+          const double t = (t0 + t1) + (t2 + t3);
           const double num = (i < j) ? tot[64 + i] : cj;
           H[i * m + j] = (num - t) / nu;
         }

@@ -638,8 +638,10 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
         __syncthreads();
         if (!(hn2 > 1e-4 * n1)) hn2 = norm2(w);  // severe cancellation: measure
         const double hn = sqrt(fmax(hn2, 0.0));
-        double hs = 0.0;
-        for (int i = 0; i <= j; ++i) hs = fma(H[i * m + j], H[i * m + j], hs);
+        // |column j of H|^2, lane i holding row i (every wave sums it itself)
+        const int ln = tid & 63;
+        const double hv = ln <= j ? H[ln * m + j] : 0.0;
+        const double hs = wave_sum(hv * hv);
         if (tid == 0) H[(j + 1) * m + j] = hn;
         if (!(hn > 1e-14 * sqrt(hs + hn * hn))) {  // invariant subspace reached
           k = j + 1;
@@ -773,11 +775,9 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
         // complete column j-1: H[i][j-1] += s_i, H[j][j-1] = nu
         bool brk = false;
         if (j > 0) {
-          double hs = 0.0;
-          for (int i = 0; i < j; ++i) {
-            const double hij = H[i * m + j - 1] + tot[i];
-            hs = fma(hij, hij, hs);
-          }
+          // |corrected column j-1|^2, lane i holding row i (every wave sums it)
+          const double hij = lane < j ? H[lane * m + j - 1] + tot[lane] : 0.0;
+          const double hs = wave_sum(hij * hij);
           brk = !(nu > 1e-14 * sqrt(hs + nu * nu));  // invariant subspace reached
         } else {
           brk = !(nu > 0.0);
@@ -794,11 +794,20 @@ __global__ __launch_bounds__(NT) void krylov_lds_kernel(KrylovArgs a) {
             hcorr = (i < j) ? H[i * m + j - 1] + tot[i] : nu;
           }
           if (!last && !brk) {
-            double t = 0.0;
-            for (int l = (i > 0 ? i - 1 : 0); l < j; ++l) {
-              const double hil = (l == j - 1) ? hcorr : H[i * m + l];
-              t = fma(hil, tot[l], t);
+            // four partial sums: the loads of four terms in flight together
+            auto hl = [&](int l) __attribute__((always_inline)) {
+              return (l == j - 1) ? hcorr : H[i * m + l];
+            };
+            double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+            int l = i > 0 ? i - 1 : 0;
+            for (; l + 3 < j; l += 4) {
+              t0 = fma(hl(l), tot[l], t0);
+              t1 = fma(hl(l + 1), tot[l + 1], t1);
+              t2 = fma(hl(l + 2), tot[l + 2], t2);
+              t3 = fma(hl(l + 3), tot[l + 3], t3);
             }
+            for (; l < j; ++l) t0 = fma(hl(l), tot[l], t0);
+            const double t = (t0 + t1) + (t2 + t3);
             const double num = (i < j) ? tot[32 + i] : cj;
             H[i * m + j] = (num - t) / nu;
           }
