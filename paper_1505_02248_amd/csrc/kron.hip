@@ -34,6 +34,12 @@ typedef __attribute__((address_space(1))) double gdouble;
 __device__ __forceinline__ double gload(const double* p, int64_t i) {
   return ((const gdouble*)p)[i];
 }
+// two adjacent doubles (16-byte aligned: i even, p 16-byte aligned)
+typedef double kd2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) kd2 gkd2;
+__device__ __forceinline__ kd2 gload2(const double* p, int64_t i) {
+  return ((const gkd2*)p)[i >> 1];
+}
 __device__ __forceinline__ void gstore(double* p, int64_t i, double v) {
   ((gdouble*)p)[i] = v;
 }
@@ -45,6 +51,7 @@ struct KronArgs {
   double* x_out;
   int* status;         // used when a block carries none
   int chunks;          // member groups of S per block in the grid
+  int vec_ns;          // member-vector loads: the member count of every block
 };
 
 constexpr int kKronMaxL = 128;  // box side
@@ -85,8 +92,10 @@ __device__ __forceinline__ int xcd_contiguous(int g, int count) {
 // Fragment layouts (16x16x4, f64): lane l supplies A[l%16][l/16] and
 // B[l/16][l%16]; accumulator register i of lane l is D[4 i + l/16][l%16].
 // (MINW: waves per SIMD the registers must allow; 4 for the ensemble shape
-// at c <= 32, i.e. two eight-wave workgroups per CU, which LDS allows too)
-template <int S, int NW, int MAXT, int LMAX, int MINW>
+// at c <= 32, i.e. two eight-wave workgroups per CU, which LDS allows too.
+// VEC: the member count is a multiple of S, and a thread loads all S members
+// of its points with 16-byte loads instead of one member per load.)
+template <int S, int NW, int MAXT, int LMAX, int MINW, bool VEC>
 __global__ __launch_bounds__(NW * 64, MINW) void kron_mfma_kernel(KronArgs a) {
   constexpr int NT = NW * 64;
   static_assert(NT % (16 * S) == 0, "threads cover whole (member, slab row) sets");
@@ -99,6 +108,10 @@ __global__ __launch_bounds__(NW * 64, MINW) void kron_mfma_kernel(KronArgs a) {
   // neighbouring blocks share buffer rows, in that XCD's L2
   const int g = xcd_contiguous(blockIdx.x, gridDim.x);
   const KronBlock b = a.blocks[g / a.chunks];
+  if (VEC && b.ns != a.vec_ns) {  // a table built against the launch's precondition
+    if (threadIdx.x == 0) atomicOr(b.status ? b.status : a.status, kStatusNonFinite);
+    return;
+  }
   const int s0 = (g % a.chunks) * S;
   if (s0 >= b.ns) return;
   const int sv = min(S, b.ns - s0);
@@ -158,18 +171,57 @@ __global__ __launch_bounds__(NW * 64, MINW) void kron_mfma_kernel(KronArgs a) {
       v[i] = gload(x_in, ok[i] ? (row + gx) * ns + s0 + sm : origin);
     }
   };
+  // VEC: thread (slab row rv, box column lv) loads the S members of columns
+  // lv + i STEPV, S adjacent doubles of the member-fastest state each
+  constexpr int STEPV = NT / 16;
+  constexpr int GV = LMAX / STEPV;
+  static_assert(!VEC || GV * S == GMAX, "member-vector loads cover the same slab");
+  const int rv = tid & 15, lv = tid >> 4;
+  auto slab_loads_v = [&](int ly0, double (&v)[GMAX], bool (&ok)[GMAX]) {
+    const int ly = ly0 + rv;
+    int gy = b.oy - h + ly;
+    gy += gy < 0 ? n : 0;
+    gy -= gy >= n ? n : 0;
+    const int64_t row = (int64_t)gy * n;
+    const bool row_ok = ly < L;
+#pragma unroll
+    for (int i = 0; i < GV; ++i) {
+      int gx = b.ox - h + lv + i * STEPV;
+      gx += gx < 0 ? n : 0;
+      gx -= gx >= n ? n : 0;
+      ok[i] = row_ok && lv + i * STEPV < L;
+      const int64_t base = ok[i] ? (row + gx) * ns + s0 : origin;
+#pragma unroll
+      for (int q = 0; q < S / 2; ++q) {
+        const kd2 t = gload2(x_in, base + 2 * q);
+        v[i * S + 2 * q] = t.x;
+        v[i * S + 2 * q + 1] = t.y;
+      }
+    }
+  };
   double pre[GMAX];
   bool pok[GMAX];
-  slab_loads(0, pre, pok);
+  if constexpr (VEC) slab_loads_v(0, pre, pok);
+  else slab_loads(0, pre, pok);
   kd4 acc[MAXT];
 #pragma unroll
   for (int j = 0; j < MAXT; ++j) acc[j] = (kd4){0.0, 0.0, 0.0, 0.0};
 
   for (int ly0 = 0; ly0 < L; ly0 += kSlab) {
     // store the prefetched slab (columns up to Lk; zero outside the box)
+    if constexpr (VEC) {
 #pragma unroll
-    for (int i = 0; i < GMAX; ++i)
-      if (lx0 + i * STEP < Lk) X[sm * XM + (lx0 + i * STEP) * 16 + rs] = pok[i] ? pre[i] : 0.0;
+      for (int i = 0; i < GV; ++i)
+        if (lv + i * STEPV < Lk) {
+#pragma unroll
+          for (int q = 0; q < S; ++q)
+            X[q * XM + (lv + i * STEPV) * 16 + rv] = pok[i] ? pre[i * S + q] : 0.0;
+        }
+    } else {
+#pragma unroll
+      for (int i = 0; i < GMAX; ++i)
+        if (lx0 + i * STEP < Lk) X[sm * XM + (lx0 + i * STEP) * 16 + rs] = pok[i] ? pre[i] : 0.0;
+    }
     __syncthreads();
     // E_y fragments of this slab for the resident tiles, issued before the
     // next slab's loads (the wait for them then leaves those in flight)
@@ -186,7 +238,10 @@ __global__ __launch_bounds__(NW * 64, MINW) void kron_mfma_kernel(KronArgs a) {
         ey[j][kk] = ok ? v : 0.0;
       }
     }
-    if (ly0 + kSlab < L) slab_loads(ly0 + kSlab, pre, pok);
+    if (ly0 + kSlab < L) {
+      if constexpr (VEC) slab_loads_v(ly0 + kSlab, pre, pok);
+      else slab_loads(ly0 + kSlab, pre, pok);
+    }
     // first contraction: one (member, 16 core columns) tile per wave at a
     // time, 16 box columns per pass
     for (int u = wave; u < S * ct; u += NW) {
@@ -262,46 +317,56 @@ __global__ __launch_bounds__(NW * 64, MINW) void kron_mfma_kernel(KronArgs a) {
 int kron_max_side() { return kKronMaxL; }
 int kron_max_core() { return kKronMaxC; }
 
-template <int S, int NW, int MAXT, int LMAX, int MINW>
+template <int S, int NW, int MAXT, int LMAX, int MINW, bool VEC>
 static hipError_t launch_kron_shape(const KronBlock* blocks, int n_blocks, int max_ns, int max_L,
                                     int max_c, const double* x_in, double* x_out, int* status,
                                     hipStream_t st) {
   const int chunks = (max_ns + S - 1) / S;
   const size_t lds = kron_lds_doubles(S, max_L, max_c) * sizeof(double);
-  auto fn = kron_mfma_kernel<S, NW, MAXT, LMAX, MINW>;
+  auto fn = kron_mfma_kernel<S, NW, MAXT, LMAX, MINW, VEC>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(fn, dim3((unsigned)((int64_t)n_blocks * chunks)), dim3(NW * 64), lds, st,
-                     KronArgs{blocks, n_blocks, x_in, x_out, status, chunks});
+                     KronArgs{blocks, n_blocks, x_in, x_out, status, chunks, VEC ? max_ns : 0});
   return hipGetLastError();
 }
 
-// Blocks of one launch may differ in core side (<= max_c <= 64), box side
-// (<= max_L <= 128) and member count (<= max_ns).  Shapes (members per
-// workgroup S, waves, resident tiles per wave = ceil((c/16)^2 S / waves), box
-// side bound of the prefetch registers):
+// Blocks of one launch may differ in core side (<= max_c <= 64) and box side
+// (<= max_L <= 128); with more than one member they share the member count
+// max_ns (single-state launches may mix any).  Shapes (members per workgroup
+// S, waves, resident tiles per wave = ceil((c/16)^2 S / waves), box side
+// bound of the prefetch registers):
 //   ensembles, c <= 32, L <= 64:  S = 4, 8 waves, 2 tiles
 //   other ensembles:              S = 2, 8 waves, 4 tiles
 //   single states:                S = 1, 4 waves, 1 tile (c <= 32) or 4
+// Member counts that S divides use 16-byte member-vector loads.
 hipError_t launch_kron(const KronBlock* blocks, int n_blocks, int max_ns, int max_L, int max_c,
                        const double* x_in, double* x_out, int* status, hipStream_t st) {
   if (n_blocks == 0) return hipSuccess;
   if (max_L > kKronMaxL || max_L < 1 || max_ns < 1 || max_c < 1 || max_c > kKronMaxC)
     return hipErrorInvalidValue;
-  if (max_ns >= 4 && max_c <= 32 && max_L <= 64)
-    return launch_kron_shape<4, 8, 2, 64, 4>(blocks, n_blocks, max_ns, max_L, max_c, x_in, x_out,
-                                          status, st);
-  if (max_ns >= 2)
-    return launch_kron_shape<2, 8, 4, kKronMaxL, 1>(blocks, n_blocks, max_ns, max_L, max_c, x_in,
-                                                 x_out, status, st);
+  if (max_ns >= 4 && max_c <= 32 && max_L <= 64) {
+    if (max_ns % 4 == 0)
+      return launch_kron_shape<4, 8, 2, 64, 4, true>(blocks, n_blocks, max_ns, max_L, max_c,
+                                                     x_in, x_out, status, st);
+    return launch_kron_shape<4, 8, 2, 64, 4, false>(blocks, n_blocks, max_ns, max_L, max_c, x_in,
+                                                    x_out, status, st);
+  }
+  if (max_ns >= 2) {
+    if (max_ns % 2 == 0)
+      return launch_kron_shape<2, 8, 4, kKronMaxL, 1, true>(blocks, n_blocks, max_ns, max_L,
+                                                            max_c, x_in, x_out, status, st);
+    return launch_kron_shape<2, 8, 4, kKronMaxL, 1, false>(blocks, n_blocks, max_ns, max_L, max_c,
+                                                           x_in, x_out, status, st);
+  }
   if (max_c <= 32)
-    return launch_kron_shape<1, 4, 1, kKronMaxL, 1>(blocks, n_blocks, max_ns, max_L, max_c, x_in,
-                                                 x_out, status, st);
-  return launch_kron_shape<1, 4, 4, kKronMaxL, 1>(blocks, n_blocks, max_ns, max_L, max_c, x_in,
-                                               x_out, status, st);
+    return launch_kron_shape<1, 4, 1, kKronMaxL, 1, false>(blocks, n_blocks, max_ns, max_L, max_c,
+                                                           x_in, x_out, status, st);
+  return launch_kron_shape<1, 4, 4, kKronMaxL, 1, false>(blocks, n_blocks, max_ns, max_L, max_c,
+                                                         x_in, x_out, status, st);
 }
 
 }  // namespace lem

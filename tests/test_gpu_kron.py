@@ -51,6 +51,23 @@ def test_core_40_three_members_ten_steps():
     assert rel_l2(got, want) <= 1e-12
 
 
+# member counts around the launch shapes: four members per workgroup with
+# 16-byte member loads (8) or one member per load (5, 6), two per workgroup
+# for cores above 32 points with member loads (4, 2) or without (3)
+@pytest.mark.parametrize("core,h,ns", [(16, 8, 8), (16, 8, 5), (16, 8, 6), (48, 8, 4),
+                                       (48, 8, 2), (48, 8, 3)])
+def test_member_counts_and_shapes(core, h, ns):
+    n = 96
+    base = L.workload_2d_ensemble(n=n, n_states=ns)
+    plan = lem.Plan(lem.Operator.from_problem(base), base.dt, method="kronecker", core=core,
+                    halo=h, n_states=ns)
+    got = run(plan, base.states, 2)
+    boxes = P.uniform_boxes(2, n, core, h)
+    want = olem.run(op.sparse(op.from_problem(base)), boxes, 2, n, base.states, 2)
+    assert rel_l2(got, want) <= 1e-12
+    assert plan.query()["device_status"] == 0
+
+
 def test_anisotropic_mesh():
     n = 128
     base = L.workload_2d_ensemble(n=n, n_states=2)
