@@ -155,3 +155,19 @@ def test_columns_anisotropic_dimension_above_30():
     want = oracle(p, plan, p.states, 2)
     assert rel_l2(got, want) <= 1e-12
     assert plan.query()["device_status"] == 0
+
+
+def test_forced_variable_nu_large_boxes():
+    # a forcing with lognormal diffusivity: the augmented coordinate beside the
+    # per-block weight table (its weights are zero) on 8837-point boxes
+    p = L.workload_2d_variable(n=128)
+    g = L.source_fields_2d(p.n, 1, seed=11)
+    base = lem.Operator.from_problem(p)
+    o = lem.Operator(base.ndim, base.n, base.dx, base.vel, base.nu, base.nu_field, forcing=g)
+    plan = lem.Plan(o, p.dt, method="krylov", core=64, halo=15, krylov_m_max=40,
+                    max_substeps=16, krylov_tol=1e-13)
+    assert plan.query()["n_loc_max"] == 94 * 94
+    got = run(plan, p.states, 2)
+    want = oracle(p, plan, p.states, 2, dtg=p.dt * g)
+    assert rel_l2(got, want) <= 1e-12
+    assert plan.query()["device_status"] == 0
