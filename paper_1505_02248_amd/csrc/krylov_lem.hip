@@ -10,8 +10,11 @@
 // accumulated over the sub-steps and latched into the status word when above
 // tolerance.  The basis stays in LDS whenever it fits (the planner chooses
 // the Krylov dimension and sub-step count for that), otherwise it lives in a
-// per-block slice of device memory read through the L2.  Each Arnoldi column
-// takes three sweeps and two reductions:
+// per-block slice of device memory read through the L2 (a buffer resource:
+// row offset in a scalar register, point offset per lane), with the current
+// direction also kept in LDS for the stencil product, and the columns follow
+// the delayed re-orthogonalization described at the streamed branch.  With
+// the basis in LDS each Arnoldi column takes three sweeps and two reductions:
 //   * sweep 1: stencil product on the LDS-resident v_j fused with the first
 //     Gram-Schmidt dots; one reduction;
 //   * sweep 2: first update fused with the re-orthogonalization dots and the
